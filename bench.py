@@ -1,0 +1,301 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched 1D depth inversions of extended diffraction tomography.
+
+Metric: 1D subproblems (k_m values) solved per second on one MI355X, for the
+mixed-precision path (BF16x3 Gram on MFMA + FP64 Cholesky + FP64 refinement)
+next to the plain FP64 path (FP64 MFMA Gram + FP64 Cholesky), at relative
+error <= 1e-6 (mixed) / <= 1e-10 (FP64) against the FP64 CPU oracle.
+
+Workload (default): the 2D layered survey -- 512 surface positions at 12.5 m
+(512 k_m, 257 +-k_m pairs), 8-layer reference, nz = 256 at 8 m, 128
+frequencies 3-60 Hz, smooth random model, 5% complex Gaussian data noise.
+A step is one pass of green -> assemble -> solve(-> refine -> recombine) over
+the whole survey with inputs resident in HBM.
+
+Inputs are synthesised on the GPU (Born forward map of the seeded model plus
+counter-based noise); the CPU-baseline leg re-derives its own data with the
+oracle, times the oracle on a sample of pairs, and feeds that same oracle
+data through the GPU path once more to state the error on identical inputs.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "1D subproblems solved/s, mixed vs FP64 plain, at rel err ≤1e-6 vs FP64 oracle"
+PEAK = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6, "hbm": 8000.0}   # TFLOP/s, GB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--mixed", default="bf16x3", choices=["bf16x3", "fp32"])
+    ap.add_argument("--refine-tol", type=float, default=1e-8)
+    ap.add_argument("--max-refine", type=int, default=8)
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--cpu-pairs", type=int, default=48)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
+    ap.add_argument("--only", choices=["both", "mixed", "fp64"], default="both")
+    return ap.parse_args()
+
+
+def synth_inputs(s, plan, vel, torch):
+    """Data rows from the HIP forward map plus counter-based noise (no oracle)."""
+    from edt_inputs import noise, vhat
+    g64, _ = plan.green(vel, want32=False)
+    d = plan.forward(g64, torch.from_numpy(vhat(s)).cuda())
+    if s.noise_rel == 0.0:
+        return d
+    m = plan.rowmap()
+    dn = d.cpu().numpy()
+    f = m["rows"][:, 0].astype(np.int64)
+    mx = np.zeros(s.n_freq)
+    np.maximum.at(mx, f, np.maximum(np.abs(dn[:, 0]), np.abs(dn[:, 1])))
+    scale = s.noise_rel * mx
+    keys = m["keys"].astype(np.int64)
+    if s.dim == 2:
+        N = s.n_mid
+        k0 = (keys[:, 0], keys[:, 1])
+        k1 = ((-keys[:, 1]) % N, (-keys[:, 0]) % N)
+    else:
+        pair = np.repeat(np.arange(plan.n_pairs), np.diff(m["row_off"]))
+        k0 = (m["pair_km"][pair, 0], keys[:, 0])
+        k1 = (m["pair_km"][pair, 1], keys[:, 0])
+    dn[:, 0] += scale[f] * noise(s.seed, f, *k0)
+    dn[:, 1] += scale[f] * noise(s.seed, f, *k1)
+    return torch.from_numpy(dn).cuda()
+
+
+class Runner:
+    """Preallocated buffers for one precision; step() is one full pass."""
+
+    def __init__(self, plan, vel, d, lam, prec, refine_tol, max_refine, torch):
+        self.p, self.vel, self.d, self.lam, self.prec = plan, vel, d, lam, prec
+        self.tol, self.maxr = refine_tol, max_refine
+        P, nz = plan.n_pairs, plan.nz
+        dev = plan.device
+        self.G64 = torch.empty(*plan.table_shape, dtype=torch.complex128, device=dev)
+        self.G32 = torch.empty(*plan.table_shape, dtype=torch.complex64, device=dev)
+        self.gram = torch.zeros(P, nz, nz, dtype=torch.float64, device=dev)
+        self.rhs = torch.empty(P, 2, nz, dtype=torch.float64, device=dev)
+        self.trace = torch.empty(P, dtype=torch.float64, device=dev)
+        self.x = torch.empty(P, 2, nz, dtype=torch.float64, device=dev)
+        self.v = torch.empty(plan.n_km, nz, dtype=torch.complex128, device=dev)
+        self.info = torch.empty(P, dtype=torch.int32, device=dev)
+        self.steps = torch.zeros(P, dtype=torch.int32, device=dev)
+
+    def step(self, d=None):
+        d = self.d if d is None else d
+        mixed = self.prec != "fp64"
+        g64, g32 = self.p.green(self.vel, want32=mixed, out=(self.G64, self.G32))
+        self.p.assemble(g64, g32, d, self.prec, out=(self.gram, self.rhs, self.trace))
+        self.p.solve(g64, d, self.gram, self.rhs, self.trace, self.lam, refine=mixed,
+                     refine_tol=self.tol, max_refine=self.maxr,
+                     out=(self.x, self.v, self.info, self.steps))
+
+
+def time_steps(run, steps, warmup, torch):
+    for _ in range(warmup):
+        run.step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        run.step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def kernel_times(run, steps, torch):
+    """Average duration per launch of every kernel over `steps` passes, measured
+    with HIP events recorded by the library on the launch stream."""
+    run.p.timing(True)
+    run.p.timing_read()
+    for _ in range(steps):
+        run.step()
+    torch.cuda.synchronize()
+    t = run.p.timing_read()
+    run.p.timing(False)
+    return {k: {"avg_ms": ms / max(n, 1), "launches_per_step": n / steps, "ms_per_step": ms / steps}
+            for k, (ms, n) in t.items()}
+
+
+def roofline(plan, s, ktimes, prec):
+    """Roofline entry of the dominant kernel of one step."""
+    info = plan.info
+    dom = max(ktimes, key=lambda k: ktimes[k]["ms_per_step"])
+    avg_s = ktimes[dom]["avg_ms"] * 1e-3
+    if dom.startswith("gram_"):
+        dt = {"gram_bf16x3": "bf16", "gram_fp32": "fp32", "gram_fp64": "fp64"}[dom]
+        ach = info["gram_flops"] / avg_s / 1e12
+        return dom, {"bound": "mfma", "achieved": ach, "peak": PEAK[dt], "unit": "TFLOP/s",
+                     "frac": ach / PEAK[dt], "traffic": None}
+    if dom in ("refine residual", "rhs_trace"):
+        # 16 R nz FP64 flops per refinement step (8 R nz for the right-hand sides),
+        # counting every data row of every pair
+        fl = (16.0 if dom != "rhs_trace" else 8.0) * info["n_rows"] * s.nz
+        ach = fl / avg_s / 1e12
+        return dom, {"bound": "alu", "achieved": ach, "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                     "frac": ach / PEAK["fp64"], "traffic": None}
+    if dom == "green":
+        by = info["table_elems"] * (16 + (8 if prec != "fp64" else 0))
+        ach = by / avg_s / 1e9
+        return dom, {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm"], "unit": "GB/s",
+                     "frac": ach / PEAK["hbm"], "traffic": None}
+    by = 3.0 * plan.n_pairs * s.nz * s.nz * 8
+    ach = by / avg_s / 1e9
+    return dom, {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm"], "unit": "GB/s",
+                 "frac": ach / PEAK["hbm"], "traffic": None}
+
+
+def cpu_baseline_leg(s, plan, runners, n_pairs_sample, torch):
+    """Time the FP64 oracle on a seeded sample of pairs (host cores), and state
+    the GPU error on the same oracle data for those pairs."""
+    from edt_inputs import vhat
+    from oracle.rows import plan as oplan, row_values
+    from oracle.solve import gtables, forward, noise_scale, add_noise, solve_pair
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    pl = oplan(s)
+    rng = np.random.default_rng(1234)
+    nonempty = [i for i, q in enumerate(pl.pairs) if q.n_rows > 0]
+    pick = sorted(rng.choice(nonempty, size=min(n_pairs_sample, len(nonempty)), replace=False).tolist())
+    # noise scale needs the clean data of every row (max per frequency)
+    tabs_all = gtables(s, pl)
+    clean_all = forward(s, pl, vhat(s), tabs_all)
+    scale = noise_scale(s, pl, clean_all)
+    sub = [pl.pairs[i] for i in pick]
+    data = add_noise(s, pl, [clean_all[i] for i in pick], scale, pairs=sub)
+    del clean_all
+    # timed: the oracle solve of the sampled pairs (tables for their rows, rows,
+    # normal equations, Cholesky)
+    t0 = time.perf_counter()
+    tabs = gtables(s, pl, pairs=sub)
+    xs = []
+    for q, (d0, d1) in zip(sub, data):
+        A = row_values(s, q, tabs.lookup)
+        xs.append(solve_pair(s, q, A, d0, d1)[0])
+    dt = time.perf_counter() - t0
+    n_km = sum(1 if q.self_conjugate else 2 for q in sub)
+    # GPU on identical inputs: the oracle's data overwrite the sampled pairs
+    m = plan.rowmap()
+    off = m["row_off"]
+    d_host = runners[0].d.cpu().numpy()
+    for i, (d0, d1) in zip(pick, data):
+        d_host[off[i]:off[i + 1], 0] = d0
+        d_host[off[i]:off[i + 1], 1] = d1
+    d_mix = torch.from_numpy(d_host).cuda()
+    errs = {}
+    for r in runners:
+        r.step(d_mix)
+        torch.cuda.synchronize()
+        v = r.v.cpu().numpy()
+        num = den = 0.0
+        per = []
+        norms = []
+        for q, x in zip(sub, xs):
+            ref = x[0] + 1j * x[1]
+            e = np.linalg.norm(v[q.u] - ref) ** 2
+            n = np.linalg.norm(ref) ** 2
+            if not q.self_conjugate:
+                e += np.linalg.norm(v[q.u_neg] - np.conj(ref)) ** 2
+                n += np.linalg.norm(ref) ** 2
+            num += e
+            den += n
+            per.append(np.sqrt(e))
+            norms.append(np.sqrt(n))
+        norms = np.array(norms)
+        fl = 1e-3 * norms.max()
+        errs[r.prec] = {"global": float(np.sqrt(num / den)),
+                        "per_pair_max": float(np.max(np.array(per) / np.maximum(norms, fl))),
+                        "pairs": len(sub)}
+    base = {"value": n_km / dt, "unit": "subproblems/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{len(sub)} of {plan.n_pairs} +-k_m pairs ({n_km} k_m, seeded), "
+                      f"FP64 NumPy/SciPy: G0 tables, Born rows, Re(A^H A), Cholesky; {dt:.1f} s",
+            "host_cpus": os.cpu_count()}
+    return base, errs
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {a.gpus} is not supported "
+              "(the +-k_m pairs would shard across GPUs with no exchange, see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_0905_0238_amd as E
+    from edt_inputs import make_config, CONFIG_NAMES
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    s = make_config(a.config)
+    t0 = time.perf_counter()
+    plan = E.Plan(s, chunk_rows=a.chunk).upload()
+    plan_s = time.perf_counter() - t0
+    vel = torch.tensor(s.vel, dtype=torch.float64, device="cuda")
+    d = synth_inputs(s, plan, vel, torch)
+    torch.cuda.synchronize()
+    precs = {"both": ["fp64", a.mixed], "mixed": [a.mixed], "fp64": ["fp64"]}[a.only]
+    runners = [Runner(plan, vel, d, s.lambda_rel, pr, a.refine_tol, a.max_refine, torch) for pr in precs]
+    res = {}
+    for r in runners:
+        ms, wall = time_steps(r, a.steps, a.warmup, torch)
+        kt = kernel_times(r, max(2, min(a.steps, 5)), torch)
+        st = r.steps.cpu().numpy()
+        info = r.info.cpu().numpy()
+        res[r.prec] = {"ms_per_step": ms, "wall_ms_per_step": wall, "kernels": kt,
+                       "refine_steps": {"max": int(st.max()), "mean": float(st.mean())},
+                       "info_nonzero": int(np.sum((info != 0) & (info != -1)))}
+    main_prec = precs[-1]
+    t_main = res[main_prec]["ms_per_step"]
+    value = plan.n_km / (t_main * 1e-3)
+    dom, roof = roofline(plan, s, res[main_prec]["kernels"], main_prec)
+    roof["kernel"] = dom
+    out = {
+        "metric": METRIC, "value": value, "unit": "subproblems/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": t_main, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3+f64" if main_prec == "bf16x3" else ("f32+f64" if main_prec == "fp32" else "f64"),
+        "data": "synthetic",
+        "config": {"workload": CONFIG_NAMES[a.config], "n_km": plan.n_km, "n_pairs": plan.n_pairs,
+                   "nz": s.nz, "n_freq": s.n_freq, "rows": plan.n_rows, "unique_rows": plan.info["n_urows"],
+                   "precision": main_prec, "refine_tol": a.refine_tol, "max_refine": a.max_refine,
+                   "chunk_rows": plan.info["chunk_rows"]},
+        "roofline": roof,
+    }
+    if "fp64" in res and main_prec != "fp64":
+        out["fp64_plain"] = {"value": plan.n_km / (res["fp64"]["ms_per_step"] * 1e-3),
+                             "ms_per_step": res["fp64"]["ms_per_step"]}
+        out["speedup_vs_fp64"] = res["fp64"]["ms_per_step"] / t_main
+    out["detail"] = {k: {kk: vv for kk, vv in v.items()} for k, v in res.items()}
+    out["detail"]["plan_s"] = plan_s
+    if not a.no_cpu:
+        base, errs = cpu_baseline_leg(s, plan, runners, a.cpu_pairs, torch)
+        out["cpu_baseline"] = base
+        out["rel_err_vs_oracle"] = errs
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,262 @@
+/*
+ * edt.h -- C-ABI of libedt, the MI355X (gfx950) hot path of extended
+ * diffraction tomography (Schlottmann, "Extended diffraction tomography").
+ *
+ * The paper (Section 2.1) turns the linear Born inversion of surface seismic
+ * data over a depth-dependent reference medium into many independent 1D depth
+ * problems, one per midpoint wavenumber k_m (eq. DMV), whose kernel M is a
+ * product of two reference Green's functions (eq. M).  Because M(k_m) =
+ * M(-k_m), the problems at +k_m and -k_m are solved together as one *pair*
+ * for the real unknowns Re V~ and Im V~ (eqs. VSym, Split).  This library
+ * computes, on one GPU:
+ *
+ *   edt_green     the Green's-function tables g(z; |k|, w) of the layered
+ *                 reference (the 1D reference Helmholtz problem, Section 2.1)
+ *   edt_assemble  per pair the Gram matrix G = Re(A^H A) of the Born rows
+ *                 A = w^2 dz g(k_r) g(k_s) (eq. M, infinite-aperture limit),
+ *                 the right-hand sides c = Re(A^H b+-) (eq. Split) and tr(G)
+ *   edt_solve     the relatively damped normal equations
+ *                 (G + lambda_rel tr(G)/nz I) x = c by Cholesky, with FP64
+ *                 iterative refinement for the mixed-precision Grams, and the
+ *                 recombination V~(+-k_m) = x+ +- i x-  (eq. VSym)
+ *   edt_adjoint   the reverse-mode gradient of a loss on V~ with respect to
+ *                 the data, lambda_rel and the layer velocities
+ *   edt_forward   the Born forward map V~ -> data rows (eq. DMV), used for
+ *                 data synthesis and adjoint (dot-product) checks
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Complex numbers are interleaved (re, im) pairs: edt_c128 == two doubles,
+ *   edt_c64 == two floats (the layouts of torch.complex128 / complex64).
+ * - Time dependence e^{-i w t}, complex angular frequency w = 2 pi f + i eps.
+ * - Horizontal wavenumber indices are in numpy fftfreq order.  2D: the k_m
+ *   index u in [0, N); 3D: u = ux*N + uy.
+ * - A *row* is one datum of one pair: (frequency f, class of |k_r|, class of
+ *   |k_s|).  Classes index the distinct |k| values of the plan (cls_k).
+ * - Rows of a pair are contiguous, pairs are ordered by their representative
+ *   k_m index; within a pair rows are ordered by frequency then (2D) by the
+ *   signed receiver-wavenumber index, (3D) by the k_h index n_x*N_h + n_y.
+ * - Device arrays are caller-owned (e.g. torch tensors); the library never
+ *   allocates device memory.  All device work is enqueued on the caller's
+ *   stream, nothing synchronises the host.
+ * - Errors: a negative edt_status means nothing was enqueued (bad argument,
+ *   missing upload, HIP launch failure).  Numerical outcomes are written per
+ *   pair to info[] on the device and are valid after a stream sync.
+ */
+#ifndef EDT_H
+#define EDT_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } edt_c128;
+typedef struct { float re, im; } edt_c64;
+
+typedef enum {
+    EDT_OK = 0,
+    EDT_EINVAL = -1,   /* invalid argument; message via edt_last_error() */
+    EDT_ENOMEM = -2,   /* host allocation failed, or a caller buffer is too small */
+    EDT_EHIP = -3,     /* a HIP runtime call or kernel launch failed */
+    EDT_ESTATE = -4    /* the plan has no device copy (edt_plan_upload not called) */
+} edt_status;
+
+/* per-pair info[] values; a positive value k means the Cholesky factorisation
+ * met a non-positive pivot at column k-1 */
+enum {
+    EDT_INFO_OK = 0,
+    EDT_INFO_EMPTY = -1,     /* no rows survive the evanescent cut: V~ = 0 */
+    EDT_INFO_NOCONV = -2,    /* refinement did not reach refine_tol in max_refine steps */
+    EDT_INFO_NONFINITE = -3  /* a NaN or Inf reached the solution */
+};
+
+typedef enum {
+    EDT_FP64 = 0,    /* Gram on FP64 MFMA (v_mfma_f64_16x16x4) */
+    EDT_FP32 = 1,    /* Gram on FP32 MFMA with FP32 accumulation */
+    EDT_BF16X3 = 2   /* Gram on BF16 MFMA: hi*hi + hi*lo + lo*hi, FP32 accumulation */
+} edt_precision;
+
+/*
+ * Survey geometry (paper Sections 2.1-2.2 and 3.1).
+ * dim 2: split-spread periodic line of n_mid positions at spacing d_mid, every
+ *        source recorded by every receiver; rows of k_m index u are the receiver
+ *        wavenumbers a with source wavenumber b = u - a (mod N).
+ * dim 3: areal survey, k_m on an n_mid x n_mid grid (spacing 2 pi/(n_mid d_mid)),
+ *        k_h on an n_off x n_off grid with n_off*d_off == n_mid*d_mid/2, so
+ *        k_r = (k_m + k_h)/2 and k_s = (k_m - k_h)/2 (eq. COV).
+ * Frequencies freq_hz[n_freq] are used simultaneously (Section 3.1); eps is the
+ * imaginary part of w (Section 2.1; 0.15 1/s in Section 3.1).  Depths are
+ * z_i = z0 + i*dz, i < nz.  A row is kept iff |k_r| and |k_s| are both
+ * <= kappa * 2 pi f / c_top, with c_top the velocity of the source layer.
+ */
+typedef struct {
+    int dim;
+    int n_mid;
+    double d_mid;
+    int n_off;
+    double d_off;
+    int n_freq;
+    const double* freq_hz;   /* host pointer, copied by edt_plan_create */
+    double eps;
+    int nz;
+    double z0, dz;
+    double kappa;
+} edt_survey;
+
+/* Layered reference c0(z) (Section 2.1): layer 0 extends up to -infinity and
+ * holds sources and receivers at z = 0, so zif[0] > 0; layer n_layers-1 is a
+ * half space; zif (host, length n_layers-1) is strictly increasing.  vel
+ * (host) fixes c_top for the evanescent cut; the velocities used by the
+ * kernels are passed to edt_green / edt_adjoint on the device. */
+typedef struct {
+    int n_layers;
+    const double* vel;
+    const double* zif;
+} edt_layers;
+
+typedef struct edt_plan edt_plan;
+
+typedef struct {
+    int64_t n_km;          /* number of k_m problems */
+    int64_t n_pairs;       /* number of +-k_m pairs (factorisations) */
+    int64_t n_rows;        /* rows summed over pairs (length of d_rows) */
+    int64_t n_urows;       /* distinct Born rows: data rows of a pair with equal
+                              (f, {|k_r|, |k_s|}) share one row of A */
+    int64_t max_rows;      /* rows of the largest pair */
+    int64_t n_empty;       /* pairs with no rows */
+    int64_t n_items;       /* work items (pair, row chunk) of the assembly */
+    int n_freq, n_cls, nz, n_layers;
+    int chunk_rows;        /* rows per work item */
+    size_t table_elems;    /* n_freq * n_cls * nz: length of g64 / g32 */
+    size_t dev_plan_bytes; /* size of the device copy of the plan */
+    size_t work_bytes;     /* workspace needed by assemble / solve / adjoint */
+    double gram_flops;     /* sum over pairs of 2 R_p nz (nz+1): algorithmic Gram work */
+} edt_plan_info;
+
+typedef struct {
+    int refine;            /* 0: one solve; 1: FP64 iterative refinement */
+    double refine_tol;     /* stop when ||dx|| <= refine_tol ||x|| (per pair) */
+    int max_refine;        /* at most this many refinement steps */
+} edt_solve_opts;
+
+/* Message of the last failing call on this thread (static storage). */
+const char* edt_last_error(void);
+
+/*
+ * Host planner: enumerates pairs and rows, the |k| classes and the work
+ * items (pair, chunk of <= chunk_rows rows) in longest-first order.
+ * chunk_rows <= 0 picks the default.  Host only, no HIP calls.
+ * Errors: EDT_EINVAL (dim, sizes, zif[0] <= 0, non-increasing zif, n_cls or
+ * n_freq >= 65536), EDT_ENOMEM.  *out is owned by the caller: edt_plan_destroy.
+ */
+edt_status edt_plan_create(const edt_survey* survey, const edt_layers* layers,
+                           int chunk_rows, edt_plan** out);
+edt_status edt_plan_destroy(edt_plan* plan);
+edt_status edt_plan_query(const edt_plan* plan, edt_plan_info* out);
+
+/*
+ * Host copies of the plan (every pointer nullable; sizes from edt_plan_query):
+ *   row_off[n_pairs+1]  first row of each pair
+ *   rows[n_rows*3]      (f, class of |k_r|, class of |k_s|)
+ *   keys[n_rows*2]      2D: fftfreq indices (a, b) of the +k_m datum, whose
+ *                       -k_m partner is (-b, -a); 3D: (k_h index n, 0)
+ *   pair_km[n_pairs*2]  (u, index of -u); equal for a self-conjugate k_m
+ *   cls_k[n_cls]        |k| of each class, rad/m
+ */
+edt_status edt_plan_rowmap(const edt_plan* plan, int64_t* row_off, int32_t* rows,
+                           int32_t* keys, int32_t* pair_km, double* cls_k);
+
+/*
+ * Copy the plan's device tables into a caller device buffer of at least
+ * dev_plan_bytes bytes (256-byte aligned) and remember it in the plan.  Must
+ * precede every compute call; the buffer must outlive them.  Enqueued on
+ * `stream` (an async copy from host memory owned by the plan).
+ */
+edt_status edt_plan_upload(edt_plan* plan, void* dev_buf, size_t bytes, hipStream_t stream);
+
+/*
+ * Kernel (a): Green's-function tables.  g64[f][c][z] = g(z_i; cls_k[c], w_f)
+ * solving g'' + (w^2/c0(z)^2 - k^2) g = -delta(z) with radiation conditions
+ * (Section 2.1), by a generalised reflection recursion over the layers.
+ * g32 (nullable) receives the same table in FP32 scaled by |w_f| sqrt(dz), the
+ * factor whose square |w_f^2 dz| multiplies Re(A^H A) (the phase of w^2 cancels).
+ * vel_dev: device, n_layers doubles.  Shapes: n_freq*n_cls*nz.
+ */
+edt_status edt_green(const edt_plan* plan, const double* vel_dev, edt_c128* g64, edt_c64* g32,
+                     hipStream_t stream);
+
+/*
+ * Kernel (b): per pair p, gram[p] (nz x nz, row-major, the lower triangle
+ * i >= j is written) = Re(A_p^H A_p) in the given precision, plus, always in
+ * FP64 from g64 and the data, rhs[p][0|1][z] = Re(A_p^H b+-) and
+ * trace[p] = tr Re(A_p^H A_p).  d_rows[r] = (datum at +k_m, datum at -k_m) of
+ * row r, complex128, so b+ = (d0+d1)/2 and b- = (d0-d1)/(2i) (eq. Split).
+ * prec EDT_FP64 reads g64; EDT_FP32 / EDT_BF16X3 read g32 (from edt_green).
+ * work: device, >= work_bytes.  Empty pairs get zero Gram, rhs and trace.
+ */
+edt_status edt_assemble(const edt_plan* plan, const edt_c128* g64, const edt_c64* g32,
+                        const edt_c128* d_rows, edt_precision prec, double* gram, double* rhs,
+                        double* trace, void* work, hipStream_t stream);
+
+/*
+ * Kernel (c): lambda_p = lambda_rel * trace[p] / nz; gram[p] is overwritten by
+ * the Cholesky factor L of gram + lambda_p I (lower triangle); x[p][0|1] =
+ * (L L^T)^{-1} rhs[p][0|1].  With opts->refine, x is refined in FP64: the
+ * residual Re(A^H (b - A x)) - lambda x is rebuilt from g64 and d_rows until
+ * ||dx|| <= refine_tol ||x|| or max_refine steps (per pair; steps[p] counts
+ * them, info NOCONV if the tolerance was not met).  A self-conjugate k_m keeps
+ * x- = 0.  v_out[u] = x+ + i x-, v_out[-u] = x+ - i x- (eq. VSym), zero for
+ * empty pairs.  x: [n_pairs][2][nz]; v_out: [n_km][nz]; info, steps: [n_pairs]
+ * (steps nullable).  opts nullable (= no refinement).
+ */
+edt_status edt_solve(const edt_plan* plan, const edt_c128* g64, const edt_c128* d_rows,
+                     double* gram, const double* rhs, const double* trace, double lambda_rel,
+                     const edt_solve_opts* opts, double* x, edt_c128* v_out, int32_t* info,
+                     int32_t* steps, void* work, hipStream_t stream);
+
+/*
+ * Born forward map (eq. DMV): d_rows[r] = (A_r . v_in[u_p], A_r . v_in[-u_p]),
+ * A_r = w_f^2 dz g(k_r) g(k_s), for every row r of pair p.
+ * v_in: [n_km][nz] complex128; d_rows: [n_rows][2] complex128.
+ */
+edt_status edt_forward(const edt_plan* plan, const edt_c128* g64, const edt_c128* v_in,
+                       edt_c128* d_rows, hipStream_t stream);
+
+/*
+ * Kernel (d): reverse-mode gradient of a real loss L(V~) given
+ * grad_v = dL/dRe V~ + i dL/dIm V~ ([n_km][nz]).  Uses the factor `chol` and
+ * solution `x` left by edt_solve, trace from edt_assemble, and recomputes the
+ * Green's tables and their velocity sensitivities from vel_dev (g64 is the
+ * table of the forward pass).  Outputs (each nullable):
+ *   grad_d[r] = (dL/dd0, dL/dd1) in the same complex convention ([n_rows][2])
+ *   grad_lambda[0] = dL/dlambda_rel
+ *   grad_vel[l] = dL/dc_l, l < n_layers
+ * The evanescent-cut mask is held fixed.
+ */
+edt_status edt_adjoint(const edt_plan* plan, const double* vel_dev, const edt_c128* g64,
+                       const edt_c128* d_rows, const double* chol, const double* trace,
+                       const double* x, double lambda_rel, const edt_c128* grad_v,
+                       edt_c128* grad_d, double* grad_lambda, double* grad_vel, void* work,
+                       hipStream_t stream);
+
+/*
+ * Optional kernel timing, for benchmarks: with timing enabled every kernel
+ * launch made for `plan` is bracketed by two HIP events on its stream (no
+ * device memory, no host sync).  edt_timing_read waits for the recorded
+ * events and returns, per kernel name, the summed milliseconds and launch
+ * count since the previous read: names[k*32 .. k*32+31] (NUL-terminated),
+ * ms[k], count[k] for k < min(*n_out, max_entries).  Not for use while a
+ * stream is being captured into a graph.
+ */
+edt_status edt_timing_enable(edt_plan* plan, int enable);
+edt_status edt_timing_read(edt_plan* plan, int max_entries, char* names, double* ms, int64_t* count,
+                           int* n_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EDT_H */

@@ -1,0 +1,268 @@
+// C-ABI entry points: argument checks and kernel orchestration on the
+// caller's stream.  No device memory is allocated here; all scratch lives in
+// the caller's workspace (layout from edt::work_layout).
+
+#include <cstdio>
+#include <string>
+
+#include "dev_common.h"
+#include "timing.h"
+
+namespace edt {
+hipError_t launch_green(const edt_plan* p, const double* vel, zd* g64, float2* g32, hipStream_t st);
+hipError_t launch_gram(const edt_plan* p, edt_precision prec, const zd* g64, const float2* g32,
+                       void* part, hipStream_t st);
+hipError_t launch_gram_reduce(const edt_plan* p, edt_precision prec, const void* part, double* gram,
+                              hipStream_t st);
+hipError_t launch_rhs_reduce(const edt_plan* p, const double* rpart, double* rhs, double* trace,
+                             hipStream_t st);
+hipError_t launch_bsum(const edt_plan* p, const zd* d_rows, zd* ub, hipStream_t st);
+hipError_t launch_resid(const edt_plan* p, const zd* g64, const zd* ub, const double* x,
+                        const int32_t* conv, double* rpart, hipStream_t st);
+hipError_t launch_forward(const edt_plan* p, const zd* g64, const zd* v, zd* d_rows, hipStream_t st);
+hipError_t launch_chol(const edt_plan* p, double* gram, const double* trace, const double* rhs,
+                       double lambda_rel, double* lam, double* x, int32_t* info, int32_t* conv,
+                       int32_t* steps, hipStream_t st);
+hipError_t launch_refine_update(const edt_plan* p, const double* gram, const double* rpart,
+                                const double* lam, double* x, int32_t* conv, int32_t* steps, double tol,
+                                hipStream_t st);
+hipError_t launch_recombine(const edt_plan* p, const double* x, int refine, const int32_t* conv,
+                            int32_t* info, zd* v, hipStream_t st);
+hipError_t launch_adjoint(const edt_plan* p, const double* vel, const zd* g64, const zd* d_rows,
+                          const double* chol, const double* trace, const double* x, double lambda_rel,
+                          const zd* grad_v, zd* grad_d, double* grad_lambda, double* grad_vel,
+                          unsigned char* work, hipStream_t st);
+size_t chol_lds_bytes(int nz);
+size_t refine_lds_bytes(int nz);
+hipError_t configure_kernels();
+
+Timer& timer_of(const edt_plan* p) {
+    edt_plan* q = const_cast<edt_plan*>(p);
+    if (!q->timer) {
+        q->timer = new Timer();
+        q->timer_free = [](void* t) { delete static_cast<Timer*>(t); };
+    }
+    return *static_cast<Timer*>(q->timer);
+}
+}  // namespace edt
+
+using namespace edt;
+
+namespace {
+
+edt_status hip_fail(hipError_t e, const char* where) {
+    set_error(std::string(where) + ": " + hipGetErrorString(e));
+    return EDT_EHIP;
+}
+
+edt_status check_plan(const edt_plan* p) {
+    if (!p) {
+        set_error("null plan");
+        return EDT_EINVAL;
+    }
+    if (!p->dev) {
+        set_error("plan has no device copy: call edt_plan_upload first");
+        return EDT_ESTATE;
+    }
+    if (p->nz > 256) {
+        set_error("nz > 256 is not supported by the assembly kernels");
+        return EDT_EINVAL;
+    }
+    return EDT_OK;
+}
+
+// launch `call` on `st`, bracketed by timer events when timing is enabled
+#define EDT_TRY(call, where)                                   \
+    do {                                                       \
+        timer_of(p).begin(stream);                             \
+        hipError_t e_ = (call);                                \
+        timer_of(p).end(stream, where);                        \
+        if (e_ != hipSuccess) return hip_fail(e_, where);      \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+edt_status edt_timing_enable(edt_plan* p, int enable) {
+    if (!p) {
+        set_error("null plan");
+        return EDT_EINVAL;
+    }
+    timer_of(p).enabled = enable != 0;
+    return EDT_OK;
+}
+
+edt_status edt_timing_read(edt_plan* p, int max_entries, char* names, double* ms, int64_t* count,
+                           int* n_out) {
+    if (!p || !n_out || (max_entries > 0 && (!names || !ms || !count))) {
+        set_error("null argument");
+        return EDT_EINVAL;
+    }
+    Timer& t = timer_of(p);
+    std::vector<std::string> key;
+    std::vector<double> tot;
+    std::vector<int64_t> cnt;
+    for (auto& r : t.recs) {
+        if (hipEventSynchronize(r.stop) != hipSuccess) return hip_fail(hipGetLastError(), "timing read");
+        float e = 0.f;
+        if (hipEventElapsedTime(&e, r.start, r.stop) != hipSuccess) return hip_fail(hipGetLastError(), "timing read");
+        size_t k = 0;
+        while (k < key.size() && key[k] != r.name) ++k;
+        if (k == key.size()) {
+            key.emplace_back(r.name);
+            tot.push_back(0.0);
+            cnt.push_back(0);
+        }
+        tot[k] += double(e);
+        cnt[k] += 1;
+        t.pool.push_back(r.start);
+        t.pool.push_back(r.stop);
+    }
+    t.recs.clear();
+    const int n = int(key.size());
+    *n_out = n;
+    for (int k = 0; k < n && k < max_entries; ++k) {
+        std::snprintf(names + 32 * k, 32, "%s", key[k].c_str());
+        ms[k] = tot[k];
+        count[k] = cnt[k];
+    }
+    return EDT_OK;
+}
+
+edt_status edt_plan_upload(edt_plan* p, void* dev_buf, size_t bytes, hipStream_t stream) {
+    if (!p || !dev_buf) {
+        set_error("null argument");
+        return EDT_EINVAL;
+    }
+    if (bytes < p->lay.total) {
+        set_error("device plan buffer too small");
+        return EDT_ENOMEM;
+    }
+    if (reinterpret_cast<uintptr_t>(dev_buf) % 256 != 0) {
+        set_error("device plan buffer must be 256-byte aligned");
+        return EDT_EINVAL;
+    }
+    hipError_t e = configure_kernels();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dev_buf, p->host_image.data(), p->lay.total, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "plan upload");
+    p->dev = static_cast<unsigned char*>(dev_buf);
+    return EDT_OK;
+}
+
+edt_status edt_green(const edt_plan* p, const double* vel_dev, edt_c128* g64, edt_c64* g32,
+                     hipStream_t stream) {
+    edt_status s = check_plan(p);
+    if (s != EDT_OK) return s;
+    if (!vel_dev || !g64) {
+        set_error("vel_dev and g64 are required");
+        return EDT_EINVAL;
+    }
+    EDT_TRY(launch_green(p, vel_dev, reinterpret_cast<zd*>(g64), reinterpret_cast<float2*>(g32), stream),
+            "green");
+    return EDT_OK;
+}
+
+edt_status edt_assemble(const edt_plan* p, const edt_c128* g64, const edt_c64* g32,
+                        const edt_c128* d_rows, edt_precision prec, double* gram, double* rhs,
+                        double* trace, void* work, hipStream_t stream) {
+    edt_status s = check_plan(p);
+    if (s != EDT_OK) return s;
+    if (prec != EDT_FP64 && prec != EDT_FP32 && prec != EDT_BF16X3) {
+        set_error("unknown precision");
+        return EDT_EINVAL;
+    }
+    if (!g64 || !d_rows || !gram || !rhs || !trace || !work || (prec != EDT_FP64 && !g32)) {
+        set_error("missing argument (g32 is required for FP32 and BF16X3)");
+        return EDT_EINVAL;
+    }
+    const WorkLayout wl = work_layout(p);
+    unsigned char* w = static_cast<unsigned char*>(work);
+    zd* ub = reinterpret_cast<zd*>(w + wl.ub);
+    const zd* G64 = reinterpret_cast<const zd*>(g64);
+    EDT_TRY(launch_bsum(p, reinterpret_cast<const zd*>(d_rows), ub, stream), "bsum");
+    EDT_TRY(launch_gram(p, prec, G64, reinterpret_cast<const float2*>(g32), w + wl.gram_part, stream),
+            prec == EDT_FP64 ? "gram_fp64" : (prec == EDT_FP32 ? "gram_fp32" : "gram_bf16x3"));
+    EDT_TRY(launch_gram_reduce(p, prec, w + wl.gram_part, gram, stream), "gram_reduce");
+    double* rpart = reinterpret_cast<double*>(w + wl.rhs_part);
+    EDT_TRY(launch_resid(p, G64, ub, nullptr, nullptr, rpart, stream), "rhs_trace");
+    EDT_TRY(launch_rhs_reduce(p, rpart, rhs, trace, stream), "rhs reduce");
+    return EDT_OK;
+}
+
+edt_status edt_solve(const edt_plan* p, const edt_c128* g64, const edt_c128* d_rows, double* gram,
+                     const double* rhs, const double* trace, double lambda_rel,
+                     const edt_solve_opts* opts, double* x, edt_c128* v_out, int32_t* info,
+                     int32_t* steps, void* work, hipStream_t stream) {
+    edt_status s = check_plan(p);
+    if (s != EDT_OK) return s;
+    const int refine = opts ? opts->refine : 0;
+    if (!gram || !rhs || !trace || !x || !v_out || !info || !work || (refine && (!g64 || !d_rows))) {
+        set_error("missing argument (g64 and d_rows are required with refinement)");
+        return EDT_EINVAL;
+    }
+    if (!(lambda_rel >= 0.0)) {
+        set_error("lambda_rel must be >= 0");
+        return EDT_EINVAL;
+    }
+    if (refine && (opts->max_refine < 0 || !(opts->refine_tol > 0.0))) {
+        set_error("refinement needs max_refine >= 0 and refine_tol > 0");
+        return EDT_EINVAL;
+    }
+    const WorkLayout wl = work_layout(p);
+    unsigned char* w = static_cast<unsigned char*>(work);
+    double* lam = reinterpret_cast<double*>(w + wl.lam);
+    int32_t* conv = reinterpret_cast<int32_t*>(w + wl.conv);
+    int32_t* stp = steps ? steps : reinterpret_cast<int32_t*>(w + wl.aux);
+    EDT_TRY(launch_chol(p, gram, trace, rhs, lambda_rel, lam, x, info, conv, stp, stream), "cholesky");
+    if (refine) {
+        const zd* ub = reinterpret_cast<const zd*>(w + wl.ub);
+        double* rpart = reinterpret_cast<double*>(w + wl.rhs_part);
+        // the summed data were formed by edt_assemble on this workspace; rebuild
+        // them so edt_solve does not depend on an earlier call's scratch
+        EDT_TRY(launch_bsum(p, reinterpret_cast<const zd*>(d_rows), const_cast<zd*>(ub), stream), "bsum");
+        for (int it = 0; it < opts->max_refine; ++it) {
+            EDT_TRY(launch_resid(p, reinterpret_cast<const zd*>(g64), ub, x, conv, rpart, stream),
+                    "refine residual");
+            EDT_TRY(launch_refine_update(p, gram, rpart, lam, x, conv, stp, opts->refine_tol, stream),
+                    "refine update");
+        }
+    }
+    EDT_TRY(launch_recombine(p, x, refine, conv, info, reinterpret_cast<zd*>(v_out), stream), "recombine");
+    return EDT_OK;
+}
+
+edt_status edt_forward(const edt_plan* p, const edt_c128* g64, const edt_c128* v_in, edt_c128* d_rows,
+                       hipStream_t stream) {
+    edt_status s = check_plan(p);
+    if (s != EDT_OK) return s;
+    if (!g64 || !v_in || !d_rows) {
+        set_error("missing argument");
+        return EDT_EINVAL;
+    }
+    EDT_TRY(launch_forward(p, reinterpret_cast<const zd*>(g64), reinterpret_cast<const zd*>(v_in),
+                           reinterpret_cast<zd*>(d_rows), stream),
+            "forward");
+    return EDT_OK;
+}
+
+edt_status edt_adjoint(const edt_plan* p, const double* vel_dev, const edt_c128* g64,
+                       const edt_c128* d_rows, const double* chol, const double* trace, const double* x,
+                       double lambda_rel, const edt_c128* grad_v, edt_c128* grad_d, double* grad_lambda,
+                       double* grad_vel, void* work, hipStream_t stream) {
+    edt_status s = check_plan(p);
+    if (s != EDT_OK) return s;
+    if (!vel_dev || !g64 || !d_rows || !chol || !trace || !x || !grad_v || !work) {
+        set_error("missing argument");
+        return EDT_EINVAL;
+    }
+    EDT_TRY(launch_adjoint(p, vel_dev, reinterpret_cast<const zd*>(g64), reinterpret_cast<const zd*>(d_rows),
+                           chol, trace, x, lambda_rel, reinterpret_cast<const zd*>(grad_v),
+                           reinterpret_cast<zd*>(grad_d), grad_lambda, grad_vel,
+                           static_cast<unsigned char*>(work), stream),
+            "adjoint");
+    return EDT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// Device helpers: complex double arithmetic and wave-level utilities (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "edt_internal.h"
+
+namespace edt {
+
+struct zd {
+    double x, y;
+};
+
+__device__ __forceinline__ zd zmk(double x, double y) { return zd{x, y}; }
+__device__ __forceinline__ zd operator+(zd a, zd b) { return zd{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ zd operator-(zd a, zd b) { return zd{a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ zd operator*(zd a, zd b) {
+    return zd{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__device__ __forceinline__ zd operator*(double s, zd a) { return zd{s * a.x, s * a.y}; }
+__device__ __forceinline__ zd zconj(zd a) { return zd{a.x, -a.y}; }
+__device__ __forceinline__ double zabs2(zd a) { return a.x * a.x + a.y * a.y; }
+
+// a / b by Smith's method (avoids overflow of |b|^2).
+__device__ __forceinline__ zd zdiv(zd a, zd b) {
+    if (fabs(b.x) >= fabs(b.y)) {
+        const double r = b.y / b.x, d = b.x + r * b.y;
+        return zd{(a.x + a.y * r) / d, (a.y - a.x * r) / d};
+    }
+    const double r = b.x / b.y, d = b.y + r * b.x;
+    return zd{(a.x * r + a.y) / d, (a.y * r - a.x) / d};
+}
+
+// exp(i k d) for complex k and real distance d >= 0.
+__device__ __forceinline__ zd zexpi(zd k, double d) {
+    double s, c;
+    sincos(k.x * d, &s, &c);
+    const double m = exp(-k.y * d);
+    return zd{m * c, m * s};
+}
+
+// Principal square root (branch cut on the negative real axis): for an
+// argument in the upper half plane the result lies in the first quadrant.
+__device__ __forceinline__ zd zsqrt(zd a) {
+    const double m = hypot(a.x, a.y);
+    if (m == 0.0) return zd{0.0, 0.0};
+    const double t = sqrt(0.5 * (m + fabs(a.x)));
+    if (a.x >= 0.0) return zd{t, a.y / (2.0 * t)};
+    return zd{fabs(a.y) / (2.0 * t), copysign(t, a.y)};
+}
+
+constexpr double kTwoPiD = 2.0 * 3.141592653589793;
+
+// Complex angular frequency w = 2 pi f + i eps.
+__device__ __forceinline__ zd omega_of(double f, double eps) { return zd{kTwoPiD * f, eps}; }
+
+// Unique-row descriptor: f | mult << 16, cr | cs << 16.
+struct URow {
+    int f, mult, cr, cs;
+};
+__device__ __forceinline__ URow load_urow(const uint32_t* urows, int64_t r) {
+    const uint32_t a = urows[2 * r], b = urows[2 * r + 1];
+    return URow{int(a & 0xFFFFu), int(a >> 16), int(b & 0xFFFFu), int(b >> 16)};
+}
+
+// Sum of a double over the 64 lanes of a wave (every lane gets the total).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+}  // namespace edt

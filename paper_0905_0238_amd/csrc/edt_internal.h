@@ -1,0 +1,105 @@
+// Internal plan layout shared by the host planner and the kernel launchers.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/edt.h"
+
+namespace edt {
+
+// One assembly work item: a contiguous chunk of one pair's unique rows.
+struct Item {
+    int32_t pair;
+    int32_t row_begin;   // global unique-row index
+    int32_t row_end;
+    int32_t slot;        // index of this item's partial-result slot
+};
+
+// Byte offsets of the sections of the device copy of the plan.
+struct DevLayout {
+    size_t freq, zif, cls_k, row_off, pair_u, rows, urow_off, urows, umem_off, umem,
+        row_unique, urow_pair, tab_off, tab_ent, items, sched, pair_item, total;
+};
+
+constexpr int kMaxLayers = 64;   // layer-recursion state is held in LDS
+
+}  // namespace edt
+
+struct edt_plan {
+    // survey
+    int dim, n_mid, n_off, n_freq, nz, n_layers;
+    double d_mid, d_off, eps, z0, dz, kappa, ctop;
+    std::vector<double> freq, zif;
+    // |k| classes
+    int n_cls;
+    std::vector<double> cls_k;
+    // pairs and rows
+    int64_t n_km, n_pairs, n_rows, max_rows, n_empty;
+    std::vector<int64_t> row_off;        // [P+1]
+    std::vector<int32_t> pair_u;         // [2P]: u, -u
+    std::vector<uint32_t> rows;          // [2R]: f, cr | cs << 16
+    std::vector<int32_t> keys;           // [2R]
+    // unique rows: data rows of one pair with equal (f, {cr, cs}) share one
+    // Born row A (source-receiver reciprocity and lattice symmetry)
+    int64_t n_urows;
+    std::vector<int64_t> urow_off;       // [P+1]
+    std::vector<uint32_t> urows;         // [2U]: f | mult << 16, cr | cs << 16
+    std::vector<int32_t> umem_off;       // [U+1] members of each unique row
+    std::vector<int32_t> umem;           // [R] data rows, grouped
+    std::vector<int32_t> row_unique;     // [R] unique row of each data row
+    std::vector<int32_t> urow_pair;      // [U] pair of each unique row
+    // table-entry contributors (adjoint): entry e = f*n_cls + c receives from
+    // unique rows that use class c at frequency f; tab_ent = (row, other class)
+    std::vector<int32_t> tab_off;        // [n_freq*n_cls + 1]
+    std::vector<int32_t> tab_ent;        // [2 * 2U]
+    // work items
+    int chunk_rows;
+    std::vector<edt::Item> items;        // pair-major
+    std::vector<int32_t> sched;          // longest-first launch order
+    std::vector<int32_t> pair_item;      // [P+1] first item of each pair
+    double gram_flops;
+    // device copy
+    edt::DevLayout lay;
+    std::vector<unsigned char> host_image;
+    unsigned char* dev = nullptr;
+    // optional kernel timer (owned; created on first use by the HIP side)
+    void* timer = nullptr;
+    void (*timer_free)(void*) = nullptr;
+    ~edt_plan() {
+        if (timer && timer_free) timer_free(timer);
+    }
+};
+
+namespace edt {
+
+void set_error(const std::string& msg);
+
+// Device pointers into the uploaded plan.
+template <class T>
+inline T* dptr(const edt_plan* p, size_t off) {
+    return reinterpret_cast<T*>(p->dev + off);
+}
+
+// Workspace layout (bytes); identical for every call on a plan.
+struct WorkLayout {
+    size_t ub;          // [U][2] complex128 summed data b+ and b- of each unique row
+    size_t gram_part;   // [n_items][ntiles][tile] partial Gram tiles (FP64 or FP32)
+    size_t rhs_part;    // [n_items][2*nz + 1] FP64 partial rhs and trace
+    size_t lam;         // [P] lambda per pair
+    size_t conv;        // [P] int32 converged flags
+    size_t aux;         // [P][2][nz] FP64 scratch (refinement, adjoint)
+    size_t aux2;        // [P][2][nz] FP64 scratch
+    size_t gbar;        // [n_freq][n_cls][nz] complex128 (adjoint table gradient)
+    size_t adj_y;       // [P][2][nz] adjoint solutions
+    size_t adj_dl;      // [P] dL/dlambda_p
+    size_t adj_row;     // [U][4] complex128: e+, e-, A y+, A y-
+    size_t adj_vel;     // [n_freq*n_cls][n_layers] per-entry velocity gradients
+    size_t scal;        // [64] FP64 scalars
+    size_t total;
+};
+WorkLayout work_layout(const edt_plan* p);
+size_t gram_part_bytes_per_item(const edt_plan* p);
+
+}  // namespace edt

@@ -1,0 +1,301 @@
+// FP64 row kernels: right-hand sides, trace, refinement residual, forward map.
+//
+// Paper, Section 2.1, eqs. DMV and Split: for a pair with rows A (complex)
+// and data b+ = (d(k_m) + d(-k_m))/2, b- = (d(k_m) - d(-k_m))/(2i), the real
+// unknowns x+- satisfy the normal equations with right-hand side
+// c+- = Re(A^H b+-).  The refinement residual of the damped system is
+// Re(A^H (b - A x)) - lambda x.  Rows are rebuilt in FP64 from the Green's
+// table, A = W g(k_r) g(k_s), W = w^2 dz, and never stored.
+//
+// Rows that stand for several data rows (same frequency and |k_r|,|k_s|) are
+// processed once: their data are summed (bsum_kernel) and their A x term is
+// weighted by the multiplicity.
+//
+// Layout: a 256-thread block per work item; each wave takes its own rows,
+// lanes span depth (ZPL depths per lane).  A x needs a sum over depth per
+// row: four rows at a time are reduced with a transposing butterfly, so a
+// row costs about one cross-lane exchange per lane instead of six.
+
+#include "dev_common.h"
+
+namespace edt {
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(u), l);
+    const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(u >> 32), l);
+    return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+
+// Sum each of 16 per-lane values over the 64 lanes; every lane receives all
+// 16 totals.  Four halving exchanges leave lane l with the partial total of
+// index 8*b5 + 4*b4 + 2*b3 + b2 (b = bits of l), two more finish the sum.
+__device__ __forceinline__ void butterfly16(const double (&v)[16], double (&out)[16], int lane) {
+    double a8[8], a4[4], a2[2];
+    {
+        const bool b = lane & 32;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const double send = b ? v[i] : v[i + 8];
+            const double keep = b ? v[i + 8] : v[i];
+            a8[i] = keep + __shfl_xor(send, 32, 64);
+        }
+    }
+    {
+        const bool b = lane & 16;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double send = b ? a8[i] : a8[i + 4];
+            const double keep = b ? a8[i + 4] : a8[i];
+            a4[i] = keep + __shfl_xor(send, 16, 64);
+        }
+    }
+    {
+        const bool b = lane & 8;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const double send = b ? a4[i] : a4[i + 2];
+            const double keep = b ? a4[i + 2] : a4[i];
+            a2[i] = keep + __shfl_xor(send, 8, 64);
+        }
+    }
+    double s;
+    {
+        const bool b = lane & 4;
+        const double send = b ? a2[0] : a2[1];
+        const double keep = b ? a2[1] : a2[0];
+        s = keep + __shfl_xor(send, 4, 64);
+    }
+    s += __shfl_xor(s, 2, 64);
+    s += __shfl_xor(s, 1, 64);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int src = (((k >> 3) & 1) << 5) | (((k >> 2) & 1) << 4) | (((k >> 1) & 1) << 3) | ((k & 1) << 2);
+        out[k] = readlane_d(s, src);
+    }
+}
+
+// ub[u] = (sum of b+ over the data rows of unique row u, sum of b-)
+__global__ __launch_bounds__(256) void bsum_kernel(const int32_t* __restrict__ umem_off,
+                                                   const int32_t* __restrict__ umem,
+                                                   const zd* __restrict__ d_rows, int64_t U,
+                                                   zd* __restrict__ ub) {
+    const int64_t u = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (u >= U) return;
+    zd bp{0.0, 0.0}, bm{0.0, 0.0};
+    for (int k = umem_off[u]; k < umem_off[u + 1]; ++k) {
+        const int64_t r = umem[k];
+        const zd d0 = d_rows[2 * r], d1 = d_rows[2 * r + 1];
+        bp = bp + 0.5 * (d0 + d1);
+        const zd df = d0 - d1;                    // (d0 - d1) / (2i) = -i (d0 - d1) / 2
+        bm = bm + zd{0.5 * df.y, -0.5 * df.x};
+    }
+    ub[2 * u] = bp;
+    ub[2 * u + 1] = bm;
+}
+
+// Partial over one work item of
+//   WITHX = false:  c+- = Re(A^H B+-) and tr = sum mult |A|^2
+//   WITHX = true:   r+- = Re(A^H (B+- - mult A x+-))
+// written to rpart[slot][h*nz + z] (and the trace at [2 nz]).
+template <int ZPL, bool WITHX>
+__global__ __launch_bounds__(256) void resid_kernel(const uint32_t* __restrict__ urows,
+                                                    const Item* __restrict__ items,
+                                                    const int32_t* __restrict__ sched,
+                                                    const zd* __restrict__ g64,
+                                                    const double* __restrict__ freq, double eps,
+                                                    double dz, int ncls, int nz,
+                                                    const zd* __restrict__ ub,
+                                                    const double* __restrict__ x,
+                                                    const int32_t* __restrict__ conv,
+                                                    double* __restrict__ rpart) {
+    __shared__ double s_acc[4][2][ZPL * 64];
+    __shared__ double s_tr[4];
+    const Item it = items[sched[blockIdx.x]];
+    if (WITHX && conv[it.pair]) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int n = it.row_end - it.row_begin;
+    double xv[2][ZPL];
+#pragma unroll
+    for (int q = 0; q < ZPL; ++q) {
+        const int z = lane + 64 * q;
+        xv[0][q] = (WITHX && z < nz) ? x[size_t(it.pair) * 2 * nz + z] : 0.0;
+        xv[1][q] = (WITHX && z < nz) ? x[size_t(it.pair) * 2 * nz + nz + z] : 0.0;
+    }
+    double acc[2][ZPL], tr[ZPL];
+#pragma unroll
+    for (int q = 0; q < ZPL; ++q) acc[0][q] = acc[1][q] = tr[q] = 0.0;
+
+    for (int b0 = 0; b0 < n; b0 += 16) {
+        zd P[4][ZPL];
+        URow u[4];
+        bool valid[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = b0 + 4 * j + wv;
+            valid[j] = r < n;
+            u[j] = valid[j] ? load_urow(urows, int64_t(it.row_begin) + r) : URow{0, 0, 0, 0};
+            const int64_t fb = int64_t(u[j].f) * ncls;
+#pragma unroll
+            for (int q = 0; q < ZPL; ++q) {
+                const int z = lane + 64 * q;
+                P[j][q] = zd{0.0, 0.0};
+                if (valid[j] && z < nz) P[j][q] = g64[(fb + u[j].cr) * nz + z] * g64[(fb + u[j].cs) * nz + z];
+            }
+        }
+        double y[16];
+        if (WITHX) {
+            double v[16];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll
+                for (int q = 0; q < ZPL; ++q) {
+                    a0 += P[j][q].x * xv[0][q];
+                    a1 += P[j][q].y * xv[0][q];
+                    a2 += P[j][q].x * xv[1][q];
+                    a3 += P[j][q].y * xv[1][q];
+                }
+                v[4 * j] = a0;
+                v[4 * j + 1] = a1;
+                v[4 * j + 2] = a2;
+                v[4 * j + 3] = a3;
+            }
+            butterfly16(v, y, lane);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (!valid[j]) continue;
+            const int64_t row = int64_t(it.row_begin) + b0 + 4 * j + wv;
+            const zd w = omega_of(freq[u[j].f], eps);
+            const zd W = dz * (w * w);
+            zd ep = ub[2 * row], em = ub[2 * row + 1];
+            if (WITHX) {
+                const double m = double(u[j].mult);
+                ep = ep - m * (W * zd{y[4 * j], y[4 * j + 1]});
+                em = em - m * (W * zd{y[4 * j + 2], y[4 * j + 3]});
+            }
+            const zd cp = zconj(W) * ep, cm = zconj(W) * em;
+            const double mw2 = double(u[j].mult) * zabs2(W);
+#pragma unroll
+            for (int q = 0; q < ZPL; ++q) {
+                acc[0][q] += P[j][q].x * cp.x + P[j][q].y * cp.y;
+                acc[1][q] += P[j][q].x * cm.x + P[j][q].y * cm.y;
+                if (!WITHX) tr[q] += mw2 * zabs2(P[j][q]);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < ZPL; ++q) {
+        s_acc[wv][0][q * 64 + lane] = acc[0][q];
+        s_acc[wv][1][q * 64 + lane] = acc[1][q];
+    }
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < ZPL; ++q) t += tr[q];
+    t = wave_sum(t);
+    if (lane == 0) s_tr[wv] = t;
+    __syncthreads();
+    double* out = rpart + size_t(it.slot) * (2 * nz + 1);
+    for (int e = tid; e < 2 * nz; e += 256) {
+        const int h = e / nz, z = e - h * nz;
+        out[e] = s_acc[0][h][z] + s_acc[1][h][z] + s_acc[2][h][z] + s_acc[3][h][z];
+    }
+    if (tid == 0) out[2 * nz] = WITHX ? 0.0 : (s_tr[0] + s_tr[1] + s_tr[2] + s_tr[3]);
+}
+
+// Born forward map: for each unique row of an item, A.v[u] and A.v[-u],
+// scattered to every data row it stands for.
+__global__ __launch_bounds__(256) void forward_kernel(const uint32_t* __restrict__ urows,
+                                                     const Item* __restrict__ items,
+                                                     const int32_t* __restrict__ pair_u,
+                                                     const int32_t* __restrict__ umem_off,
+                                                     const int32_t* __restrict__ umem,
+                                                     const zd* __restrict__ g64,
+                                                     const double* __restrict__ freq, double eps,
+                                                     double dz, int ncls, int nz,
+                                                     const zd* __restrict__ v, zd* __restrict__ d_rows) {
+    const Item it = items[blockIdx.x];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int u0 = pair_u[2 * it.pair], u1 = pair_u[2 * it.pair + 1];
+    for (int r = it.row_begin + wv; r < it.row_end; r += 4) {
+        const URow u = load_urow(urows, r);
+        const int64_t fb = int64_t(u.f) * ncls;
+        double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        for (int z = lane; z < nz; z += 64) {
+            const zd P = g64[(fb + u.cr) * nz + z] * g64[(fb + u.cs) * nz + z];
+            const zd q0 = P * v[size_t(u0) * nz + z];
+            const zd q1 = P * v[size_t(u1) * nz + z];
+            a0 += q0.x;
+            a1 += q0.y;
+            a2 += q1.x;
+            a3 += q1.y;
+        }
+        a0 = wave_sum(a0);
+        a1 = wave_sum(a1);
+        a2 = wave_sum(a2);
+        a3 = wave_sum(a3);
+        const zd w = omega_of(freq[u.f], eps);
+        const zd W = dz * (w * w);
+        const zd d0 = W * zd{a0, a1}, d1 = W * zd{a2, a3};
+        for (int k = umem_off[r] + lane; k < umem_off[r + 1]; k += 64) {
+            const int64_t dr = umem[k];
+            d_rows[2 * dr] = d0;
+            d_rows[2 * dr + 1] = d1;
+        }
+    }
+}
+
+// ------------------------------------------------------------- launchers ---
+hipError_t launch_bsum(const edt_plan* p, const zd* d_rows, zd* ub, hipStream_t st) {
+    if (p->n_urows == 0) return hipSuccess;
+    const unsigned blocks = unsigned((p->n_urows + 255) / 256);
+    hipLaunchKernelGGL(bsum_kernel, dim3(blocks), dim3(256), 0, st,
+                       dptr<const int32_t>(p, p->lay.umem_off), dptr<const int32_t>(p, p->lay.umem),
+                       d_rows, p->n_urows, ub);
+    return hipGetLastError();
+}
+
+template <int ZPL>
+static hipError_t launch_resid_z(const edt_plan* p, const zd* g64, const zd* ub, const double* x,
+                                 const int32_t* conv, double* rpart, hipStream_t st) {
+    const unsigned nit = unsigned(p->items.size());
+    if (nit == 0) return hipSuccess;
+    if (x)
+        hipLaunchKernelGGL((resid_kernel<ZPL, true>), dim3(nit), dim3(256), 0, st,
+                           dptr<const uint32_t>(p, p->lay.urows), dptr<const Item>(p, p->lay.items),
+                           dptr<const int32_t>(p, p->lay.sched), g64, dptr<const double>(p, p->lay.freq),
+                           p->eps, p->dz, p->n_cls, p->nz, ub, x, conv, rpart);
+    else
+        hipLaunchKernelGGL((resid_kernel<ZPL, false>), dim3(nit), dim3(256), 0, st,
+                           dptr<const uint32_t>(p, p->lay.urows), dptr<const Item>(p, p->lay.items),
+                           dptr<const int32_t>(p, p->lay.sched), g64, dptr<const double>(p, p->lay.freq),
+                           p->eps, p->dz, p->n_cls, p->nz, ub, x, conv, rpart);
+    return hipGetLastError();
+}
+
+hipError_t launch_resid(const edt_plan* p, const zd* g64, const zd* ub, const double* x,
+                        const int32_t* conv, double* rpart, hipStream_t st) {
+    switch ((p->nz + 63) / 64) {
+        case 1: return launch_resid_z<1>(p, g64, ub, x, conv, rpart, st);
+        case 2: return launch_resid_z<2>(p, g64, ub, x, conv, rpart, st);
+        case 3: return launch_resid_z<3>(p, g64, ub, x, conv, rpart, st);
+        case 4: return launch_resid_z<4>(p, g64, ub, x, conv, rpart, st);
+        case 5: return launch_resid_z<5>(p, g64, ub, x, conv, rpart, st);
+        case 6: return launch_resid_z<6>(p, g64, ub, x, conv, rpart, st);
+        case 7: return launch_resid_z<7>(p, g64, ub, x, conv, rpart, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_forward(const edt_plan* p, const zd* g64, const zd* v, zd* d_rows, hipStream_t st) {
+    const unsigned nit = unsigned(p->items.size());
+    if (nit == 0) return hipSuccess;
+    hipLaunchKernelGGL(forward_kernel, dim3(nit), dim3(256), 0, st, dptr<const uint32_t>(p, p->lay.urows),
+                       dptr<const Item>(p, p->lay.items), dptr<const int32_t>(p, p->lay.pair_u),
+                       dptr<const int32_t>(p, p->lay.umem_off), dptr<const int32_t>(p, p->lay.umem), g64,
+                       dptr<const double>(p, p->lay.freq), p->eps, p->dz, p->n_cls, p->nz, v, d_rows);
+    return hipGetLastError();
+}
+
+}  // namespace edt

@@ -1,0 +1,205 @@
+"""Python face of libedt: a Plan owns the host plan, its device copy and the
+workspace; every method marshals torch tensors into one C-ABI call on the
+current HIP stream.  No arithmetic of the method happens here."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+
+__all__ = ["Plan", "solve"]
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """Rows, classes and work items of one survey, resident on one GPU.
+
+    ``survey`` needs: dim, n_mid, d_mid, n_off, d_off, freqs, eps, nz, z0, dz,
+    kappa, vel (layer velocities; vel[0] fixes c_top for the evanescent cut)
+    and zif (interface depths).
+    """
+
+    def __init__(self, survey, chunk_rows: int = 0, device: str = "cuda"):
+        L = _lib.load()
+        self.device = torch.device(device)
+        self._freq = np.ascontiguousarray(survey.freqs, dtype=np.float64)
+        self._vel = np.ascontiguousarray(survey.vel, dtype=np.float64)
+        self._zif = np.ascontiguousarray(survey.zif, dtype=np.float64)
+        dp = C.POINTER(C.c_double)
+        sv = _lib.Survey(int(survey.dim), int(survey.n_mid), float(survey.d_mid),
+                         int(getattr(survey, "n_off", 0)), float(getattr(survey, "d_off", 0.0)),
+                         int(self._freq.shape[0]), self._freq.ctypes.data_as(dp), float(survey.eps),
+                         int(survey.nz), float(survey.z0), float(survey.dz), float(survey.kappa))
+        ly = _lib.Layers(int(self._vel.shape[0]), self._vel.ctypes.data_as(dp),
+                         self._zif.ctypes.data_as(dp) if self._zif.size else None)
+        h = C.c_void_p()
+        _lib.check(L.edt_plan_create(C.byref(sv), C.byref(ly), int(chunk_rows), C.byref(h)),
+                   "edt_plan_create")
+        self._h = h
+        info = _lib.PlanInfo()
+        _lib.check(L.edt_plan_query(h, C.byref(info)), "edt_plan_query")
+        self.info = {k: getattr(info, k) for k, _ in _lib.PlanInfo._fields_}
+        self.nz = int(survey.nz)
+        self.n_km = int(info.n_km)
+        self.n_pairs = int(info.n_pairs)
+        self.n_rows = int(info.n_rows)
+        self.n_layers = int(info.n_layers)
+        self.table_shape = (int(info.n_freq), int(info.n_cls), int(info.nz))
+        self._dev_plan = None
+        self._work = None
+
+    # ----------------------------------------------------------- host side --
+    def rowmap(self):
+        """Host copies: row_off, rows (f, cls_r, cls_s), keys, pair_km, cls_k."""
+        L = _lib.load()
+        P, R = self.n_pairs, self.n_rows
+        row_off = np.zeros(P + 1, np.int64)
+        rows = np.zeros((R, 3), np.int32)
+        keys = np.zeros((R, 2), np.int32)
+        pair_km = np.zeros((P, 2), np.int32)
+        cls_k = np.zeros(self.table_shape[1], np.float64)
+        i64p, ip, dp = C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_double)
+        _lib.check(L.edt_plan_rowmap(self._h, row_off.ctypes.data_as(i64p), rows.ctypes.data_as(ip),
+                                     keys.ctypes.data_as(ip), pair_km.ctypes.data_as(ip),
+                                     cls_k.ctypes.data_as(dp)), "edt_plan_rowmap")
+        return dict(row_off=row_off, rows=rows, keys=keys, pair_km=pair_km, cls_k=cls_k)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().edt_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------- device side --
+    def upload(self):
+        """Copy the plan to the GPU and allocate the workspace (once)."""
+        if self._dev_plan is None:
+            L = _lib.load()
+            nb = int(self.info["dev_plan_bytes"])
+            self._dev_plan = torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device)
+            _lib.check(L.edt_plan_upload(self._h, _ptr(self._dev_plan), nb, _stream()), "edt_plan_upload")
+            self._work = torch.empty(max(int(self.info["work_bytes"]), 256), dtype=torch.uint8,
+                                     device=self.device)
+        return self
+
+    def _c128(self, *shape):
+        return torch.empty(*shape, dtype=torch.complex128, device=self.device)
+
+    def green(self, vel, want32: bool = True, out=None):
+        """(g64, g32) tables of shape (n_freq, n_cls, nz)."""
+        self.upload()
+        vel = vel.to(device=self.device, dtype=torch.float64).contiguous()
+        g64 = out[0] if out else self._c128(*self.table_shape)
+        g32 = (out[1] if out else torch.empty(*self.table_shape, dtype=torch.complex64,
+                                              device=self.device)) if want32 else None
+        _lib.check(_lib.load().edt_green(self._h, _ptr(vel), _ptr(g64), _ptr(g32), _stream()), "edt_green")
+        return g64, g32
+
+    def assemble(self, g64, g32, d_rows, prec="fp64", out=None):
+        """(gram[P, nz, nz] lower triangle, rhs[P, 2, nz], trace[P])."""
+        self.upload()
+        P, nz = self.n_pairs, self.nz
+        if out is None:
+            gram = torch.zeros(P, nz, nz, dtype=torch.float64, device=self.device)
+            rhs = torch.empty(P, 2, nz, dtype=torch.float64, device=self.device)
+            trace = torch.empty(P, dtype=torch.float64, device=self.device)
+        else:
+            gram, rhs, trace = out
+        _lib.check(_lib.load().edt_assemble(self._h, _ptr(g64), _ptr(g32), _ptr(d_rows),
+                                            _lib.PRECISIONS[prec], _ptr(gram), _ptr(rhs), _ptr(trace),
+                                            _ptr(self._work), _stream()), "edt_assemble")
+        return gram, rhs, trace
+
+    def solve(self, g64, d_rows, gram, rhs, trace, lambda_rel, refine=False, refine_tol=1e-8,
+              max_refine=8, out=None):
+        """(x[P, 2, nz], v[n_km, nz] complex128, info[P], steps[P])."""
+        self.upload()
+        P, nz = self.n_pairs, self.nz
+        if out is None:
+            x = torch.empty(P, 2, nz, dtype=torch.float64, device=self.device)
+            v = self._c128(self.n_km, nz)
+            info = torch.empty(P, dtype=torch.int32, device=self.device)
+            steps = torch.zeros(P, dtype=torch.int32, device=self.device)
+        else:
+            x, v, info, steps = out
+        opts = _lib.SolveOpts(1 if refine else 0, float(refine_tol), int(max_refine))
+        _lib.check(_lib.load().edt_solve(self._h, _ptr(g64), _ptr(d_rows), _ptr(gram), _ptr(rhs), _ptr(trace),
+                                         float(lambda_rel), C.byref(opts), _ptr(x), _ptr(v), _ptr(info),
+                                         _ptr(steps), _ptr(self._work), _stream()), "edt_solve")
+        return x, v, info, steps
+
+    def forward(self, g64, v, out=None):
+        """Born data rows d_rows[R, 2] (complex128) of the model spectrum v[n_km, nz]."""
+        self.upload()
+        d = out if out is not None else self._c128(self.n_rows, 2)
+        v = v.to(device=self.device, dtype=torch.complex128).contiguous()
+        _lib.check(_lib.load().edt_forward(self._h, _ptr(g64), _ptr(v), _ptr(d), _stream()), "edt_forward")
+        return d
+
+    def adjoint(self, vel, g64, d_rows, chol, trace, x, lambda_rel, grad_v, want_d=True,
+                want_lambda=True, want_vel=True):
+        """(grad_d[R, 2], grad_lambda[1], grad_vel[n_layers]) of a loss with gradient grad_v."""
+        self.upload()
+        vel = vel.to(device=self.device, dtype=torch.float64).contiguous()
+        grad_v = grad_v.to(device=self.device, dtype=torch.complex128).contiguous()
+        gd = self._c128(self.n_rows, 2) if want_d else None
+        gl = torch.zeros(1, dtype=torch.float64, device=self.device) if want_lambda else None
+        gvel = torch.zeros(self.n_layers, dtype=torch.float64, device=self.device) if want_vel else None
+        _lib.check(_lib.load().edt_adjoint(self._h, _ptr(vel), _ptr(g64), _ptr(d_rows), _ptr(chol),
+                                           _ptr(trace), _ptr(x), float(lambda_rel), _ptr(grad_v),
+                                           _ptr(gd), _ptr(gl), _ptr(gvel), _ptr(self._work), _stream()),
+                   "edt_adjoint")
+        return gd, gl, gvel
+
+    # -------------------------------------------------------------- timing --
+    def timing(self, enable: bool = True):
+        _lib.check(_lib.load().edt_timing_enable(self._h, 1 if enable else 0), "edt_timing_enable")
+
+    def timing_read(self):
+        """{kernel name: (total ms, launches)} since the previous read."""
+        L = _lib.load()
+        n = C.c_int(0)
+        cap = 64
+        names = C.create_string_buffer(32 * cap)
+        ms = (C.c_double * cap)()
+        cnt = (C.c_int64 * cap)()
+        _lib.check(L.edt_timing_read(self._h, cap, names, ms, cnt, C.byref(n)), "edt_timing_read")
+        out = {}
+        for k in range(min(n.value, cap)):
+            nm = names.raw[32 * k:32 * k + 32].split(b"\0", 1)[0].decode()
+            out[nm] = (ms[k], int(cnt[k]))
+        return out
+
+    # ------------------------------------------------------------ pipeline --
+    def run(self, vel, d_rows, lambda_rel, prec="fp64", refine=None, refine_tol=1e-8, max_refine=8):
+        """green -> assemble -> solve.  Mixed precisions refine by default."""
+        if refine is None:
+            refine = prec != "fp64"
+        g64, g32 = self.green(vel, want32=prec != "fp64")
+        gram, rhs, trace = self.assemble(g64, g32, d_rows, prec)
+        x, v, info, steps = self.solve(g64, d_rows, gram, rhs, trace, lambda_rel, refine=refine,
+                                       refine_tol=refine_tol, max_refine=max_refine)
+        return dict(v=v, x=x, info=info, steps=steps, gram=gram, rhs=rhs, trace=trace, g64=g64, g32=g32)
+
+
+def solve(survey, d_rows, lambda_rel=None, prec="fp64", **kw):
+    """One-shot solve of a survey's data rows; returns V~ (n_km, nz) complex128."""
+    p = Plan(survey)
+    vel = torch.as_tensor(np.asarray(survey.vel, np.float64), device=p.device)
+    lam = survey.lambda_rel if lambda_rel is None else lambda_rel
+    return p.run(vel, d_rows, lam, prec=prec, **kw)["v"]
