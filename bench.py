@@ -45,7 +45,8 @@ def parse():
     ap.add_argument("--mixed", default="bf16x3", choices=["bf16x3", "fp32"])
     ap.add_argument("--refine-tol", type=float, default=1e-8)
     ap.add_argument("--max-refine", type=int, default=8)
-    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--chunk", type=int, default=0, help="rows per Gram item (0 = planner default)")
+    ap.add_argument("--band", type=int, default=0, help="frequencies per Gram band (0 = planner default)")
     ap.add_argument("--cpu-pairs", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--only", choices=["both", "mixed", "fp64"], default="both")
@@ -137,32 +138,67 @@ def kernel_times(run, steps, torch):
             for k, (ms, n) in t.items()}
 
 
-def roofline(plan, s, ktimes, prec):
-    """Roofline entry of the dominant kernel of one step."""
+def _bf16_mfma_flops(plan, nz):
+    """FP flops the BF16x3 Gram kernel issues to MFMA: per stage of 8 unique
+    rows, every lower 32x32 tile gets three 32x32x16 products."""
+    items, _ = plan.schedule("gram")
+    stages = int(np.sum((items[:, 2] - items[:, 1] + 7) // 8))
+    nt = (nz + 31) // 32
+    return stages * (nt * (nt + 1) // 2) * 3 * 32 * 32 * 16 * 2.0
+
+
+def _f64_mfma_flops(plan, nz):
+    """FP64 flops the FP64 Gram kernel issues to MFMA: per stage of 8 unique
+    rows (16 real rows), every lower 16x16 tile gets four 16x16x4 products."""
+    items, _ = plan.schedule("gram")
+    stages = int(np.sum((items[:, 2] - items[:, 1] + 7) // 8))
+    nb = 2 * ((nz + 31) // 32)
+    return stages * (nb * (nb + 1) // 2) * 4 * 16 * 16 * 4 * 2.0
+
+
+def roofline(plan, s, ktimes, prec, steps):
+    """Roofline entry of the dominant kernel of one step.  Algorithmic work
+    counts the distinct Born rows (rows merged by reciprocity are formed once):
+    the symmetric Gram is 2 U nz (nz+1) flops; a refinement residual is 22 nz
+    FP64 flops per unique row of every pair still iterating (6 to form the row,
+    8 for A x, 8 for A^H e)."""
     info = plan.info
     dom = max(ktimes, key=lambda k: ktimes[k]["ms_per_step"])
-    avg_s = ktimes[dom]["avg_ms"] * 1e-3
+    kt = ktimes[dom]
+    avg_s = kt["avg_ms"] * 1e-3
+    U = info["n_urows"]
     if dom.startswith("gram_"):
         dt = {"gram_bf16x3": "bf16", "gram_fp32": "fp32", "gram_fp64": "fp64"}[dom]
-        ach = info["gram_flops"] / avg_s / 1e12
-        return dom, {"bound": "mfma", "achieved": ach, "peak": PEAK[dt], "unit": "TFLOP/s",
-                     "frac": ach / PEAK[dt], "traffic": None}
-    if dom in ("refine residual", "rhs_trace"):
-        # 16 R nz FP64 flops per refinement step (8 R nz for the right-hand sides),
-        # counting every data row of every pair
-        fl = (16.0 if dom != "rhs_trace" else 8.0) * info["n_rows"] * s.nz
+        fl = 2.0 * U * s.nz * (s.nz + 1)
         ach = fl / avg_s / 1e12
+        out = {"bound": "mfma", "achieved": ach, "peak": PEAK[dt], "unit": "TFLOP/s",
+               "frac": ach / PEAK[dt], "traffic": None,
+               "per_launch": f"2 U nz (nz+1) = {fl:.4g} flop (U = {U} unique rows)"}
+        ex = {"bf16": _bf16_mfma_flops, "fp64": _f64_mfma_flops}.get(dt)
+        if ex is not None:
+            out["mfma_issued_frac"] = ex(plan, s.nz) / avg_s / 1e12 / PEAK[dt]
+        return dom, out
+    if dom == "refine residual":
+        uo = plan.urows()["urow_off"]
+        per_pair = np.diff(uo).astype(np.float64)
+        fl_step = 22.0 * s.nz * float(np.sum(per_pair * steps))   # over all launches of one step
+        ach = fl_step / (kt["ms_per_step"] * 1e-3) / 1e12
         return dom, {"bound": "alu", "achieved": ach, "peak": PEAK["fp64"], "unit": "TFLOP/s",
-                     "frac": ach / PEAK["fp64"], "traffic": None}
+                     "frac": ach / PEAK["fp64"], "traffic": None,
+                     "per_launch": f"22 nz x (unique rows of the pairs still iterating); "
+                                   f"{fl_step / kt['launches_per_step']:.4g} flop per launch on average"}
     if dom == "green":
         by = info["table_elems"] * (16 + (8 if prec != "fp64" else 0))
         ach = by / avg_s / 1e9
         return dom, {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm"], "unit": "GB/s",
-                     "frac": ach / PEAK["hbm"], "traffic": None}
-    by = 3.0 * plan.n_pairs * s.nz * s.nz * 8
+                     "frac": ach / PEAK["hbm"], "traffic": None,
+                     "per_launch": f"table writes {by:.4g} B"}
+    # Cholesky / solves: the Gram is read and the factor written once
+    by = 2.0 * plan.n_pairs * s.nz * (s.nz + 1) / 2 * 8
     ach = by / avg_s / 1e9
     return dom, {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm"], "unit": "GB/s",
-                 "frac": ach / PEAK["hbm"], "traffic": None}
+                 "frac": ach / PEAK["hbm"], "traffic": None,
+                 "per_launch": f"lower triangles read + written {by:.4g} B"}
 
 
 def cpu_baseline_leg(s, plan, runners, n_pairs_sample, torch):
@@ -251,7 +287,7 @@ def main():
         sys.exit(2)
     s = make_config(a.config)
     t0 = time.perf_counter()
-    plan = E.Plan(s, chunk_rows=a.chunk).upload()
+    plan = E.Plan(s, chunk_rows=a.chunk, gram_band=a.band).upload()
     plan_s = time.perf_counter() - t0
     vel = torch.tensor(s.vel, dtype=torch.float64, device="cuda")
     d = synth_inputs(s, plan, vel, torch)
@@ -264,13 +300,15 @@ def main():
         kt = kernel_times(r, max(2, min(a.steps, 5)), torch)
         st = r.steps.cpu().numpy()
         info = r.info.cpu().numpy()
-        res[r.prec] = {"ms_per_step": ms, "wall_ms_per_step": wall, "kernels": kt,
+        res[r.prec] = {"ms_per_step": ms, "wall_ms_per_step": wall, "kernels": kt, "_steps": st,
                        "refine_steps": {"max": int(st.max()), "mean": float(st.mean())},
                        "info_nonzero": int(np.sum((info != 0) & (info != -1)))}
     main_prec = precs[-1]
     t_main = res[main_prec]["ms_per_step"]
     value = plan.n_km / (t_main * 1e-3)
-    dom, roof = roofline(plan, s, res[main_prec]["kernels"], main_prec)
+    dom, roof = roofline(plan, s, res[main_prec]["kernels"], main_prec, res[main_prec]["_steps"])
+    for v in res.values():
+        v.pop("_steps")
     roof["kernel"] = dom
     out = {
         "metric": METRIC, "value": value, "unit": "subproblems/s", "n_gpus": 1, "steps": a.steps,
@@ -281,7 +319,7 @@ def main():
         "config": {"workload": CONFIG_NAMES[a.config], "n_km": plan.n_km, "n_pairs": plan.n_pairs,
                    "nz": s.nz, "n_freq": s.n_freq, "rows": plan.n_rows, "unique_rows": plan.info["n_urows"],
                    "precision": main_prec, "refine_tol": a.refine_tol, "max_refine": a.max_refine,
-                   "chunk_rows": plan.info["chunk_rows"]},
+                   "chunk_rows": plan.info["chunk_rows"], "gram_band": plan.info["gram_band"]},
         "roofline": roof,
     }
     if "fp64" in res and main_prec != "fp64":

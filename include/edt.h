@@ -128,9 +128,10 @@ typedef struct {
                               (f, {|k_r|, |k_s|}) share one row of A */
     int64_t max_rows;      /* rows of the largest pair */
     int64_t n_empty;       /* pairs with no rows */
-    int64_t n_items;       /* work items (pair, row chunk) of the assembly */
+    int64_t n_items;       /* Gram work items (pair, frequency band, <= chunk_rows rows) */
     int n_freq, n_cls, nz, n_layers;
-    int chunk_rows;        /* rows per work item */
+    int chunk_rows;        /* unique rows per Gram work item at most */
+    int gram_band;         /* frequencies per Gram band */
     size_t table_elems;    /* n_freq * n_cls * nz: length of g64 / g32 */
     size_t dev_plan_bytes; /* size of the device copy of the plan */
     size_t work_bytes;     /* workspace needed by assemble / solve / adjoint */
@@ -147,14 +148,31 @@ typedef struct {
 const char* edt_last_error(void);
 
 /*
- * Host planner: enumerates pairs and rows, the |k| classes and the work
- * items (pair, chunk of <= chunk_rows rows) in longest-first order.
- * chunk_rows <= 0 picks the default.  Host only, no HIP calls.
+ * Work-item shape of a plan (0 in a field = default).
+ *   chunk_rows  unique rows per Gram work item at most (default and maximum 2048)
+ *   gram_band   frequencies per Gram band (default: as many as keep one band's
+ *               FP32 table slab, n_cls * nz * 8 bytes per frequency, near
+ *               2.5 MB, so that it stays in one XCD's 4 MB L2)
+ */
+typedef struct {
+    int chunk_rows;
+    int gram_band;
+} edt_plan_opts;
+
+/*
+ * Host planner: enumerates pairs and rows, the |k| classes, the unique rows
+ * (rows of a pair with equal frequency and equal {|k_r|, |k_s|} share their
+ * Born row) and the work items: for the Gram, a pair's rows within one
+ * frequency band (<= chunk_rows of them); for the residual, within two
+ * frequencies.  Both are laid out in an XCD-aware launch order.  opts is
+ * nullable (= defaults).  Host only, no HIP calls.
  * Errors: EDT_EINVAL (dim, sizes, zif[0] <= 0, non-increasing zif, n_cls or
- * n_freq >= 65536), EDT_ENOMEM.  *out is owned by the caller: edt_plan_destroy.
+ * n_freq >= 65536, n_freq * n_cls * nz >= 2^32, chunk_rows or gram_band out of
+ * range), EDT_ENOMEM.
+ * *out is owned by the caller: edt_plan_destroy.
  */
 edt_status edt_plan_create(const edt_survey* survey, const edt_layers* layers,
-                           int chunk_rows, edt_plan** out);
+                           const edt_plan_opts* opts, edt_plan** out);
 edt_status edt_plan_destroy(edt_plan* plan);
 edt_status edt_plan_query(const edt_plan* plan, edt_plan_info* out);
 
@@ -169,6 +187,24 @@ edt_status edt_plan_query(const edt_plan* plan, edt_plan_info* out);
  */
 edt_status edt_plan_rowmap(const edt_plan* plan, int64_t* row_off, int32_t* rows,
                            int32_t* keys, int32_t* pair_km, double* cls_k);
+
+/*
+ * Host copies of the unique rows (nullable outputs): urow_off[n_pairs+1] first
+ * unique row of each pair; urows[n_urows*4] = (f, mult, class r, class s),
+ * sorted by f within a pair; row_unique[n_rows] unique row of each data row.
+ */
+edt_status edt_plan_urows(const edt_plan* plan, int64_t* urow_off, int32_t* urows, int32_t* row_unique);
+
+/*
+ * Host copies of the work items and launch order (for checks and tools).
+ * which 0: Gram items, 1: residual items.  counts[0] = number of items,
+ * counts[1] = length of the launch order (items plus holes).  items (nullable,
+ * counts[0]*3): pair, first and one-past-last unique row; sched (nullable,
+ * counts[1]): item launched by workgroup b, -1 for a hole.  Workgroup b runs
+ * on XCD b % 8.
+ */
+edt_status edt_plan_schedule(const edt_plan* plan, int which, int64_t* counts, int32_t* items,
+                             int32_t* sched);
 
 /*
  * Copy the plan's device tables into a caller device buffer of at least
@@ -191,11 +227,14 @@ edt_status edt_green(const edt_plan* plan, const double* vel_dev, edt_c128* g64,
 
 /*
  * Kernel (b): per pair p, gram[p] (nz x nz, row-major, the lower triangle
- * i >= j is written) = Re(A_p^H A_p) in the given precision, plus, always in
- * FP64 from g64 and the data, rhs[p][0|1][z] = Re(A_p^H b+-) and
+ * i >= j is written) = Re(A_p^H A_p) in the given precision, and, from the
+ * same pass over the rows, rhs[p][0|1][z] = Re(A_p^H b+-) and
  * trace[p] = tr Re(A_p^H A_p).  d_rows[r] = (datum at +k_m, datum at -k_m) of
  * row r, complex128, so b+ = (d0+d1)/2 and b- = (d0-d1)/(2i) (eq. Split).
- * prec EDT_FP64 reads g64; EDT_FP32 / EDT_BF16X3 read g32 (from edt_green).
+ * prec EDT_FP64 reads g64 and gives rhs and trace in FP64.  EDT_FP32 and
+ * EDT_BF16X3 read g32 (from edt_green); their rhs is accumulated in FP32 (an
+ * approximation that the FP64 refinement residual of edt_solve corrects) and
+ * their trace from FP32 rows with FP64 sums (relative error about 1e-8).
  * work: device, >= work_bytes.  Empty pairs get zero Gram, rhs and trace.
  */
 edt_status edt_assemble(const edt_plan* plan, const edt_c128* g64, const edt_c64* g32,

@@ -29,8 +29,13 @@ class PlanInfo(C.Structure):
     _fields_ = [("n_km", C.c_int64), ("n_pairs", C.c_int64), ("n_rows", C.c_int64),
                 ("n_urows", C.c_int64), ("max_rows", C.c_int64), ("n_empty", C.c_int64),
                 ("n_items", C.c_int64), ("n_freq", C.c_int), ("n_cls", C.c_int), ("nz", C.c_int),
-                ("n_layers", C.c_int), ("chunk_rows", C.c_int), ("table_elems", C.c_size_t),
+                ("n_layers", C.c_int), ("chunk_rows", C.c_int), ("gram_band", C.c_int),
+                ("table_elems", C.c_size_t),
                 ("dev_plan_bytes", C.c_size_t), ("work_bytes", C.c_size_t), ("gram_flops", C.c_double)]
+
+
+class PlanOpts(C.Structure):
+    _fields_ = [("chunk_rows", C.c_int), ("gram_band", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -38,7 +43,7 @@ class SolveOpts(C.Structure):
 
 
 EXPORTS = ["edt_last_error", "edt_plan_create", "edt_plan_destroy", "edt_plan_query",
-           "edt_plan_rowmap", "edt_plan_upload", "edt_green", "edt_assemble", "edt_solve",
+           "edt_plan_rowmap", "edt_plan_urows", "edt_plan_schedule", "edt_plan_upload", "edt_green", "edt_assemble", "edt_solve",
            "edt_forward", "edt_adjoint", "edt_timing_enable", "edt_timing_read"]
 
 _lib = None
@@ -56,10 +61,12 @@ def load(path: str = LIB_PATH):
     L.edt_last_error.restype = C.c_char_p
     L.edt_last_error.argtypes = []
     sig = {
-        "edt_plan_create": [C.POINTER(Survey), C.POINTER(Layers), C.c_int, C.POINTER(vp)],
+        "edt_plan_create": [C.POINTER(Survey), C.POINTER(Layers), C.POINTER(PlanOpts), C.POINTER(vp)],
         "edt_plan_destroy": [vp],
         "edt_plan_query": [vp, C.POINTER(PlanInfo)],
         "edt_plan_rowmap": [vp, i64p, ip, ip, ip, dp],
+        "edt_plan_urows": [vp, i64p, ip, ip],
+        "edt_plan_schedule": [vp, C.c_int, i64p, ip, ip],
         "edt_plan_upload": [vp, vp, C.c_size_t, vp],
         "edt_green": [vp, vp, vp, vp, vp],
         "edt_assemble": [vp, vp, vp, vp, C.c_int, vp, vp, vp, vp, vp],

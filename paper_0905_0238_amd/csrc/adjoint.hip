@@ -27,7 +27,8 @@
 namespace edt {
 
 size_t refine_lds_bytes(int nz);
-hipError_t launch_bsum(const edt_plan* p, const zd* d_rows, zd* ub, hipStream_t st);
+hipError_t launch_bsum(const edt_plan* p, const zd* d_rows, zd* ub, hipStream_t st, zd* ubw = nullptr,
+                       float4* ub32 = nullptr);
 
 // ------------------------------------------------------------ 1. pairs ---
 __global__ __launch_bounds__(256) void adj_pair_kernel(const double* __restrict__ chol,
@@ -41,8 +42,8 @@ __global__ __launch_bounds__(256) void adj_pair_kernel(const double* __restrict_
                                                        double* __restrict__ glam_part) {
     extern __shared__ double smem[];
     double* sx = smem;
-    double* sD = sx + 2 * nz;
-    double* sred = sD + 32 * 33;
+    double* sL = sx + 2 * nz;
+    double* sred = sL + size_t(nz) * CBP;
     __shared__ double s_red[8];
     const int p = blockIdx.x, tid = threadIdx.x;
     const int u0 = pair_u[2 * p], u1 = pair_u[2 * p + 1];
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(256) void adj_pair_kernel(const double* __restrict_
         }
     }
     __syncthreads();
-    trisolve2(chol + size_t(p) * nz * nz, nz, sx, sD, sred);
+    trisolve2(chol + size_t(p) * nz * nz, nz, sx, sL, sred);
     double s = 0.0;
     for (int e = tid; e < 2 * nz; e += blockDim.x) {
         const double v = (selfc && e >= nz) ? 0.0 : sx[e];
@@ -387,6 +388,11 @@ __global__ __launch_bounds__(256) void adj_table_kernel(
         const zd t = zconj(kb[l]) * dk;
         out[l] = t.x;
     }
+}
+
+hipError_t configure_adjoint_kernels(int bytes) {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(adj_pair_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 // ------------------------------------------------------------ 4. sums ---

@@ -11,12 +11,13 @@
 namespace edt {
 hipError_t launch_green(const edt_plan* p, const double* vel, zd* g64, float2* g32, hipStream_t st);
 hipError_t launch_gram(const edt_plan* p, edt_precision prec, const zd* g64, const float2* g32,
-                       void* part, hipStream_t st);
+                       const zd* ubw, const float4* ub32, void* part, double* rpart, hipStream_t st);
 hipError_t launch_gram_reduce(const edt_plan* p, edt_precision prec, const void* part, double* gram,
                               hipStream_t st);
 hipError_t launch_rhs_reduce(const edt_plan* p, const double* rpart, double* rhs, double* trace,
                              hipStream_t st);
-hipError_t launch_bsum(const edt_plan* p, const zd* d_rows, zd* ub, hipStream_t st);
+hipError_t launch_bsum(const edt_plan* p, const zd* d_rows, zd* ub, hipStream_t st, zd* ubw = nullptr,
+                       float4* ub32 = nullptr);
 hipError_t launch_resid(const edt_plan* p, const zd* g64, const zd* ub, const double* x,
                         const int32_t* conv, double* rpart, hipStream_t st);
 hipError_t launch_forward(const edt_plan* p, const zd* g64, const zd* v, zd* d_rows, hipStream_t st);
@@ -180,13 +181,20 @@ edt_status edt_assemble(const edt_plan* p, const edt_c128* g64, const edt_c64* g
     const WorkLayout wl = work_layout(p);
     unsigned char* w = static_cast<unsigned char*>(work);
     zd* ub = reinterpret_cast<zd*>(w + wl.ub);
+    zd* ubw = reinterpret_cast<zd*>(w + wl.ubw);
+    float4* ub32 = reinterpret_cast<float4*>(w + wl.ub32);
+    const bool f64 = prec == EDT_FP64;
     const zd* G64 = reinterpret_cast<const zd*>(g64);
-    EDT_TRY(launch_bsum(p, reinterpret_cast<const zd*>(d_rows), ub, stream), "bsum");
-    EDT_TRY(launch_gram(p, prec, G64, reinterpret_cast<const float2*>(g32), w + wl.gram_part, stream),
-            prec == EDT_FP64 ? "gram_fp64" : (prec == EDT_FP32 ? "gram_fp32" : "gram_bf16x3"));
+    EDT_TRY(launch_bsum(p, reinterpret_cast<const zd*>(d_rows), ub, stream, f64 ? ubw : nullptr,
+                        f64 ? nullptr : ub32),
+            "bsum");
+    // one pass over the rows gives the Gram partials and the right-hand side
+    // and trace partials of every item
+    double* rpart = reinterpret_cast<double*>(w + wl.gram_rpart);
+    EDT_TRY(launch_gram(p, prec, G64, reinterpret_cast<const float2*>(g32), ubw, ub32, w + wl.gram_part,
+                        rpart, stream),
+            f64 ? "gram_fp64" : (prec == EDT_FP32 ? "gram_fp32" : "gram_bf16x3"));
     EDT_TRY(launch_gram_reduce(p, prec, w + wl.gram_part, gram, stream), "gram_reduce");
-    double* rpart = reinterpret_cast<double*>(w + wl.rhs_part);
-    EDT_TRY(launch_resid(p, G64, ub, nullptr, nullptr, rpart, stream), "rhs_trace");
     EDT_TRY(launch_rhs_reduce(p, rpart, rhs, trace, stream), "rhs reduce");
     return EDT_OK;
 }

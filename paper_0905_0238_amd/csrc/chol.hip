@@ -6,32 +6,34 @@
 //   (G + lambda I) x+- = c+-,  lambda = lambda_rel tr(G) / nz,
 //   V~(k_m) = x+ + i x-,  V~(-k_m) = x+ - i x-.
 // One workgroup per pair.  The factorisation is left-looking by 32-column
-// panels: the panel is updated from the finished columns (staged through LDS
-// in 32-column tiles) and then factored in LDS.  The factor L overwrites the
-// lower triangle of the Gram in place.  The triangular solves work on
-// 32-blocks: one wave solves the diagonal block with shuffles, the block
-// updates the remaining right-hand sides.
+// panels.  The update of a panel by all finished columns is a dense
+// contraction, P -= L[k0:, :k0] L[k0:k0+32, :k0]^T, done on FP64 MFMA
+// (v_mfma_f64_16x16x4) with the panel held in the accumulators and the
+// operands read straight from the factor in global memory (L2-resident).
+// The updated panel then goes to LDS: one wave factors its 32 x 32 diagonal
+// block in registers (row per lane, columns broadcast with readlane) and the
+// remaining rows are solved against it one row per thread.  The factor L
+// overwrites the lower triangle of the Gram in place.  LDS stays under
+// 70 KiB so two pairs share a CU.
 
 #include "dev_linalg.h"
 
 namespace edt {
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
 // Factor gram[p] + lambda_p I in place and solve for x from rhs.
-// Dynamic LDS: panel m x CBP, tile m x CBP (m <= nz), sx 2nz, sD, sred.
-__global__ __launch_bounds__(256) void chol_solve_kernel(
+// Dynamic LDS: the panel, nz x CBP doubles (reused by the solves afterwards).
+__global__ __launch_bounds__(256, 2) void chol_solve_kernel(
     double* __restrict__ gram, const double* __restrict__ trace, const double* __restrict__ rhs,
     const int64_t* __restrict__ urow_off, const int32_t* __restrict__ pair_u, int nz,
     double lambda_rel, double* __restrict__ lam_out, double* __restrict__ x,
     int32_t* __restrict__ info, int32_t* __restrict__ conv, int32_t* __restrict__ steps) {
     extern __shared__ double smem[];
     double* sP = smem;
-    double* sT = sP + size_t(nz) * CBP;
-    double* sx = sT + size_t(nz) * CBP;
-    double* sD = sx + 2 * nz;
-    double* sred = sD + CB * CBP;
     __shared__ int s_bad;
-    __shared__ double s_red[8];
-    const int p = blockIdx.x, tid = threadIdx.x;
+    __shared__ double s_col[64];
+    const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     double* A = gram + size_t(p) * nz * nz;
     const bool empty = urow_off[p + 1] == urow_off[p];
     const bool selfc = pair_u[2 * p] == pair_u[2 * p + 1];
@@ -49,91 +51,167 @@ __global__ __launch_bounds__(256) void chol_solve_kernel(
         }
         return;
     }
+    const int li = lane & 15, lk = lane >> 4;   // MFMA operand lane: (row, k)
     for (int k0 = 0; k0 < nz; k0 += CB) {
         const int kb = min(CB, nz - k0), m = nz - k0;
-        for (int e = tid; e < m * CB; e += blockDim.x) {
-            const int i = e / CB, j = e % CB;
-            double v = 0.0;
-            if (j < kb && i >= j) {
-                v = A[size_t(k0 + i) * nz + k0 + j];
-                if (i == j) v += lam;
-            }
-            sP[i * CBP + j] = v;
-        }
-        __syncthreads();
+        const int nrb = (m + 15) >> 4;
+        // accumulators: row blocks rb = wv + 4q (q < 4), column blocks 0..1;
+        // v_mfma_f64_16x16x4 lane l, register v holds (row 4v + l/16, column l%16)
+        f64x4 acc[4][2];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int rb = wv + 4 * q;
+                    const int i = 16 * rb + 4 * v + lk, j = 16 * cb + li;
+                    double a = 0.0;
+                    if (rb < nrb && i < m && j < kb && i >= j) {
+                        a = A[size_t(k0 + i) * nz + k0 + j];
+                        if (i == j) a += lam;
+                    }
+                    acc[q][cb][v] = a;
+                }
+        // P -= L[k0+i][t] L[k0+j][t], t < k0: 32 finished columns at a time
+        // are staged in LDS (coalesced), then four columns per MFMA
         for (int t0 = 0; t0 < k0; t0 += CB) {
             for (int e = tid; e < m * CB; e += blockDim.x) {
-                const int i = e / CB, t = e % CB;
-                sT[i * CBP + t] = A[size_t(k0 + i) * nz + t0 + t];
+                const int i = e / CB, c = e % CB;
+                sP[i * CBP + c] = A[size_t(k0 + i) * nz + t0 + c];
             }
             __syncthreads();
-            // P[i][j] -= sum_t T[i][t] T[j][t], 4 rows x 4 columns per thread
-            const int nbi = (m + 3) / 4;
-            for (int e = tid; e < nbi * (CB / 4); e += blockDim.x) {
-                const int bi = e / (CB / 4), bj = e % (CB / 4);
-                const int i0 = 4 * bi, j0 = 4 * bj;
-                if (j0 >= kb || i0 + 3 < j0) continue;
-                double s[4][4] = {};
-                for (int t = 0; t < CB; ++t) {
-                    double a[4], b[4];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        a[q] = (i0 + q < m) ? sT[(i0 + q) * CBP + t] : 0.0;
-                        b[q] = sT[(j0 + q) * CBP + t];
+            for (int kk = 0; kk < CB; kk += 4) {
+                const double b0 = (li < kb) ? sP[li * CBP + kk + lk] : 0.0;
+                const double b1 = (16 + li < kb) ? sP[(16 + li) * CBP + kk + lk] : 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int rb = wv + 4 * q;
+                    if (rb < nrb) {
+                        const int i = 16 * rb + li;
+                        const double a = (i < m) ? -sP[i * CBP + kk + lk] : 0.0;
+                        acc[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc[q][0], 0, 0, 0);
+                        acc[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc[q][1], 0, 0, 0);
                     }
-#pragma unroll
-                    for (int qi = 0; qi < 4; ++qi)
-#pragma unroll
-                        for (int qj = 0; qj < 4; ++qj) s[qi][qj] += a[qi] * b[qj];
                 }
-#pragma unroll
-                for (int qi = 0; qi < 4; ++qi)
-#pragma unroll
-                    for (int qj = 0; qj < 4; ++qj) {
-                        const int i = i0 + qi, j = j0 + qj;
-                        if (i < m && j < kb && i >= j) sP[i * CBP + j] -= s[qi][qj];
-                    }
             }
             __syncthreads();
         }
-        // factor the m x kb panel (right-looking inside the panel)
-        for (int j = 0; j < kb; ++j) {
-            if (tid == 0) {
-                double d = sP[j * CBP + j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int rb = wv + 4 * q;
+                    const int i = 16 * rb + 4 * v + lk, j = 16 * cb + li;
+                    if (rb < nrb && i < m) sP[i * CBP + j] = acc[q][cb][v];
+                }
+        __syncthreads();
+        // factor the kb x kb diagonal block in one wave, in place in LDS (lane j
+        // owns row j); a wave executes its LDS operations in order, so the
+        // fences only keep the compiler from reordering across the steps
+        if (tid < 64) {
+            // lane (bi, bj) = (lane / 8, lane % 8) holds the 4 x 4 block of rows
+            // 4 bi.., columns 4 bj.. (lower blocks only); right-looking, the
+            // pivot column of each step is broadcast through LDS
+            const int bi = tid >> 3, bj = tid & 7;
+            const bool act = bi >= bj;
+            double a[4][4];
+            int bad = 0;   // first failing column of this block (wave-uniform)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int i = 4 * bi + r, jj = 4 * bj + c;
+                    a[r][c] = (act && i < kb && jj < kb && jj <= i) ? sP[i * CBP + jj] : (i == jj ? 1.0 : 0.0);
+                }
+            for (int k = 0; k < kb; ++k) {
+                const int kb4 = k >> 2, kr = k & 3;
+                double dg = a[0][0];
+#pragma unroll
+                for (int q = 1; q < 4; ++q) dg = (kr == q) ? a[q][q] : dg;
+                double d = readlane_d(dg, kb4 * 9);   // lane of diagonal block (kb4, kb4)
                 if (!(d > 0.0) || !isfinite(d)) {
-                    if (s_bad == 0) s_bad = k0 + j + 1;
+                    if (bad == 0) bad = k0 + k + 1;
                     d = 1.0;
                 }
-                sP[j * CBP + j] = sqrt(d);
-            }
-            __syncthreads();
-            const double dj = sP[j * CBP + j];
-            for (int i = j + 1 + tid; i < m; i += blockDim.x) sP[i * CBP + j] /= dj;
-            __syncthreads();
-            const int w = kb - j - 1;
-            if (w > 0)
-                for (int e = tid; e < (m - j - 1) * w; e += blockDim.x) {
-                    const int i = j + 1 + e / w, jj = j + 1 + e % w;
-                    if (i >= jj) sP[i * CBP + jj] -= sP[i * CBP + j] * sP[jj * CBP + j];
+                const double lkk = sqrt(d), inv = 1.0 / lkk;
+                if (act && bj == kb4) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = 4 * bi + r;
+                        double v = a[r][0];
+#pragma unroll
+                        for (int q = 1; q < 4; ++q) v = (kr == q) ? a[r][q] : v;
+                        v = (i == k) ? lkk : v * inv;   // L[i][k] for i >= k
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) a[r][q] = (kr == q && i >= k) ? v : a[r][q];
+                        if (i >= k) s_col[i] = v;
+                    }
                 }
-            __syncthreads();
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                if (act) {
+                    double ci[4], cj[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        ci[q] = s_col[4 * bi + q];
+                        cj[q] = s_col[4 * bj + q];
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            const int i = 4 * bi + r, jj = 4 * bj + c;
+                            if (jj > k && i >= jj) a[r][c] -= ci[r] * cj[c];
+                        }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int i = 4 * bi + r, jj = 4 * bj + c;
+                    if (act && i < kb && jj <= i) {
+                        sP[i * CBP + jj] = a[r][c];
+                        if (i == jj) sP[i * CBP + CB] = 1.0 / a[r][c];   // reciprocal pivot
+                    }
+                }
+            if (tid == 0 && bad != 0 && s_bad == 0) s_bad = bad;
         }
-        for (int e = tid; e < m * CB; e += blockDim.x) {
+        __syncthreads();
+        // rows below the diagonal block: x L_kk^T = P[i][0:kb], one thread per row
+        for (int i = kb + tid; i < m; i += blockDim.x) {
+            double* row = sP + i * CBP;
+            for (int t = 0; t < kb; ++t) {
+                double s = row[t];
+                for (int q = 0; q < t; ++q) s -= row[q] * sP[t * CBP + q];
+                s *= sP[t * CBP + CB];
+                row[t] = s;
+                A[size_t(k0 + i) * nz + k0 + t] = s;
+            }
+        }
+        for (int e = tid; e < kb * CB; e += blockDim.x) {
             const int i = e / CB, j = e % CB;
-            if (j < kb && i >= j) A[size_t(k0 + i) * nz + k0 + j] = sP[i * CBP + j];
+            if (j <= i) A[size_t(k0 + i) * nz + k0 + j] = sP[i * CBP + j];
         }
         __syncthreads();
     }
+    // triangular solves (LDS reused)
+    double* sx = smem;
+    double* sL = sx + 2 * nz;
+    double* sred = sL + size_t(nz) * CBP;
     for (int e = tid; e < 2 * nz; e += blockDim.x) sx[e] = rhs[size_t(p) * 2 * nz + e];
     __syncthreads();
-    trisolve2(A, nz, sx, sD, sred);
+    trisolve2(A, nz, sx, sL, sred);
     for (int e = tid; e < 2 * nz; e += blockDim.x)
         x[size_t(p) * 2 * nz + e] = (selfc && e >= nz) ? 0.0 : sx[e];
     if (tid == 0) {
         info[p] = s_bad;
         conv[p] = 0;
     }
-    (void)s_red;
 }
 
 // One refinement step for every unconverged pair:
@@ -146,8 +224,8 @@ __global__ __launch_bounds__(256) void refine_update_kernel(
     int32_t* __restrict__ steps, double tol) {
     extern __shared__ double smem[];
     double* sx = smem;
-    double* sD = sx + 2 * nz;
-    double* sred = sD + CB * CBP;
+    double* sL = sx + 2 * nz;
+    double* sred = sL + size_t(nz) * CBP;
     __shared__ double s_red[8];
     const int p = blockIdx.x, tid = threadIdx.x;
     if (conv[p]) return;
@@ -157,12 +235,19 @@ __global__ __launch_bounds__(256) void refine_update_kernel(
     double* xp = x + size_t(p) * 2 * nz;
     const double lp = lam[p];
     for (int e = tid; e < 2 * nz; e += blockDim.x) {
-        double s = 0.0;
-        for (int k = k0; k < k1; ++k) s += rpart[size_t(k) * w + e];
+        // eight independent partial sums keep eight loads in flight; the
+        // combination order is fixed, so the result is deterministic
+        double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int k = k0;
+        for (; k + 8 <= k1; k += 8)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s8[q] += rpart[size_t(k + q) * w + e];
+        for (int q = 0; k < k1; ++k, ++q) s8[q] += rpart[size_t(k) * w + e];
+        const double s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
         sx[e] = (selfc && e >= nz) ? 0.0 : s - lp * xp[e];
     }
     __syncthreads();
-    trisolve2(gram + size_t(p) * nz * nz, nz, sx, sD, sred);
+    trisolve2(gram + size_t(p) * nz * nz, nz, sx, sL, sred);
     double dn = 0.0, xn = 0.0;
     for (int e = tid; e < 2 * nz; e += blockDim.x) {
         const double d = (selfc && e >= nz) ? 0.0 : sx[e];
@@ -204,15 +289,30 @@ __global__ __launch_bounds__(256) void recombine_kernel(const double* __restrict
 }
 
 // ------------------------------------------------------------- launchers ---
-// Allow the factorisation kernel the large dynamic LDS it needs (gfx950 has
-// 160 KiB per CU).
-hipError_t configure_kernels() {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(chol_solve_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 256);
+size_t refine_lds_bytes(int nz) { return trisolve_lds_doubles(nz) * sizeof(double); }
+size_t chol_lds_bytes(int nz) {
+    const size_t panel = size_t(nz) * CBP * sizeof(double);
+    const size_t solve = refine_lds_bytes(nz);
+    return panel > solve ? panel : solve;
 }
 
-size_t chol_lds_bytes(int nz) { return (size_t(2) * nz * CBP + 2 * nz + CB * CBP + 16 * CB) * sizeof(double); }
-size_t refine_lds_bytes(int nz) { return (size_t(2) * nz + CB * CBP + 16 * CB) * sizeof(double); }
+// Allow the factorisation kernel more than 64 KiB of dynamic LDS (gfx950 has
+// 160 KiB per CU).
+hipError_t configure_adjoint_kernels(int bytes);
+hipError_t configure_gram_kernels();
+// The largest dynamic LDS any supported depth count (nz <= 256) needs.
+static int max_dynamic_lds() { return int(chol_lds_bytes(256)); }
+hipError_t configure_kernels() {
+    const int bytes = max_dynamic_lds();
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(chol_solve_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(refine_update_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess) e = configure_adjoint_kernels(bytes);
+    if (e == hipSuccess) e = configure_gram_kernels();
+    return e;
+}
 
 hipError_t launch_chol(const edt_plan* p, double* gram, const double* trace, const double* rhs,
                        double lambda_rel, double* lam, double* x, int32_t* info, int32_t* conv,
@@ -230,7 +330,7 @@ hipError_t launch_refine_update(const edt_plan* p, const double* gram, const dou
                                 hipStream_t st) {
     if (p->n_pairs == 0) return hipSuccess;
     hipLaunchKernelGGL(refine_update_kernel, dim3(unsigned(p->n_pairs)), dim3(256),
-                       refine_lds_bytes(p->nz), st, gram, rpart, dptr<const int32_t>(p, p->lay.pair_item),
+                       refine_lds_bytes(p->nz), st, gram, rpart, dptr<const int32_t>(p, p->lay.pair_ritem),
                        dptr<const int32_t>(p, p->lay.pair_u), p->nz, lam, x, conv, steps, tol);
     return hipGetLastError();
 }

@@ -64,6 +64,14 @@ __device__ __forceinline__ URow load_urow(const uint32_t* urows, int64_t r) {
     return URow{int(a & 0xFFFFu), int(a >> 16), int(b & 0xFFFFu), int(b >> 16)};
 }
 
+// Value of lane l (uniform index) of a double register, as a scalar.
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(u), l);
+    const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(u >> 32), l);
+    return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+
 // Sum of a double over the 64 lanes of a wave (every lane gets the total).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

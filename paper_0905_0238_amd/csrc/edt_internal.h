@@ -17,10 +17,18 @@ struct Item {
     int32_t slot;        // index of this item's partial-result slot
 };
 
+// Per-unique-row record of the Gram kernels, formed by the planner.
+struct GRow {
+    uint32_t off_r, off_s;   // table offsets (f n_cls + class) nz of g(k_r) and g(k_s)
+    float sw;                // sqrt(mult), correctly rounded
+    float mt;                // mult
+};
+
 // Byte offsets of the sections of the device copy of the plan.
 struct DevLayout {
     size_t freq, zif, cls_k, row_off, pair_u, rows, urow_off, urows, umem_off, umem,
-        row_unique, urow_pair, tab_off, tab_ent, items, sched, pair_item, total;
+        row_unique, urow_pair, tab_off, tab_ent, items, sched, pair_item, ritems, rsched, pair_ritem,
+        grow, gsc, total;
 };
 
 constexpr int kMaxLayers = 64;   // layer-recursion state is held in LDS
@@ -50,15 +58,21 @@ struct edt_plan {
     std::vector<int32_t> umem;           // [R] data rows, grouped
     std::vector<int32_t> row_unique;     // [R] unique row of each data row
     std::vector<int32_t> urow_pair;      // [U] pair of each unique row
+    std::vector<edt::GRow> grow;         // [U] table offsets and scales (Gram kernels)
+    std::vector<double> gsc;             // [U] |w^2 dz| sqrt(mult) (FP64 Gram row scale)
     // table-entry contributors (adjoint): entry e = f*n_cls + c receives from
     // unique rows that use class c at frequency f; tab_ent = (row, other class)
     std::vector<int32_t> tab_off;        // [n_freq*n_cls + 1]
     std::vector<int32_t> tab_ent;        // [2 * 2U]
     // work items
     int chunk_rows;
-    std::vector<edt::Item> items;        // pair-major
-    std::vector<int32_t> sched;          // longest-first launch order
+    int gram_band;                       // frequencies per Gram band
+    std::vector<edt::Item> items;        // Gram items (pair, frequency band), pair-major
+    std::vector<int32_t> sched;          // XCD-aware launch order, -1 = hole
     std::vector<int32_t> pair_item;      // [P+1] first item of each pair
+    std::vector<edt::Item> ritems;       // residual items (pair, frequency group), pair-major
+    std::vector<int32_t> rsched;         // XCD-aware launch order, -1 = hole
+    std::vector<int32_t> pair_ritem;     // [P+1] first residual item of each pair
     double gram_flops;
     // device copy
     edt::DevLayout lay;
@@ -85,8 +99,11 @@ inline T* dptr(const edt_plan* p, size_t off) {
 // Workspace layout (bytes); identical for every call on a plan.
 struct WorkLayout {
     size_t ub;          // [U][2] complex128 summed data b+ and b- of each unique row
+    size_t ubw;         // [U][2] complex128 conj(W) ub (FP64 Gram right-hand side)
+    size_t ub32;        // [U] float4 conj(W)/|W| ub (FP32 / BF16x3 Gram right-hand side)
     size_t gram_part;   // [n_items][ntiles][tile] partial Gram tiles (FP64 or FP32)
-    size_t rhs_part;    // [n_items][2*nz + 1] FP64 partial rhs and trace
+    size_t rhs_part;    // [n_ritems][2*nz + 1] FP64 partial residuals (refinement, adjoint)
+    size_t gram_rpart;  // [n_items][2*nz + 1] FP64 partial rhs and trace from the Gram kernels
     size_t lam;         // [P] lambda per pair
     size_t conv;        // [P] int32 converged flags
     size_t aux;         // [P][2][nz] FP64 scratch (refinement, adjoint)

@@ -56,7 +56,6 @@ struct Bf16Cfg {
     static constexpr int NTL = NT * (NT + 1) / 2;
     static constexpr int TPW = (NTL + 3) / 4;
     static constexpr int STR = 24;   // bf16 per LDS z-row: 16 real rows + 8 pad (48 B)
-    static constexpr int EPT = NT;   // (8 complex rows x NZP) / 256 threads
 };
 
 template <int NT, int W>
@@ -106,82 +105,181 @@ __device__ __forceinline__ void f32_store_tiles(const f32x16 (&acc)[Bf16Cfg<NT>:
     }
 }
 
+// Per-row records of an item in LDS for the FP32 / BF16x3 kernels:
+// s_row[2 r] = {off_r, off_s, sqrt(mult), mult}, s_row[2 r + 1] = the row's
+// data conj(W)/|W| (b+, b-) in FP32.  Rows are padded to a multiple of 8 with
+// all-zero records (table offset 0, no weight, no data): a padding row loads
+// valid table entries and contributes nothing.
+__device__ __forceinline__ void stage_rows(uint4* s_row, const GRow* __restrict__ grow,
+                                           const float4* __restrict__ ub32, int64_t row_begin, int n,
+                                           int nst, int tid, int nthreads) {
+    for (int e = tid; e < 8 * nst; e += nthreads) {
+        uint4 a = make_uint4(0u, 0u, 0u, 0u), b = a;
+        if (e < n) {
+            const GRow g = grow[row_begin + e];
+            a = make_uint4(g.off_r, g.off_s, __float_as_uint(g.sw), __float_as_uint(g.mt));
+            const float4 w = ub32[row_begin + e];
+            b = make_uint4(__float_as_uint(w.x), __float_as_uint(w.y), __float_as_uint(w.z),
+                           __float_as_uint(w.w));
+        }
+        s_row[2 * e] = a;
+        s_row[2 * e + 1] = b;
+    }
+}
+
+// Producer side of the BF16x3 kernel: raw table values of one stage (8
+// complex rows) at the producer thread's depth.
+struct RawStage {
+    float2 ga[8], gb[8];
+};
+
+// Warp-specialised: waves 0-3 consume bf16 stages from LDS into MFMA, waves
+// 4-7 produce them.  A producer issues the table loads of stage s+2 while it
+// forms stage s+1 (loaded one iteration earlier), so each load has about two
+// MFMA stages to arrive.  A producer thread owns one depth z and all 8 rows
+// of a stage, so it writes its 16 hi and 16 lo values as 16-byte stores; with
+// the 48-byte LDS row pitch any 8 consecutive depths hit distinct bank
+// groups.  Row records come from LDS (the row of a stage is uniform over the
+// wave: broadcast reads, and the table base of a load is a scalar).  Depths
+// nz..NZP-1 are zeroed once per item and never written again.
+// The producers also accumulate the item's right-hand side
+// c+-(z) = Re(A^H B+-) in FP32 (an approximation: the FP64 refinement
+// residual corrects it) and the trace sum mult |A|^2 (per stage in FP32, then
+// in FP64) into rpart[slot][0 .. 2 nz].
 template <int NT>
-__global__ __launch_bounds__(256, 1) void gram_bf16x3_kernel(const uint32_t* __restrict__ urows,
-                                                             const Item* __restrict__ items,
+__global__ __launch_bounds__(512, 1) void gram_bf16x3_kernel(const Item* __restrict__ items,
                                                              const int32_t* __restrict__ sched,
-                                                             const float2* __restrict__ g32, int ncls,
-                                                             int nz, float* __restrict__ part) {
+                                                             const GRow* __restrict__ grow,
+                                                             const float4* __restrict__ ub32,
+                                                             const float2* __restrict__ g32, int nz,
+                                                             float* __restrict__ part,
+                                                             double* __restrict__ rpart, int max_rows) {
     using C = Bf16Cfg<NT>;
     __shared__ __attribute__((aligned(16))) __bf16 sh[2][2][C::NZP * C::STR];
-    const Item it = items[sched[blockIdx.x]];
+    __shared__ double s_tr[4];
+    extern __shared__ __attribute__((aligned(16))) uint4 s_row[];
+    const int32_t k = sched[blockIdx.x];
+    if (k < 0) return;   // hole in the XCD-aware schedule
+    const Item it = items[k];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int n = it.row_end - it.row_begin;
+    const int n = min(it.row_end - it.row_begin, max_rows);
     const int nst = (n + 7) >> 3;
-    f32x16 acc[C::TPW];
+    stage_rows(s_row, grow, ub32, it.row_begin, n, nst, tid, 512);
+    {
+        const int z = tid - 256;
+        if (z >= nz && z < C::NZP) {
+            const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
-    for (int m = 0; m < C::TPW; ++m)
+            for (int b = 0; b < 2; ++b)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) acc[m][v] = 0.0f;
+                for (int h = 0; h < 2; ++h) {
+                    uint4* o = reinterpret_cast<uint4*>(sh[b][h] + z * C::STR);
+                    o[0] = zero;
+                    o[1] = zero;
+                }
+        }
+    }
+    __syncthreads();
 
-    float2 ga[C::EPT], gb[C::EPT];
-    float sw[C::EPT];
-    auto load = [&](int s) {
+    const bool producer = wv >= 4;
+    if (producer) {
+        const int z = tid - 256;               // producer thread -> depth
+        const int zc = min(z, nz - 1);         // clamped: loads are unconditional
+        float cp = 0.0f, cm = 0.0f;
+        double tr = 0.0;
+        auto load = [&](RawStage& R, int s) {
 #pragma unroll
-        for (int e = 0; e < C::EPT; ++e) {
-            const int idx = tid + 256 * e;
-            const int j = idx / C::NZP, z = idx - j * C::NZP;
-            const int r = s * 8 + j;
-            ga[e] = make_float2(0.f, 0.f);
-            gb[e] = make_float2(0.f, 0.f);
-            sw[e] = 0.f;
-            if (r < n && z < nz) {
-                const URow u = load_urow(urows, int64_t(it.row_begin) + r);
-                const int64_t fb = int64_t(u.f) * ncls;
-                ga[e] = g32[(fb + u.cr) * nz + z];
-                gb[e] = g32[(fb + u.cs) * nz + z];
-                sw[e] = sqrtf(float(u.mult));
+            for (int j = 0; j < 8; ++j) {
+                const uint4 a = s_row[2 * (8 * s + j)];
+                const uint32_t o_r = __builtin_amdgcn_readfirstlane(a.x);
+                const uint32_t o_s = __builtin_amdgcn_readfirstlane(a.y);
+                R.ga[j] = (g32 + o_r)[zc];
+                R.gb[j] = (g32 + o_s)[zc];
+            }
+        };
+        auto form = [&](const RawStage& R, int buf, int s) {
+            uint32_t h[8], l[8];
+            float t = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const uint4 a = s_row[2 * (8 * s + j)];
+                const uint4 b = s_row[2 * (8 * s + j) + 1];
+                const float sw = __uint_as_float(a.z), mt = __uint_as_float(a.w);
+                const float px = R.ga[j].x * R.gb[j].x - R.ga[j].y * R.gb[j].y;
+                const float py = R.ga[j].x * R.gb[j].y + R.ga[j].y * R.gb[j].x;
+                cp += px * __uint_as_float(b.x) + py * __uint_as_float(b.y);
+                cm += px * __uint_as_float(b.z) + py * __uint_as_float(b.w);
+                t += mt * (px * px + py * py);
+                const float pr = sw * px, pi = sw * py;
+                const __bf16 hr = __bf16(pr), hm = __bf16(pi);
+                const __bf16 lr = __bf16(pr - float(hr)), lm = __bf16(pi - float(hm));
+                h[j] = pack_bf16x2(hr, hm);
+                l[j] = pack_bf16x2(lr, lm);
+            }
+            tr += double(t);
+            if (z < nz) {
+                uint4* hi = reinterpret_cast<uint4*>(sh[buf][0] + z * C::STR);
+                uint4* lo = reinterpret_cast<uint4*>(sh[buf][1] + z * C::STR);
+                hi[0] = make_uint4(h[0], h[1], h[2], h[3]);
+                hi[1] = make_uint4(h[4], h[5], h[6], h[7]);
+                lo[0] = make_uint4(l[0], l[1], l[2], l[3]);
+                lo[1] = make_uint4(l[4], l[5], l[6], l[7]);
+            }
+        };
+        RawStage R0, R1;   // stage k lives in R(k & 1)
+        load(R0, 0);
+        if (nst > 1) load(R1, 1);
+        form(R0, 0, 0);
+        __syncthreads();
+        // iteration s: stage s is being consumed from buffer s&1
+        for (int s = 0; s < nst; s += 2) {
+            if (s + 2 < nst) load(R0, s + 2);
+            if (s + 1 < nst) form(R1, 1, s + 1);
+            __syncthreads();
+            if (s + 1 < nst) {
+                if (s + 3 < nst) load(R1, s + 3);
+                if (s + 2 < nst) form(R0, 0, s + 2);
+                __syncthreads();
             }
         }
-    };
-    auto store = [&](int buf) {
-        __bf16* hi = sh[buf][0];
-        __bf16* lo = sh[buf][1];
-#pragma unroll
-        for (int e = 0; e < C::EPT; ++e) {
-            const int idx = tid + 256 * e;
-            const int j = idx / C::NZP, z = idx - j * C::NZP;
-            const float pr = sw[e] * (ga[e].x * gb[e].x - ga[e].y * gb[e].y);
-            const float pi = sw[e] * (ga[e].x * gb[e].y + ga[e].y * gb[e].x);
-            const __bf16 hr = __bf16(pr), hm = __bf16(pi);
-            const __bf16 lr = __bf16(pr - float(hr)), lm = __bf16(pi - float(hm));
-            *reinterpret_cast<uint32_t*>(hi + z * C::STR + 2 * j) = pack_bf16x2(hr, hm);
-            *reinterpret_cast<uint32_t*>(lo + z * C::STR + 2 * j) = pack_bf16x2(lr, lm);
+        if (z < nz) {
+            double* rp = rpart + size_t(it.slot) * (2 * nz + 1);
+            rp[z] = double(cp);
+            rp[nz + z] = double(cm);
         }
-    };
-    auto compute = [&](int buf) {
-        const __bf16* hi = sh[buf][0];
-        const __bf16* lo = sh[buf][1];
-        if (wv == 0) bf16_wave_mfma<NT, 0>(acc, hi, lo, lane);
-        else if (wv == 1) bf16_wave_mfma<NT, 1>(acc, hi, lo, lane);
-        else if (wv == 2) bf16_wave_mfma<NT, 2>(acc, hi, lo, lane);
-        else bf16_wave_mfma<NT, 3>(acc, hi, lo, lane);
-    };
-
-    load(0);
-    store(0);
-    __syncthreads();
-    for (int s = 0; s < nst; ++s) {
-        if (s + 1 < nst) load(s + 1);
-        compute(s & 1);
-        if (s + 1 < nst) store((s + 1) & 1);
+        const double t = wave_sum(z < nz ? tr : 0.0);
+        if (lane == 0) s_tr[wv - 4] = t;
+    } else {
+        f32x16 acc[C::TPW];
+#pragma unroll
+        for (int m = 0; m < C::TPW; ++m)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[m][v] = 0.0f;
+        auto compute = [&](int buf) {
+            const __bf16* hi = sh[buf][0];
+            const __bf16* lo = sh[buf][1];
+            if (wv == 0) bf16_wave_mfma<NT, 0>(acc, hi, lo, lane);
+            else if (wv == 1) bf16_wave_mfma<NT, 1>(acc, hi, lo, lane);
+            else if (wv == 2) bf16_wave_mfma<NT, 2>(acc, hi, lo, lane);
+            else bf16_wave_mfma<NT, 3>(acc, hi, lo, lane);
+        };
         __syncthreads();
+        for (int s = 0; s < nst; s += 2) {
+            compute(0);
+            __syncthreads();
+            if (s + 1 < nst) {
+                compute(1);
+                __syncthreads();
+            }
+        }
+        float* out = part + size_t(it.slot) * C::NTL * 1024;
+        if (wv == 0) f32_store_tiles<NT, 0>(acc, out, lane);
+        else if (wv == 1) f32_store_tiles<NT, 1>(acc, out, lane);
+        else if (wv == 2) f32_store_tiles<NT, 2>(acc, out, lane);
+        else f32_store_tiles<NT, 3>(acc, out, lane);
     }
-    float* out = part + size_t(it.slot) * C::NTL * 1024;
-    if (wv == 0) f32_store_tiles<NT, 0>(acc, out, lane);
-    else if (wv == 1) f32_store_tiles<NT, 1>(acc, out, lane);
-    else if (wv == 2) f32_store_tiles<NT, 2>(acc, out, lane);
-    else f32_store_tiles<NT, 3>(acc, out, lane);
+    __syncthreads();
+    if (tid == 0) rpart[size_t(it.slot) * (2 * nz + 1) + 2 * nz] = (s_tr[0] + s_tr[1]) + (s_tr[2] + s_tr[3]);
 }
 
 // ------------------------------------------------------------------ FP32 ---
@@ -191,7 +289,6 @@ struct F32Cfg {
     static constexpr int NTL = NT * (NT + 1) / 2;
     static constexpr int TPW = (NTL + 3) / 4;
     static constexpr int STR = 20;   // floats per LDS z-row: [h][8] + 4 pad (80 B)
-    static constexpr int EPT = NT;
 };
 
 template <int NT, int W>
@@ -225,51 +322,79 @@ __device__ __forceinline__ void f32_wave_mfma(f32x16 (&acc)[F32Cfg<NT>::TPW], co
     }
 }
 
+// Every thread owns one depth z of a stage (8 complex rows), forms it into
+// LDS with 16-byte stores and accumulates the item's right-hand side and
+// trace like the BF16x3 producers; all four waves then run MFMA on it.
 template <int NT>
-__global__ __launch_bounds__(256, 1) void gram_f32_kernel(const uint32_t* __restrict__ urows,
-                                                          const Item* __restrict__ items,
+__global__ __launch_bounds__(256, 1) void gram_f32_kernel(const Item* __restrict__ items,
                                                           const int32_t* __restrict__ sched,
-                                                          const float2* __restrict__ g32, int ncls,
-                                                          int nz, float* __restrict__ part) {
+                                                          const GRow* __restrict__ grow,
+                                                          const float4* __restrict__ ub32,
+                                                          const float2* __restrict__ g32, int nz,
+                                                          float* __restrict__ part,
+                                                          double* __restrict__ rpart, int max_rows) {
     using C = F32Cfg<NT>;
     __shared__ __attribute__((aligned(16))) float sh[2][C::NZP * C::STR];
-    const Item it = items[sched[blockIdx.x]];
+    __shared__ double s_tr[4];
+    extern __shared__ __attribute__((aligned(16))) uint4 s_row[];
+    const int32_t k = sched[blockIdx.x];
+    if (k < 0) return;   // hole in the XCD-aware schedule
+    const Item it = items[k];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int n = it.row_end - it.row_begin;
+    const int n = min(it.row_end - it.row_begin, max_rows);
     const int nst = (n + 7) >> 3;
+    const int z = tid, zc = min(z, nz - 1);
+    stage_rows(s_row, grow, ub32, it.row_begin, n, nst, tid, 256);
+    if (z >= nz && z < C::NZP) {
+        const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) reinterpret_cast<float4*>(sh[b] + z * C::STR)[q] = zero;
+    }
+    __syncthreads();
     f32x16 acc[C::TPW];
 #pragma unroll
     for (int m = 0; m < C::TPW; ++m)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[m][v] = 0.0f;
-    float2 ga[C::EPT], gb[C::EPT];
-    float sw[C::EPT];
+    float2 ga[8], gb[8];
+    float cp = 0.0f, cm = 0.0f;
+    double tr = 0.0;
     auto load = [&](int s) {
 #pragma unroll
-        for (int e = 0; e < C::EPT; ++e) {
-            const int idx = tid + 256 * e;
-            const int j = idx / C::NZP, z = idx - j * C::NZP;
-            const int r = s * 8 + j;
-            ga[e] = make_float2(0.f, 0.f);
-            gb[e] = make_float2(0.f, 0.f);
-            sw[e] = 0.f;
-            if (r < n && z < nz) {
-                const URow u = load_urow(urows, int64_t(it.row_begin) + r);
-                const int64_t fb = int64_t(u.f) * ncls;
-                ga[e] = g32[(fb + u.cr) * nz + z];
-                gb[e] = g32[(fb + u.cs) * nz + z];
-                sw[e] = sqrtf(float(u.mult));
-            }
+        for (int j = 0; j < 8; ++j) {
+            const uint4 a = s_row[2 * (8 * s + j)];
+            const uint32_t o_r = __builtin_amdgcn_readfirstlane(a.x);
+            const uint32_t o_s = __builtin_amdgcn_readfirstlane(a.y);
+            ga[j] = (g32 + o_r)[zc];
+            gb[j] = (g32 + o_s)[zc];
         }
     };
-    auto store = [&](int buf) {
-        float* o = sh[buf];
+    auto store = [&](int buf, int s) {
+        float re[8], im[8];
+        float t = 0.0f;
 #pragma unroll
-        for (int e = 0; e < C::EPT; ++e) {
-            const int idx = tid + 256 * e;
-            const int j = idx / C::NZP, z = idx - j * C::NZP;
-            o[z * C::STR + j] = sw[e] * (ga[e].x * gb[e].x - ga[e].y * gb[e].y);       // k = 2j
-            o[z * C::STR + 8 + j] = sw[e] * (ga[e].x * gb[e].y + ga[e].y * gb[e].x);   // k = 2j+1
+        for (int j = 0; j < 8; ++j) {
+            const uint4 a = s_row[2 * (8 * s + j)];
+            const uint4 b = s_row[2 * (8 * s + j) + 1];
+            const float sw = __uint_as_float(a.z), mt = __uint_as_float(a.w);
+            const float px = ga[j].x * gb[j].x - ga[j].y * gb[j].y;
+            const float py = ga[j].x * gb[j].y + ga[j].y * gb[j].x;
+            cp += px * __uint_as_float(b.x) + py * __uint_as_float(b.y);
+            cm += px * __uint_as_float(b.z) + py * __uint_as_float(b.w);
+            t += mt * (px * px + py * py);
+            re[j] = sw * px;
+            im[j] = sw * py;
+        }
+        tr += double(t);
+        if (z < nz) {
+            // z-row layout: real parts of the 8 rows, then imaginary parts
+            float4* o = reinterpret_cast<float4*>(sh[buf] + z * C::STR);
+            o[0] = make_float4(re[0], re[1], re[2], re[3]);
+            o[1] = make_float4(re[4], re[5], re[6], re[7]);
+            o[2] = make_float4(im[0], im[1], im[2], im[3]);
+            o[3] = make_float4(im[4], im[5], im[6], im[7]);
         }
     };
     auto compute = [&](int buf) {
@@ -280,12 +405,12 @@ __global__ __launch_bounds__(256, 1) void gram_f32_kernel(const uint32_t* __rest
         else f32_wave_mfma<NT, 3>(acc, o, lane);
     };
     load(0);
-    store(0);
+    store(0, 0);
     __syncthreads();
     for (int s = 0; s < nst; ++s) {
         if (s + 1 < nst) load(s + 1);
         compute(s & 1);
-        if (s + 1 < nst) store((s + 1) & 1);
+        if (s + 1 < nst) store((s + 1) & 1, s + 1);
         __syncthreads();
     }
     float* out = part + size_t(it.slot) * C::NTL * 1024;
@@ -293,6 +418,15 @@ __global__ __launch_bounds__(256, 1) void gram_f32_kernel(const uint32_t* __rest
     else if (wv == 1) f32_store_tiles<NT, 1>(acc, out, lane);
     else if (wv == 2) f32_store_tiles<NT, 2>(acc, out, lane);
     else f32_store_tiles<NT, 3>(acc, out, lane);
+    double* rp = rpart + size_t(it.slot) * (2 * nz + 1);
+    if (z < nz) {
+        rp[z] = double(cp);
+        rp[nz + z] = double(cm);
+    }
+    const double t = wave_sum(z < nz ? tr : 0.0);
+    if (lane == 0) s_tr[wv] = t;
+    __syncthreads();
+    if (tid == 0) rp[2 * nz] = (s_tr[0] + s_tr[1]) + (s_tr[2] + s_tr[3]);
 }
 
 // ------------------------------------------------------------------ FP64 ---
@@ -302,7 +436,6 @@ struct F64Cfg {
     static constexpr int NB = 2 * NT;                    // 16-wide blocks
     static constexpr int NBL = NB * (NB + 1) / 2;        // lower 16x16 tiles
     static constexpr int TPW = (NBL + 7) / 8;            // 8 waves
-    static constexpr int EPT = (8 * NZP + 511) / 512;    // formation elements per thread
 };
 
 template <int NT, int W>
@@ -352,56 +485,74 @@ __device__ __forceinline__ void f64_store_tiles(const f64x4 (&acc)[F64Cfg<NT>::T
     }
 }
 
+// Thread t owns depth z = t % 256 and the rows j = t / 256 + 2 i (i < 4) of
+// each stage (the row is uniform across a wave, so its data come through
+// scalar loads).  Besides the Gram tiles, an item yields its exact FP64
+// right-hand side c+-(z) = Re(A^H B+-) and trace sum mult |A|^2 in
+// rpart[slot][0 .. 2 nz].
 template <int NT>
-__global__ __launch_bounds__(512, 1) void gram_f64_kernel(const uint32_t* __restrict__ urows,
-                                                          const Item* __restrict__ items,
+__global__ __launch_bounds__(512, 1) void gram_f64_kernel(const Item* __restrict__ items,
                                                           const int32_t* __restrict__ sched,
-                                                          const zd* __restrict__ g64,
-                                                          const double* __restrict__ freq, double eps,
-                                                          double dz, int ncls, int nz,
-                                                          double* __restrict__ part) {
+                                                          const GRow* __restrict__ grow,
+                                                          const double* __restrict__ gsc,
+                                                          const zd* __restrict__ ubw,
+                                                          const zd* __restrict__ g64, int nz,
+                                                          double* __restrict__ part,
+                                                          double* __restrict__ rpart) {
     using C = F64Cfg<NT>;
     __shared__ __attribute__((aligned(16))) double sh[2][16 * C::NZP];
-    const Item it = items[sched[blockIdx.x]];
+    __shared__ double s_tr[8];
+    const int32_t k = sched[blockIdx.x];
+    if (k < 0) return;   // hole in the XCD-aware schedule
+    const Item it = items[k];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int n = it.row_end - it.row_begin;
     const int nst = (n + 7) >> 3;
+    const int z = tid & 255, hf = __builtin_amdgcn_readfirstlane(tid >> 8);
+    const int zc = min(z, nz - 1);
+    const bool zon = z < nz;
+    // depths nz..NZP-1 of both stage buffers stay zero for the whole item
+    if (z >= nz && z < C::NZP)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) sh[b][(2 * (hf + 2 * (q >> 1)) + (q & 1)) * C::NZP + z] = 0.0;
     f64x4 acc[C::TPW];
 #pragma unroll
     for (int m = 0; m < C::TPW; ++m)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[m][v] = 0.0;
-    zd ga[C::EPT], gb[C::EPT];
-    double sw[C::EPT];
+    zd ga[4], gb[4], bp[4], bm[4];
+    double sw[4];
+    double cp = 0.0, cm = 0.0, tr = 0.0;
     auto load = [&](int s) {
 #pragma unroll
-        for (int e = 0; e < C::EPT; ++e) {
-            const int idx = tid + 512 * e;
-            const int j = idx / C::NZP, z = idx - j * C::NZP;
-            const int r = s * 8 + j;
-            ga[e] = zd{0.0, 0.0};
-            gb[e] = zd{0.0, 0.0};
-            sw[e] = 0.0;
-            if (idx < 8 * C::NZP && r < n && z < nz) {
-                const URow u = load_urow(urows, int64_t(it.row_begin) + r);
-                const int64_t fb = int64_t(u.f) * ncls;
-                ga[e] = g64[(fb + u.cr) * nz + z];
-                gb[e] = g64[(fb + u.cs) * nz + z];
-                const zd w = omega_of(freq[u.f], eps);
-                sw[e] = zabs2(w) * dz * sqrt(double(u.mult));
-            }
+        for (int i = 0; i < 4; ++i) {
+            const int r = s * 8 + hf + 2 * i;
+            const int64_t row = int64_t(it.row_begin) + min(r, n - 1);
+            const GRow g = grow[row];
+            ga[i] = g64[size_t(g.off_r) + zc];
+            gb[i] = g64[size_t(g.off_s) + zc];
+            const bool on = r < n;
+            const zd b0 = ubw[2 * row], b1 = ubw[2 * row + 1];
+            bp[i] = on ? b0 : zd{0.0, 0.0};
+            bm[i] = on ? b1 : zd{0.0, 0.0};
+            sw[i] = on ? gsc[row] : 0.0;
         }
     };
     auto store = [&](int buf) {
         double* o = sh[buf];
 #pragma unroll
-        for (int e = 0; e < C::EPT; ++e) {
-            const int idx = tid + 512 * e;
-            if (idx < 8 * C::NZP) {
-                const int j = idx / C::NZP, z = idx - j * C::NZP;
-                const zd p = ga[e] * gb[e];
-                o[(2 * j) * C::NZP + z] = sw[e] * p.x;
-                o[(2 * j + 1) * C::NZP + z] = sw[e] * p.y;
+        for (int i = 0; i < 4; ++i) {
+            const int j = hf + 2 * i;
+            const zd p = ga[i] * gb[i];
+            cp += p.x * bp[i].x + p.y * bp[i].y;
+            cm += p.x * bm[i].x + p.y * bm[i].y;
+            const double ax = sw[i] * p.x, ay = sw[i] * p.y;
+            tr += ax * ax + ay * ay;
+            if (zon) {
+                o[(2 * j) * C::NZP + z] = ax;
+                o[(2 * j + 1) * C::NZP + z] = ay;
             }
         }
     };
@@ -438,6 +589,22 @@ __global__ __launch_bounds__(512, 1) void gram_f64_kernel(const uint32_t* __rest
         case 6: f64_store_tiles<NT, 6>(acc, out, lane); break;
         default: f64_store_tiles<NT, 7>(acc, out, lane); break;
     }
+    // the two row halves of depth z meet in LDS (stage buffers are free now)
+    double* sc = sh[0];
+    if (hf == 1) {
+        sc[z] = cp;
+        sc[256 + z] = cm;
+    }
+    const double t = wave_sum(zon ? tr : 0.0);
+    if (lane == 0) s_tr[wv] = t;
+    __syncthreads();
+    double* rp = rpart + size_t(it.slot) * (2 * nz + 1);
+    if (hf == 0 && zon) {
+        rp[z] = cp + sc[z];
+        rp[nz + z] = cm + sc[256 + z];
+    }
+    if (tid == 0)
+        rp[2 * nz] = ((s_tr[0] + s_tr[1]) + (s_tr[2] + s_tr[3])) + ((s_tr[4] + s_tr[5]) + (s_tr[6] + s_tr[7]));
 }
 
 // ---------------------------------------------------------------- reduce ---
@@ -472,48 +639,91 @@ __global__ __launch_bounds__(256) void rhs_reduce_kernel(const double* __restric
     const int k0 = pair_item[p], k1 = pair_item[p + 1];
     const int w = 2 * nz + 1;
     for (int e = threadIdx.x; e < w; e += 256) {
-        double s = 0.0;
-        for (int k = k0; k < k1; ++k) s += rpart[size_t(k) * w + e];
+        double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int k = k0;
+        for (; k + 8 <= k1; k += 8)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s8[q] += rpart[size_t(k + q) * w + e];
+        for (int q = 0; k < k1; ++k, ++q) s8[q] += rpart[size_t(k) * w + e];
+        const double s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
         if (e < 2 * nz) rhs[size_t(p) * 2 * nz + e] = s;
         else trace[p] = s;
     }
 }
 
 // ------------------------------------------------------------- launchers ---
+// dynamic LDS of the FP32 / BF16x3 kernels: the row records of an item,
+// padded to a multiple of 8 rows, 32 bytes each
+size_t row_lds_bytes(int64_t chunk_rows) { return size_t((chunk_rows + 7) / 8) * 8 * 32; }
+
+// Row data the Gram kernels read besides the tables (formed by bsum_kernel).
+struct GramRowData {
+    const zd* ubw;        // FP64: conj(W) (b+, b-)
+    const float4* ub32;   // FP32 / BF16x3: conj(W)/|W| (b+, b-)
+};
+
 template <int NT>
 static hipError_t launch_gram_nt(const edt_plan* p, edt_precision prec, const zd* g64,
-                                 const float2* g32, void* part, hipStream_t st) {
-    const uint32_t* urows = dptr<const uint32_t>(p, p->lay.urows);
+                                 const float2* g32, const GramRowData& rd, void* part, double* rpart,
+                                 hipStream_t st) {
     const Item* items = dptr<const Item>(p, p->lay.items);
     const int32_t* sched = dptr<const int32_t>(p, p->lay.sched);
-    const int nit = int(p->items.size());
-    if (nit == 0) return hipSuccess;
+    const GRow* grow = dptr<const GRow>(p, p->lay.grow);
+    const unsigned nb = unsigned(p->sched.size());
+    if (nb == 0) return hipSuccess;
     if (prec == EDT_BF16X3)
-        hipLaunchKernelGGL(gram_bf16x3_kernel<NT>, dim3(nit), dim3(256), 0, st, urows, items, sched,
-                           g32, p->n_cls, p->nz, static_cast<float*>(part));
+        hipLaunchKernelGGL(gram_bf16x3_kernel<NT>, dim3(nb), dim3(512), row_lds_bytes(p->chunk_rows), st,
+                           items, sched, grow, rd.ub32, g32, p->nz, static_cast<float*>(part), rpart,
+                           p->chunk_rows);
     else if (prec == EDT_FP32)
-        hipLaunchKernelGGL(gram_f32_kernel<NT>, dim3(nit), dim3(256), 0, st, urows, items, sched, g32,
-                           p->n_cls, p->nz, static_cast<float*>(part));
+        hipLaunchKernelGGL(gram_f32_kernel<NT>, dim3(nb), dim3(256), row_lds_bytes(p->chunk_rows), st,
+                           items, sched, grow, rd.ub32, g32, p->nz, static_cast<float*>(part), rpart,
+                           p->chunk_rows);
     else
-        hipLaunchKernelGGL(gram_f64_kernel<NT>, dim3(nit), dim3(512), 0, st, urows, items, sched, g64,
-                           dptr<const double>(p, p->lay.freq), p->eps, p->dz, p->n_cls, p->nz,
-                           static_cast<double*>(part));
+        hipLaunchKernelGGL(gram_f64_kernel<NT>, dim3(nb), dim3(512), 0, st, items, sched, grow,
+                           dptr<const double>(p, p->lay.gsc), rd.ubw, g64, p->nz,
+                           static_cast<double*>(part), rpart);
     return hipGetLastError();
 }
 
+template <int NT>
+static hipError_t configure_gram_nt() {
+    const int bytes = int(row_lds_bytes(2048));
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_bf16x3_kernel<NT>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_f32_kernel<NT>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return e;
+}
+
+// Allow the largest item size (2048 rows) for every depth-tile count.
+hipError_t configure_gram_kernels() {
+    hipError_t e = configure_gram_nt<1>();
+    if (e == hipSuccess) e = configure_gram_nt<2>();
+    if (e == hipSuccess) e = configure_gram_nt<3>();
+    if (e == hipSuccess) e = configure_gram_nt<4>();
+    if (e == hipSuccess) e = configure_gram_nt<5>();
+    if (e == hipSuccess) e = configure_gram_nt<6>();
+    if (e == hipSuccess) e = configure_gram_nt<7>();
+    if (e == hipSuccess) e = configure_gram_nt<8>();
+    return e;
+}
+
 hipError_t launch_gram(const edt_plan* p, edt_precision prec, const zd* g64, const float2* g32,
-                       void* part, hipStream_t st) {
+                       const zd* ubw, const float4* ub32, void* part, double* rpart, hipStream_t st) {
     const int NT = (p->nz + 31) / 32;
+    const GramRowData rd{ubw, ub32};
     hipError_t e;
     switch (NT) {
-        case 1: e = launch_gram_nt<1>(p, prec, g64, g32, part, st); break;
-        case 2: e = launch_gram_nt<2>(p, prec, g64, g32, part, st); break;
-        case 3: e = launch_gram_nt<3>(p, prec, g64, g32, part, st); break;
-        case 4: e = launch_gram_nt<4>(p, prec, g64, g32, part, st); break;
-        case 5: e = launch_gram_nt<5>(p, prec, g64, g32, part, st); break;
-        case 6: e = launch_gram_nt<6>(p, prec, g64, g32, part, st); break;
-        case 7: e = launch_gram_nt<7>(p, prec, g64, g32, part, st); break;
-        case 8: e = launch_gram_nt<8>(p, prec, g64, g32, part, st); break;
+        case 1: e = launch_gram_nt<1>(p, prec, g64, g32, rd, part, rpart, st); break;
+        case 2: e = launch_gram_nt<2>(p, prec, g64, g32, rd, part, rpart, st); break;
+        case 3: e = launch_gram_nt<3>(p, prec, g64, g32, rd, part, rpart, st); break;
+        case 4: e = launch_gram_nt<4>(p, prec, g64, g32, rd, part, rpart, st); break;
+        case 5: e = launch_gram_nt<5>(p, prec, g64, g32, rd, part, rpart, st); break;
+        case 6: e = launch_gram_nt<6>(p, prec, g64, g32, rd, part, rpart, st); break;
+        case 7: e = launch_gram_nt<7>(p, prec, g64, g32, rd, part, rpart, st); break;
+        case 8: e = launch_gram_nt<8>(p, prec, g64, g32, rd, part, rpart, st); break;
         default: return hipErrorInvalidValue;
     }
     return e;

@@ -28,11 +28,73 @@ thread_local std::string g_err;
 
 constexpr double kTwoPi = 2.0 * 3.141592653589793;   // == 2.0 * numpy.pi
 constexpr int kDefaultChunk = 2048;
+constexpr int kMaxChunk = 2048;   // row records of an item must fit in LDS
+constexpr int kFreqGroup = 2;     // frequencies per residual work item
+constexpr int kResidRows = 1024;  // rows per residual work item at most
+constexpr int kXcd = 8;           // accelerator dies (separate L2 caches) on MI355X
+constexpr double kL2Slab = 2.5e6; // bytes of FP32 table per Gram band (an XCD's L2 is 4 MB)
 
 inline int64_t signed_of(int64_t n, int64_t N) { return n < (N + 1) / 2 ? n : n - N; }
 inline int64_t wrap(int64_t n, int64_t N) { return ((n % N) + N) % N; }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Split every pair's unique rows (sorted by frequency) into work items that
+// stay inside one band of `band` frequencies and hold at most `max_rows`
+// rows.  Items are pair-major; pair_first[q] is the first item of pair q and
+// band_of[i] the frequency band of item i.
+void split_items(const edt_plan* p, int band, int64_t max_rows, std::vector<edt::Item>& items,
+                 std::vector<int32_t>& pair_first, std::vector<int32_t>& band_of) {
+    items.clear();
+    pair_first.assign(1, 0);
+    band_of.clear();
+    for (int64_t q = 0; q < p->n_pairs; ++q) {
+        int64_t b = p->urow_off[q];
+        while (b < p->urow_off[q + 1]) {
+            const int g = int(p->urows[2 * b] & 0xFFFFu) / band;
+            int64_t e = b;
+            while (e < p->urow_off[q + 1] && e - b < max_rows && int(p->urows[2 * e] & 0xFFFFu) / band == g) ++e;
+            items.push_back(edt::Item{int32_t(q), int32_t(b), int32_t(e), int32_t(items.size())});
+            band_of.push_back(g);
+            b = e;
+        }
+        pair_first.push_back(int32_t(items.size()));
+    }
+}
+
+// XCD-aware launch order.  Workgroup b of a launch runs on XCD b % kXcd and
+// each XCD starts its workgroups in launch order.  Items sorted by (band,
+// rows descending) are cut into kXcd contiguous runs of about equal row count,
+// so each XCD walks a few neighbouring bands (their table slabs stay in its
+// L2) and the XCDs finish together; run x fills positions x, x + kXcd, ...
+// Shorter runs are padded with holes (-1), which exit at once.
+std::vector<int32_t> xcd_schedule(const std::vector<edt::Item>& items, const std::vector<int32_t>& band_of) {
+    std::vector<int32_t> order(items.size());
+    std::iota(order.begin(), order.end(), 0);
+    auto rows = [&](int32_t i) { return int64_t(items[size_t(i)].row_end) - items[size_t(i)].row_begin; };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        if (band_of[size_t(a)] != band_of[size_t(b)]) return band_of[size_t(a)] < band_of[size_t(b)];
+        return rows(a) > rows(b);
+    });
+    int64_t total = 0;
+    for (int32_t i : order) total += rows(i);
+    std::vector<std::vector<int32_t>> run(kXcd);
+    int64_t acc = 0;
+    for (int32_t i : order) {
+        // XCD of an item: where the midpoint of its rows falls in the total
+        const int64_t mid = acc + rows(i) / 2;
+        const int x = total > 0 ? int(std::min<int64_t>(kXcd - 1, mid * kXcd / total)) : 0;
+        run[size_t(x)].push_back(i);
+        acc += rows(i);
+    }
+    size_t len = 0;
+    for (auto& r : run) len = std::max(len, r.size());
+    std::vector<int32_t> sched(len * kXcd, -1);
+    for (int x = 0; x < kXcd; ++x)
+        for (size_t k = 0; k < run[size_t(x)].size(); ++k) sched[k * kXcd + size_t(x)] = run[size_t(x)][k];
+    return sched;
+}
+
 
 edt_status fail(edt_status s, const std::string& m) {
     g_err = m;
@@ -125,10 +187,16 @@ WorkLayout work_layout(const edt_plan* p) {
     const size_t P = size_t(p->n_pairs), nz = size_t(p->nz);
     w.ub = off;
     off = align256(off + size_t(p->n_urows) * 2 * 16);
+    w.ubw = off;
+    off = align256(off + size_t(p->n_urows) * 2 * 16);
+    w.ub32 = off;
+    off = align256(off + size_t(p->n_urows) * 16);
     w.gram_part = off;
     off = align256(off + size_t(p->items.size()) * gram_part_bytes_per_item(p));
     w.rhs_part = off;
-    off = align256(off + size_t(p->items.size()) * (2 * nz + 1) * sizeof(double));
+    off = align256(off + p->ritems.size() * (2 * nz + 1) * sizeof(double));
+    w.gram_rpart = off;
+    off = align256(off + p->items.size() * (2 * nz + 1) * sizeof(double));
     w.lam = off;
     off = align256(off + P * sizeof(double));
     w.conv = off;
@@ -159,14 +227,18 @@ extern "C" {
 
 const char* edt_last_error(void) { return g_err.c_str(); }
 
-edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, int chunk_rows,
+edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_plan_opts* opts,
                            edt_plan** out) {
+    const int chunk_rows = opts ? opts->chunk_rows : 0;
+    const int band_opt = opts ? opts->gram_band : 0;
     if (!s || !l || !out) return fail(EDT_EINVAL, "null argument");
     *out = nullptr;
     if (s->dim != 2 && s->dim != 3) return fail(EDT_EINVAL, "dim must be 2 or 3");
     if (s->n_mid < 2 || !(s->d_mid > 0)) return fail(EDT_EINVAL, "n_mid >= 2 and d_mid > 0 required");
     if (s->n_freq < 1 || s->n_freq >= 65536 || !s->freq_hz) return fail(EDT_EINVAL, "1 <= n_freq < 65536");
     if (s->nz < 1 || s->nz > 1024) return fail(EDT_EINVAL, "1 <= nz <= 1024");
+    if (chunk_rows < 0 || chunk_rows > kMaxChunk) return fail(EDT_EINVAL, "0 <= chunk_rows <= 2048");
+    if (band_opt < 0) return fail(EDT_EINVAL, "gram_band >= 0");
     if (!(s->dz > 0) || !(s->eps >= 0) || !(s->kappa > 0)) return fail(EDT_EINVAL, "dz > 0, eps >= 0, kappa > 0");
     if (s->dim == 3) {
         if (s->n_off < 1 || !(s->d_off > 0)) return fail(EDT_EINVAL, "3D needs n_off >= 1, d_off > 0");
@@ -319,21 +391,42 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, int chunk_r
             p->gram_flops += 2.0 * double(R) * double(p->nz) * double(p->nz + 1);
         }
 
-        // work items: chunks of a pair's unique rows; slots are pair-major
-        p->chunk_rows = chunk_rows > 0 ? chunk_rows : kDefaultChunk;
-        p->pair_item.push_back(0);
-        for (int64_t q = 0; q < p->n_pairs; ++q) {
-            for (int64_t b = p->urow_off[q]; b < p->urow_off[q + 1]; b += p->chunk_rows) {
-                const int64_t e = std::min(p->urow_off[q + 1], b + p->chunk_rows);
-                p->items.push_back(edt::Item{int32_t(q), int32_t(b), int32_t(e), int32_t(p->items.size())});
-            }
-            p->pair_item.push_back(int32_t(p->items.size()));
+        // per-unique-row records of the Gram kernels
+        if (double(p->n_freq) * double(p->n_cls) * double(p->nz) >= 4294967296.0) {
+            delete p;
+            return fail(EDT_EINVAL, "Green's table too large for 32-bit offsets (n_freq * n_cls * nz >= 2^32)");
         }
-        p->sched.resize(p->items.size());
-        std::iota(p->sched.begin(), p->sched.end(), 0);
-        std::stable_sort(p->sched.begin(), p->sched.end(), [&](int32_t a, int32_t b) {
-            return (p->items[a].row_end - p->items[a].row_begin) > (p->items[b].row_end - p->items[b].row_begin);
-        });
+        p->grow.resize(size_t(p->n_urows));
+        p->gsc.resize(size_t(p->n_urows));
+        for (int64_t u = 0; u < p->n_urows; ++u) {
+            const uint32_t a = p->urows[2 * u], b = p->urows[2 * u + 1];
+            const uint32_t f = a & 0xFFFFu, m = a >> 16;
+            const uint64_t base = uint64_t(f) * uint64_t(p->n_cls);
+            edt::GRow& g = p->grow[size_t(u)];
+            g.off_r = uint32_t((base + (b & 0xFFFFu)) * uint64_t(p->nz));
+            g.off_s = uint32_t((base + (b >> 16)) * uint64_t(p->nz));
+            g.sw = std::sqrt(float(m));
+            g.mt = float(m);
+            const double wr = kTwoPi * p->freq[f];
+            p->gsc[size_t(u)] = (wr * wr + p->eps * p->eps) * p->dz * std::sqrt(double(m));
+        }
+
+        // Gram work items: a pair's rows within a band of consecutive
+        // frequencies (at most chunk_rows rows).  The band is sized so that
+        // its FP32 Green's table slab (n_cls x nz entries per frequency) fits
+        // an XCD's L2 with room for the next band; slots are pair-major.
+        p->chunk_rows = chunk_rows > 0 ? chunk_rows : kDefaultChunk;
+        p->gram_band = band_opt > 0 ? std::min(band_opt, p->n_freq)
+                                    : int(std::max<int64_t>(1, std::min<int64_t>(p->n_freq, int64_t(kL2Slab / (double(p->n_cls) * double(p->nz) * 8.0)))));
+        std::vector<int32_t> gband;
+        split_items(p, p->gram_band, p->chunk_rows, p->items, p->pair_item, gband);
+        p->sched = xcd_schedule(p->items, gband);
+
+        // residual work items: a pair's rows within a group of kFreqGroup
+        // frequencies (at most kResidRows rows), scheduled the same way
+        std::vector<int32_t> rgroup;
+        split_items(p, kFreqGroup, kResidRows, p->ritems, p->pair_ritem, rgroup);
+        p->rsched = xcd_schedule(p->ritems, rgroup);
 
         // device image
         edt::DevLayout& L = p->lay;
@@ -355,6 +448,11 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, int chunk_r
         L.items = off;     off = align256(off + std::max<size_t>(1, p->items.size()) * sizeof(edt::Item));
         L.sched = off;     off = align256(off + std::max<size_t>(1, p->sched.size()) * 4);
         L.pair_item = off; off = align256(off + p->pair_item.size() * 4);
+        L.ritems = off;    off = align256(off + std::max<size_t>(1, p->ritems.size()) * sizeof(edt::Item));
+        L.rsched = off;    off = align256(off + std::max<size_t>(1, p->rsched.size()) * 4);
+        L.pair_ritem = off; off = align256(off + p->pair_ritem.size() * 4);
+        L.grow = off;      off = align256(off + std::max<size_t>(1, p->grow.size()) * sizeof(edt::GRow));
+        L.gsc = off;       off = align256(off + std::max<size_t>(1, p->gsc.size()) * 8);
         L.total = off;
         p->host_image.assign(L.total, 0);
         auto put = [&](size_t o, const void* src, size_t n) { if (n) std::memcpy(p->host_image.data() + o, src, n); };
@@ -375,6 +473,11 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, int chunk_r
         put(L.items, p->items.data(), p->items.size() * sizeof(edt::Item));
         put(L.sched, p->sched.data(), p->sched.size() * 4);
         put(L.pair_item, p->pair_item.data(), p->pair_item.size() * 4);
+        put(L.ritems, p->ritems.data(), p->ritems.size() * sizeof(edt::Item));
+        put(L.rsched, p->rsched.data(), p->rsched.size() * 4);
+        put(L.pair_ritem, p->pair_ritem.data(), p->pair_ritem.size() * 4);
+        put(L.grow, p->grow.data(), p->grow.size() * sizeof(edt::GRow));
+        put(L.gsc, p->gsc.data(), p->gsc.size() * 8);
     } catch (const std::bad_alloc&) {
         delete p;
         return fail(EDT_ENOMEM, "out of host memory while planning");
@@ -402,10 +505,44 @@ edt_status edt_plan_query(const edt_plan* p, edt_plan_info* o) {
     o->nz = p->nz;
     o->n_layers = p->n_layers;
     o->chunk_rows = p->chunk_rows;
+    o->gram_band = p->gram_band;
     o->table_elems = size_t(p->n_freq) * size_t(p->n_cls) * size_t(p->nz);
     o->dev_plan_bytes = p->lay.total;
     o->work_bytes = edt::work_layout(p).total;
     o->gram_flops = p->gram_flops;
+    return EDT_OK;
+}
+
+edt_status edt_plan_urows(const edt_plan* p, int64_t* urow_off, int32_t* urows, int32_t* row_unique) {
+    if (!p) return fail(EDT_EINVAL, "null plan");
+    if (urow_off) std::memcpy(urow_off, p->urow_off.data(), p->urow_off.size() * 8);
+    if (urows)
+        for (int64_t u = 0; u < p->n_urows; ++u) {
+            const uint32_t a = p->urows[2 * u], b = p->urows[2 * u + 1];
+            urows[4 * u] = int32_t(a & 0xFFFFu);
+            urows[4 * u + 1] = int32_t(a >> 16);
+            urows[4 * u + 2] = int32_t(b & 0xFFFFu);
+            urows[4 * u + 3] = int32_t(b >> 16);
+        }
+    if (row_unique && !p->row_unique.empty()) std::memcpy(row_unique, p->row_unique.data(), p->row_unique.size() * 4);
+    return EDT_OK;
+}
+
+edt_status edt_plan_schedule(const edt_plan* p, int which, int64_t* counts, int32_t* items,
+                             int32_t* sched) {
+    if (!p || !counts) return fail(EDT_EINVAL, "null argument");
+    if (which != 0 && which != 1) return fail(EDT_EINVAL, "which must be 0 (Gram) or 1 (residual)");
+    const std::vector<edt::Item>& it = which == 0 ? p->items : p->ritems;
+    const std::vector<int32_t>& sc = which == 0 ? p->sched : p->rsched;
+    counts[0] = int64_t(it.size());
+    counts[1] = int64_t(sc.size());
+    if (items)
+        for (size_t i = 0; i < it.size(); ++i) {
+            items[3 * i] = it[i].pair;
+            items[3 * i + 1] = it[i].row_begin;
+            items[3 * i + 2] = it[i].row_end;
+        }
+    if (sched && !sc.empty()) std::memcpy(sched, sc.data(), sc.size() * 4);
     return EDT_OK;
 }
 

@@ -20,13 +20,6 @@
 
 namespace edt {
 
-__device__ __forceinline__ double readlane_d(double v, int l) {
-    const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(u), l);
-    const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(u >> 32), l);
-    return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
-}
-
 // Sum each of 16 per-lane values over the 64 lanes; every lane receives all
 // 16 totals.  Four halving exchanges leave lane l with the partial total of
 // index 8*b5 + 4*b4 + 2*b3 + b2 (b = bits of l), two more finish the sum.
@@ -75,11 +68,17 @@ __device__ __forceinline__ void butterfly16(const double (&v)[16], double (&out)
     }
 }
 
-// ub[u] = (sum of b+ over the data rows of unique row u, sum of b-)
+// ub[u] = (sum of b+ over the data rows of unique row u, sum of b-).
+// Optionally also the data as the Gram kernels consume them (the right-hand
+// side c = Re(A^H B) with A = W g g):
+//   ubw[u]  = conj(W) ub             (FP64 rows are built without W)
+//   ub32[u] = conj(W) / |W| ub, FP32 (FP32 rows already carry |W|)
 __global__ __launch_bounds__(256) void bsum_kernel(const int32_t* __restrict__ umem_off,
                                                    const int32_t* __restrict__ umem,
                                                    const zd* __restrict__ d_rows, int64_t U,
-                                                   zd* __restrict__ ub) {
+                                                   zd* __restrict__ ub, const uint32_t* __restrict__ urows,
+                                                   const double* __restrict__ freq, double eps, double dz,
+                                                   zd* __restrict__ ubw, float4* __restrict__ ub32) {
     const int64_t u = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (u >= U) return;
     zd bp{0.0, 0.0}, bm{0.0, 0.0};
@@ -92,6 +91,20 @@ __global__ __launch_bounds__(256) void bsum_kernel(const int32_t* __restrict__ u
     }
     ub[2 * u] = bp;
     ub[2 * u + 1] = bm;
+    if (ubw || ub32) {
+        const uint32_t a = urows[2 * u];
+        const zd w = omega_of(freq[a & 0xFFFFu], eps);
+        const zd cW = zconj(dz * (w * w));
+        if (ubw) {
+            ubw[2 * u] = cW * bp;
+            ubw[2 * u + 1] = cW * bm;
+        }
+        if (ub32) {
+            const zd ph = (1.0 / sqrt(zabs2(cW))) * cW;
+            const zd a = ph * bp, b = ph * bm;
+            ub32[u] = make_float4(float(a.x), float(a.y), float(b.x), float(b.y));
+        }
+    }
 }
 
 // Partial over one work item of
@@ -111,9 +124,12 @@ __global__ __launch_bounds__(256) void resid_kernel(const uint32_t* __restrict__
                                                     double* __restrict__ rpart) {
     __shared__ double s_acc[4][2][ZPL * 64];
     __shared__ double s_tr[4];
-    const Item it = items[sched[blockIdx.x]];
+    const int32_t k = sched[blockIdx.x];
+    if (k < 0) return;   // hole in the XCD-interleaved schedule
+    const Item it = items[k];
     if (WITHX && conv[it.pair]) return;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: row data via scalar loads
     const int n = it.row_end - it.row_begin;
     double xv[2][ZPL];
 #pragma unroll
@@ -127,22 +143,39 @@ __global__ __launch_bounds__(256) void resid_kernel(const uint32_t* __restrict__
     for (int q = 0; q < ZPL; ++q) acc[0][q] = acc[1][q] = tr[q] = 0.0;
 
     for (int b0 = 0; b0 < n; b0 += 16) {
-        zd P[4][ZPL];
+        // Loads are unconditional (clamped row and depth) and masked after the
+        // fact, so a batch issues all of its table loads before one wait.
+        zd P[4][ZPL], ep[4], em[4], W[4];
         URow u[4];
         bool valid[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int r = b0 + 4 * j + wv;
             valid[j] = r < n;
-            u[j] = valid[j] ? load_urow(urows, int64_t(it.row_begin) + r) : URow{0, 0, 0, 0};
+            const int64_t row = int64_t(it.row_begin) + min(r, n - 1);
+            u[j] = load_urow(urows, row);
+            ep[j] = ub[2 * row];
+            em[j] = ub[2 * row + 1];
+            const zd w = omega_of(freq[u[j].f], eps);
+            W[j] = dz * (w * w);
+        }
+        zd gr[4][ZPL], gs[4][ZPL];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
             const int64_t fb = int64_t(u[j].f) * ncls;
 #pragma unroll
             for (int q = 0; q < ZPL; ++q) {
-                const int z = lane + 64 * q;
-                P[j][q] = zd{0.0, 0.0};
-                if (valid[j] && z < nz) P[j][q] = g64[(fb + u[j].cr) * nz + z] * g64[(fb + u[j].cs) * nz + z];
+                const int zc = min(lane + 64 * q, nz - 1);
+                gr[j][q] = g64[(fb + u[j].cr) * nz + zc];
+                gs[j][q] = g64[(fb + u[j].cs) * nz + zc];
             }
         }
+        __builtin_amdgcn_sched_barrier(0);   // keep every load of the batch ahead of its use
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int q = 0; q < ZPL; ++q)
+                P[j][q] = (valid[j] && lane + 64 * q < nz) ? gr[j][q] * gs[j][q] : zd{0.0, 0.0};
         double y[16];
         if (WITHX) {
             double v[16];
@@ -165,18 +198,14 @@ __global__ __launch_bounds__(256) void resid_kernel(const uint32_t* __restrict__
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            if (!valid[j]) continue;
-            const int64_t row = int64_t(it.row_begin) + b0 + 4 * j + wv;
-            const zd w = omega_of(freq[u[j].f], eps);
-            const zd W = dz * (w * w);
-            zd ep = ub[2 * row], em = ub[2 * row + 1];
             if (WITHX) {
                 const double m = double(u[j].mult);
-                ep = ep - m * (W * zd{y[4 * j], y[4 * j + 1]});
-                em = em - m * (W * zd{y[4 * j + 2], y[4 * j + 3]});
+                ep[j] = ep[j] - m * (W[j] * zd{y[4 * j], y[4 * j + 1]});
+                em[j] = em[j] - m * (W[j] * zd{y[4 * j + 2], y[4 * j + 3]});
             }
-            const zd cp = zconj(W) * ep, cm = zconj(W) * em;
-            const double mw2 = double(u[j].mult) * zabs2(W);
+            const zd zero{0.0, 0.0};
+            const zd cp = valid[j] ? zconj(W[j]) * ep[j] : zero, cm = valid[j] ? zconj(W[j]) * em[j] : zero;
+            const double mw2 = valid[j] ? double(u[j].mult) * zabs2(W[j]) : 0.0;
 #pragma unroll
             for (int q = 0; q < ZPL; ++q) {
                 acc[0][q] += P[j][q].x * cp.x + P[j][q].y * cp.y;
@@ -247,29 +276,31 @@ __global__ __launch_bounds__(256) void forward_kernel(const uint32_t* __restrict
 }
 
 // ------------------------------------------------------------- launchers ---
-hipError_t launch_bsum(const edt_plan* p, const zd* d_rows, zd* ub, hipStream_t st) {
+hipError_t launch_bsum(const edt_plan* p, const zd* d_rows, zd* ub, hipStream_t st, zd* ubw,
+                       float4* ub32) {
     if (p->n_urows == 0) return hipSuccess;
     const unsigned blocks = unsigned((p->n_urows + 255) / 256);
     hipLaunchKernelGGL(bsum_kernel, dim3(blocks), dim3(256), 0, st,
                        dptr<const int32_t>(p, p->lay.umem_off), dptr<const int32_t>(p, p->lay.umem),
-                       d_rows, p->n_urows, ub);
+                       d_rows, p->n_urows, ub, dptr<const uint32_t>(p, p->lay.urows),
+                       dptr<const double>(p, p->lay.freq), p->eps, p->dz, ubw, ub32);
     return hipGetLastError();
 }
 
 template <int ZPL>
 static hipError_t launch_resid_z(const edt_plan* p, const zd* g64, const zd* ub, const double* x,
                                  const int32_t* conv, double* rpart, hipStream_t st) {
-    const unsigned nit = unsigned(p->items.size());
+    const unsigned nit = unsigned(p->rsched.size());
     if (nit == 0) return hipSuccess;
     if (x)
         hipLaunchKernelGGL((resid_kernel<ZPL, true>), dim3(nit), dim3(256), 0, st,
-                           dptr<const uint32_t>(p, p->lay.urows), dptr<const Item>(p, p->lay.items),
-                           dptr<const int32_t>(p, p->lay.sched), g64, dptr<const double>(p, p->lay.freq),
+                           dptr<const uint32_t>(p, p->lay.urows), dptr<const Item>(p, p->lay.ritems),
+                           dptr<const int32_t>(p, p->lay.rsched), g64, dptr<const double>(p, p->lay.freq),
                            p->eps, p->dz, p->n_cls, p->nz, ub, x, conv, rpart);
     else
         hipLaunchKernelGGL((resid_kernel<ZPL, false>), dim3(nit), dim3(256), 0, st,
-                           dptr<const uint32_t>(p, p->lay.urows), dptr<const Item>(p, p->lay.items),
-                           dptr<const int32_t>(p, p->lay.sched), g64, dptr<const double>(p, p->lay.freq),
+                           dptr<const uint32_t>(p, p->lay.urows), dptr<const Item>(p, p->lay.ritems),
+                           dptr<const int32_t>(p, p->lay.rsched), g64, dptr<const double>(p, p->lay.freq),
                            p->eps, p->dz, p->n_cls, p->nz, ub, x, conv, rpart);
     return hipGetLastError();
 }

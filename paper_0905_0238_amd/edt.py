@@ -29,7 +29,7 @@ class Plan:
     and zif (interface depths).
     """
 
-    def __init__(self, survey, chunk_rows: int = 0, device: str = "cuda"):
+    def __init__(self, survey, chunk_rows: int = 0, gram_band: int = 0, device: str = "cuda"):
         L = _lib.load()
         self.device = torch.device(device)
         self._freq = np.ascontiguousarray(survey.freqs, dtype=np.float64)
@@ -43,7 +43,8 @@ class Plan:
         ly = _lib.Layers(int(self._vel.shape[0]), self._vel.ctypes.data_as(dp),
                          self._zif.ctypes.data_as(dp) if self._zif.size else None)
         h = C.c_void_p()
-        _lib.check(L.edt_plan_create(C.byref(sv), C.byref(ly), int(chunk_rows), C.byref(h)),
+        opts = _lib.PlanOpts(int(chunk_rows), int(gram_band))
+        _lib.check(L.edt_plan_create(C.byref(sv), C.byref(ly), C.byref(opts), C.byref(h)),
                    "edt_plan_create")
         self._h = h
         info = _lib.PlanInfo()
@@ -73,6 +74,31 @@ class Plan:
                                      keys.ctypes.data_as(ip), pair_km.ctypes.data_as(ip),
                                      cls_k.ctypes.data_as(dp)), "edt_plan_rowmap")
         return dict(row_off=row_off, rows=rows, keys=keys, pair_km=pair_km, cls_k=cls_k)
+
+    def urows(self):
+        """Host copies: urow_off, urows (f, mult, cls_r, cls_s), row_unique."""
+        L = _lib.load()
+        U = int(self.info["n_urows"])
+        urow_off = np.zeros(self.n_pairs + 1, np.int64)
+        urows = np.zeros((U, 4), np.int32)
+        row_unique = np.zeros(self.n_rows, np.int32)
+        i64p, ip = C.POINTER(C.c_int64), C.POINTER(C.c_int32)
+        _lib.check(L.edt_plan_urows(self._h, urow_off.ctypes.data_as(i64p), urows.ctypes.data_as(ip),
+                                    row_unique.ctypes.data_as(ip)), "edt_plan_urows")
+        return dict(urow_off=urow_off, urows=urows, row_unique=row_unique)
+
+    def schedule(self, which: str = "gram"):
+        """Host copies of the work items (pair, begin, end) and launch order."""
+        L = _lib.load()
+        w = {"gram": 0, "resid": 1}[which]
+        i64p, ip = C.POINTER(C.c_int64), C.POINTER(C.c_int32)
+        counts = np.zeros(2, np.int64)
+        _lib.check(L.edt_plan_schedule(self._h, w, counts.ctypes.data_as(i64p), None, None), "edt_plan_schedule")
+        items = np.zeros((int(counts[0]), 3), np.int32)
+        sched = np.zeros(int(counts[1]), np.int32)
+        _lib.check(L.edt_plan_schedule(self._h, w, counts.ctypes.data_as(i64p), items.ctypes.data_as(ip),
+                                       sched.ctypes.data_as(ip)), "edt_plan_schedule")
+        return items, sched
 
     def close(self):
         if getattr(self, "_h", None):

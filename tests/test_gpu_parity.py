@@ -150,6 +150,50 @@ def test_mixed_gram_is_close_to_fp64(refs):
         assert np.max(np.abs(Gf[i][low] - G64[i][low])) <= 1e-5 * sc
 
 
+@pytest.mark.parametrize("opts", [dict(chunk_rows=16, gram_band=1), dict(chunk_rows=5, gram_band=2)])
+def test_fp64_assemble_with_small_banded_items(refs, opts):
+    """Many items per pair (one or two frequencies, a few rows each) and an
+    XCD schedule with holes give the same Gram, rhs and trace."""
+    s, r = _ref(refs, "layered-nz40")
+    p = E.Plan(s, **opts)
+    items, sched = p.schedule("gram")
+    assert len(items) > 4 * p.n_pairs and np.any(sched < 0)
+    g64, _ = p.green(_vel(s), want32=False)
+    gram, rhs, trace = p.assemble(g64, None, _dev(r["d_rows"]), "fp64")
+    torch.cuda.synchronize()
+    gram, rhs, trace = gram.cpu().numpy(), rhs.cpu().numpy(), trace.cpu().numpy()
+    low = np.tril(np.ones((s.nz, s.nz), bool))
+    for i, q in enumerate(r["pl"].pairs):
+        if q.n_rows == 0:
+            continue
+        A = row_values(s, q, r["tabs"].lookup)
+        G, c, tr = normal_equations(A, *r["data"][i])
+        assert np.max(np.abs(gram[i][low] - G[low])) <= 1e-12 * np.max(np.abs(G))
+        assert np.max(np.abs(rhs[i] - c)) <= 1e-12 * np.max(np.abs(c))
+        assert abs(trace[i] - tr) <= 1e-12 * tr
+    out = p.run(_vel(s), _dev(r["d_rows"]), s.lambda_rel, prec="bf16x3", refine_tol=1e-9, max_refine=10)
+    g, per = rel_errors(out["v"].cpu().numpy(), r["V"], r["pl"])
+    assert g <= 1e-6 and per <= 1e-6, (g, per)
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+def test_mixed_rhs_and_trace(refs, prec):
+    """FP32/BF16x3 assembly: the trace (which fixes lambda) is FP32 rows summed
+    in FP64, within 1e-7 of FP64; the right-hand side is an FP32 estimate that
+    the FP64 refinement residual corrects."""
+    s, r = _ref(refs, "layered-nz200")
+    p = E.Plan(s)
+    g64, g32 = p.green(_vel(s))
+    d = _dev(r["d_rows"])
+    _, c64, t64 = p.assemble(g64, g32, d, "fp64")
+    _, cm, tm = p.assemble(g64, g32, d, prec)
+    c64, t64, cm, tm = (a.cpu().numpy() for a in (c64, t64, cm, tm))
+    ok = t64 > 0
+    assert np.all(np.abs(tm[ok] - t64[ok]) <= 1e-7 * t64[ok])
+    for i in np.flatnonzero(ok):
+        assert np.max(np.abs(cm[i] - c64[i])) <= 1e-4 * np.max(np.abs(c64[i]))
+
+
 def test_empty_and_nonfinite_and_singular():
     s = make_custom(N=64, nz=6, dx=25.0, freqs=(2.0, 3.0), vel=(2500.0,), noise_rel=0.0, seed=2)
     r = oracle_case(s)

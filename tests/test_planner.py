@@ -116,3 +116,96 @@ def test_invalid_surveys_are_rejected(bad):
         s.d_off = s.d_off * 1.5
     with pytest.raises(RuntimeError):
         E.Plan(s)
+
+
+@pytest.mark.parametrize("name", list(SURVEYS))
+def test_unique_rows_merge_equal_born_rows(name):
+    """A unique row stands for data rows of one pair with the same frequency and
+    the same {|k_r|, |k_s|} (equal Born rows by source-receiver reciprocity);
+    its multiplicity is their count, and the rows of a pair are sorted by f."""
+    _lib_or_skip()
+    s = SURVEYS[name]()
+    p = E.Plan(s)
+    m, u = p.rowmap(), p.urows()
+    rows, uo, ur, ru = m["rows"], u["urow_off"], u["urows"], u["row_unique"]
+    assert uo[0] == 0 and uo[-1] == len(ur)
+    mult = np.bincount(ru, minlength=len(ur))
+    assert np.array_equal(mult, ur[:, 1])
+    for q in range(p.n_pairs):
+        a, b = m["row_off"][q], m["row_off"][q + 1]
+        assert np.all((ru[a:b] >= uo[q]) & (ru[a:b] < uo[q + 1]))
+        uu = ur[ru[a:b]]
+        assert np.array_equal(uu[:, 0], rows[a:b, 0])
+        assert np.array_equal(np.sort(uu[:, 2:], 1), np.sort(rows[a:b, 1:], 1))
+        seg = ur[uo[q]:uo[q + 1]]
+        assert np.all(np.diff(seg[:, 0]) >= 0)
+        keys = {(f, min(c1, c2), max(c1, c2)) for f, _, c1, c2 in seg}
+        assert len(keys) == len(seg)
+
+
+def _check_items(p, which, band, max_rows):
+    items, sched = p.schedule(which)
+    u = p.urows()
+    uo, f = u["urow_off"], u["urows"][:, 0]
+    # pair-major, contiguous, covering every unique row once
+    k = 0
+    for q in range(p.n_pairs):
+        pos = uo[q]
+        while pos < uo[q + 1]:
+            pq, b, e = items[k]
+            assert (pq, b) == (q, pos) and b < e <= uo[q + 1]
+            assert e - b <= max_rows
+            assert np.all(f[b:e] // band == f[b] // band)
+            # items are maximal: they end at the pair's end, a band edge or the size cap
+            assert e == uo[q + 1] or f[e] // band != f[b] // band or e - b == max_rows
+            pos, k = e, k + 1
+    assert k == len(items)
+    # launch order: every item once, holes are -1, length a multiple of the XCD count
+    assert len(sched) % 8 == 0
+    real = sched[sched >= 0]
+    assert np.array_equal(np.sort(real), np.arange(len(items)))
+    nrows = items[:, 2] - items[:, 1]
+    bands = f[items[:, 1]] // band
+    runs = [sched[x::8][sched[x::8] >= 0] for x in range(8)]
+    for r in runs:
+        # each XCD walks its bands in order, longest items of a band first
+        assert np.all(np.diff(bands[r]) >= 0)
+        for g in np.unique(bands[r]):
+            assert np.all(np.diff(nrows[r][bands[r] == g]) <= 0)
+    # the runs are consecutive pieces of the band order and carry about equal work
+    order = np.concatenate(runs)
+    assert np.all(np.diff(bands[order]) >= 0)
+    load = np.array([nrows[r].sum() for r in runs])
+    assert load.max() - load.min() <= 2 * nrows.max()
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(chunk_rows=16, gram_band=1), dict(chunk_rows=7, gram_band=3)])
+@pytest.mark.parametrize("name", ["cfg1", "2d-even-cut", "3d-small"])
+def test_work_items_and_xcd_schedule(name, opts):
+    _lib_or_skip()
+    s = SURVEYS[name]()
+    p = E.Plan(s, **opts)
+    band = p.info["gram_band"]
+    if "gram_band" in opts:
+        assert band == min(opts["gram_band"], p.table_shape[0])
+    assert p.info["chunk_rows"] == opts.get("chunk_rows", 2048)
+    _check_items(p, "gram", band, p.info["chunk_rows"])
+    _check_items(p, "resid", 2, 1024)
+
+
+def test_default_band_fits_l2():
+    _lib_or_skip()
+    s = make_config(2, with_model=False)
+    p = E.Plan(s)
+    n_cls, nz = p.table_shape[1], p.table_shape[2]
+    band = p.info["gram_band"]
+    # one band's FP32 table slab is at most 2.5 MB and one more frequency would exceed it
+    assert band * n_cls * nz * 8 <= 2.5e6 < (band + 1) * n_cls * nz * 8
+
+
+@pytest.mark.parametrize("opts", [dict(chunk_rows=2049), dict(chunk_rows=-1), dict(gram_band=-2)])
+def test_invalid_plan_options_are_rejected(opts):
+    _lib_or_skip()
+    s = SURVEYS["cfg1"]()
+    with pytest.raises(RuntimeError):
+        E.Plan(s, **opts)
