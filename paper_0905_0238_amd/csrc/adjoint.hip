@@ -26,7 +26,7 @@
 
 namespace edt {
 
-size_t refine_lds_bytes(int nz);
+size_t adjoint_lds_bytes(int nz);
 hipError_t launch_bsum(const edt_plan* p, const zd* d_rows, zd* ub, hipStream_t st, zd* ubw = nullptr,
                        float4* ub32 = nullptr);
 
@@ -441,7 +441,7 @@ hipError_t launch_adjoint(const edt_plan* p, const double* vel, const zd* g64, c
     hipError_t e;
     if (p->n_pairs == 0) return hipSuccess;
     if ((e = launch_bsum(p, d_rows, ub, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(adj_pair_kernel, dim3(unsigned(p->n_pairs)), dim3(256), refine_lds_bytes(p->nz), st,
+    hipLaunchKernelGGL(adj_pair_kernel, dim3(unsigned(p->n_pairs)), dim3(256), adjoint_lds_bytes(p->nz), st,
                        chol, x, trace, dptr<const int64_t>(p, p->lay.urow_off),
                        dptr<const int32_t>(p, p->lay.pair_u), p->nz, grad_v, y, dl, glam_part);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -18,15 +18,15 @@ hipError_t launch_rhs_reduce(const edt_plan* p, const double* rpart, double* rhs
                              hipStream_t st);
 hipError_t launch_bsum(const edt_plan* p, const zd* d_rows, zd* ub, hipStream_t st, zd* ubw = nullptr,
                        float4* ub32 = nullptr);
-hipError_t launch_resid(const edt_plan* p, const zd* g64, const zd* ub, const double* x,
+hipError_t launch_resid(const edt_plan* p, const zd* g64, const zd* ubw, const double* x,
                         const int32_t* conv, double* rpart, hipStream_t st);
 hipError_t launch_forward(const edt_plan* p, const zd* g64, const zd* v, zd* d_rows, hipStream_t st);
 hipError_t launch_chol(const edt_plan* p, double* gram, const double* trace, const double* rhs,
-                       double lambda_rel, double* lam, double* x, int32_t* info, int32_t* conv,
-                       int32_t* steps, hipStream_t st);
-hipError_t launch_refine_update(const edt_plan* p, const double* gram, const double* rpart,
-                                const double* lam, double* x, int32_t* conv, int32_t* steps, double tol,
-                                hipStream_t st);
+                       double lambda_rel, double* lam, double* dinv, double* x, int32_t* info,
+                       int32_t* conv, int32_t* steps, hipStream_t st);
+hipError_t launch_refine_update(const edt_plan* p, const double* gram, const double* dinv,
+                                const double* rpart, const double* lam, double* x, int32_t* conv,
+                                int32_t* steps, double tol, hipStream_t st);
 hipError_t launch_recombine(const edt_plan* p, const double* x, int refine, const int32_t* conv,
                             int32_t* info, zd* v, hipStream_t st);
 hipError_t launch_adjoint(const edt_plan* p, const double* vel, const zd* g64, const zd* d_rows,
@@ -223,17 +223,19 @@ edt_status edt_solve(const edt_plan* p, const edt_c128* g64, const edt_c128* d_r
     double* lam = reinterpret_cast<double*>(w + wl.lam);
     int32_t* conv = reinterpret_cast<int32_t*>(w + wl.conv);
     int32_t* stp = steps ? steps : reinterpret_cast<int32_t*>(w + wl.aux);
-    EDT_TRY(launch_chol(p, gram, trace, rhs, lambda_rel, lam, x, info, conv, stp, stream), "cholesky");
+    double* dinv = reinterpret_cast<double*>(w + wl.dinv);
+    EDT_TRY(launch_chol(p, gram, trace, rhs, lambda_rel, lam, dinv, x, info, conv, stp, stream), "cholesky");
     if (refine) {
-        const zd* ub = reinterpret_cast<const zd*>(w + wl.ub);
+        zd* ub = reinterpret_cast<zd*>(w + wl.ub);
+        zd* ubw = reinterpret_cast<zd*>(w + wl.ubw);
         double* rpart = reinterpret_cast<double*>(w + wl.rhs_part);
-        // the summed data were formed by edt_assemble on this workspace; rebuild
-        // them so edt_solve does not depend on an earlier call's scratch
-        EDT_TRY(launch_bsum(p, reinterpret_cast<const zd*>(d_rows), const_cast<zd*>(ub), stream), "bsum");
+        // the summed data, conj(W) B per unique row, are rebuilt here so that
+        // edt_solve does not depend on an earlier call's scratch
+        EDT_TRY(launch_bsum(p, reinterpret_cast<const zd*>(d_rows), ub, stream, ubw), "bsum");
         for (int it = 0; it < opts->max_refine; ++it) {
-            EDT_TRY(launch_resid(p, reinterpret_cast<const zd*>(g64), ub, x, conv, rpart, stream),
+            EDT_TRY(launch_resid(p, reinterpret_cast<const zd*>(g64), ubw, x, conv, rpart, stream),
                     "refine residual");
-            EDT_TRY(launch_refine_update(p, gram, rpart, lam, x, conv, stp, opts->refine_tol, stream),
+            EDT_TRY(launch_refine_update(p, gram, dinv, rpart, lam, x, conv, stp, opts->refine_tol, stream),
                     "refine update");
         }
     }

@@ -6,15 +6,18 @@
 //   (G + lambda I) x+- = c+-,  lambda = lambda_rel tr(G) / nz,
 //   V~(k_m) = x+ + i x-,  V~(-k_m) = x+ - i x-.
 // One workgroup per pair.  The factorisation is left-looking by 32-column
-// panels.  The update of a panel by all finished columns is a dense
-// contraction, P -= L[k0:, :k0] L[k0:k0+32, :k0]^T, done on FP64 MFMA
-// (v_mfma_f64_16x16x4) with the panel held in the accumulators and the
-// operands read straight from the factor in global memory (L2-resident).
-// The updated panel then goes to LDS: one wave factors its 32 x 32 diagonal
-// block in registers (row per lane, columns broadcast with readlane) and the
-// remaining rows are solved against it one row per thread.  The factor L
-// overwrites the lower triangle of the Gram in place.  LDS stays under
-// 70 KiB so two pairs share a CU.
+// panels:
+//  * update: P -= L[k0:, :k0] L[k0:k0+32, :k0]^T on FP64 MFMA
+//    (v_mfma_f64_16x16x4) with the panel in the accumulators; the finished
+//    columns are staged in LDS 32 at a time;
+//  * diagonal block: one wave factors it in registers (4 x 4 blocks per
+//    lane) and, in the same pivot loop, forms D = L_kk^{-1} by forward
+//    substitution on the identity;
+//  * the rows below: L_ik = P_ik D^T, again on FP64 MFMA (no serial
+//    triangular solve).
+// L overwrites the lower triangle of the Gram in place; the block inverses
+// D go to a workspace, where the block solves (block_solve2) use them.
+// LDS stays under 80 KiB so two pairs share a CU.
 
 #include "dev_linalg.h"
 
@@ -22,19 +25,24 @@ namespace edt {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// Factor gram[p] + lambda_p I in place and solve for x from rhs.
-// Dynamic LDS: the panel, nz x CBP doubles (reused by the solves afterwards).
+// Factor gram[p] + lambda_p I in place, store the diagonal-block inverses in
+// dinv[p][nblk][32][32] and solve for x from rhs.
+// Dynamic LDS: the panel (nz x CBP doubles) and D (32 x CBP doubles), reused
+// by the solve afterwards.
 __global__ __launch_bounds__(256, 2) void chol_solve_kernel(
     double* __restrict__ gram, const double* __restrict__ trace, const double* __restrict__ rhs,
     const int64_t* __restrict__ urow_off, const int32_t* __restrict__ pair_u, int nz,
-    double lambda_rel, double* __restrict__ lam_out, double* __restrict__ x,
+    double lambda_rel, double* __restrict__ lam_out, double* __restrict__ dinv, double* __restrict__ x,
     int32_t* __restrict__ info, int32_t* __restrict__ conv, int32_t* __restrict__ steps) {
     extern __shared__ double smem[];
     double* sP = smem;
+    double* sD = smem + size_t(nz) * CBP;
     __shared__ int s_bad;
-    __shared__ double s_col[64];
+    __shared__ double s_col[CB], s_drow[CB];
     const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int nblk = (nz + CB - 1) / CB;
     double* A = gram + size_t(p) * nz * nz;
+    double* Dp = dinv + size_t(p) * nblk * CB * CB;
     const bool empty = urow_off[p + 1] == urow_off[p];
     const bool selfc = pair_u[2 * p] == pair_u[2 * p + 1];
     const double lam = lambda_rel * trace[p] / double(nz);
@@ -74,7 +82,6 @@ __global__ __launch_bounds__(256, 2) void chol_solve_kernel(
                     acc[q][cb][v] = a;
                 }
         // P -= L[k0+i][t] L[k0+j][t], t < k0: 32 finished columns at a time
-        // are staged in LDS (coalesced), then four columns per MFMA
         for (int t0 = 0; t0 < k0; t0 += CB) {
             for (int e = tid; e < m * CB; e += blockDim.x) {
                 const int i = e / CB, c = e % CB;
@@ -109,16 +116,17 @@ __global__ __launch_bounds__(256, 2) void chol_solve_kernel(
                     if (rb < nrb && i < m) sP[i * CBP + j] = acc[q][cb][v];
                 }
         __syncthreads();
-        // factor the kb x kb diagonal block in one wave, in place in LDS (lane j
-        // owns row j); a wave executes its LDS operations in order, so the
-        // fences only keep the compiler from reordering across the steps
+        // Factor the kb x kb diagonal block in one wave and invert it.  Lane
+        // (bi, bj) = (lane / 8, lane % 8) holds the 4 x 4 blocks of rows
+        // 4 bi.., columns 4 bj.. of L (a) and of D = L^{-1} (dv), lower blocks
+        // only.  Right-looking: at pivot k, column k of L and row k of D are
+        // broadcast through LDS; rows > k of both are updated.  Padding
+        // (k >= kb) stays the identity.  A wave executes its LDS operations in
+        // order, so the fences only keep the compiler from reordering.
         if (tid < 64) {
-            // lane (bi, bj) = (lane / 8, lane % 8) holds the 4 x 4 block of rows
-            // 4 bi.., columns 4 bj.. (lower blocks only); right-looking, the
-            // pivot column of each step is broadcast through LDS
             const int bi = tid >> 3, bj = tid & 7;
             const bool act = bi >= bj;
-            double a[4][4];
+            double a[4][4], dv[4][4];
             int bad = 0;   // first failing column of this block (wave-uniform)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
@@ -126,6 +134,7 @@ __global__ __launch_bounds__(256, 2) void chol_solve_kernel(
                 for (int c = 0; c < 4; ++c) {
                     const int i = 4 * bi + r, jj = 4 * bj + c;
                     a[r][c] = (act && i < kb && jj < kb && jj <= i) ? sP[i * CBP + jj] : (i == jj ? 1.0 : 0.0);
+                    dv[r][c] = (i == jj) ? 1.0 : 0.0;
                 }
             for (int k = 0; k < kb; ++k) {
                 const int kb4 = k >> 2, kr = k & 3;
@@ -151,13 +160,26 @@ __global__ __launch_bounds__(256, 2) void chol_solve_kernel(
                         if (i >= k) s_col[i] = v;
                     }
                 }
+                if (bi == kb4) {   // row k of D is final once scaled by 1 / L[k][k]
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        double v = dv[0][c];
+#pragma unroll
+                        for (int q = 1; q < 4; ++q) v = (kr == q) ? dv[q][c] : v;
+                        v *= inv;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) dv[q][c] = (kr == q) ? v : dv[q][c];
+                        s_drow[4 * bj + c] = v;
+                    }
+                }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 if (act) {
-                    double ci[4], cj[4];
+                    double ci[4], cj[4], dr[4];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         ci[q] = s_col[4 * bi + q];
                         cj[q] = s_col[4 * bj + q];
+                        dr[q] = s_drow[4 * bj + q];
                     }
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
@@ -165,6 +187,7 @@ __global__ __launch_bounds__(256, 2) void chol_solve_kernel(
                         for (int c = 0; c < 4; ++c) {
                             const int i = 4 * bi + r, jj = 4 * bj + c;
                             if (jj > k && i >= jj) a[r][c] -= ci[r] * cj[c];
+                            if (i > k) dv[r][c] -= ci[r] * dr[c];
                         }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -174,38 +197,62 @@ __global__ __launch_bounds__(256, 2) void chol_solve_kernel(
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const int i = 4 * bi + r, jj = 4 * bj + c;
-                    if (act && i < kb && jj <= i) {
-                        sP[i * CBP + jj] = a[r][c];
-                        if (i == jj) sP[i * CBP + CB] = 1.0 / a[r][c];   // reciprocal pivot
-                    }
+                    if (act && i < kb && jj <= i) sP[i * CBP + jj] = a[r][c];
+                    sD[i * CBP + jj] = act ? dv[r][c] : 0.0;
                 }
             if (tid == 0 && bad != 0 && s_bad == 0) s_bad = bad;
         }
         __syncthreads();
-        // rows below the diagonal block: x L_kk^T = P[i][0:kb], one thread per row
-        for (int i = kb + tid; i < m; i += blockDim.x) {
-            double* row = sP + i * CBP;
-            for (int t = 0; t < kb; ++t) {
-                double s = row[t];
-                for (int q = 0; q < t; ++q) s -= row[q] * sP[t * CBP + q];
-                s *= sP[t * CBP + CB];
-                row[t] = s;
-                A[size_t(k0 + i) * nz + k0 + t] = s;
+        // rows below the diagonal block: L_ik = P_ik D^T on MFMA (B[k][c] = D[c][k])
+        if (m > kb) {
+            f64x4 t[4][2];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) t[q][cb][v] = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < CB; kk += 4) {
+                const double b0 = sD[li * CBP + kk + lk];
+                const double b1 = sD[(16 + li) * CBP + kk + lk];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int rb = wv + 4 * q;
+                    if (rb >= 2 && rb < nrb) {
+                        const int i = 16 * rb + li;
+                        const double a = (i < m) ? sP[i * CBP + kk + lk] : 0.0;
+                        t[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, t[q][0], 0, 0, 0);
+                        t[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, t[q][1], 0, 0, 0);
+                    }
+                }
             }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int rb = wv + 4 * q;
+                        const int i = 16 * rb + 4 * v + lk, j = 16 * cb + li;
+                        if (rb >= 2 && rb < nrb && i < m) A[size_t(k0 + i) * nz + k0 + j] = t[q][cb][v];
+                    }
         }
         for (int e = tid; e < kb * CB; e += blockDim.x) {
             const int i = e / CB, j = e % CB;
             if (j <= i) A[size_t(k0 + i) * nz + k0 + j] = sP[i * CBP + j];
         }
+        for (int e = tid; e < CB * CB; e += blockDim.x)
+            Dp[size_t(k0 / CB) * CB * CB + e] = sD[(e >> 5) * CBP + (e & 31)];
         __syncthreads();
     }
-    // triangular solves (LDS reused)
+    // block solves (LDS reused)
     double* sx = smem;
-    double* sL = sx + 2 * nz;
-    double* sred = sL + size_t(nz) * CBP;
+    double* sred = sx + 2 * nz;
+    double* sDs = sred + 576;
     for (int e = tid; e < 2 * nz; e += blockDim.x) sx[e] = rhs[size_t(p) * 2 * nz + e];
     __syncthreads();
-    trisolve2(A, nz, sx, sL, sred);
+    block_solve2(A, Dp, nz, sx, sred, sDs);
     for (int e = tid; e < 2 * nz; e += blockDim.x)
         x[size_t(p) * 2 * nz + e] = (selfc && e >= nz) ? 0.0 : sx[e];
     if (tid == 0) {
@@ -218,20 +265,21 @@ __global__ __launch_bounds__(256, 2) void chol_solve_kernel(
 //   r = (sum of the residual partials) - lambda x,  dx = (L L^T)^{-1} r,
 //   x += dx, converged when ||dx|| <= tol ||x||.
 __global__ __launch_bounds__(256) void refine_update_kernel(
-    const double* __restrict__ gram, const double* __restrict__ rpart,
+    const double* __restrict__ gram, const double* __restrict__ dinv, const double* __restrict__ rpart,
     const int32_t* __restrict__ pair_item, const int32_t* __restrict__ pair_u, int nz,
     const double* __restrict__ lam, double* __restrict__ x, int32_t* __restrict__ conv,
     int32_t* __restrict__ steps, double tol) {
     extern __shared__ double smem[];
     double* sx = smem;
-    double* sL = sx + 2 * nz;
-    double* sred = sL + size_t(nz) * CBP;
+    double* sred = sx + 2 * nz;
+    double* sD = sred + 576;
     __shared__ double s_red[8];
     const int p = blockIdx.x, tid = threadIdx.x;
     if (conv[p]) return;
     const bool selfc = pair_u[2 * p] == pair_u[2 * p + 1];
     const int k0 = pair_item[p], k1 = pair_item[p + 1];
     const int w = 2 * nz + 1;
+    const int nblk = (nz + CB - 1) / CB;
     double* xp = x + size_t(p) * 2 * nz;
     const double lp = lam[p];
     for (int e = tid; e < 2 * nz; e += blockDim.x) {
@@ -247,7 +295,7 @@ __global__ __launch_bounds__(256) void refine_update_kernel(
         sx[e] = (selfc && e >= nz) ? 0.0 : s - lp * xp[e];
     }
     __syncthreads();
-    trisolve2(gram + size_t(p) * nz * nz, nz, sx, sL, sred);
+    block_solve2(gram + size_t(p) * nz * nz, dinv + size_t(p) * nblk * CB * CB, nz, sx, sred, sD);
     double dn = 0.0, xn = 0.0;
     for (int e = tid; e < 2 * nz; e += blockDim.x) {
         const double d = (selfc && e >= nz) ? 0.0 : sx[e];
@@ -289,19 +337,24 @@ __global__ __launch_bounds__(256) void recombine_kernel(const double* __restrict
 }
 
 // ------------------------------------------------------------- launchers ---
-size_t refine_lds_bytes(int nz) { return trisolve_lds_doubles(nz) * sizeof(double); }
+size_t refine_lds_bytes(int nz) { return block_solve_lds_doubles(nz) * sizeof(double); }
 size_t chol_lds_bytes(int nz) {
-    const size_t panel = size_t(nz) * CBP * sizeof(double);
+    const size_t panel = (size_t(nz) + CB) * CBP * sizeof(double);
     const size_t solve = refine_lds_bytes(nz);
     return panel > solve ? panel : solve;
 }
+// adjoint solves still use trisolve2 (staged panels in LDS)
+size_t adjoint_lds_bytes(int nz) { return trisolve_lds_doubles(nz) * sizeof(double); }
 
 // Allow the factorisation kernel more than 64 KiB of dynamic LDS (gfx950 has
 // 160 KiB per CU).
 hipError_t configure_adjoint_kernels(int bytes);
 hipError_t configure_gram_kernels();
 // The largest dynamic LDS any supported depth count (nz <= 256) needs.
-static int max_dynamic_lds() { return int(chol_lds_bytes(256)); }
+static int max_dynamic_lds() {
+    const size_t a = chol_lds_bytes(256), b = adjoint_lds_bytes(256);
+    return int(a > b ? a : b);
+}
 hipError_t configure_kernels() {
     const int bytes = max_dynamic_lds();
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(chol_solve_kernel),
@@ -315,22 +368,22 @@ hipError_t configure_kernels() {
 }
 
 hipError_t launch_chol(const edt_plan* p, double* gram, const double* trace, const double* rhs,
-                       double lambda_rel, double* lam, double* x, int32_t* info, int32_t* conv,
-                       int32_t* steps, hipStream_t st) {
+                       double lambda_rel, double* lam, double* dinv, double* x, int32_t* info,
+                       int32_t* conv, int32_t* steps, hipStream_t st) {
     if (p->n_pairs == 0) return hipSuccess;
     const size_t lds = chol_lds_bytes(p->nz);
     hipLaunchKernelGGL(chol_solve_kernel, dim3(unsigned(p->n_pairs)), dim3(256), lds, st, gram, trace,
                        rhs, dptr<const int64_t>(p, p->lay.urow_off), dptr<const int32_t>(p, p->lay.pair_u),
-                       p->nz, lambda_rel, lam, x, info, conv, steps);
+                       p->nz, lambda_rel, lam, dinv, x, info, conv, steps);
     return hipGetLastError();
 }
 
-hipError_t launch_refine_update(const edt_plan* p, const double* gram, const double* rpart,
-                                const double* lam, double* x, int32_t* conv, int32_t* steps, double tol,
-                                hipStream_t st) {
+hipError_t launch_refine_update(const edt_plan* p, const double* gram, const double* dinv,
+                                const double* rpart, const double* lam, double* x, int32_t* conv,
+                                int32_t* steps, double tol, hipStream_t st) {
     if (p->n_pairs == 0) return hipSuccess;
     hipLaunchKernelGGL(refine_update_kernel, dim3(unsigned(p->n_pairs)), dim3(256),
-                       refine_lds_bytes(p->nz), st, gram, rpart, dptr<const int32_t>(p, p->lay.pair_ritem),
+                       refine_lds_bytes(p->nz), st, gram, dinv, rpart, dptr<const int32_t>(p, p->lay.pair_ritem),
                        dptr<const int32_t>(p, p->lay.pair_u), p->nz, lam, x, conv, steps, tol);
     return hipGetLastError();
 }

@@ -98,6 +98,108 @@ __host__ __device__ constexpr size_t trisolve_lds_doubles(int nz) {
     return size_t(2) * nz + size_t(nz) * CBP + 16 * CB;
 }
 
+// Sum over the 8 lanes l ^ {1, 2, 4} of a group of 8 (every lane gets it).
+__device__ __forceinline__ double sum8(double v) {
+    v += __shfl_xor(v, 4, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 1, 64);
+    return v;
+}
+
+// Solve L L^T x = r for the two right-hand sides in sx[0..nz), sx[nz..2nz)
+// (LDS), in place, by block substitution with explicit inverses of the 32 x 32
+// diagonal blocks of L:
+//   forward   y_b = D_b (r_b - sum_{j<b} L_bj y_j),
+//   backward  x_b = D_b^T (y_b - sum_{j>b} L_jb^T x_j).
+// L: lower triangle of a row-major nz x nz matrix (global); D: [nblk][32][32]
+// row-major lower-triangular inverses (global).  No step has a serial chain
+// longer than one block: 2 nblk dependent matrix-vector products.
+// LDS: sred >= 576 doubles, sD >= 32 * CBP doubles.  blockDim.x must be 256.
+__device__ __forceinline__ void block_solve2(const double* __restrict__ L, const double* __restrict__ D,
+                                             int nz, double* sx, double* sred, double* sD) {
+    const int tid = threadIdx.x;
+    const int nblk = (nz + CB - 1) / CB;
+    for (int b = 0; b < nblk; ++b) {
+        const int k0 = b * CB, kb = min(CB, nz - k0);
+        const int i = tid >> 3, part = tid & 7;   // row i of the block, 8 threads per row
+        for (int e = tid; e < CB * CB; e += 256) sD[(e >> 5) * CBP + (e & 31)] = D[size_t(b) * CB * CB + e];
+        double s0 = 0.0, s1 = 0.0;
+        if (i < kb) {
+            const double* row = L + size_t(k0 + i) * nz;
+            for (int c = part; c < k0; c += 8) {
+                const double l = row[c];
+                s0 += l * sx[c];
+                s1 += l * sx[nz + c];
+            }
+        }
+        s0 = sum8(s0);
+        s1 = sum8(s1);
+        if (part == 0) {
+            sred[i] = i < kb ? sx[k0 + i] - s0 : 0.0;
+            sred[CB + i] = i < kb ? sx[nz + k0 + i] - s1 : 0.0;
+        }
+        __syncthreads();
+        double y0 = 0.0, y1 = 0.0;
+        if (i < kb)
+            for (int j = part; j <= i; j += 8) {
+                const double d = sD[i * CBP + j];
+                y0 += d * sred[j];
+                y1 += d * sred[CB + j];
+            }
+        y0 = sum8(y0);
+        y1 = sum8(y1);
+        if (part == 0 && i < kb) {
+            sx[k0 + i] = y0;
+            sx[nz + k0 + i] = y1;
+        }
+        __syncthreads();
+    }
+    for (int b = nblk - 1; b >= 0; --b) {
+        const int k0 = b * CB, kb = min(CB, nz - k0);
+        for (int e = tid; e < CB * CB; e += 256) sD[(e >> 5) * CBP + (e & 31)] = D[size_t(b) * CB * CB + e];
+        {
+            const int c = tid & 31, g = tid >> 5;   // column c of the block, 8 row groups
+            double s0 = 0.0, s1 = 0.0;
+            if (c < kb)
+                for (int m = k0 + CB + g; m < nz; m += 8) {
+                    const double l = L[size_t(m) * nz + k0 + c];
+                    s0 += l * sx[m];
+                    s1 += l * sx[nz + m];
+                }
+            sred[g * 64 + c] = s0;
+            sred[g * 64 + CB + c] = s1;
+        }
+        __syncthreads();
+        if (tid < 64) {
+            const int h = tid >> 5, c = tid & 31;
+            double t = 0.0;
+            for (int g = 0; g < 8; ++g) t += sred[g * 64 + h * CB + c];
+            sred[512 + h * CB + c] = c < kb ? sx[h * nz + k0 + c] - t : 0.0;
+        }
+        __syncthreads();
+        const int c = tid >> 3, part = tid & 7;   // x_c = sum_{j >= c} D[j][c] t_j
+        double x0 = 0.0, x1 = 0.0;
+        if (c < kb)
+            for (int j = c + part; j < kb; j += 8) {
+                const double d = sD[j * CBP + c];
+                x0 += d * sred[512 + j];
+                x1 += d * sred[512 + CB + j];
+            }
+        x0 = sum8(x0);
+        x1 = sum8(x1);
+        if (part == 0 && c < kb) {
+            sx[k0 + c] = x0;
+            sx[nz + k0 + c] = x1;
+        }
+        __syncthreads();
+    }
+}
+
+// LDS doubles needed by block_solve2 for depth count nz (sx, sred, sD).
+__host__ __device__ constexpr size_t block_solve_lds_doubles(int nz) {
+    return size_t(2) * nz + 576 + size_t(CB) * CBP;
+}
+
 __device__ __forceinline__ double block_sum(double v, double* sbuf) {
     v = wave_sum(v);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;

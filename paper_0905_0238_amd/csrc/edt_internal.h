@@ -105,6 +105,7 @@ struct WorkLayout {
     size_t rhs_part;    // [n_ritems][2*nz + 1] FP64 partial residuals (refinement, adjoint)
     size_t gram_rpart;  // [n_items][2*nz + 1] FP64 partial rhs and trace from the Gram kernels
     size_t lam;         // [P] lambda per pair
+    size_t dinv;        // [P][nblk][32][32] FP64 inverses of the 32 x 32 diagonal blocks of L
     size_t conv;        // [P] int32 converged flags
     size_t aux;         // [P][2][nz] FP64 scratch (refinement, adjoint)
     size_t aux2;        // [P][2][nz] FP64 scratch

@@ -199,6 +199,8 @@ WorkLayout work_layout(const edt_plan* p) {
     off = align256(off + p->items.size() * (2 * nz + 1) * sizeof(double));
     w.lam = off;
     off = align256(off + P * sizeof(double));
+    w.dinv = off;
+    off = align256(off + P * size_t((p->nz + 31) / 32) * 32 * 32 * sizeof(double));
     w.conv = off;
     off = align256(off + P * sizeof(int32_t));
     w.aux = off;

@@ -107,27 +107,29 @@ __global__ __launch_bounds__(256) void bsum_kernel(const int32_t* __restrict__ u
     }
 }
 
-// Partial over one work item of
-//   WITHX = false:  c+- = Re(A^H B+-) and tr = sum mult |A|^2
-//   WITHX = true:   r+- = Re(A^H (B+- - mult A x+-))
-// written to rpart[slot][h*nz + z] (and the trace at [2 nz]).
-template <int ZPL, bool WITHX>
-__global__ __launch_bounds__(256) void resid_kernel(const uint32_t* __restrict__ urows,
-                                                    const Item* __restrict__ items,
+// Refinement residual, partial over one work item (a pair's rows within two
+// frequencies):  r+-(z) = Re(A^H (B+- - mult A x+-)), written to
+// rpart[slot][h*nz + z].  With A = W p, p = g(k_r) g(k_s) and the row data
+// ubw = conj(W) B from bsum_kernel, a row contributes
+//   Re(conj(p) (ubw - |W|^2 mult (p . x))),   |W|^2 mult = gsc^2.
+// Rows past the item (padding of the last batch) get zero data and weight and
+// depths past nz get x = 0, so no per-element masking is needed; the depths
+// past nz are never stored.
+template <int ZPL>
+__global__ __launch_bounds__(256) void resid_kernel(const Item* __restrict__ items,
                                                     const int32_t* __restrict__ sched,
-                                                    const zd* __restrict__ g64,
-                                                    const double* __restrict__ freq, double eps,
-                                                    double dz, int ncls, int nz,
-                                                    const zd* __restrict__ ub,
+                                                    const GRow* __restrict__ grow,
+                                                    const double* __restrict__ gsc,
+                                                    const zd* __restrict__ ubw,
+                                                    const zd* __restrict__ g64, int nz,
                                                     const double* __restrict__ x,
                                                     const int32_t* __restrict__ conv,
                                                     double* __restrict__ rpart) {
     __shared__ double s_acc[4][2][ZPL * 64];
-    __shared__ double s_tr[4];
     const int32_t k = sched[blockIdx.x];
-    if (k < 0) return;   // hole in the XCD-interleaved schedule
+    if (k < 0) return;   // hole in the XCD-aware schedule
     const Item it = items[k];
-    if (WITHX && conv[it.pair]) return;
+    if (conv[it.pair]) return;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: row data via scalar loads
     const int n = it.row_end - it.row_begin;
@@ -135,82 +137,67 @@ __global__ __launch_bounds__(256) void resid_kernel(const uint32_t* __restrict__
 #pragma unroll
     for (int q = 0; q < ZPL; ++q) {
         const int z = lane + 64 * q;
-        xv[0][q] = (WITHX && z < nz) ? x[size_t(it.pair) * 2 * nz + z] : 0.0;
-        xv[1][q] = (WITHX && z < nz) ? x[size_t(it.pair) * 2 * nz + nz + z] : 0.0;
+        xv[0][q] = z < nz ? x[size_t(it.pair) * 2 * nz + z] : 0.0;
+        xv[1][q] = z < nz ? x[size_t(it.pair) * 2 * nz + nz + z] : 0.0;
     }
-    double acc[2][ZPL], tr[ZPL];
+    double acc[2][ZPL];
 #pragma unroll
-    for (int q = 0; q < ZPL; ++q) acc[0][q] = acc[1][q] = tr[q] = 0.0;
+    for (int q = 0; q < ZPL; ++q) acc[0][q] = acc[1][q] = 0.0;
 
     for (int b0 = 0; b0 < n; b0 += 16) {
-        // Loads are unconditional (clamped row and depth) and masked after the
-        // fact, so a batch issues all of its table loads before one wait.
-        zd P[4][ZPL], ep[4], em[4], W[4];
-        URow u[4];
-        bool valid[4];
+        // the 4 rows of this wave in the batch; every load of the batch is
+        // issued before the first use
+        zd gr[4][ZPL], gs[4][ZPL], bp[4], bm[4];
+        double w2[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int r = b0 + 4 * j + wv;
-            valid[j] = r < n;
+            const bool on = r < n;
             const int64_t row = int64_t(it.row_begin) + min(r, n - 1);
-            u[j] = load_urow(urows, row);
-            ep[j] = ub[2 * row];
-            em[j] = ub[2 * row + 1];
-            const zd w = omega_of(freq[u[j].f], eps);
-            W[j] = dz * (w * w);
-        }
-        zd gr[4][ZPL], gs[4][ZPL];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t fb = int64_t(u[j].f) * ncls;
+            const GRow g = grow[row];
+            const zd b0v = ubw[2 * row], b1v = ubw[2 * row + 1];
+            const double sc = gsc[row];
+            bp[j] = on ? b0v : zd{0.0, 0.0};
+            bm[j] = on ? b1v : zd{0.0, 0.0};
+            w2[j] = on ? sc * sc : 0.0;
 #pragma unroll
             for (int q = 0; q < ZPL; ++q) {
                 const int zc = min(lane + 64 * q, nz - 1);
-                gr[j][q] = g64[(fb + u[j].cr) * nz + zc];
-                gs[j][q] = g64[(fb + u[j].cs) * nz + zc];
+                gr[j][q] = g64[size_t(g.off_r) + zc];
+                gs[j][q] = g64[size_t(g.off_s) + zc];
             }
         }
-        __builtin_amdgcn_sched_barrier(0);   // keep every load of the batch ahead of its use
+        __builtin_amdgcn_sched_barrier(0);
+        zd P[4][ZPL];
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int q = 0; q < ZPL; ++q)
-                P[j][q] = (valid[j] && lane + 64 * q < nz) ? gr[j][q] * gs[j][q] : zd{0.0, 0.0};
-        double y[16];
-        if (WITHX) {
-            double v[16];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-#pragma unroll
-                for (int q = 0; q < ZPL; ++q) {
-                    a0 += P[j][q].x * xv[0][q];
-                    a1 += P[j][q].y * xv[0][q];
-                    a2 += P[j][q].x * xv[1][q];
-                    a3 += P[j][q].y * xv[1][q];
-                }
-                v[4 * j] = a0;
-                v[4 * j + 1] = a1;
-                v[4 * j + 2] = a2;
-                v[4 * j + 3] = a3;
-            }
-            butterfly16(v, y, lane);
-        }
+            for (int q = 0; q < ZPL; ++q) P[j][q] = gr[j][q] * gs[j][q];
+        double v[16], y[16];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            if (WITHX) {
-                const double m = double(u[j].mult);
-                ep[j] = ep[j] - m * (W[j] * zd{y[4 * j], y[4 * j + 1]});
-                em[j] = em[j] - m * (W[j] * zd{y[4 * j + 2], y[4 * j + 3]});
+            double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll
+            for (int q = 0; q < ZPL; ++q) {
+                a0 += P[j][q].x * xv[0][q];
+                a1 += P[j][q].y * xv[0][q];
+                a2 += P[j][q].x * xv[1][q];
+                a3 += P[j][q].y * xv[1][q];
             }
-            const zd zero{0.0, 0.0};
-            const zd cp = valid[j] ? zconj(W[j]) * ep[j] : zero, cm = valid[j] ? zconj(W[j]) * em[j] : zero;
-            const double mw2 = valid[j] ? double(u[j].mult) * zabs2(W[j]) : 0.0;
+            v[4 * j] = a0;
+            v[4 * j + 1] = a1;
+            v[4 * j + 2] = a2;
+            v[4 * j + 3] = a3;
+        }
+        butterfly16(v, y, lane);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const zd cp{bp[j].x - w2[j] * y[4 * j], bp[j].y - w2[j] * y[4 * j + 1]};
+            const zd cm{bm[j].x - w2[j] * y[4 * j + 2], bm[j].y - w2[j] * y[4 * j + 3]};
 #pragma unroll
             for (int q = 0; q < ZPL; ++q) {
                 acc[0][q] += P[j][q].x * cp.x + P[j][q].y * cp.y;
                 acc[1][q] += P[j][q].x * cm.x + P[j][q].y * cm.y;
-                if (!WITHX) tr[q] += mw2 * zabs2(P[j][q]);
             }
         }
     }
@@ -219,18 +206,12 @@ __global__ __launch_bounds__(256) void resid_kernel(const uint32_t* __restrict__
         s_acc[wv][0][q * 64 + lane] = acc[0][q];
         s_acc[wv][1][q * 64 + lane] = acc[1][q];
     }
-    double t = 0.0;
-#pragma unroll
-    for (int q = 0; q < ZPL; ++q) t += tr[q];
-    t = wave_sum(t);
-    if (lane == 0) s_tr[wv] = t;
     __syncthreads();
     double* out = rpart + size_t(it.slot) * (2 * nz + 1);
     for (int e = tid; e < 2 * nz; e += 256) {
         const int h = e / nz, z = e - h * nz;
-        out[e] = s_acc[0][h][z] + s_acc[1][h][z] + s_acc[2][h][z] + s_acc[3][h][z];
+        out[e] = (s_acc[0][h][z] + s_acc[1][h][z]) + (s_acc[2][h][z] + s_acc[3][h][z]);
     }
-    if (tid == 0) out[2 * nz] = WITHX ? 0.0 : (s_tr[0] + s_tr[1] + s_tr[2] + s_tr[3]);
 }
 
 // Born forward map: for each unique row of an item, A.v[u] and A.v[-u],
@@ -288,33 +269,26 @@ hipError_t launch_bsum(const edt_plan* p, const zd* d_rows, zd* ub, hipStream_t 
 }
 
 template <int ZPL>
-static hipError_t launch_resid_z(const edt_plan* p, const zd* g64, const zd* ub, const double* x,
+static hipError_t launch_resid_z(const edt_plan* p, const zd* g64, const zd* ubw, const double* x,
                                  const int32_t* conv, double* rpart, hipStream_t st) {
     const unsigned nit = unsigned(p->rsched.size());
     if (nit == 0) return hipSuccess;
-    if (x)
-        hipLaunchKernelGGL((resid_kernel<ZPL, true>), dim3(nit), dim3(256), 0, st,
-                           dptr<const uint32_t>(p, p->lay.urows), dptr<const Item>(p, p->lay.ritems),
-                           dptr<const int32_t>(p, p->lay.rsched), g64, dptr<const double>(p, p->lay.freq),
-                           p->eps, p->dz, p->n_cls, p->nz, ub, x, conv, rpart);
-    else
-        hipLaunchKernelGGL((resid_kernel<ZPL, false>), dim3(nit), dim3(256), 0, st,
-                           dptr<const uint32_t>(p, p->lay.urows), dptr<const Item>(p, p->lay.ritems),
-                           dptr<const int32_t>(p, p->lay.rsched), g64, dptr<const double>(p, p->lay.freq),
-                           p->eps, p->dz, p->n_cls, p->nz, ub, x, conv, rpart);
+    hipLaunchKernelGGL(resid_kernel<ZPL>, dim3(nit), dim3(256), 0, st, dptr<const Item>(p, p->lay.ritems),
+                       dptr<const int32_t>(p, p->lay.rsched), dptr<const GRow>(p, p->lay.grow),
+                       dptr<const double>(p, p->lay.gsc), ubw, g64, p->nz, x, conv, rpart);
     return hipGetLastError();
 }
 
-hipError_t launch_resid(const edt_plan* p, const zd* g64, const zd* ub, const double* x,
+hipError_t launch_resid(const edt_plan* p, const zd* g64, const zd* ubw, const double* x,
                         const int32_t* conv, double* rpart, hipStream_t st) {
     switch ((p->nz + 63) / 64) {
-        case 1: return launch_resid_z<1>(p, g64, ub, x, conv, rpart, st);
-        case 2: return launch_resid_z<2>(p, g64, ub, x, conv, rpart, st);
-        case 3: return launch_resid_z<3>(p, g64, ub, x, conv, rpart, st);
-        case 4: return launch_resid_z<4>(p, g64, ub, x, conv, rpart, st);
-        case 5: return launch_resid_z<5>(p, g64, ub, x, conv, rpart, st);
-        case 6: return launch_resid_z<6>(p, g64, ub, x, conv, rpart, st);
-        case 7: return launch_resid_z<7>(p, g64, ub, x, conv, rpart, st);
+        case 1: return launch_resid_z<1>(p, g64, ubw, x, conv, rpart, st);
+        case 2: return launch_resid_z<2>(p, g64, ubw, x, conv, rpart, st);
+        case 3: return launch_resid_z<3>(p, g64, ubw, x, conv, rpart, st);
+        case 4: return launch_resid_z<4>(p, g64, ubw, x, conv, rpart, st);
+        case 5: return launch_resid_z<5>(p, g64, ubw, x, conv, rpart, st);
+        case 6: return launch_resid_z<6>(p, g64, ubw, x, conv, rpart, st);
+        case 7: return launch_resid_z<7>(p, g64, ubw, x, conv, rpart, st);
         default: return hipErrorInvalidValue;
     }
 }
