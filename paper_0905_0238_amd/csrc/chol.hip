@@ -38,7 +38,6 @@ __global__ __launch_bounds__(256, 2) void chol_solve_kernel(
     double* sP = smem;
     double* sD = smem + size_t(nz) * CBP;
     __shared__ int s_bad;
-    __shared__ double s_col[CB], s_drow[CB];
     const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int nblk = (nz + CB - 1) / CB;
     double* A = gram + size_t(p) * nz * nz;
@@ -83,9 +82,18 @@ __global__ __launch_bounds__(256, 2) void chol_solve_kernel(
                 }
         // P -= L[k0+i][t] L[k0+j][t], t < k0: 32 finished columns at a time
         for (int t0 = 0; t0 < k0; t0 += CB) {
-            for (int e = tid; e < m * CB; e += blockDim.x) {
-                const int i = e / CB, c = e % CB;
-                sP[i * CBP + c] = A[size_t(k0 + i) * nz + t0 + c];
+            // the loads of a half chunk go out together (clamped rows), then
+            // the stores: two memory round trips per chunk
+            for (int h = 0; h < 2; ++h) {
+                const int c = tid & 31, r0 = (tid >> 5) + 128 * h;
+                if (r0 < m) {
+                    double v[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) v[u] = A[size_t(k0 + min(r0 + 8 * u, m - 1)) * nz + t0 + c];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u)
+                        if (r0 + 8 * u < m) sP[(r0 + 8 * u) * CBP + c] = v[u];
+                }
             }
             __syncthreads();
 #pragma unroll
@@ -118,11 +126,13 @@ __global__ __launch_bounds__(256, 2) void chol_solve_kernel(
         __syncthreads();
         // Factor the kb x kb diagonal block in one wave and invert it.  Lane
         // (bi, bj) = (lane / 8, lane % 8) holds the 4 x 4 blocks of rows
-        // 4 bi.., columns 4 bj.. of L (a) and of D = L^{-1} (dv), lower blocks
-        // only.  Right-looking: at pivot k, column k of L and row k of D are
-        // broadcast through LDS; rows > k of both are updated.  Padding
-        // (k >= kb) stays the identity.  A wave executes its LDS operations in
-        // order, so the fences only keep the compiler from reordering.
+        // 4 bi.., columns 4 bj.. of L (a) and of D = L^{-1} (dv).  Right-
+        // looking, the pivot steps unrolled by four so that register indices
+        // are static, with no branches (a partial block is padded with the
+        // identity): at pivot k,
+        // column k of L and row k of D are scaled by their owners and passed
+        // to every lane by cross-lane permutes, then rows > k of both are
+        // updated.
         if (tid < 64) {
             const int bi = tid >> 3, bj = tid & 7;
             const bool act = bi >= bj;
@@ -136,61 +146,51 @@ __global__ __launch_bounds__(256, 2) void chol_solve_kernel(
                     a[r][c] = (act && i < kb && jj < kb && jj <= i) ? sP[i * CBP + jj] : (i == jj ? 1.0 : 0.0);
                     dv[r][c] = (i == jj) ? 1.0 : 0.0;
                 }
-            for (int k = 0; k < kb; ++k) {
-                const int kb4 = k >> 2, kr = k & 3;
-                double dg = a[0][0];
+            for (int kb4 = 0; kb4 < CB / 4; ++kb4)
 #pragma unroll
-                for (int q = 1; q < 4; ++q) dg = (kr == q) ? a[q][q] : dg;
-                double d = readlane_d(dg, kb4 * 9);   // lane of diagonal block (kb4, kb4)
-                if (!(d > 0.0) || !isfinite(d)) {
-                    if (bad == 0) bad = k0 + k + 1;
-                    d = 1.0;
+            for (int kr = 0; kr < 4; ++kr) {
+                const int k = 4 * kb4 + kr;
+                double d = readlane_d(a[kr][kr], kb4 * 9);   // lane of diagonal block (kb4, kb4)
+                const bool ok = d > 0.0 && isfinite(d);
+                bad = (!ok && bad == 0 && k < kb) ? k0 + k + 1 : bad;
+                d = ok ? d : 1.0;
+                // 1/sqrt(d) from the hardware estimate and two Newton steps
+                double inv = __builtin_amdgcn_rsq(d);
+                const double hd = 0.5 * d;
+                inv = inv * fma(-hd * inv, inv, 1.5);
+                inv = inv * fma(-hd * inv, inv, 1.5);
+                const double lkk = d * inv;
+                // colz: L[i][k] below the pivot, zero at and above it, so the
+                // rank-1 updates below need no masks (a zero factor leaves the
+                // finished rows and columns unchanged)
+                double colz[4], drow[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = 4 * bi + r;
+                    const double v = a[r][kr] * inv;
+                    colz[r] = (i > k) ? v : 0.0;
+                    if (bj == kb4) a[r][kr] = (i > k) ? v : ((i == k) ? lkk : a[r][kr]);
                 }
-                const double lkk = sqrt(d), inv = 1.0 / lkk;
-                if (act && bj == kb4) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int i = 4 * bi + r;
-                        double v = a[r][0];
-#pragma unroll
-                        for (int q = 1; q < 4; ++q) v = (kr == q) ? a[r][q] : v;
-                        v = (i == k) ? lkk : v * inv;   // L[i][k] for i >= k
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) a[r][q] = (kr == q && i >= k) ? v : a[r][q];
-                        if (i >= k) s_col[i] = v;
-                    }
+                for (int c = 0; c < 4; ++c) {
+                    const double v = dv[kr][c] * inv;   // D[k][4 bj + c], final
+                    drow[c] = v;
+                    if (bi == kb4) dv[kr][c] = v;
                 }
-                if (bi == kb4) {   // row k of D is final once scaled by 1 / L[k][k]
+                double ci[4], cj[4], dr[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    ci[q] = __shfl(colz[q], 8 * bi + kb4, 64);   // L[4 bi + q][k]
+                    cj[q] = __shfl(colz[q], 8 * bj + kb4, 64);   // L[4 bj + q][k]
+                    dr[q] = __shfl(drow[q], 8 * kb4 + bj, 64);  // D[k][4 bj + q]
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
-                        double v = dv[0][c];
-#pragma unroll
-                        for (int q = 1; q < 4; ++q) v = (kr == q) ? dv[q][c] : v;
-                        v *= inv;
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) dv[q][c] = (kr == q) ? v : dv[q][c];
-                        s_drow[4 * bj + c] = v;
+                        a[r][c] -= ci[r] * cj[c];
+                        dv[r][c] -= ci[r] * dr[c];
                     }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                if (act) {
-                    double ci[4], cj[4], dr[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        ci[q] = s_col[4 * bi + q];
-                        cj[q] = s_col[4 * bj + q];
-                        dr[q] = s_drow[4 * bj + q];
-                    }
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) {
-                            const int i = 4 * bi + r, jj = 4 * bj + c;
-                            if (jj > k && i >= jj) a[r][c] -= ci[r] * cj[c];
-                            if (i > k) dv[r][c] -= ci[r] * dr[c];
-                        }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r)

@@ -6,6 +6,9 @@
 namespace edt {
 
 constexpr int CB = 32;        // panel / solve block width
+// Off-diagonal part of a block row (or column) of L, in groups of 8: at most
+// (256 - 32) / 8 for nz <= 256.
+constexpr int kPanelGroups = 28;
 constexpr int CBP = CB + 1;   // padded LDS row
 
 // Solve L L^T x = r for the two right-hand sides held in sx[0..nz), sx[nz..2nz)
@@ -124,12 +127,20 @@ __device__ __forceinline__ void block_solve2(const double* __restrict__ L, const
         const int i = tid >> 3, part = tid & 7;   // row i of the block, 8 threads per row
         for (int e = tid; e < CB * CB; e += 256) sD[(e >> 5) * CBP + (e & 31)] = D[size_t(b) * CB * CB + e];
         double s0 = 0.0, s1 = 0.0;
-        if (i < kb) {
-            const double* row = L + size_t(k0 + i) * nz;
-            for (int c = part; c < k0; c += 8) {
-                const double l = row[c];
-                s0 += l * sx[c];
-                s1 += l * sx[nz + c];
+        if (k0 > 0) {
+            // all loads of the row panel first (clamped, unrolled), then the
+            // products: one memory round trip per block step
+            const double* row = L + size_t(k0 + min(i, kb - 1)) * nz;
+            double lv[kPanelGroups];
+#pragma unroll
+            for (int u = 0; u < kPanelGroups; ++u) lv[u] = row[min(part + 8 * u, k0 - 1)];
+#pragma unroll
+            for (int u = 0; u < kPanelGroups; ++u) {
+                const int c = part + 8 * u;
+                const double l = (c < k0 && i < kb) ? lv[u] : 0.0;
+                const int cc = min(c, k0 - 1);
+                s0 += l * sx[cc];
+                s1 += l * sx[nz + cc];
             }
         }
         s0 = sum8(s0);
@@ -160,12 +171,20 @@ __device__ __forceinline__ void block_solve2(const double* __restrict__ L, const
         {
             const int c = tid & 31, g = tid >> 5;   // column c of the block, 8 row groups
             double s0 = 0.0, s1 = 0.0;
-            if (c < kb)
-                for (int m = k0 + CB + g; m < nz; m += 8) {
-                    const double l = L[size_t(m) * nz + k0 + c];
-                    s0 += l * sx[m];
-                    s1 += l * sx[nz + m];
+            const int r0 = k0 + CB;   // rows r0 + g + 8u below the block
+            if (r0 < nz) {
+                double lv[kPanelGroups];
+#pragma unroll
+                for (int u = 0; u < kPanelGroups; ++u) lv[u] = L[size_t(min(r0 + g + 8 * u, nz - 1)) * nz + k0 + min(c, kb - 1)];
+#pragma unroll
+                for (int u = 0; u < kPanelGroups; ++u) {
+                    const int m = r0 + g + 8 * u;
+                    const double l = (m < nz && c < kb) ? lv[u] : 0.0;
+                    const int mm = min(m, nz - 1);
+                    s0 += l * sx[mm];
+                    s1 += l * sx[nz + mm];
                 }
+            }
             sred[g * 64 + c] = s0;
             sred[g * 64 + CB + c] = s1;
         }
