@@ -10,7 +10,9 @@ Workload (default): the 2D layered survey -- 512 surface positions at 12.5 m
 (512 k_m, 257 +-k_m pairs), 8-layer reference, nz = 256 at 8 m, 128
 frequencies 3-60 Hz, smooth random model, 5% complex Gaussian data noise.
 A step is one pass of green -> assemble -> solve(-> refine -> recombine) over
-the whole survey with inputs resident in HBM.
+the whole survey with inputs resident in HBM, captured once into a HIP graph
+and replayed; per-kernel times come from an eager pass with the library's
+HIP-event timer.
 
 Inputs are synthesised on the GPU (Born forward map of the seeded model plus
 counter-based noise); the CPU-baseline leg re-derives its own data with the
@@ -43,13 +45,14 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--mixed", default="bf16x3", choices=["bf16x3", "fp32"])
-    ap.add_argument("--refine-tol", type=float, default=1e-8)
+    ap.add_argument("--refine-tol", type=float, default=1e-6)
     ap.add_argument("--max-refine", type=int, default=8)
     ap.add_argument("--chunk", type=int, default=0, help="rows per Gram item (0 = planner default)")
     ap.add_argument("--band", type=int, default=0, help="frequencies per Gram band (0 = planner default)")
     ap.add_argument("--cpu-pairs", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--only", choices=["both", "mixed", "fp64"], default="both")
+    ap.add_argument("--tune", action="store_true", help="autotune chunk_rows / gram_band per precision first")
     return ap.parse_args()
 
 
@@ -80,60 +83,43 @@ def synth_inputs(s, plan, vel, torch):
     return torch.from_numpy(dn).cuda()
 
 
-class Runner:
-    """Preallocated buffers for one precision; step() is one full pass."""
-
-    def __init__(self, plan, vel, d, lam, prec, refine_tol, max_refine, torch):
-        self.p, self.vel, self.d, self.lam, self.prec = plan, vel, d, lam, prec
-        self.tol, self.maxr = refine_tol, max_refine
-        P, nz = plan.n_pairs, plan.nz
-        dev = plan.device
-        self.G64 = torch.empty(*plan.table_shape, dtype=torch.complex128, device=dev)
-        self.G32 = torch.empty(*plan.table_shape, dtype=torch.complex64, device=dev)
-        self.gram = torch.zeros(P, nz, nz, dtype=torch.float64, device=dev)
-        self.rhs = torch.empty(P, 2, nz, dtype=torch.float64, device=dev)
-        self.trace = torch.empty(P, dtype=torch.float64, device=dev)
-        self.x = torch.empty(P, 2, nz, dtype=torch.float64, device=dev)
-        self.v = torch.empty(plan.n_km, nz, dtype=torch.complex128, device=dev)
-        self.info = torch.empty(P, dtype=torch.int32, device=dev)
-        self.steps = torch.zeros(P, dtype=torch.int32, device=dev)
-
-    def step(self, d=None):
-        d = self.d if d is None else d
-        mixed = self.prec != "fp64"
-        g64, g32 = self.p.green(self.vel, want32=mixed, out=(self.G64, self.G32))
-        self.p.assemble(g64, g32, d, self.prec, out=(self.gram, self.rhs, self.trace))
-        self.p.solve(g64, d, self.gram, self.rhs, self.trace, self.lam, refine=mixed,
-                     refine_tol=self.tol, max_refine=self.maxr,
-                     out=(self.x, self.v, self.info, self.steps))
-
-
-def time_steps(run, steps, warmup, torch):
+def time_steps(pipe, steps, warmup, torch):
+    """ms per step of the captured pass (HIP graph replays bracketed by
+    device synchronisations and events on the replay stream), and of the
+    eager pass for reference."""
+    pipe.capture(warmup=max(1, warmup))
     for _ in range(warmup):
-        run.step()
+        pipe.replay()
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record()
     for _ in range(steps):
-        run.step()
+        pipe.replay()
     e1.record()
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3 / steps
-    return e0.elapsed_time(e1) / steps, wall
-
-
-def kernel_times(run, steps, torch):
-    """Average duration per launch of every kernel over `steps` passes, measured
-    with HIP events recorded by the library on the launch stream."""
-    run.p.timing(True)
-    run.p.timing_read()
-    for _ in range(steps):
-        run.step()
+    graph_ms = e0.elapsed_time(e1) / steps
     torch.cuda.synchronize()
-    t = run.p.timing_read()
-    run.p.timing(False)
+    e0.record()
+    for _ in range(steps):
+        pipe.step()
+    e1.record()
+    torch.cuda.synchronize()
+    return graph_ms, wall, e0.elapsed_time(e1) / steps
+
+
+def kernel_times(pipe, steps, torch):
+    """Average duration per launch of every kernel over `steps` eager passes,
+    measured with HIP events recorded by the library on the launch stream."""
+    pipe.p.timing(True)
+    pipe.p.timing_read()
+    for _ in range(steps):
+        pipe.step()
+    torch.cuda.synchronize()
+    t = pipe.p.timing_read()
+    pipe.p.timing(False)
     return {k: {"avg_ms": ms / max(n, 1), "launches_per_step": n / steps, "ms_per_step": ms / steps}
             for k, (ms, n) in t.items()}
 
@@ -201,7 +187,7 @@ def roofline(plan, s, ktimes, prec, steps):
                  "per_launch": f"lower triangles read + written {by:.4g} B"}
 
 
-def cpu_baseline_leg(s, plan, runners, n_pairs_sample, torch):
+def cpu_baseline_leg(s, plan, pipes, n_pairs_sample, torch):
     """Time the FP64 oracle on a seeded sample of pairs (host cores), and state
     the GPU error on the same oracle data for those pairs."""
     from edt_inputs import vhat
@@ -236,16 +222,19 @@ def cpu_baseline_leg(s, plan, runners, n_pairs_sample, torch):
     # GPU on identical inputs: the oracle's data overwrite the sampled pairs
     m = plan.rowmap()
     off = m["row_off"]
-    d_host = runners[0].d.cpu().numpy()
+    d_keep = pipes[0].d.clone()
+    d_host = d_keep.cpu().numpy()
     for i, (d0, d1) in zip(pick, data):
         d_host[off[i]:off[i + 1], 0] = d0
         d_host[off[i]:off[i + 1], 1] = d1
     d_mix = torch.from_numpy(d_host).cuda()
     errs = {}
-    for r in runners:
-        r.step(d_mix)
+    for r in pipes:
+        r.set_data(d_mix)
+        r.step()
         torch.cuda.synchronize()
         v = r.v.cpu().numpy()
+        r.set_data(d_keep)
         num = den = 0.0
         per = []
         norms = []
@@ -286,27 +275,43 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     s = make_config(a.config)
-    t0 = time.perf_counter()
-    plan = E.Plan(s, chunk_rows=a.chunk, gram_band=a.band).upload()
-    plan_s = time.perf_counter() - t0
+    precs = {"both": ["fp64", a.mixed], "mixed": [a.mixed], "fp64": ["fp64"]}[a.only]
     vel = torch.tensor(s.vel, dtype=torch.float64, device="cuda")
+    tuned = {}
+    if a.tune:
+        from paper_0905_0238_amd.tune import autotune
+        for pr in precs:
+            tuned[pr] = autotune(s, prec=pr)
+    t0 = time.perf_counter()
+    plans = {}
+    for pr in precs:
+        opts = (tuned[pr]["chunk_rows"], tuned[pr]["gram_band"]) if pr in tuned else (a.chunk, a.band)
+        if opts not in plans:
+            plans[opts] = E.Plan(s, chunk_rows=opts[0], gram_band=opts[1]).upload()
+        plans[pr] = plans[opts]
+    plan_s = time.perf_counter() - t0
+    plan = plans[precs[-1]]
     d = synth_inputs(s, plan, vel, torch)
     torch.cuda.synchronize()
-    precs = {"both": ["fp64", a.mixed], "mixed": [a.mixed], "fp64": ["fp64"]}[a.only]
-    runners = [Runner(plan, vel, d, s.lambda_rel, pr, a.refine_tol, a.max_refine, torch) for pr in precs]
+    pipes = [E.Pipeline(plans[pr], vel, d, s.lambda_rel, pr, a.refine_tol, a.max_refine) for pr in precs]
     res = {}
-    for r in runners:
-        ms, wall = time_steps(r, a.steps, a.warmup, torch)
-        kt = kernel_times(r, max(2, min(a.steps, 5)), torch)
-        st = r.steps.cpu().numpy()
-        info = r.info.cpu().numpy()
-        res[r.prec] = {"ms_per_step": ms, "wall_ms_per_step": wall, "kernels": kt, "_steps": st,
-                       "refine_steps": {"max": int(st.max()), "mean": float(st.mean())},
-                       "info_nonzero": int(np.sum((info != 0) & (info != -1)))}
+    for pipe in pipes:
+        ms, wall, eager_ms = time_steps(pipe, a.steps, a.warmup, torch)
+        kt = kernel_times(pipe, max(2, min(a.steps, 5)), torch)
+        st = pipe.steps.cpu().numpy()
+        info = pipe.info.cpu().numpy()
+        res[pipe.prec] = {"ms_per_step": ms, "wall_ms_per_step": wall, "eager_ms_per_step": eager_ms,
+                          "kernels": kt, "_steps": st,
+                          "refine_steps": {"max": int(st.max()), "mean": float(st.mean())},
+                          "info_nonzero": int(np.sum((info != 0) & (info != -1))),
+                          "items": {"chunk_rows": pipe.p.info["chunk_rows"], "gram_band": pipe.p.info["gram_band"],
+                                    "n_items": pipe.p.info["n_items"]}}
+        if pipe.prec in tuned:
+            res[pipe.prec]["tuner"] = tuned[pipe.prec]["table"]
     main_prec = precs[-1]
     t_main = res[main_prec]["ms_per_step"]
     value = plan.n_km / (t_main * 1e-3)
-    dom, roof = roofline(plan, s, res[main_prec]["kernels"], main_prec, res[main_prec]["_steps"])
+    dom, roof = roofline(plans[main_prec], s, res[main_prec]["kernels"], main_prec, res[main_prec]["_steps"])
     for v in res.values():
         v.pop("_steps")
     roof["kernel"] = dom
@@ -329,7 +334,7 @@ def main():
     out["detail"] = {k: {kk: vv for kk, vv in v.items()} for k, v in res.items()}
     out["detail"]["plan_s"] = plan_s
     if not a.no_cpu:
-        base, errs = cpu_baseline_leg(s, plan, runners, a.cpu_pairs, torch)
+        base, errs = cpu_baseline_leg(s, plan, pipes, a.cpu_pairs, torch)
         out["cpu_baseline"] = base
         out["rel_err_vs_oracle"] = errs
     print(json.dumps(out), flush=True)

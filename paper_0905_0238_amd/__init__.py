@@ -10,5 +10,7 @@ C-ABI (``include/edt.h``).
 """
 from . import _lib
 from .edt import Plan, solve
+from .pipeline import Pipeline
+from .autograd import EDTSolve, edt_solve
 
-__all__ = ["Plan", "solve", "_lib"]
+__all__ = ["Plan", "solve", "Pipeline", "EDTSolve", "edt_solve", "_lib"]
