@@ -142,6 +142,24 @@ def _f64_mfma_flops(plan, nz):
     return stages * (nb * (nb + 1) // 2) * 4 * 16 * 16 * 4 * 2.0
 
 
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes scaled by a plain-copy calibration), or
+    None if there is none or the kernel's source changed since it was taken."""
+    import glob
+    import hashlib
+    for fn in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")):
+        with open(fn) as fh:
+            t = json.load(fh)
+        if t.get("kernel") != kernel or t.get("workload") != workload:
+            continue
+        with open(os.path.join(ROOT, t["source"]), "rb") as fh:
+            if hashlib.sha1(fh.read()).hexdigest() != t["source_sha1"]:
+                return None
+        return float(t["hbm_bytes_per_launch"])
+    return None
+
+
 def roofline(plan, s, ktimes, prec, steps):
     """Roofline entry of the dominant kernel of one step.  Algorithmic work
     counts the distinct Born rows (rows merged by reciprocity are formed once):
@@ -315,6 +333,9 @@ def main():
     for v in res.values():
         v.pop("_steps")
     roof["kernel"] = dom
+    roof["traffic"] = measured_traffic(dom, CONFIG_NAMES[a.config])
+    if roof["traffic"] is not None:
+        roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)"
     out = {
         "metric": METRIC, "value": value, "unit": "subproblems/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": t_main, "higher_is_better": True, "scaling": "weak",
