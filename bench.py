@@ -2,9 +2,10 @@
 """Benchmark of the batched 1D depth inversions of extended diffraction tomography.
 
 Metric: 1D subproblems (k_m values) solved per second on one MI355X, for the
-mixed-precision path (BF16x3 Gram on MFMA + FP64 Cholesky + FP64 refinement)
-next to the plain FP64 path (FP64 MFMA Gram + FP64 Cholesky), at relative
-error <= 1e-6 (mixed) / <= 1e-10 (FP64) against the FP64 CPU oracle.
+mixed-precision path (split-half Gram on MFMA -- FP16x3 by default, BF16x3
+also timed -- + FP64 Cholesky + FP64 refinement) next to the plain FP64 path
+(FP64 MFMA Gram + FP64 Cholesky), at relative error <= 1e-6 (mixed) /
+<= 1e-10 (FP64) against the FP64 CPU oracle.
 
 Workload (default): the 2D layered survey -- 512 surface positions at 12.5 m
 (512 k_m, 257 +-k_m pairs), 8-layer reference, nz = 256 at 8 m, 128
@@ -35,7 +36,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "1D subproblems solved/s, mixed vs FP64 plain, at rel err ≤1e-6 vs FP64 oracle"
-PEAK = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6, "hbm": 8000.0}   # TFLOP/s, GB/s
+PEAK = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3, "fp64": 78.6, "hbm": 8000.0}   # TFLOP/s, GB/s
 
 
 def parse():
@@ -44,7 +45,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--mixed", default="bf16x3", choices=["bf16x3", "fp32"])
+    ap.add_argument("--mixed", default="fp16x3", choices=["bf16x3", "fp16x3", "fp32"],
+                    help="mixed path of the headline value")
+    ap.add_argument("--also", default="bf16x3", help="comma-separated further mixed paths timed for the detail "
+                    "('' for none)")
     ap.add_argument("--refine-tol", type=float, default=1e-6)
     ap.add_argument("--max-refine", type=int, default=8)
     ap.add_argument("--chunk", type=int, default=0, help="rows per Gram item (0 = planner default)")
@@ -172,13 +176,13 @@ def roofline(plan, s, ktimes, prec, steps):
     avg_s = kt["avg_ms"] * 1e-3
     U = info["n_urows"]
     if dom.startswith("gram_"):
-        dt = {"gram_bf16x3": "bf16", "gram_fp32": "fp32", "gram_fp64": "fp64"}[dom]
+        dt = {"gram_bf16x3": "bf16", "gram_fp16x3": "fp16", "gram_fp32": "fp32", "gram_fp64": "fp64"}[dom]
         fl = 2.0 * U * s.nz * (s.nz + 1)
         ach = fl / avg_s / 1e12
         out = {"bound": "mfma", "achieved": ach, "peak": PEAK[dt], "unit": "TFLOP/s",
                "frac": ach / PEAK[dt], "traffic": None,
                "per_launch": f"2 U nz (nz+1) = {fl:.4g} flop (U = {U} unique rows)"}
-        ex = {"bf16": _bf16_mfma_flops, "fp64": _f64_mfma_flops}.get(dt)
+        ex = {"bf16": _bf16_mfma_flops, "fp16": _bf16_mfma_flops, "fp64": _f64_mfma_flops}.get(dt)
         if ex is not None:
             out["mfma_issued_frac"] = ex(plan, s.nz) / avg_s / 1e12 / PEAK[dt]
         return dom, out
@@ -293,7 +297,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     s = make_config(a.config)
-    precs = {"both": ["fp64", a.mixed], "mixed": [a.mixed], "fp64": ["fp64"]}[a.only]
+    extra = [m for m in a.also.split(",") if m and m != a.mixed] if a.only == "both" else []
+    precs = {"both": ["fp64"] + extra + [a.mixed], "mixed": [a.mixed], "fp64": ["fp64"]}[a.only]
     vel = torch.tensor(s.vel, dtype=torch.float64, device="cuda")
     tuned = {}
     if a.tune:
@@ -340,7 +345,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "subproblems/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": t_main, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16x3+f64" if main_prec == "bf16x3" else ("f32+f64" if main_prec == "fp32" else "f64"),
+        "dtype": {"bf16x3": "bf16x3+f64", "fp16x3": "f16x3+f64", "fp32": "f32+f64"}.get(main_prec, "f64"),
         "data": "synthetic",
         "config": {"workload": CONFIG_NAMES[a.config], "n_km": plan.n_km, "n_pairs": plan.n_pairs,
                    "nz": s.nz, "n_freq": s.n_freq, "rows": plan.n_rows, "unique_rows": plan.info["n_urows"],

@@ -77,7 +77,9 @@ enum {
 typedef enum {
     EDT_FP64 = 0,    /* Gram on FP64 MFMA (v_mfma_f64_16x16x4) */
     EDT_FP32 = 1,    /* Gram on FP32 MFMA with FP32 accumulation */
-    EDT_BF16X3 = 2   /* Gram on BF16 MFMA: hi*hi + hi*lo + lo*hi, FP32 accumulation */
+    EDT_BF16X3 = 2,  /* Gram on BF16 MFMA: hi*hi + hi*lo + lo*hi, FP32 accumulation */
+    EDT_FP16X3 = 3   /* the same split in IEEE half (about 22 bits per product), the rows of
+                        each work item scaled by a power of two into the half range */
 } edt_precision;
 
 /*
@@ -231,10 +233,11 @@ edt_status edt_green(const edt_plan* plan, const double* vel_dev, edt_c128* g64,
  * same pass over the rows, rhs[p][0|1][z] = Re(A_p^H b+-) and
  * trace[p] = tr Re(A_p^H A_p).  d_rows[r] = (datum at +k_m, datum at -k_m) of
  * row r, complex128, so b+ = (d0+d1)/2 and b- = (d0-d1)/(2i) (eq. Split).
- * prec EDT_FP64 reads g64 and gives rhs and trace in FP64.  EDT_FP32 and
- * EDT_BF16X3 read g32 (from edt_green); their rhs is accumulated in FP32 (an
- * approximation that the FP64 refinement residual of edt_solve corrects) and
- * their trace from FP32 rows with FP64 sums (relative error about 1e-8).
+ * prec EDT_FP64 reads g64 and gives rhs and trace in FP64.  EDT_FP32,
+ * EDT_BF16X3 and EDT_FP16X3 read g32 (from edt_green); their rhs is
+ * accumulated in FP32 (an approximation that the FP64 refinement residual of
+ * edt_solve corrects) and their trace from FP32 rows with FP64 sums
+ * (relative error about 1e-8).
  * work: device, >= work_bytes.  Empty pairs get zero Gram, rhs and trace.
  */
 edt_status edt_assemble(const edt_plan* plan, const edt_c128* g64, const edt_c64* g32,

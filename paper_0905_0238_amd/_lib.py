@@ -10,8 +10,8 @@ LIB_PATH = os.path.join(HERE, "lib", "libedt.so")
 
 EDT_OK, EDT_EINVAL, EDT_ENOMEM, EDT_EHIP, EDT_ESTATE = 0, -1, -2, -3, -4
 INFO_OK, INFO_EMPTY, INFO_NOCONV, INFO_NONFINITE = 0, -1, -2, -3
-FP64, FP32, BF16X3 = 0, 1, 2
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+FP64, FP32, BF16X3, FP16X3 = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3}
 
 
 class Survey(C.Structure):

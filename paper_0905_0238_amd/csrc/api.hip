@@ -11,7 +11,9 @@
 namespace edt {
 hipError_t launch_green(const edt_plan* p, const double* vel, zd* g64, float2* g32, hipStream_t st);
 hipError_t launch_gram(const edt_plan* p, edt_precision prec, const zd* g64, const float2* g32,
-                       const zd* ubw, const float4* ub32, void* part, double* rpart, hipStream_t st);
+                       const zd* ubw, const float4* ub32, const float* gmax, void* part, double* rpart,
+                       hipStream_t st);
+hipError_t launch_gmax(const edt_plan* p, const float2* g32, float* gmax, hipStream_t st);
 hipError_t launch_gram_reduce(const edt_plan* p, edt_precision prec, const void* part, double* gram,
                               hipStream_t st);
 hipError_t launch_rhs_reduce(const edt_plan* p, const double* rpart, double* rhs, double* trace,
@@ -170,7 +172,7 @@ edt_status edt_assemble(const edt_plan* p, const edt_c128* g64, const edt_c64* g
                         double* trace, void* work, hipStream_t stream) {
     edt_status s = check_plan(p);
     if (s != EDT_OK) return s;
-    if (prec != EDT_FP64 && prec != EDT_FP32 && prec != EDT_BF16X3) {
+    if (prec != EDT_FP64 && prec != EDT_FP32 && prec != EDT_BF16X3 && prec != EDT_FP16X3) {
         set_error("unknown precision");
         return EDT_EINVAL;
     }
@@ -191,9 +193,13 @@ edt_status edt_assemble(const edt_plan* p, const edt_c128* g64, const edt_c64* g
     // one pass over the rows gives the Gram partials and the right-hand side
     // and trace partials of every item
     double* rpart = reinterpret_cast<double*>(w + wl.gram_rpart);
-    EDT_TRY(launch_gram(p, prec, G64, reinterpret_cast<const float2*>(g32), ubw, ub32, w + wl.gram_part,
+    float* gmax = reinterpret_cast<float*>(w + wl.gmax);
+    if (prec == EDT_FP16X3)
+        EDT_TRY(launch_gmax(p, reinterpret_cast<const float2*>(g32), gmax, stream), "gmax");
+    EDT_TRY(launch_gram(p, prec, G64, reinterpret_cast<const float2*>(g32), ubw, ub32, gmax, w + wl.gram_part,
                         rpart, stream),
-            f64 ? "gram_fp64" : (prec == EDT_FP32 ? "gram_fp32" : "gram_bf16x3"));
+            f64 ? "gram_fp64"
+                : (prec == EDT_FP32 ? "gram_fp32" : (prec == EDT_BF16X3 ? "gram_bf16x3" : "gram_fp16x3")));
     EDT_TRY(launch_gram_reduce(p, prec, w + wl.gram_part, gram, stream), "gram_reduce");
     EDT_TRY(launch_rhs_reduce(p, rpart, rhs, trace, stream), "rhs reduce");
     return EDT_OK;

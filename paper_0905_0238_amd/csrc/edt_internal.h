@@ -101,6 +101,7 @@ struct WorkLayout {
     size_t ub;          // [U][2] complex128 summed data b+ and b- of each unique row
     size_t ubw;         // [U][2] complex128 conj(W) ub (FP64 Gram right-hand side)
     size_t ub32;        // [U] float4 conj(W)/|W| ub (FP32 / BF16x3 Gram right-hand side)
+    size_t gmax;        // [n_freq * n_cls] FP32 max_z |g32| (FP16x3 row scaling)
     size_t gram_part;   // [n_items][ntiles][tile] partial Gram tiles (FP64 or FP32)
     size_t rhs_part;    // [n_ritems][2*nz + 1] FP64 partial residuals (refinement, adjoint)
     size_t gram_rpart;  // [n_items][2*nz + 1] FP64 partial rhs and trace from the Gram kernels

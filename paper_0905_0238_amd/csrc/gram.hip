@@ -21,11 +21,14 @@
 //   FP32:   v_mfma_f32_32x32x2_f32;
 //   FP64:   v_mfma_f64_16x16x4_f64 on FP64 rows built from the FP64 table.
 
+#include <type_traits>
+
 #include "dev_common.h"
 
 namespace edt {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -49,6 +52,23 @@ __device__ __forceinline__ uint32_t pack_bf16x2(__bf16 a, __bf16 b) {
     return uint32_t(ua) | (uint32_t(ub) << 16);
 }
 
+// Split x = hi + lo into two 16-bit values (F16: IEEE half, else bfloat16)
+// and pack (x0, x1) halves as (hi0 | hi1 << 16), (lo0 | lo1 << 16).
+template <bool F16>
+__device__ __forceinline__ void split_pack(float x0, float x1, uint32_t& hi, uint32_t& lo) {
+    if constexpr (F16) {
+        const _Float16 h0 = _Float16(x0), h1 = _Float16(x1);
+        const _Float16 l0 = _Float16(x0 - float(h0)), l1 = _Float16(x1 - float(h1));
+        hi = uint32_t(__builtin_bit_cast(uint16_t, h0)) | (uint32_t(__builtin_bit_cast(uint16_t, h1)) << 16);
+        lo = uint32_t(__builtin_bit_cast(uint16_t, l0)) | (uint32_t(__builtin_bit_cast(uint16_t, l1)) << 16);
+    } else {
+        const __bf16 h0 = __bf16(x0), h1 = __bf16(x1);
+        const __bf16 l0 = __bf16(x0 - float(h0)), l1 = __bf16(x1 - float(h1));
+        hi = pack_bf16x2(h0, h1);
+        lo = pack_bf16x2(l0, l1);
+    }
+}
+
 // ---------------------------------------------------------------- BF16x3 ---
 template <int NT>
 struct Bf16Cfg {
@@ -58,20 +78,21 @@ struct Bf16Cfg {
     static constexpr int STR = 24;   // bf16 per LDS z-row: 16 real rows + 8 pad (48 B)
 };
 
-template <int NT, int W>
-__device__ __forceinline__ void bf16_wave_mfma(f32x16 (&acc)[Bf16Cfg<NT>::TPW], const __bf16* hi,
-                                               const __bf16* lo, int lane) {
+template <int NT, int W, bool F16>
+__device__ __forceinline__ void split3_wave_mfma(f32x16 (&acc)[Bf16Cfg<NT>::TPW], const uint16_t* hi,
+                                                 const uint16_t* lo, int lane) {
     using C = Bf16Cfg<NT>;
+    typedef typename std::conditional<F16, f16x8, bf16x8>::type v8;
     constexpr int t0 = W * C::TPW;
     constexpr int t1 = (t0 + C::TPW < C::NTL) ? t0 + C::TPW : C::NTL;
     constexpr uint32_t need = t0 < t1 ? block_mask(t0, t1) : 0u;
-    bf16x8 fh[NT], fl[NT];
+    v8 fh[NT], fl[NT];
     const int roff = (lane & 31) * C::STR + (lane >> 5) * 8;
 #pragma unroll
     for (int b = 0; b < NT; ++b) {
         if (need & (1u << b)) {
-            fh[b] = *reinterpret_cast<const bf16x8*>(hi + b * 32 * C::STR + roff);
-            fl[b] = *reinterpret_cast<const bf16x8*>(lo + b * 32 * C::STR + roff);
+            fh[b] = *reinterpret_cast<const v8*>(hi + b * 32 * C::STR + roff);
+            fl[b] = *reinterpret_cast<const v8*>(lo + b * 32 * C::STR + roff);
         }
     }
 #pragma unroll
@@ -79,16 +100,22 @@ __device__ __forceinline__ void bf16_wave_mfma(f32x16 (&acc)[Bf16Cfg<NT>::TPW], 
         const int t = t0 + m;
         if (t < t1) {
             const int I = tri_I(t), J = tri_J(t);
-            acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh[I], fh[J], acc[m], 0, 0, 0);
-            acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh[I], fl[J], acc[m], 0, 0, 0);
-            acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fl[I], fh[J], acc[m], 0, 0, 0);
+            if constexpr (F16) {
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fh[I], fh[J], acc[m], 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fh[I], fl[J], acc[m], 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fl[I], fh[J], acc[m], 0, 0, 0);
+            } else {
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh[I], fh[J], acc[m], 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh[I], fl[J], acc[m], 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fl[I], fh[J], acc[m], 0, 0, 0);
+            }
         }
     }
 }
 
 template <int NT, int W>
 __device__ __forceinline__ void f32_store_tiles(const f32x16 (&acc)[Bf16Cfg<NT>::TPW], float* out,
-                                                int lane) {
+                                                int lane, float scale = 1.0f) {
     using C = Bf16Cfg<NT>;
     constexpr int t0 = W * C::TPW;
 #pragma unroll
@@ -99,7 +126,7 @@ __device__ __forceinline__ void f32_store_tiles(const f32x16 (&acc)[Bf16Cfg<NT>:
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                o[i * 32 + (lane & 31)] = acc[m][v];
+                o[i * 32 + (lane & 31)] = acc[m][v] * scale;
             }
         }
     }
@@ -133,7 +160,11 @@ struct RawStage {
     float2 ga[8], gb[8];
 };
 
-// Warp-specialised: waves 0-3 consume bf16 stages from LDS into MFMA, waves
+// Split Gram (BF16x3 or FP16x3).  Each FP32 row value x is split into two
+// 16-bit values x = hi + lo and Ah^T Ah ~ hi^T hi + hi^T lo + lo^T hi with
+// FP32 accumulation: about 16 significant bits per product with bfloat16
+// halves, about 22 with IEEE halves (which need the per-item scaling below).
+// Warp-specialised: waves 0-3 consume 16-bit stages from LDS into MFMA, waves
 // 4-7 produce them.  A producer issues the table loads of stage s+2 while it
 // forms stage s+1 (loaded one iteration earlier), so each load has about two
 // MFMA stages to arrive.  A producer thread owns one depth z and all 8 rows
@@ -146,17 +177,19 @@ struct RawStage {
 // c+-(z) = Re(A^H B+-) in FP32 (an approximation: the FP64 refinement
 // residual corrects it) and the trace sum mult |A|^2 (per stage in FP32, then
 // in FP64) into rpart[slot][0 .. 2 nz].
-template <int NT>
-__global__ __launch_bounds__(512, 1) void gram_bf16x3_kernel(const Item* __restrict__ items,
+template <int NT, bool F16>
+__global__ __launch_bounds__(512, 1) void gram_split3_kernel(const Item* __restrict__ items,
                                                              const int32_t* __restrict__ sched,
                                                              const GRow* __restrict__ grow,
                                                              const float4* __restrict__ ub32,
-                                                             const float2* __restrict__ g32, int nz,
+                                                             const float2* __restrict__ g32,
+                                                             const float* __restrict__ gmax, int nz,
                                                              float* __restrict__ part,
                                                              double* __restrict__ rpart, int max_rows) {
     using C = Bf16Cfg<NT>;
-    __shared__ __attribute__((aligned(16))) __bf16 sh[2][2][C::NZP * C::STR];
+    __shared__ __attribute__((aligned(16))) uint16_t sh[2][2][C::NZP * C::STR];
     __shared__ double s_tr[4];
+    __shared__ float s_max[8];
     extern __shared__ __attribute__((aligned(16))) uint4 s_row[];
     const int32_t k = sched[blockIdx.x];
     if (k < 0) return;   // hole in the XCD-aware schedule
@@ -165,6 +198,26 @@ __global__ __launch_bounds__(512, 1) void gram_bf16x3_kernel(const Item* __restr
     const int n = min(it.row_end - it.row_begin, max_rows);
     const int nst = (n + 7) >> 3;
     stage_rows(s_row, grow, ub32, it.row_begin, n, nst, tid, 512);
+    // FP16: the rows of the item are scaled by a power of two s so that the
+    // largest |value| is near 2^14 (inside the half range, above its
+    // subnormals); the partial Gram is scaled back by 1/s^2 (exact).  The
+    // bound per row is max_z |g(k_r)| max_z |g(k_s)| sqrt(mult).
+    float scale = 1.0f;
+    if constexpr (F16) {
+        float mx = 0.0f;
+        for (int e = tid; e < n; e += 512) {
+            const GRow g = grow[it.row_begin + e];
+            mx = fmaxf(mx, gmax[g.off_r / uint32_t(nz)] * gmax[g.off_s / uint32_t(nz)] * g.sw);
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+        if (lane == 0) s_max[wv] = mx;
+        __syncthreads();
+        float m = s_max[0];
+#pragma unroll
+        for (int w = 1; w < 8; ++w) m = fmaxf(m, s_max[w]);
+        if (m > 0.0f && isfinite(m)) scale = ldexpf(1.0f, 14 - ilogbf(m) - 1);
+    }
     {
         const int z = tid - 256;
         if (z >= nz && z < C::NZP) {
@@ -210,11 +263,8 @@ __global__ __launch_bounds__(512, 1) void gram_bf16x3_kernel(const Item* __restr
                 cp += px * __uint_as_float(b.x) + py * __uint_as_float(b.y);
                 cm += px * __uint_as_float(b.z) + py * __uint_as_float(b.w);
                 t += mt * (px * px + py * py);
-                const float pr = sw * px, pi = sw * py;
-                const __bf16 hr = __bf16(pr), hm = __bf16(pi);
-                const __bf16 lr = __bf16(pr - float(hr)), lm = __bf16(pi - float(hm));
-                h[j] = pack_bf16x2(hr, hm);
-                l[j] = pack_bf16x2(lr, lm);
+                const float ss = F16 ? sw * scale : sw;
+                split_pack<F16>(ss * px, ss * py, h[j], l[j]);
             }
             tr += double(t);
             if (z < nz) {
@@ -256,12 +306,12 @@ __global__ __launch_bounds__(512, 1) void gram_bf16x3_kernel(const Item* __restr
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[m][v] = 0.0f;
         auto compute = [&](int buf) {
-            const __bf16* hi = sh[buf][0];
-            const __bf16* lo = sh[buf][1];
-            if (wv == 0) bf16_wave_mfma<NT, 0>(acc, hi, lo, lane);
-            else if (wv == 1) bf16_wave_mfma<NT, 1>(acc, hi, lo, lane);
-            else if (wv == 2) bf16_wave_mfma<NT, 2>(acc, hi, lo, lane);
-            else bf16_wave_mfma<NT, 3>(acc, hi, lo, lane);
+            const uint16_t* hi = sh[buf][0];
+            const uint16_t* lo = sh[buf][1];
+            if (wv == 0) split3_wave_mfma<NT, 0, F16>(acc, hi, lo, lane);
+            else if (wv == 1) split3_wave_mfma<NT, 1, F16>(acc, hi, lo, lane);
+            else if (wv == 2) split3_wave_mfma<NT, 2, F16>(acc, hi, lo, lane);
+            else split3_wave_mfma<NT, 3, F16>(acc, hi, lo, lane);
         };
         __syncthreads();
         for (int s = 0; s < nst; s += 2) {
@@ -273,10 +323,11 @@ __global__ __launch_bounds__(512, 1) void gram_bf16x3_kernel(const Item* __restr
             }
         }
         float* out = part + size_t(it.slot) * C::NTL * 1024;
-        if (wv == 0) f32_store_tiles<NT, 0>(acc, out, lane);
-        else if (wv == 1) f32_store_tiles<NT, 1>(acc, out, lane);
-        else if (wv == 2) f32_store_tiles<NT, 2>(acc, out, lane);
-        else f32_store_tiles<NT, 3>(acc, out, lane);
+        const float back = 1.0f / (scale * scale);
+        if (wv == 0) f32_store_tiles<NT, 0>(acc, out, lane, back);
+        else if (wv == 1) f32_store_tiles<NT, 1>(acc, out, lane, back);
+        else if (wv == 2) f32_store_tiles<NT, 2>(acc, out, lane, back);
+        else f32_store_tiles<NT, 3>(acc, out, lane, back);
     }
     __syncthreads();
     if (tid == 0) rpart[size_t(it.slot) * (2 * nz + 1) + 2 * nz] = (s_tr[0] + s_tr[1]) + (s_tr[2] + s_tr[3]);
@@ -651,6 +702,24 @@ __global__ __launch_bounds__(256) void rhs_reduce_kernel(const double* __restric
     }
 }
 
+// gmax[f][c] = max_z |g32[f][c][z]| (FP32), for the FP16 row scaling.
+// One wave per table column.
+__global__ __launch_bounds__(256) void gmax_kernel(const float2* __restrict__ g32, int64_t ncol, int nz,
+                                                   float* __restrict__ gmax) {
+    const int lane = threadIdx.x & 63;
+    const int64_t c = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (c >= ncol) return;
+    float m = 0.0f;
+    for (int z = lane; z < nz; z += 64) {
+        const float2 v = g32[c * nz + z];
+        m = fmaxf(m, sqrtf(v.x * v.x + v.y * v.y));
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    // rounded up by a few ulps: the bound must not be below the true maximum
+    if (lane == 0) gmax[c] = m * 1.0001f;
+}
+
 // ------------------------------------------------------------- launchers ---
 // dynamic LDS of the FP32 / BF16x3 kernels: the row records of an item,
 // padded to a multiple of 8 rows, 32 bytes each
@@ -659,7 +728,8 @@ size_t row_lds_bytes(int64_t chunk_rows) { return size_t((chunk_rows + 7) / 8) *
 // Row data the Gram kernels read besides the tables (formed by bsum_kernel).
 struct GramRowData {
     const zd* ubw;        // FP64: conj(W) (b+, b-)
-    const float4* ub32;   // FP32 / BF16x3: conj(W)/|W| (b+, b-)
+    const float4* ub32;   // FP32 / split: conj(W)/|W| (b+, b-)
+    const float* gmax;    // FP16x3: max_z |g32| per table column
 };
 
 template <int NT>
@@ -672,8 +742,12 @@ static hipError_t launch_gram_nt(const edt_plan* p, edt_precision prec, const zd
     const unsigned nb = unsigned(p->sched.size());
     if (nb == 0) return hipSuccess;
     if (prec == EDT_BF16X3)
-        hipLaunchKernelGGL(gram_bf16x3_kernel<NT>, dim3(nb), dim3(512), row_lds_bytes(p->chunk_rows), st,
-                           items, sched, grow, rd.ub32, g32, p->nz, static_cast<float*>(part), rpart,
+        hipLaunchKernelGGL((gram_split3_kernel<NT, false>), dim3(nb), dim3(512), row_lds_bytes(p->chunk_rows), st,
+                           items, sched, grow, rd.ub32, g32, rd.gmax, p->nz, static_cast<float*>(part), rpart,
+                           p->chunk_rows);
+    else if (prec == EDT_FP16X3)
+        hipLaunchKernelGGL((gram_split3_kernel<NT, true>), dim3(nb), dim3(512), row_lds_bytes(p->chunk_rows), st,
+                           items, sched, grow, rd.ub32, g32, rd.gmax, p->nz, static_cast<float*>(part), rpart,
                            p->chunk_rows);
     else if (prec == EDT_FP32)
         hipLaunchKernelGGL(gram_f32_kernel<NT>, dim3(nb), dim3(256), row_lds_bytes(p->chunk_rows), st,
@@ -689,8 +763,11 @@ static hipError_t launch_gram_nt(const edt_plan* p, edt_precision prec, const zd
 template <int NT>
 static hipError_t configure_gram_nt() {
     const int bytes = int(row_lds_bytes(2048));
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_bf16x3_kernel<NT>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_split3_kernel<NT, false>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_split3_kernel<NT, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e == hipSuccess)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_f32_kernel<NT>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
@@ -710,10 +787,18 @@ hipError_t configure_gram_kernels() {
     return e;
 }
 
+hipError_t launch_gmax(const edt_plan* p, const float2* g32, float* gmax, hipStream_t st) {
+    const int64_t ncol = int64_t(p->n_freq) * p->n_cls;
+    if (ncol == 0) return hipSuccess;
+    hipLaunchKernelGGL(gmax_kernel, dim3(unsigned((ncol + 3) / 4)), dim3(256), 0, st, g32, ncol, p->nz, gmax);
+    return hipGetLastError();
+}
+
 hipError_t launch_gram(const edt_plan* p, edt_precision prec, const zd* g64, const float2* g32,
-                       const zd* ubw, const float4* ub32, void* part, double* rpart, hipStream_t st) {
+                       const zd* ubw, const float4* ub32, const float* gmax, void* part, double* rpart,
+                       hipStream_t st) {
     const int NT = (p->nz + 31) / 32;
-    const GramRowData rd{ubw, ub32};
+    const GramRowData rd{ubw, ub32, gmax};
     hipError_t e;
     switch (NT) {
         case 1: e = launch_gram_nt<1>(p, prec, g64, g32, rd, part, rpart, st); break;

@@ -191,6 +191,8 @@ WorkLayout work_layout(const edt_plan* p) {
     off = align256(off + size_t(p->n_urows) * 2 * 16);
     w.ub32 = off;
     off = align256(off + size_t(p->n_urows) * 16);
+    w.gmax = off;
+    off = align256(off + size_t(p->n_freq) * size_t(p->n_cls) * sizeof(float));
     w.gram_part = off;
     off = align256(off + size_t(p->items.size()) * gram_part_bytes_per_item(p));
     w.rhs_part = off;

@@ -118,7 +118,7 @@ def test_fp64_solve(refs, name):
         assert inf == (-1 if q.n_rows == 0 else 0)
 
 
-@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3", "fp32"])
 @pytest.mark.parametrize("name", ["cfg1", "layered-nz40", "layered-nz200", "3d-small"])
 def test_mixed_solve_with_refinement(refs, name, prec):
     s, r = _ref(refs, name)
@@ -140,6 +140,7 @@ def test_mixed_gram_is_close_to_fp64(refs):
     d = _dev(r["d_rows"])
     G64 = p.assemble(g64, g32, d, "fp64")[0].cpu().numpy()
     Gb = p.assemble(g64, g32, d, "bf16x3")[0].cpu().numpy()
+    Gh = p.assemble(g64, g32, d, "fp16x3")[0].cpu().numpy()
     Gf = p.assemble(g64, g32, d, "fp32")[0].cpu().numpy()
     low = np.tril(np.ones((s.nz, s.nz), bool))
     for i in range(G64.shape[0]):
@@ -147,6 +148,7 @@ def test_mixed_gram_is_close_to_fp64(refs):
         if sc == 0:
             continue
         assert np.max(np.abs(Gb[i][low] - G64[i][low])) <= 1e-4 * sc
+        assert np.max(np.abs(Gh[i][low] - G64[i][low])) <= 1e-5 * sc
         assert np.max(np.abs(Gf[i][low] - G64[i][low])) <= 1e-5 * sc
 
 
@@ -176,7 +178,7 @@ def test_fp64_assemble_with_small_banded_items(refs, opts):
     assert g <= 1e-6 and per <= 1e-6, (g, per)
 
 
-@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3", "fp32"])
 def test_mixed_rhs_and_trace(refs, prec):
     """FP32/BF16x3 assembly: the trace (which fixes lambda) is FP32 rows summed
     in FP64, within 1e-7 of FP64; the right-hand side is an FP32 estimate that
