@@ -49,7 +49,7 @@ def parse():
                     help="mixed path of the headline value")
     ap.add_argument("--also", default="bf16x3", help="comma-separated further mixed paths timed for the detail "
                     "('' for none)")
-    ap.add_argument("--refine-tol", type=float, default=1e-6)
+    ap.add_argument("--refine-tol", type=float, default=3e-6)
     ap.add_argument("--max-refine", type=int, default=8)
     ap.add_argument("--chunk", type=int, default=0, help="rows per Gram item (0 = planner default)")
     ap.add_argument("--band", type=int, default=0, help="frequencies per Gram band (0 = planner default)")

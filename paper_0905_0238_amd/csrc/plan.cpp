@@ -150,13 +150,28 @@ void rows_3d(edt_plan* p, const std::vector<double>& kmax, std::vector<int64_t>&
         p->pair_u.push_back(int32_t(u));
         p->pair_u.push_back(int32_t(un));
         for (int f = 0; f < p->n_freq; ++f) {
-            int64_t nflat = 0;
-            for (int64_t nx = -(Nh / 2); nx < Nh - Nh / 2; ++nx) {
-                for (int64_t ny = -(Nh / 2); ny < Nh - Nh / 2; ++ny, ++nflat) {
+            // Only offsets inside both disks |q_u +- 2n|^2 <= K can be kept; the
+            // loops are narrowed to that box (with a margin of one) and the exact
+            // test below decides, so the rows are those of the full enumeration.
+            const double K = kmax2[f] / hh;
+            const int64_t rK = int64_t(std::floor(std::sqrt(std::max(K, 0.0)))) + 1;
+            const int64_t nlo = -(Nh / 2), nhi = Nh - Nh / 2;   // [nlo, nhi)
+            auto range = [&](int64_t q, int64_t& lo, int64_t& hi) {
+                // 2n in [-rK - q, rK - q] and in [q - rK, q + rK]
+                const int64_t a = std::max(-rK - q, q - rK), b = std::min(rK - q, q + rK);
+                lo = std::max(nlo, (a >= 0 ? (a + 1) / 2 : -((-a) / 2)) - 1);
+                hi = std::min(nhi, (b >= 0 ? b / 2 : -((-b + 1) / 2)) + 2);
+            };
+            int64_t xlo, xhi, ylo, yhi;
+            range(qx, xlo, xhi);
+            range(qy, ylo, yhi);
+            for (int64_t nx = xlo; nx < xhi; ++nx) {
+                for (int64_t ny = ylo; ny < yhi; ++ny) {
                     const int64_t sr = (qx + 2 * nx) * (qx + 2 * nx) + (qy + 2 * ny) * (qy + 2 * ny);
                     const int64_t ss = (qx - 2 * nx) * (qx - 2 * nx) + (qy - 2 * ny) * (qy - 2 * ny);
                     const bool keep = (double(sr) * hh <= kmax2[f]) && (double(ss) * hh <= kmax2[f]);
                     if (!keep) continue;
+                    const int64_t nflat = (nx - nlo) * Nh + (ny - nlo);
                     p->rows.push_back(uint32_t(f));
                     p->rows.push_back(0);
                     key_r.push_back(sr);
@@ -292,7 +307,7 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
 
         // classes: 2D class = |q| (|k| = |q| dk); 3D class = rank of the integer key
         const double dk = kTwoPi / (double(p->n_mid) * p->d_mid);
-        std::map<int64_t, int> cls;
+        std::vector<int32_t> cls_of_key;
         if (p->dim == 2) {
             int64_t mx = -1;
             for (int64_t v : kr) mx = std::max(mx, v);
@@ -300,13 +315,19 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
             p->n_cls = int(mx + 1);
             for (int c = 0; c < p->n_cls; ++c) p->cls_k.push_back(std::fabs(double(c)) * dk);
         } else {
-            for (int64_t v : kr) cls[v] = 0;
-            for (int64_t v : ks) cls[v] = 0;
+            // keys are small non-negative integers: rank them through a dense table
+            int64_t mx = -1;
+            for (int64_t v : kr) mx = std::max(mx, v);
+            for (int64_t v : ks) mx = std::max(mx, v);
+            cls_of_key.assign(size_t(mx + 1), -1);
+            for (int64_t v : kr) cls_of_key[size_t(v)] = 0;
+            for (int64_t v : ks) cls_of_key[size_t(v)] = 0;
             int c = 0;
-            for (auto& kv : cls) {
-                kv.second = c++;
-                p->cls_k.push_back(std::sqrt(double(kv.first)) * (0.5 * dk));
-            }
+            for (int64_t v = 0; v <= mx; ++v)
+                if (cls_of_key[size_t(v)] == 0) {
+                    cls_of_key[size_t(v)] = c++;
+                    p->cls_k.push_back(std::sqrt(double(v)) * (0.5 * dk));
+                }
             p->n_cls = c;
         }
         if (p->n_cls == 0) { p->n_cls = 1; p->cls_k.push_back(0.0); }
@@ -314,38 +335,53 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
         for (int64_t r = 0; r < p->n_rows; ++r) {
             uint32_t cr, cs;
             if (p->dim == 2) { cr = uint32_t(kr[r]); cs = uint32_t(ks[r]); }
-            else { cr = uint32_t(cls[kr[r]]); cs = uint32_t(cls[ks[r]]); }
+            else { cr = uint32_t(cls_of_key[size_t(kr[r])]); cs = uint32_t(cls_of_key[size_t(ks[r])]); }
             p->rows[2 * r + 1] = cr | (cs << 16);
         }
 
         // unique rows: within a pair, data rows with the same frequency and the
-        // same unordered class pair have the same Born row A
+        // same unordered class pair have the same Born row A.  Rows of a pair
+        // come frequency by frequency; each frequency's rows are grouped by
+        // sorting their keys (ties keep row order), so a unique row lists its
+        // data rows in increasing order and unique rows stay sorted by f.
         p->urow_off.push_back(0);
+        p->umem_off.push_back(0);
         p->row_unique.assign(size_t(p->n_rows), -1);
-        std::vector<std::vector<int32_t>> members;
+        p->umem.reserve(size_t(p->n_rows));
+        std::vector<std::pair<uint32_t, int32_t>> seg;
+        int64_t n_u = 0;
         for (int64_t q = 0; q < p->n_pairs; ++q) {
-            std::map<uint64_t, int64_t> seen;
-            for (int64_t r = p->row_off[q]; r < p->row_off[q + 1]; ++r) {
-                const uint64_t f = p->rows[2 * r];
-                const uint64_t a = p->rows[2 * r + 1] & 0xFFFFu, b = p->rows[2 * r + 1] >> 16;
-                const uint64_t key = (f << 32) | (std::min(a, b) << 16) | std::max(a, b);
-                auto it = seen.find(key);
-                int64_t uidx;
-                if (it == seen.end()) {
-                    uidx = int64_t(members.size());
-                    seen.emplace(key, uidx);
-                    members.emplace_back();
-                    p->urows.push_back(uint32_t(f));
-                    p->urows.push_back(uint32_t(std::min(a, b) | (std::max(a, b) << 16)));
-                } else {
-                    uidx = it->second;
+            int64_t r = p->row_off[q];
+            while (r < p->row_off[q + 1]) {
+                const uint32_t f = p->rows[2 * r];
+                int64_t e = r;
+                seg.clear();
+                while (e < p->row_off[q + 1] && p->rows[2 * e] == f) {
+                    const uint32_t a = p->rows[2 * e + 1] & 0xFFFFu, b = p->rows[2 * e + 1] >> 16;
+                    seg.emplace_back(std::min(a, b) | (std::max(a, b) << 16), int32_t(e));
+                    ++e;
                 }
-                members[size_t(uidx)].push_back(int32_t(r));
-                p->row_unique[size_t(r)] = int32_t(uidx);
+                std::sort(seg.begin(), seg.end());
+                for (size_t i = 0; i < seg.size();) {
+                    size_t j = i;
+                    while (j < seg.size() && seg[j].first == seg[i].first) ++j;
+                    const size_t m = j - i;
+                    if (m >= 65536) { delete p; return fail(EDT_EINVAL, "row multiplicity >= 65536"); }
+                    p->urows.push_back(f | (uint32_t(m) << 16));
+                    p->urows.push_back(seg[i].first);
+                    for (size_t k = i; k < j; ++k) {
+                        p->umem.push_back(seg[k].second);
+                        p->row_unique[size_t(seg[k].second)] = int32_t(n_u);
+                    }
+                    p->umem_off.push_back(int32_t(p->umem.size()));
+                    ++n_u;
+                    i = j;
+                }
+                r = e;
             }
-            p->urow_off.push_back(int64_t(members.size()));
+            p->urow_off.push_back(n_u);
         }
-        p->n_urows = int64_t(members.size());
+        p->n_urows = n_u;
         p->urow_pair.assign(size_t(p->n_urows), 0);
         for (int64_t q = 0; q < p->n_pairs; ++q)
             for (int64_t uidx = p->urow_off[q]; uidx < p->urow_off[q + 1]; ++uidx)
@@ -355,7 +391,7 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
             const size_t ne = size_t(p->n_freq) * size_t(p->n_cls);
             std::vector<int32_t> cnt(ne + 1, 0);
             for (int64_t uidx = 0; uidx < p->n_urows; ++uidx) {
-                const uint32_t f = p->urows[2 * uidx];
+                const uint32_t f = p->urows[2 * uidx] & 0xFFFFu;
                 const uint32_t a = p->urows[2 * uidx + 1] & 0xFFFFu, b = p->urows[2 * uidx + 1] >> 16;
                 cnt[size_t(f) * p->n_cls + a + 1]++;
                 cnt[size_t(f) * p->n_cls + b + 1]++;
@@ -365,7 +401,7 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
             p->tab_ent.assign(size_t(cnt[ne]) * 2, 0);
             std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
             for (int64_t uidx = 0; uidx < p->n_urows; ++uidx) {
-                const uint32_t f = p->urows[2 * uidx];
+                const uint32_t f = p->urows[2 * uidx] & 0xFFFFu;
                 const uint32_t a = p->urows[2 * uidx + 1] & 0xFFFFu, b = p->urows[2 * uidx + 1] >> 16;
                 int32_t k = fill[size_t(f) * p->n_cls + a]++;
                 p->tab_ent[2 * size_t(k)] = int32_t(uidx);
@@ -375,15 +411,6 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
                 p->tab_ent[2 * size_t(k) + 1] = int32_t(a);
             }
         }
-        p->umem_off.push_back(0);
-        for (size_t uidx = 0; uidx < members.size(); ++uidx) {
-            const size_t m = members[uidx].size();
-            if (m >= 65536) { delete p; return fail(EDT_EINVAL, "row multiplicity >= 65536"); }
-            p->urows[2 * uidx] |= uint32_t(m) << 16;
-            for (int32_t r : members[uidx]) p->umem.push_back(r);
-            p->umem_off.push_back(int32_t(p->umem.size()));
-        }
-
         // stats (algorithmic Gram work counts every data row)
         p->max_rows = 0;
         p->n_empty = 0;

@@ -209,3 +209,24 @@ def test_invalid_plan_options_are_rejected(opts):
     s = SURVEYS["cfg1"]()
     with pytest.raises(RuntimeError):
         E.Plan(s, **opts)
+
+
+def test_rowmap_equals_oracle_full_size_3d():
+    """The narrowed offset loops of the 3D planner keep exactly the rows of the
+    oracle's full enumeration (128 x 128 midpoints, 64 x 64 offsets)."""
+    _lib_or_skip()
+    s = make_config(4, with_model=False)
+    p = E.Plan(s)
+    m = p.rowmap()
+    pl = oracle_plan(s)
+    off = np.zeros(len(pl.pairs) + 1, np.int64)
+    off[1:] = np.cumsum([q.n_rows for q in pl.pairs])
+    assert np.array_equal(m["row_off"], off)
+    f = np.concatenate([q.f for q in pl.pairs])
+    kr = np.concatenate([q.kr for q in pl.pairs])
+    ks = np.concatenate([q.ks for q in pl.pairs])
+    key = np.concatenate([q.key0[:, 1] for q in pl.pairs])
+    assert np.array_equal(m["rows"][:, 0], f)
+    assert np.array_equal(m["cls_k"][m["rows"][:, 1]], kr)
+    assert np.array_equal(m["cls_k"][m["rows"][:, 2]], ks)
+    assert np.array_equal(m["keys"][:, 0], key)
