@@ -141,9 +141,11 @@ typedef struct {
 } edt_plan_info;
 
 typedef struct {
-    int refine;            /* 0: one solve; 1: FP64 iterative refinement */
-    double refine_tol;     /* stop when ||dx|| <= refine_tol ||x|| (per pair) */
-    int max_refine;        /* at most this many refinement steps */
+    int refine;            /* 0: one solve; 1: FP64 refinement (preconditioned CG) */
+    double refine_tol;     /* stop when the correction ||z|| <= refine_tol ||x + z|| (per pair) */
+    int max_refine;        /* at most this many refinement sweeps over the rows */
+    int escalate;          /* with refine: pairs whose factorisation fails (info > 0) are
+                              re-assembled with the FP64 Gram and factored again */
 } edt_solve_opts;
 
 /* Message of the last failing call on this thread (static storage). */
@@ -247,10 +249,17 @@ edt_status edt_assemble(const edt_plan* plan, const edt_c128* g64, const edt_c64
 /*
  * Kernel (c): lambda_p = lambda_rel * trace[p] / nz; gram[p] is overwritten by
  * the Cholesky factor L of gram + lambda_p I (lower triangle); x[p][0|1] =
- * (L L^T)^{-1} rhs[p][0|1].  With opts->refine, x is refined in FP64: the
- * residual Re(A^H (b - A x)) - lambda x is rebuilt from g64 and d_rows until
- * ||dx|| <= refine_tol ||x|| or max_refine steps (per pair; steps[p] counts
- * them, info NOCONV if the tolerance was not met).  A self-conjugate k_m keeps
+ * (L L^T)^{-1} rhs[p][0|1].  With opts->refine, x is refined in FP64 against
+ * the exact operator M = Re(A^H A) + lambda I, applied from g64 (the first
+ * sweep forms the residual Re(A^H (b - A x)) - lambda x with d_rows): conjugate
+ * gradients preconditioned by L L^T, finished by the correction z = (L L^T)^-1 r
+ * once ||z|| <= refine_tol ||x + z||.  At most max_refine sweeps (per pair;
+ * steps[p] counts them, info NOCONV if the tolerance was not met or the
+ * iteration broke down).  With opts->escalate (and refine), a pair whose
+ * factorisation hit a non-positive pivot (a mixed-precision Gram error above
+ * lambda) is re-assembled from g64 and d_rows with the FP64 Gram, rhs and
+ * trace and factored again before the refinement; info then reports the second
+ * factorisation.  A self-conjugate k_m keeps
  * x- = 0.  v_out[u] = x+ + i x-, v_out[-u] = x+ - i x- (eq. VSym), zero for
  * empty pairs.  x: [n_pairs][2][nz]; v_out: [n_km][nz]; info, steps: [n_pairs]
  * (steps nullable).  opts nullable (= no refinement).

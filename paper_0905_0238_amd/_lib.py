@@ -39,7 +39,8 @@ class PlanOpts(C.Structure):
 
 
 class SolveOpts(C.Structure):
-    _fields_ = [("refine", C.c_int), ("refine_tol", C.c_double), ("max_refine", C.c_int)]
+    _fields_ = [("refine", C.c_int), ("refine_tol", C.c_double), ("max_refine", C.c_int),
+                ("escalate", C.c_int)]
 
 
 EXPORTS = ["edt_last_error", "edt_plan_create", "edt_plan_destroy", "edt_plan_query",

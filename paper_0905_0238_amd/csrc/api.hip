@@ -12,12 +12,12 @@ namespace edt {
 hipError_t launch_green(const edt_plan* p, const double* vel, zd* g64, float2* g32, hipStream_t st);
 hipError_t launch_gram(const edt_plan* p, edt_precision prec, const zd* g64, const float2* g32,
                        const zd* ubw, const float4* ub32, const float* gmax, void* part, double* rpart,
-                       hipStream_t st);
+                       hipStream_t st, const int32_t* only = nullptr);
 hipError_t launch_gmax(const edt_plan* p, const float2* g32, float* gmax, hipStream_t st);
 hipError_t launch_gram_reduce(const edt_plan* p, edt_precision prec, const void* part, double* gram,
-                              hipStream_t st);
+                              hipStream_t st, const int32_t* only = nullptr);
 hipError_t launch_rhs_reduce(const edt_plan* p, const double* rpart, double* rhs, double* trace,
-                             hipStream_t st);
+                             hipStream_t st, const int32_t* only = nullptr);
 hipError_t launch_bsum(const edt_plan* p, const zd* d_rows, zd* ub, hipStream_t st, zd* ubw = nullptr,
                        float4* ub32 = nullptr);
 hipError_t launch_resid(const edt_plan* p, const zd* g64, const zd* ubw, const double* x,
@@ -25,10 +25,10 @@ hipError_t launch_resid(const edt_plan* p, const zd* g64, const zd* ubw, const d
 hipError_t launch_forward(const edt_plan* p, const zd* g64, const zd* v, zd* d_rows, hipStream_t st);
 hipError_t launch_chol(const edt_plan* p, double* gram, const double* trace, const double* rhs,
                        double lambda_rel, double* lam, double* dinv, double* x, int32_t* info,
-                       int32_t* conv, int32_t* steps, hipStream_t st);
-hipError_t launch_refine_update(const edt_plan* p, const double* gram, const double* dinv,
-                                const double* rpart, const double* lam, double* x, int32_t* conv,
-                                int32_t* steps, double tol, hipStream_t st);
+                       int32_t* conv, int32_t* steps, hipStream_t st, int only_failed = 0);
+hipError_t launch_pcg_update(const edt_plan* p, const double* gram, const double* dinv, const double* rpart,
+                             const double* lam, double* x, double* r, double* pv, double* rho, int32_t* conv,
+                             int32_t* steps, double tol, int first, hipStream_t st);
 hipError_t launch_recombine(const edt_plan* p, const double* x, int refine, const int32_t* conv,
                             int32_t* info, zd* v, hipStream_t st);
 hipError_t launch_adjoint(const edt_plan* p, const double* vel, const zd* g64, const zd* d_rows,
@@ -36,7 +36,6 @@ hipError_t launch_adjoint(const edt_plan* p, const double* vel, const zd* g64, c
                           const zd* grad_v, zd* grad_d, double* grad_lambda, double* grad_vel,
                           unsigned char* work, hipStream_t st);
 size_t chol_lds_bytes(int nz);
-size_t refine_lds_bytes(int nz);
 hipError_t configure_kernels();
 
 Timer& timer_of(const edt_plan* p) {
@@ -67,8 +66,8 @@ edt_status check_plan(const edt_plan* p) {
         set_error("plan has no device copy: call edt_plan_upload first");
         return EDT_ESTATE;
     }
-    if (p->nz > 256) {
-        set_error("nz > 256 is not supported by the assembly kernels");
+    if (p->nz > kMaxDepth) {
+        set_error("nz > " + std::to_string(kMaxDepth) + " is not supported by the factorisation kernels");
         return EDT_EINVAL;
     }
     return EDT_OK;
@@ -180,6 +179,10 @@ edt_status edt_assemble(const edt_plan* p, const edt_c128* g64, const edt_c64* g
         set_error("missing argument (g32 is required for FP32 and BF16X3)");
         return EDT_EINVAL;
     }
+    if (prec == EDT_FP32 && p->nz > kSuperDepth) {
+        set_error("the FP32 Gram supports nz <= 256 (use FP64, BF16X3 or FP16X3)");
+        return EDT_EINVAL;
+    }
     const WorkLayout wl = work_layout(p);
     unsigned char* w = static_cast<unsigned char*>(work);
     zd* ub = reinterpret_cast<zd*>(w + wl.ub);
@@ -235,13 +238,35 @@ edt_status edt_solve(const edt_plan* p, const edt_c128* g64, const edt_c128* d_r
         zd* ub = reinterpret_cast<zd*>(w + wl.ub);
         zd* ubw = reinterpret_cast<zd*>(w + wl.ubw);
         double* rpart = reinterpret_cast<double*>(w + wl.rhs_part);
+        const zd* G64 = reinterpret_cast<const zd*>(g64);
         // the summed data, conj(W) B per unique row, are rebuilt here so that
         // edt_solve does not depend on an earlier call's scratch
         EDT_TRY(launch_bsum(p, reinterpret_cast<const zd*>(d_rows), ub, stream, ubw), "bsum");
+        if (opts->escalate) {
+            // pairs whose factorisation failed (info > 0): FP64 Gram, rhs and
+            // trace from the rows, and a second factorisation; every launch
+            // returns at once for the other pairs
+            double* erhs = reinterpret_cast<double*>(w + wl.esc_rhs);
+            double* etr = reinterpret_cast<double*>(w + wl.esc_trace);
+            double* gpart = reinterpret_cast<double*>(w + wl.gram_rpart);
+            EDT_TRY(launch_gram(p, EDT_FP64, G64, nullptr, ubw, nullptr, nullptr, w + wl.gram_part, gpart, stream,
+                                info),
+                    "escalate gram_fp64");
+            EDT_TRY(launch_gram_reduce(p, EDT_FP64, w + wl.gram_part, gram, stream, info), "escalate gram_reduce");
+            EDT_TRY(launch_rhs_reduce(p, gpart, erhs, etr, stream, info), "escalate rhs reduce");
+            EDT_TRY(launch_chol(p, gram, etr, erhs, lambda_rel, lam, dinv, x, info, conv, stp, stream, 1),
+                    "escalate cholesky");
+        }
+        double* r = reinterpret_cast<double*>(w + wl.pcg_r);
+        double* pv = reinterpret_cast<double*>(w + wl.pcg_p);
+        double* rho = reinterpret_cast<double*>(w + wl.pcg_rho);
+        // sweep 0: the data residual at x0; then one operator sweep per step
         for (int it = 0; it < opts->max_refine; ++it) {
-            EDT_TRY(launch_resid(p, reinterpret_cast<const zd*>(g64), ubw, x, conv, rpart, stream),
+            EDT_TRY(launch_resid(p, G64, it == 0 ? ubw : nullptr, it == 0 ? x : pv,
+                                 conv, rpart, stream),
                     "refine residual");
-            EDT_TRY(launch_refine_update(p, gram, dinv, rpart, lam, x, conv, stp, opts->refine_tol, stream),
+            EDT_TRY(launch_pcg_update(p, gram, dinv, rpart, lam, x, r, pv, rho, conv, stp, opts->refine_tol,
+                                      it == 0, stream),
                     "refine update");
         }
     }
@@ -271,6 +296,10 @@ edt_status edt_adjoint(const edt_plan* p, const double* vel_dev, const edt_c128*
     if (s != EDT_OK) return s;
     if (!vel_dev || !g64 || !d_rows || !chol || !trace || !x || !grad_v || !work) {
         set_error("missing argument");
+        return EDT_EINVAL;
+    }
+    if (p->nz > kMaxAdjointDepth) {
+        set_error("the adjoint supports nz <= 256");
         return EDT_EINVAL;
     }
     EDT_TRY(launch_adjoint(p, vel_dev, reinterpret_cast<const zd*>(g64), reinterpret_cast<const zd*>(d_rows),

@@ -17,7 +17,7 @@
 //    triangular solve).
 // L overwrites the lower triangle of the Gram in place; the block inverses
 // D go to a workspace, where the block solves (block_solve2) use them.
-// LDS stays under 80 KiB so two pairs share a CU.
+// LDS stays under 80 KiB for nz <= 256, so two pairs share a CU.
 
 #include "dev_linalg.h"
 
@@ -29,16 +29,20 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // dinv[p][nblk][32][32] and solve for x from rhs.
 // Dynamic LDS: the panel (nz x CBP doubles) and D (32 x CBP doubles), reused
 // by the solve afterwards.
-__global__ __launch_bounds__(256, 2) void chol_solve_kernel(
+// Q: row-block groups of the panel accumulators (wave w holds the 16-row
+// blocks w + 4 q, q < Q): 4 for nz <= 256, 7 for nz <= 448.
+template <int Q>
+__global__ __launch_bounds__(256, Q > 4 ? 1 : 2) void chol_solve_kernel(
     double* __restrict__ gram, const double* __restrict__ trace, const double* __restrict__ rhs,
     const int64_t* __restrict__ urow_off, const int32_t* __restrict__ pair_u, int nz,
     double lambda_rel, double* __restrict__ lam_out, double* __restrict__ dinv, double* __restrict__ x,
-    int32_t* __restrict__ info, int32_t* __restrict__ conv, int32_t* __restrict__ steps) {
+    int32_t* __restrict__ info, int32_t* __restrict__ conv, int32_t* __restrict__ steps, int only_failed) {
     extern __shared__ double smem[];
     double* sP = smem;
     double* sD = smem + size_t(nz) * CBP;
     __shared__ int s_bad;
     const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (only_failed && info[p] <= 0) return;   // second pass: failed factorisations only
     const int nblk = (nz + CB - 1) / CB;
     double* A = gram + size_t(p) * nz * nz;
     double* Dp = dinv + size_t(p) * nblk * CB * CB;
@@ -62,11 +66,11 @@ __global__ __launch_bounds__(256, 2) void chol_solve_kernel(
     for (int k0 = 0; k0 < nz; k0 += CB) {
         const int kb = min(CB, nz - k0), m = nz - k0;
         const int nrb = (m + 15) >> 4;
-        // accumulators: row blocks rb = wv + 4q (q < 4), column blocks 0..1;
+        // accumulators: row blocks rb = wv + 4q (q < Q), column blocks 0..1;
         // v_mfma_f64_16x16x4 lane l, register v holds (row 4v + l/16, column l%16)
-        f64x4 acc[4][2];
+        f64x4 acc[Q][2];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < Q; ++q)
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
@@ -84,7 +88,7 @@ __global__ __launch_bounds__(256, 2) void chol_solve_kernel(
         for (int t0 = 0; t0 < k0; t0 += CB) {
             // the loads of a half chunk go out together (clamped rows), then
             // the stores: two memory round trips per chunk
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; 128 * h < m; ++h) {
                 const int c = tid & 31, r0 = (tid >> 5) + 128 * h;
                 if (r0 < m) {
                     double v[16];
@@ -101,7 +105,7 @@ __global__ __launch_bounds__(256, 2) void chol_solve_kernel(
                 const double b0 = (li < kb) ? sP[li * CBP + kk + lk] : 0.0;
                 const double b1 = (16 + li < kb) ? sP[(16 + li) * CBP + kk + lk] : 0.0;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < Q; ++q) {
                     const int rb = wv + 4 * q;
                     if (rb < nrb) {
                         const int i = 16 * rb + li;
@@ -114,7 +118,7 @@ __global__ __launch_bounds__(256, 2) void chol_solve_kernel(
             __syncthreads();
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < Q; ++q)
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
@@ -205,9 +209,9 @@ __global__ __launch_bounds__(256, 2) void chol_solve_kernel(
         __syncthreads();
         // rows below the diagonal block: L_ik = P_ik D^T on MFMA (B[k][c] = D[c][k])
         if (m > kb) {
-            f64x4 t[4][2];
+            f64x4 t[Q][2];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < Q; ++q)
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
@@ -217,7 +221,7 @@ __global__ __launch_bounds__(256, 2) void chol_solve_kernel(
                 const double b0 = sD[li * CBP + kk + lk];
                 const double b1 = sD[(16 + li) * CBP + kk + lk];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < Q; ++q) {
                     const int rb = wv + 4 * q;
                     if (rb >= 2 && rb < nrb) {
                         const int i = 16 * rb + li;
@@ -228,7 +232,7 @@ __global__ __launch_bounds__(256, 2) void chol_solve_kernel(
                 }
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < Q; ++q)
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
@@ -249,10 +253,11 @@ __global__ __launch_bounds__(256, 2) void chol_solve_kernel(
     // block solves (LDS reused)
     double* sx = smem;
     double* sred = sx + 2 * nz;
-    double* sDs = sred + 576;
+    double* sDs = sred + kSolveRed;
+    double* sLs = sDs + CB * CBP;
     for (int e = tid; e < 2 * nz; e += blockDim.x) sx[e] = rhs[size_t(p) * 2 * nz + e];
     __syncthreads();
-    block_solve2(A, Dp, nz, sx, sred, sDs);
+    block_solve2(A, Dp, nz, sx, sred, sDs, sLs);
     for (int e = tid; e < 2 * nz; e += blockDim.x)
         x[size_t(p) * 2 * nz + e] = (selfc && e >= nz) ? 0.0 : sx[e];
     if (tid == 0) {
@@ -261,18 +266,32 @@ __global__ __launch_bounds__(256, 2) void chol_solve_kernel(
     }
 }
 
-// One refinement step for every unconverged pair:
-//   r = (sum of the residual partials) - lambda x,  dx = (L L^T)^{-1} r,
-//   x += dx, converged when ||dx|| <= tol ||x||.
-__global__ __launch_bounds__(256) void refine_update_kernel(
+// Refinement of x against the exact FP64 operator M = Re(A^H A) + lambda I
+// (applied from the Born rows by resid_kernel), preconditioned by the
+// factorisation L L^T of the assembled Gram (FP64 or mixed): conjugate
+// gradients on M x = c, one operator sweep per iteration, ending with a plain
+// correction step once it is small:
+//   z = (L L^T)^{-1} r;  if ||z|| <= tol ||x + z||: x += z, converged;
+//   else p = z + beta p (beta = (r.z)/(r.z)_prev, 0 first), next sweep q = M p,
+//        alpha = (r.z)/(p.q), x += alpha p, r -= alpha q.
+// With an accurate factorisation alpha ~ 1 and this costs the sweeps of plain
+// iterative refinement (x += z per sweep); where the mixed-precision Gram is
+// too far from M for that to contract (cond(M) times its relative error near
+// or above 1), the Krylov steps still converge.
+//   first: rpart holds c - Re(A^H A) x (swept with the data): r = it - lambda x;
+//   else:  rpart holds -Re(A^H A) p: q = lambda p - it.
+// conv: 0 running, 1 converged, -1 stopped (p.q <= 0 or not finite).
+__global__ __launch_bounds__(256) void pcg_update_kernel(
     const double* __restrict__ gram, const double* __restrict__ dinv, const double* __restrict__ rpart,
     const int32_t* __restrict__ pair_item, const int32_t* __restrict__ pair_u, int nz,
-    const double* __restrict__ lam, double* __restrict__ x, int32_t* __restrict__ conv,
-    int32_t* __restrict__ steps, double tol) {
+    const double* __restrict__ lam, double* __restrict__ x, double* __restrict__ r, double* __restrict__ pv,
+    double* __restrict__ rho, int32_t* __restrict__ conv, int32_t* __restrict__ steps, double tol, int first) {
     extern __shared__ double smem[];
     double* sx = smem;
-    double* sred = sx + 2 * nz;
-    double* sD = sred + 576;
+    double* sq = sx + 2 * nz;
+    double* sred = sq + 2 * nz;
+    double* sD = sred + kSolveRed;
+    double* sL = sD + CB * CBP;
     __shared__ double s_red[8];
     const int p = blockIdx.x, tid = threadIdx.x;
     if (conv[p]) return;
@@ -281,10 +300,13 @@ __global__ __launch_bounds__(256) void refine_update_kernel(
     const int w = 2 * nz + 1;
     const int nblk = (nz + CB - 1) / CB;
     double* xp = x + size_t(p) * 2 * nz;
+    double* rp = r + size_t(p) * 2 * nz;
+    double* pp = pv + size_t(p) * 2 * nz;
     const double lp = lam[p];
+    // sum of the item partials: eight independent partial sums keep eight
+    // loads in flight; the combination order is fixed (deterministic)
+    double pq = 0.0;
     for (int e = tid; e < 2 * nz; e += blockDim.x) {
-        // eight independent partial sums keep eight loads in flight; the
-        // combination order is fixed, so the result is deterministic
         double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         int k = k0;
         for (; k + 8 <= k1; k += 8)
@@ -292,23 +314,56 @@ __global__ __launch_bounds__(256) void refine_update_kernel(
             for (int q = 0; q < 8; ++q) s8[q] += rpart[size_t(k + q) * w + e];
         for (int q = 0; k < k1; ++k, ++q) s8[q] += rpart[size_t(k) * w + e];
         const double s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
-        sx[e] = (selfc && e >= nz) ? 0.0 : s - lp * xp[e];
+        const bool zero = selfc && e >= nz;
+        if (first) {
+            sx[e] = zero ? 0.0 : s - lp * xp[e];
+        } else {
+            const double q = zero ? 0.0 : lp * pp[e] - s;
+            sq[e] = q;
+            pq += pp[e] * q;
+        }
+    }
+    if (!first) {
+        pq = block_sum(pq, s_red);
+        const double alpha = rho[p] / pq;
+        if (!(pq > 0.0) || !isfinite(alpha)) {
+            if (tid == 0) {
+                conv[p] = -1;
+                steps[p] += 1;
+            }
+            return;
+        }
+        for (int e = tid; e < 2 * nz; e += blockDim.x) {
+            xp[e] += alpha * pp[e];
+            sx[e] = rp[e] - alpha * sq[e];
+        }
     }
     __syncthreads();
-    block_solve2(gram + size_t(p) * nz * nz, dinv + size_t(p) * nblk * CB * CB, nz, sx, sred, sD);
-    double dn = 0.0, xn = 0.0;
+    for (int e = tid; e < 2 * nz; e += blockDim.x) rp[e] = sx[e];
+    block_solve2(gram + size_t(p) * nz * nz, dinv + size_t(p) * nblk * CB * CB, nz, sx, sred, sD, sL);
+    double dn = 0.0, xn = 0.0, rz = 0.0;
     for (int e = tid; e < 2 * nz; e += blockDim.x) {
-        const double d = (selfc && e >= nz) ? 0.0 : sx[e];
-        const double v = xp[e] + d;
-        xp[e] = v;
-        dn += d * d;
+        const double z = (selfc && e >= nz) ? 0.0 : sx[e];
+        sx[e] = z;
+        const double v = xp[e] + z;
+        dn += z * z;
         xn += v * v;
+        rz += rp[e] * z;
     }
     dn = block_sum(dn, s_red);
     xn = block_sum(xn, s_red);
+    rz = block_sum(rz, s_red);
+    const bool done = dn <= tol * tol * xn;
+    const double beta = first ? 0.0 : rz / rho[p];
+    for (int e = tid; e < 2 * nz; e += blockDim.x) {
+        if (done) xp[e] += sx[e];
+        else pp[e] = sx[e] + beta * (first ? 0.0 : pp[e]);
+    }
+    __syncthreads();
     if (tid == 0) {
         steps[p] += 1;
-        if (dn <= tol * tol * xn) conv[p] = 1;
+        if (done) conv[p] = 1;
+        else rho[p] = rz;
     }
 }
 
@@ -332,15 +387,15 @@ __global__ __launch_bounds__(256) void recombine_kernel(const double* __restrict
     __syncthreads();
     if (tid == 0 && info[p] == EDT_INFO_OK) {
         if (s_nf) info[p] = EDT_INFO_NONFINITE;
-        else if (refine && !conv[p]) info[p] = EDT_INFO_NOCONV;
+        else if (refine && conv[p] != 1) info[p] = EDT_INFO_NOCONV;
     }
 }
 
 // ------------------------------------------------------------- launchers ---
-size_t refine_lds_bytes(int nz) { return block_solve_lds_doubles(nz) * sizeof(double); }
+size_t pcg_lds_bytes(int nz) { return (block_solve_lds_doubles(nz) + 2 * size_t(nz)) * sizeof(double); }
 size_t chol_lds_bytes(int nz) {
     const size_t panel = (size_t(nz) + CB) * CBP * sizeof(double);
-    const size_t solve = refine_lds_bytes(nz);
+    const size_t solve = block_solve_lds_doubles(nz) * sizeof(double);
     return panel > solve ? panel : solve;
 }
 // adjoint solves still use trisolve2 (staged panels in LDS)
@@ -350,17 +405,20 @@ size_t adjoint_lds_bytes(int nz) { return trisolve_lds_doubles(nz) * sizeof(doub
 // 160 KiB per CU).
 hipError_t configure_adjoint_kernels(int bytes);
 hipError_t configure_gram_kernels();
-// The largest dynamic LDS any supported depth count (nz <= 256) needs.
+// The largest dynamic LDS any supported depth count needs.
 static int max_dynamic_lds() {
-    const size_t a = chol_lds_bytes(256), b = adjoint_lds_bytes(256);
+    const size_t a = chol_lds_bytes(kMaxDepth), b = adjoint_lds_bytes(kMaxAdjointDepth);
     return int(a > b ? a : b);
 }
 hipError_t configure_kernels() {
     const int bytes = max_dynamic_lds();
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(chol_solve_kernel),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(chol_solve_kernel<4>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(refine_update_kernel),
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(chol_solve_kernel<7>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(pcg_update_kernel),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e == hipSuccess) e = configure_adjoint_kernels(bytes);
     if (e == hipSuccess) e = configure_gram_kernels();
@@ -369,22 +427,27 @@ hipError_t configure_kernels() {
 
 hipError_t launch_chol(const edt_plan* p, double* gram, const double* trace, const double* rhs,
                        double lambda_rel, double* lam, double* dinv, double* x, int32_t* info,
-                       int32_t* conv, int32_t* steps, hipStream_t st) {
+                       int32_t* conv, int32_t* steps, hipStream_t st, int only_failed) {
     if (p->n_pairs == 0) return hipSuccess;
     const size_t lds = chol_lds_bytes(p->nz);
-    hipLaunchKernelGGL(chol_solve_kernel, dim3(unsigned(p->n_pairs)), dim3(256), lds, st, gram, trace,
-                       rhs, dptr<const int64_t>(p, p->lay.urow_off), dptr<const int32_t>(p, p->lay.pair_u),
-                       p->nz, lambda_rel, lam, dinv, x, info, conv, steps);
+    if (p->nz <= 256)
+        hipLaunchKernelGGL(chol_solve_kernel<4>, dim3(unsigned(p->n_pairs)), dim3(256), lds, st, gram, trace,
+                           rhs, dptr<const int64_t>(p, p->lay.urow_off), dptr<const int32_t>(p, p->lay.pair_u),
+                           p->nz, lambda_rel, lam, dinv, x, info, conv, steps, only_failed);
+    else
+        hipLaunchKernelGGL(chol_solve_kernel<7>, dim3(unsigned(p->n_pairs)), dim3(256), lds, st, gram, trace,
+                           rhs, dptr<const int64_t>(p, p->lay.urow_off), dptr<const int32_t>(p, p->lay.pair_u),
+                           p->nz, lambda_rel, lam, dinv, x, info, conv, steps, only_failed);
     return hipGetLastError();
 }
 
-hipError_t launch_refine_update(const edt_plan* p, const double* gram, const double* dinv,
-                                const double* rpart, const double* lam, double* x, int32_t* conv,
-                                int32_t* steps, double tol, hipStream_t st) {
+hipError_t launch_pcg_update(const edt_plan* p, const double* gram, const double* dinv, const double* rpart,
+                             const double* lam, double* x, double* r, double* pv, double* rho, int32_t* conv,
+                             int32_t* steps, double tol, int first, hipStream_t st) {
     if (p->n_pairs == 0) return hipSuccess;
-    hipLaunchKernelGGL(refine_update_kernel, dim3(unsigned(p->n_pairs)), dim3(256),
-                       refine_lds_bytes(p->nz), st, gram, dinv, rpart, dptr<const int32_t>(p, p->lay.pair_ritem),
-                       dptr<const int32_t>(p, p->lay.pair_u), p->nz, lam, x, conv, steps, tol);
+    hipLaunchKernelGGL(pcg_update_kernel, dim3(unsigned(p->n_pairs)), dim3(256), pcg_lds_bytes(p->nz), st, gram,
+                       dinv, rpart, dptr<const int32_t>(p, p->lay.pair_ritem), dptr<const int32_t>(p, p->lay.pair_u),
+                       p->nz, lam, x, r, pv, rho, conv, steps, tol, first);
     return hipGetLastError();
 }
 

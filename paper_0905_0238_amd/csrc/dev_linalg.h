@@ -6,8 +6,8 @@
 namespace edt {
 
 constexpr int CB = 32;        // panel / solve block width
-// Off-diagonal part of a block row (or column) of L, in groups of 8: at most
-// (256 - 32) / 8 for nz <= 256.
+// Off-diagonal part of a block row (or column) of L is read in chunks of
+// kPanelGroups groups of 8 (one chunk covers nz <= 256).
 constexpr int kPanelGroups = 28;
 constexpr int CBP = CB + 1;   // padded LDS row
 
@@ -109,34 +109,52 @@ __device__ __forceinline__ double sum8(double v) {
     return v;
 }
 
+// Reduction scratch of block_solve2 (doubles).
+constexpr int kSolveRed = 704;
+
 // Solve L L^T x = r for the two right-hand sides in sx[0..nz), sx[nz..2nz)
 // (LDS), in place, by block substitution with explicit inverses of the 32 x 32
 // diagonal blocks of L:
-//   forward   y_b = D_b (r_b - sum_{j<b} L_bj y_j),
-//   backward  x_b = D_b^T (y_b - sum_{j>b} L_jb^T x_j).
+//   forward   t_b = r_b - sum_{j<b} L_bj y_j,      y_b = D_b t_b,
+//   backward  t_b = y_b - sum_{j>b} L_jb^T x_j,    x_b = D_b^T t_b,
+// each block result followed by one correction with the block itself,
+// y_b += D_b (t_b - L_bb y_b) (and the transposed form backward): applying an
+// explicit inverse loses a factor up to cond(L_bb) against substitution, the
+// correction restores substitution-level accuracy.
 // L: lower triangle of a row-major nz x nz matrix (global); D: [nblk][32][32]
 // row-major lower-triangular inverses (global).  No step has a serial chain
-// longer than one block: 2 nblk dependent matrix-vector products.
-// LDS: sred >= 576 doubles, sD >= 32 * CBP doubles.  blockDim.x must be 256.
+// longer than one block: 2 nblk dependent block steps.
+// LDS: sred >= kSolveRed doubles, sD and sL >= 32 * CBP doubles each.
+// blockDim.x must be 256.
 __device__ __forceinline__ void block_solve2(const double* __restrict__ L, const double* __restrict__ D,
-                                             int nz, double* sx, double* sred, double* sD) {
+                                             int nz, double* sx, double* sred, double* sD, double* sL) {
     const int tid = threadIdx.x;
     const int nblk = (nz + CB - 1) / CB;
+    // D_b and the lower triangle of L_bb (zero elsewhere: the upper part of
+    // the matrix is not part of L)
+    auto stage = [&](int b, int k0, int kb) {
+        for (int e = tid; e < CB * CB; e += 256) {
+            const int i = e >> 5, j = e & 31;
+            sD[i * CBP + j] = D[size_t(b) * CB * CB + e];
+            const double l = L[size_t(k0 + min(i, kb - 1)) * nz + k0 + min(j, kb - 1)];
+            sL[i * CBP + j] = (i < kb && j <= i) ? l : 0.0;
+        }
+    };
     for (int b = 0; b < nblk; ++b) {
         const int k0 = b * CB, kb = min(CB, nz - k0);
         const int i = tid >> 3, part = tid & 7;   // row i of the block, 8 threads per row
-        for (int e = tid; e < CB * CB; e += 256) sD[(e >> 5) * CBP + (e & 31)] = D[size_t(b) * CB * CB + e];
+        stage(b, k0, kb);
         double s0 = 0.0, s1 = 0.0;
-        if (k0 > 0) {
-            // all loads of the row panel first (clamped, unrolled), then the
-            // products: one memory round trip per block step
-            const double* row = L + size_t(k0 + min(i, kb - 1)) * nz;
+        // all loads of a chunk of the row panel first (clamped, unrolled),
+        // then the products: one memory round trip per chunk
+        const double* row = L + size_t(k0 + min(i, kb - 1)) * nz;
+        for (int c0 = 0; c0 < k0; c0 += 8 * kPanelGroups) {
             double lv[kPanelGroups];
 #pragma unroll
-            for (int u = 0; u < kPanelGroups; ++u) lv[u] = row[min(part + 8 * u, k0 - 1)];
+            for (int u = 0; u < kPanelGroups; ++u) lv[u] = row[min(c0 + part + 8 * u, k0 - 1)];
 #pragma unroll
             for (int u = 0; u < kPanelGroups; ++u) {
-                const int c = part + 8 * u;
+                const int c = c0 + part + 8 * u;
                 const double l = (c < k0 && i < kb) ? lv[u] : 0.0;
                 const int cc = min(c, k0 - 1);
                 s0 += l * sx[cc];
@@ -145,34 +163,64 @@ __device__ __forceinline__ void block_solve2(const double* __restrict__ L, const
         }
         s0 = sum8(s0);
         s1 = sum8(s1);
+        const double t0 = i < kb ? sx[k0 + i] - s0 : 0.0;
+        const double t1 = i < kb ? sx[nz + k0 + i] - s1 : 0.0;
         if (part == 0) {
-            sred[i] = i < kb ? sx[k0 + i] - s0 : 0.0;
-            sred[CB + i] = i < kb ? sx[nz + k0 + i] - s1 : 0.0;
+            sred[i] = t0;
+            sred[CB + i] = t1;
         }
         __syncthreads();
+        // y = D t   (rows past kb: D and L are zero there, y = 0)
         double y0 = 0.0, y1 = 0.0;
-        if (i < kb)
-            for (int j = part; j <= i; j += 8) {
-                const double d = sD[i * CBP + j];
-                y0 += d * sred[j];
-                y1 += d * sred[CB + j];
-            }
+        for (int j = part; j <= i; j += 8) {
+            const double d = sD[i * CBP + j];
+            y0 += d * sred[j];
+            y1 += d * sred[CB + j];
+        }
         y0 = sum8(y0);
         y1 = sum8(y1);
+        if (part == 0) {
+            sred[64 + i] = y0;
+            sred[96 + i] = y1;
+        }
+        __syncthreads();
+        // e = t - L_bb y
+        double r0 = 0.0, r1 = 0.0;
+        for (int j = part; j <= i; j += 8) {
+            const double l = sL[i * CBP + j];
+            r0 += l * sred[64 + j];
+            r1 += l * sred[96 + j];
+        }
+        r0 = sum8(r0);
+        r1 = sum8(r1);
+        if (part == 0) {
+            sred[128 + i] = t0 - r0;
+            sred[160 + i] = t1 - r1;
+        }
+        __syncthreads();
+        // y += D e
+        double c0 = 0.0, c1 = 0.0;
+        for (int j = part; j <= i; j += 8) {
+            const double d = sD[i * CBP + j];
+            c0 += d * sred[128 + j];
+            c1 += d * sred[160 + j];
+        }
+        c0 = sum8(c0);
+        c1 = sum8(c1);
         if (part == 0 && i < kb) {
-            sx[k0 + i] = y0;
-            sx[nz + k0 + i] = y1;
+            sx[k0 + i] = y0 + c0;
+            sx[nz + k0 + i] = y1 + c1;
         }
         __syncthreads();
     }
     for (int b = nblk - 1; b >= 0; --b) {
         const int k0 = b * CB, kb = min(CB, nz - k0);
-        for (int e = tid; e < CB * CB; e += 256) sD[(e >> 5) * CBP + (e & 31)] = D[size_t(b) * CB * CB + e];
+        stage(b, k0, kb);
         {
             const int c = tid & 31, g = tid >> 5;   // column c of the block, 8 row groups
             double s0 = 0.0, s1 = 0.0;
-            const int r0 = k0 + CB;   // rows r0 + g + 8u below the block
-            if (r0 < nz) {
+            // rows r0 + g + 8u below the block, a chunk at a time
+            for (int r0 = k0 + CB; r0 < nz; r0 += 8 * kPanelGroups) {
                 double lv[kPanelGroups];
 #pragma unroll
                 for (int u = 0; u < kPanelGroups; ++u) lv[u] = L[size_t(min(r0 + g + 8 * u, nz - 1)) * nz + k0 + min(c, kb - 1)];
@@ -196,27 +244,55 @@ __device__ __forceinline__ void block_solve2(const double* __restrict__ L, const
             sred[512 + h * CB + c] = c < kb ? sx[h * nz + k0 + c] - t : 0.0;
         }
         __syncthreads();
-        const int c = tid >> 3, part = tid & 7;   // x_c = sum_{j >= c} D[j][c] t_j
+        const int c = tid >> 3, part = tid & 7;   // column c, 8 threads per column
+        // x = D^T t:  x_c = sum_{j >= c} D[j][c] t_j
         double x0 = 0.0, x1 = 0.0;
-        if (c < kb)
-            for (int j = c + part; j < kb; j += 8) {
-                const double d = sD[j * CBP + c];
-                x0 += d * sred[512 + j];
-                x1 += d * sred[512 + CB + j];
-            }
+        for (int j = c + part; j < CB; j += 8) {
+            const double d = sD[j * CBP + c];
+            x0 += d * sred[512 + j];
+            x1 += d * sred[512 + CB + j];
+        }
         x0 = sum8(x0);
         x1 = sum8(x1);
+        if (part == 0) {
+            sred[576 + c] = x0;
+            sred[608 + c] = x1;
+        }
+        __syncthreads();
+        // e = t - L_bb^T x
+        double r0 = 0.0, r1 = 0.0;
+        for (int j = c + part; j < CB; j += 8) {
+            const double l = sL[j * CBP + c];
+            r0 += l * sred[576 + j];
+            r1 += l * sred[608 + j];
+        }
+        r0 = sum8(r0);
+        r1 = sum8(r1);
+        if (part == 0) {
+            sred[640 + c] = sred[512 + c] - r0;
+            sred[672 + c] = sred[512 + CB + c] - r1;
+        }
+        __syncthreads();
+        // x += D^T e
+        double c0 = 0.0, c1 = 0.0;
+        for (int j = c + part; j < CB; j += 8) {
+            const double d = sD[j * CBP + c];
+            c0 += d * sred[640 + j];
+            c1 += d * sred[672 + j];
+        }
+        c0 = sum8(c0);
+        c1 = sum8(c1);
         if (part == 0 && c < kb) {
-            sx[k0 + c] = x0;
-            sx[nz + k0 + c] = x1;
+            sx[k0 + c] = x0 + c0;
+            sx[nz + k0 + c] = x1 + c1;
         }
         __syncthreads();
     }
 }
 
-// LDS doubles needed by block_solve2 for depth count nz (sx, sred, sD).
+// LDS doubles needed by block_solve2 for depth count nz (sx, sred, sD, sL).
 __host__ __device__ constexpr size_t block_solve_lds_doubles(int nz) {
-    return size_t(2) * nz + 576 + size_t(CB) * CBP;
+    return size_t(2) * nz + kSolveRed + 2 * size_t(CB) * CBP;
 }
 
 __device__ __forceinline__ double block_sum(double v, double* sbuf) {

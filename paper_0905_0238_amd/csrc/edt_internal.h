@@ -31,6 +31,17 @@ struct DevLayout {
         grow, gsc, total;
 };
 
+// Gram tasks split the depths into super-blocks of at most 256 (8 tiles of
+// 32); each item's right-hand-side/trace partial holds c+, c- and one trace
+// per super-block.
+constexpr int kSuperDepth = 256;
+// Depth limits: the factorisation and refinement (7 accumulator row-block
+// groups, LDS), and the adjoint's table kernel (4 depths per lane).
+constexpr int kMaxDepth = 448;
+constexpr int kMaxAdjointDepth = 256;
+constexpr int n_super(int nz) { return (nz + kSuperDepth - 1) / kSuperDepth; }
+constexpr int rpart_width(int nz) { return 2 * nz + n_super(nz); }
+
 constexpr int kMaxLayers = 64;   // layer-recursion state is held in LDS
 
 }  // namespace edt
@@ -104,10 +115,15 @@ struct WorkLayout {
     size_t gmax;        // [n_freq * n_cls] FP32 max_z |g32| (FP16x3 row scaling)
     size_t gram_part;   // [n_items][ntiles][tile] partial Gram tiles (FP64 or FP32)
     size_t rhs_part;    // [n_ritems][2*nz + 1] FP64 partial residuals (refinement, adjoint)
-    size_t gram_rpart;  // [n_items][2*nz + 1] FP64 partial rhs and trace from the Gram kernels
+    size_t gram_rpart;  // [n_items][2*nz + n_super] FP64 partial rhs and traces from the Gram kernels
     size_t lam;         // [P] lambda per pair
     size_t dinv;        // [P][nblk][32][32] FP64 inverses of the 32 x 32 diagonal blocks of L
     size_t conv;        // [P] int32 converged flags
+    size_t pcg_r;       // [P][2][nz] FP64 refinement residual
+    size_t pcg_p;       // [P][2][nz] FP64 refinement search direction
+    size_t pcg_rho;     // [P] FP64 r.z of the refinement
+    size_t esc_rhs;     // [P][2][nz] FP64 rhs of re-assembled (escalated) pairs
+    size_t esc_trace;   // [P] FP64 trace of re-assembled pairs
     size_t aux;         // [P][2][nz] FP64 scratch (refinement, adjoint)
     size_t aux2;        // [P][2][nz] FP64 scratch
     size_t gbar;        // [n_freq][n_cls][nz] complex128 (adjoint table gradient)

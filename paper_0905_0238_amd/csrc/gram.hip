@@ -69,60 +69,95 @@ __device__ __forceinline__ void split_pack(float x0, float x1, uint32_t& hi, uin
     }
 }
 
-// ---------------------------------------------------------------- BF16x3 ---
-template <int NT>
-struct Bf16Cfg {
-    static constexpr int NZP = 32 * NT;
-    static constexpr int NTL = NT * (NT + 1) / 2;
+// ------------------------------------------------------- split (16-bit) ---
+// A Gram task covers the tiles between two depth super-blocks of at most 256
+// depths (8 blocks of 32): a diagonal task (NTJ = 0) the lower triangle of
+// one super-block of NT blocks, a rectangular task (NTJ > 0) the NT x NTJ
+// tiles between NT blocks of a later super-block (the I set) and NTJ blocks
+// of an earlier one (the J set).  Depth counts up to 256 need one diagonal
+// task; larger ones add the super-blocks below and the rectangles between.
+template <int NT, int NTJ>
+struct SplitCfg {
+    static constexpr bool RECT = NTJ > 0;
+    static constexpr int NZPI = 32 * NT, NZPJ = 32 * NTJ, NZP = NZPI + NZPJ;
+    static constexpr int NTL = RECT ? NT * NTJ : NT * (NT + 1) / 2;
     static constexpr int TPW = (NTL + 3) / 4;
-    static constexpr int STR = 24;   // bf16 per LDS z-row: 16 real rows + 8 pad (48 B)
+    static constexpr int STR = 24;   // 16-bit values per LDS depth row: 16 real rows + 8 pad (48 B)
+    __host__ __device__ static constexpr int tI(int t) { return RECT ? t / NTJ : tri_I(t); }
+    __host__ __device__ static constexpr int tJ(int t) { return RECT ? t % NTJ : tri_J(t); }
+    // blocks of the I (J) set read by the tiles [t0, t1)
+    __host__ __device__ static constexpr uint32_t maskI(int t0, int t1) {
+        uint32_t m = 0;
+        for (int t = t0; t < t1; ++t) m |= RECT ? (1u << tI(t)) : ((1u << tI(t)) | (1u << tJ(t)));
+        return m;
+    }
+    __host__ __device__ static constexpr uint32_t maskJ(int t0, int t1) {
+        uint32_t m = 0;
+        if (RECT)
+            for (int t = t0; t < t1; ++t) m |= 1u << tJ(t);
+        return m;
+    }
 };
 
-template <int NT, int W, bool F16>
-__device__ __forceinline__ void split3_wave_mfma(f32x16 (&acc)[Bf16Cfg<NT>::TPW], const uint16_t* hi,
+template <class C, int W, bool F16>
+__device__ __forceinline__ void split3_wave_mfma(f32x16 (&acc)[C::TPW], const uint16_t* hi,
                                                  const uint16_t* lo, int lane) {
-    using C = Bf16Cfg<NT>;
     typedef typename std::conditional<F16, f16x8, bf16x8>::type v8;
     constexpr int t0 = W * C::TPW;
     constexpr int t1 = (t0 + C::TPW < C::NTL) ? t0 + C::TPW : C::NTL;
-    constexpr uint32_t need = t0 < t1 ? block_mask(t0, t1) : 0u;
-    v8 fh[NT], fl[NT];
+    constexpr uint32_t needI = t0 < t1 ? C::maskI(t0, t1) : 0u;
+    constexpr uint32_t needJ = t0 < t1 ? C::maskJ(t0, t1) : 0u;
+    constexpr int NBI = C::NZPI / 32, NBJ = C::RECT ? C::NZPJ / 32 : 1;
+    v8 fh[NBI], fl[NBI], gh[NBJ], gl[NBJ];
     const int roff = (lane & 31) * C::STR + (lane >> 5) * 8;
 #pragma unroll
-    for (int b = 0; b < NT; ++b) {
-        if (need & (1u << b)) {
+    for (int b = 0; b < NBI; ++b) {
+        if (needI & (1u << b)) {
             fh[b] = *reinterpret_cast<const v8*>(hi + b * 32 * C::STR + roff);
             fl[b] = *reinterpret_cast<const v8*>(lo + b * 32 * C::STR + roff);
+        }
+    }
+    if constexpr (C::RECT) {
+#pragma unroll
+        for (int b = 0; b < NBJ; ++b) {
+            if (needJ & (1u << b)) {
+                gh[b] = *reinterpret_cast<const v8*>(hi + (C::NZPI + b * 32) * C::STR + roff);
+                gl[b] = *reinterpret_cast<const v8*>(lo + (C::NZPI + b * 32) * C::STR + roff);
+            }
         }
     }
 #pragma unroll
     for (int m = 0; m < C::TPW; ++m) {
         const int t = t0 + m;
         if (t < t1) {
-            const int I = tri_I(t), J = tri_J(t);
+            const int I = C::tI(t), J = C::tJ(t);
+            const v8 aH = fh[I], aL = fl[I];
+            const v8 bH = C::RECT ? gh[J] : fh[J], bL = C::RECT ? gl[J] : fl[J];
             if constexpr (F16) {
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fh[I], fh[J], acc[m], 0, 0, 0);
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fh[I], fl[J], acc[m], 0, 0, 0);
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fl[I], fh[J], acc[m], 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aH, bH, acc[m], 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aH, bL, acc[m], 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aL, bH, acc[m], 0, 0, 0);
             } else {
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh[I], fh[J], acc[m], 0, 0, 0);
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh[I], fl[J], acc[m], 0, 0, 0);
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fl[I], fh[J], acc[m], 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH, bH, acc[m], 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH, bL, acc[m], 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aL, bH, acc[m], 0, 0, 0);
             }
         }
     }
 }
 
-template <int NT, int W>
-__device__ __forceinline__ void f32_store_tiles(const f32x16 (&acc)[Bf16Cfg<NT>::TPW], float* out,
-                                                int lane, float scale = 1.0f) {
-    using C = Bf16Cfg<NT>;
+// Store the wave's 32 x 32 accumulator tiles into the item's partial, at the
+// global tile (bI0 + I, bJ0 + J) of the lower triangle of all depth blocks.
+template <class C, int W>
+__device__ __forceinline__ void f32_store_tiles(const f32x16 (&acc)[C::TPW], float* out, int lane,
+                                                float scale, int bI0, int bJ0) {
     constexpr int t0 = W * C::TPW;
 #pragma unroll
     for (int m = 0; m < C::TPW; ++m) {
         const int t = t0 + m;
         if (t < C::NTL) {
-            float* o = out + size_t(t) * 1024;
+            const int Ig = bI0 + C::tI(t), Jg = bJ0 + C::tJ(t);
+            float* o = out + size_t(Ig * (Ig + 1) / 2 + Jg) * 1024;
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
@@ -154,39 +189,41 @@ __device__ __forceinline__ void stage_rows(uint4* s_row, const GRow* __restrict_
     }
 }
 
-// Producer side of the BF16x3 kernel: raw table values of one stage (8
-// complex rows) at the producer thread's depth.
+// Producer side of the split kernels: raw table values of one stage (8
+// complex rows) at one depth.
 struct RawStage {
     float2 ga[8], gb[8];
 };
 
-// Split Gram (BF16x3 or FP16x3).  Each FP32 row value x is split into two
-// 16-bit values x = hi + lo and Ah^T Ah ~ hi^T hi + hi^T lo + lo^T hi with
-// FP32 accumulation: about 16 significant bits per product with bfloat16
-// halves, about 22 with IEEE halves (which need the per-item scaling below).
+// Split Gram (BF16x3 or FP16x3) task over one work item.  Each FP32 row value
+// x is split into two 16-bit values x = hi + lo and the block
+// Ah_I^T Ah_J ~ hi_I^T hi_J + hi_I^T lo_J + lo_I^T hi_J is accumulated in
+// FP32: about 16 significant bits per product with bfloat16 halves, about 22
+// with IEEE halves (which need the per-item scaling below).
 // Warp-specialised: waves 0-3 consume 16-bit stages from LDS into MFMA, waves
 // 4-7 produce them.  A producer issues the table loads of stage s+2 while it
 // forms stage s+1 (loaded one iteration earlier), so each load has about two
-// MFMA stages to arrive.  A producer thread owns one depth z and all 8 rows
-// of a stage, so it writes its 16 hi and 16 lo values as 16-byte stores; with
-// the 48-byte LDS row pitch any 8 consecutive depths hit distinct bank
-// groups.  Row records come from LDS (the row of a stage is uniform over the
-// wave: broadcast reads, and the table base of a load is a scalar).  Depths
-// nz..NZP-1 are zeroed once per item and never written again.
-// The producers also accumulate the item's right-hand side
-// c+-(z) = Re(A^H B+-) in FP32 (an approximation: the FP64 refinement
-// residual corrects it) and the trace sum mult |A|^2 (per stage in FP32, then
-// in FP64) into rpart[slot][0 .. 2 nz].
-template <int NT, bool F16>
+// MFMA stages to arrive.  A producer thread owns one depth of the I set (and
+// one of the J set) and all 8 rows of a stage, so it writes its 16 hi and 16
+// lo values as 16-byte stores; with the 48-byte LDS row pitch any 8
+// consecutive depths hit distinct bank groups.  Row records come from LDS
+// (the row of a stage is uniform over the wave: broadcast reads, and the
+// table base of a load is a scalar).  Depths past nz are zeroed once per item.
+// Diagonal tasks also accumulate the item's right-hand side
+// c+-(z) = Re(A^H B+-) over their depths in FP32 (an approximation: the FP64
+// refinement residual corrects it) and the trace sum mult |A|^2 (per stage in
+// FP32, then in FP64) into rpart[slot] (c+, c-, one trace per super-block).
+template <int NT, int NTJ, bool F16>
 __global__ __launch_bounds__(512, 1) void gram_split3_kernel(const Item* __restrict__ items,
                                                              const int32_t* __restrict__ sched,
                                                              const GRow* __restrict__ grow,
                                                              const float4* __restrict__ ub32,
                                                              const float2* __restrict__ g32,
                                                              const float* __restrict__ gmax, int nz,
+                                                             int zI0, int zJ0, int ntot,
                                                              float* __restrict__ part,
                                                              double* __restrict__ rpart, int max_rows) {
-    using C = Bf16Cfg<NT>;
+    using C = SplitCfg<NT, NTJ>;
     __shared__ __attribute__((aligned(16))) uint16_t sh[2][2][C::NZP * C::STR];
     __shared__ double s_tr[4];
     __shared__ float s_max[8];
@@ -197,6 +234,7 @@ __global__ __launch_bounds__(512, 1) void gram_split3_kernel(const Item* __restr
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int n = min(it.row_end - it.row_begin, max_rows);
     const int nst = (n + 7) >> 3;
+    const int nzI = min(C::NZPI, nz - zI0);   // valid depths of the I set
     stage_rows(s_row, grow, ub32, it.row_begin, n, nst, tid, 512);
     // FP16: the rows of the item are scaled by a power of two s so that the
     // largest |value| is near 2^14 (inside the half range, above its
@@ -220,7 +258,7 @@ __global__ __launch_bounds__(512, 1) void gram_split3_kernel(const Item* __restr
     }
     {
         const int z = tid - 256;
-        if (z >= nz && z < C::NZP) {
+        if (z >= nzI && z < C::NZPI) {
             const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
             for (int b = 0; b < 2; ++b)
@@ -236,11 +274,14 @@ __global__ __launch_bounds__(512, 1) void gram_split3_kernel(const Item* __restr
 
     const bool producer = wv >= 4;
     if (producer) {
-        const int z = tid - 256;               // producer thread -> depth
-        const int zc = min(z, nz - 1);         // clamped: loads are unconditional
+        const int pid = tid - 256;
+        const bool onI = pid < nzI;                  // this thread forms I-set depth zI0 + pid
+        const bool onJ = C::RECT && pid < C::NZPJ;   // and J-set depth zJ0 + pid (always < nz)
+        const int zIc = zI0 + min(pid, nzI - 1);     // clamped: loads are unconditional
+        const int zJc = min(zJ0 + pid, nz - 1);
         float cp = 0.0f, cm = 0.0f;
         double tr = 0.0;
-        auto load = [&](RawStage& R, int s) {
+        auto load = [&](RawStage& R, int s, int zc) {
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const uint4 a = s_row[2 * (8 * s + j)];
@@ -250,55 +291,68 @@ __global__ __launch_bounds__(512, 1) void gram_split3_kernel(const Item* __restr
                 R.gb[j] = (g32 + o_s)[zc];
             }
         };
-        auto form = [&](const RawStage& R, int buf, int s) {
+        auto form = [&](const RawStage& R, int buf, int s, int row, bool diag_sums, bool on) {
             uint32_t h[8], l[8];
             float t = 0.0f;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const uint4 a = s_row[2 * (8 * s + j)];
-                const uint4 b = s_row[2 * (8 * s + j) + 1];
-                const float sw = __uint_as_float(a.z), mt = __uint_as_float(a.w);
+                const float sw = __uint_as_float(a.z);
                 const float px = R.ga[j].x * R.gb[j].x - R.ga[j].y * R.gb[j].y;
                 const float py = R.ga[j].x * R.gb[j].y + R.ga[j].y * R.gb[j].x;
-                cp += px * __uint_as_float(b.x) + py * __uint_as_float(b.y);
-                cm += px * __uint_as_float(b.z) + py * __uint_as_float(b.w);
-                t += mt * (px * px + py * py);
+                if (diag_sums) {
+                    const uint4 b = s_row[2 * (8 * s + j) + 1];
+                    const float mt = __uint_as_float(a.w);
+                    cp += px * __uint_as_float(b.x) + py * __uint_as_float(b.y);
+                    cm += px * __uint_as_float(b.z) + py * __uint_as_float(b.w);
+                    t += mt * (px * px + py * py);
+                }
                 const float ss = F16 ? sw * scale : sw;
                 split_pack<F16>(ss * px, ss * py, h[j], l[j]);
             }
-            tr += double(t);
-            if (z < nz) {
-                uint4* hi = reinterpret_cast<uint4*>(sh[buf][0] + z * C::STR);
-                uint4* lo = reinterpret_cast<uint4*>(sh[buf][1] + z * C::STR);
+            if (diag_sums) tr += double(t);
+            if (on) {
+                uint4* hi = reinterpret_cast<uint4*>(sh[buf][0] + row * C::STR);
+                uint4* lo = reinterpret_cast<uint4*>(sh[buf][1] + row * C::STR);
                 hi[0] = make_uint4(h[0], h[1], h[2], h[3]);
                 hi[1] = make_uint4(h[4], h[5], h[6], h[7]);
                 lo[0] = make_uint4(l[0], l[1], l[2], l[3]);
                 lo[1] = make_uint4(l[4], l[5], l[6], l[7]);
             }
         };
-        RawStage R0, R1;   // stage k lives in R(k & 1)
-        load(R0, 0);
-        if (nst > 1) load(R1, 1);
-        form(R0, 0, 0);
+        auto load_stage = [&](RawStage (&R)[2], int s) {
+            load(R[0], s, zIc);
+            if constexpr (C::RECT) load(R[1], s, zJc);
+        };
+        auto form_stage = [&](const RawStage (&R)[2], int buf, int s) {
+            form(R[0], buf, s, pid, !C::RECT, onI);
+            if constexpr (C::RECT) form(R[1], buf, s, C::NZPI + pid, false, onJ);
+        };
+        RawStage R0[2], R1[2];   // stage k lives in R(k & 1); [0] I set, [1] J set
+        load_stage(R0, 0);
+        if (nst > 1) load_stage(R1, 1);
+        form_stage(R0, 0, 0);
         __syncthreads();
         // iteration s: stage s is being consumed from buffer s&1
         for (int s = 0; s < nst; s += 2) {
-            if (s + 2 < nst) load(R0, s + 2);
-            if (s + 1 < nst) form(R1, 1, s + 1);
+            if (s + 2 < nst) load_stage(R0, s + 2);
+            if (s + 1 < nst) form_stage(R1, 1, s + 1);
             __syncthreads();
             if (s + 1 < nst) {
-                if (s + 3 < nst) load(R1, s + 3);
-                if (s + 2 < nst) form(R0, 0, s + 2);
+                if (s + 3 < nst) load_stage(R1, s + 3);
+                if (s + 2 < nst) form_stage(R0, 0, s + 2);
                 __syncthreads();
             }
         }
-        if (z < nz) {
-            double* rp = rpart + size_t(it.slot) * (2 * nz + 1);
-            rp[z] = double(cp);
-            rp[nz + z] = double(cm);
+        if constexpr (!C::RECT) {
+            if (onI) {
+                double* rp = rpart + size_t(it.slot) * rpart_width(nz);
+                rp[zI0 + pid] = double(cp);
+                rp[nz + zI0 + pid] = double(cm);
+            }
+            const double t = wave_sum(onI ? tr : 0.0);
+            if (lane == 0) s_tr[wv - 4] = t;
         }
-        const double t = wave_sum(z < nz ? tr : 0.0);
-        if (lane == 0) s_tr[wv - 4] = t;
     } else {
         f32x16 acc[C::TPW];
 #pragma unroll
@@ -308,10 +362,10 @@ __global__ __launch_bounds__(512, 1) void gram_split3_kernel(const Item* __restr
         auto compute = [&](int buf) {
             const uint16_t* hi = sh[buf][0];
             const uint16_t* lo = sh[buf][1];
-            if (wv == 0) split3_wave_mfma<NT, 0, F16>(acc, hi, lo, lane);
-            else if (wv == 1) split3_wave_mfma<NT, 1, F16>(acc, hi, lo, lane);
-            else if (wv == 2) split3_wave_mfma<NT, 2, F16>(acc, hi, lo, lane);
-            else split3_wave_mfma<NT, 3, F16>(acc, hi, lo, lane);
+            if (wv == 0) split3_wave_mfma<C, 0, F16>(acc, hi, lo, lane);
+            else if (wv == 1) split3_wave_mfma<C, 1, F16>(acc, hi, lo, lane);
+            else if (wv == 2) split3_wave_mfma<C, 2, F16>(acc, hi, lo, lane);
+            else split3_wave_mfma<C, 3, F16>(acc, hi, lo, lane);
         };
         __syncthreads();
         for (int s = 0; s < nst; s += 2) {
@@ -322,15 +376,20 @@ __global__ __launch_bounds__(512, 1) void gram_split3_kernel(const Item* __restr
                 __syncthreads();
             }
         }
-        float* out = part + size_t(it.slot) * C::NTL * 1024;
+        float* out = part + size_t(it.slot) * (ntot * (ntot + 1) / 2) * 1024;
         const float back = 1.0f / (scale * scale);
-        if (wv == 0) f32_store_tiles<NT, 0>(acc, out, lane, back);
-        else if (wv == 1) f32_store_tiles<NT, 1>(acc, out, lane, back);
-        else if (wv == 2) f32_store_tiles<NT, 2>(acc, out, lane, back);
-        else f32_store_tiles<NT, 3>(acc, out, lane, back);
+        const int bI0 = zI0 / 32, bJ0 = C::RECT ? zJ0 / 32 : zI0 / 32;
+        if (wv == 0) f32_store_tiles<C, 0>(acc, out, lane, back, bI0, bJ0);
+        else if (wv == 1) f32_store_tiles<C, 1>(acc, out, lane, back, bI0, bJ0);
+        else if (wv == 2) f32_store_tiles<C, 2>(acc, out, lane, back, bI0, bJ0);
+        else f32_store_tiles<C, 3>(acc, out, lane, back, bI0, bJ0);
     }
-    __syncthreads();
-    if (tid == 0) rpart[size_t(it.slot) * (2 * nz + 1) + 2 * nz] = (s_tr[0] + s_tr[1]) + (s_tr[2] + s_tr[3]);
+    if constexpr (!C::RECT) {
+        __syncthreads();
+        if (tid == 0)
+            rpart[size_t(it.slot) * rpart_width(nz) + 2 * nz + zI0 / kSuperDepth] =
+                (s_tr[0] + s_tr[1]) + (s_tr[2] + s_tr[3]);
+    }
 }
 
 // ------------------------------------------------------------------ FP32 ---
@@ -465,11 +524,12 @@ __global__ __launch_bounds__(256, 1) void gram_f32_kernel(const Item* __restrict
         __syncthreads();
     }
     float* out = part + size_t(it.slot) * C::NTL * 1024;
-    if (wv == 0) f32_store_tiles<NT, 0>(acc, out, lane);
-    else if (wv == 1) f32_store_tiles<NT, 1>(acc, out, lane);
-    else if (wv == 2) f32_store_tiles<NT, 2>(acc, out, lane);
-    else f32_store_tiles<NT, 3>(acc, out, lane);
-    double* rp = rpart + size_t(it.slot) * (2 * nz + 1);
+    using S = SplitCfg<NT, 0>;
+    if (wv == 0) f32_store_tiles<S, 0>(acc, out, lane, 1.0f, 0, 0);
+    else if (wv == 1) f32_store_tiles<S, 1>(acc, out, lane, 1.0f, 0, 0);
+    else if (wv == 2) f32_store_tiles<S, 2>(acc, out, lane, 1.0f, 0, 0);
+    else f32_store_tiles<S, 3>(acc, out, lane, 1.0f, 0, 0);
+    double* rp = rpart + size_t(it.slot) * rpart_width(nz);
     if (z < nz) {
         rp[z] = double(cp);
         rp[nz + z] = double(cm);
@@ -481,50 +541,74 @@ __global__ __launch_bounds__(256, 1) void gram_f32_kernel(const Item* __restrict
 }
 
 // ------------------------------------------------------------------ FP64 ---
-template <int NT>
+// FP64 Gram task: the same super-block tasks as the split kernels, on
+// 16 x 16 tiles (v_mfma_f64_16x16x4): NB (NBJ) 16-wide blocks in the I (J)
+// set, lower triangle (diagonal task) or NB x NBJ rectangle, over 8 waves.
+template <int NT, int NTJ>
 struct F64Cfg {
-    static constexpr int NZP = 32 * NT;
-    static constexpr int NB = 2 * NT;                    // 16-wide blocks
-    static constexpr int NBL = NB * (NB + 1) / 2;        // lower 16x16 tiles
-    static constexpr int TPW = (NBL + 7) / 8;            // 8 waves
+    static constexpr bool RECT = NTJ > 0;
+    static constexpr int NZPI = 32 * NT, NZPJ = 32 * NTJ, NZP = NZPI + NZPJ;
+    static constexpr int NB = 2 * NT, NBJ = 2 * NTJ;
+    static constexpr int NBL = RECT ? NB * NBJ : NB * (NB + 1) / 2;
+    static constexpr int TPW = (NBL + 7) / 8;   // 8 waves
+    __host__ __device__ static constexpr int tI(int t) { return RECT ? t / NBJ : tri_I(t); }
+    __host__ __device__ static constexpr int tJ(int t) { return RECT ? t % NBJ : tri_J(t); }
+    __host__ __device__ static constexpr uint32_t maskI(int t0, int t1) {
+        uint32_t m = 0;
+        for (int t = t0; t < t1; ++t) m |= RECT ? (1u << tI(t)) : ((1u << tI(t)) | (1u << tJ(t)));
+        return m;
+    }
+    __host__ __device__ static constexpr uint32_t maskJ(int t0, int t1) {
+        uint32_t m = 0;
+        if (RECT)
+            for (int t = t0; t < t1; ++t) m |= 1u << tJ(t);
+        return m;
+    }
 };
 
-template <int NT, int W>
-__device__ __forceinline__ void f64_wave_mfma(f64x4 (&acc)[F64Cfg<NT>::TPW], const double* sh,
-                                              int lane) {
-    using C = F64Cfg<NT>;
+template <class C, int W>
+__device__ __forceinline__ void f64_wave_mfma(f64x4 (&acc)[C::TPW], const double* sh, int lane) {
     constexpr int t0 = W * C::TPW;
     constexpr int t1 = (t0 + C::TPW < C::NBL) ? t0 + C::TPW : C::NBL;
-    constexpr uint32_t need = t0 < t1 ? block_mask(t0, t1) : 0u;
+    constexpr uint32_t needI = t0 < t1 ? C::maskI(t0, t1) : 0u;
+    constexpr uint32_t needJ = t0 < t1 ? C::maskJ(t0, t1) : 0u;
+    constexpr int NBJX = C::RECT ? C::NBJ : 1;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        double fa[C::NB];
+        double fa[C::NB], fb[NBJX];
         const int roff = (4 * s + (lane >> 4)) * C::NZP + (lane & 15);
 #pragma unroll
         for (int b = 0; b < C::NB; ++b)
-            if (need & (1u << b)) fa[b] = sh[roff + 16 * b];
+            if (needI & (1u << b)) fa[b] = sh[roff + 16 * b];
+        if constexpr (C::RECT) {
+#pragma unroll
+            for (int b = 0; b < NBJX; ++b)
+                if (needJ & (1u << b)) fb[b] = sh[roff + C::NZPI + 16 * b];
+        }
 #pragma unroll
         for (int m = 0; m < C::TPW; ++m) {
             const int t = t0 + m;
             if (t < t1) {
-                const int I = tri_I(t), J = tri_J(t);
-                acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[I], fa[J], acc[m], 0, 0, 0);
+                const int I = C::tI(t), J = C::tJ(t);
+                const double bj = C::RECT ? fb[J] : fa[J];
+                acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[I], bj, acc[m], 0, 0, 0);
             }
         }
     }
 }
 
-template <int NT, int W>
-__device__ __forceinline__ void f64_store_tiles(const f64x4 (&acc)[F64Cfg<NT>::TPW], double* out,
-                                                int lane) {
-    using C = F64Cfg<NT>;
+// Store 16 x 16 tiles into the 32 x 32 tile layout of the item's partial:
+// global 16-blocks (2 bI0 + I, 2 bJ0 + J).
+template <class C, int W>
+__device__ __forceinline__ void f64_store_tiles(const f64x4 (&acc)[C::TPW], double* out, int lane,
+                                                int bI0, int bJ0) {
     constexpr int t0 = W * C::TPW;
 #pragma unroll
     for (int m = 0; m < C::TPW; ++m) {
         const int t = t0 + m;
         if (t < C::NBL) {
-            const int I = tri_I(t), J = tri_J(t);
-            const int T = tri_I(t) / 2 * (tri_I(t) / 2 + 1) / 2 + J / 2;   // 32-tile index
+            const int I = 2 * bI0 + C::tI(t), J = 2 * bJ0 + C::tJ(t);
+            const int T = (I / 2) * (I / 2 + 1) / 2 + J / 2;   // 32-tile index
             double* o = out + size_t(T) * 1024 + (I & 1) * 16 * 32 + (J & 1) * 16;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -536,34 +620,38 @@ __device__ __forceinline__ void f64_store_tiles(const f64x4 (&acc)[F64Cfg<NT>::T
     }
 }
 
-// Thread t owns depth z = t % 256 and the rows j = t / 256 + 2 i (i < 4) of
-// each stage (the row is uniform across a wave, so its data come through
-// scalar loads).  Besides the Gram tiles, an item yields its exact FP64
-// right-hand side c+-(z) = Re(A^H B+-) and trace sum mult |A|^2 in
-// rpart[slot][0 .. 2 nz].
-template <int NT>
+// only: when set, items of pairs p with only[p] <= 0 are skipped.
+// Thread t owns depth z = t % 256 of the I set (and of the J set) and the rows
+// j = t / 256 + 2 i (i < 4) of each stage (the row is uniform across a wave,
+// so its data come through scalar loads).  A diagonal task also yields the
+// item's exact FP64 right-hand side c+-(z) = Re(A^H B+-) over its depths and
+// its trace sum mult |A|^2 in rpart[slot].
+template <int NT, int NTJ>
 __global__ __launch_bounds__(512, 1) void gram_f64_kernel(const Item* __restrict__ items,
                                                           const int32_t* __restrict__ sched,
                                                           const GRow* __restrict__ grow,
                                                           const double* __restrict__ gsc,
                                                           const zd* __restrict__ ubw,
-                                                          const zd* __restrict__ g64, int nz,
-                                                          double* __restrict__ part,
-                                                          double* __restrict__ rpart) {
-    using C = F64Cfg<NT>;
+                                                          const zd* __restrict__ g64, int nz, int zI0,
+                                                          int zJ0, int ntot, double* __restrict__ part,
+                                                          double* __restrict__ rpart,
+                                                          const int32_t* __restrict__ only) {
+    using C = F64Cfg<NT, NTJ>;
     __shared__ __attribute__((aligned(16))) double sh[2][16 * C::NZP];
     __shared__ double s_tr[8];
     const int32_t k = sched[blockIdx.x];
     if (k < 0) return;   // hole in the XCD-aware schedule
     const Item it = items[k];
+    if (only && only[it.pair] <= 0) return;   // pair not selected
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int n = it.row_end - it.row_begin;
     const int nst = (n + 7) >> 3;
     const int z = tid & 255, hf = __builtin_amdgcn_readfirstlane(tid >> 8);
-    const int zc = min(z, nz - 1);
-    const bool zon = z < nz;
-    // depths nz..NZP-1 of both stage buffers stay zero for the whole item
-    if (z >= nz && z < C::NZP)
+    const int nzI = min(C::NZPI, nz - zI0);
+    const bool onI = z < nzI, onJ = C::RECT && z < C::NZPJ;
+    const int zIc = zI0 + min(z, nzI - 1), zJc = min(zJ0 + z, nz - 1);
+    // depths past nz of the I set stay zero for the whole item
+    if (z >= nzI && z < C::NZPI)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -573,7 +661,7 @@ __global__ __launch_bounds__(512, 1) void gram_f64_kernel(const Item* __restrict
     for (int m = 0; m < C::TPW; ++m)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[m][v] = 0.0;
-    zd ga[4], gb[4], bp[4], bm[4];
+    zd ga[4], gb[4], ha[4], hb[4], bp[4], bm[4];
     double sw[4];
     double cp = 0.0, cm = 0.0, tr = 0.0;
     auto load = [&](int s) {
@@ -582,12 +670,18 @@ __global__ __launch_bounds__(512, 1) void gram_f64_kernel(const Item* __restrict
             const int r = s * 8 + hf + 2 * i;
             const int64_t row = int64_t(it.row_begin) + min(r, n - 1);
             const GRow g = grow[row];
-            ga[i] = g64[size_t(g.off_r) + zc];
-            gb[i] = g64[size_t(g.off_s) + zc];
+            ga[i] = g64[size_t(g.off_r) + zIc];
+            gb[i] = g64[size_t(g.off_s) + zIc];
+            if constexpr (C::RECT) {
+                ha[i] = g64[size_t(g.off_r) + zJc];
+                hb[i] = g64[size_t(g.off_s) + zJc];
+            }
             const bool on = r < n;
-            const zd b0 = ubw[2 * row], b1 = ubw[2 * row + 1];
-            bp[i] = on ? b0 : zd{0.0, 0.0};
-            bm[i] = on ? b1 : zd{0.0, 0.0};
+            if constexpr (!C::RECT) {
+                const zd b0 = ubw[2 * row], b1 = ubw[2 * row + 1];
+                bp[i] = on ? b0 : zd{0.0, 0.0};
+                bm[i] = on ? b1 : zd{0.0, 0.0};
+            }
             sw[i] = on ? gsc[row] : 0.0;
         }
     };
@@ -597,27 +691,36 @@ __global__ __launch_bounds__(512, 1) void gram_f64_kernel(const Item* __restrict
         for (int i = 0; i < 4; ++i) {
             const int j = hf + 2 * i;
             const zd p = ga[i] * gb[i];
-            cp += p.x * bp[i].x + p.y * bp[i].y;
-            cm += p.x * bm[i].x + p.y * bm[i].y;
+            if constexpr (!C::RECT) {
+                cp += p.x * bp[i].x + p.y * bp[i].y;
+                cm += p.x * bm[i].x + p.y * bm[i].y;
+            }
             const double ax = sw[i] * p.x, ay = sw[i] * p.y;
-            tr += ax * ax + ay * ay;
-            if (zon) {
+            if constexpr (!C::RECT) tr += ax * ax + ay * ay;
+            if (onI) {
                 o[(2 * j) * C::NZP + z] = ax;
                 o[(2 * j + 1) * C::NZP + z] = ay;
+            }
+            if constexpr (C::RECT) {
+                const zd q = ha[i] * hb[i];
+                if (onJ) {
+                    o[(2 * j) * C::NZP + C::NZPI + z] = sw[i] * q.x;
+                    o[(2 * j + 1) * C::NZP + C::NZPI + z] = sw[i] * q.y;
+                }
             }
         }
     };
     auto compute = [&](int buf) {
         const double* o = sh[buf];
         switch (wv) {
-            case 0: f64_wave_mfma<NT, 0>(acc, o, lane); break;
-            case 1: f64_wave_mfma<NT, 1>(acc, o, lane); break;
-            case 2: f64_wave_mfma<NT, 2>(acc, o, lane); break;
-            case 3: f64_wave_mfma<NT, 3>(acc, o, lane); break;
-            case 4: f64_wave_mfma<NT, 4>(acc, o, lane); break;
-            case 5: f64_wave_mfma<NT, 5>(acc, o, lane); break;
-            case 6: f64_wave_mfma<NT, 6>(acc, o, lane); break;
-            default: f64_wave_mfma<NT, 7>(acc, o, lane); break;
+            case 0: f64_wave_mfma<C, 0>(acc, o, lane); break;
+            case 1: f64_wave_mfma<C, 1>(acc, o, lane); break;
+            case 2: f64_wave_mfma<C, 2>(acc, o, lane); break;
+            case 3: f64_wave_mfma<C, 3>(acc, o, lane); break;
+            case 4: f64_wave_mfma<C, 4>(acc, o, lane); break;
+            case 5: f64_wave_mfma<C, 5>(acc, o, lane); break;
+            case 6: f64_wave_mfma<C, 6>(acc, o, lane); break;
+            default: f64_wave_mfma<C, 7>(acc, o, lane); break;
         }
     };
     load(0);
@@ -629,43 +732,50 @@ __global__ __launch_bounds__(512, 1) void gram_f64_kernel(const Item* __restrict
         if (s + 1 < nst) store((s + 1) & 1);
         __syncthreads();
     }
-    double* out = part + size_t(it.slot) * (NT * (NT + 1) / 2) * 1024;
+    double* out = part + size_t(it.slot) * (ntot * (ntot + 1) / 2) * 1024;
+    const int bI0 = zI0 / 32, bJ0 = C::RECT ? zJ0 / 32 : zI0 / 32;
     switch (wv) {
-        case 0: f64_store_tiles<NT, 0>(acc, out, lane); break;
-        case 1: f64_store_tiles<NT, 1>(acc, out, lane); break;
-        case 2: f64_store_tiles<NT, 2>(acc, out, lane); break;
-        case 3: f64_store_tiles<NT, 3>(acc, out, lane); break;
-        case 4: f64_store_tiles<NT, 4>(acc, out, lane); break;
-        case 5: f64_store_tiles<NT, 5>(acc, out, lane); break;
-        case 6: f64_store_tiles<NT, 6>(acc, out, lane); break;
-        default: f64_store_tiles<NT, 7>(acc, out, lane); break;
+        case 0: f64_store_tiles<C, 0>(acc, out, lane, bI0, bJ0); break;
+        case 1: f64_store_tiles<C, 1>(acc, out, lane, bI0, bJ0); break;
+        case 2: f64_store_tiles<C, 2>(acc, out, lane, bI0, bJ0); break;
+        case 3: f64_store_tiles<C, 3>(acc, out, lane, bI0, bJ0); break;
+        case 4: f64_store_tiles<C, 4>(acc, out, lane, bI0, bJ0); break;
+        case 5: f64_store_tiles<C, 5>(acc, out, lane, bI0, bJ0); break;
+        case 6: f64_store_tiles<C, 6>(acc, out, lane, bI0, bJ0); break;
+        default: f64_store_tiles<C, 7>(acc, out, lane, bI0, bJ0); break;
     }
-    // the two row halves of depth z meet in LDS (stage buffers are free now)
-    double* sc = sh[0];
-    if (hf == 1) {
-        sc[z] = cp;
-        sc[256 + z] = cm;
+    if constexpr (!C::RECT) {
+        // the two row halves of depth z meet in LDS (stage buffers are free now)
+        double* sc = sh[0];
+        if (hf == 1) {
+            sc[z] = cp;
+            sc[256 + z] = cm;
+        }
+        const double t = wave_sum(onI ? tr : 0.0);
+        if (lane == 0) s_tr[wv] = t;
+        __syncthreads();
+        double* rp = rpart + size_t(it.slot) * rpart_width(nz);
+        if (hf == 0 && onI) {
+            rp[zI0 + z] = cp + sc[z];
+            rp[nz + zI0 + z] = cm + sc[256 + z];
+        }
+        if (tid == 0)
+            rp[2 * nz + zI0 / kSuperDepth] =
+                ((s_tr[0] + s_tr[1]) + (s_tr[2] + s_tr[3])) + ((s_tr[4] + s_tr[5]) + (s_tr[6] + s_tr[7]));
     }
-    const double t = wave_sum(zon ? tr : 0.0);
-    if (lane == 0) s_tr[wv] = t;
-    __syncthreads();
-    double* rp = rpart + size_t(it.slot) * (2 * nz + 1);
-    if (hf == 0 && zon) {
-        rp[z] = cp + sc[z];
-        rp[nz + z] = cm + sc[256 + z];
-    }
-    if (tid == 0)
-        rp[2 * nz] = ((s_tr[0] + s_tr[1]) + (s_tr[2] + s_tr[3])) + ((s_tr[4] + s_tr[5]) + (s_tr[6] + s_tr[7]));
 }
 
 // ---------------------------------------------------------------- reduce ---
 // gram[p][zi][zj] (zi >= zj) = sum over the pair's items of the partial tiles,
 // accumulated in FP64 in item order.  Grid: (n_pairs, lower 32-tiles).
+// only: when set, pairs with only[p] <= 0 are skipped (also below).
 template <class T>
 __global__ __launch_bounds__(256) void gram_reduce_kernel(const T* __restrict__ part,
                                                           const int32_t* __restrict__ pair_item,
-                                                          int nz, int ntl, double* __restrict__ gram) {
+                                                          int nz, int ntl, double* __restrict__ gram,
+                                                          const int32_t* __restrict__ only) {
     const int p = blockIdx.x, t = blockIdx.y;
+    if (only && only[p] <= 0) return;
     const int I = tri_I(t), J = tri_J(t);
     const int k0 = pair_item[p], k1 = pair_item[p + 1];
     double* G = gram + size_t(p) * nz * nz;
@@ -681,14 +791,18 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const T* __restrict__ 
     }
 }
 
-// rhs[p][h][z] and trace[p] from the per-item partials, in item order.
+// rhs[p][h][z] and trace[p] from the per-item partials, in item order (the
+// trace: per super-block over the items, then over the super-blocks).
 __global__ __launch_bounds__(256) void rhs_reduce_kernel(const double* __restrict__ rpart,
                                                          const int32_t* __restrict__ pair_item,
                                                          int nz, double* __restrict__ rhs,
-                                                         double* __restrict__ trace) {
+                                                         double* __restrict__ trace,
+                                                         const int32_t* __restrict__ only) {
+    __shared__ double s_t[8];
     const int p = blockIdx.x;
+    if (only && only[p] <= 0) return;
     const int k0 = pair_item[p], k1 = pair_item[p + 1];
-    const int w = 2 * nz + 1;
+    const int w = rpart_width(nz);
     for (int e = threadIdx.x; e < w; e += 256) {
         double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         int k = k0;
@@ -698,7 +812,13 @@ __global__ __launch_bounds__(256) void rhs_reduce_kernel(const double* __restric
         for (int q = 0; k < k1; ++k, ++q) s8[q] += rpart[size_t(k) * w + e];
         const double s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
         if (e < 2 * nz) rhs[size_t(p) * 2 * nz + e] = s;
-        else trace[p] = s;
+        else s_t[e - 2 * nz] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int b = 0; b < n_super(nz); ++b) t += s_t[b];
+        trace[p] = t;
     }
 }
 
@@ -730,51 +850,75 @@ struct GramRowData {
     const zd* ubw;        // FP64: conj(W) (b+, b-)
     const float4* ub32;   // FP32 / split: conj(W)/|W| (b+, b-)
     const float* gmax;    // FP16x3: max_z |g32| per table column
+    const int32_t* only;  // FP64: when set, only the pairs with only[p] > 0
 };
 
-template <int NT>
-static hipError_t launch_gram_nt(const edt_plan* p, edt_precision prec, const zd* g64,
-                                 const float2* g32, const GramRowData& rd, void* part, double* rpart,
-                                 hipStream_t st) {
+// One Gram task kind (diagonal NTJ = 0 or rectangular) over every item.
+template <int NT, int NTJ>
+static hipError_t launch_gram_task(const edt_plan* p, edt_precision prec, const zd* g64,
+                                   const float2* g32, const GramRowData& rd, void* part, double* rpart,
+                                   int zI0, int zJ0, int ntot, hipStream_t st) {
+    // (rd.only applies to the FP64 kernel)
     const Item* items = dptr<const Item>(p, p->lay.items);
     const int32_t* sched = dptr<const int32_t>(p, p->lay.sched);
     const GRow* grow = dptr<const GRow>(p, p->lay.grow);
     const unsigned nb = unsigned(p->sched.size());
-    if (nb == 0) return hipSuccess;
     if (prec == EDT_BF16X3)
-        hipLaunchKernelGGL((gram_split3_kernel<NT, false>), dim3(nb), dim3(512), row_lds_bytes(p->chunk_rows), st,
-                           items, sched, grow, rd.ub32, g32, rd.gmax, p->nz, static_cast<float*>(part), rpart,
-                           p->chunk_rows);
+        hipLaunchKernelGGL((gram_split3_kernel<NT, NTJ, false>), dim3(nb), dim3(512),
+                           row_lds_bytes(p->chunk_rows), st, items, sched, grow, rd.ub32, g32, rd.gmax,
+                           p->nz, zI0, zJ0, ntot, static_cast<float*>(part), rpart, p->chunk_rows);
     else if (prec == EDT_FP16X3)
-        hipLaunchKernelGGL((gram_split3_kernel<NT, true>), dim3(nb), dim3(512), row_lds_bytes(p->chunk_rows), st,
-                           items, sched, grow, rd.ub32, g32, rd.gmax, p->nz, static_cast<float*>(part), rpart,
-                           p->chunk_rows);
-    else if (prec == EDT_FP32)
+        hipLaunchKernelGGL((gram_split3_kernel<NT, NTJ, true>), dim3(nb), dim3(512),
+                           row_lds_bytes(p->chunk_rows), st, items, sched, grow, rd.ub32, g32, rd.gmax,
+                           p->nz, zI0, zJ0, ntot, static_cast<float*>(part), rpart, p->chunk_rows);
+    else if (prec == EDT_FP64)
+        hipLaunchKernelGGL((gram_f64_kernel<NT, NTJ>), dim3(nb), dim3(512), 0, st, items, sched, grow,
+                           dptr<const double>(p, p->lay.gsc), rd.ubw, g64, p->nz, zI0, zJ0, ntot,
+                           static_cast<double*>(part), rpart, rd.only);
+    else if constexpr (NTJ == 0)
         hipLaunchKernelGGL(gram_f32_kernel<NT>, dim3(nb), dim3(256), row_lds_bytes(p->chunk_rows), st,
                            items, sched, grow, rd.ub32, g32, p->nz, static_cast<float*>(part), rpart,
                            p->chunk_rows);
     else
-        hipLaunchKernelGGL(gram_f64_kernel<NT>, dim3(nb), dim3(512), 0, st, items, sched, grow,
-                           dptr<const double>(p, p->lay.gsc), rd.ubw, g64, p->nz,
-                           static_cast<double*>(part), rpart);
+        return hipErrorInvalidValue;   // FP32 Gram: depth counts up to 256 only
     return hipGetLastError();
 }
 
-template <int NT>
-static hipError_t configure_gram_nt() {
+template <int NTJ>
+static hipError_t launch_gram_nt(int nt, const edt_plan* p, edt_precision prec, const zd* g64,
+                                 const float2* g32, const GramRowData& rd, void* part, double* rpart,
+                                 int zI0, int zJ0, int ntot, hipStream_t st) {
+    switch (nt) {
+#define EDT_CASE(N) \
+    case N: return launch_gram_task<N, NTJ>(p, prec, g64, g32, rd, part, rpart, zI0, zJ0, ntot, st);
+        EDT_CASE(1) EDT_CASE(2) EDT_CASE(3) EDT_CASE(4) EDT_CASE(5) EDT_CASE(6) EDT_CASE(7) EDT_CASE(8)
+#undef EDT_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int NT, int NTJ>
+static hipError_t configure_gram_task() {
     const int bytes = int(row_lds_bytes(2048));
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_split3_kernel<NT, false>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_split3_kernel<NT, NTJ, false>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_split3_kernel<NT, true>),
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_split3_kernel<NT, NTJ, true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess)
+    if (e == hipSuccess && NTJ == 0)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_f32_kernel<NT>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     return e;
 }
 
-// Allow the largest item size (2048 rows) for every depth-tile count.
+template <int NT>
+static hipError_t configure_gram_nt() {
+    hipError_t e = configure_gram_task<NT, 0>();
+    if (e == hipSuccess) e = configure_gram_task<NT, 4>();
+    return e;
+}
+
+// Allow the largest item size (2048 rows) for every task shape.
 hipError_t configure_gram_kernels() {
     hipError_t e = configure_gram_nt<1>();
     if (e == hipSuccess) e = configure_gram_nt<2>();
@@ -794,46 +938,53 @@ hipError_t launch_gmax(const edt_plan* p, const float2* g32, float* gmax, hipStr
     return hipGetLastError();
 }
 
+// The item partials of all tasks: a diagonal task per depth super-block and,
+// for each pair of super-blocks sbi > sbj, two rectangular tasks between
+// super-block sbi and the halves (128 depths) of super-block sbj.
 hipError_t launch_gram(const edt_plan* p, edt_precision prec, const zd* g64, const float2* g32,
                        const zd* ubw, const float4* ub32, const float* gmax, void* part, double* rpart,
-                       hipStream_t st) {
-    const int NT = (p->nz + 31) / 32;
-    const GramRowData rd{ubw, ub32, gmax};
-    hipError_t e;
-    switch (NT) {
-        case 1: e = launch_gram_nt<1>(p, prec, g64, g32, rd, part, rpart, st); break;
-        case 2: e = launch_gram_nt<2>(p, prec, g64, g32, rd, part, rpart, st); break;
-        case 3: e = launch_gram_nt<3>(p, prec, g64, g32, rd, part, rpart, st); break;
-        case 4: e = launch_gram_nt<4>(p, prec, g64, g32, rd, part, rpart, st); break;
-        case 5: e = launch_gram_nt<5>(p, prec, g64, g32, rd, part, rpart, st); break;
-        case 6: e = launch_gram_nt<6>(p, prec, g64, g32, rd, part, rpart, st); break;
-        case 7: e = launch_gram_nt<7>(p, prec, g64, g32, rd, part, rpart, st); break;
-        case 8: e = launch_gram_nt<8>(p, prec, g64, g32, rd, part, rpart, st); break;
-        default: return hipErrorInvalidValue;
+                       hipStream_t st, const int32_t* only) {
+    if (p->sched.empty()) return hipSuccess;
+    const int nz = p->nz, ntot = (nz + 31) / 32, ns = n_super(nz);
+    if (prec == EDT_FP32 && ns > 1) return hipErrorInvalidValue;
+    if (only && prec != EDT_FP64) return hipErrorInvalidValue;
+    const GramRowData rd{ubw, ub32, gmax, only};
+    auto nt_of = [&](int sb) { return (std::min(kSuperDepth, nz - kSuperDepth * sb) + 31) / 32; };
+    for (int sb = 0; sb < ns; ++sb) {
+        const hipError_t e =
+            launch_gram_nt<0>(nt_of(sb), p, prec, g64, g32, rd, part, rpart, kSuperDepth * sb, 0, ntot, st);
+        if (e != hipSuccess) return e;
     }
-    return e;
+    for (int sbi = 1; sbi < ns; ++sbi)
+        for (int sbj = 0; sbj < sbi; ++sbj)
+            for (int h = 0; h < 2; ++h) {
+                const hipError_t e = launch_gram_nt<4>(nt_of(sbi), p, prec, g64, g32, rd, part, rpart,
+                                                       kSuperDepth * sbi, kSuperDepth * sbj + 128 * h, ntot, st);
+                if (e != hipSuccess) return e;
+            }
+    return hipSuccess;
 }
 
 hipError_t launch_gram_reduce(const edt_plan* p, edt_precision prec, const void* part, double* gram,
-                              hipStream_t st) {
+                              hipStream_t st, const int32_t* only) {
     const int NT = (p->nz + 31) / 32;
     const int ntl = NT * (NT + 1) / 2;
     const int32_t* pair_item = dptr<const int32_t>(p, p->lay.pair_item);
     if (p->n_pairs == 0) return hipSuccess;
     if (prec == EDT_FP64)
         hipLaunchKernelGGL(gram_reduce_kernel<double>, dim3(unsigned(p->n_pairs), ntl), dim3(256), 0,
-                           st, static_cast<const double*>(part), pair_item, p->nz, ntl, gram);
+                           st, static_cast<const double*>(part), pair_item, p->nz, ntl, gram, only);
     else
         hipLaunchKernelGGL(gram_reduce_kernel<float>, dim3(unsigned(p->n_pairs), ntl), dim3(256), 0,
-                           st, static_cast<const float*>(part), pair_item, p->nz, ntl, gram);
+                           st, static_cast<const float*>(part), pair_item, p->nz, ntl, gram, only);
     return hipGetLastError();
 }
 
 hipError_t launch_rhs_reduce(const edt_plan* p, const double* rpart, double* rhs, double* trace,
-                             hipStream_t st) {
+                             hipStream_t st, const int32_t* only) {
     if (p->n_pairs == 0) return hipSuccess;
     hipLaunchKernelGGL(rhs_reduce_kernel, dim3(unsigned(p->n_pairs)), dim3(256), 0, st, rpart,
-                       dptr<const int32_t>(p, p->lay.pair_item), p->nz, rhs, trace);
+                       dptr<const int32_t>(p, p->lay.pair_item), p->nz, rhs, trace, only);
     return hipGetLastError();
 }
 

@@ -213,13 +213,23 @@ WorkLayout work_layout(const edt_plan* p) {
     w.rhs_part = off;
     off = align256(off + p->ritems.size() * (2 * nz + 1) * sizeof(double));
     w.gram_rpart = off;
-    off = align256(off + p->items.size() * (2 * nz + 1) * sizeof(double));
+    off = align256(off + p->items.size() * size_t(rpart_width(p->nz)) * sizeof(double));
     w.lam = off;
     off = align256(off + P * sizeof(double));
     w.dinv = off;
     off = align256(off + P * size_t((p->nz + 31) / 32) * 32 * 32 * sizeof(double));
     w.conv = off;
     off = align256(off + P * sizeof(int32_t));
+    w.pcg_r = off;
+    off = align256(off + P * 2 * nz * sizeof(double));
+    w.pcg_p = off;
+    off = align256(off + P * 2 * nz * sizeof(double));
+    w.pcg_rho = off;
+    off = align256(off + P * sizeof(double));
+    w.esc_rhs = off;
+    off = align256(off + P * 2 * nz * sizeof(double));
+    w.esc_trace = off;
+    off = align256(off + P * sizeof(double));
     w.aux = off;
     off = align256(off + P * 2 * nz * sizeof(double));
     w.aux2 = off;

@@ -112,10 +112,12 @@ __global__ __launch_bounds__(256) void bsum_kernel(const int32_t* __restrict__ u
 // rpart[slot][h*nz + z].  With A = W p, p = g(k_r) g(k_s) and the row data
 // ubw = conj(W) B from bsum_kernel, a row contributes
 //   Re(conj(p) (ubw - |W|^2 mult (p . x))),   |W|^2 mult = gsc^2.
+// Without DATA the row data are taken as zero and the kernel returns the
+// partial of -Re(A^H A) x (the operator applied to a search direction).
 // Rows past the item (padding of the last batch) get zero data and weight and
 // depths past nz get x = 0, so no per-element masking is needed; the depths
 // past nz are never stored.
-template <int ZPL>
+template <int ZPL, bool DATA>
 __global__ __launch_bounds__(256) void resid_kernel(const Item* __restrict__ items,
                                                     const int32_t* __restrict__ sched,
                                                     const GRow* __restrict__ grow,
@@ -155,10 +157,14 @@ __global__ __launch_bounds__(256) void resid_kernel(const Item* __restrict__ ite
             const bool on = r < n;
             const int64_t row = int64_t(it.row_begin) + min(r, n - 1);
             const GRow g = grow[row];
-            const zd b0v = ubw[2 * row], b1v = ubw[2 * row + 1];
             const double sc = gsc[row];
-            bp[j] = on ? b0v : zd{0.0, 0.0};
-            bm[j] = on ? b1v : zd{0.0, 0.0};
+            if constexpr (DATA) {
+                const zd b0v = ubw[2 * row], b1v = ubw[2 * row + 1];
+                bp[j] = on ? b0v : zd{0.0, 0.0};
+                bm[j] = on ? b1v : zd{0.0, 0.0};
+            } else {
+                bp[j] = bm[j] = zd{0.0, 0.0};
+            }
             w2[j] = on ? sc * sc : 0.0;
 #pragma unroll
             for (int q = 0; q < ZPL; ++q) {
@@ -273,9 +279,16 @@ static hipError_t launch_resid_z(const edt_plan* p, const zd* g64, const zd* ubw
                                  const int32_t* conv, double* rpart, hipStream_t st) {
     const unsigned nit = unsigned(p->rsched.size());
     if (nit == 0) return hipSuccess;
-    hipLaunchKernelGGL(resid_kernel<ZPL>, dim3(nit), dim3(256), 0, st, dptr<const Item>(p, p->lay.ritems),
-                       dptr<const int32_t>(p, p->lay.rsched), dptr<const GRow>(p, p->lay.grow),
-                       dptr<const double>(p, p->lay.gsc), ubw, g64, p->nz, x, conv, rpart);
+    const Item* items = dptr<const Item>(p, p->lay.ritems);
+    const int32_t* sched = dptr<const int32_t>(p, p->lay.rsched);
+    const GRow* grow = dptr<const GRow>(p, p->lay.grow);
+    const double* gsc = dptr<const double>(p, p->lay.gsc);
+    if (ubw)
+        hipLaunchKernelGGL((resid_kernel<ZPL, true>), dim3(nit), dim3(256), 0, st, items, sched, grow, gsc, ubw,
+                           g64, p->nz, x, conv, rpart);
+    else
+        hipLaunchKernelGGL((resid_kernel<ZPL, false>), dim3(nit), dim3(256), 0, st, items, sched, grow, gsc,
+                           ubw, g64, p->nz, x, conv, rpart);
     return hipGetLastError();
 }
 

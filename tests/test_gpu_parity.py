@@ -33,6 +33,9 @@ def _cases():
         "cfg1": lambda: make_config(1),
         "layered-nz40": lambda: layered_small(),
         "layered-nz200": lambda: layered_small(nz=200, N=32, nf=6, seed=3),
+        # past one 256-depth super-block: a 1-depth second block, and a ragged one
+        "layered-nz257": lambda: layered_small(nz=257, N=16, nf=4, seed=4),
+        "layered-nz400": lambda: layered_small(nz=400, N=24, nf=5, seed=6, dz=5.0),
         "3d-small": lambda: make_custom(dim=3, N=12, Nh=6, nz=37, dx=25.0, dz=10.0,
                                         freqs=(8.0, 14.0, 20.0), vel=(1800.0, 2500.0, 2100.0),
                                         zif=(60.0, 200.0), noise_rel=0.05, seed=5),
@@ -86,7 +89,8 @@ def test_forward_born_rows(refs, name):
     assert np.max(np.abs(d - clean)) <= 1e-12 * np.max(np.abs(clean))
 
 
-@pytest.mark.parametrize("name", ["cfg1", "layered-nz40", "layered-nz200", "3d-small"])
+@pytest.mark.parametrize("name", ["cfg1", "layered-nz40", "layered-nz200", "layered-nz257", "layered-nz400",
+                                  "3d-small"])
 def test_fp64_gram_rhs_trace(refs, name):
     s, r = _ref(refs, name)
     p = E.Plan(s)
@@ -105,7 +109,8 @@ def test_fp64_gram_rhs_trace(refs, name):
         assert abs(trace[i] - tr) <= 1e-12 * tr
 
 
-@pytest.mark.parametrize("name", ["cfg1", "layered-nz40", "layered-nz200", "3d-small"])
+@pytest.mark.parametrize("name", ["cfg1", "layered-nz40", "layered-nz200", "layered-nz257", "layered-nz400",
+                                  "3d-small"])
 def test_fp64_solve(refs, name):
     s, r = _ref(refs, name)
     p = E.Plan(s)
@@ -119,9 +124,12 @@ def test_fp64_solve(refs, name):
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "fp16x3", "fp32"])
-@pytest.mark.parametrize("name", ["cfg1", "layered-nz40", "layered-nz200", "3d-small"])
+@pytest.mark.parametrize("name", ["cfg1", "layered-nz40", "layered-nz200", "layered-nz257", "layered-nz400",
+                                  "3d-small"])
 def test_mixed_solve_with_refinement(refs, name, prec):
     s, r = _ref(refs, name)
+    if prec == "fp32" and s.nz > 256:
+        pytest.skip("the FP32 Gram covers nz <= 256 (rejected with EINVAL, tested below)")
     p = E.Plan(s)
     out = p.run(_vel(s), _dev(r["d_rows"]), s.lambda_rel, prec=prec, refine_tol=1e-9, max_refine=10)
     torch.cuda.synchronize()
@@ -133,15 +141,16 @@ def test_mixed_solve_with_refinement(refs, name, prec):
     print(name, prec, "global", g, "pair", per, "steps max", steps.max(), "mean", steps.mean())
 
 
-def test_mixed_gram_is_close_to_fp64(refs):
-    s, r = _ref(refs, "layered-nz40")
+@pytest.mark.parametrize("name", ["layered-nz40", "layered-nz400"])
+def test_mixed_gram_is_close_to_fp64(refs, name):
+    s, r = _ref(refs, name)
     p = E.Plan(s)
     g64, g32 = p.green(_vel(s))
     d = _dev(r["d_rows"])
     G64 = p.assemble(g64, g32, d, "fp64")[0].cpu().numpy()
     Gb = p.assemble(g64, g32, d, "bf16x3")[0].cpu().numpy()
     Gh = p.assemble(g64, g32, d, "fp16x3")[0].cpu().numpy()
-    Gf = p.assemble(g64, g32, d, "fp32")[0].cpu().numpy()
+    Gf = p.assemble(g64, g32, d, "fp32")[0].cpu().numpy() if s.nz <= 256 else G64
     low = np.tril(np.ones((s.nz, s.nz), bool))
     for i in range(G64.shape[0]):
         sc = np.max(np.abs(G64[i]))
@@ -194,6 +203,43 @@ def test_mixed_rhs_and_trace(refs, prec):
     assert np.all(np.abs(tm[ok] - t64[ok]) <= 1e-7 * t64[ok])
     for i in np.flatnonzero(ok):
         assert np.max(np.abs(cm[i] - c64[i])) <= 1e-4 * np.max(np.abs(c64[i]))
+
+
+def test_bf16x3_pivot_failure_escalates_to_fp64(refs):
+    """nz = 400 with few rows: lambda is below the BF16x3 Gram error for one
+    pair, whose factorisation fails (info = failing column).  Without
+    escalation the failure is reported; with it that pair is re-assembled in
+    FP64 and every pair meets the mixed-precision bar."""
+    s, r = _ref(refs, "layered-nz400")
+    p = E.Plan(s)
+    vel = _vel(s)
+    d = _dev(r["d_rows"])
+    g64, g32 = p.green(vel)
+    gram, rhs, trace = p.assemble(g64, g32, d, "bf16x3")
+    _, _, info0, _ = p.solve(g64, d, gram.clone(), rhs, trace, s.lambda_rel, refine=True, refine_tol=1e-9,
+                             max_refine=10, escalate=False)
+    info0 = info0.cpu().numpy()
+    assert np.any(info0 > 0), "expected a failed BF16x3 factorisation in this case"
+    _, v, info1, _ = p.solve(g64, d, gram.clone(), rhs, trace, s.lambda_rel, refine=True, refine_tol=1e-9,
+                             max_refine=10, escalate=True)
+    info1 = info1.cpu().numpy()
+    assert np.all((info1 == 0) | (info1 == -1))
+    g, per = rel_errors(v.cpu().numpy(), r["V"], r["pl"])
+    assert g <= 1e-6 and per <= 1e-6, (g, per)
+
+
+def test_depth_limits(refs):
+    """nz > 256 is served by FP64 and the split Grams; FP32 and the adjoint
+    reject it, and nz > 448 is rejected at every entry point."""
+    s, r = _ref(refs, "layered-nz400")
+    p = E.Plan(s)
+    g64, g32 = p.green(_vel(s))
+    with pytest.raises(RuntimeError, match="FP32 Gram"):
+        p.assemble(g64, g32, _dev(r["d_rows"]), "fp32")
+    big = layered_small(nz=449, N=4, nf=2, seed=1)
+    pb = E.Plan(big)
+    with pytest.raises(RuntimeError, match="nz > 448"):
+        pb.green(_vel(big))
 
 
 def test_empty_and_nonfinite_and_singular():
