@@ -138,6 +138,9 @@ typedef struct {
     size_t dev_plan_bytes; /* size of the device copy of the plan */
     size_t work_bytes;     /* workspace needed by assemble / solve / adjoint */
     double gram_flops;     /* sum over pairs of 2 R_p nz (nz+1): algorithmic Gram work */
+    int64_t n_pairs_all;   /* pairs of the whole survey */
+    int64_t pair_begin;    /* survey index of this plan's first pair */
+    int resid_group;       /* frequencies per residual work item */
 } edt_plan_info;
 
 typedef struct {
@@ -152,15 +155,24 @@ typedef struct {
 const char* edt_last_error(void);
 
 /*
- * Work-item shape of a plan (0 in a field = default).
+ * Work-item shape and pair range of a plan (0 in a field = default).
  *   chunk_rows  unique rows per Gram work item at most (default and maximum 2048)
  *   gram_band   frequencies per Gram band (default: as many as keep one band's
  *               FP32 table slab, n_cls * nz * 8 bytes per frequency, near
- *               2.5 MB, so that it stays in one XCD's 4 MB L2)
+ *               2.5 MB, so that it stays in one XCD's 4 MB L2, or, if more,
+ *               as many as give an average item 256 unique rows)
+ *   pair_begin, pair_end
+ *               plan only the pairs [pair_begin, pair_end) of the survey's pair
+ *               order (pair_end 0 = to the end): a batch of a survey too large
+ *               for one workspace.  The |k| classes, and so the Green's table,
+ *               are those of the whole survey, so that every batch uses one
+ *               table; v_out of a batch's solve receives only its pairs' k_m.
  */
 typedef struct {
     int chunk_rows;
     int gram_band;
+    int64_t pair_begin;
+    int64_t pair_end;
 } edt_plan_opts;
 
 /*
@@ -177,6 +189,16 @@ typedef struct {
  */
 edt_status edt_plan_create(const edt_survey* survey, const edt_layers* layers,
                            const edt_plan_opts* opts, edt_plan** out);
+
+/*
+ * Rows (data rows, before the unique-row merge) of every pair of the survey,
+ * in the survey's pair order, without building a plan: for cutting a large
+ * survey into pair-range batches.  *n_pairs_all receives the pair count;
+ * rows_per_pair (nullable: query the count first) must hold that many.
+ * Host only.  Errors: as edt_plan_create for the survey and layers.
+ */
+edt_status edt_survey_pair_rows(const edt_survey* survey, const edt_layers* layers, int64_t* n_pairs_all,
+                                int64_t* rows_per_pair);
 edt_status edt_plan_destroy(edt_plan* plan);
 edt_status edt_plan_query(const edt_plan* plan, edt_plan_info* out);
 

@@ -74,19 +74,23 @@ class Plan:
     pairs: list
     ctop: float
     kmax: np.ndarray
+    index: list = None     # survey pair index of each listed pair (all pairs: 0..P-1)
 
 
 def _ctop(s):
     return float(s.vel[0])
 
 
-def _plan2d(s):
+def _plan2d(s, only):
     N = s.n_mid
     dk = TWO_PI / (N * s.d_mid)
     kmax = kmax_of(s.freqs, s.kappa, _ctop(s))
     qs = np.arange(-(N // 2), N - N // 2)          # signed a, ascending
-    pairs = []
+    pairs, index = [], []
     for u in range(N // 2 + 1):
+        if only is not None and u not in only:
+            continue
+        index.append(u)
         un = (-u) % N
         fl, al, bl = [], [], []
         for f in range(s.n_freq):
@@ -106,10 +110,10 @@ def _plan2d(s):
         key0 = np.stack([a_ % N, b_ % N], axis=1)
         key1 = np.stack([pa, pb], axis=1)
         pairs.append(Pair(u, un, f_, np.abs(a_) * dk, np.abs(b_) * dk, key0, key1))
-    return Plan(N, pairs, _ctop(s), kmax)
+    return Plan(N, pairs, _ctop(s), kmax, index)
 
 
-def _plan3d(s):
+def _plan3d(s, only):
     N, Nh = s.n_mid, s.n_off
     if abs(Nh * s.d_off - N * s.d_mid / 2) > 1e-9 * N * s.d_mid:
         raise ValueError("3D areal reading needs N_h*dh = N_m*dm/2")
@@ -120,12 +124,17 @@ def _plan3d(s):
     ns = np.arange(-(Nh // 2), Nh - Nh // 2)
     nx, ny = np.meshgrid(ns, ns, indexing="ij")
     nx, ny = nx.ravel(), ny.ravel()
-    pairs = []
+    pairs, index = [], []
+    gp = -1   # survey pair index
     for u in range(N * N):
         ux, uy = divmod(u, N)
         un = ((-ux) % N) * N + ((-uy) % N)
         if un < u:
             continue
+        gp += 1
+        if only is not None and gp not in only:
+            continue
+        index.append(gp)
         qx = ux if ux < (N + 1) // 2 else ux - N
         qy = uy if uy < (N + 1) // 2 else uy - N
         sr = (qx + 2 * nx) ** 2 + (qy + 2 * ny) ** 2
@@ -146,15 +155,19 @@ def _plan3d(s):
         key1 = np.stack([np.full(n_.shape, un), n_], axis=1)
         pairs.append(Pair(u, un, f_, np.sqrt(sr_) * (0.5 * dk), np.sqrt(ss_) * (0.5 * dk),
                           key0, key1))
-    return Plan(N * N, pairs, _ctop(s), kmax)
+    return Plan(N * N, pairs, _ctop(s), kmax, index)
 
 
-def plan(s) -> Plan:
-    """Enumerate pairs and rows of a survey (see module docstring)."""
+def plan(s, only=None) -> Plan:
+    """Enumerate pairs and rows of a survey (see module docstring).  ``only``:
+    a set of survey pair indices (the pair order above) to list, e.g. a sample
+    of a survey too large to enumerate whole; ``Plan.index`` gives each listed
+    pair's survey index."""
+    only = None if only is None else set(int(i) for i in only)
     if s.dim == 2:
-        return _plan2d(s)
+        return _plan2d(s, only)
     if s.dim == 3:
-        return _plan3d(s)
+        return _plan3d(s, only)
     raise ValueError("dim must be 2 or 3")
 
 

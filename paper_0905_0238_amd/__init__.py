@@ -9,8 +9,9 @@ refinement and the adjoint; this package only marshals torch tensors into its
 C-ABI (``include/edt.h``).
 """
 from . import _lib
-from .edt import Plan, solve
+from .edt import Plan, solve, pair_rows
 from .pipeline import Pipeline
+from .stream import Stream, cut_batches
 from .autograd import EDTSolve, edt_solve
 
-__all__ = ["Plan", "solve", "Pipeline", "EDTSolve", "edt_solve", "_lib"]
+__all__ = ["Plan", "solve", "pair_rows", "Pipeline", "Stream", "cut_batches", "EDTSolve", "edt_solve", "_lib"]

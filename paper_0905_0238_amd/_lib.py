@@ -31,11 +31,13 @@ class PlanInfo(C.Structure):
                 ("n_items", C.c_int64), ("n_freq", C.c_int), ("n_cls", C.c_int), ("nz", C.c_int),
                 ("n_layers", C.c_int), ("chunk_rows", C.c_int), ("gram_band", C.c_int),
                 ("table_elems", C.c_size_t),
-                ("dev_plan_bytes", C.c_size_t), ("work_bytes", C.c_size_t), ("gram_flops", C.c_double)]
+                ("dev_plan_bytes", C.c_size_t), ("work_bytes", C.c_size_t), ("gram_flops", C.c_double),
+                ("n_pairs_all", C.c_int64), ("pair_begin", C.c_int64), ("resid_group", C.c_int)]
 
 
 class PlanOpts(C.Structure):
-    _fields_ = [("chunk_rows", C.c_int), ("gram_band", C.c_int)]
+    _fields_ = [("chunk_rows", C.c_int), ("gram_band", C.c_int), ("pair_begin", C.c_int64),
+                ("pair_end", C.c_int64)]
 
 
 class SolveOpts(C.Structure):
@@ -43,7 +45,7 @@ class SolveOpts(C.Structure):
                 ("escalate", C.c_int)]
 
 
-EXPORTS = ["edt_last_error", "edt_plan_create", "edt_plan_destroy", "edt_plan_query",
+EXPORTS = ["edt_last_error", "edt_plan_create", "edt_survey_pair_rows", "edt_plan_destroy", "edt_plan_query",
            "edt_plan_rowmap", "edt_plan_urows", "edt_plan_schedule", "edt_plan_upload", "edt_green", "edt_assemble", "edt_solve",
            "edt_forward", "edt_adjoint", "edt_timing_enable", "edt_timing_read"]
 
@@ -63,6 +65,7 @@ def load(path: str = LIB_PATH):
     L.edt_last_error.argtypes = []
     sig = {
         "edt_plan_create": [C.POINTER(Survey), C.POINTER(Layers), C.POINTER(PlanOpts), C.POINTER(vp)],
+        "edt_survey_pair_rows": [C.POINTER(Survey), C.POINTER(Layers), i64p, i64p],
         "edt_plan_destroy": [vp],
         "edt_plan_query": [vp, C.POINTER(PlanInfo)],
         "edt_plan_rowmap": [vp, i64p, ip, ip, ip, dp],

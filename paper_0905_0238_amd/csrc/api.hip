@@ -25,7 +25,7 @@ hipError_t launch_resid(const edt_plan* p, const zd* g64, const zd* ubw, const d
 hipError_t launch_forward(const edt_plan* p, const zd* g64, const zd* v, zd* d_rows, hipStream_t st);
 hipError_t launch_chol(const edt_plan* p, double* gram, const double* trace, const double* rhs,
                        double lambda_rel, double* lam, double* dinv, double* x, int32_t* info,
-                       int32_t* conv, int32_t* steps, hipStream_t st, int only_failed = 0);
+                       int32_t* conv, int32_t* steps, hipStream_t st, int only_failed, int exact);
 hipError_t launch_pcg_update(const edt_plan* p, const double* gram, const double* dinv, const double* rpart,
                              const double* lam, double* x, double* r, double* pv, double* rho, int32_t* conv,
                              int32_t* steps, double tol, int first, hipStream_t st);
@@ -233,7 +233,8 @@ edt_status edt_solve(const edt_plan* p, const edt_c128* g64, const edt_c128* d_r
     int32_t* conv = reinterpret_cast<int32_t*>(w + wl.conv);
     int32_t* stp = steps ? steps : reinterpret_cast<int32_t*>(w + wl.aux);
     double* dinv = reinterpret_cast<double*>(w + wl.dinv);
-    EDT_TRY(launch_chol(p, gram, trace, rhs, lambda_rel, lam, dinv, x, info, conv, stp, stream), "cholesky");
+    EDT_TRY(launch_chol(p, gram, trace, rhs, lambda_rel, lam, dinv, x, info, conv, stp, stream, 0, !refine),
+            "cholesky");
     if (refine) {
         zd* ub = reinterpret_cast<zd*>(w + wl.ub);
         zd* ubw = reinterpret_cast<zd*>(w + wl.ubw);
@@ -254,7 +255,7 @@ edt_status edt_solve(const edt_plan* p, const edt_c128* g64, const edt_c128* d_r
                     "escalate gram_fp64");
             EDT_TRY(launch_gram_reduce(p, EDT_FP64, w + wl.gram_part, gram, stream, info), "escalate gram_reduce");
             EDT_TRY(launch_rhs_reduce(p, gpart, erhs, etr, stream, info), "escalate rhs reduce");
-            EDT_TRY(launch_chol(p, gram, etr, erhs, lambda_rel, lam, dinv, x, info, conv, stp, stream, 1),
+            EDT_TRY(launch_chol(p, gram, etr, erhs, lambda_rel, lam, dinv, x, info, conv, stp, stream, 1, 0),
                     "escalate cholesky");
         }
         double* r = reinterpret_cast<double*>(w + wl.pcg_r);

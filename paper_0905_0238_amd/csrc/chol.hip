@@ -26,7 +26,8 @@ namespace edt {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // Factor gram[p] + lambda_p I in place, store the diagonal-block inverses in
-// dinv[p][nblk][32][32] and solve for x from rhs.
+// dinv[p][nblk][32][32] and solve for x from rhs (exact: with the corrected
+// block solves, for a result that no refinement follows).
 // Dynamic LDS: the panel (nz x CBP doubles) and D (32 x CBP doubles), reused
 // by the solve afterwards.
 // Q: row-block groups of the panel accumulators (wave w holds the 16-row
@@ -36,7 +37,8 @@ __global__ __launch_bounds__(256, Q > 4 ? 1 : 2) void chol_solve_kernel(
     double* __restrict__ gram, const double* __restrict__ trace, const double* __restrict__ rhs,
     const int64_t* __restrict__ urow_off, const int32_t* __restrict__ pair_u, int nz,
     double lambda_rel, double* __restrict__ lam_out, double* __restrict__ dinv, double* __restrict__ x,
-    int32_t* __restrict__ info, int32_t* __restrict__ conv, int32_t* __restrict__ steps, int only_failed) {
+    int32_t* __restrict__ info, int32_t* __restrict__ conv, int32_t* __restrict__ steps, int only_failed,
+    int exact) {
     extern __shared__ double smem[];
     double* sP = smem;
     double* sD = smem + size_t(nz) * CBP;
@@ -257,7 +259,8 @@ __global__ __launch_bounds__(256, Q > 4 ? 1 : 2) void chol_solve_kernel(
     double* sLs = sDs + CB * CBP;
     for (int e = tid; e < 2 * nz; e += blockDim.x) sx[e] = rhs[size_t(p) * 2 * nz + e];
     __syncthreads();
-    block_solve2(A, Dp, nz, sx, sred, sDs, sLs);
+    if (exact) block_solve2<true>(A, Dp, nz, sx, sred, sDs, sLs);
+    else block_solve2<false>(A, Dp, nz, sx, sred, sDs, sLs);
     for (int e = tid; e < 2 * nz; e += blockDim.x)
         x[size_t(p) * 2 * nz + e] = (selfc && e >= nz) ? 0.0 : sx[e];
     if (tid == 0) {
@@ -340,7 +343,7 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(
     }
     __syncthreads();
     for (int e = tid; e < 2 * nz; e += blockDim.x) rp[e] = sx[e];
-    block_solve2(gram + size_t(p) * nz * nz, dinv + size_t(p) * nblk * CB * CB, nz, sx, sred, sD, sL);
+    block_solve2<false>(gram + size_t(p) * nz * nz, dinv + size_t(p) * nblk * CB * CB, nz, sx, sred, sD, sL);
     double dn = 0.0, xn = 0.0, rz = 0.0;
     for (int e = tid; e < 2 * nz; e += blockDim.x) {
         const double z = (selfc && e >= nz) ? 0.0 : sx[e];
@@ -427,17 +430,17 @@ hipError_t configure_kernels() {
 
 hipError_t launch_chol(const edt_plan* p, double* gram, const double* trace, const double* rhs,
                        double lambda_rel, double* lam, double* dinv, double* x, int32_t* info,
-                       int32_t* conv, int32_t* steps, hipStream_t st, int only_failed) {
+                       int32_t* conv, int32_t* steps, hipStream_t st, int only_failed, int exact) {
     if (p->n_pairs == 0) return hipSuccess;
     const size_t lds = chol_lds_bytes(p->nz);
     if (p->nz <= 256)
         hipLaunchKernelGGL(chol_solve_kernel<4>, dim3(unsigned(p->n_pairs)), dim3(256), lds, st, gram, trace,
                            rhs, dptr<const int64_t>(p, p->lay.urow_off), dptr<const int32_t>(p, p->lay.pair_u),
-                           p->nz, lambda_rel, lam, dinv, x, info, conv, steps, only_failed);
+                           p->nz, lambda_rel, lam, dinv, x, info, conv, steps, only_failed, exact);
     else
         hipLaunchKernelGGL(chol_solve_kernel<7>, dim3(unsigned(p->n_pairs)), dim3(256), lds, st, gram, trace,
                            rhs, dptr<const int64_t>(p, p->lay.urow_off), dptr<const int32_t>(p, p->lay.pair_u),
-                           p->nz, lambda_rel, lam, dinv, x, info, conv, steps, only_failed);
+                           p->nz, lambda_rel, lam, dinv, x, info, conv, steps, only_failed, exact);
     return hipGetLastError();
 }
 

@@ -117,15 +117,17 @@ constexpr int kSolveRed = 704;
 // diagonal blocks of L:
 //   forward   t_b = r_b - sum_{j<b} L_bj y_j,      y_b = D_b t_b,
 //   backward  t_b = y_b - sum_{j>b} L_jb^T x_j,    x_b = D_b^T t_b,
-// each block result followed by one correction with the block itself,
-// y_b += D_b (t_b - L_bb y_b) (and the transposed form backward): applying an
-// explicit inverse loses a factor up to cond(L_bb) against substitution, the
-// correction restores substitution-level accuracy.
+// with CORR each block result followed by one correction with the block
+// itself, y_b += D_b (t_b - L_bb y_b) (and the transposed form backward):
+// applying an explicit inverse loses a factor up to cond(L_bb) against
+// substitution, the correction restores substitution-level accuracy.  Without
+// CORR (a preconditioner inside an iteration) the correction is skipped.
 // L: lower triangle of a row-major nz x nz matrix (global); D: [nblk][32][32]
 // row-major lower-triangular inverses (global).  No step has a serial chain
 // longer than one block: 2 nblk dependent block steps.
 // LDS: sred >= kSolveRed doubles, sD and sL >= 32 * CBP doubles each.
 // blockDim.x must be 256.
+template <bool CORR>
 __device__ __forceinline__ void block_solve2(const double* __restrict__ L, const double* __restrict__ D,
                                              int nz, double* sx, double* sred, double* sD, double* sL) {
     const int tid = threadIdx.x;
@@ -136,8 +138,10 @@ __device__ __forceinline__ void block_solve2(const double* __restrict__ L, const
         for (int e = tid; e < CB * CB; e += 256) {
             const int i = e >> 5, j = e & 31;
             sD[i * CBP + j] = D[size_t(b) * CB * CB + e];
-            const double l = L[size_t(k0 + min(i, kb - 1)) * nz + k0 + min(j, kb - 1)];
-            sL[i * CBP + j] = (i < kb && j <= i) ? l : 0.0;
+            if constexpr (CORR) {
+                const double l = L[size_t(k0 + min(i, kb - 1)) * nz + k0 + min(j, kb - 1)];
+                sL[i * CBP + j] = (i < kb && j <= i) ? l : 0.0;
+            }
         }
     };
     for (int b = 0; b < nblk; ++b) {
@@ -179,6 +183,14 @@ __device__ __forceinline__ void block_solve2(const double* __restrict__ L, const
         }
         y0 = sum8(y0);
         y1 = sum8(y1);
+        if constexpr (!CORR) {
+            if (part == 0 && i < kb) {
+                sx[k0 + i] = y0;
+                sx[nz + k0 + i] = y1;
+            }
+            __syncthreads();
+            continue;
+        }
         if (part == 0) {
             sred[64 + i] = y0;
             sred[96 + i] = y1;
@@ -254,6 +266,14 @@ __device__ __forceinline__ void block_solve2(const double* __restrict__ L, const
         }
         x0 = sum8(x0);
         x1 = sum8(x1);
+        if constexpr (!CORR) {
+            if (part == 0 && c < kb) {
+                sx[k0 + c] = x0;
+                sx[nz + k0 + c] = x1;
+            }
+            __syncthreads();
+            continue;
+        }
         if (part == 0) {
             sred[576 + c] = x0;
             sred[608 + c] = x1;

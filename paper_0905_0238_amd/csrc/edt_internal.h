@@ -56,6 +56,7 @@ struct edt_plan {
     std::vector<double> cls_k;
     // pairs and rows
     int64_t n_km, n_pairs, n_rows, max_rows, n_empty;
+    int64_t n_pairs_all = 0, pair_begin = 0;   // the survey's pairs; first pair of this plan
     std::vector<int64_t> row_off;        // [P+1]
     std::vector<int32_t> pair_u;         // [2P]: u, -u
     std::vector<uint32_t> rows;          // [2R]: f, cr | cs << 16
@@ -78,6 +79,7 @@ struct edt_plan {
     // work items
     int chunk_rows;
     int gram_band;                       // frequencies per Gram band
+    int resid_group = 2;                 // frequencies per residual work item
     std::vector<edt::Item> items;        // Gram items (pair, frequency band), pair-major
     std::vector<int32_t> sched;          // XCD-aware launch order, -1 = hole
     std::vector<int32_t> pair_item;      // [P+1] first item of each pair

@@ -33,6 +33,8 @@ constexpr int kFreqGroup = 2;     // frequencies per residual work item
 constexpr int kResidRows = 1024;  // rows per residual work item at most
 constexpr int kXcd = 8;           // accelerator dies (separate L2 caches) on MI355X
 constexpr double kL2Slab = 2.5e6; // bytes of FP32 table per Gram band (an XCD's L2 is 4 MB)
+constexpr int kMinItemRows = 256; // unique rows of an average work item at least, where the band allows
+constexpr int kMinResidRows = 64; // the same for residual work items
 
 inline int64_t signed_of(int64_t n, int64_t N) { return n < (N + 1) / 2 ? n : n - N; }
 inline int64_t wrap(int64_t n, int64_t N) { return ((n % N) + N) % N; }
@@ -101,24 +103,39 @@ edt_status fail(edt_status s, const std::string& m) {
     return s;
 }
 
+// Pairs [pb, pe) of the survey's pair order get their rows; the |k| classes
+// (the columns of the Green's table) are those of the whole survey, so that
+// plans of different pair ranges share one table.
+
 // 2D periodic split-spread survey: rows of u are receiver wavenumbers a with
 // source wavenumber b = u - a (mod N); class of a wavenumber = |signed index|.
-void rows_2d(edt_plan* p, const std::vector<double>& kmax, std::vector<int64_t>& cls_of_row_r,
-             std::vector<int64_t>& cls_of_row_s) {
+// max_cls: the largest class of any row of any pair.
+void rows_2d(edt_plan* p, const std::vector<double>& kmax, int64_t pb, int64_t pe, std::vector<int64_t>& cls_of_row_r,
+             std::vector<int64_t>& cls_of_row_s, int64_t& max_cls, int64_t& n_all,
+             std::vector<int64_t>* counts = nullptr) {
     const int64_t N = p->n_mid;
     const double dk = kTwoPi / (double(N) * p->d_mid);
     p->n_km = N;
     p->row_off.push_back(0);
+    max_cls = -1;
+    n_all = N / 2 + 1;
     for (int64_t u = 0; u <= N / 2; ++u) {
+        const bool mine = u >= pb && u < pe;
         const int64_t un = wrap(-u, N);
-        p->pair_u.push_back(int32_t(u));
-        p->pair_u.push_back(int32_t(un));
+        if (mine) {
+            p->pair_u.push_back(int32_t(u));
+            p->pair_u.push_back(int32_t(un));
+        }
+        int64_t kept = 0;
         for (int f = 0; f < p->n_freq; ++f) {
             for (int64_t qa = -(N / 2); qa < N - N / 2; ++qa) {
                 const int64_t qb = signed_of(wrap(u - qa, N), N);
                 const bool keep = (std::fabs(double(qa)) * dk <= kmax[f]) &&
                                   (std::fabs(double(qb)) * dk <= kmax[f]);
                 if (!keep) continue;
+                ++kept;
+                max_cls = std::max<int64_t>(max_cls, std::max<int64_t>(std::llabs(qa), std::llabs(qb)));
+                if (!mine) continue;
                 p->rows.push_back(uint32_t(f));
                 p->rows.push_back(0);   // classes filled later
                 cls_of_row_r.push_back(std::llabs(qa));
@@ -127,14 +144,17 @@ void rows_2d(edt_plan* p, const std::vector<double>& kmax, std::vector<int64_t>&
                 p->keys.push_back(int32_t(wrap(qb, N)));
             }
         }
-        p->row_off.push_back(int64_t(cls_of_row_r.size()));
+        if (mine) p->row_off.push_back(int64_t(cls_of_row_r.size()));
+        if (counts) counts->push_back(kept);
     }
 }
 
 // 3D areal survey: in units of dk/2, k_r = q_u + 2n and k_s = q_u - 2n for the
 // signed k_m index q_u and k_h index n; class key = |k|^2 / (dk/2)^2 (integer).
-void rows_3d(edt_plan* p, const std::vector<double>& kmax, std::vector<int64_t>& key_r,
-             std::vector<int64_t>& key_s) {
+// key_used[v] = 1 for every key v of any row of any pair.
+void rows_3d(edt_plan* p, const std::vector<double>& kmax, int64_t pb, int64_t pe, std::vector<int64_t>& key_r,
+             std::vector<int64_t>& key_s, std::vector<uint8_t>& key_used, int64_t& n_all,
+             std::vector<int64_t>* counts = nullptr) {
     const int64_t N = p->n_mid, Nh = p->n_off;
     const double dk = kTwoPi / (double(N) * p->d_mid);
     const double hh = (0.5 * dk) * (0.5 * dk);
@@ -142,13 +162,37 @@ void rows_3d(edt_plan* p, const std::vector<double>& kmax, std::vector<int64_t>&
     for (size_t f = 0; f < kmax.size(); ++f) kmax2[f] = kmax[f] * kmax[f];
     p->n_km = N * N;
     p->row_off.push_back(0);
+    // When the largest disk |a|^2 <= K (a in units of dk/2) fits inside the
+    // k_m index range, every key a^2 + b^2 of the disk is used (by the row
+    // k_r = k_s = a of k_m index a, k_h = 0, at the highest frequency) and no
+    // other key can be: the key set is known without visiting the pairs
+    // outside [pb, pe).
+    double k2max = 0.0;
+    for (double v : kmax2) k2max = std::max(k2max, v);
+    const int64_t rmax = int64_t(std::floor(std::sqrt(k2max / hh))) + 1;
+    const bool disk_inside = rmax < N / 2 - 1 && Nh >= 1;
+    if (disk_inside) {
+        key_used.assign(size_t(2 * rmax * rmax + 1), 0);
+        for (int64_t a = -rmax; a <= rmax; ++a)
+            for (int64_t b = -rmax; b <= rmax; ++b) {
+                const int64_t v = a * a + b * b;
+                if (double(v) * hh <= k2max) key_used[size_t(v)] = 1;
+            }
+    }
+    int64_t gp = 0;   // pair index in the survey's pair order
     for (int64_t u = 0; u < N * N; ++u) {
         const int64_t ux = u / N, uy = u % N;
         const int64_t un = wrap(-ux, N) * N + wrap(-uy, N);
         if (un < u) continue;
+        const bool mine = gp >= pb && gp < pe;
+        ++gp;
+        if (!mine && disk_inside && !counts) continue;
+        int64_t kept = 0;
         const int64_t qx = signed_of(ux, N), qy = signed_of(uy, N);
-        p->pair_u.push_back(int32_t(u));
-        p->pair_u.push_back(int32_t(un));
+        if (mine) {
+            p->pair_u.push_back(int32_t(u));
+            p->pair_u.push_back(int32_t(un));
+        }
         for (int f = 0; f < p->n_freq; ++f) {
             // Only offsets inside both disks |q_u +- 2n|^2 <= K can be kept; the
             // loops are narrowed to that box (with a margin of one) and the exact
@@ -171,6 +215,14 @@ void rows_3d(edt_plan* p, const std::vector<double>& kmax, std::vector<int64_t>&
                     const int64_t ss = (qx - 2 * nx) * (qx - 2 * nx) + (qy - 2 * ny) * (qy - 2 * ny);
                     const bool keep = (double(sr) * hh <= kmax2[f]) && (double(ss) * hh <= kmax2[f]);
                     if (!keep) continue;
+                    ++kept;
+                    if (!disk_inside) {
+                        const int64_t mk = std::max(sr, ss);
+                        if (mk >= int64_t(key_used.size())) key_used.resize(size_t(mk + 1) * 2, 0);
+                        key_used[size_t(sr)] = 1;
+                        key_used[size_t(ss)] = 1;
+                    }
+                    if (!mine) continue;
                     const int64_t nflat = (nx - nlo) * Nh + (ny - nlo);
                     p->rows.push_back(uint32_t(f));
                     p->rows.push_back(0);
@@ -181,8 +233,10 @@ void rows_3d(edt_plan* p, const std::vector<double>& kmax, std::vector<int64_t>&
                 }
             }
         }
-        p->row_off.push_back(int64_t(key_r.size()));
+        if (mine) p->row_off.push_back(int64_t(key_r.size()));
+        if (counts) counts->push_back(kept);
     }
+    n_all = gp;
 }
 
 }  // namespace
@@ -252,22 +306,14 @@ WorkLayout work_layout(const edt_plan* p) {
 
 }  // namespace edt
 
-extern "C" {
+namespace {
 
-const char* edt_last_error(void) { return g_err.c_str(); }
-
-edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_plan_opts* opts,
-                           edt_plan** out) {
-    const int chunk_rows = opts ? opts->chunk_rows : 0;
-    const int band_opt = opts ? opts->gram_band : 0;
-    if (!s || !l || !out) return fail(EDT_EINVAL, "null argument");
-    *out = nullptr;
+// Checks of a survey and its layers shared by the planner entry points.
+edt_status validate(const edt_survey* s, const edt_layers* l) {
     if (s->dim != 2 && s->dim != 3) return fail(EDT_EINVAL, "dim must be 2 or 3");
     if (s->n_mid < 2 || !(s->d_mid > 0)) return fail(EDT_EINVAL, "n_mid >= 2 and d_mid > 0 required");
     if (s->n_freq < 1 || s->n_freq >= 65536 || !s->freq_hz) return fail(EDT_EINVAL, "1 <= n_freq < 65536");
     if (s->nz < 1 || s->nz > 1024) return fail(EDT_EINVAL, "1 <= nz <= 1024");
-    if (chunk_rows < 0 || chunk_rows > kMaxChunk) return fail(EDT_EINVAL, "0 <= chunk_rows <= 2048");
-    if (band_opt < 0) return fail(EDT_EINVAL, "gram_band >= 0");
     if (!(s->dz > 0) || !(s->eps >= 0) || !(s->kappa > 0)) return fail(EDT_EINVAL, "dz > 0, eps >= 0, kappa > 0");
     if (s->dim == 3) {
         if (s->n_off < 1 || !(s->d_off > 0)) return fail(EDT_EINVAL, "3D needs n_off >= 1, d_off > 0");
@@ -287,6 +333,66 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
     for (int f = 0; f < s->n_freq; ++f)
         if (!(s->freq_hz[f] > 0) || !std::isfinite(s->freq_hz[f])) return fail(EDT_EINVAL, "frequencies must be positive");
 
+    return EDT_OK;
+}
+
+// Horizontal wavenumber limit per frequency (the evanescent cut).
+std::vector<double> kmax_of(const edt_survey* s, double ctop) {
+    std::vector<double> kmax(s->n_freq);
+    for (int f = 0; f < s->n_freq; ++f) kmax[f] = s->kappa * (kTwoPi * s->freq_hz[f]) / ctop;
+    return kmax;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* edt_last_error(void) { return g_err.c_str(); }
+
+edt_status edt_survey_pair_rows(const edt_survey* s, const edt_layers* l, int64_t* n_pairs_all,
+                                int64_t* rows_per_pair) {
+    if (!s || !l || !n_pairs_all) return fail(EDT_EINVAL, "null argument");
+    {
+        const edt_status v = validate(s, l);
+        if (v != EDT_OK) return v;
+    }
+    try {
+        edt_plan q;
+        q.dim = s->dim;
+        q.n_mid = s->n_mid;
+        q.n_off = s->dim == 3 ? s->n_off : 0;
+        q.d_mid = s->d_mid;
+        q.n_freq = s->n_freq;
+        const std::vector<double> kmax = kmax_of(s, l->vel[0]);
+        std::vector<int64_t> kr, ks, counts;
+        std::vector<uint8_t> key_used;
+        int64_t max_cls = -1, n_all = 0;
+        if (s->dim == 2) rows_2d(&q, kmax, 0, 0, kr, ks, max_cls, n_all, &counts);
+        else rows_3d(&q, kmax, 0, 0, kr, ks, key_used, n_all, &counts);
+        *n_pairs_all = n_all;
+        if (rows_per_pair) std::memcpy(rows_per_pair, counts.data(), counts.size() * sizeof(int64_t));
+    } catch (const std::bad_alloc&) {
+        return fail(EDT_ENOMEM, "out of host memory");
+    }
+    return EDT_OK;
+}
+
+edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_plan_opts* opts,
+                           edt_plan** out) {
+    const int chunk_rows = opts ? opts->chunk_rows : 0;
+    const int band_opt = opts ? opts->gram_band : 0;
+    const int64_t pair_begin = opts ? opts->pair_begin : 0;
+    const int64_t pair_end = opts && opts->pair_end > 0 ? opts->pair_end : INT64_MAX;
+    if (!s || !l || !out) return fail(EDT_EINVAL, "null argument");
+    *out = nullptr;
+    if (chunk_rows < 0 || chunk_rows > kMaxChunk) return fail(EDT_EINVAL, "0 <= chunk_rows <= 2048");
+    if (band_opt < 0) return fail(EDT_EINVAL, "gram_band >= 0");
+    if (pair_begin < 0 || pair_begin > pair_end) return fail(EDT_EINVAL, "0 <= pair_begin <= pair_end");
+    {
+        const edt_status v = validate(s, l);
+        if (v != EDT_OK) return v;
+    }
+
     edt_plan* p = new (std::nothrow) edt_plan();
     if (!p) return fail(EDT_ENOMEM, "out of host memory");
     try {
@@ -305,12 +411,19 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
         p->ctop = l->vel[0];
         p->freq.assign(s->freq_hz, s->freq_hz + s->n_freq);
         if (l->n_layers > 1) p->zif.assign(l->zif, l->zif + l->n_layers - 1);
-        std::vector<double> kmax(s->n_freq);
-        for (int f = 0; f < s->n_freq; ++f) kmax[f] = p->kappa * (kTwoPi * p->freq[f]) / p->ctop;
+        const std::vector<double> kmax = kmax_of(s, p->ctop);
 
         std::vector<int64_t> kr, ks;
-        if (p->dim == 2) rows_2d(p, kmax, kr, ks);
-        else rows_3d(p, kmax, kr, ks);
+        std::vector<uint8_t> key_used;
+        int64_t max_cls = -1, n_all = 0;
+        if (p->dim == 2) rows_2d(p, kmax, pair_begin, pair_end, kr, ks, max_cls, n_all);
+        else rows_3d(p, kmax, pair_begin, pair_end, kr, ks, key_used, n_all);
+        if (pair_end != INT64_MAX && pair_end > n_all) {
+            delete p;
+            return fail(EDT_EINVAL, "pair_end beyond the survey's pairs (" + std::to_string(n_all) + ")");
+        }
+        p->n_pairs_all = n_all;
+        p->pair_begin = std::min(pair_begin, n_all);
         p->n_pairs = int64_t(p->row_off.size()) - 1;
         p->n_rows = p->row_off.back();
         if (p->n_rows >= (int64_t(1) << 31)) { delete p; return fail(EDT_EINVAL, "more than 2^31 rows"); }
@@ -319,23 +432,15 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
         const double dk = kTwoPi / (double(p->n_mid) * p->d_mid);
         std::vector<int32_t> cls_of_key;
         if (p->dim == 2) {
-            int64_t mx = -1;
-            for (int64_t v : kr) mx = std::max(mx, v);
-            for (int64_t v : ks) mx = std::max(mx, v);
-            p->n_cls = int(mx + 1);
+            p->n_cls = int(max_cls + 1);
             for (int c = 0; c < p->n_cls; ++c) p->cls_k.push_back(std::fabs(double(c)) * dk);
         } else {
             // keys are small non-negative integers: rank them through a dense table
-            int64_t mx = -1;
-            for (int64_t v : kr) mx = std::max(mx, v);
-            for (int64_t v : ks) mx = std::max(mx, v);
-            cls_of_key.assign(size_t(mx + 1), -1);
-            for (int64_t v : kr) cls_of_key[size_t(v)] = 0;
-            for (int64_t v : ks) cls_of_key[size_t(v)] = 0;
+            cls_of_key.assign(key_used.size(), -1);
             int c = 0;
-            for (int64_t v = 0; v <= mx; ++v)
-                if (cls_of_key[size_t(v)] == 0) {
-                    cls_of_key[size_t(v)] = c++;
+            for (size_t v = 0; v < key_used.size(); ++v)
+                if (key_used[v]) {
+                    cls_of_key[v] = c++;
                     p->cls_k.push_back(std::sqrt(double(v)) * (0.5 * dk));
                 }
             p->n_cls = c;
@@ -457,16 +562,26 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
         // its FP32 Green's table slab (n_cls x nz entries per frequency) fits
         // an XCD's L2 with room for the next band; slots are pair-major.
         p->chunk_rows = chunk_rows > 0 ? chunk_rows : kDefaultChunk;
+        // Where one frequency's slab alone exceeds that (large 3D tables) the
+        // band is widened until an average item holds kMinItemRows rows: an
+        // item's partial Gram (nz^2 values) must stay small next to its rows.
+        const double per_pf = double(p->n_urows) / std::max(1.0, double(p->n_pairs - p->n_empty) * p->n_freq);
+        const int64_t band_rows = int64_t(std::ceil(double(kMinItemRows) / std::max(per_pf, 1e-9)));
+        const int64_t band_l2 = int64_t(kL2Slab / (double(p->n_cls) * double(p->nz) * 8.0));
         p->gram_band = band_opt > 0 ? std::min(band_opt, p->n_freq)
-                                    : int(std::max<int64_t>(1, std::min<int64_t>(p->n_freq, int64_t(kL2Slab / (double(p->n_cls) * double(p->nz) * 8.0)))));
+                                    : int(std::max<int64_t>(1, std::min<int64_t>(p->n_freq, std::max(band_l2, band_rows))));
         std::vector<int32_t> gband;
         split_items(p, p->gram_band, p->chunk_rows, p->items, p->pair_item, gband);
         p->sched = xcd_schedule(p->items, gband);
 
-        // residual work items: a pair's rows within a group of kFreqGroup
-        // frequencies (at most kResidRows rows), scheduled the same way
+        // residual work items: a pair's rows within a group of at least
+        // kFreqGroup frequencies (widened like the Gram band, to kMinResidRows
+        // rows, where rows are sparse; at most kResidRows rows), scheduled the
+        // same way
+        const int64_t group_rows = int64_t(std::ceil(double(kMinResidRows) / std::max(per_pf, 1e-9)));
+        p->resid_group = int(std::max<int64_t>(kFreqGroup, std::min<int64_t>(p->n_freq, group_rows)));
         std::vector<int32_t> rgroup;
-        split_items(p, kFreqGroup, kResidRows, p->ritems, p->pair_ritem, rgroup);
+        split_items(p, p->resid_group, kResidRows, p->ritems, p->pair_ritem, rgroup);
         p->rsched = xcd_schedule(p->ritems, rgroup);
 
         // device image
@@ -551,6 +666,9 @@ edt_status edt_plan_query(const edt_plan* p, edt_plan_info* o) {
     o->dev_plan_bytes = p->lay.total;
     o->work_bytes = edt::work_layout(p).total;
     o->gram_flops = p->gram_flops;
+    o->n_pairs_all = p->n_pairs_all;
+    o->resid_group = p->resid_group;
+    o->pair_begin = p->pair_begin;
     return EDT_OK;
 }
 

@@ -10,7 +10,7 @@ import torch
 
 from . import _lib
 
-__all__ = ["Plan", "solve"]
+__all__ = ["Plan", "solve", "pair_rows"]
 
 
 def _ptr(t):
@@ -21,29 +21,51 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _structs(survey):
+    """(edt_survey, edt_layers, arrays they point into) of a survey object."""
+    freq = np.ascontiguousarray(survey.freqs, dtype=np.float64)
+    vel = np.ascontiguousarray(survey.vel, dtype=np.float64)
+    zif = np.ascontiguousarray(survey.zif, dtype=np.float64)
+    dp = C.POINTER(C.c_double)
+    sv = _lib.Survey(int(survey.dim), int(survey.n_mid), float(survey.d_mid),
+                     int(getattr(survey, "n_off", 0)), float(getattr(survey, "d_off", 0.0)),
+                     int(freq.shape[0]), freq.ctypes.data_as(dp), float(survey.eps),
+                     int(survey.nz), float(survey.z0), float(survey.dz), float(survey.kappa))
+    ly = _lib.Layers(int(vel.shape[0]), vel.ctypes.data_as(dp), zif.ctypes.data_as(dp) if zif.size else None)
+    return sv, ly, (freq, vel, zif)
+
+
+def pair_rows(survey) -> np.ndarray:
+    """Data rows of every pair of the survey (survey pair order), no plan built."""
+    L = _lib.load()
+    sv, ly, keep = _structs(survey)
+    n = C.c_int64(0)
+    i64p = C.POINTER(C.c_int64)
+    _lib.check(L.edt_survey_pair_rows(C.byref(sv), C.byref(ly), C.byref(n), None), "edt_survey_pair_rows")
+    out = np.zeros(n.value, np.int64)
+    _lib.check(L.edt_survey_pair_rows(C.byref(sv), C.byref(ly), C.byref(n), out.ctypes.data_as(i64p)),
+               "edt_survey_pair_rows")
+    del keep
+    return out
+
+
 class Plan:
     """Rows, classes and work items of one survey, resident on one GPU.
 
     ``survey`` needs: dim, n_mid, d_mid, n_off, d_off, freqs, eps, nz, z0, dz,
     kappa, vel (layer velocities; vel[0] fixes c_top for the evanescent cut)
-    and zif (interface depths).
+    and zif (interface depths).  ``pairs = (begin, end)`` plans only that
+    range of the survey's pairs (a batch); its Green's table is the survey's.
     """
 
-    def __init__(self, survey, chunk_rows: int = 0, gram_band: int = 0, device: str = "cuda"):
+    def __init__(self, survey, chunk_rows: int = 0, gram_band: int = 0, device: str = "cuda",
+                 pairs: tuple[int, int] | None = None):
         L = _lib.load()
         self.device = torch.device(device)
-        self._freq = np.ascontiguousarray(survey.freqs, dtype=np.float64)
-        self._vel = np.ascontiguousarray(survey.vel, dtype=np.float64)
-        self._zif = np.ascontiguousarray(survey.zif, dtype=np.float64)
-        dp = C.POINTER(C.c_double)
-        sv = _lib.Survey(int(survey.dim), int(survey.n_mid), float(survey.d_mid),
-                         int(getattr(survey, "n_off", 0)), float(getattr(survey, "d_off", 0.0)),
-                         int(self._freq.shape[0]), self._freq.ctypes.data_as(dp), float(survey.eps),
-                         int(survey.nz), float(survey.z0), float(survey.dz), float(survey.kappa))
-        ly = _lib.Layers(int(self._vel.shape[0]), self._vel.ctypes.data_as(dp),
-                         self._zif.ctypes.data_as(dp) if self._zif.size else None)
+        sv, ly, self._keep = _structs(survey)
         h = C.c_void_p()
-        opts = _lib.PlanOpts(int(chunk_rows), int(gram_band))
+        pb, pe = (0, 0) if pairs is None else (int(pairs[0]), int(pairs[1]))
+        opts = _lib.PlanOpts(int(chunk_rows), int(gram_band), pb, pe)
         _lib.check(L.edt_plan_create(C.byref(sv), C.byref(ly), C.byref(opts), C.byref(h)),
                    "edt_plan_create")
         self._h = h
@@ -53,6 +75,8 @@ class Plan:
         self.nz = int(survey.nz)
         self.n_km = int(info.n_km)
         self.n_pairs = int(info.n_pairs)
+        self.n_pairs_all = int(info.n_pairs_all)
+        self.pair_begin = int(info.pair_begin)
         self.n_rows = int(info.n_rows)
         self.n_layers = int(info.n_layers)
         self.table_shape = (int(info.n_freq), int(info.n_cls), int(info.nz))
@@ -112,13 +136,21 @@ class Plan:
             pass
 
     # ---------------------------------------------------------- device side --
-    def upload(self):
-        """Copy the plan to the GPU and allocate the workspace (once)."""
+    def upload(self, work=None):
+        """Copy the plan to the GPU and allocate the workspace (once).  ``work``
+        (a uint8 tensor of at least work_bytes) is used instead of a new one:
+        plans that run one after another on a stream can share it."""
         if self._dev_plan is None:
             L = _lib.load()
             nb = int(self.info["dev_plan_bytes"])
             self._dev_plan = torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device)
             _lib.check(L.edt_plan_upload(self._h, _ptr(self._dev_plan), nb, _stream()), "edt_plan_upload")
+        if work is not None:
+            if (work.dtype != torch.uint8 or work.numel() < int(self.info["work_bytes"])
+                    or work.device.type != self.device.type):
+                raise ValueError("shared workspace too small or on another device")
+            self._work = work
+        elif self._work is None:
             self._work = torch.empty(max(int(self.info["work_bytes"]), 256), dtype=torch.uint8,
                                      device=self.device)
         return self

@@ -94,3 +94,23 @@ def test_rows_invariant_under_lattice_rotation_and_cut():
                     elif max(kr, ks) <= km[f] * (1 + 1e-12):
                         pytest.skip("tie at the cut")
         assert cnt == p.n_rows
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_subset_enumeration_lists_the_same_pairs(dim):
+    """plan(s, only=...) lists exactly the chosen pairs of the full
+    enumeration, row for row, with their survey indices."""
+    from edt_inputs import make_custom
+    if dim == 2:
+        s = make_custom(N=40, nz=3, dx=12.5, freqs=(4.0, 9.0, 20.0), vel=(2100.0,), model=None)
+    else:
+        s = make_custom(dim=3, N=16, Nh=8, nz=3, dx=20.0, freqs=(9.0, 21.0), vel=(2000.0,), model=None)
+    full = plan(s)
+    pick = [0, 3, len(full.pairs) - 1]
+    sub = plan(s, only=pick)
+    assert sub.index == pick and full.index == list(range(len(full.pairs)))
+    for i, q in zip(pick, sub.pairs):
+        r = full.pairs[i]
+        assert (q.u, q.u_neg) == (r.u, r.u_neg)
+        for a in ("f", "kr", "ks", "key0", "key1"):
+            assert np.array_equal(getattr(q, a), getattr(r, a))

@@ -44,6 +44,9 @@ SURVEYS = {
                                     vel=(2000.0, 2500.0), zif=(30.0,), model=None),
     "3d-nocut": lambda: make_custom(dim=3, N=8, Nh=4, nz=3, dx=30.0, freqs=(6.0,), kappa=100.0,
                                     model=None),
+    # the largest evanescent disk lies inside the k_m grid (class set known in closed form)
+    "3d-disk-inside": lambda: make_custom(dim=3, N=32, Nh=16, nz=3, dx=20.0, freqs=(5.0, 9.0),
+                                          vel=(2000.0,), model=None),
 }
 
 
@@ -190,7 +193,16 @@ def test_work_items_and_xcd_schedule(name, opts):
         assert band == min(opts["gram_band"], p.table_shape[0])
     assert p.info["chunk_rows"] == opts.get("chunk_rows", 2048)
     _check_items(p, "gram", band, p.info["chunk_rows"])
-    _check_items(p, "resid", 2, 1024)
+    assert p.info["resid_group"] >= 2
+    _check_items(p, "resid", p.info["resid_group"], 1024)
+
+
+def _band_rules(p):
+    n_f, n_cls, nz = p.table_shape
+    l2 = int(2.5e6 // (n_cls * nz * 8))
+    per_pf = p.info["n_urows"] / max(1, (p.n_pairs - p.info["n_empty"]) * n_f)
+    rows = int(np.ceil(256 / per_pf))
+    return l2, rows
 
 
 def test_default_band_fits_l2():
@@ -199,8 +211,24 @@ def test_default_band_fits_l2():
     p = E.Plan(s)
     n_cls, nz = p.table_shape[1], p.table_shape[2]
     band = p.info["gram_band"]
+    l2, rows = _band_rules(p)
+    assert rows <= l2
     # one band's FP32 table slab is at most 2.5 MB and one more frequency would exceed it
     assert band * n_cls * nz * 8 <= 2.5e6 < (band + 1) * n_cls * nz * 8
+
+
+def test_default_band_widens_for_sparse_rows():
+    """3D 128 x 128 survey: one frequency's FP32 slab is near the L2 budget, so
+    the band is set by the rows rule (an average item of 256 unique rows)."""
+    _lib_or_skip()
+    s = make_config(4, with_model=False)
+    p = E.Plan(s)
+    l2, rows = _band_rules(p)
+    assert rows > l2
+    assert p.info["gram_band"] == min(p.table_shape[0], rows)
+    n_f = p.table_shape[0]
+    per_pf = p.info["n_urows"] / max(1, (p.n_pairs - p.info["n_empty"]) * n_f)
+    assert p.info["resid_group"] == min(n_f, max(2, int(np.ceil(64 / per_pf))))
 
 
 @pytest.mark.parametrize("opts", [dict(chunk_rows=2049), dict(chunk_rows=-1), dict(gram_band=-2)])
@@ -230,3 +258,52 @@ def test_rowmap_equals_oracle_full_size_3d():
     assert np.array_equal(m["cls_k"][m["rows"][:, 1]], kr)
     assert np.array_equal(m["cls_k"][m["rows"][:, 2]], ks)
     assert np.array_equal(m["keys"][:, 0], key)
+
+
+@pytest.mark.parametrize("name", ["3d-small", "3d-nocut", "3d-disk-inside"])
+def test_classes_are_exactly_the_used_wavenumbers(name):
+    """The |k| classes are exactly the distinct |k_r|, |k_s| of the oracle's
+    rows over the whole survey, also where they are derived without visiting
+    every pair."""
+    _lib_or_skip()
+    s = SURVEYS[name]()
+    pl = oracle_plan(s)
+    used = np.unique(np.concatenate([np.concatenate([q.kr, q.ks]) for q in pl.pairs if q.n_rows]))
+    for pairs in (None, (0, 1)):
+        cls_k = E.Plan(s, pairs=pairs).rowmap()["cls_k"]
+        assert np.array_equal(np.sort(cls_k), used)
+
+
+@pytest.mark.parametrize("name", ["cfg1", "2d-even-cut", "2d-empty", "3d-small", "3d-disk-inside"])
+def test_pair_range_plans_are_slices_of_the_full_plan(name):
+    """A plan of pairs [a, b) (a batch) holds exactly those pairs' rows, data
+    keys and unique rows of the full plan, with the full survey's |k| classes
+    (so that every batch shares one Green's table)."""
+    _lib_or_skip()
+    s = SURVEYS[name]()
+    full = E.Plan(s)
+    m, u = full.rowmap(), full.urows()
+    P = full.n_pairs
+    cuts = sorted({0, P // 3, P // 3 + 1, P - 1, P})
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        q = E.Plan(s, pairs=(a, b))
+        mq, uq = q.rowmap(), q.urows()
+        assert (q.n_pairs, q.n_pairs_all, q.pair_begin, q.n_km) == (b - a, P, a, full.n_km)
+        assert q.table_shape == full.table_shape
+        assert np.array_equal(mq["cls_k"], m["cls_k"])
+        r0, r1 = m["row_off"][a], m["row_off"][b]
+        assert np.array_equal(mq["row_off"], m["row_off"][a:b + 1] - r0)
+        assert np.array_equal(mq["rows"], m["rows"][r0:r1])
+        assert np.array_equal(mq["keys"], m["keys"][r0:r1])
+        assert np.array_equal(mq["pair_km"], m["pair_km"][a:b])
+        u0, u1 = u["urow_off"][a], u["urow_off"][b]
+        assert np.array_equal(uq["urow_off"], u["urow_off"][a:b + 1] - u0)
+        assert np.array_equal(uq["urows"], u["urows"][u0:u1])
+        assert np.array_equal(uq["row_unique"], u["row_unique"][r0:r1] - u0)
+
+
+@pytest.mark.parametrize("pairs", [(0, 10 ** 6), (3, 2), (-1, 2)])
+def test_invalid_pair_ranges_are_rejected(pairs):
+    _lib_or_skip()
+    with pytest.raises(RuntimeError):
+        E.Plan(SURVEYS["cfg1"](), pairs=pairs)
