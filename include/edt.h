@@ -146,7 +146,7 @@ typedef struct {
 typedef struct {
     int refine;            /* 0: one solve; 1: FP64 refinement (preconditioned CG) */
     double refine_tol;     /* stop when the correction ||z|| <= refine_tol ||x + z|| (per pair) */
-    int max_refine;        /* at most this many refinement sweeps over the rows */
+    int max_refine;        /* at most this many refinement sweeps over the rows (<= 62) */
     int escalate;          /* with refine: pairs whose factorisation fails (info > 0) are
                               re-assembled with the FP64 Gram and factored again */
 } edt_solve_opts;

@@ -12,7 +12,7 @@ namespace edt {
 hipError_t launch_green(const edt_plan* p, const double* vel, zd* g64, float2* g32, hipStream_t st);
 hipError_t launch_gram(const edt_plan* p, edt_precision prec, const zd* g64, const float2* g32,
                        const zd* ubw, const float4* ub32, const float* gmax, void* part, double* rpart,
-                       hipStream_t st, const int32_t* only = nullptr);
+                       hipStream_t st, const int32_t* only = nullptr, const int32_t* gate = nullptr);
 hipError_t launch_gmax(const edt_plan* p, const float2* g32, float* gmax, hipStream_t st);
 hipError_t launch_gram_reduce(const edt_plan* p, edt_precision prec, const void* part, double* gram,
                               hipStream_t st, const int32_t* only = nullptr);
@@ -21,14 +21,16 @@ hipError_t launch_rhs_reduce(const edt_plan* p, const double* rpart, double* rhs
 hipError_t launch_bsum(const edt_plan* p, const zd* d_rows, zd* ub, hipStream_t st, zd* ubw = nullptr,
                        float4* ub32 = nullptr);
 hipError_t launch_resid(const edt_plan* p, const zd* g64, const zd* ubw, const double* x,
-                        const int32_t* conv, double* rpart, hipStream_t st);
+                        const int32_t* conv, double* rpart, hipStream_t st, const int32_t* active);
 hipError_t launch_forward(const edt_plan* p, const zd* g64, const zd* v, zd* d_rows, hipStream_t st);
 hipError_t launch_chol(const edt_plan* p, double* gram, const double* trace, const double* rhs,
                        double lambda_rel, double* lam, double* dinv, double* x, int32_t* info,
-                       int32_t* conv, int32_t* steps, hipStream_t st, int only_failed, int exact);
+                       int32_t* conv, int32_t* steps, hipStream_t st, int only_failed, int exact,
+                       int32_t* n_failed);
 hipError_t launch_pcg_update(const edt_plan* p, const double* gram, const double* dinv, const double* rpart,
                              const double* lam, double* x, double* r, double* pv, double* rho, int32_t* conv,
-                             int32_t* steps, double tol, int first, hipStream_t st);
+                             int32_t* steps, double tol, int first, int32_t* next_active, hipStream_t st);
+hipError_t launch_reset_counters(int32_t* c, int n, hipStream_t st);
 hipError_t launch_recombine(const edt_plan* p, const double* x, int refine, const int32_t* conv,
                             int32_t* info, zd* v, hipStream_t st);
 hipError_t launch_adjoint(const edt_plan* p, const double* vel, const zd* g64, const zd* d_rows,
@@ -223,8 +225,8 @@ edt_status edt_solve(const edt_plan* p, const edt_c128* g64, const edt_c128* d_r
         set_error("lambda_rel must be >= 0");
         return EDT_EINVAL;
     }
-    if (refine && (opts->max_refine < 0 || !(opts->refine_tol > 0.0))) {
-        set_error("refinement needs max_refine >= 0 and refine_tol > 0");
+    if (refine && (opts->max_refine < 0 || opts->max_refine > kMaxRefine || !(opts->refine_tol > 0.0))) {
+        set_error("refinement needs 0 <= max_refine <= " + std::to_string(kMaxRefine) + " and refine_tol > 0");
         return EDT_EINVAL;
     }
     const WorkLayout wl = work_layout(p);
@@ -233,7 +235,12 @@ edt_status edt_solve(const edt_plan* p, const edt_c128* g64, const edt_c128* d_r
     int32_t* conv = reinterpret_cast<int32_t*>(w + wl.conv);
     int32_t* stp = steps ? steps : reinterpret_cast<int32_t*>(w + wl.aux);
     double* dinv = reinterpret_cast<double*>(w + wl.dinv);
-    EDT_TRY(launch_chol(p, gram, trace, rhs, lambda_rel, lam, dinv, x, info, conv, stp, stream, 0, !refine),
+    // counters: pairs iterating before each sweep, then the failed factorisations
+    int32_t* cnt = reinterpret_cast<int32_t*>(w + wl.counters);
+    int32_t* n_failed = cnt + kMaxRefine + 1;
+    if (refine) EDT_TRY(launch_reset_counters(cnt, kMaxRefine + 2, stream), "reset counters");
+    EDT_TRY(launch_chol(p, gram, trace, rhs, lambda_rel, lam, dinv, x, info, conv, stp, stream, 0, !refine,
+                        refine ? n_failed : nullptr),
             "cholesky");
     if (refine) {
         zd* ub = reinterpret_cast<zd*>(w + wl.ub);
@@ -251,11 +258,11 @@ edt_status edt_solve(const edt_plan* p, const edt_c128* g64, const edt_c128* d_r
             double* etr = reinterpret_cast<double*>(w + wl.esc_trace);
             double* gpart = reinterpret_cast<double*>(w + wl.gram_rpart);
             EDT_TRY(launch_gram(p, EDT_FP64, G64, nullptr, ubw, nullptr, nullptr, w + wl.gram_part, gpart, stream,
-                                info),
+                                info, n_failed),
                     "escalate gram_fp64");
             EDT_TRY(launch_gram_reduce(p, EDT_FP64, w + wl.gram_part, gram, stream, info), "escalate gram_reduce");
             EDT_TRY(launch_rhs_reduce(p, gpart, erhs, etr, stream, info), "escalate rhs reduce");
-            EDT_TRY(launch_chol(p, gram, etr, erhs, lambda_rel, lam, dinv, x, info, conv, stp, stream, 1, 0),
+            EDT_TRY(launch_chol(p, gram, etr, erhs, lambda_rel, lam, dinv, x, info, conv, stp, stream, 1, 0, nullptr),
                     "escalate cholesky");
         }
         double* r = reinterpret_cast<double*>(w + wl.pcg_r);
@@ -264,10 +271,10 @@ edt_status edt_solve(const edt_plan* p, const edt_c128* g64, const edt_c128* d_r
         // sweep 0: the data residual at x0; then one operator sweep per step
         for (int it = 0; it < opts->max_refine; ++it) {
             EDT_TRY(launch_resid(p, G64, it == 0 ? ubw : nullptr, it == 0 ? x : pv,
-                                 conv, rpart, stream),
+                                 conv, rpart, stream, cnt + it),
                     "refine residual");
             EDT_TRY(launch_pcg_update(p, gram, dinv, rpart, lam, x, r, pv, rho, conv, stp, opts->refine_tol,
-                                      it == 0, stream),
+                                      it == 0, cnt + it + 1, stream),
                     "refine update");
         }
     }

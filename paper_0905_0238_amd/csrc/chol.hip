@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256, Q > 4 ? 1 : 2) void chol_solve_kernel(
     const int64_t* __restrict__ urow_off, const int32_t* __restrict__ pair_u, int nz,
     double lambda_rel, double* __restrict__ lam_out, double* __restrict__ dinv, double* __restrict__ x,
     int32_t* __restrict__ info, int32_t* __restrict__ conv, int32_t* __restrict__ steps, int only_failed,
-    int exact) {
+    int exact, int32_t* __restrict__ n_failed) {
     extern __shared__ double smem[];
     double* sP = smem;
     double* sD = smem + size_t(nz) * CBP;
@@ -266,6 +266,7 @@ __global__ __launch_bounds__(256, Q > 4 ? 1 : 2) void chol_solve_kernel(
     if (tid == 0) {
         info[p] = s_bad;
         conv[p] = 0;
+        if (s_bad != 0 && n_failed) atomicAdd(n_failed, 1);
     }
 }
 
@@ -284,11 +285,13 @@ __global__ __launch_bounds__(256, Q > 4 ? 1 : 2) void chol_solve_kernel(
 //   first: rpart holds c - Re(A^H A) x (swept with the data): r = it - lambda x;
 //   else:  rpart holds -Re(A^H A) p: q = lambda p - it.
 // conv: 0 running, 1 converged, -1 stopped (p.q <= 0 or not finite).
+// next_active counts the pairs that need the next sweep.
 __global__ __launch_bounds__(256) void pcg_update_kernel(
     const double* __restrict__ gram, const double* __restrict__ dinv, const double* __restrict__ rpart,
     const int32_t* __restrict__ pair_item, const int32_t* __restrict__ pair_u, int nz,
     const double* __restrict__ lam, double* __restrict__ x, double* __restrict__ r, double* __restrict__ pv,
-    double* __restrict__ rho, int32_t* __restrict__ conv, int32_t* __restrict__ steps, double tol, int first) {
+    double* __restrict__ rho, int32_t* __restrict__ conv, int32_t* __restrict__ steps, double tol, int first,
+    int32_t* __restrict__ next_active) {
     extern __shared__ double smem[];
     double* sx = smem;
     double* sq = sx + 2 * nz;
@@ -365,9 +368,20 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(
     __syncthreads();
     if (tid == 0) {
         steps[p] += 1;
-        if (done) conv[p] = 1;
-        else rho[p] = rz;
+        if (done) {
+            conv[p] = 1;
+        } else {
+            rho[p] = rz;
+            atomicAdd(next_active, 1);   // this pair needs the next sweep
+        }
     }
+}
+
+// Counters of one solve: active[0] = 1 (every pair takes the first sweep),
+// active[1..] = 0 (pairs still iterating before each later sweep, counted by
+// pcg_update_kernel), and the failed-factorisation count.
+__global__ void reset_counters_kernel(int32_t* __restrict__ c, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) c[i] = i == 0 ? 1 : 0;
 }
 
 // V~(u) = x+ + i x-, V~(-u) = x+ - i x-; info NOCONV / NONFINITE.
@@ -430,27 +444,33 @@ hipError_t configure_kernels() {
 
 hipError_t launch_chol(const edt_plan* p, double* gram, const double* trace, const double* rhs,
                        double lambda_rel, double* lam, double* dinv, double* x, int32_t* info,
-                       int32_t* conv, int32_t* steps, hipStream_t st, int only_failed, int exact) {
+                       int32_t* conv, int32_t* steps, hipStream_t st, int only_failed, int exact,
+                       int32_t* n_failed) {
     if (p->n_pairs == 0) return hipSuccess;
     const size_t lds = chol_lds_bytes(p->nz);
     if (p->nz <= 256)
         hipLaunchKernelGGL(chol_solve_kernel<4>, dim3(unsigned(p->n_pairs)), dim3(256), lds, st, gram, trace,
                            rhs, dptr<const int64_t>(p, p->lay.urow_off), dptr<const int32_t>(p, p->lay.pair_u),
-                           p->nz, lambda_rel, lam, dinv, x, info, conv, steps, only_failed, exact);
+                           p->nz, lambda_rel, lam, dinv, x, info, conv, steps, only_failed, exact, n_failed);
     else
         hipLaunchKernelGGL(chol_solve_kernel<7>, dim3(unsigned(p->n_pairs)), dim3(256), lds, st, gram, trace,
                            rhs, dptr<const int64_t>(p, p->lay.urow_off), dptr<const int32_t>(p, p->lay.pair_u),
-                           p->nz, lambda_rel, lam, dinv, x, info, conv, steps, only_failed, exact);
+                           p->nz, lambda_rel, lam, dinv, x, info, conv, steps, only_failed, exact, n_failed);
     return hipGetLastError();
 }
 
 hipError_t launch_pcg_update(const edt_plan* p, const double* gram, const double* dinv, const double* rpart,
                              const double* lam, double* x, double* r, double* pv, double* rho, int32_t* conv,
-                             int32_t* steps, double tol, int first, hipStream_t st) {
+                             int32_t* steps, double tol, int first, int32_t* next_active, hipStream_t st) {
     if (p->n_pairs == 0) return hipSuccess;
     hipLaunchKernelGGL(pcg_update_kernel, dim3(unsigned(p->n_pairs)), dim3(256), pcg_lds_bytes(p->nz), st, gram,
                        dinv, rpart, dptr<const int32_t>(p, p->lay.pair_ritem), dptr<const int32_t>(p, p->lay.pair_u),
-                       p->nz, lam, x, r, pv, rho, conv, steps, tol, first);
+                       p->nz, lam, x, r, pv, rho, conv, steps, tol, first, next_active);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_counters(int32_t* c, int n, hipStream_t st) {
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, st, c, n);
     return hipGetLastError();
 }
 

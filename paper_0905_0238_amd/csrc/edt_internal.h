@@ -39,6 +39,8 @@ constexpr int kSuperDepth = 256;
 // groups, LDS), and the adjoint's table kernel (4 depths per lane).
 constexpr int kMaxDepth = 448;
 constexpr int kMaxAdjointDepth = 256;
+// Refinement sweeps of one solve at most (device counters per sweep).
+constexpr int kMaxRefine = 62;
 constexpr int n_super(int nz) { return (nz + kSuperDepth - 1) / kSuperDepth; }
 constexpr int rpart_width(int nz) { return 2 * nz + n_super(nz); }
 
@@ -126,6 +128,7 @@ struct WorkLayout {
     size_t pcg_rho;     // [P] FP64 r.z of the refinement
     size_t esc_rhs;     // [P][2][nz] FP64 rhs of re-assembled (escalated) pairs
     size_t esc_trace;   // [P] FP64 trace of re-assembled pairs
+    size_t counters;    // [kMaxRefine + 2] int32: pairs iterating before each sweep, failed factorisations
     size_t aux;         // [P][2][nz] FP64 scratch (refinement, adjoint)
     size_t aux2;        // [P][2][nz] FP64 scratch
     size_t gbar;        // [n_freq][n_cls][nz] complex128 (adjoint table gradient)

@@ -21,6 +21,7 @@
 //   FP32:   v_mfma_f32_32x32x2_f32;
 //   FP64:   v_mfma_f64_16x16x4_f64 on FP64 rows built from the FP64 table.
 
+#include <cstdlib>
 #include <type_traits>
 
 #include "dev_common.h"
@@ -47,26 +48,20 @@ __host__ __device__ constexpr uint32_t block_mask(int t0, int t1) {
     return m;
 }
 
-__device__ __forceinline__ uint32_t pack_bf16x2(__bf16 a, __bf16 b) {
-    const uint16_t ua = __builtin_bit_cast(uint16_t, a), ub = __builtin_bit_cast(uint16_t, b);
-    return uint32_t(ua) | (uint32_t(ub) << 16);
-}
-
-// Split x = hi + lo into two 16-bit values (F16: IEEE half, else bfloat16)
-// and pack (x0, x1) halves as (hi0 | hi1 << 16), (lo0 | lo1 << 16).
+// Split x = hi + lo into two 16-bit values (F16: IEEE half, else bfloat16),
+// each rounded to nearest, and pack (x0, x1) halves as (hi0 | hi1 << 16),
+// (lo0 | lo1 << 16).  On gfx950 the pair conversions are single packed
+// instructions and x - hi folds into a mixed-precision FMA.
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 template <bool F16>
 __device__ __forceinline__ void split_pack(float x0, float x1, uint32_t& hi, uint32_t& lo) {
-    if constexpr (F16) {
-        const _Float16 h0 = _Float16(x0), h1 = _Float16(x1);
-        const _Float16 l0 = _Float16(x0 - float(h0)), l1 = _Float16(x1 - float(h1));
-        hi = uint32_t(__builtin_bit_cast(uint16_t, h0)) | (uint32_t(__builtin_bit_cast(uint16_t, h1)) << 16);
-        lo = uint32_t(__builtin_bit_cast(uint16_t, l0)) | (uint32_t(__builtin_bit_cast(uint16_t, l1)) << 16);
-    } else {
-        const __bf16 h0 = __bf16(x0), h1 = __bf16(x1);
-        const __bf16 l0 = __bf16(x0 - float(h0)), l1 = __bf16(x1 - float(h1));
-        hi = pack_bf16x2(h0, h1);
-        lo = pack_bf16x2(l0, l1);
-    }
+    typedef typename std::conditional<F16, f16x2, bf16x2>::type v2;
+    const v2 h = __builtin_convertvector(f32x2{x0, x1}, v2);
+    const f32x2 r = {x0 - float(h[0]), x1 - float(h[1])};
+    hi = __builtin_bit_cast(uint32_t, h);
+    lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, v2));
 }
 
 // ------------------------------------------------------- split (16-bit) ---
@@ -161,7 +156,9 @@ __device__ __forceinline__ void f32_store_tiles(const f32x16 (&acc)[C::TPW], flo
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                o[i * 32 + (lane & 31)] = acc[m][v] * scale;
+                // streaming store: the partials are read once, by the reduce,
+                // and must not evict the Green's table slab from L2
+                __builtin_nontemporal_store(acc[m][v] * scale, &o[i * 32 + (lane & 31)]);
             }
         }
     }
@@ -189,6 +186,10 @@ __device__ __forceinline__ void stage_rows(uint4* s_row, const GRow* __restrict_
     }
 }
 
+// Zero stages a split kernel may append to an item (its load pipeline depth
+// at most, plus one).
+constexpr int kPadStages = 4;
+
 // Producer side of the split kernels: raw table values of one stage (8
 // complex rows) at one depth.
 struct RawStage {
@@ -201,9 +202,10 @@ struct RawStage {
 // FP32: about 16 significant bits per product with bfloat16 halves, about 22
 // with IEEE halves (which need the per-item scaling below).
 // Warp-specialised: waves 0-3 consume 16-bit stages from LDS into MFMA, waves
-// 4-7 produce them.  A producer issues the table loads of stage s+2 while it
-// forms stage s+1 (loaded one iteration earlier), so each load has about two
-// MFMA stages to arrive.  A producer thread owns one depth of the I set (and
+// 4-7 produce them.  A producer issues the table loads of stage s+PF while it
+// forms stage s+1, so each load has PF-1 MFMA stages to arrive (PF = 3 for a
+// diagonal task, 2 for a rectangular one, whose two depth sets double the
+// registers per stage).  A producer thread owns one depth of the I set (and
 // one of the J set) and all 8 rows of a stage, so it writes its 16 hi and 16
 // lo values as 16-byte stores; with the 48-byte LDS row pitch any 8
 // consecutive depths hit distinct bank groups.  Row records come from LDS
@@ -224,6 +226,9 @@ __global__ __launch_bounds__(512, 1) void gram_split3_kernel(const Item* __restr
                                                              float* __restrict__ part,
                                                              double* __restrict__ rpart, int max_rows) {
     using C = SplitCfg<NT, NTJ>;
+    // stages of table loads in flight per producer (register sets of raw values)
+    constexpr int PF = 2;
+    static_assert(PF + 1 <= kPadStages, "padding stages exceed the row LDS");
     __shared__ __attribute__((aligned(16))) uint16_t sh[2][2][C::NZP * C::STR];
     __shared__ double s_tr[4];
     __shared__ float s_max[8];
@@ -234,8 +239,12 @@ __global__ __launch_bounds__(512, 1) void gram_split3_kernel(const Item* __restr
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int n = min(it.row_end - it.row_begin, max_rows);
     const int nst = (n + 7) >> 3;
+    // stages padded with at least one all-zero stage to a multiple of PF: the
+    // producer pipeline below then runs without branches (a branch around the
+    // loads would make the compiler wait for every load in flight at the join)
+    const int nsp = ((nst + 1 + PF - 1) / PF) * PF;
     const int nzI = min(C::NZPI, nz - zI0);   // valid depths of the I set
-    stage_rows(s_row, grow, ub32, it.row_begin, n, nst, tid, 512);
+    stage_rows(s_row, grow, ub32, it.row_begin, n, nsp, tid, 512);
     // FP16: the rows of the item are scaled by a power of two s so that the
     // largest |value| is near 2^14 (inside the half range, above its
     // subnormals); the partial Gram is scaled back by 1/s^2 (exact).  The
@@ -328,19 +337,24 @@ __global__ __launch_bounds__(512, 1) void gram_split3_kernel(const Item* __restr
             form(R[0], buf, s, pid, !C::RECT, onI);
             if constexpr (C::RECT) form(R[1], buf, s, C::NZPI + pid, false, onJ);
         };
-        RawStage R0[2], R1[2];   // stage k lives in R(k & 1); [0] I set, [1] J set
-        load_stage(R0, 0);
-        if (nst > 1) load_stage(R1, 1);
-        form_stage(R0, 0, 0);
+        // Stage k's raw values live in R[k % PF] ([0] I set, [1] J set): the
+        // loads of stage t + PF are issued while stage t + 1 is formed, so
+        // each load has PF - 1 stage periods to arrive.
+        // Stage indices past the padded end are clamped to its last (zero)
+        // stage: the extra loads read valid entries, and the extra form writes
+        // a buffer nobody consumes and adds zeros to the sums.
+        RawStage R[PF][2];
+#pragma unroll
+        for (int q = 0; q < PF; ++q) load_stage(R[q], q);
+        form_stage(R[0], 0, 0);
         __syncthreads();
-        // iteration s: stage s is being consumed from buffer s&1
-        for (int s = 0; s < nst; s += 2) {
-            if (s + 2 < nst) load_stage(R0, s + 2);
-            if (s + 1 < nst) form_stage(R1, 1, s + 1);
-            __syncthreads();
-            if (s + 1 < nst) {
-                if (s + 3 < nst) load_stage(R1, s + 3);
-                if (s + 2 < nst) form_stage(R0, 0, s + 2);
+        // part t: stage t is being consumed from buffer t & 1
+        for (int s = 0; s < nsp; s += PF) {
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                const int t = s + q;
+                load_stage(R[q], min(t + PF, nsp - 1));
+                form_stage(R[(q + 1) % PF], (t + 1) & 1, min(t + 1, nsp - 1));
                 __syncthreads();
             }
         }
@@ -368,13 +382,9 @@ __global__ __launch_bounds__(512, 1) void gram_split3_kernel(const Item* __restr
             else split3_wave_mfma<C, 3, F16>(acc, hi, lo, lane);
         };
         __syncthreads();
-        for (int s = 0; s < nst; s += 2) {
-            compute(0);
+        for (int t = 0; t < nsp; ++t) {
+            if (t < nst) compute(t & 1);   // padding stages are zero
             __syncthreads();
-            if (s + 1 < nst) {
-                compute(1);
-                __syncthreads();
-            }
         }
         float* out = part + size_t(it.slot) * (ntot * (ntot + 1) / 2) * 1024;
         const float back = 1.0f / (scale * scale);
@@ -390,6 +400,250 @@ __global__ __launch_bounds__(512, 1) void gram_split3_kernel(const Item* __restr
             rpart[size_t(it.slot) * rpart_width(nz) + 2 * nz + zI0 / kSuperDepth] =
                 (s_tr[0] + s_tr[1]) + (s_tr[2] + s_tr[3]);
     }
+}
+
+// ------------------------------------------- split, diagonal, unified ---
+// The diagonal split task again, with every wave both forming rows and
+// issuing MFMA: a wave's MFMAs on stage t (from LDS) are independent of its
+// VALU work forming stage t+1, so the two overlap inside the wave, and the
+// two waves of a SIMD cover each other's memory waits.
+// Tiles: the lower triangle in row-major order is cut into four SIMD groups
+// of G consecutive tiles; waves s and s+4 (one SIMD) take the first TA and
+// the remaining G-TA tiles of group s.
+template <int NT>
+struct UCfg {
+    static constexpr int NTL = NT * (NT + 1) / 2;
+    static constexpr int G = (NTL + 3) / 4;
+    static constexpr int TA = (G + 1) / 2;
+    static constexpr int TPW = TA;
+    static constexpr int STR = 24;   // 16-bit values per LDS depth row (16 real rows + 8 pad)
+    static constexpr int NZP = 32 * NT;
+    __host__ __device__ static constexpr int t0(int w) {
+        return w < 4 ? (w * G < NTL ? w * G : NTL) : ((w - 4) * G + TA < NTL ? (w - 4) * G + TA : NTL);
+    }
+    __host__ __device__ static constexpr int t1(int w) {
+        return w < 4 ? (w * G + TA < NTL ? w * G + TA : NTL) : ((w - 3) * G < NTL ? (w - 3) * G : NTL);
+    }
+};
+
+template <int NT, int W, bool F16>
+__device__ __forceinline__ void u_wave_mfma(f32x16 (&acc)[UCfg<NT>::TPW], const uint16_t* hi,
+                                            const uint16_t* lo, int lane) {
+    using C = UCfg<NT>;
+    typedef typename std::conditional<F16, f16x8, bf16x8>::type v8;
+    constexpr int t0 = C::t0(W), t1 = C::t1(W);
+    constexpr uint32_t need = t0 < t1 ? block_mask(t0, t1) : 0u;
+    v8 fh[NT], fl[NT];
+    const int roff = (lane & 31) * C::STR + (lane >> 5) * 8;
+#pragma unroll
+    for (int b = 0; b < NT; ++b) {
+        if (need & (1u << b)) {
+            fh[b] = *reinterpret_cast<const v8*>(hi + b * 32 * C::STR + roff);
+            fl[b] = *reinterpret_cast<const v8*>(lo + b * 32 * C::STR + roff);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < C::TPW; ++m) {
+        const int t = t0 + m;
+        if (t < t1) {
+            const int I = tri_I(t), J = tri_J(t);
+            if constexpr (F16) {
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fh[I], fh[J], acc[m], 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fh[I], fl[J], acc[m], 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fl[I], fh[J], acc[m], 0, 0, 0);
+            } else {
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh[I], fh[J], acc[m], 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh[I], fl[J], acc[m], 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fl[I], fh[J], acc[m], 0, 0, 0);
+            }
+        }
+    }
+}
+
+template <int NT, int W>
+__device__ __forceinline__ void u_store_tiles(const f32x16 (&acc)[UCfg<NT>::TPW], float* out, int lane,
+                                              float scale, int bI0) {
+    using C = UCfg<NT>;
+    constexpr int t0 = C::t0(W), t1 = C::t1(W);
+#pragma unroll
+    for (int m = 0; m < C::TPW; ++m) {
+        const int t = t0 + m;
+        if (t < t1) {
+            const int Ig = bI0 + tri_I(t), Jg = bI0 + tri_J(t);
+            float* o = out + size_t(Ig * (Ig + 1) / 2 + Jg) * 1024;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                __builtin_nontemporal_store(acc[m][v] * scale, &o[i * 32 + (lane & 31)]);
+            }
+        }
+    }
+}
+
+// raw table values of half a stage (4 complex rows) at one depth
+struct RawHalf {
+    float2 ga[4], gb[4];
+};
+
+// Diagonal split task (one super-block of NT <= 8 tiles from depth zI0):
+// thread t forms depth t % 256 of rows 4 (t / 256) .. +3 of every stage, so
+// a wave's row is uniform (its records are LDS broadcasts and its table base
+// a scalar); results as gram_split3_kernel<NT, 0, F16>.
+template <int NT, bool F16>
+__global__ __launch_bounds__(512, 1) void gram_split3u_kernel(const Item* __restrict__ items,
+                                                              const int32_t* __restrict__ sched,
+                                                              const GRow* __restrict__ grow,
+                                                              const float4* __restrict__ ub32,
+                                                              const float2* __restrict__ g32,
+                                                              const float* __restrict__ gmax, int nz, int zI0,
+                                                              int ntot, float* __restrict__ part,
+                                                              double* __restrict__ rpart, int max_rows) {
+    using C = UCfg<NT>;
+    constexpr int PF = 2;
+    static_assert(PF + 1 <= kPadStages, "padding stages exceed the row LDS");
+    __shared__ __attribute__((aligned(16))) uint16_t sh[2][2][C::NZP * C::STR];
+    __shared__ double s_tr[8];
+    __shared__ float s_max[8];
+    extern __shared__ __attribute__((aligned(16))) uint4 s_row[];
+    const int32_t k = sched[blockIdx.x];
+    if (k < 0) return;   // hole in the XCD-aware schedule
+    const Item it = items[k];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int n = min(it.row_end - it.row_begin, max_rows);
+    const int nst = (n + 7) >> 3;
+    const int nsp = ((nst + 1 + PF - 1) / PF) * PF;   // + zero stages, a multiple of PF
+    const int nzI = min(C::NZP, nz - zI0);
+    stage_rows(s_row, grow, ub32, it.row_begin, n, nsp, tid, 512);
+    float scale = 1.0f;
+    if constexpr (F16) {
+        float mx = 0.0f;
+        for (int e = tid; e < n; e += 512) {
+            const GRow g = grow[it.row_begin + e];
+            mx = fmaxf(mx, gmax[g.off_r / uint32_t(nz)] * gmax[g.off_s / uint32_t(nz)] * g.sw);
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+        if (lane == 0) s_max[wv] = mx;
+        __syncthreads();
+        float m = s_max[0];
+#pragma unroll
+        for (int w = 1; w < 8; ++w) m = fmaxf(m, s_max[w]);
+        if (m > 0.0f && isfinite(m)) scale = ldexpf(1.0f, 14 - ilogbf(m) - 1);
+    }
+    const int z = tid & 255;
+    const int hf = __builtin_amdgcn_readfirstlane(tid >> 8);   // rows 4 hf .. 4 hf + 3 of a stage
+    const bool on = z < nzI;
+    // unsigned: the table loads take a scalar base and a 32-bit lane offset
+    const uint32_t zc = uint32_t(zI0 + min(z, nzI - 1));
+    if (z >= nzI && z < C::NZP) {   // depths past nz stay zero for the whole item
+        const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) reinterpret_cast<uint4*>(sh[b][h] + z * C::STR)[hf] = zero;
+    }
+    float cp = 0.0f, cm = 0.0f;
+    double tr = 0.0;
+    const uint32_t zoff = zc * uint32_t(sizeof(float2));   // byte offset of this lane's depth
+    auto load = [&](RawHalf& R, int s) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint4 a = s_row[2 * (8 * s + 4 * hf + j)];
+            const uint32_t o_r = __builtin_amdgcn_readfirstlane(a.x);
+            const uint32_t o_s = __builtin_amdgcn_readfirstlane(a.y);
+            R.ga[j] = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(g32 + o_r) + zoff);
+            R.gb[j] = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(g32 + o_s) + zoff);
+        }
+    };
+    auto form = [&](const RawHalf& R, int buf, int s) {
+        uint32_t h[4], l[4];
+        float t = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint4 a = s_row[2 * (8 * s + 4 * hf + j)];
+            const uint4 b = s_row[2 * (8 * s + 4 * hf + j) + 1];
+            const float sw = __uint_as_float(a.z), mt = __uint_as_float(a.w);
+            const float px = R.ga[j].x * R.gb[j].x - R.ga[j].y * R.gb[j].y;
+            const float py = R.ga[j].x * R.gb[j].y + R.ga[j].y * R.gb[j].x;
+            cp += px * __uint_as_float(b.x) + py * __uint_as_float(b.y);
+            cm += px * __uint_as_float(b.z) + py * __uint_as_float(b.w);
+            t += mt * (px * px + py * py);
+            const float ss = F16 ? sw * scale : sw;
+            split_pack<F16>(ss * px, ss * py, h[j], l[j]);
+        }
+        tr += double(t);
+        if (on) {
+            reinterpret_cast<uint4*>(sh[buf][0] + z * C::STR)[hf] = make_uint4(h[0], h[1], h[2], h[3]);
+            reinterpret_cast<uint4*>(sh[buf][1] + z * C::STR)[hf] = make_uint4(l[0], l[1], l[2], l[3]);
+        }
+    };
+    f32x16 acc[C::TPW];
+#pragma unroll
+    for (int m = 0; m < C::TPW; ++m)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[m][v] = 0.0f;
+    auto compute = [&](int buf) {
+        const uint16_t* hi = sh[buf][0];
+        const uint16_t* lo = sh[buf][1];
+        switch (wv) {
+            case 0: u_wave_mfma<NT, 0, F16>(acc, hi, lo, lane); break;
+            case 1: u_wave_mfma<NT, 1, F16>(acc, hi, lo, lane); break;
+            case 2: u_wave_mfma<NT, 2, F16>(acc, hi, lo, lane); break;
+            case 3: u_wave_mfma<NT, 3, F16>(acc, hi, lo, lane); break;
+            case 4: u_wave_mfma<NT, 4, F16>(acc, hi, lo, lane); break;
+            case 5: u_wave_mfma<NT, 5, F16>(acc, hi, lo, lane); break;
+            case 6: u_wave_mfma<NT, 6, F16>(acc, hi, lo, lane); break;
+            default: u_wave_mfma<NT, 7, F16>(acc, hi, lo, lane); break;
+        }
+    };
+    // stage k's raw values live in R[k % PF]; indices past the padded end are
+    // clamped to its last (zero) stage
+    RawHalf R[PF];
+    __syncthreads();   // rows staged, padding depths zeroed
+#pragma unroll
+    for (int q = 0; q < PF; ++q) load(R[q], q);
+    form(R[0], 0, 0);
+    __syncthreads();
+    for (int s = 0; s < nsp; s += PF) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int t = s + q;
+            compute(t & 1);
+            load(R[q], min(t + PF, nsp - 1));
+            form(R[(q + 1) % PF], (t + 1) & 1, min(t + 1, nsp - 1));
+            __syncthreads();
+        }
+    }
+    float* out = part + size_t(it.slot) * (ntot * (ntot + 1) / 2) * 1024;
+    const float back = 1.0f / (scale * scale);
+    const int bI0 = zI0 / 32;
+    switch (wv) {
+        case 0: u_store_tiles<NT, 0>(acc, out, lane, back, bI0); break;
+        case 1: u_store_tiles<NT, 1>(acc, out, lane, back, bI0); break;
+        case 2: u_store_tiles<NT, 2>(acc, out, lane, back, bI0); break;
+        case 3: u_store_tiles<NT, 3>(acc, out, lane, back, bI0); break;
+        case 4: u_store_tiles<NT, 4>(acc, out, lane, back, bI0); break;
+        case 5: u_store_tiles<NT, 5>(acc, out, lane, back, bI0); break;
+        case 6: u_store_tiles<NT, 6>(acc, out, lane, back, bI0); break;
+        default: u_store_tiles<NT, 7>(acc, out, lane, back, bI0); break;
+    }
+    // the two row halves of depth z meet in LDS (the stage buffers are free)
+    float* sc = reinterpret_cast<float*>(&sh[0][0][0]);
+    if (hf == 1) {
+        sc[z] = cp;
+        sc[256 + z] = cm;
+    }
+    const double t = wave_sum(on ? tr : 0.0);
+    if (lane == 0) s_tr[wv] = t;
+    __syncthreads();
+    double* rp = rpart + size_t(it.slot) * rpart_width(nz);
+    if (hf == 0 && on) {
+        rp[zI0 + z] = double(cp) + double(sc[z]);
+        rp[nz + zI0 + z] = double(cm) + double(sc[256 + z]);
+    }
+    if (tid == 0)
+        rp[2 * nz + zI0 / kSuperDepth] =
+            ((s_tr[0] + s_tr[1]) + (s_tr[2] + s_tr[3])) + ((s_tr[4] + s_tr[5]) + (s_tr[6] + s_tr[7]));
 }
 
 // ------------------------------------------------------------------ FP32 ---
@@ -614,13 +868,16 @@ __device__ __forceinline__ void f64_store_tiles(const f64x4 (&acc)[C::TPW], doub
             for (int v = 0; v < 4; ++v) {
                 // v_mfma_f64_16x16x4: lane l, register v holds row 4 v + l/16, column l%16
                 const int i = 4 * v + (lane >> 4);
-                o[i * 32 + (lane & 15)] = acc[m][v];
+                __builtin_nontemporal_store(acc[m][v], &o[i * 32 + (lane & 15)]);
             }
         }
     }
 }
 
-// only: when set, items of pairs p with only[p] <= 0 are skipped.
+// only: when set, items of pairs p with only[p] <= 0 are skipped; gate: when
+// set and zero, the launch does nothing.  With fewer blocks than schedule
+// entries the blocks loop over the schedule (a multiple of 8 blocks keeps
+// every entry on its XCD).
 // Thread t owns depth z = t % 256 of the I set (and of the J set) and the rows
 // j = t / 256 + 2 i (i < 4) of each stage (the row is uniform across a wave,
 // so its data come through scalar loads).  A diagonal task also yields the
@@ -635,14 +892,18 @@ __global__ __launch_bounds__(512, 1) void gram_f64_kernel(const Item* __restrict
                                                           const zd* __restrict__ g64, int nz, int zI0,
                                                           int zJ0, int ntot, double* __restrict__ part,
                                                           double* __restrict__ rpart,
-                                                          const int32_t* __restrict__ only) {
+                                                          const int32_t* __restrict__ only, int nsched,
+                                                          const int32_t* __restrict__ gate) {
     using C = F64Cfg<NT, NTJ>;
     __shared__ __attribute__((aligned(16))) double sh[2][16 * C::NZP];
     __shared__ double s_tr[8];
-    const int32_t k = sched[blockIdx.x];
-    if (k < 0) return;   // hole in the XCD-aware schedule
+    if (gate && *gate == 0) return;   // nothing selected: one load
+    // block b takes schedule entries b, b + G, ... (one each when G = nsched)
+    for (int ks = blockIdx.x; ks < nsched; ks += gridDim.x) {
+    const int32_t k = sched[ks];
+    if (k < 0) continue;   // hole in the XCD-aware schedule
     const Item it = items[k];
-    if (only && only[it.pair] <= 0) return;   // pair not selected
+    if (only && only[it.pair] <= 0) continue;   // pair not selected
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int n = it.row_end - it.row_begin;
     const int nst = (n + 7) >> 3;
@@ -763,6 +1024,8 @@ __global__ __launch_bounds__(512, 1) void gram_f64_kernel(const Item* __restrict
             rp[2 * nz + zI0 / kSuperDepth] =
                 ((s_tr[0] + s_tr[1]) + (s_tr[2] + s_tr[3])) + ((s_tr[4] + s_tr[5]) + (s_tr[6] + s_tr[7]));
     }
+    __syncthreads();   // LDS is reused by the next entry
+    }
 }
 
 // ---------------------------------------------------------------- reduce ---
@@ -785,9 +1048,17 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const T* __restrict__ 
         const int i = e >> 5, j = e & 31;
         const int zi = 32 * I + i, zj = 32 * J + j;
         if (zi >= nz || zj > zi) continue;
-        double s = 0.0;
-        for (int k = k0; k < k1; ++k) s += double(part[(size_t(k) * ntl + t) * 1024 + e]);
-        G[size_t(zi) * nz + zj] = s;
+        // eight independent partial sums keep eight loads in flight; the
+        // combination order is fixed (deterministic)
+        const T* src = part + size_t(t) * 1024 + e;
+        const size_t stride = size_t(ntl) * 1024;
+        double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int k = k0;
+        for (; k + 8 <= k1; k += 8)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s8[q] += double(__builtin_nontemporal_load(src + size_t(k + q) * stride));
+        for (int q = 0; k < k1; ++k, ++q) s8[q] += double(__builtin_nontemporal_load(src + size_t(k) * stride));
+        G[size_t(zi) * nz + zj] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
     }
 }
 
@@ -841,9 +1112,10 @@ __global__ __launch_bounds__(256) void gmax_kernel(const float2* __restrict__ g3
 }
 
 // ------------------------------------------------------------- launchers ---
-// dynamic LDS of the FP32 / BF16x3 kernels: the row records of an item,
-// padded to a multiple of 8 rows, 32 bytes each
-size_t row_lds_bytes(int64_t chunk_rows) { return size_t((chunk_rows + 7) / 8) * 8 * 32; }
+// dynamic LDS of the FP32 / split kernels: the row records of an item,
+// padded to a multiple of 8 rows plus the split kernels' padding stages, 32
+// bytes each
+size_t row_lds_bytes(int64_t chunk_rows) { return size_t((chunk_rows + 7) / 8 + kPadStages) * 8 * 32; }
 
 // Row data the Gram kernels read besides the tables (formed by bsum_kernel).
 struct GramRowData {
@@ -851,7 +1123,15 @@ struct GramRowData {
     const float4* ub32;   // FP32 / split: conj(W)/|W| (b+, b-)
     const float* gmax;    // FP16x3: max_z |g32| per table column
     const int32_t* only;  // FP64: when set, only the pairs with only[p] > 0
+    const int32_t* gate;  // FP64: when set and zero, nothing to do
 };
+
+// Diagonal split tasks run the unified kernel unless EDT_SPLIT_SPECIALISED is
+// set in the environment (the warp-specialised kernel, kept for comparison).
+static bool split_unified() {
+    static const bool u = std::getenv("EDT_SPLIT_SPECIALISED") == nullptr;
+    return u;
+}
 
 // One Gram task kind (diagonal NTJ = 0 or rectangular) over every item.
 template <int NT, int NTJ>
@@ -863,7 +1143,18 @@ static hipError_t launch_gram_task(const edt_plan* p, edt_precision prec, const 
     const int32_t* sched = dptr<const int32_t>(p, p->lay.sched);
     const GRow* grow = dptr<const GRow>(p, p->lay.grow);
     const unsigned nb = unsigned(p->sched.size());
-    if (prec == EDT_BF16X3)
+    // a gated (rarely needed) FP64 pass runs on a small persistent grid
+    const unsigned grid = rd.gate ? std::min(nb, 512u) : nb;
+    if ((prec == EDT_BF16X3 || prec == EDT_FP16X3) && NTJ == 0 && split_unified()) {
+        if (prec == EDT_BF16X3)
+            hipLaunchKernelGGL((gram_split3u_kernel<NT, false>), dim3(nb), dim3(512), row_lds_bytes(p->chunk_rows),
+                               st, items, sched, grow, rd.ub32, g32, rd.gmax, p->nz, zI0, ntot,
+                               static_cast<float*>(part), rpart, p->chunk_rows);
+        else
+            hipLaunchKernelGGL((gram_split3u_kernel<NT, true>), dim3(nb), dim3(512), row_lds_bytes(p->chunk_rows),
+                               st, items, sched, grow, rd.ub32, g32, rd.gmax, p->nz, zI0, ntot,
+                               static_cast<float*>(part), rpart, p->chunk_rows);
+    } else if (prec == EDT_BF16X3)
         hipLaunchKernelGGL((gram_split3_kernel<NT, NTJ, false>), dim3(nb), dim3(512),
                            row_lds_bytes(p->chunk_rows), st, items, sched, grow, rd.ub32, g32, rd.gmax,
                            p->nz, zI0, zJ0, ntot, static_cast<float*>(part), rpart, p->chunk_rows);
@@ -872,9 +1163,9 @@ static hipError_t launch_gram_task(const edt_plan* p, edt_precision prec, const 
                            row_lds_bytes(p->chunk_rows), st, items, sched, grow, rd.ub32, g32, rd.gmax,
                            p->nz, zI0, zJ0, ntot, static_cast<float*>(part), rpart, p->chunk_rows);
     else if (prec == EDT_FP64)
-        hipLaunchKernelGGL((gram_f64_kernel<NT, NTJ>), dim3(nb), dim3(512), 0, st, items, sched, grow,
+        hipLaunchKernelGGL((gram_f64_kernel<NT, NTJ>), dim3(grid), dim3(512), 0, st, items, sched, grow,
                            dptr<const double>(p, p->lay.gsc), rd.ubw, g64, p->nz, zI0, zJ0, ntot,
-                           static_cast<double*>(part), rpart, rd.only);
+                           static_cast<double*>(part), rpart, rd.only, int(nb), rd.gate);
     else if constexpr (NTJ == 0)
         hipLaunchKernelGGL(gram_f32_kernel<NT>, dim3(nb), dim3(256), row_lds_bytes(p->chunk_rows), st,
                            items, sched, grow, rd.ub32, g32, p->nz, static_cast<float*>(part), rpart,
@@ -904,6 +1195,12 @@ static hipError_t configure_gram_task() {
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e == hipSuccess)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_split3_kernel<NT, NTJ, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess && NTJ == 0)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_split3u_kernel<NT, false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess && NTJ == 0)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_split3u_kernel<NT, true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e == hipSuccess && NTJ == 0)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_f32_kernel<NT>),
@@ -943,12 +1240,12 @@ hipError_t launch_gmax(const edt_plan* p, const float2* g32, float* gmax, hipStr
 // super-block sbi and the halves (128 depths) of super-block sbj.
 hipError_t launch_gram(const edt_plan* p, edt_precision prec, const zd* g64, const float2* g32,
                        const zd* ubw, const float4* ub32, const float* gmax, void* part, double* rpart,
-                       hipStream_t st, const int32_t* only) {
+                       hipStream_t st, const int32_t* only, const int32_t* gate) {
     if (p->sched.empty()) return hipSuccess;
     const int nz = p->nz, ntot = (nz + 31) / 32, ns = n_super(nz);
     if (prec == EDT_FP32 && ns > 1) return hipErrorInvalidValue;
-    if (only && prec != EDT_FP64) return hipErrorInvalidValue;
-    const GramRowData rd{ubw, ub32, gmax, only};
+    if ((only || gate) && prec != EDT_FP64) return hipErrorInvalidValue;
+    const GramRowData rd{ubw, ub32, gmax, only, gate};
     auto nt_of = [&](int sb) { return (std::min(kSuperDepth, nz - kSuperDepth * sb) + 31) / 32; };
     for (int sb = 0; sb < ns; ++sb) {
         const hipError_t e =

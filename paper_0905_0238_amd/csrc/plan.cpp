@@ -284,6 +284,8 @@ WorkLayout work_layout(const edt_plan* p) {
     off = align256(off + P * 2 * nz * sizeof(double));
     w.esc_trace = off;
     off = align256(off + P * sizeof(double));
+    w.counters = off;
+    off = align256(off + (edt::kMaxRefine + 2) * sizeof(int32_t));
     w.aux = off;
     off = align256(off + P * 2 * nz * sizeof(double));
     w.aux2 = off;

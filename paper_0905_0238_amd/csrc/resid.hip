@@ -126,12 +126,18 @@ __global__ __launch_bounds__(256) void resid_kernel(const Item* __restrict__ ite
                                                     const zd* __restrict__ g64, int nz,
                                                     const double* __restrict__ x,
                                                     const int32_t* __restrict__ conv,
-                                                    double* __restrict__ rpart) {
+                                                    double* __restrict__ rpart, int nsched,
+                                                    const int32_t* __restrict__ active) {
     __shared__ double s_acc[4][2][ZPL * 64];
-    const int32_t k = sched[blockIdx.x];
-    if (k < 0) return;   // hole in the XCD-aware schedule
+    // no pair left iterating: the whole sweep is skipped with one load
+    if (active && *active == 0) return;
+    // persistent blocks: block b takes schedule entries b, b + G, ... (G a
+    // multiple of the XCD count, so every entry keeps its XCD)
+    for (int ks = blockIdx.x; ks < nsched; ks += gridDim.x) {
+    const int32_t k = sched[ks];
+    if (k < 0) continue;   // hole in the XCD-aware schedule
     const Item it = items[k];
-    if (conv[it.pair]) return;
+    if (conv[it.pair]) continue;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: row data via scalar loads
     const int n = it.row_end - it.row_begin;
@@ -218,6 +224,8 @@ __global__ __launch_bounds__(256) void resid_kernel(const Item* __restrict__ ite
         const int h = e / nz, z = e - h * nz;
         out[e] = (s_acc[0][h][z] + s_acc[1][h][z]) + (s_acc[2][h][z] + s_acc[3][h][z]);
     }
+    __syncthreads();   // s_acc is reused by the next entry
+    }
 }
 
 // Born forward map: for each unique row of an item, A.v[u] and A.v[-u],
@@ -274,34 +282,39 @@ hipError_t launch_bsum(const edt_plan* p, const zd* d_rows, zd* ub, hipStream_t 
     return hipGetLastError();
 }
 
+// Blocks of the persistent residual sweep at most (a multiple of 8: each
+// schedule entry stays on its XCD).
+constexpr int kResidGrid = 4096;
+
 template <int ZPL>
 static hipError_t launch_resid_z(const edt_plan* p, const zd* g64, const zd* ubw, const double* x,
-                                 const int32_t* conv, double* rpart, hipStream_t st) {
-    const unsigned nit = unsigned(p->rsched.size());
+                                 const int32_t* conv, double* rpart, const int32_t* active, hipStream_t st) {
+    const int nit = int(p->rsched.size());
     if (nit == 0) return hipSuccess;
+    const unsigned grid = unsigned(std::min(nit, kResidGrid));
     const Item* items = dptr<const Item>(p, p->lay.ritems);
     const int32_t* sched = dptr<const int32_t>(p, p->lay.rsched);
     const GRow* grow = dptr<const GRow>(p, p->lay.grow);
     const double* gsc = dptr<const double>(p, p->lay.gsc);
     if (ubw)
-        hipLaunchKernelGGL((resid_kernel<ZPL, true>), dim3(nit), dim3(256), 0, st, items, sched, grow, gsc, ubw,
-                           g64, p->nz, x, conv, rpart);
+        hipLaunchKernelGGL((resid_kernel<ZPL, true>), dim3(grid), dim3(256), 0, st, items, sched, grow, gsc, ubw,
+                           g64, p->nz, x, conv, rpart, nit, active);
     else
-        hipLaunchKernelGGL((resid_kernel<ZPL, false>), dim3(nit), dim3(256), 0, st, items, sched, grow, gsc,
-                           ubw, g64, p->nz, x, conv, rpart);
+        hipLaunchKernelGGL((resid_kernel<ZPL, false>), dim3(grid), dim3(256), 0, st, items, sched, grow, gsc,
+                           ubw, g64, p->nz, x, conv, rpart, nit, active);
     return hipGetLastError();
 }
 
 hipError_t launch_resid(const edt_plan* p, const zd* g64, const zd* ubw, const double* x,
-                        const int32_t* conv, double* rpart, hipStream_t st) {
+                        const int32_t* conv, double* rpart, hipStream_t st, const int32_t* active) {
     switch ((p->nz + 63) / 64) {
-        case 1: return launch_resid_z<1>(p, g64, ubw, x, conv, rpart, st);
-        case 2: return launch_resid_z<2>(p, g64, ubw, x, conv, rpart, st);
-        case 3: return launch_resid_z<3>(p, g64, ubw, x, conv, rpart, st);
-        case 4: return launch_resid_z<4>(p, g64, ubw, x, conv, rpart, st);
-        case 5: return launch_resid_z<5>(p, g64, ubw, x, conv, rpart, st);
-        case 6: return launch_resid_z<6>(p, g64, ubw, x, conv, rpart, st);
-        case 7: return launch_resid_z<7>(p, g64, ubw, x, conv, rpart, st);
+        case 1: return launch_resid_z<1>(p, g64, ubw, x, conv, rpart, active, st);
+        case 2: return launch_resid_z<2>(p, g64, ubw, x, conv, rpart, active, st);
+        case 3: return launch_resid_z<3>(p, g64, ubw, x, conv, rpart, active, st);
+        case 4: return launch_resid_z<4>(p, g64, ubw, x, conv, rpart, active, st);
+        case 5: return launch_resid_z<5>(p, g64, ubw, x, conv, rpart, active, st);
+        case 6: return launch_resid_z<6>(p, g64, ubw, x, conv, rpart, active, st);
+        case 7: return launch_resid_z<7>(p, g64, ubw, x, conv, rpart, active, st);
         default: return hipErrorInvalidValue;
     }
 }
