@@ -1,6 +1,6 @@
 """GPU parity of the HIP path against the FP64 oracle, through the C-ABI.
 
-Bars (the benchmark spec): FP64 path <= 1e-10 relative, mixed precision (FP32 or
+Bars: FP64 path <= 1e-10 relative, mixed precision (FP32 or
 BF16x3 Gram + FP64 Cholesky + FP64 refinement) <= 1e-6 relative, both as a
 global Frobenius ratio and per +-k_m pair (floor 1e-3 of the largest pair).
 Intermediate tables, Grams and data are checked at FP64 rounding level.
