@@ -258,10 +258,10 @@ edt_status edt_green(const edt_plan* plan, const double* vel_dev, edt_c128* g64,
  * trace[p] = tr Re(A_p^H A_p).  d_rows[r] = (datum at +k_m, datum at -k_m) of
  * row r, complex128, so b+ = (d0+d1)/2 and b- = (d0-d1)/(2i) (eq. Split).
  * prec EDT_FP64 reads g64 and gives rhs and trace in FP64.  EDT_FP32,
- * EDT_BF16X3 and EDT_FP16X3 read g32 (from edt_green); their rhs is
- * accumulated in FP32 (an approximation that the FP64 refinement residual of
- * edt_solve corrects) and their trace from FP32 rows with FP64 sums
- * (relative error about 1e-8).
+ * EDT_BF16X3 and EDT_FP16X3 read g32 (from edt_green); their rhs and trace
+ * come from FP32 rows summed per stage of 8 rows in FP32 and then in FP64
+ * (the rhs is an approximation, about 1e-7 relative, that the FP64
+ * refinement residual of edt_solve corrects; the trace is within about 1e-8).
  * work: device, >= work_bytes.  Empty pairs get zero Gram, rhs and trace.
  */
 edt_status edt_assemble(const edt_plan* plan, const edt_c128* g64, const edt_c64* g32,

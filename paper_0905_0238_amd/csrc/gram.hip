@@ -212,9 +212,10 @@ struct RawStage {
 // (the row of a stage is uniform over the wave: broadcast reads, and the
 // table base of a load is a scalar).  Depths past nz are zeroed once per item.
 // Diagonal tasks also accumulate the item's right-hand side
-// c+-(z) = Re(A^H B+-) over their depths in FP32 (an approximation: the FP64
-// refinement residual corrects it) and the trace sum mult |A|^2 (per stage in
-// FP32, then in FP64) into rpart[slot] (c+, c-, one trace per super-block).
+// c+-(z) = Re(A^H B+-) over their depths from FP32 rows (an approximation: the
+// FP64 refinement residual corrects it) and the trace sum mult |A|^2, both per
+// stage in FP32 and then in FP64 (so that the error does not grow with the
+// item's length), into rpart[slot] (c+, c-, one trace per super-block).
 template <int NT, int NTJ, bool F16>
 __global__ __launch_bounds__(512, 1) void gram_split3_kernel(const Item* __restrict__ items,
                                                              const int32_t* __restrict__ sched,
@@ -288,8 +289,7 @@ __global__ __launch_bounds__(512, 1) void gram_split3_kernel(const Item* __restr
         const bool onJ = C::RECT && pid < C::NZPJ;   // and J-set depth zJ0 + pid (always < nz)
         const int zIc = zI0 + min(pid, nzI - 1);     // clamped: loads are unconditional
         const int zJc = min(zJ0 + pid, nz - 1);
-        float cp = 0.0f, cm = 0.0f;
-        double tr = 0.0;
+        double cp = 0.0, cm = 0.0, tr = 0.0;   // per stage in FP32, then in FP64
         auto load = [&](RawStage& R, int s, int zc) {
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(512, 1) void gram_split3_kernel(const Item* __restr
         };
         auto form = [&](const RawStage& R, int buf, int s, int row, bool diag_sums, bool on) {
             uint32_t h[8], l[8];
-            float t = 0.0f;
+            float t = 0.0f, sp = 0.0f, sm = 0.0f;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const uint4 a = s_row[2 * (8 * s + j)];
@@ -312,14 +312,18 @@ __global__ __launch_bounds__(512, 1) void gram_split3_kernel(const Item* __restr
                 if (diag_sums) {
                     const uint4 b = s_row[2 * (8 * s + j) + 1];
                     const float mt = __uint_as_float(a.w);
-                    cp += px * __uint_as_float(b.x) + py * __uint_as_float(b.y);
-                    cm += px * __uint_as_float(b.z) + py * __uint_as_float(b.w);
+                    sp += px * __uint_as_float(b.x) + py * __uint_as_float(b.y);
+                    sm += px * __uint_as_float(b.z) + py * __uint_as_float(b.w);
                     t += mt * (px * px + py * py);
                 }
                 const float ss = F16 ? sw * scale : sw;
                 split_pack<F16>(ss * px, ss * py, h[j], l[j]);
             }
-            if (diag_sums) tr += double(t);
+            if (diag_sums) {
+                tr += double(t);
+                cp += double(sp);
+                cm += double(sm);
+            }
             if (on) {
                 uint4* hi = reinterpret_cast<uint4*>(sh[buf][0] + row * C::STR);
                 uint4* lo = reinterpret_cast<uint4*>(sh[buf][1] + row * C::STR);
@@ -361,8 +365,8 @@ __global__ __launch_bounds__(512, 1) void gram_split3_kernel(const Item* __restr
         if constexpr (!C::RECT) {
             if (onI) {
                 double* rp = rpart + size_t(it.slot) * rpart_width(nz);
-                rp[zI0 + pid] = double(cp);
-                rp[nz + zI0 + pid] = double(cm);
+                rp[zI0 + pid] = cp;
+                rp[nz + zI0 + pid] = cm;
             }
             const double t = wave_sum(onI ? tr : 0.0);
             if (lane == 0) s_tr[wv - 4] = t;
@@ -542,8 +546,7 @@ __global__ __launch_bounds__(512, 1) void gram_split3u_kernel(const Item* __rest
 #pragma unroll
             for (int h = 0; h < 2; ++h) reinterpret_cast<uint4*>(sh[b][h] + z * C::STR)[hf] = zero;
     }
-    float cp = 0.0f, cm = 0.0f;
-    double tr = 0.0;
+    double cp = 0.0, cm = 0.0, tr = 0.0;   // per stage in FP32, then in FP64
     const uint32_t zoff = zc * uint32_t(sizeof(float2));   // byte offset of this lane's depth
     auto load = [&](RawHalf& R, int s) {
 #pragma unroll
@@ -557,7 +560,7 @@ __global__ __launch_bounds__(512, 1) void gram_split3u_kernel(const Item* __rest
     };
     auto form = [&](const RawHalf& R, int buf, int s) {
         uint32_t h[4], l[4];
-        float t = 0.0f;
+        float t = 0.0f, sp = 0.0f, sm = 0.0f;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint4 a = s_row[2 * (8 * s + 4 * hf + j)];
@@ -565,13 +568,15 @@ __global__ __launch_bounds__(512, 1) void gram_split3u_kernel(const Item* __rest
             const float sw = __uint_as_float(a.z), mt = __uint_as_float(a.w);
             const float px = R.ga[j].x * R.gb[j].x - R.ga[j].y * R.gb[j].y;
             const float py = R.ga[j].x * R.gb[j].y + R.ga[j].y * R.gb[j].x;
-            cp += px * __uint_as_float(b.x) + py * __uint_as_float(b.y);
-            cm += px * __uint_as_float(b.z) + py * __uint_as_float(b.w);
+            sp += px * __uint_as_float(b.x) + py * __uint_as_float(b.y);
+            sm += px * __uint_as_float(b.z) + py * __uint_as_float(b.w);
             t += mt * (px * px + py * py);
             const float ss = F16 ? sw * scale : sw;
             split_pack<F16>(ss * px, ss * py, h[j], l[j]);
         }
         tr += double(t);
+        cp += double(sp);
+        cm += double(sm);
         if (on) {
             reinterpret_cast<uint4*>(sh[buf][0] + z * C::STR)[hf] = make_uint4(h[0], h[1], h[2], h[3]);
             reinterpret_cast<uint4*>(sh[buf][1] + z * C::STR)[hf] = make_uint4(l[0], l[1], l[2], l[3]);
@@ -628,7 +633,7 @@ __global__ __launch_bounds__(512, 1) void gram_split3u_kernel(const Item* __rest
         default: u_store_tiles<NT, 7>(acc, out, lane, back, bI0); break;
     }
     // the two row halves of depth z meet in LDS (the stage buffers are free)
-    float* sc = reinterpret_cast<float*>(&sh[0][0][0]);
+    double* sc = reinterpret_cast<double*>(&sh[0][0][0]);
     if (hf == 1) {
         sc[z] = cp;
         sc[256 + z] = cm;
@@ -638,8 +643,8 @@ __global__ __launch_bounds__(512, 1) void gram_split3u_kernel(const Item* __rest
     __syncthreads();
     double* rp = rpart + size_t(it.slot) * rpart_width(nz);
     if (hf == 0 && on) {
-        rp[zI0 + z] = double(cp) + double(sc[z]);
-        rp[nz + zI0 + z] = double(cm) + double(sc[256 + z]);
+        rp[zI0 + z] = cp + sc[z];
+        rp[nz + zI0 + z] = cm + sc[256 + z];
     }
     if (tid == 0)
         rp[2 * nz + zI0 / kSuperDepth] =
@@ -723,8 +728,7 @@ __global__ __launch_bounds__(256, 1) void gram_f32_kernel(const Item* __restrict
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[m][v] = 0.0f;
     float2 ga[8], gb[8];
-    float cp = 0.0f, cm = 0.0f;
-    double tr = 0.0;
+    double cp = 0.0, cm = 0.0, tr = 0.0;   // per stage in FP32, then in FP64
     auto load = [&](int s) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -737,7 +741,7 @@ __global__ __launch_bounds__(256, 1) void gram_f32_kernel(const Item* __restrict
     };
     auto store = [&](int buf, int s) {
         float re[8], im[8];
-        float t = 0.0f;
+        float t = 0.0f, sp = 0.0f, sm = 0.0f;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const uint4 a = s_row[2 * (8 * s + j)];
@@ -745,13 +749,15 @@ __global__ __launch_bounds__(256, 1) void gram_f32_kernel(const Item* __restrict
             const float sw = __uint_as_float(a.z), mt = __uint_as_float(a.w);
             const float px = ga[j].x * gb[j].x - ga[j].y * gb[j].y;
             const float py = ga[j].x * gb[j].y + ga[j].y * gb[j].x;
-            cp += px * __uint_as_float(b.x) + py * __uint_as_float(b.y);
-            cm += px * __uint_as_float(b.z) + py * __uint_as_float(b.w);
+            sp += px * __uint_as_float(b.x) + py * __uint_as_float(b.y);
+            sm += px * __uint_as_float(b.z) + py * __uint_as_float(b.w);
             t += mt * (px * px + py * py);
             re[j] = sw * px;
             im[j] = sw * py;
         }
         tr += double(t);
+        cp += double(sp);
+        cm += double(sm);
         if (z < nz) {
             // z-row layout: real parts of the 8 rows, then imaginary parts
             float4* o = reinterpret_cast<float4*>(sh[buf] + z * C::STR);
@@ -785,8 +791,8 @@ __global__ __launch_bounds__(256, 1) void gram_f32_kernel(const Item* __restrict
     else f32_store_tiles<S, 3>(acc, out, lane, 1.0f, 0, 0);
     double* rp = rpart + size_t(it.slot) * rpart_width(nz);
     if (z < nz) {
-        rp[z] = double(cp);
-        rp[nz + z] = double(cm);
+        rp[z] = cp;
+        rp[nz + z] = cm;
     }
     const double t = wave_sum(z < nz ? tr : 0.0);
     if (lane == 0) s_tr[wv] = t;

@@ -33,8 +33,8 @@ constexpr int kFreqGroup = 2;     // frequencies per residual work item
 constexpr int kResidRows = 1024;  // rows per residual work item at most
 constexpr int kXcd = 8;           // accelerator dies (separate L2 caches) on MI355X
 constexpr double kL2Slab = 2.5e6; // bytes of FP32 table per Gram band (an XCD's L2 is 4 MB)
-constexpr int kMinItemRows = 256; // unique rows of an average work item at least, where the band allows
-constexpr int kMinResidRows = 64; // the same for residual work items
+constexpr int kMinItemRows = 256; // unique rows of an average Gram work item at least, where the band allows
+constexpr int kMinResidRows = 64; // unique rows of an average residual work item at least
 
 inline int64_t signed_of(int64_t n, int64_t N) { return n < (N + 1) / 2 ? n : n - N; }
 inline int64_t wrap(int64_t n, int64_t N) { return ((n % N) + N) % N; }
@@ -563,10 +563,13 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
         // frequencies (at most chunk_rows rows).  The band is sized so that
         // its FP32 Green's table slab (n_cls x nz entries per frequency) fits
         // an XCD's L2 with room for the next band; slots are pair-major.
-        p->chunk_rows = chunk_rows > 0 ? chunk_rows : kDefaultChunk;
         // Where one frequency's slab alone exceeds that (large 3D tables) the
         // band is widened until an average item holds kMinItemRows rows: an
         // item's partial Gram (nz^2 values) must stay small next to its rows.
+        // (Items over all frequencies are fewer and the split Gram faster, but
+        // an FP16x3 item then spans a wider range of row magnitudes under its
+        // one scale, and some pairs need one more refinement sweep.)
+        p->chunk_rows = chunk_rows > 0 ? chunk_rows : kDefaultChunk;
         const double per_pf = double(p->n_urows) / std::max(1.0, double(p->n_pairs - p->n_empty) * p->n_freq);
         const int64_t band_rows = int64_t(std::ceil(double(kMinItemRows) / std::max(per_pf, 1e-9)));
         const int64_t band_l2 = int64_t(kL2Slab / (double(p->n_cls) * double(p->nz) * 8.0));
@@ -577,9 +580,11 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
         p->sched = xcd_schedule(p->items, gband);
 
         // residual work items: a pair's rows within a group of at least
-        // kFreqGroup frequencies (widened like the Gram band, to kMinResidRows
-        // rows, where rows are sparse; at most kResidRows rows), scheduled the
-        // same way
+        // kFreqGroup frequencies (widened, where rows are sparse, until an
+        // average item holds kMinResidRows rows; at most kResidRows rows),
+        // scheduled the same way.  The residual sweep reads its table slab
+        // from L2, and its partials are small (2 nz values), so its groups
+        // stay narrow.
         const int64_t group_rows = int64_t(std::ceil(double(kMinResidRows) / std::max(per_pf, 1e-9)));
         p->resid_group = int(std::max<int64_t>(kFreqGroup, std::min<int64_t>(p->n_freq, group_rows)));
         std::vector<int32_t> rgroup;

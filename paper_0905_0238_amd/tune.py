@@ -21,7 +21,7 @@ __all__ = ["candidates", "autotune"]
 
 
 def candidates(survey):
-    """(chunk_rows, gram_band) pairs to try; band 0 = sized to the L2 slab."""
+    """(chunk_rows, gram_band) pairs to try; band 0 = the planner default."""
     nf = len(survey.freqs)
     bands = sorted({0, 4, 8, 16, 32, nf})
     return [(c, b) for c in (1024, 2048) for b in bands if b <= nf]

@@ -201,8 +201,7 @@ def _band_rules(p):
     n_f, n_cls, nz = p.table_shape
     l2 = int(2.5e6 // (n_cls * nz * 8))
     per_pf = p.info["n_urows"] / max(1, (p.n_pairs - p.info["n_empty"]) * n_f)
-    rows = int(np.ceil(256 / per_pf))
-    return l2, rows
+    return l2, int(np.ceil(256 / per_pf)), per_pf
 
 
 def test_default_band_fits_l2():
@@ -211,7 +210,7 @@ def test_default_band_fits_l2():
     p = E.Plan(s)
     n_cls, nz = p.table_shape[1], p.table_shape[2]
     band = p.info["gram_band"]
-    l2, rows = _band_rules(p)
+    l2, rows, _ = _band_rules(p)
     assert rows <= l2
     # one band's FP32 table slab is at most 2.5 MB and one more frequency would exceed it
     assert band * n_cls * nz * 8 <= 2.5e6 < (band + 1) * n_cls * nz * 8
@@ -219,15 +218,15 @@ def test_default_band_fits_l2():
 
 def test_default_band_widens_for_sparse_rows():
     """3D 128 x 128 survey: one frequency's FP32 slab is near the L2 budget, so
-    the band is set by the rows rule (an average item of 256 unique rows)."""
+    the band is set by the rows rule (an average item of 256 unique rows);
+    residual groups: at least 2 frequencies, widened to 64 rows per item."""
     _lib_or_skip()
     s = make_config(4, with_model=False)
     p = E.Plan(s)
-    l2, rows = _band_rules(p)
-    assert rows > l2
-    assert p.info["gram_band"] == min(p.table_shape[0], rows)
+    l2, rows, per_pf = _band_rules(p)
     n_f = p.table_shape[0]
-    per_pf = p.info["n_urows"] / max(1, (p.n_pairs - p.info["n_empty"]) * n_f)
+    assert rows > l2
+    assert p.info["gram_band"] == min(n_f, rows)
     assert p.info["resid_group"] == min(n_f, max(2, int(np.ceil(64 / per_pf))))
 
 
