@@ -13,59 +13,76 @@
 //
 // Layout: a 256-thread block per work item; each wave takes its own rows,
 // lanes span depth (ZPL depths per lane).  A x needs a sum over depth per
-// row: four rows at a time are reduced with a transposing butterfly, so a
-// row costs about one cross-lane exchange per lane instead of six.
+// row: four rows at a time are reduced with a transposing butterfly of lane
+// swaps and DPP moves, so a row costs about one cross-lane exchange per lane
+// instead of six.
 
 #include "dev_common.h"
 
 namespace edt {
 
+// Cross-lane moves of a double as two 32-bit halves.
+// permlane32_swap: lanes 32..63 of x trade places with lanes 0..31 of y.
+// permlane16_swap: rows 1 and 3 (16 lanes each) of x trade places with rows
+// 0 and 2 of y.  mov_dpp<CTRL>: the DPP lane pattern CTRL within each row.
+__device__ __forceinline__ void swap32_d(double& x, double& y) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(y), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(y), false, false);
+    x = __hiloint2double(int(hi[0]), int(lo[0]));
+    y = __hiloint2double(int(hi[1]), int(lo[1]));
+}
+__device__ __forceinline__ void swap16_d(double& x, double& y) {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(y), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(y), false, false);
+    x = __hiloint2double(int(hi[0]), int(lo[0]));
+    y = __hiloint2double(int(hi[1]), int(lo[1]));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    return __hiloint2double(__builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false),
+                            __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false));
+}
+constexpr int kDppRowMirror = 0x140;       // lane i <- lane 15 - i of its row
+constexpr int kDppRowHalfMirror = 0x141;   // lane i <- lane 7 - i of its half row
+constexpr int kDppQuadXor2 = 0x4E;         // quad_perm [2, 3, 0, 1]
+constexpr int kDppQuadXor1 = 0xB1;         // quad_perm [1, 0, 3, 2]
+
 // Sum each of 16 per-lane values over the 64 lanes; every lane receives all
-// 16 totals.  Four halving exchanges leave lane l with the partial total of
-// index 8*b5 + 4*b4 + 2*b3 + b2 (b = bits of l), two more finish the sum.
-__device__ __forceinline__ void butterfly16(const double (&v)[16], double (&out)[16], int lane) {
-    double a8[8], a4[4], a2[2];
-    {
-        const bool b = lane & 32;
+// 16 totals.  Four halving steps leave lane l with the partial total of
+// index 8*b5 + 4*b4 + 2*b3 + b2 (b = bits of l): the lane swaps pair l with
+// l ^ 32 and l ^ 16, the row mirrors pair l with a lane of the other bit-3
+// (bit-2) half of its row (half row); two quad exchanges finish the sum.
+// No step goes through LDS.  The input array is overwritten.
+__device__ __forceinline__ void butterfly16(double (&a)[16], double (&out)[16], int lane) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const double send = b ? v[i] : v[i + 8];
-            const double keep = b ? v[i + 8] : v[i];
-            a8[i] = keep + __shfl_xor(send, 32, 64);
-        }
+    for (int i = 0; i < 8; ++i) {   // bit 5: lanes 0..31 keep index i, lanes 32..63 index i + 8
+        double x = a[i], y = a[i + 8];
+        swap32_d(x, y);
+        a[i] = x + y;
     }
-    {
-        const bool b = lane & 16;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const double send = b ? a8[i] : a8[i + 4];
-            const double keep = b ? a8[i + 4] : a8[i];
-            a4[i] = keep + __shfl_xor(send, 16, 64);
-        }
+    for (int i = 0; i < 4; ++i) {   // bit 4
+        double x = a[i], y = a[i + 4];
+        swap16_d(x, y);
+        a[i] = x + y;
     }
-    {
-        const bool b = lane & 8;
+    const bool b3 = lane & 8, b2 = lane & 4;
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const double send = b ? a4[i] : a4[i + 2];
-            const double keep = b ? a4[i + 2] : a4[i];
-            a2[i] = keep + __shfl_xor(send, 8, 64);
-        }
+    for (int i = 0; i < 2; ++i) {   // bit 3
+        const double lo = a[i] + dpp_d<kDppRowMirror>(a[i]);
+        const double hi = a[i + 2] + dpp_d<kDppRowMirror>(a[i + 2]);
+        a[i] = b3 ? hi : lo;
     }
-    double s;
-    {
-        const bool b = lane & 4;
-        const double send = b ? a2[0] : a2[1];
-        const double keep = b ? a2[1] : a2[0];
-        s = keep + __shfl_xor(send, 4, 64);
+    {   // bit 2
+        const double lo = a[0] + dpp_d<kDppRowHalfMirror>(a[0]);
+        const double hi = a[1] + dpp_d<kDppRowHalfMirror>(a[1]);
+        a[0] = b2 ? hi : lo;
     }
-    s += __shfl_xor(s, 2, 64);
-    s += __shfl_xor(s, 1, 64);
+    double s = a[0];
+    s += dpp_d<kDppQuadXor2>(s);
+    s += dpp_d<kDppQuadXor1>(s);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const int src = (((k >> 3) & 1) << 5) | (((k >> 2) & 1) << 4) | (((k >> 1) & 1) << 3) | ((k & 1) << 2);
-        out[k] = readlane_d(s, src);
-    }
+    for (int k = 0; k < 16; ++k) out[k] = readlane_d(s, k << 2);
 }
 
 // ub[u] = (sum of b+ over the data rows of unique row u, sum of b-).
@@ -153,8 +170,7 @@ __global__ __launch_bounds__(256) void resid_kernel(const Item* __restrict__ ite
     for (int q = 0; q < ZPL; ++q) acc[0][q] = acc[1][q] = 0.0;
 
     for (int b0 = 0; b0 < n; b0 += 16) {
-        // the 4 rows of this wave in the batch; every load of the batch is
-        // issued before the first use
+        // the 4 rows of this wave in the batch
         zd gr[4][ZPL], gs[4][ZPL], bp[4], bm[4];
         double w2[4];
 #pragma unroll
@@ -179,7 +195,6 @@ __global__ __launch_bounds__(256) void resid_kernel(const Item* __restrict__ ite
                 gs[j][q] = g64[size_t(g.off_s) + zc];
             }
         }
-        __builtin_amdgcn_sched_barrier(0);
         zd P[4][ZPL];
 #pragma unroll
         for (int j = 0; j < 4; ++j)
