@@ -149,6 +149,10 @@ typedef struct {
     int max_refine;        /* at most this many refinement sweeps over the rows (<= 62) */
     int escalate;          /* with refine: pairs whose factorisation fails (info > 0) are
                               re-assembled with the FP64 Gram and factored again */
+    int data_summed;       /* with refine: nonzero if `work` still holds the summed data
+                              left by edt_assemble of this plan with these d_rows (nothing
+                              written to work or d_rows since); the solve then does not
+                              sum the data rows again */
 } edt_solve_opts;
 
 /* Message of the last failing call on this thread (static storage). */
@@ -262,7 +266,9 @@ edt_status edt_green(const edt_plan* plan, const double* vel_dev, edt_c128* g64,
  * come from FP32 rows summed per stage of 8 rows in FP32 and then in FP64
  * (the rhs is an approximation, about 1e-7 relative, that the FP64
  * refinement residual of edt_solve corrects; the trace is within about 1e-8).
- * work: device, >= work_bytes.  Empty pairs get zero Gram, rhs and trace.
+ * work: device, >= work_bytes; it keeps the data summed per unique row, which
+ * edt_solve can reuse (edt_solve_opts.data_summed).  Empty pairs get zero
+ * Gram, rhs and trace.
  */
 edt_status edt_assemble(const edt_plan* plan, const edt_c128* g64, const edt_c64* g32,
                         const edt_c128* d_rows, edt_precision prec, double* gram, double* rhs,

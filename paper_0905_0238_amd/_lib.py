@@ -42,7 +42,7 @@ class PlanOpts(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("refine", C.c_int), ("refine_tol", C.c_double), ("max_refine", C.c_int),
-                ("escalate", C.c_int)]
+                ("escalate", C.c_int), ("data_summed", C.c_int)]
 
 
 EXPORTS = ["edt_last_error", "edt_plan_create", "edt_survey_pair_rows", "edt_plan_destroy", "edt_plan_query",

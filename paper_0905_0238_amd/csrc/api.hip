@@ -192,8 +192,9 @@ edt_status edt_assemble(const edt_plan* p, const edt_c128* g64, const edt_c64* g
     float4* ub32 = reinterpret_cast<float4*>(w + wl.ub32);
     const bool f64 = prec == EDT_FP64;
     const zd* G64 = reinterpret_cast<const zd*>(g64);
-    EDT_TRY(launch_bsum(p, reinterpret_cast<const zd*>(d_rows), ub, stream, f64 ? ubw : nullptr,
-                        f64 ? nullptr : ub32),
+    // conj(W) B in FP64 for every precision: the FP64 Gram reads it, and the
+    // data sweep of a refining edt_solve can reuse it
+    EDT_TRY(launch_bsum(p, reinterpret_cast<const zd*>(d_rows), ub, stream, ubw, f64 ? nullptr : ub32),
             "bsum");
     // one pass over the rows gives the Gram partials and the right-hand side
     // and trace partials of every item
@@ -247,9 +248,10 @@ edt_status edt_solve(const edt_plan* p, const edt_c128* g64, const edt_c128* d_r
         zd* ubw = reinterpret_cast<zd*>(w + wl.ubw);
         double* rpart = reinterpret_cast<double*>(w + wl.rhs_part);
         const zd* G64 = reinterpret_cast<const zd*>(g64);
-        // the summed data, conj(W) B per unique row, are rebuilt here so that
-        // edt_solve does not depend on an earlier call's scratch
-        EDT_TRY(launch_bsum(p, reinterpret_cast<const zd*>(d_rows), ub, stream, ubw), "bsum");
+        // the summed data, conj(W) B per unique row, unless the caller states
+        // that edt_assemble left them in work
+        if (!opts->data_summed)
+            EDT_TRY(launch_bsum(p, reinterpret_cast<const zd*>(d_rows), ub, stream, ubw), "bsum");
         if (opts->escalate) {
             // pairs whose factorisation failed (info > 0): FP64 Gram, rhs and
             // trace from the rows, and a second factorisation; every launch

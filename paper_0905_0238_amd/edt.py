@@ -184,9 +184,11 @@ class Plan:
         return gram, rhs, trace
 
     def solve(self, g64, d_rows, gram, rhs, trace, lambda_rel, refine=False, refine_tol=1e-8,
-              max_refine=8, escalate=True, out=None):
+              max_refine=8, escalate=True, data_summed=False, out=None):
         """(x[P, 2, nz], v[n_km, nz] complex128, info[P], steps[P]).  With refine,
-        escalate re-assembles in FP64 the pairs whose factorisation failed."""
+        escalate re-assembles in FP64 the pairs whose factorisation failed, and
+        data_summed reuses the data sums that assemble(d_rows) left in the
+        workspace (only right after that call, with d_rows unchanged)."""
         self.upload()
         P, nz = self.n_pairs, self.nz
         if out is None:
@@ -197,7 +199,7 @@ class Plan:
         else:
             x, v, info, steps = out
         opts = _lib.SolveOpts(1 if refine else 0, float(refine_tol), int(max_refine),
-                              1 if (refine and escalate) else 0)
+                              1 if (refine and escalate) else 0, 1 if data_summed else 0)
         _lib.check(_lib.load().edt_solve(self._h, _ptr(g64), _ptr(d_rows), _ptr(gram), _ptr(rhs), _ptr(trace),
                                          float(lambda_rel), C.byref(opts), _ptr(x), _ptr(v), _ptr(info),
                                          _ptr(steps), _ptr(self._work), _stream()), "edt_solve")

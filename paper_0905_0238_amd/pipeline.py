@@ -52,7 +52,8 @@ class Pipeline:
         p.green(self.vel, want32=self.mixed, out=(self.G64, self.G32))
         p.assemble(self.G64, self.G32, self.d, self.prec, out=(self.gram, self.rhs, self.trace))
         p.solve(self.G64, self.d, self.gram, self.rhs, self.trace, self.lam, refine=self.mixed,
-                refine_tol=self.tol, max_refine=self.maxr, out=(self.x, self.v, self.info, self.steps))
+                refine_tol=self.tol, max_refine=self.maxr, data_summed=True,
+                out=(self.x, self.v, self.info, self.steps))
         return self.v
 
     def capture(self, warmup: int = 1):

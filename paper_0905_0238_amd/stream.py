@@ -112,7 +112,8 @@ class Stream:
             gram, rhs, trace = self.gram[:P], self.rhs[:P], self.trace[:P]
             p.assemble(self.G64, self.G32, d, prec, out=(gram, rhs, trace))
             p.solve(self.G64, d, gram, rhs, trace, self.lam, refine=mixed, refine_tol=self.tol,
-                    max_refine=self.maxr, out=(self.x[a:b], self.v, self.info[a:b], self.steps[a:b]))
+                    max_refine=self.maxr, data_summed=True,
+                    out=(self.x[a:b], self.v, self.info[a:b], self.steps[a:b]))
         return self.v
 
     def capture(self, prec=None, warmup: int = 1):

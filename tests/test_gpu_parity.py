@@ -228,6 +228,27 @@ def test_bf16x3_pivot_failure_escalates_to_fp64(refs):
     assert g <= 1e-6 and per <= 1e-6, (g, per)
 
 
+@pytest.mark.parametrize("prec", ["fp16x3", "bf16x3"])
+def test_solve_reuses_the_data_sums_of_assemble(refs, prec):
+    """edt_solve with data_summed takes the data sums that edt_assemble left in
+    the workspace: the same refined result, bit for bit, as summing again."""
+    s, r = _ref(refs, "layered-nz257")
+    p = E.Plan(s)
+    vel = _vel(s)
+    d = _dev(r["d_rows"])
+    g64, g32 = p.green(vel)
+    gram, rhs, trace = p.assemble(g64, g32, d, prec)
+    x0, v0, i0, s0 = p.solve(g64, d, gram.clone(), rhs, trace, s.lambda_rel, refine=True, refine_tol=1e-9,
+                             max_refine=10)
+    gram, rhs, trace = p.assemble(g64, g32, d, prec)
+    x1, v1, i1, s1 = p.solve(g64, d, gram, rhs, trace, s.lambda_rel, refine=True, refine_tol=1e-9,
+                             max_refine=10, data_summed=True)
+    for a, b in ((x0, x1), (v0, v1), (i0, i1), (s0, s1)):
+        assert torch.equal(a, b)
+    g, per = rel_errors(v1.cpu().numpy(), r["V"], r["pl"])
+    assert g <= 1e-6 and per <= 1e-6, (g, per)
+
+
 def test_depth_limits(refs):
     """nz > 256 is served by FP64 and the split Grams; FP32 and the adjoint
     reject it, and nz > 448 is rejected at every entry point."""
