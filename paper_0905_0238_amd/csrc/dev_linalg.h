@@ -124,7 +124,10 @@ constexpr int kSolveRed = 704;
 // CORR (a preconditioner inside an iteration) the correction is skipped.
 // L: lower triangle of a row-major nz x nz matrix (global); D: [nblk][32][32]
 // row-major lower-triangular inverses (global).  No step has a serial chain
-// longer than one block: 2 nblk dependent block steps.
+// longer than one block: 2 nblk dependent block steps.  None of the loads
+// depends on the right-hand side, so the next block's D_b, L_bb and first
+// panel chunk are requested while the current block is finished, and a block
+// step waits on global memory only when that latency exceeds its own work.
 // LDS: sred >= kSolveRed doubles, sD and sL >= 32 * CBP doubles each.
 // blockDim.x must be 256.
 template <bool CORR>
@@ -132,38 +135,75 @@ __device__ __forceinline__ void block_solve2(const double* __restrict__ L, const
                                              int nz, double* sx, double* sred, double* sD, double* sL) {
     const int tid = threadIdx.x;
     const int nblk = (nz + CB - 1) / CB;
-    // D_b and the lower triangle of L_bb (zero elsewhere: the upper part of
-    // the matrix is not part of L)
-    auto stage = [&](int b, int k0, int kb) {
-        for (int e = tid; e < CB * CB; e += 256) {
-            const int i = e >> 5, j = e & 31;
-            sD[i * CBP + j] = D[size_t(b) * CB * CB + e];
-            if constexpr (CORR) {
-                const double l = L[size_t(k0 + min(i, kb - 1)) * nz + k0 + min(j, kb - 1)];
-                sL[i * CBP + j] = (i < kb && j <= i) ? l : 0.0;
-            }
+    constexpr int PC = 8 * kPanelGroups;   // panel rows (columns) per chunk
+    // the next block's D_b and L_bb (4 elements per thread) and its first
+    // panel chunk, in flight
+    double nd[4], nl[4], nv[kPanelGroups];
+    auto fetch_diag = [&](int b) {
+        const int k0 = b * CB, kb = min(CB, nz - k0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + 256 * q, i = e >> 5, j = e & 31;
+            nd[q] = D[size_t(b) * CB * CB + e];
+            if constexpr (CORR) nl[q] = L[size_t(k0 + min(i, kb - 1)) * nz + k0 + min(j, kb - 1)];
         }
     };
+    // D_b and the lower triangle of L_bb (zero elsewhere: the upper part of
+    // the matrix is not part of L)
+    auto put_diag = [&](int b) {
+        const int k0 = b * CB, kb = min(CB, nz - k0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + 256 * q, i = e >> 5, j = e & 31;
+            sD[i * CBP + j] = nd[q];
+            if constexpr (CORR) sL[i * CBP + j] = (i < kb && j <= i) ? nl[q] : 0.0;
+        }
+    };
+    // forward: row i = tid / 8 of block b, columns c0 + tid % 8 + 8 u (< k0)
+    auto fetch_row = [&](double (&v)[kPanelGroups], int b, int c0) {
+        const int k0 = b * CB, kb = min(CB, nz - k0);
+        const double* row = L + size_t(k0 + min(tid >> 3, kb - 1)) * nz;
+        const int cmax = max(k0 - 1, 0);
+#pragma unroll
+        for (int u = 0; u < kPanelGroups; ++u) v[u] = row[min(c0 + (tid & 7) + 8 * u, cmax)];
+    };
+    // backward: column c = tid % 32 of block b, rows r0 + tid / 32 + 8 u (< nz)
+    auto fetch_col = [&](double (&v)[kPanelGroups], int b, int r0) {
+        const int k0 = b * CB, kb = min(CB, nz - k0);
+        const int col = k0 + min(tid & 31, kb - 1);
+#pragma unroll
+        for (int u = 0; u < kPanelGroups; ++u) v[u] = L[size_t(min(r0 + (tid >> 5) + 8 * u, nz - 1)) * nz + col];
+    };
+    fetch_diag(0);
+    fetch_row(nv, 0, 0);
     for (int b = 0; b < nblk; ++b) {
         const int k0 = b * CB, kb = min(CB, nz - k0);
         const int i = tid >> 3, part = tid & 7;   // row i of the block, 8 threads per row
-        stage(b, k0, kb);
+        put_diag(b);
         double s0 = 0.0, s1 = 0.0;
-        // all loads of a chunk of the row panel first (clamped, unrolled),
-        // then the products: one memory round trip per chunk
-        const double* row = L + size_t(k0 + min(i, kb - 1)) * nz;
-        for (int c0 = 0; c0 < k0; c0 += 8 * kPanelGroups) {
-            double lv[kPanelGroups];
-#pragma unroll
-            for (int u = 0; u < kPanelGroups; ++u) lv[u] = row[min(c0 + part + 8 * u, k0 - 1)];
+        auto row_dot = [&](const double (&v)[kPanelGroups], int c0) {
 #pragma unroll
             for (int u = 0; u < kPanelGroups; ++u) {
                 const int c = c0 + part + 8 * u;
-                const double l = (c < k0 && i < kb) ? lv[u] : 0.0;
-                const int cc = min(c, k0 - 1);
+                const double l = (c < k0 && i < kb) ? v[u] : 0.0;
+                const int cc = min(c, max(k0 - 1, 0));
                 s0 += l * sx[cc];
                 s1 += l * sx[nz + cc];
             }
+        };
+        row_dot(nv, 0);
+        for (int c0 = PC; c0 < k0; c0 += PC) {   // nz > PC + CB only
+            double lv[kPanelGroups];
+            fetch_row(lv, b, c0);
+            row_dot(lv, c0);
+        }
+        // the next block step's loads (the first backward block after the last)
+        if (b + 1 < nblk) {
+            fetch_diag(b + 1);
+            fetch_row(nv, b + 1, 0);
+        } else {
+            fetch_diag(b);
+            fetch_col(nv, b, k0 + CB);
         }
         s0 = sum8(s0);
         s1 = sum8(s1);
@@ -227,26 +267,33 @@ __device__ __forceinline__ void block_solve2(const double* __restrict__ L, const
     }
     for (int b = nblk - 1; b >= 0; --b) {
         const int k0 = b * CB, kb = min(CB, nz - k0);
-        stage(b, k0, kb);
+        put_diag(b);
         {
             const int c = tid & 31, g = tid >> 5;   // column c of the block, 8 row groups
             double s0 = 0.0, s1 = 0.0;
-            // rows r0 + g + 8u below the block, a chunk at a time
-            for (int r0 = k0 + CB; r0 < nz; r0 += 8 * kPanelGroups) {
-                double lv[kPanelGroups];
-#pragma unroll
-                for (int u = 0; u < kPanelGroups; ++u) lv[u] = L[size_t(min(r0 + g + 8 * u, nz - 1)) * nz + k0 + min(c, kb - 1)];
+            // rows k0 + CB + g + 8 u below the block, a chunk at a time
+            auto col_dot = [&](const double (&v)[kPanelGroups], int r0) {
 #pragma unroll
                 for (int u = 0; u < kPanelGroups; ++u) {
                     const int m = r0 + g + 8 * u;
-                    const double l = (m < nz && c < kb) ? lv[u] : 0.0;
+                    const double l = (m < nz && c < kb) ? v[u] : 0.0;
                     const int mm = min(m, nz - 1);
                     s0 += l * sx[mm];
                     s1 += l * sx[nz + mm];
                 }
+            };
+            col_dot(nv, k0 + CB);
+            for (int r0 = k0 + CB + PC; r0 < nz; r0 += PC) {
+                double lv[kPanelGroups];
+                fetch_col(lv, b, r0);
+                col_dot(lv, r0);
             }
             sred[g * 64 + c] = s0;
             sred[g * 64 + CB + c] = s1;
+        }
+        if (b > 0) {
+            fetch_diag(b - 1);
+            fetch_col(nv, b - 1, k0);   // rows below block b - 1 start at its k0 + CB = k0
         }
         __syncthreads();
         if (tid < 64) {

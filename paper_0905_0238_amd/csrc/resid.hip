@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void bsum_kernel(const int32_t* __restrict__ u
 // depths past nz get x = 0, so no per-element masking is needed; the depths
 // past nz are never stored.
 template <int ZPL, bool DATA>
-__global__ __launch_bounds__(256) void resid_kernel(const Item* __restrict__ items,
+__global__ __launch_bounds__(256, ZPL <= 4 ? 3 : (ZPL == 5 ? 2 : 1)) void resid_kernel(const Item* __restrict__ items,
                                                     const int32_t* __restrict__ sched,
                                                     const GRow* __restrict__ grow,
                                                     const double* __restrict__ gsc,
