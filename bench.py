@@ -61,7 +61,23 @@ def parse():
                     help="solve in pair-range batches (always on for config 5, the 3D 256 x 256 survey)")
     ap.add_argument("--batch-rows", type=int, default=100_000_000, help="data rows per batch at most")
     ap.add_argument("--batch-pairs", type=int, default=4096, help="pairs per batch at most")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run three plain 1 GiB device copies (the reference for the HBM byte "
+                         "counters FETCH_SIZE / WRITE_SIZE) and exit")
     return ap.parse_args()
+
+
+def copy_calibration(torch):
+    """Three launches of a plain device copy that reads and writes exactly 1 GiB:
+    under rocprofv3 --pmc it gives the counter reading of known traffic."""
+    n = 1 << 27   # 128 Mi doubles
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_launch": n * 8, "launches": 3}))
 
 
 def synth_inputs(s, plan, vel, torch):
@@ -408,15 +424,18 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {a.gpus} is not supported "
-              "(the +-k_m pairs would shard across GPUs with no exchange, see DESIGN.md)",
+              "(the +-k_m pairs are independent problems: a multi-GPU run would give each GPU "
+              "its own pair range, with no exchange)",
               file=sys.stderr)
         sys.exit(2)
     import torch
-    import paper_0905_0238_amd as E
-    from edt_inputs import make_config, CONFIG_NAMES
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if a.copy_calibration:
+        return copy_calibration(torch)
+    import paper_0905_0238_amd as E
+    from edt_inputs import make_config, CONFIG_NAMES
     s = make_config(a.config)
     if a.stream or a.config == 5:
         return stream_main(a, s, torch, E, CONFIG_NAMES)
