@@ -229,6 +229,25 @@ def roofline(plan, s, ktimes, prec, steps):
                  "per_launch": f"lower triangles read + written {by:.4g} B"}
 
 
+def gram_mfma(plan, s, ktimes):
+    """MFMA use of one precision's Gram kernel: the algorithmic 2 U nz (nz+1)
+    flop per launch and, for the split and FP64 kernels, the MFMA work the
+    kernel actually issues (three 16-bit products per algorithmic product,
+    padding stages included), each against the dense peak of its input type."""
+    name = next((k for k in ktimes if k.startswith("gram_") and k != "gram_reduce"), None)
+    if name is None:
+        return None
+    dt = {"gram_bf16x3": "bf16", "gram_fp16x3": "fp16", "gram_fp32": "fp32", "gram_fp64": "fp64"}[name]
+    avg_s = ktimes[name]["avg_ms"] * 1e-3
+    alg = 2.0 * plan.info["n_urows"] * s.nz * (s.nz + 1) / avg_s / 1e12
+    out = {"kernel": name, "avg_ms": ktimes[name]["avg_ms"], "peak_tflops": PEAK[dt],
+           "algorithmic_tflops": alg, "algorithmic_frac": alg / PEAK[dt]}
+    ex = {"bf16": _bf16_mfma_flops, "fp16": _bf16_mfma_flops, "fp64": _f64_mfma_flops}.get(dt)
+    if ex is not None:
+        out["issued_frac"] = ex(plan, s.nz) / avg_s / 1e12 / PEAK[dt]
+    return out
+
+
 def cpu_baseline_leg(s, plan, pipes, n_pairs_sample, torch):
     """Time the FP64 oracle on a seeded sample of pairs (host cores), and state
     the GPU error on the same oracle data for those pairs."""
@@ -477,8 +496,9 @@ def main():
     t_main = res[main_prec]["ms_per_step"]
     value = plan.n_km / (t_main * 1e-3)
     dom, roof = roofline(plans[main_prec], s, res[main_prec]["kernels"], main_prec, res[main_prec]["_steps"])
-    for v in res.values():
+    for pr, v in res.items():
         v.pop("_steps")
+        v["gram_mfma"] = gram_mfma(plans[pr], s, v["kernels"])
     roof["kernel"] = dom
     roof["traffic"] = measured_traffic(dom, CONFIG_NAMES[a.config])
     if roof["traffic"] is not None:
