@@ -71,6 +71,8 @@ __device__ __forceinline__ void split_pack(float x0, float x1, uint32_t& hi, uin
 // tiles between NT blocks of a later super-block (the I set) and NTJ blocks
 // of an earlier one (the J set).  Depth counts up to 256 need one diagonal
 // task; larger ones add the super-blocks below and the rectangles between.
+// Rectangle tiles are numbered column by column, so that an MFMA wave's tiles
+// share their J blocks and read every I block.
 template <int NT, int NTJ>
 struct SplitCfg {
     static constexpr bool RECT = NTJ > 0;
@@ -78,8 +80,8 @@ struct SplitCfg {
     static constexpr int NTL = RECT ? NT * NTJ : NT * (NT + 1) / 2;
     static constexpr int TPW = (NTL + 3) / 4;
     static constexpr int STR = 24;   // 16-bit values per LDS depth row: 16 real rows + 8 pad (48 B)
-    __host__ __device__ static constexpr int tI(int t) { return RECT ? t / NTJ : tri_I(t); }
-    __host__ __device__ static constexpr int tJ(int t) { return RECT ? t % NTJ : tri_J(t); }
+    __host__ __device__ static constexpr int tI(int t) { return RECT ? t % NT : tri_I(t); }
+    __host__ __device__ static constexpr int tJ(int t) { return RECT ? t / NT : tri_J(t); }
     // blocks of the I (J) set read by the tiles [t0, t1)
     __host__ __device__ static constexpr uint32_t maskI(int t0, int t1) {
         uint32_t m = 0;
@@ -1168,11 +1170,14 @@ static hipError_t launch_gram_task(const edt_plan* p, edt_precision prec, const 
         hipLaunchKernelGGL((gram_split3_kernel<NT, NTJ, true>), dim3(nb), dim3(512),
                            row_lds_bytes(p->chunk_rows), st, items, sched, grow, rd.ub32, g32, rd.gmax,
                            p->nz, zI0, zJ0, ntot, static_cast<float*>(part), rpart, p->chunk_rows);
-    else if (prec == EDT_FP64)
-        hipLaunchKernelGGL((gram_f64_kernel<NT, NTJ>), dim3(grid), dim3(512), 0, st, items, sched, grow,
-                           dptr<const double>(p, p->lay.gsc), rd.ubw, g64, p->nz, zI0, zJ0, ntot,
-                           static_cast<double*>(part), rpart, rd.only, int(nb), rd.gate);
-    else if constexpr (NTJ == 0)
+    else if (prec == EDT_FP64) {
+        if constexpr (NTJ <= 4)
+            hipLaunchKernelGGL((gram_f64_kernel<NT, NTJ>), dim3(grid), dim3(512), 0, st, items, sched, grow,
+                               dptr<const double>(p, p->lay.gsc), rd.ubw, g64, p->nz, zI0, zJ0, ntot,
+                               static_cast<double*>(part), rpart, rd.only, int(nb), rd.gate);
+        else
+            return hipErrorInvalidValue;   // FP64 rectangles are half super-blocks
+    } else if constexpr (NTJ == 0)
         hipLaunchKernelGGL(gram_f32_kernel<NT>, dim3(nb), dim3(256), row_lds_bytes(p->chunk_rows), st,
                            items, sched, grow, rd.ub32, g32, p->nz, static_cast<float*>(part), rpart,
                            p->chunk_rows);
@@ -1180,6 +1185,11 @@ static hipError_t launch_gram_task(const edt_plan* p, edt_precision prec, const 
         return hipErrorInvalidValue;   // FP32 Gram: depth counts up to 256 only
     return hipGetLastError();
 }
+
+// Split rectangles over a whole earlier super-block (8 J blocks) for I sets
+// of at most this many blocks: 8 NT tiles, 2 NT per MFMA wave, fit its
+// registers; larger I sets take the two halves of the super-block in turn.
+constexpr int kWideRectMaxNT = 5;
 
 template <int NTJ>
 static hipError_t launch_gram_nt(int nt, const edt_plan* p, edt_precision prec, const zd* g64,
@@ -1189,6 +1199,19 @@ static hipError_t launch_gram_nt(int nt, const edt_plan* p, edt_precision prec, 
 #define EDT_CASE(N) \
     case N: return launch_gram_task<N, NTJ>(p, prec, g64, g32, rd, part, rpart, zI0, zJ0, ntot, st);
         EDT_CASE(1) EDT_CASE(2) EDT_CASE(3) EDT_CASE(4) EDT_CASE(5) EDT_CASE(6) EDT_CASE(7) EDT_CASE(8)
+#undef EDT_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+static hipError_t launch_gram_wide(int nt, const edt_plan* p, edt_precision prec, const zd* g64,
+                                   const float2* g32, const GramRowData& rd, void* part, double* rpart,
+                                   int zI0, int zJ0, int ntot, hipStream_t st) {
+    static_assert(kWideRectMaxNT == 5, "the cases below");
+    switch (nt) {
+#define EDT_CASE(N) \
+    case N: return launch_gram_task<N, 8>(p, prec, g64, g32, rd, part, rpart, zI0, zJ0, ntot, st);
+        EDT_CASE(1) EDT_CASE(2) EDT_CASE(3) EDT_CASE(4) EDT_CASE(5)
 #undef EDT_CASE
         default: return hipErrorInvalidValue;
     }
@@ -1218,6 +1241,8 @@ template <int NT>
 static hipError_t configure_gram_nt() {
     hipError_t e = configure_gram_task<NT, 0>();
     if (e == hipSuccess) e = configure_gram_task<NT, 4>();
+    if constexpr (NT <= kWideRectMaxNT)
+        if (e == hipSuccess) e = configure_gram_task<NT, 8>();
     return e;
 }
 
@@ -1242,8 +1267,10 @@ hipError_t launch_gmax(const edt_plan* p, const float2* g32, float* gmax, hipStr
 }
 
 // The item partials of all tasks: a diagonal task per depth super-block and,
-// for each pair of super-blocks sbi > sbj, two rectangular tasks between
-// super-block sbi and the halves (128 depths) of super-block sbj.
+// for each pair of super-blocks sbi > sbj, the rectangle between them: for
+// the split Grams with an I set of at most kWideRectMaxNT blocks one task
+// over all of super-block sbj (which is full: only the last one can be
+// partial), otherwise two tasks over its halves (128 depths).
 hipError_t launch_gram(const edt_plan* p, edt_precision prec, const zd* g64, const float2* g32,
                        const zd* ubw, const float4* ub32, const float* gmax, void* part, double* rpart,
                        hipStream_t st, const int32_t* only, const int32_t* gate) {
@@ -1258,13 +1285,21 @@ hipError_t launch_gram(const edt_plan* p, edt_precision prec, const zd* g64, con
             launch_gram_nt<0>(nt_of(sb), p, prec, g64, g32, rd, part, rpart, kSuperDepth * sb, 0, ntot, st);
         if (e != hipSuccess) return e;
     }
+    const bool split = prec == EDT_BF16X3 || prec == EDT_FP16X3;
     for (int sbi = 1; sbi < ns; ++sbi)
-        for (int sbj = 0; sbj < sbi; ++sbj)
+        for (int sbj = 0; sbj < sbi; ++sbj) {
+            if (split && nt_of(sbi) <= kWideRectMaxNT) {
+                const hipError_t e = launch_gram_wide(nt_of(sbi), p, prec, g64, g32, rd, part, rpart,
+                                                      kSuperDepth * sbi, kSuperDepth * sbj, ntot, st);
+                if (e != hipSuccess) return e;
+                continue;
+            }
             for (int h = 0; h < 2; ++h) {
                 const hipError_t e = launch_gram_nt<4>(nt_of(sbi), p, prec, g64, g32, rd, part, rpart,
                                                        kSuperDepth * sbi, kSuperDepth * sbj + 128 * h, ntot, st);
                 if (e != hipSuccess) return e;
             }
+        }
     return hipSuccess;
 }
 

@@ -36,6 +36,9 @@ def _cases():
         # past one 256-depth super-block: a 1-depth second block, and a ragged one
         "layered-nz257": lambda: layered_small(nz=257, N=16, nf=4, seed=4),
         "layered-nz400": lambda: layered_small(nz=400, N=24, nf=5, seed=6, dz=5.0),
+        # one layer: the Green's function is the closed form exp(i k_z |z|) i / (2 k_z)
+        "homogeneous": lambda: make_custom(N=32, nz=33, dx=12.5, dz=8.0, freqs=(6.0, 17.0, 29.0, 41.0),
+                                           vel=(2300.0,), zif=(), noise_rel=0.05, seed=11),
         "3d-small": lambda: make_custom(dim=3, N=12, Nh=6, nz=37, dx=25.0, dz=10.0,
                                         freqs=(8.0, 14.0, 20.0), vel=(1800.0, 2500.0, 2100.0),
                                         zif=(60.0, 200.0), noise_rel=0.05, seed=5),
@@ -55,7 +58,7 @@ def _ref(refs, name):
     return s, r
 
 
-@pytest.mark.parametrize("name", ["cfg1", "layered-nz40", "3d-small"])
+@pytest.mark.parametrize("name", ["cfg1", "layered-nz40", "homogeneous", "3d-small"])
 def test_green_tables(refs, name):
     s, r = _ref(refs, name)
     p = E.Plan(s)
@@ -89,8 +92,8 @@ def test_forward_born_rows(refs, name):
     assert np.max(np.abs(d - clean)) <= 1e-12 * np.max(np.abs(clean))
 
 
-@pytest.mark.parametrize("name", ["cfg1", "layered-nz40", "layered-nz200", "layered-nz257", "layered-nz400",
-                                  "3d-small"])
+@pytest.mark.parametrize("name", ["cfg1", "layered-nz40", "homogeneous", "layered-nz200", "layered-nz257",
+                                  "layered-nz400", "3d-small"])
 def test_fp64_gram_rhs_trace(refs, name):
     s, r = _ref(refs, name)
     p = E.Plan(s)
@@ -109,8 +112,8 @@ def test_fp64_gram_rhs_trace(refs, name):
         assert abs(trace[i] - tr) <= 1e-12 * tr
 
 
-@pytest.mark.parametrize("name", ["cfg1", "layered-nz40", "layered-nz200", "layered-nz257", "layered-nz400",
-                                  "3d-small"])
+@pytest.mark.parametrize("name", ["cfg1", "layered-nz40", "homogeneous", "layered-nz200", "layered-nz257",
+                                  "layered-nz400", "3d-small"])
 def test_fp64_solve(refs, name):
     s, r = _ref(refs, name)
     p = E.Plan(s)
@@ -124,8 +127,8 @@ def test_fp64_solve(refs, name):
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "fp16x3", "fp32"])
-@pytest.mark.parametrize("name", ["cfg1", "layered-nz40", "layered-nz200", "layered-nz257", "layered-nz400",
-                                  "3d-small"])
+@pytest.mark.parametrize("name", ["cfg1", "layered-nz40", "homogeneous", "layered-nz200", "layered-nz257",
+                                  "layered-nz400", "3d-small"])
 def test_mixed_solve_with_refinement(refs, name, prec):
     s, r = _ref(refs, name)
     if prec == "fp32" and s.nz > 256:
