@@ -13,9 +13,9 @@
 //
 // Layout: a 256-thread block per work item; each wave takes its own rows,
 // lanes span depth (ZPL depths per lane).  A x needs a sum over depth per
-// row: four rows at a time are reduced with a transposing butterfly of lane
-// swaps and DPP moves, so a row costs about one cross-lane exchange per lane
-// instead of six.
+// row: four rows at a time (two beyond 256 depths) are reduced with a
+// transposing butterfly of lane swaps and DPP moves, so a row costs about one
+// cross-lane exchange per lane instead of six.
 
 #include "dev_common.h"
 
@@ -85,6 +85,40 @@ __device__ __forceinline__ void butterfly16(double (&a)[16], double (&out)[16], 
     for (int k = 0; k < 16; ++k) out[k] = readlane_d(s, k << 2);
 }
 
+// The same for 8 values (two rows): three halving steps leave lane l with
+// index 4*b5 + 2*b4 + b3; the half-row mirror (which flips bits 0-2) and two
+// quad exchanges sum the 8 lanes of each group.
+__device__ __forceinline__ void butterfly8(double (&a)[8], double (&out)[8], int lane) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {   // bit 5
+        double x = a[i], y = a[i + 4];
+        swap32_d(x, y);
+        a[i] = x + y;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {   // bit 4
+        double x = a[i], y = a[i + 2];
+        swap16_d(x, y);
+        a[i] = x + y;
+    }
+    const bool b3 = lane & 8;
+    const double lo = a[0] + dpp_d<kDppRowMirror>(a[0]);
+    const double hi = a[1] + dpp_d<kDppRowMirror>(a[1]);
+    double s = b3 ? hi : lo;   // bit 3
+    s += dpp_d<kDppRowHalfMirror>(s);
+    s += dpp_d<kDppQuadXor2>(s);
+    s += dpp_d<kDppQuadXor1>(s);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) out[k] = readlane_d(s, k << 3);
+}
+
+template <int NV>
+__device__ __forceinline__ void butterfly(double (&a)[NV], double (&out)[NV], int lane) {
+    static_assert(NV == 8 || NV == 16, "two or four rows");
+    if constexpr (NV == 16) butterfly16(a, out, lane);
+    else butterfly8(a, out, lane);
+}
+
 // ub[u] = (sum of b+ over the data rows of unique row u, sum of b-).
 // Optionally also the data as the Gram kernels consume them (the right-hand
 // side c = Re(A^H B) with A = W g g):
@@ -134,8 +168,8 @@ __global__ __launch_bounds__(256) void bsum_kernel(const int32_t* __restrict__ u
 // Rows past the item (padding of the last batch) get zero data and weight and
 // depths past nz get x = 0, so no per-element masking is needed; the depths
 // past nz are never stored.
-template <int ZPL, bool DATA>
-__global__ __launch_bounds__(256, ZPL <= 4 ? 3 : (ZPL == 5 ? 2 : 1)) void resid_kernel(const Item* __restrict__ items,
+template <int ZPL, int RB, bool DATA>
+__global__ __launch_bounds__(256, ZPL <= 4 ? 3 : 2) void resid_kernel(const Item* __restrict__ items,
                                                     const int32_t* __restrict__ sched,
                                                     const GRow* __restrict__ grow,
                                                     const double* __restrict__ gsc,
@@ -169,12 +203,12 @@ __global__ __launch_bounds__(256, ZPL <= 4 ? 3 : (ZPL == 5 ? 2 : 1)) void resid_
 #pragma unroll
     for (int q = 0; q < ZPL; ++q) acc[0][q] = acc[1][q] = 0.0;
 
-    for (int b0 = 0; b0 < n; b0 += 16) {
-        // the 4 rows of this wave in the batch
-        zd gr[4][ZPL], gs[4][ZPL], bp[4], bm[4];
-        double w2[4];
+    for (int b0 = 0; b0 < n; b0 += 4 * RB) {
+        // the RB rows of this wave in the batch
+        zd gr[RB][ZPL], gs[RB][ZPL], bp[RB], bm[RB];
+        double w2[RB];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < RB; ++j) {
             const int r = b0 + 4 * j + wv;
             const bool on = r < n;
             const int64_t row = int64_t(it.row_begin) + min(r, n - 1);
@@ -195,14 +229,14 @@ __global__ __launch_bounds__(256, ZPL <= 4 ? 3 : (ZPL == 5 ? 2 : 1)) void resid_
                 gs[j][q] = g64[size_t(g.off_s) + zc];
             }
         }
-        zd P[4][ZPL];
+        zd P[RB][ZPL];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < RB; ++j)
 #pragma unroll
             for (int q = 0; q < ZPL; ++q) P[j][q] = gr[j][q] * gs[j][q];
-        double v[16], y[16];
+        double v[4 * RB], y[4 * RB];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < RB; ++j) {
             double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
 #pragma unroll
             for (int q = 0; q < ZPL; ++q) {
@@ -216,9 +250,9 @@ __global__ __launch_bounds__(256, ZPL <= 4 ? 3 : (ZPL == 5 ? 2 : 1)) void resid_
             v[4 * j + 2] = a2;
             v[4 * j + 3] = a3;
         }
-        butterfly16(v, y, lane);
+        butterfly<4 * RB>(v, y, lane);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < RB; ++j) {
             const zd cp{bp[j].x - w2[j] * y[4 * j], bp[j].y - w2[j] * y[4 * j + 1]};
             const zd cm{bm[j].x - w2[j] * y[4 * j + 2], bm[j].y - w2[j] * y[4 * j + 3]};
 #pragma unroll
@@ -304,6 +338,10 @@ constexpr int kResidGrid = 4096;
 template <int ZPL>
 static hipError_t launch_resid_z(const edt_plan* p, const zd* g64, const zd* ubw, const double* x,
                                  const int32_t* conv, double* rpart, const int32_t* active, hipStream_t st) {
+    // rows per wave per batch: four (one 16-value reduction) up to 256
+    // depths; two beyond, where four rows' table values would not leave
+    // registers for a second wave per SIMD
+    constexpr int kRB = ZPL <= 4 ? 4 : 2;
     const int nit = int(p->rsched.size());
     if (nit == 0) return hipSuccess;
     const unsigned grid = unsigned(std::min(nit, kResidGrid));
@@ -312,10 +350,10 @@ static hipError_t launch_resid_z(const edt_plan* p, const zd* g64, const zd* ubw
     const GRow* grow = dptr<const GRow>(p, p->lay.grow);
     const double* gsc = dptr<const double>(p, p->lay.gsc);
     if (ubw)
-        hipLaunchKernelGGL((resid_kernel<ZPL, true>), dim3(grid), dim3(256), 0, st, items, sched, grow, gsc, ubw,
+        hipLaunchKernelGGL((resid_kernel<ZPL, kRB, true>), dim3(grid), dim3(256), 0, st, items, sched, grow, gsc, ubw,
                            g64, p->nz, x, conv, rpart, nit, active);
     else
-        hipLaunchKernelGGL((resid_kernel<ZPL, false>), dim3(grid), dim3(256), 0, st, items, sched, grow, gsc,
+        hipLaunchKernelGGL((resid_kernel<ZPL, kRB, false>), dim3(grid), dim3(256), 0, st, items, sched, grow, gsc,
                            ubw, g64, p->nz, x, conv, rpart, nit, active);
     return hipGetLastError();
 }
