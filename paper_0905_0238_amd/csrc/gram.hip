@@ -539,8 +539,7 @@ __global__ __launch_bounds__(512, 1) void gram_split3u_kernel(const Item* __rest
     const int z = tid & 255;
     const int hf = __builtin_amdgcn_readfirstlane(tid >> 8);   // rows 4 hf .. 4 hf + 3 of a stage
     const bool on = z < nzI;
-    // unsigned: the table loads take a scalar base and a 32-bit lane offset
-    const uint32_t zc = uint32_t(zI0 + min(z, nzI - 1));
+    const uint32_t zc = uint32_t(zI0 + min(z, nzI - 1));   // clamped: loads are unconditional
     if (z >= nzI && z < C::NZP) {   // depths past nz stay zero for the whole item
         const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
