@@ -20,6 +20,8 @@ solve   the normal equations with relative Tikhonov damping, the
 grad    gradient of a model misfit with respect to data, damping and layer
         velocities (adjoint of the normal equations + tangent-mode G0).
 born    brute-force space-domain Born data on tiny periodic grids.
+tsvd    the paper's own solver: truncated SVD of each pair's system (through
+        the eigen-decomposition of its Gram), with a relative tolerance.
 
 Every function is pinned by a test in ``tests/test_oracle_*.py`` against a
 closed form, an invariant, a library routine that solves the same problem a
