@@ -61,6 +61,9 @@ def parse():
                     help="solve in pair-range batches (always on for config 5, the 3D 256 x 256 survey)")
     ap.add_argument("--batch-rows", type=int, default=100_000_000, help="data rows per batch at most")
     ap.add_argument("--batch-pairs", type=int, default=4096, help="pairs per batch at most")
+    ap.add_argument("--tsvd", type=float, default=1e-2,
+                    help="relative tolerance of the truncated-SVD leg (the paper's own solver), "
+                         "timed after the main passes; 0 skips it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three plain 1 GiB device copies (the reference for the HBM byte "
                          "counters FETCH_SIZE / WRITE_SIZE) and exit")
@@ -246,6 +249,58 @@ def gram_mfma(plan, s, ktimes):
     if ex is not None:
         out["issued_frac"] = ex(plan, s.nz) / avg_s / 1e12 / PEAK[dt]
     return out
+
+
+def tsvd_leg(plan, vel, d, tol_rel, reps, torch):
+    """The paper's truncated-SVD solve (edt_tsvd) on the FP64 Gram of the same
+    data: time per solve (the Gram is copied in first, since the solve
+    overwrites it; the copy is not timed), sign steps, and the rate of the sign
+    iteration's FP64 products -- symmetric, so nz^2 (nz + 1) flop each (the
+    lower triangle), two per step of every pair still iterating -- over the
+    library timer's time of the sign steps, against the FP64 MFMA peak."""
+    import ctypes as C
+    from paper_0905_0238_amd import _lib
+    g64, _ = plan.green(vel, want32=False)
+    gram0, rhs, _ = plan.assemble(g64, None, d, "fp64")
+    gram = torch.empty_like(gram0)
+    n = C.c_size_t(0)
+    _lib.check(_lib.load().edt_tsvd_work_bytes(plan._h, C.byref(n)), "edt_tsvd_work_bytes")
+    work = torch.empty(max(int(n.value), 256), dtype=torch.uint8, device="cuda")
+    P, nz = plan.n_pairs, plan.nz
+    out = (torch.empty(P, 2, nz, dtype=torch.float64, device="cuda"),
+           torch.empty(plan.n_km, nz, dtype=torch.complex128, device="cuda"),
+           torch.empty(P, dtype=torch.int32, device="cuda"), torch.zeros(P, dtype=torch.int32, device="cuda"))
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tot = 0.0
+    for r in range(reps + 1):
+        gram.copy_(gram0)
+        ev0.record()
+        plan.tsvd(gram, rhs, tol_rel, out=out, tsvd_work=work)
+        ev1.record()
+        torch.cuda.synchronize()
+        if r > 0:
+            tot += ev0.elapsed_time(ev1)
+    ms = tot / reps
+    gram.copy_(gram0)
+    torch.cuda.synchronize()
+    plan.timing(True)
+    plan.timing_read()
+    plan.tsvd(gram, rhs, tol_rel, out=out, tsvd_work=work)
+    kt = plan.timing_read()
+    plan.timing(False)
+    it = out[3].cpu().numpy().astype(np.float64)
+    info = out[2].cpu().numpy()
+    fl = float(np.sum(it)) * 2 * float(nz) ** 2 * (nz + 1)
+    sign_ms = kt.get("tsvd sign step", (float("nan"), 0))[0]
+    ach = fl / (sign_ms * 1e-3) / 1e12
+    return {"tol_rel": tol_rel, "ms_per_solve": ms,
+            "sign_steps": {"max": int(it.max()), "mean": float(it.mean())},
+            "info_noconv": int(np.sum(info == -2)),
+            "kernels_ms": {k: round(v[0], 4) for k, v in kt.items()},
+            "sign_gemm": {"bound": "mfma", "achieved": ach, "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                          "frac": ach / PEAK["fp64"],
+                          "per_solve": f"2 symmetric products x nz^2 (nz+1) flop x sign steps summed over "
+                                       f"pairs = {fl:.4g} flop"}}
 
 
 def cpu_baseline_leg(s, plan, pipes, n_pairs_sample, torch):
@@ -521,6 +576,8 @@ def main():
         out["speedup_vs_fp64"] = res["fp64"]["ms_per_step"] / t_main
     out["detail"] = {k: {kk: vv for kk, vv in v.items()} for k, v in res.items()}
     out["detail"]["plan_s"] = plan_s
+    if a.tsvd > 0 and "fp64" in plans:
+        out["detail"]["tsvd"] = tsvd_leg(plans["fp64"], vel, d, a.tsvd, 3, torch)
     if not a.no_cpu:
         base, errs = cpu_baseline_leg(s, plan, pipes, a.cpu_pairs, torch)
         out["cpu_baseline"] = base

@@ -298,6 +298,30 @@ edt_status edt_solve(const edt_plan* plan, const edt_c128* g64, const edt_c128* 
                      int32_t* steps, void* work, hipStream_t stream);
 
 /*
+ * The paper's own solver (Section 3.1): per pair, the truncated-SVD solution
+ * x+- = sum_{s_j^2 >= sigma^2} v_j (v_j . c+-) / s_j^2, where s_j^2 and v_j
+ * are the eigenpairs of the pair's Gram (the squared singular values and the
+ * right singular vectors of its real rows), with a relative tolerance
+ * sigma^2 = tol_rel^2 ||G||_F (Frobenius norm).  Computed without an
+ * eigen-decomposition: the spectral projector P onto eigenvalues >= sigma^2
+ * comes from the matrix sign of G - sigma^2 I by Newton-Schulz steps (FP64
+ * MFMA, at most max_iter <= 200, a pair stopping once ||X^2 - I||_F <= 1e-9),
+ * then (G + sigma^2 (I - P)) x = P c is solved by the FP64 Cholesky path.
+ * gram: in, the lower triangles from edt_assemble (use EDT_FP64 for an FP64
+ * result); out, the factor of G + sigma^2 (I - P).  rhs: [P][2][nz] from
+ * edt_assemble.  x, v_out, info as edt_solve; info is EDT_INFO_NOCONV for a
+ * pair whose sign iteration did not converge (an eigenvalue within rounding
+ * of sigma^2 has no definite side) and EDT_INFO_EMPTY for an empty pair (x =
+ * 0).  iters[p]: sign steps taken (device, int32).  work: the plan's
+ * workspace; tsvd_work: device, >= edt_tsvd_work_bytes (three nz x nz FP64
+ * matrices per pair and small per-pair state).
+ */
+edt_status edt_tsvd_work_bytes(const edt_plan* plan, size_t* bytes);
+edt_status edt_tsvd(const edt_plan* plan, double* gram, const double* rhs, double tol_rel, int max_iter,
+                    double* x, edt_c128* v_out, int32_t* info, int32_t* iters, void* work, void* tsvd_work,
+                    hipStream_t stream);
+
+/*
  * Born forward map (eq. DMV): d_rows[r] = (A_r . v_in[u_p], A_r . v_in[-u_p]),
  * A_r = w_f^2 dz g(k_r) g(k_s), for every row r of pair p.
  * v_in: [n_km][nz] complex128; d_rows: [n_rows][2] complex128.

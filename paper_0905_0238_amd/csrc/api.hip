@@ -2,6 +2,7 @@
 // caller's stream.  No device memory is allocated here; all scratch lives in
 // the caller's workspace (layout from edt::work_layout).
 
+#include <cmath>
 #include <cstdio>
 #include <string>
 
@@ -37,6 +38,11 @@ hipError_t launch_adjoint(const edt_plan* p, const double* vel, const zd* g64, c
                           const double* chol, const double* trace, const double* x, double lambda_rel,
                           const zd* grad_v, zd* grad_d, double* grad_lambda, double* grad_vel,
                           unsigned char* work, hipStream_t st);
+hipError_t launch_tsvd_init(const edt_plan* p, const double* gram, double tol_rel, unsigned char* tw,
+                            int32_t* iters, hipStream_t st);
+hipError_t launch_tsvd_step(const edt_plan* p, int k, unsigned char* tw, int32_t* iters, hipStream_t st);
+hipError_t launch_tsvd_final(const edt_plan* p, double* gram, const double* rhs, unsigned char* tw,
+                             const int32_t* iters, hipStream_t st);
 size_t chol_lds_bytes(int nz);
 hipError_t configure_kernels();
 
@@ -281,6 +287,53 @@ edt_status edt_solve(const edt_plan* p, const edt_c128* g64, const edt_c128* d_r
         }
     }
     EDT_TRY(launch_recombine(p, x, refine, conv, info, reinterpret_cast<zd*>(v_out), stream), "recombine");
+    return EDT_OK;
+}
+
+edt_status edt_tsvd_work_bytes(const edt_plan* p, size_t* bytes) {
+    if (!p || !bytes) {
+        set_error("null argument");
+        return EDT_EINVAL;
+    }
+    *bytes = tsvd_layout(p).total;
+    return EDT_OK;
+}
+
+edt_status edt_tsvd(const edt_plan* p, double* gram, const double* rhs, double tol_rel, int max_iter, double* x,
+                    edt_c128* v_out, int32_t* info, int32_t* iters, void* work, void* tsvd_work,
+                    hipStream_t stream) {
+    edt_status s = check_plan(p);
+    if (s != EDT_OK) return s;
+    if (!gram || !rhs || !x || !v_out || !info || !iters || !work || !tsvd_work) {
+        set_error("missing argument");
+        return EDT_EINVAL;
+    }
+    if (!(tol_rel >= 0.0) || !std::isfinite(tol_rel)) {
+        set_error("tol_rel must be finite and >= 0");
+        return EDT_EINVAL;
+    }
+    if (max_iter < 1 || max_iter > kMaxSignIter) {
+        set_error("max_iter must be in [1, " + std::to_string(kMaxSignIter) + "]");
+        return EDT_EINVAL;
+    }
+    const WorkLayout wl = work_layout(p);
+    unsigned char* w = static_cast<unsigned char*>(work);
+    unsigned char* tw = static_cast<unsigned char*>(tsvd_work);
+    const TsvdLayout tl = tsvd_layout(p);
+    EDT_TRY(launch_tsvd_init(p, gram, tol_rel, tw, iters, stream), "tsvd init");
+    for (int k = 0; k < max_iter; ++k) EDT_TRY(launch_tsvd_step(p, k, tw, iters, stream), "tsvd sign step");
+    EDT_TRY(launch_tsvd_final(p, gram, rhs, tw, iters, stream), "tsvd projector");
+    // (G + sigma^2 (I - P)) x = P c by the factorisation with no damping and
+    // the corrected block solves
+    EDT_TRY(launch_chol(p, gram, reinterpret_cast<const double*>(tw + tl.tau2),
+                        reinterpret_cast<const double*>(tw + tl.rhs), 0.0, reinterpret_cast<double*>(w + wl.lam),
+                        reinterpret_cast<double*>(w + wl.dinv), x, info, reinterpret_cast<int32_t*>(w + wl.conv),
+                        reinterpret_cast<int32_t*>(w + wl.aux), stream, 0, 1, nullptr),
+            "tsvd cholesky");
+    // pairs whose sign iteration did not converge are reported as such
+    EDT_TRY(launch_recombine(p, x, 1, reinterpret_cast<const int32_t*>(tw + tl.conv), info,
+                             reinterpret_cast<zd*>(v_out), stream),
+            "recombine");
     return EDT_OK;
 }
 

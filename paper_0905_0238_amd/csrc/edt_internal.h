@@ -41,6 +41,7 @@ constexpr int kMaxDepth = 448;
 constexpr int kMaxAdjointDepth = 256;
 // Refinement sweeps of one solve at most (device counters per sweep).
 constexpr int kMaxRefine = 62;
+constexpr int kMaxSignIter = 200;   // sign-iteration steps of the truncated-SVD solve at most
 constexpr int n_super(int nz) { return (nz + kSuperDepth - 1) / kSuperDepth; }
 constexpr int rpart_width(int nz) { return 2 * nz + n_super(nz); }
 
@@ -140,6 +141,18 @@ struct WorkLayout {
     size_t total;
 };
 WorkLayout work_layout(const edt_plan* p);
+
+// Layout (bytes) of the separate scratch of the truncated-SVD solve.
+struct TsvdLayout {
+    size_t x0, x1;   // [P][nz][nz] FP64 sign iterates (ping-pong)
+    size_t y;        // [P][nz][nz] FP64 X^2
+    size_t rhs;      // [P][2][nz] FP64 projected right-hand sides P c
+    size_t tau2;     // [P] FP64 truncation threshold sigma^2
+    size_t dpart;    // [P][nt (nt+1)/2] FP64 lower-tile partials of ||X^2 - I||_F^2
+    size_t conv;     // [P] int32 sign iteration converged
+    size_t total;
+};
+TsvdLayout tsvd_layout(const edt_plan* p);
 size_t gram_part_bytes_per_item(const edt_plan* p);
 
 }  // namespace edt

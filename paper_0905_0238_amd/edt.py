@@ -205,6 +205,27 @@ class Plan:
                                          _ptr(steps), _ptr(self._work), _stream()), "edt_solve")
         return x, v, info, steps
 
+    def tsvd(self, gram, rhs, tol_rel, max_iter=100, out=None, tsvd_work=None):
+        """The paper's truncated-SVD solve from an assembled Gram (overwritten):
+        (x[P, 2, nz], v[n_km, nz] complex128, info[P], iters[P])."""
+        self.upload()
+        L = _lib.load()
+        P, nz = self.n_pairs, self.nz
+        if tsvd_work is None:
+            nb = C.c_size_t(0)
+            _lib.check(L.edt_tsvd_work_bytes(self._h, C.byref(nb)), "edt_tsvd_work_bytes")
+            tsvd_work = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=self.device)
+        if out is None:
+            x = torch.empty(P, 2, nz, dtype=torch.float64, device=self.device)
+            v = self._c128(self.n_km, nz)
+            info = torch.empty(P, dtype=torch.int32, device=self.device)
+            iters = torch.zeros(P, dtype=torch.int32, device=self.device)
+        else:
+            x, v, info, iters = out
+        _lib.check(L.edt_tsvd(self._h, _ptr(gram), _ptr(rhs), float(tol_rel), int(max_iter), _ptr(x), _ptr(v),
+                              _ptr(info), _ptr(iters), _ptr(self._work), _ptr(tsvd_work), _stream()), "edt_tsvd")
+        return x, v, info, iters
+
     def forward(self, g64, v, out=None):
         """Born data rows d_rows[R, 2] (complex128) of the model spectrum v[n_km, nz]."""
         self.upload()
