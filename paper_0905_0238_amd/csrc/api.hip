@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "dev_common.h"
 #include "timing.h"
@@ -40,7 +41,9 @@ hipError_t launch_adjoint(const edt_plan* p, const double* vel, const zd* g64, c
                           unsigned char* work, hipStream_t st);
 hipError_t launch_tsvd_init(const edt_plan* p, const double* gram, double tol_rel, unsigned char* tw,
                             int32_t* iters, hipStream_t st);
-hipError_t launch_tsvd_step(const edt_plan* p, int k, unsigned char* tw, int32_t* iters, hipStream_t st);
+hipError_t launch_tsvd_step(const edt_plan* p, int k, double a, unsigned char* tw, int32_t* iters,
+                            hipStream_t st);
+void tsvd_step_scales(double l0, int n, double* a);
 hipError_t launch_tsvd_final(const edt_plan* p, double* gram, const double* rhs, unsigned char* tw,
                              const int32_t* iters, hipStream_t st);
 size_t chol_lds_bytes(int nz);
@@ -321,7 +324,13 @@ edt_status edt_tsvd(const edt_plan* p, double* gram, const double* rhs, double t
     unsigned char* tw = static_cast<unsigned char*>(tsvd_work);
     const TsvdLayout tl = tsvd_layout(p);
     EDT_TRY(launch_tsvd_init(p, gram, tol_rel, tw, iters, stream), "tsvd init");
-    for (int k = 0; k < max_iter; ++k) EDT_TRY(launch_tsvd_step(p, k, tw, iters, stream), "tsvd sign step");
+    // step scalings from a guess of the smallest eigenvalue magnitude of X_0:
+    // a dropped direction of G (eigenvalue ~0) sits at about tol_rel^2, one
+    // 1% away from the threshold at 1e-2 tol_rel^2
+    std::vector<double> scale(static_cast<size_t>(max_iter));
+    tsvd_step_scales(std::max(1e-2 * tol_rel * tol_rel, 1e-14), max_iter, scale.data());
+    for (int k = 0; k < max_iter; ++k)
+        EDT_TRY(launch_tsvd_step(p, k, scale[size_t(k)], tw, iters, stream), "tsvd sign step");
     EDT_TRY(launch_tsvd_final(p, gram, rhs, tw, iters, stream), "tsvd projector");
     // (G + sigma^2 (I - P)) x = P c by the factorisation with no damping and
     // the corrected block solves

@@ -10,11 +10,17 @@
 // G and P commute, and the bracket is G on range(P) (eigenvalues >= sigma^2)
 // and G + sigma^2 on the rest (eigenvalues in [sigma^2, 2 sigma^2)), so it is
 // positive definite and the existing Cholesky solve applies.  P = (I + S)/2
-// with S the matrix sign of G - sigma^2 I, by the Newton-Schulz iteration
-//     X_0 = (G - sigma^2 I) / ||G - sigma^2 I||_F,   X <- X (3 I - X^2) / 2,
-// which drives every nonzero eigenvalue of X_0 (all in [-1, 1]) to +-1:
-// about 1.5 times per step while small, quadratically near +-1.  Two batched
-// FP64 GEMMs per step; a pair stops once ||X^2 - I||_F <= 1e-9.  An
+// with S the matrix sign of G - sigma^2 I, by scaled Newton-Schulz steps
+//     X_0 = (G - sigma^2 I) / ||G - sigma^2 I||_F,   X <- (a/2) X (3 I - a^2 X^2),
+// which drive every nonzero eigenvalue of X_0 (all in [-1, 1]) to +-1.  Any
+// a in [1, sqrt 3] keeps the spectrum in [-1, 1]; with a lower bound l on the
+// eigenvalue magnitudes, a = sqrt(3 / (1 + l + l^2)) maps [l, 1] onto
+// [f(l), 1] (the scaling of Chen and Chow for the Hermitian sign function),
+// so small eigenvalues grow up to 2.6 times per step instead of 1.5; the host
+// runs the bound l from a guess, caps a (see tsvd_step_scales) and sets a = 1
+// (the plain step, quadratic near +-1) once l >= 0.999.  An eigenvalue below
+// the guess still converges, in more steps.  Two batched FP64 products per step; a pair stops after a plain
+// step once ||X^2 - I||_F <= 1e-9 (a scaled step would move it off +-1).  An
 // eigenvalue of G within rounding of sigma^2 has no definite side (the
 // truncation itself is discontinuous there): such a pair does not converge
 // and is reported as such.
@@ -27,6 +33,28 @@ namespace edt {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr double kSignTol = 1e-9;   // ||X^2 - I||_F at which the sign iteration stops
+
+// Scaling of each sign step from a guess l0 of the smallest eigenvalue
+// magnitude of X_0 (the bound is advanced as l <- f(l)); 1 from l >= 0.999 on.
+// The scaling is capped at its value for l = 0.3: a fully scaled step maps +-1
+// to about +-2.6 l, by the difference of two terms of order 1, and the
+// rounding of that difference then perturbs every direction's sign by about
+// u / l; capped, +-1 stays above 0.57 in magnitude and small eigenvalues
+// still grow about 2.23 times per step.
+void tsvd_step_scales(double l0, int n, double* a) {
+    constexpr double kCapBound = 0.3;
+    double l = l0;
+    for (int k = 0; k < n; ++k) {
+        if (l >= 0.999) {
+            a[k] = 1.0;
+            continue;
+        }
+        const double lb = l > kCapBound ? l : kCapBound;
+        const double s = sqrt(3.0 / (1.0 + lb + lb * lb));
+        a[k] = s;
+        l = 0.5 * s * l * (3.0 - s * s * l * l);
+    }
+}
 
 // Per pair: the threshold, X_0 (full, row-major nz x nz) from the lower
 // triangle of G, and the iteration state.  An empty pair, or one whose Gram
@@ -88,11 +116,11 @@ __global__ __launch_bounds__(256) void tsvd_init_kernel(const double* __restrict
 // quarter: 2 x 2 MFMA tiles; lane l of register v holds row 4 v + l / 16,
 // column l % 16).
 //   MODE 0: C = X X,                 and per tile sum (C - I)^2 -> dpart
-//   MODE 1: C = 1.5 X - 0.5 X B      (B = X X)
+//   MODE 1: C = 1.5 a X - 0.5 a^3 X B      (B = X X)
 template <int MODE>
 __global__ __launch_bounds__(256) void ns_gemm_kernel(const double* __restrict__ X, const double* __restrict__ B,
                                                       double* __restrict__ C, const int32_t* __restrict__ conv,
-                                                      double* __restrict__ dpart, int nz, int nt) {
+                                                      double* __restrict__ dpart, int nz, int nt, double a) {
     __shared__ double As[64][33];
     __shared__ double Bs[32][65];
     __shared__ double s_red[4];
@@ -151,6 +179,7 @@ __global__ __launch_bounds__(256) void ns_gemm_kernel(const double* __restrict__
         __syncthreads();
     }
     const bool mirror = ti != tj;
+    const double c1 = 1.5 * a, c3 = 0.5 * a * a * a;
     double d2 = 0.0;
     double* Cp = C + base;
 #pragma unroll
@@ -168,7 +197,7 @@ __global__ __launch_bounds__(256) void ns_gemm_kernel(const double* __restrict__
                         const double e = c - (i == j ? 1.0 : 0.0);
                         d2 += (mirror ? 2.0 : 1.0) * e * e;
                     } else {
-                        c = 1.5 * Xp[at] - 0.5 * acc[a][b][v];
+                        c = c1 * Xp[at] - c3 * acc[a][b][v];
                     }
                     Cp[at] = c;
                     if (mirror) Cp[size_t(j) * nz + i] = c;
@@ -183,18 +212,18 @@ __global__ __launch_bounds__(256) void ns_gemm_kernel(const double* __restrict__
 }
 
 // After one step: ||X_k^2 - I||_F from the tile partials (fixed order); the
-// new iterate is accepted (iters + 1) and the pair stops once X_k was within
-// the tolerance (X_{k+1} is then closer still).
+// new iterate is accepted (iters + 1), and after a plain step (accept) the
+// pair stops once X_k was within the tolerance (X_{k+1} is then closer still).
 __global__ __launch_bounds__(256) void ns_check_kernel(const double* __restrict__ dpart, int nt,
                                                        int32_t* __restrict__ conv, int32_t* __restrict__ iters,
-                                                       int n_pairs) {
+                                                       int n_pairs, int accept) {
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= n_pairs || conv[p]) return;
     double s = 0.0;
     const int ntri = nt * (nt + 1) / 2;
     for (int t = 0; t < ntri; ++t) s += dpart[size_t(p) * ntri + t];
     iters[p] += 1;
-    if (sqrt(s) <= kSignTol) conv[p] = 1;
+    if (accept && sqrt(s) <= kSignTol) conv[p] = 1;
 }
 
 // P = (I + X)/2 with X the last iterate (buffer iters % 2):
@@ -259,8 +288,10 @@ hipError_t launch_tsvd_init(const edt_plan* p, const double* gram, double tol_re
     return hipGetLastError();
 }
 
-// Step k reads X_k from buffer k % 2 and writes X_{k+1} to the other.
-hipError_t launch_tsvd_step(const edt_plan* p, int k, unsigned char* tw, int32_t* iters, hipStream_t st) {
+// Step k reads X_k from buffer k % 2 and writes X_{k+1} to the other, with
+// scaling a (a = 1: a plain step, after which converged pairs stop).
+hipError_t launch_tsvd_step(const edt_plan* p, int k, double a, unsigned char* tw, int32_t* iters,
+                            hipStream_t st) {
     const TsvdLayout l = tsvd_layout(p);
     const int nz = p->nz, nt = (nz + 63) / 64;
     double* xa = reinterpret_cast<double*>(tw + ((k & 1) ? l.x1 : l.x0));
@@ -269,10 +300,10 @@ hipError_t launch_tsvd_step(const edt_plan* p, int k, unsigned char* tw, int32_t
     double* dpart = reinterpret_cast<double*>(tw + l.dpart);
     int32_t* conv = reinterpret_cast<int32_t*>(tw + l.conv);
     const dim3 grid(unsigned(nt * (nt + 1) / 2 * p->n_pairs));
-    hipLaunchKernelGGL(ns_gemm_kernel<0>, grid, dim3(256), 0, st, xa, xa, y, conv, dpart, nz, nt);
-    hipLaunchKernelGGL(ns_gemm_kernel<1>, grid, dim3(256), 0, st, xa, y, xb, conv, dpart, nz, nt);
+    hipLaunchKernelGGL(ns_gemm_kernel<0>, grid, dim3(256), 0, st, xa, xa, y, conv, dpart, nz, nt, 1.0);
+    hipLaunchKernelGGL(ns_gemm_kernel<1>, grid, dim3(256), 0, st, xa, y, xb, conv, dpart, nz, nt, a);
     hipLaunchKernelGGL(ns_check_kernel, dim3(unsigned((p->n_pairs + 255) / 256)), dim3(256), 0, st, dpart, nt,
-                       conv, iters, int(p->n_pairs));
+                       conv, iters, int(p->n_pairs), a == 1.0 ? 1 : 0);
     return hipGetLastError();
 }
 
