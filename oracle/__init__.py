@@ -22,6 +22,8 @@ grad    gradient of a model misfit with respect to data, damping and layer
 born    brute-force space-domain Born data on tiny periodic grids.
 tsvd    the paper's own solver: truncated SVD of each pair's system (through
         the eigen-decomposition of its Gram), with a relative tolerance.
+kz      the restriction of the solution to a disk in (k_m, k_z): the truncated
+        SVD of each pair's system on the kept discrete Fourier modes in depth.
 
 Every function is pinned by a test in ``tests/test_oracle_*.py`` against a
 closed form, an invariant, a library routine that solves the same problem a
