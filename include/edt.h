@@ -304,9 +304,11 @@ edt_status edt_solve(const edt_plan* plan, const edt_c128* g64, const edt_c128* 
  * right singular vectors of its real rows), with a relative tolerance
  * sigma^2 = tol_rel^2 ||G||_F (Frobenius norm).  Computed without an
  * eigen-decomposition: the spectral projector P onto eigenvalues >= sigma^2
- * comes from the matrix sign of G - sigma^2 I by Newton-Schulz steps (FP64
- * MFMA, at most max_iter <= 200, a pair stopping once ||X^2 - I||_F <= 1e-9),
- * then (G + sigma^2 (I - P)) x = P c is solved by the FP64 Cholesky path.
+ * comes from the matrix sign of G - sigma^2 I by scaled Newton-Schulz steps
+ * (FP64 MFMA; the host fixes each step's scaling in advance, capped so that
+ * rounding cannot flip a sign; at most max_iter <= 200 steps, a pair stopping
+ * once ||X^2 - I||_F <= 1e-9 after an unscaled step), then
+ * (G + sigma^2 (I - P)) x = P c is solved by the FP64 Cholesky path.
  * gram: in, the lower triangles from edt_assemble (use EDT_FP64 for an FP64
  * result); out, the factor of G + sigma^2 (I - P).  rhs: [P][2][nz] from
  * edt_assemble.  x, v_out, info as edt_solve; info is EDT_INFO_NOCONV for a
