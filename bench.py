@@ -253,54 +253,80 @@ def gram_mfma(plan, s, ktimes):
 
 def tsvd_leg(plan, vel, d, tol_rel, reps, torch):
     """The paper's truncated-SVD solve (edt_tsvd) on the FP64 Gram of the same
-    data: time per solve (the Gram is copied in first, since the solve
-    overwrites it; the copy is not timed), sign steps, and the rate of the sign
-    iteration's FP64 products -- symmetric, so nz^2 (nz + 1) flop each (the
-    lower triangle), two per step of every pair still iterating -- over the
-    library timer's time of the sign steps, against the FP64 MFMA peak."""
-    import ctypes as C
-    from paper_0905_0238_amd import _lib
+    data, plain and restricted to the paper's (k_m, k_z) disk (edt_kz_restrict
+    first, radius 2.2 w_max / c_top): time per solve (the Gram and rhs are
+    copied in first, since the solve overwrites them; the copy is not timed),
+    sign steps, and two MFMA rates over the library timer's kernel times,
+    against the FP64 MFMA peak:
+    * the sign iteration's products -- symmetric, so nz^2 (nz + 1) flop each
+      (the lower triangle), two per step of every pair still iterating;
+    * the restriction's Q G Q -- 2 nz^3 flop for G Q and nz^2 (nz + 1) for the
+      lower triangle of Q (G Q), every pair."""
     g64, _ = plan.green(vel, want32=False)
-    gram0, rhs, _ = plan.assemble(g64, None, d, "fp64")
-    gram = torch.empty_like(gram0)
-    n = C.c_size_t(0)
-    _lib.check(_lib.load().edt_tsvd_work_bytes(plan._h, C.byref(n)), "edt_tsvd_work_bytes")
-    work = torch.empty(max(int(n.value), 256), dtype=torch.uint8, device="cuda")
+    gram0, rhs0, _ = plan.assemble(g64, None, d, "fp64")
+    gram, rhs = torch.empty_like(gram0), torch.empty_like(rhs0)
+    work = plan.tsvd_work()
     P, nz = plan.n_pairs, plan.nz
     out = (torch.empty(P, 2, nz, dtype=torch.float64, device="cuda"),
            torch.empty(plan.n_km, nz, dtype=torch.complex128, device="cuda"),
            torch.empty(P, dtype=torch.int32, device="cuda"), torch.zeros(P, dtype=torch.int32, device="cuda"))
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    tot = 0.0
-    for r in range(reps + 1):
-        gram.copy_(gram0)
-        ev0.record()
+    n_keep = torch.empty(P, dtype=torch.int32, device="cuda")
+    K = plan.kz_disk_radius(2.2)
+
+    def solve(kz):
+        if kz:
+            plan.kz_restrict(gram, rhs, K, work, n_keep=n_keep)
         plan.tsvd(gram, rhs, tol_rel, out=out, tsvd_work=work)
-        ev1.record()
+
+    def leg(kz):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        tot = 0.0
+        for r in range(reps + 1):
+            gram.copy_(gram0)
+            rhs.copy_(rhs0)
+            ev0.record()
+            solve(kz)
+            ev1.record()
+            torch.cuda.synchronize()
+            if r > 0:
+                tot += ev0.elapsed_time(ev1)
+        gram.copy_(gram0)
+        rhs.copy_(rhs0)
         torch.cuda.synchronize()
-        if r > 0:
-            tot += ev0.elapsed_time(ev1)
-    ms = tot / reps
-    gram.copy_(gram0)
-    torch.cuda.synchronize()
-    plan.timing(True)
-    plan.timing_read()
-    plan.tsvd(gram, rhs, tol_rel, out=out, tsvd_work=work)
-    kt = plan.timing_read()
-    plan.timing(False)
-    it = out[3].cpu().numpy().astype(np.float64)
-    info = out[2].cpu().numpy()
-    fl = float(np.sum(it)) * 2 * float(nz) ** 2 * (nz + 1)
-    sign_ms = kt.get("tsvd sign step", (float("nan"), 0))[0]
-    ach = fl / (sign_ms * 1e-3) / 1e12
-    return {"tol_rel": tol_rel, "ms_per_solve": ms,
-            "sign_steps": {"max": int(it.max()), "mean": float(it.mean())},
-            "info_noconv": int(np.sum(info == -2)),
-            "kernels_ms": {k: round(v[0], 4) for k, v in kt.items()},
-            "sign_gemm": {"bound": "mfma", "achieved": ach, "peak": PEAK["fp64"], "unit": "TFLOP/s",
-                          "frac": ach / PEAK["fp64"],
-                          "per_solve": f"2 symmetric products x nz^2 (nz+1) flop x sign steps summed over "
-                                       f"pairs = {fl:.4g} flop"}}
+        plan.timing(True)
+        plan.timing_read()
+        solve(kz)
+        kt = plan.timing_read()
+        plan.timing(False)
+        it = out[3].cpu().numpy().astype(np.float64)
+        info = out[2].cpu().numpy()
+        fl = float(np.sum(it)) * 2 * float(nz) ** 2 * (nz + 1)
+        sign_ms = kt.get("tsvd sign step", (float("nan"), 0))[0]
+        ach = fl / (sign_ms * 1e-3) / 1e12
+        res = {"ms_per_solve": tot / reps,
+               "sign_steps": {"max": int(it.max()), "mean": float(it.mean())},
+               "info_noconv": int(np.sum(info == -2)),
+               "kernels_ms": {k: round(v[0], 4) for k, v in kt.items()},
+               "sign_gemm": {"bound": "mfma", "achieved": ach, "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                             "frac": ach / PEAK["fp64"],
+                             "per_solve": f"2 symmetric products x nz^2 (nz+1) flop x sign steps summed over "
+                                          f"pairs = {fl:.4g} flop"}}
+        if kz:
+            nk = n_keep.cpu().numpy()
+            fk = P * (2.0 * nz ** 3 + float(nz) ** 2 * (nz + 1))
+            kz_ms = kt.get("kz restrict", (float("nan"), 0))[0]
+            ak = fk / (kz_ms * 1e-3) / 1e12
+            res["disk"] = {"radius": K, "factor": 2.2, "kept_modes_mean": float(nk.mean()),
+                           "pairs_cut": int(np.sum(nk < nz)), "pairs_empty": int(np.sum(nk == 0))}
+            res["kz_gemm"] = {"bound": "mfma", "achieved": ak, "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                              "frac": ak / PEAK["fp64"],
+                              "per_solve": f"P (2 nz^3 + nz^2 (nz+1)) = {fk:.4g} flop"}
+        return res
+
+    out_d = {"tol_rel": tol_rel}
+    out_d.update(leg(False))
+    out_d["kz_disk"] = leg(True)
+    return out_d
 
 
 def cpu_baseline_leg(s, plan, pipes, n_pairs_sample, torch):

@@ -324,6 +324,34 @@ edt_status edt_tsvd(const edt_plan* plan, double* gram, const double* rhs, doubl
                     hipStream_t stream);
 
 /*
+ * Radius of the (k_m, k_z) disk of Section 3.1: k_disk = factor * 2 pi f_max
+ * / c_top (rad/m), f_max the largest frequency of the plan and c_top the
+ * velocity of the top layer (the paper's c0, undefined for a layered
+ * reference); the paper's factor is 2.2.  Host only.
+ */
+edt_status edt_kz_disk_radius(const edt_plan* plan, double factor, double* k_disk);
+
+/*
+ * The k_z restriction of Section 3.1: every pair's unknowns are restricted to
+ * the discrete Fourier modes in depth (k_z,j = 2 pi j / (nz dz)) with
+ * k_z,j^2 + |k_m|^2 <= k_disk^2.  With Q the orthogonal projector onto those
+ * modes (circulant in depth), the pair's Gram and right-hand sides become
+ * Q G Q and Q c, in place; edt_tsvd on the result gives the truncated-SVD
+ * solution restricted to the disk (Q G Q vanishes off the kept modes, whose
+ * singular values are then zero and dropped; use tol_rel > 0).  Apply it
+ * before edt_tsvd only: edt_solve's refinement works from the rows.
+ * gram: [P][nz][nz] lower triangles from edt_assemble (EDT_FP64); rhs:
+ * [P][2][nz]; both device, overwritten.  n_keep: device int32 [P] or NULL,
+ * the number of kept real modes per pair (0 for a pair with |k_m| > k_disk,
+ * whose Gram and rhs become zero).  tsvd_work: device, >= edt_tsvd_work_bytes,
+ * used as scratch (it holds nothing between this call and edt_tsvd).
+ * Errors: EDT_EINVAL for a null gram, rhs or tsvd_work, or k_disk negative
+ * or not finite.
+ */
+edt_status edt_kz_restrict(const edt_plan* plan, double k_disk, double* gram, double* rhs, int32_t* n_keep,
+                           void* tsvd_work, hipStream_t stream);
+
+/*
  * Born forward map (eq. DMV): d_rows[r] = (A_r . v_in[u_p], A_r . v_in[-u_p]),
  * A_r = w_f^2 dz g(k_r) g(k_s), for every row r of pair p.
  * v_in: [n_km][nz] complex128; d_rows: [n_rows][2] complex128.

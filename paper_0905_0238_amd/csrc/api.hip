@@ -46,6 +46,8 @@ hipError_t launch_tsvd_step(const edt_plan* p, int k, double a, unsigned char* t
 void tsvd_step_scales(double l0, int n, double* a);
 hipError_t launch_tsvd_final(const edt_plan* p, double* gram, const double* rhs, unsigned char* tw,
                              const int32_t* iters, hipStream_t st);
+hipError_t launch_kz_restrict(const edt_plan* p, double K, double* gram, double* rhs, unsigned char* tw,
+                              int32_t* n_keep, hipStream_t st);
 size_t chol_lds_bytes(int nz);
 hipError_t configure_kernels();
 
@@ -343,6 +345,34 @@ edt_status edt_tsvd(const edt_plan* p, double* gram, const double* rhs, double t
     EDT_TRY(launch_recombine(p, x, 1, reinterpret_cast<const int32_t*>(tw + tl.conv), info,
                              reinterpret_cast<zd*>(v_out), stream),
             "recombine");
+    return EDT_OK;
+}
+
+edt_status edt_kz_disk_radius(const edt_plan* p, double factor, double* k_disk) {
+    if (!p || !k_disk || !(factor >= 0.0) || !std::isfinite(factor)) {
+        set_error("plan and k_disk must be given and factor finite and >= 0");
+        return EDT_EINVAL;
+    }
+    double fmax = 0.0;
+    for (double f : p->freq) fmax = std::max(fmax, f);
+    *k_disk = factor * (kTwoPiD * fmax) / p->ctop;
+    return EDT_OK;
+}
+
+edt_status edt_kz_restrict(const edt_plan* p, double k_disk, double* gram, double* rhs, int32_t* n_keep,
+                           void* tsvd_work, hipStream_t stream) {
+    edt_status s = check_plan(p);
+    if (s != EDT_OK) return s;
+    if (!gram || !rhs || !tsvd_work) {
+        set_error("missing argument");
+        return EDT_EINVAL;
+    }
+    if (!(k_disk >= 0.0) || !std::isfinite(k_disk)) {
+        set_error("k_disk must be finite and >= 0");
+        return EDT_EINVAL;
+    }
+    EDT_TRY(launch_kz_restrict(p, k_disk, gram, rhs, static_cast<unsigned char*>(tsvd_work), n_keep, stream),
+            "kz restrict");
     return EDT_OK;
 }
 

@@ -212,9 +212,7 @@ class Plan:
         L = _lib.load()
         P, nz = self.n_pairs, self.nz
         if tsvd_work is None:
-            nb = C.c_size_t(0)
-            _lib.check(L.edt_tsvd_work_bytes(self._h, C.byref(nb)), "edt_tsvd_work_bytes")
-            tsvd_work = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=self.device)
+            tsvd_work = self.tsvd_work()
         if out is None:
             x = torch.empty(P, 2, nz, dtype=torch.float64, device=self.device)
             v = self._c128(self.n_km, nz)
@@ -225,6 +223,30 @@ class Plan:
         _lib.check(L.edt_tsvd(self._h, _ptr(gram), _ptr(rhs), float(tol_rel), int(max_iter), _ptr(x), _ptr(v),
                               _ptr(info), _ptr(iters), _ptr(self._work), _ptr(tsvd_work), _stream()), "edt_tsvd")
         return x, v, info, iters
+
+    def tsvd_work(self):
+        """A device workspace for tsvd and kz_restrict."""
+        nb = C.c_size_t(0)
+        _lib.check(_lib.load().edt_tsvd_work_bytes(self._h, C.byref(nb)), "edt_tsvd_work_bytes")
+        return torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=self.device)
+
+    def kz_disk_radius(self, factor=2.2):
+        """Radius factor * 2 pi f_max / c_top of the (k_m, k_z) disk (rad/m)."""
+        k = C.c_double(0.0)
+        _lib.check(_lib.load().edt_kz_disk_radius(self._h, float(factor), C.byref(k)), "edt_kz_disk_radius")
+        return k.value
+
+    def kz_restrict(self, gram, rhs, k_disk, tsvd_work, n_keep=None):
+        """Restrict every pair to the disk k_z^2 + |k_m|^2 <= k_disk^2 (in place on
+        gram and rhs); returns n_keep[P] (int32) when asked for (n_keep=True or a
+        tensor)."""
+        self.upload()
+        if n_keep is True:
+            n_keep = torch.empty(self.n_pairs, dtype=torch.int32, device=self.device)
+        _lib.check(_lib.load().edt_kz_restrict(self._h, float(k_disk), _ptr(gram), _ptr(rhs),
+                                               _ptr(n_keep) if n_keep is not None else None, _ptr(tsvd_work),
+                                               _stream()), "edt_kz_restrict")
+        return n_keep
 
     def forward(self, g64, v, out=None):
         """Born data rows d_rows[R, 2] (complex128) of the model spectrum v[n_km, nz]."""

@@ -1,0 +1,229 @@
+"""GPU: the k_z-disk restriction (edt_kz_restrict) and the truncated-SVD solve
+on the restricted system, against the oracle (oracle.kz), pair by pair.
+
+* the disk radius and the kept mode count of every pair are exact (the count
+  is an integer decided in FP64 by the same comparison on both sides);
+* the restricted Gram Q G Q and right-hand sides Q c against the oracle's
+  F F^T G F F^T and F F^T c (F its orthonormal basis of the kept modes), to
+  1e-12 of the pair's largest Gram entry;
+* the restricted truncated-SVD solution against the oracle's solve on the
+  basis F, with the conditioning-derived bar of the plain truncated-SVD test:
+  max(1e-10, 100 u (lambda_max / lambda_min,kept + lambda_max / gap)), where
+  the gap now also counts the dropped modes (eigenvalue 0, at sigma^2 from the
+  threshold); pairs with an eigenvalue within a relative 1e-6 of sigma^2 are
+  left out and counted;
+* a disk that holds every k_z leaves the system unchanged, a disk of radius 0
+  keeps only the constant mode of k_m = 0, and at the full size of the 2D
+  N = 512 survey a seeded sample of pairs matches the oracle.
+"""
+import numpy as np
+import pytest
+
+from edt_inputs import make_config, make_custom, vhat
+from oracle.kz import kz_basis, kz_disk_radius, kz_tsvd_solve, pair_km2
+from oracle.rows import plan as oracle_plan, row_values
+from oracle.solve import gtables, forward, noise_scale, add_noise, normal_equations
+from oracle.tsvd import tsvd_solve
+from tests._cases import oracle_case, layered_small
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+E = pytest.importorskip("paper_0905_0238_amd")
+
+GAP = 1e-6
+
+
+def _cases():
+    return {
+        "cfg1": lambda: make_config(1),
+        "layered-nz40": lambda: layered_small(),
+        "homogeneous": lambda: make_custom(N=32, nz=33, dx=12.5, dz=8.0, freqs=(6.0, 17.0, 29.0, 41.0),
+                                           vel=(2300.0,), zif=(), noise_rel=0.05, seed=11),
+        "3d-small": lambda: make_custom(dim=3, N=12, Nh=6, nz=37, dx=25.0, dz=10.0,
+                                        freqs=(8.0, 14.0, 20.0), vel=(1800.0, 2500.0, 2100.0),
+                                        zif=(60.0, 200.0), noise_rel=0.05, seed=5),
+    }
+
+
+def _assembled(s, r):
+    p = E.Plan(s)
+    vel = torch.tensor(np.asarray(s.vel, np.float64), device="cuda")
+    g64, _ = p.green(vel, want32=False)
+    d = torch.from_numpy(r["d_rows"]).cuda()
+    gram, rhs, _ = p.assemble(g64, None, d, "fp64")
+    return p, gram, rhs
+
+
+def _radius(s, scale):
+    return scale * kz_disk_radius(s)
+
+
+def test_disk_radius_is_exact():
+    for name, mk in _cases().items():
+        s = mk()
+        p = E.Plan(s)
+        for factor in (2.2, 1.0, 0.37):
+            assert p.kz_disk_radius(factor) == kz_disk_radius(s, factor), (name, factor)
+
+
+@pytest.mark.parametrize("scale", [1.0, 0.45])
+@pytest.mark.parametrize("name", list(_cases()))
+def test_restricted_gram_and_rhs(name, scale):
+    s = _cases()[name]()
+    r = oracle_case(s)
+    K = _radius(s, scale)
+    p, gram, rhs = _assembled(s, r)
+    G_in = gram.cpu().numpy().copy()
+    work = p.tsvd_work()
+    n_keep = p.kz_restrict(gram, rhs, K, work, n_keep=True)
+    torch.cuda.synchronize()
+    n_keep = n_keep.cpu().numpy()
+    Gq, cq = gram.cpu().numpy(), rhs.cpu().numpy()
+    nz = s.nz
+    low = np.tril(np.ones((nz, nz), bool))
+    cut = 0
+    for q, (pr, (d0, d1)) in enumerate(zip(r["pl"].pairs, r["data"])):
+        F = kz_basis(nz, s.dz, pair_km2(s, pr.u), K)
+        assert n_keep[q] == F.shape[1], (name, q, n_keep[q], F.shape[1])
+        cut += F.shape[1] < nz
+        if pr.n_rows == 0:
+            continue
+        A = row_values(s, pr, r["tabs"].lookup)
+        G, c, _ = normal_equations(A, d0, d1)
+        Pf = F @ F.T
+        ref_G = Pf @ G @ Pf
+        ref_c = c @ Pf
+        scale_g = np.max(np.abs(np.tril(G_in[q])))
+        assert np.max(np.abs(Gq[q][low] - ref_G[low])) <= 1e-12 * scale_g, (name, q)
+        assert np.max(np.abs(cq[q] - ref_c)) <= 1e-12 * max(np.max(np.abs(c)), 1e-300), (name, q)
+    assert cut > 0, "the disk cuts no pair: the case does not exercise the restriction"
+
+
+def _check_solution(name, s, pl, v, info, Vo, info_o, n_keep, tol):
+    nv = np.linalg.norm(Vo)
+    u = np.finfo(np.float64).eps / 2
+    checked = ambiguous = within = 0
+    worst = 0.0
+    for q, (pr, io) in enumerate(zip(pl.pairs, info_o)):
+        idx = [pr.u] if pr.u == pr.u_neg else [pr.u, pr.u_neg]
+        if pr.n_rows == 0 or io["n_keep"] == 0:
+            assert not np.any(v[idx]), (name, q)
+            continue
+        w, t2 = io["eig"], io["tau2"]
+        # dropped modes sit at eigenvalue 0 of Q G Q
+        gap = min(np.min(np.abs(w - t2)), t2) if n_keep[q] < s.nz else np.min(np.abs(w - t2))
+        if gap <= GAP * t2:
+            ambiguous += 1
+            continue
+        assert info[q] == 0, (name, q, info[q])
+        kept = w[w >= t2]
+        lmax = w.max()
+        kappa = lmax / kept.min() if kept.size else 0.0
+        bar = max(1e-10, 100 * u * (kappa + lmax / gap))
+        ref = Vo[idx]
+        err = np.linalg.norm(v[idx] - ref) / max(np.linalg.norm(ref), 1e-3 * nv)
+        assert err <= bar, (name, tol, q, err, bar)
+        checked += 1
+        within += err <= 1e-10
+        worst = max(worst, err)
+    assert checked >= 0.9 * (checked + ambiguous) and checked > 0, (checked, ambiguous)
+    print(f"{name} tol {tol}: {checked} pairs checked, {ambiguous} ambiguous; error <= 1e-10 for {within}, "
+          f"worst {worst:.2e}")
+
+
+@pytest.mark.parametrize("scale", [1.0, 0.45])
+@pytest.mark.parametrize("tol", [1e-2, 1e-3])
+@pytest.mark.parametrize("name", list(_cases()))
+def test_restricted_tsvd_matches_the_oracle(name, tol, scale):
+    s = _cases()[name]()
+    r = oracle_case(s)
+    K = _radius(s, scale)
+    Vo, info_o = kz_tsvd_solve(s, r["pl"], r["data"], r["tabs"], tol, K)
+    p, gram, rhs = _assembled(s, r)
+    work = p.tsvd_work()
+    n_keep = p.kz_restrict(gram, rhs, K, work, n_keep=True)
+    x, v, info, iters = p.tsvd(gram, rhs, tol, max_iter=150, tsvd_work=work)
+    torch.cuda.synchronize()
+    _check_solution(name, s, r["pl"], v.cpu().numpy(), info.cpu().numpy(), Vo, info_o,
+                    n_keep.cpu().numpy(), tol)
+
+
+def test_disk_holding_everything_and_disk_of_radius_zero():
+    s = layered_small()
+    r = oracle_case(s)
+    # every k_z kept: the restricted solve is the plain one
+    p, gram, rhs = _assembled(s, r)
+    work = p.tsvd_work()
+    n_keep = p.kz_restrict(gram, rhs, 1e3, work, n_keep=True)
+    _, v, info, _ = p.tsvd(gram, rhs, 1e-2, max_iter=150, tsvd_work=work)
+    torch.cuda.synchronize()
+    assert np.all(n_keep.cpu().numpy() == s.nz)
+    Vo, _ = tsvd_solve(s, r["pl"], r["data"], r["tabs"], 1e-2)
+    assert np.linalg.norm(v.cpu().numpy() - Vo) <= 1e-9 * np.linalg.norm(Vo)
+    # radius 0: only the constant mode of k_m = 0 survives
+    p, gram, rhs = _assembled(s, r)
+    n_keep = p.kz_restrict(gram, rhs, 0.0, work, n_keep=True).cpu().numpy()
+    _, v, info, _ = p.tsvd(gram, rhs, 1e-2, max_iter=150, tsvd_work=work)
+    torch.cuda.synchronize()
+    u0 = [q for q, pr in enumerate(r["pl"].pairs) if pr.u == 0]
+    assert n_keep[u0[0]] == 1 and np.sum(n_keep) == 1
+    v = v.cpu().numpy()
+    assert not np.any(np.delete(v, 0, axis=0))
+    # constant in depth to the FP64 bar (the sign iteration stops at
+    # ||X^2 - I||_F <= 1e-9, so the projector leaks that little)
+    assert np.allclose(v[0], v[0].mean(), rtol=0, atol=1e-10 * np.max(np.abs(v[0])))
+    Vo, _ = kz_tsvd_solve(s, r["pl"], r["data"], r["tabs"], 1e-2, 0.0)
+    assert np.max(np.abs(v - Vo)) <= 1e-10 * np.max(np.abs(Vo))
+
+
+def test_restriction_rejects_bad_arguments():
+    s = layered_small()
+    p = E.Plan(s)
+    p.upload()
+    g = torch.zeros(p.n_pairs, s.nz, s.nz, dtype=torch.float64, device="cuda")
+    c = torch.zeros(p.n_pairs, 2, s.nz, dtype=torch.float64, device="cuda")
+    work = p.tsvd_work()
+    for bad in (-1.0, float("inf"), float("nan")):
+        with pytest.raises(RuntimeError):
+            p.kz_restrict(g, c, bad, work)
+
+
+def test_sampled_pairs_at_full_size():
+    """2D N = 512, nz = 256, 128 frequencies, the paper's disk (factor 2.2):
+    8 seeded pairs solved by the oracle, the whole survey on the GPU (the other
+    pairs' data are zero)."""
+    s = make_config(2)
+    pl = oracle_plan(s)
+    rng = np.random.default_rng(7)
+    nonempty = [i for i, q in enumerate(pl.pairs) if q.n_rows > 0]
+    pick = sorted(rng.choice(nonempty, size=8, replace=False).tolist())
+    sub = [pl.pairs[i] for i in pick]
+    tabs = gtables(s, pl, pairs=sub)
+    clean = forward(s, pl, vhat(s), tabs, pairs=sub)
+    data = add_noise(s, pl, clean, noise_scale(s, pl, clean, pairs=sub), pairs=sub)
+    p = E.Plan(s)
+    K = p.kz_disk_radius(2.2)
+    tol = 1e-2
+    Vo, info_o = kz_tsvd_solve(s, pl, data, tabs, tol, K, pairs=sub)
+    off = p.rowmap()["row_off"]
+    d = np.zeros((p.n_rows, 2), np.complex128)
+    for i, (d0, d1) in zip(pick, data):
+        d[off[i]:off[i + 1], 0] = d0
+        d[off[i]:off[i + 1], 1] = d1
+    vel = torch.tensor(np.asarray(s.vel, np.float64), device="cuda")
+    g64, _ = p.green(vel, want32=False)
+    gram, rhs, _ = p.assemble(g64, None, torch.from_numpy(d).cuda(), "fp64")
+    work = p.tsvd_work()
+    n_keep = p.kz_restrict(gram, rhs, K, work, n_keep=True).cpu().numpy()
+    _, v, info, _ = p.tsvd(gram, rhs, tol, max_iter=150, tsvd_work=work)
+    torch.cuda.synchronize()
+    assert np.any(n_keep < s.nz)
+    for i, io in zip(pick, info_o):
+        assert n_keep[i] == io["n_keep"]
+
+    class _Sub:
+        pairs = sub
+
+    _check_solution("cfg2-sample", s, _Sub, v.cpu().numpy(), info.cpu().numpy()[pick], Vo, info_o,
+                    n_keep[pick], tol)
