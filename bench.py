@@ -329,6 +329,53 @@ def tsvd_leg(plan, vel, d, tol_rel, reps, torch):
     return out_d
 
 
+def shots_leg(plan, reps, torch):
+    """The transforms on either side (2D surveys): seeded records
+    [n_freq][N][N] (complex128, resident) -> d_mid * DFT2 in place ->
+    packed rows, and the solution spectrum -> model.  Time per call and the
+    HBM rate of the transform over the library timer's time: each of its two
+    passes reads and writes the records once, so 4 * 16 * n_freq * N^2 bytes
+    per call; the pack reads two values and writes two per row."""
+    if plan.dim != 2:
+        return None
+    g = torch.Generator(device="cuda").manual_seed(5)
+    shape = (plan.n_freq, plan.n_mid, plan.n_mid)
+    rec0 = torch.complex(torch.randn(shape, generator=g, device="cuda", dtype=torch.float64),
+                         torch.randn(shape, generator=g, device="cuda", dtype=torch.float64))
+    rec = torch.empty_like(rec0)
+    d = plan.shots_pack(rec0)
+    v = torch.complex(torch.randn(plan.n_km, plan.nz, generator=g, device="cuda", dtype=torch.float64),
+                      torch.randn(plan.n_km, plan.nz, generator=g, device="cuda", dtype=torch.float64))
+    m = plan.model(v)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tot = 0.0
+    for r in range(reps + 1):
+        rec.copy_(rec0)
+        ev0.record()
+        plan.shots_fft(rec)
+        plan.shots_pack(rec, out=d)
+        ev1.record()
+        torch.cuda.synchronize()
+        if r > 0:
+            tot += ev0.elapsed_time(ev1)
+    rec.copy_(rec0)
+    torch.cuda.synchronize()
+    plan.timing(True)
+    plan.timing_read()
+    plan.shots_fft(rec)
+    plan.shots_pack(rec, out=d)
+    plan.model(v, out=m)
+    kt = plan.timing_read()
+    plan.timing(False)
+    nb = 4.0 * 16 * plan.n_freq * plan.n_mid ** 2
+    fft_ms = kt.get("shots fft", (float("nan"), 0))[0]
+    ach = nb / (fft_ms * 1e-3) / 1e9
+    return {"records": list(shape), "ms_per_call": tot / reps,
+            "kernels_ms": {k: round(v_[0], 4) for k, v_ in kt.items()},
+            "fft_hbm": {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm"], "unit": "GB/s", "frac": ach / PEAK["hbm"],
+                        "per_call": f"2 passes x (read + write) x 16 B x n_freq N^2 = {nb:.4g} B"}}
+
+
 def cpu_baseline_leg(s, plan, pipes, n_pairs_sample, torch):
     """Time the FP64 oracle on a seeded sample of pairs (host cores), and state
     the GPU error on the same oracle data for those pairs."""
@@ -604,6 +651,10 @@ def main():
     out["detail"]["plan_s"] = plan_s
     if a.tsvd > 0 and "fp64" in plans:
         out["detail"]["tsvd"] = tsvd_leg(plans["fp64"], vel, d, a.tsvd, 3, torch)
+    if "fp64" in plans:
+        sl = shots_leg(plans["fp64"], 3, torch)
+        if sl is not None:
+            out["detail"]["shots"] = sl
     if not a.no_cpu:
         base, errs = cpu_baseline_leg(s, plan, pipes, a.cpu_pairs, torch)
         out["cpu_baseline"] = base

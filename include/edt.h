@@ -352,6 +352,36 @@ edt_status edt_kz_restrict(const edt_plan* plan, double k_disk, double* gram, do
                            void* tsvd_work, hipStream_t stream);
 
 /*
+ * The transforms on either side of the decoupled problems (Section 2.1), for
+ * the 2D line survey (EDT_EINVAL for dim 3 and for n_mid > 2048).
+ *
+ * edt_shots_fft: shots[n_freq][n_mid][n_mid] (complex128, device; [f][R][S],
+ * the record of the source at x_S = S d_mid by the receiver at x_R, at the
+ * plan's frequency f) is overwritten by its transform
+ *     d~[f][a][b] = d_mid sum_{R,S} D[f][R][S] exp(-2 pi i (a R + b S) / n_mid),
+ * the data convention of every other call (a, b: receiver and source
+ * wavenumber indices in fftfreq order).  One pass over the records per axis.
+ *
+ * edt_shots_pack: d_rows[n_rows][2] (device) from that spectrum: row r with
+ * frequency f and key (a, b) (edt_plan_rowmap) gets (d~[f][a][b],
+ * d~[f][-b][-a]), the datum at +k_m and its -k_m partner.  The spectrum is
+ * only read, so the plans of several pair ranges (batches) of one survey can
+ * each pack from one transform.
+ */
+edt_status edt_shots_fft(const edt_plan* plan, edt_c128* shots, hipStream_t stream);
+edt_status edt_shots_pack(const edt_plan* plan, const edt_c128* spectrum, edt_c128* d_rows, hipStream_t stream);
+
+/*
+ * The model from its spectrum (Section 2.1): v_tilde[n_km][nz] (complex128,
+ * device, fftfreq order; 3D u = ux n_mid + uy) is overwritten by its inverse
+ * transform over u (over ux and uy in 3D),
+ *     V(x_n, z) = (1/n_mid) sum_u V~(u, z) exp(2 pi i u n / n_mid)   (per axis),
+ * and model (double, device: [n_mid][nz], or [n_mid][n_mid][nz] in 3D) gets
+ * its real part.  EDT_EINVAL for n_mid > 2048.
+ */
+edt_status edt_model(const edt_plan* plan, edt_c128* v_tilde, double* model, hipStream_t stream);
+
+/*
  * Born forward map (eq. DMV): d_rows[r] = (A_r . v_in[u_p], A_r . v_in[-u_p]),
  * A_r = w_f^2 dz g(k_r) g(k_s), for every row r of pair p.
  * v_in: [n_km][nz] complex128; d_rows: [n_rows][2] complex128.

@@ -46,6 +46,9 @@ hipError_t launch_tsvd_step(const edt_plan* p, int k, double a, unsigned char* t
 void tsvd_step_scales(double l0, int n, double* a);
 hipError_t launch_tsvd_final(const edt_plan* p, double* gram, const double* rhs, unsigned char* tw,
                              const int32_t* iters, hipStream_t st);
+hipError_t launch_shots_fft(const edt_plan* p, zd* shots, hipStream_t st);
+hipError_t launch_shots_pack(const edt_plan* p, const zd* F, zd* d_rows, hipStream_t st);
+hipError_t launch_model(const edt_plan* p, zd* v, double* model, hipStream_t st);
 hipError_t launch_kz_restrict(const edt_plan* p, double K, double* gram, double* rhs, unsigned char* tw,
                               int32_t* n_keep, hipStream_t st);
 size_t chol_lds_bytes(int nz);
@@ -373,6 +376,56 @@ edt_status edt_kz_restrict(const edt_plan* p, double k_disk, double* gram, doubl
     }
     EDT_TRY(launch_kz_restrict(p, k_disk, gram, rhs, static_cast<unsigned char*>(tsvd_work), n_keep, stream),
             "kz restrict");
+    return EDT_OK;
+}
+
+edt_status edt_shots_fft(const edt_plan* p, edt_c128* shots, hipStream_t stream) {
+    edt_status s = check_plan(p);
+    if (s != EDT_OK) return s;
+    if (!shots) {
+        set_error("missing argument");
+        return EDT_EINVAL;
+    }
+    if (p->dim != 2) {
+        set_error("shot records of the 2D line survey only");
+        return EDT_EINVAL;
+    }
+    if (p->n_mid > kMaxLine) {
+        set_error("n_mid > " + std::to_string(kMaxLine) + " is not supported by the transform");
+        return EDT_EINVAL;
+    }
+    EDT_TRY(launch_shots_fft(p, reinterpret_cast<zd*>(shots), stream), "shots fft");
+    return EDT_OK;
+}
+
+edt_status edt_shots_pack(const edt_plan* p, const edt_c128* spectrum, edt_c128* d_rows, hipStream_t stream) {
+    edt_status s = check_plan(p);
+    if (s != EDT_OK) return s;
+    if (!spectrum || !d_rows) {
+        set_error("missing argument");
+        return EDT_EINVAL;
+    }
+    if (p->dim != 2) {
+        set_error("shot records of the 2D line survey only");
+        return EDT_EINVAL;
+    }
+    EDT_TRY(launch_shots_pack(p, reinterpret_cast<const zd*>(spectrum), reinterpret_cast<zd*>(d_rows), stream),
+            "shots pack");
+    return EDT_OK;
+}
+
+edt_status edt_model(const edt_plan* p, edt_c128* v_tilde, double* model, hipStream_t stream) {
+    edt_status s = check_plan(p);
+    if (s != EDT_OK) return s;
+    if (!v_tilde || !model) {
+        set_error("missing argument");
+        return EDT_EINVAL;
+    }
+    if (p->n_mid > kMaxLine) {
+        set_error("n_mid > " + std::to_string(kMaxLine) + " is not supported by the transform");
+        return EDT_EINVAL;
+    }
+    EDT_TRY(launch_model(p, reinterpret_cast<zd*>(v_tilde), model, stream), "model");
     return EDT_OK;
 }
 

@@ -26,7 +26,7 @@ struct GRow {
 
 // Byte offsets of the sections of the device copy of the plan.
 struct DevLayout {
-    size_t freq, zif, cls_k, row_off, pair_u, rows, urow_off, urows, umem_off, umem,
+    size_t freq, zif, cls_k, row_off, pair_u, rows, keys, urow_off, urows, umem_off, umem,
         row_unique, urow_pair, tab_off, tab_ent, items, sched, pair_item, ritems, rsched, pair_ritem,
         grow, gsc, total;
 };
@@ -41,6 +41,7 @@ constexpr int kMaxDepth = 448;
 constexpr int kMaxAdjointDepth = 256;
 // Refinement sweeps of one solve at most (device counters per sweep).
 constexpr int kMaxRefine = 62;
+constexpr int kMaxLine = 2048;   // longest 1D transform of the shot-record and model transforms
 constexpr int kMaxSignIter = 200;   // sign-iteration steps of the truncated-SVD solve at most
 constexpr int n_super(int nz) { return (nz + kSuperDepth - 1) / kSuperDepth; }
 constexpr int rpart_width(int nz) { return 2 * nz + n_super(nz); }

@@ -600,6 +600,7 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
         L.row_off = off;   off = align256(off + p->row_off.size() * 8);
         L.pair_u = off;    off = align256(off + p->pair_u.size() * 4);
         L.rows = off;      off = align256(off + std::max<size_t>(1, p->rows.size()) * 4);
+        L.keys = off;      off = align256(off + std::max<size_t>(1, p->keys.size()) * 4);
         L.urow_off = off;  off = align256(off + p->urow_off.size() * 8);
         L.urows = off;     off = align256(off + std::max<size_t>(1, p->urows.size()) * 4);
         L.umem_off = off;  off = align256(off + p->umem_off.size() * 4);
@@ -625,6 +626,7 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
         put(L.row_off, p->row_off.data(), p->row_off.size() * 8);
         put(L.pair_u, p->pair_u.data(), p->pair_u.size() * 4);
         put(L.rows, p->rows.data(), p->rows.size() * 4);
+        put(L.keys, p->keys.data(), p->keys.size() * 4);
         put(L.urow_off, p->urow_off.data(), p->urow_off.size() * 8);
         put(L.urows, p->urows.data(), p->urows.size() * 4);
         put(L.umem_off, p->umem_off.data(), p->umem_off.size() * 4);

@@ -73,6 +73,9 @@ class Plan:
         _lib.check(L.edt_plan_query(h, C.byref(info)), "edt_plan_query")
         self.info = {k: getattr(info, k) for k, _ in _lib.PlanInfo._fields_}
         self.nz = int(survey.nz)
+        self.dim = int(getattr(survey, "dim", 2))
+        self.n_mid = int(survey.n_mid)
+        self.n_freq = int(info.n_freq)
         self.n_km = int(info.n_km)
         self.n_pairs = int(info.n_pairs)
         self.n_pairs_all = int(info.n_pairs_all)
@@ -247,6 +250,30 @@ class Plan:
                                                _ptr(n_keep) if n_keep is not None else None, _ptr(tsvd_work),
                                                _stream()), "edt_kz_restrict")
         return n_keep
+
+    def shots_fft(self, shots):
+        """In place: shots[n_freq, N, N] (complex128, [f, receiver, source]) becomes
+        d_mid times its DFT over receivers and sources."""
+        self.upload()
+        _lib.check(_lib.load().edt_shots_fft(self._h, _ptr(shots), _stream()), "edt_shots_fft")
+        return shots
+
+    def shots_pack(self, spectrum, out=None):
+        """d_rows[R, 2] (complex128) of this plan's rows from a shots_fft spectrum."""
+        self.upload()
+        d = out if out is not None else self._c128(self.n_rows, 2)
+        _lib.check(_lib.load().edt_shots_pack(self._h, _ptr(spectrum), _ptr(d), _stream()), "edt_shots_pack")
+        return d
+
+    def model(self, v, out=None, overwrite=False):
+        """The real model V(x, z) ([N, nz], or [N, N, nz] in 3D) from the spectrum
+        v[n_km, nz]; v is used as scratch when overwrite is set, else copied."""
+        self.upload()
+        w = v if overwrite else v.clone()
+        shape = (self.n_mid, self.n_mid, self.nz) if self.dim == 3 else (self.n_mid, self.nz)
+        m = out if out is not None else torch.empty(shape, dtype=torch.float64, device=self.device)
+        _lib.check(_lib.load().edt_model(self._h, _ptr(w), _ptr(m), _stream()), "edt_model")
+        return m
 
     def forward(self, g64, v, out=None):
         """Born data rows d_rows[R, 2] (complex128) of the model spectrum v[n_km, nz]."""
