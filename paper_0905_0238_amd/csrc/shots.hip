@@ -4,8 +4,9 @@
 //
 // Both are batches of 1D discrete Fourier transforms along one axis of a
 // dense array, done one line (or a few adjacent lines) per block in LDS:
-// radix-2 decimation in time from bit-reversed loads for a power-of-two
-// length, a direct sum over an exact twiddle table otherwise.  Twiddles are
+// decimation in time from bit-reversed loads for a power-of-two length (three
+// radix-2 levels per pass over LDS, in registers), a direct sum over an exact
+// twiddle table otherwise.  Twiddles are
 // sincospi(2k/n) (exact angle reduction), so the transform is accurate to a
 // few units of rounding times log2(n).  The data are streamed through HBM
 // once per axis; the lines of an axis with unit stride between neighbours are
@@ -23,6 +24,37 @@ struct Lines {
     int64_t slab, step, stride;
     int per_slab;
 };
+
+// R consecutive radix-2 levels of decimation in time (spans h, 2h, ..., R h / 2)
+// in registers: a thread takes the R elements b0 + t h of one group, so a
+// length 2^m takes ceil(m / 3) passes over LDS instead of m.  At the level of
+// span H = lv h (blocks of M = 2H) element i pairs with i + H under the
+// twiddle W_M^(i mod H), and i mod H = pos + (t mod lv) h.
+template <int R>
+__device__ __forceinline__ void dit_levels(zd* s_x, const zd* s_w, int n, int h, int L) {
+    const int groups = n / R;
+    for (int g = threadIdx.x; g < L * groups; g += 256) {
+        const int j = g / groups, gg = g - j * groups;
+        const int pos = gg & (h - 1), blk = gg / h;
+        const int b0 = j * n + blk * R * h + pos;
+        zd x[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) x[t] = s_x[b0 + t * h];
+#pragma unroll
+        for (int lv = 1; lv < R; lv <<= 1) {
+            const int tstep = n / (2 * lv * h);
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                if (t & lv) continue;
+                const zd u = s_w[(pos + (t & (lv - 1)) * h) * tstep] * x[t + lv];
+                x[t + lv] = x[t] - u;
+                x[t] = x[t] + u;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < R; ++t) s_x[b0 + t * h] = x[t];
+    }
+}
 
 template <bool POW2>
 __global__ __launch_bounds__(256) void dft_lines_kernel(zd* __restrict__ data, int n, int logn, Lines g, int L,
@@ -51,17 +83,20 @@ __global__ __launch_bounds__(256) void dft_lines_kernel(zd* __restrict__ data, i
     }
     __syncthreads();
     if constexpr (POW2) {
-        const int half = n / 2;
-        for (int h = 1; h < n; h <<= 1) {
-            const int tstep = n / (2 * h);
-            for (int b = tid; b < L * half; b += 256) {
-                const int j = b / half, bb = b - j * half;
-                const int pos = bb & (h - 1), grp = bb / h;
-                const int i0 = j * n + grp * 2 * h + pos, i1 = i0 + h;
-                const zd t = s_w[pos * tstep] * s_x[i1];
-                const zd a = s_x[i0];
-                s_x[i0] = a + t;
-                s_x[i1] = a - t;
+        int h = 1;
+        for (int rem = logn; rem > 0;) {
+            if (rem >= 3) {
+                dit_levels<8>(s_x, s_w, n, h, L);
+                h *= 8;
+                rem -= 3;
+            } else if (rem == 2) {
+                dit_levels<4>(s_x, s_w, n, h, L);
+                h *= 4;
+                rem -= 2;
+            } else {
+                dit_levels<2>(s_x, s_w, n, h, L);
+                h *= 2;
+                rem -= 1;
             }
             __syncthreads();
         }
@@ -115,6 +150,8 @@ hipError_t launch_lines(zd* data, int n, int64_t n_slabs, Lines g, double sign, 
     if (n < 1 || n > kMaxLine) return hipErrorInvalidValue;
     const bool p2 = is_pow2(n);
     const int nw = p2 ? n / 2 : n;
+    // (8 adjacent lines, for 128-byte loads, measured slower: the larger
+    // LDS footprint halves the blocks per CU)
     int L = 1;
     for (int c : {4, 2}) {
         if (g.per_slab % c == 0 && size_t(c * n + nw) * sizeof(zd) <= kLineLds) {
