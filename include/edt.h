@@ -316,7 +316,8 @@ edt_status edt_solve(const edt_plan* plan, const edt_c128* g64, const edt_c128* 
  * of sigma^2 has no definite side) and EDT_INFO_EMPTY for an empty pair (x =
  * 0).  iters[p]: sign steps taken (device, int32).  work: the plan's
  * workspace; tsvd_work: device, >= edt_tsvd_work_bytes (three nz x nz FP64
- * matrices per pair and small per-pair state).
+ * matrices per pair and small per-pair state).  A plan with no pairs returns
+ * EDT_OK at once, its pointers unused.
  */
 edt_status edt_tsvd_work_bytes(const edt_plan* plan, size_t* bytes);
 edt_status edt_tsvd(const edt_plan* plan, double* gram, const double* rhs, double tol_rel, int max_iter,
@@ -346,7 +347,8 @@ edt_status edt_kz_disk_radius(const edt_plan* plan, double factor, double* k_dis
  * whose Gram and rhs become zero).  tsvd_work: device, >= edt_tsvd_work_bytes,
  * used as scratch (it holds nothing between this call and edt_tsvd).
  * Errors: EDT_EINVAL for a null gram, rhs or tsvd_work, or k_disk negative
- * or not finite.
+ * or not finite.  A plan with no pairs (an empty pair range) returns EDT_OK
+ * at once, its pointers unused.
  */
 edt_status edt_kz_restrict(const edt_plan* plan, double k_disk, double* gram, double* rhs, int32_t* n_keep,
                            void* tsvd_work, hipStream_t stream);

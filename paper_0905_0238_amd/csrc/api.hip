@@ -312,16 +312,17 @@ edt_status edt_tsvd(const edt_plan* p, double* gram, const double* rhs, double t
                     hipStream_t stream) {
     edt_status s = check_plan(p);
     if (s != EDT_OK) return s;
-    if (!gram || !rhs || !x || !v_out || !info || !iters || !work || !tsvd_work) {
-        set_error("missing argument");
-        return EDT_EINVAL;
-    }
     if (!(tol_rel >= 0.0) || !std::isfinite(tol_rel)) {
         set_error("tol_rel must be finite and >= 0");
         return EDT_EINVAL;
     }
     if (max_iter < 1 || max_iter > kMaxSignIter) {
         set_error("max_iter must be in [1, " + std::to_string(kMaxSignIter) + "]");
+        return EDT_EINVAL;
+    }
+    if (p->n_pairs == 0) return EDT_OK;   // an empty pair range
+    if (!gram || !rhs || !x || !v_out || !info || !iters || !work || !tsvd_work) {
+        set_error("missing argument");
         return EDT_EINVAL;
     }
     const WorkLayout wl = work_layout(p);
@@ -366,12 +367,13 @@ edt_status edt_kz_restrict(const edt_plan* p, double k_disk, double* gram, doubl
                            void* tsvd_work, hipStream_t stream) {
     edt_status s = check_plan(p);
     if (s != EDT_OK) return s;
-    if (!gram || !rhs || !tsvd_work) {
-        set_error("missing argument");
-        return EDT_EINVAL;
-    }
     if (!(k_disk >= 0.0) || !std::isfinite(k_disk)) {
         set_error("k_disk must be finite and >= 0");
+        return EDT_EINVAL;
+    }
+    if (p->n_pairs == 0) return EDT_OK;   // an empty pair range
+    if (!gram || !rhs || !tsvd_work) {
+        set_error("missing argument");
         return EDT_EINVAL;
     }
     EDT_TRY(launch_kz_restrict(p, k_disk, gram, rhs, static_cast<unsigned char*>(tsvd_work), n_keep, stream),

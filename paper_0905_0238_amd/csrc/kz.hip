@@ -203,6 +203,7 @@ __global__ __launch_bounds__(256) void kz_rhs_kernel(double* __restrict__ rhs, c
 // q table in the first sign-iterate buffer, T in the product buffer.
 hipError_t launch_kz_restrict(const edt_plan* p, double K, double* gram, double* rhs, unsigned char* tw,
                               int32_t* n_keep, hipStream_t st) {
+    if (p->n_pairs == 0) return hipSuccess;
     const TsvdLayout l = tsvd_layout(p);
     const int nz = p->nz, nt = (nz + 63) / 64;
     const unsigned P = unsigned(p->n_pairs);

@@ -280,6 +280,7 @@ TsvdLayout tsvd_layout(const edt_plan* p) {
 
 hipError_t launch_tsvd_init(const edt_plan* p, const double* gram, double tol_rel, unsigned char* tw,
                             int32_t* iters, hipStream_t st) {
+    if (p->n_pairs == 0) return hipSuccess;
     const TsvdLayout l = tsvd_layout(p);
     hipLaunchKernelGGL(tsvd_init_kernel, dim3(unsigned(p->n_pairs)), dim3(256), 0, st, gram,
                        dptr<const int64_t>(p, p->lay.urow_off), p->nz, tol_rel,
@@ -292,6 +293,7 @@ hipError_t launch_tsvd_init(const edt_plan* p, const double* gram, double tol_re
 // scaling a (a = 1: a plain step, after which converged pairs stop).
 hipError_t launch_tsvd_step(const edt_plan* p, int k, double a, unsigned char* tw, int32_t* iters,
                             hipStream_t st) {
+    if (p->n_pairs == 0) return hipSuccess;
     const TsvdLayout l = tsvd_layout(p);
     const int nz = p->nz, nt = (nz + 63) / 64;
     double* xa = reinterpret_cast<double*>(tw + ((k & 1) ? l.x1 : l.x0));
@@ -309,6 +311,7 @@ hipError_t launch_tsvd_step(const edt_plan* p, int k, double a, unsigned char* t
 
 hipError_t launch_tsvd_final(const edt_plan* p, double* gram, const double* rhs, unsigned char* tw,
                              const int32_t* iters, hipStream_t st) {
+    if (p->n_pairs == 0) return hipSuccess;
     const TsvdLayout l = tsvd_layout(p);
     hipLaunchKernelGGL(tsvd_final_kernel, dim3(unsigned(p->n_pairs)), dim3(256), 0, st, gram,
                        reinterpret_cast<const double*>(tw + l.x0), reinterpret_cast<const double*>(tw + l.x1),

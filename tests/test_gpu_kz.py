@@ -177,6 +177,20 @@ def test_disk_holding_everything_and_disk_of_radius_zero():
     assert np.max(np.abs(v - Vo)) <= 1e-10 * np.max(np.abs(Vo))
 
 
+def test_empty_pair_range():
+    """A plan of an empty pair range: restriction and solve do nothing."""
+    s = layered_small()
+    p = E.Plan(s, pairs=(3, 3))
+    assert p.n_pairs == 0
+    g = torch.zeros(0, s.nz, s.nz, dtype=torch.float64, device="cuda")
+    c = torch.zeros(0, 2, s.nz, dtype=torch.float64, device="cuda")
+    work = p.tsvd_work()
+    p.kz_restrict(g, c, 0.1, work, n_keep=True)
+    _, v, info, _ = p.tsvd(g, c, 1e-2, tsvd_work=work)
+    torch.cuda.synchronize()
+    assert v.shape[0] == p.n_km
+
+
 def test_restriction_rejects_bad_arguments():
     s = layered_small()
     p = E.Plan(s)
