@@ -213,6 +213,26 @@ def make_custom(*, dim=2, N=32, dx=12.5, Nh=0, nz=24, dz=10.0, freqs=(5.0, 10.0,
                   int(seed), v, data_c64)
 
 
+def make_square_experiment(*, depth=1500.0, two_layer=False, freqs=(1.0, 2.0, 3.0, 4.0, 5.0), N=800,
+                           tol_scale=None, seed=0) -> Survey:
+    """The numerical examples of Section 3.2: a 2D line of N positions at 50 m
+    (N = 800: the 40 km survey), depths 800-4000 m at 50 m, sources and
+    receivers at z = 0, imaginary frequency 0.15 1/s; reference water
+    (1500 m/s), or water above 1 km over 4000 m/s; model V = 1 inside a
+    1 km square centred at x = 0 and the given depth, 0 elsewhere."""
+    dx, dz, z0, nz = 50.0, 50.0, 800.0, 65
+    vel = (1500.0, 4000.0) if two_layer else (1500.0,)
+    zif = (1000.0,) if two_layer else ()
+    n = np.arange(N)
+    x = np.where(n < (N + 1) // 2, n, n - N) * dx
+    z = z0 + dz * np.arange(nz)
+    inside_x = (x >= -500.0) & (x < 500.0)
+    inside_z = (z >= depth - 500.0) & (z < depth + 500.0)
+    v = (inside_x[:, None] & inside_z[None, :]).astype(np.float64)
+    return Survey("square", 2, N, dx, 0, 0.0, np.asarray(freqs, np.float64), EPS_DEFAULT, nz, dz, z0, 1.0,
+                  np.asarray(vel, np.float64), np.asarray(zif, np.float64), 0.0, 0.0, int(seed), v, False)
+
+
 def vhat(s: Survey) -> np.ndarray:
     """Unnormalised horizontal DFT of the model, fftfreq order.
 
