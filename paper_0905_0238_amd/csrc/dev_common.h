@@ -72,6 +72,19 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
     return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
 }
 
+// Work item (pair p, tile) of block b when the P x T items of a batched
+// per-pair product are dealt to the eight XCDs pair by pair (block b runs on
+// XCD b % 8): every tile of a pair runs on one XCD, so the pair's matrices are
+// read into one L2 instead of eight.  Grid: kXcds ceil(P / kXcds) T blocks;
+// p >= P marks a block with no item.
+constexpr int kXcds = 8;
+__device__ __forceinline__ void xcd_pair_tile(unsigned b, int T, int& p, int& tile) {
+    const unsigned j = b / unsigned(kXcds);
+    p = int((j / unsigned(T)) * unsigned(kXcds) + b % unsigned(kXcds));
+    tile = int(j % unsigned(T));
+}
+inline unsigned xcd_pair_grid(int64_t P, int T) { return unsigned((P + kXcds - 1) / kXcds * kXcds * T); }
+
 // Sum of a double over the 64 lanes of a wave (every lane gets the total).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

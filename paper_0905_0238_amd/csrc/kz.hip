@@ -68,19 +68,22 @@ __global__ __launch_bounds__(256) void kz_q_kernel(const int32_t* __restrict__ p
     if (tid == 0 && n_keep) n_keep[p] = jmax < 0 ? 0 : 1 + 2 * jc + (nyq ? 1 : 0);
 }
 
-// One product per pair and 64 x 64 tile; K in chunks of 32 staged in LDS with
+// One product per pair and 64 x 64 tile (tiles dealt to the XCDs pair by
+// pair); K in chunks of 32 staged in LDS with
 // the next chunk's operands fetched into registers during the current chunk's
 // MFMAs (each wave a 32 x 32 quarter: 2 x 2 v_mfma_f64_16x16x4 tiles).
 //   MODE 0: T = G Q, every tile; G from its lower triangle.
 //   MODE 1: G' = Q T, lower tiles; the elements with i >= j are stored.
 template <int MODE>
 __global__ __launch_bounds__(256) void kz_gemm_kernel(const double* __restrict__ S, const double* __restrict__ q,
-                                                      double* __restrict__ C, int nz, int nt) {
+                                                      double* __restrict__ C, int nz, int nt, int n_pairs) {
     __shared__ double As[64][33];
     __shared__ double Bs[32][65];
     __shared__ double s_q[kMaxDepth];
     const int ntile = MODE == 0 ? nt * nt : nt * (nt + 1) / 2;
-    const int p = int(blockIdx.x / unsigned(ntile)), tile = int(blockIdx.x % unsigned(ntile));
+    int p, tile;
+    xcd_pair_tile(blockIdx.x, ntile, p, tile);
+    if (p >= n_pairs) return;
     int ti, tj;
     if constexpr (MODE == 0) {
         ti = tile / nt;
@@ -211,9 +214,10 @@ hipError_t launch_kz_restrict(const edt_plan* p, double K, double* gram, double*
     double* T = reinterpret_cast<double*>(tw + l.y);
     hipLaunchKernelGGL(kz_q_kernel, dim3(P), dim3(256), 0, st, dptr<const int32_t>(p, p->lay.pair_u), p->dim,
                        p->n_mid, p->d_mid, nz, p->dz, K, q, n_keep);
-    hipLaunchKernelGGL(kz_gemm_kernel<0>, dim3(P * unsigned(nt * nt)), dim3(256), 0, st, gram, q, T, nz, nt);
-    hipLaunchKernelGGL(kz_gemm_kernel<1>, dim3(P * unsigned(nt * (nt + 1) / 2)), dim3(256), 0, st, T, q, gram,
-                       nz, nt);
+    hipLaunchKernelGGL(kz_gemm_kernel<0>, dim3(xcd_pair_grid(P, nt * nt)), dim3(256), 0, st, gram, q, T, nz, nt,
+                       int(P));
+    hipLaunchKernelGGL(kz_gemm_kernel<1>, dim3(xcd_pair_grid(P, nt * (nt + 1) / 2)), dim3(256), 0, st, T, q, gram,
+                       nz, nt, int(P));
     hipLaunchKernelGGL(kz_rhs_kernel, dim3(P), dim3(256), 0, st, rhs, q, nz);
     return hipGetLastError();
 }

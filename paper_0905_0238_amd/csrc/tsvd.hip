@@ -109,8 +109,8 @@ __global__ __launch_bounds__(256) void tsvd_init_kernel(const double* __restrict
 
 // One product of the sign iteration for every pair still iterating.  Every
 // iterate is a polynomial in G, so both products are symmetric: only the
-// lower 64 x 64 tiles are computed (block b: pair b / T, tile b % T of the
-// T = nt (nt + 1) / 2 lower tiles) and an off-diagonal tile is also stored
+// lower 64 x 64 tiles are computed (T = nt (nt + 1) / 2 per pair, dealt to
+// the XCDs pair by pair) and an off-diagonal tile is also stored
 // mirrored.  K runs in chunks of 32 staged in LDS, the next chunk's loads in
 // flight during the current chunk's v_mfma_f64_16x16x4 (each wave a 32 x 32
 // quarter: 2 x 2 MFMA tiles; lane l of register v holds row 4 v + l / 16,
@@ -120,13 +120,15 @@ __global__ __launch_bounds__(256) void tsvd_init_kernel(const double* __restrict
 template <int MODE>
 __global__ __launch_bounds__(256) void ns_gemm_kernel(const double* __restrict__ X, const double* __restrict__ B,
                                                       double* __restrict__ C, const int32_t* __restrict__ conv,
-                                                      double* __restrict__ dpart, int nz, int nt, double a) {
+                                                      double* __restrict__ dpart, int nz, int nt, double a,
+                                                      int n_pairs) {
     __shared__ double As[64][33];
     __shared__ double Bs[32][65];
     __shared__ double s_red[4];
     const int ntri = nt * (nt + 1) / 2;
-    const int p = int(blockIdx.x / unsigned(ntri)), tile = int(blockIdx.x % unsigned(ntri));
-    if (conv[p]) return;
+    int p, tile;
+    xcd_pair_tile(blockIdx.x, ntri, p, tile);
+    if (p >= n_pairs || conv[p]) return;
     int ti = 0;
     while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
     const int tj = tile - ti * (ti + 1) / 2;
@@ -301,9 +303,10 @@ hipError_t launch_tsvd_step(const edt_plan* p, int k, double a, unsigned char* t
     double* y = reinterpret_cast<double*>(tw + l.y);
     double* dpart = reinterpret_cast<double*>(tw + l.dpart);
     int32_t* conv = reinterpret_cast<int32_t*>(tw + l.conv);
-    const dim3 grid(unsigned(nt * (nt + 1) / 2 * p->n_pairs));
-    hipLaunchKernelGGL(ns_gemm_kernel<0>, grid, dim3(256), 0, st, xa, xa, y, conv, dpart, nz, nt, 1.0);
-    hipLaunchKernelGGL(ns_gemm_kernel<1>, grid, dim3(256), 0, st, xa, y, xb, conv, dpart, nz, nt, a);
+    const int P = int(p->n_pairs);
+    const dim3 grid(xcd_pair_grid(P, nt * (nt + 1) / 2));
+    hipLaunchKernelGGL(ns_gemm_kernel<0>, grid, dim3(256), 0, st, xa, xa, y, conv, dpart, nz, nt, 1.0, P);
+    hipLaunchKernelGGL(ns_gemm_kernel<1>, grid, dim3(256), 0, st, xa, y, xb, conv, dpart, nz, nt, a, P);
     hipLaunchKernelGGL(ns_check_kernel, dim3(unsigned((p->n_pairs + 255) / 256)), dim3(256), 0, st, dpart, nt,
                        conv, iters, int(p->n_pairs), a == 1.0 ? 1 : 0);
     return hipGetLastError();
