@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--max-refine", type=int, default=8)
     ap.add_argument("--chunk", type=int, default=0, help="rows per Gram item (0 = planner default)")
     ap.add_argument("--band", type=int, default=0, help="frequencies per Gram band (0 = planner default)")
-    ap.add_argument("--cpu-pairs", type=int, default=48)
+    ap.add_argument("--cpu-pairs", type=int, default=160, help="pairs in the oracle leg (about 10 s of host work)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--only", choices=["both", "mixed", "fp64"], default="both")
     ap.add_argument("--tune", action="store_true", help="autotune chunk_rows / gram_band per precision first")
