@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void kz_q_kernel(const int32_t* __restrict__ p
 //   MODE 0: T = G Q, every tile; G from its lower triangle.
 //   MODE 1: G' = Q T, lower tiles; the elements with i >= j are stored.
 template <int MODE>
-__global__ __launch_bounds__(256) void kz_gemm_kernel(const double* __restrict__ S, const double* __restrict__ q,
+__global__ __launch_bounds__(256, 4) void kz_gemm_kernel(const double* __restrict__ S, const double* __restrict__ q,
                                                       double* __restrict__ C, int nz, int nt, int n_pairs) {
     __shared__ double As[64][33];
     __shared__ double Bs[32][65];
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void kz_gemm_kernel(const double* __restrict__
         }
         __syncthreads();
         if (k0 + 32 < nz) fetch(k0 + 32);
-#pragma unroll
+#pragma unroll 2
         for (int kk = 0; kk < 32; kk += 4) {
             const double a0 = As[wr + li][kk + lk], a1 = As[wr + 16 + li][kk + lk];
             const double b0 = Bs[kk + lk][wc + li], b1 = Bs[kk + lk][wc + 16 + li];

@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void tsvd_init_kernel(const double* __restrict
 //   MODE 0: C = X X,                 and per tile sum (C - I)^2 -> dpart
 //   MODE 1: C = 1.5 a X - 0.5 a^3 X B      (B = X X)
 template <int MODE>
-__global__ __launch_bounds__(256) void ns_gemm_kernel(const double* __restrict__ X, const double* __restrict__ B,
+__global__ __launch_bounds__(256, 4) void ns_gemm_kernel(const double* __restrict__ X, const double* __restrict__ B,
                                                       double* __restrict__ C, const int32_t* __restrict__ conv,
                                                       double* __restrict__ dpart, int nz, int nt, double a,
                                                       int n_pairs) {
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(256) void ns_gemm_kernel(const double* __restrict__
         }
         __syncthreads();
         if (k0 + 32 < nz) fetch(k0 + 32);
-#pragma unroll
+#pragma unroll 2
         for (int kk = 0; kk < 32; kk += 4) {
             const double a0 = As[wr + li][kk + lk], a1 = As[wr + 16 + li][kk + lk];
             const double b0 = Bs[kk + lk][wc + li], b1 = Bs[kk + lk][wc + 16 + li];
