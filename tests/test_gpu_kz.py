@@ -7,11 +7,15 @@ on the restricted system, against the oracle (oracle.kz), pair by pair.
   F F^T G F F^T and F F^T c (F its orthonormal basis of the kept modes), to
   1e-12 of the pair's largest Gram entry;
 * the restricted truncated-SVD solution against the oracle's solve on the
-  basis F, with the conditioning-derived bar of the plain truncated-SVD test:
-  max(1e-10, 100 u (lambda_max / lambda_min,kept + lambda_max / gap)), where
-  the gap now also counts the dropped modes (eigenvalue 0, at sigma^2 from the
-  threshold); pairs with an eigenvalue within a relative 1e-6 of sigma^2 are
-  left out and counted;
+  basis F, with the conditioning-derived bar of the plain truncated-SVD test
+  widened by the rounding of the restriction itself: Q G Q is two products of
+  length nz, each within gamma_nz ~ nz u of exact relative to ||G|| (the
+  standard product bound, ||Q|| = 1), so a Gram perturbation of up to
+  2 nz u ||G|| enters beside the 100 u of the solve:
+  max(1e-10, (100 + 2 nz) u (lambda_max / lambda_min,kept + lambda_max / gap)),
+  where the gap also counts the dropped modes (eigenvalue 0, at sigma^2 from
+  the threshold); pairs with an eigenvalue within a relative 1e-6 of sigma^2
+  are left out and counted;
 * a disk that holds every k_z leaves the system unchanged, a disk of radius 0
   keeps only the constant mode of k_m = 0, and at the full size of the 2D
   N = 512 survey a seeded sample of pairs matches the oracle.
@@ -38,6 +42,7 @@ def _cases():
     return {
         "cfg1": lambda: make_config(1),
         "layered-nz40": lambda: layered_small(),
+        "layered-nz200": lambda: layered_small(nz=200, N=32, nf=6, seed=3),
         "homogeneous": lambda: make_custom(N=32, nz=33, dx=12.5, dz=8.0, freqs=(6.0, 17.0, 29.0, 41.0),
                                            vel=(2300.0,), zif=(), noise_rel=0.05, seed=11),
         "3d-small": lambda: make_custom(dim=3, N=12, Nh=6, nz=37, dx=25.0, dz=10.0,
@@ -97,7 +102,8 @@ def test_restricted_gram_and_rhs(name, scale):
         scale_g = np.max(np.abs(np.tril(G_in[q])))
         assert np.max(np.abs(Gq[q][low] - ref_G[low])) <= 1e-12 * scale_g, (name, q)
         assert np.max(np.abs(cq[q] - ref_c)) <= 1e-12 * max(np.max(np.abs(c)), 1e-300), (name, q)
-    assert cut > 0, "the disk cuts no pair: the case does not exercise the restriction"
+    if scale < 1.0:
+        assert cut > 0, "the disk cuts no pair: the case does not exercise the restriction"
 
 
 def _check_solution(name, s, pl, v, info, Vo, info_o, n_keep, tol):
@@ -120,7 +126,7 @@ def _check_solution(name, s, pl, v, info, Vo, info_o, n_keep, tol):
         kept = w[w >= t2]
         lmax = w.max()
         kappa = lmax / kept.min() if kept.size else 0.0
-        bar = max(1e-10, 100 * u * (kappa + lmax / gap))
+        bar = max(1e-10, (100 + 2 * s.nz) * u * (kappa + lmax / gap))
         ref = Vo[idx]
         err = np.linalg.norm(v[idx] - ref) / max(np.linalg.norm(ref), 1e-3 * nv)
         assert err <= bar, (name, tol, q, err, bar)
