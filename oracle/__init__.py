@@ -24,6 +24,8 @@ tsvd    the paper's own solver: truncated SVD of each pair's system (through
         the eigen-decomposition of its Gram), with a relative tolerance.
 kz      the restriction of the solution to a disk in (k_m, k_z): the truncated
         SVD of each pair's system on the kept discrete Fourier modes in depth.
+aperture  finite aperture on the 2D line: the offset window as a discrete sinc
+        over the receiver index, the windowed Gram Re(A^H S A) and its solve.
 shots   the transforms on either side: 2D shot records to the packed rows, and
         the solution spectrum V~ to the model V(x, z).
 
