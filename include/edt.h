@@ -374,6 +374,26 @@ edt_status edt_shots_fft(const edt_plan* plan, edt_c128* shots, hipStream_t stre
 edt_status edt_shots_pack(const edt_plan* plan, const edt_c128* spectrum, edt_c128* d_rows, hipStream_t stream);
 
 /*
+ * Finite aperture (eq. M) on the 2D line survey: the Gram of every pair when
+ * the records are kept only for full offsets |x_R - x_S| <= 2 b_max (b_max:
+ * the largest half-offset, m).  On the periodic line the offset window acts
+ * at each k_m as a circular convolution S of the rows over the receiver
+ * index with the window's DFT (the discrete sinc of eq. M), an orthogonal
+ * projector, so the normal equations of the windowed data keep edt_assemble's
+ * right-hand sides and take the Gram Re(A^H S A), formed here per frequency
+ * from the rows transformed over the receiver index, over the kept offsets.
+ * gram: device [P][nz][nz], lower triangle written (FP64); trace: device [P],
+ * its trace.  Solve with edt_solve without refinement (the refinement works
+ * from the unwindowed rows) or edt_tsvd.  aperture_work: device, >=
+ * edt_aperture_work_bytes (P n_mid nz complex128: the rows of one frequency).
+ * Errors: EDT_EINVAL for dim 3, n_mid > 2048, b_max negative or not finite,
+ * or a null pointer (a plan with no pairs returns EDT_OK at once).
+ */
+edt_status edt_aperture_work_bytes(const edt_plan* plan, size_t* bytes);
+edt_status edt_aperture_gram(const edt_plan* plan, const edt_c128* g64, double b_max, double* gram, double* trace,
+                             void* aperture_work, hipStream_t stream);
+
+/*
  * The model from its spectrum (Section 2.1): v_tilde[n_km][nz] (complex128,
  * device, fftfreq order; 3D u = ux n_mid + uy) is overwritten by its inverse
  * transform over u (over ux and uy in 3D),

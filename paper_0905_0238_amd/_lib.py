@@ -47,7 +47,7 @@ class SolveOpts(C.Structure):
 
 EXPORTS = ["edt_last_error", "edt_plan_create", "edt_survey_pair_rows", "edt_plan_destroy", "edt_plan_query",
            "edt_plan_rowmap", "edt_plan_urows", "edt_plan_schedule", "edt_plan_upload", "edt_green", "edt_assemble", "edt_solve",
-           "edt_forward", "edt_adjoint", "edt_tsvd_work_bytes", "edt_tsvd", "edt_kz_disk_radius", "edt_kz_restrict", "edt_shots_fft", "edt_shots_pack", "edt_model", "edt_timing_enable",
+           "edt_forward", "edt_adjoint", "edt_tsvd_work_bytes", "edt_tsvd", "edt_kz_disk_radius", "edt_kz_restrict", "edt_shots_fft", "edt_shots_pack", "edt_model", "edt_aperture_work_bytes", "edt_aperture_gram", "edt_timing_enable",
            "edt_timing_read"]
 
 _lib = None
@@ -85,6 +85,8 @@ def load(path: str = LIB_PATH):
         "edt_shots_fft": [vp, vp, vp],
         "edt_shots_pack": [vp, vp, vp, vp],
         "edt_model": [vp, vp, vp, vp],
+        "edt_aperture_work_bytes": [vp, C.POINTER(C.c_size_t)],
+        "edt_aperture_gram": [vp, vp, C.c_double, vp, vp, vp, vp],
         "edt_timing_enable": [vp, C.c_int],
         "edt_timing_read": [vp, C.c_int, C.c_char_p, dp, i64p, C.POINTER(C.c_int)],
     }

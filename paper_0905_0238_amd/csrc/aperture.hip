@@ -1,0 +1,204 @@
+// Finite aperture on the 2D line survey (paper eq. M): the Gram of each pair
+// under an offset window |x_R - x_S| <= 2 b.
+//
+// On the periodic line the window acts at each k_m as a circular convolution
+// of the rows over the receiver index a with the window's DFT (the discrete
+// sinc); that convolution S is an orthogonal projector, so the normal
+// equations keep the right-hand sides Re(A^H d_W) of the windowed data and
+// take the Gram
+//     Re(A^H S A) = (1/N) sum_{o in window} Re(Ah(o)^H Ah(o)),
+//     Ah(o, z) = sum_a A(a, z) e^{2 pi i a o / N},
+// with the rows of one frequency transformed over a.  Per frequency: the rows
+// of every pair are laid out densely over a (zero where a row is cut),
+// transformed by the line-transform kernel, and the kept offsets enter a
+// lower-tile FP64 MFMA product that accumulates over the frequencies.  Rows
+// of one frequency mix, so unique rows do not merge here.
+
+#include <cmath>
+
+#include "dev_common.h"
+
+namespace edt {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// R[p][a][z] = w_f0^2 dz g(z; k_r) g(z; k_s) for the rows of pair p at
+// frequency f0 (receiver index a), zero elsewhere.  Rows of a pair are
+// ordered by frequency, so those of f0 are one range, found by bisection.
+__global__ __launch_bounds__(256) void ap_rows_kernel(const zd* __restrict__ g64, const uint32_t* __restrict__ rows,
+                                                      const int32_t* __restrict__ keys,
+                                                      const int64_t* __restrict__ row_off, int f0, int n_cls, int N,
+                                                      int nz, zd scale, zd* __restrict__ R) {
+    __shared__ int64_t s_range[2];
+    const int p = blockIdx.x, tid = threadIdx.x;
+    zd* Rp = R + size_t(p) * N * nz;
+    for (int64_t e = tid; e < int64_t(N) * nz; e += 256) Rp[e] = zd{0.0, 0.0};
+    if (tid < 2) {
+        // first row with frequency >= f0 + tid
+        int64_t lo = row_off[p], hi = row_off[p + 1];
+        const uint32_t key = uint32_t(f0 + tid);
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) / 2;
+            if (rows[2 * mid] < key) lo = mid + 1;
+            else hi = mid;
+        }
+        s_range[tid] = lo;
+    }
+    __syncthreads();
+    const int64_t r0 = s_range[0], n = s_range[1] - s_range[0];
+    const zd* gf = g64 + size_t(f0) * n_cls * nz;
+    for (int64_t e = tid; e < n * nz; e += 256) {
+        const int64_t r = r0 + e / nz;
+        const int z = int(e % nz);
+        const uint32_t c = rows[2 * r + 1];
+        const int a = keys[2 * r];
+        const zd gr = gf[size_t(c & 0xFFFFu) * nz + z], gs = gf[size_t(c >> 16) * nz + z];
+        Rp[size_t(a) * nz + z] = scale * (gr * gs);
+    }
+}
+
+// C (lower tiles, += or =) of (1/N) sum over kept offsets of Re(Ah^H Ah): a
+// real product over K = 2 nW (real and imaginary parts of the nW kept
+// offsets o = (lo + k) mod N).  Tiles dealt to the XCDs pair by pair; K in
+// chunks of 32 staged in LDS, the next chunk's loads in flight.
+__global__ __launch_bounds__(256, 4) void ap_gram_kernel(const zd* __restrict__ Rh, int N, int nz, int nt, int lo,
+                                                         int nW, double invN, int first, double* __restrict__ gram,
+                                                         int n_pairs) {
+    __shared__ double As[64][33];
+    __shared__ double Bs[32][65];
+    const int ntri = nt * (nt + 1) / 2;
+    int p, tile;
+    xcd_pair_tile(blockIdx.x, ntri, p, tile);
+    if (p >= n_pairs) return;
+    int ti = 0;
+    while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+    const int tj = tile - ti * (ti + 1) / 2;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int r0 = 64 * ti, c0 = 64 * tj;
+    const zd* Rp = Rh + size_t(p) * N * nz;
+    const int K = 2 * nW;
+    const int li = lane & 15, lk = lane >> 4;
+    const int wr = 32 * (wv >> 1), wc = 32 * (wv & 1);
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[a][b][v] = 0.0;
+    double ra[8], rb[8];
+    // element kk of K: offset (lo + kk / 2) mod N, real (kk even) or
+    // imaginary part; A(i, kk) = part of Ah[o][r0 + i], B(kk, j) = part of
+    // Ah[o][c0 + j]; threads run along z, so loads are contiguous
+    auto value = [&](int kk, int z) {
+        if (kk >= K || z >= nz) return 0.0;
+        int o = (lo + kk / 2) % N;
+        if (o < 0) o += N;
+        const zd v = Rp[size_t(o) * nz + z];
+        return (kk & 1) ? v.y : v.x;
+    };
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int e = tid + 256 * t;
+            const int zi = e & 63, kk = e >> 6;   // 64 depths x 32 k
+            ra[t] = value(k0 + kk, r0 + zi);
+            rb[t] = value(k0 + kk, c0 + zi);
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < K; k0 += 32) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int e = tid + 256 * t;
+            As[e & 63][e >> 6] = ra[t];
+            Bs[e >> 6][e & 63] = rb[t];
+        }
+        __syncthreads();
+        if (k0 + 32 < K) fetch(k0 + 32);
+#pragma unroll 2
+        for (int kk = 0; kk < 32; kk += 4) {
+            const double a0 = As[wr + li][kk + lk], a1 = As[wr + 16 + li][kk + lk];
+            const double b0 = Bs[kk + lk][wc + li], b1 = Bs[kk + lk][wc + 16 + li];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    double* Cp = gram + size_t(p) * nz * nz;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = r0 + wr + 16 * a + 4 * v + lk, j = c0 + wc + 16 * b + li;
+                if (i < nz && j < nz && i >= j) {
+                    const size_t at = size_t(i) * nz + j;
+                    const double c = invN * acc[a][b][v];
+                    Cp[at] = first ? c : Cp[at] + c;
+                }
+            }
+}
+
+// trace[p] = sum of the diagonal (fixed order).
+__global__ __launch_bounds__(256) void ap_trace_kernel(const double* __restrict__ gram, int nz,
+                                                       double* __restrict__ trace) {
+    __shared__ double s_red[4];
+    const int p = blockIdx.x, tid = threadIdx.x;
+    double t = 0.0;
+    for (int i = tid; i < nz; i += 256) t += gram[size_t(p) * nz * nz + size_t(i) * nz + i];
+    t = wave_sum(t);
+    if ((tid & 63) == 0) s_red[tid >> 6] = t;
+    __syncthreads();
+    if (tid == 0) trace[p] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+}
+
+// ------------------------------------------------------------- launcher ---
+size_t aperture_work_bytes(const edt_plan* p) { return size_t(p->n_pairs) * p->n_mid * p->nz * sizeof(zd); }
+
+// Kept signed offsets: |s| d_mid <= 2 b_max for s in [-N/2, (N - 1)/2]
+// (the same comparison as the oracle's); a contiguous range [lo, lo + nW).
+void aperture_offsets(const edt_plan* p, double b_max, int* lo, int* nW) {
+    const int N = p->n_mid;
+    int first = 0, count = 0;
+    for (int s = -(N / 2); s <= (N - 1) / 2; ++s) {
+        if (std::fabs(double(s)) * p->d_mid <= 2.0 * b_max) {
+            if (!count) first = s;
+            ++count;
+        }
+    }
+    *lo = first;
+    *nW = count;
+}
+
+hipError_t launch_aperture_gram(const edt_plan* p, const zd* g64, double b_max, double* gram, double* trace,
+                                zd* R, hipStream_t st) {
+    if (p->n_pairs == 0) return hipSuccess;
+    const int N = p->n_mid, nz = p->nz, nt = (nz + 63) / 64;
+    const int P = int(p->n_pairs);
+    int lo = 0, nW = 0;
+    aperture_offsets(p, b_max, &lo, &nW);
+    for (int f = 0; f < p->n_freq; ++f) {
+        // w^2 dz with w = 2 pi f + i eps
+        const double wr = kTwoPiD * p->freq[size_t(f)], wi = p->eps;
+        const zd scale{p->dz * (wr * wr - wi * wi), p->dz * (2.0 * wr * wi)};
+        hipLaunchKernelGGL(ap_rows_kernel, dim3(unsigned(P)), dim3(256), 0, st, g64,
+                           dptr<const uint32_t>(p, p->lay.rows), dptr<const int32_t>(p, p->lay.keys),
+                           dptr<const int64_t>(p, p->lay.row_off), f, p->n_cls, N, nz, scale, R);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = launch_lines(R, N, P, Lines{int64_t(N) * nz, 1, nz, nz}, 1.0, 1.0, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(ap_gram_kernel, dim3(xcd_pair_grid(P, nt * (nt + 1) / 2)), dim3(256), 0, st, R, N, nz,
+                           nt, lo, nW, 1.0 / double(N), f == 0 ? 1 : 0, gram, P);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(ap_trace_kernel, dim3(unsigned(P)), dim3(256), 0, st, gram, nz, trace);
+    return hipGetLastError();
+}
+
+}  // namespace edt

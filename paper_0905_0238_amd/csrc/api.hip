@@ -49,6 +49,9 @@ hipError_t launch_tsvd_final(const edt_plan* p, double* gram, const double* rhs,
 hipError_t launch_shots_fft(const edt_plan* p, zd* shots, hipStream_t st);
 hipError_t launch_shots_pack(const edt_plan* p, const zd* F, zd* d_rows, hipStream_t st);
 hipError_t launch_model(const edt_plan* p, zd* v, double* model, hipStream_t st);
+size_t aperture_work_bytes(const edt_plan* p);
+hipError_t launch_aperture_gram(const edt_plan* p, const zd* g64, double b_max, double* gram, double* trace,
+                                zd* R, hipStream_t st);
 hipError_t launch_kz_restrict(const edt_plan* p, double K, double* gram, double* rhs, unsigned char* tw,
                               int32_t* n_keep, hipStream_t st);
 size_t chol_lds_bytes(int nz);
@@ -413,6 +416,42 @@ edt_status edt_shots_pack(const edt_plan* p, const edt_c128* spectrum, edt_c128*
     }
     EDT_TRY(launch_shots_pack(p, reinterpret_cast<const zd*>(spectrum), reinterpret_cast<zd*>(d_rows), stream),
             "shots pack");
+    return EDT_OK;
+}
+
+edt_status edt_aperture_work_bytes(const edt_plan* p, size_t* bytes) {
+    if (!p || !bytes) {
+        set_error("null argument");
+        return EDT_EINVAL;
+    }
+    *bytes = aperture_work_bytes(p);
+    return EDT_OK;
+}
+
+edt_status edt_aperture_gram(const edt_plan* p, const edt_c128* g64, double b_max, double* gram, double* trace,
+                             void* aperture_work, hipStream_t stream) {
+    edt_status s = check_plan(p);
+    if (s != EDT_OK) return s;
+    if (p->dim != 2) {
+        set_error("finite aperture of the 2D line survey only");
+        return EDT_EINVAL;
+    }
+    if (p->n_mid > kMaxLine) {
+        set_error("n_mid > " + std::to_string(kMaxLine) + " is not supported by the transform");
+        return EDT_EINVAL;
+    }
+    if (!(b_max >= 0.0) || !std::isfinite(b_max)) {
+        set_error("b_max must be finite and >= 0");
+        return EDT_EINVAL;
+    }
+    if (p->n_pairs == 0) return EDT_OK;
+    if (!g64 || !gram || !trace || !aperture_work) {
+        set_error("missing argument");
+        return EDT_EINVAL;
+    }
+    EDT_TRY(launch_aperture_gram(p, reinterpret_cast<const zd*>(g64), b_max, gram, trace,
+                                 static_cast<zd*>(aperture_work), stream),
+            "aperture gram");
     return EDT_OK;
 }
 

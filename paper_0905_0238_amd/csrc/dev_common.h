@@ -85,6 +85,16 @@ __device__ __forceinline__ void xcd_pair_tile(unsigned b, int T, int& p, int& ti
 }
 inline unsigned xcd_pair_grid(int64_t P, int T) { return unsigned((P + kXcds - 1) / kXcds * kXcds * T); }
 
+// A batch of 1D transforms along one axis of a dense complex array: line
+// l = (slab, k), k < per_slab, has element i at
+// data[(l / per_slab) * slab + (l % per_slab) * step + i * stride].
+struct Lines {
+    int64_t slab, step, stride;
+    int per_slab;
+};
+// sign -1: forward DFT, +1: inverse (unnormalised), then times scale.
+hipError_t launch_lines(zd* data, int n, int64_t n_slabs, Lines g, double sign, double scale, hipStream_t st);
+
 // Sum of a double over the 64 lanes of a wave (every lane gets the total).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

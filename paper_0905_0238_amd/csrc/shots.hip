@@ -18,13 +18,6 @@ namespace edt {
 
 constexpr size_t kLineLds = 64 * 1024;   // LDS of one block, values and twiddles
 
-// Line l = (slab, k), k < per_slab: element i at
-// data[(l / per_slab) * slab + (l % per_slab) * step + i * stride].
-struct Lines {
-    int64_t slab, step, stride;
-    int per_slab;
-};
-
 // R consecutive radix-2 levels of decimation in time (spans h, 2h, ..., R h / 2)
 // in registers: a thread takes the R elements b0 + t h of one group, so a
 // length 2^m takes ceil(m / 3) passes over LDS instead of m.  At the level of
@@ -142,8 +135,8 @@ __global__ __launch_bounds__(256) void real_part_kernel(const zd* __restrict__ v
 
 // ------------------------------------------------------------- launchers ---
 namespace {
-
 bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+}  // namespace
 
 // One batch of transforms of length n over n_slabs * g.per_slab lines.
 hipError_t launch_lines(zd* data, int n, int64_t n_slabs, Lines g, double sign, double scale, hipStream_t st) {
@@ -173,8 +166,6 @@ hipError_t launch_lines(zd* data, int n, int64_t n_slabs, Lines g, double sign, 
                            L, sign, scale);
     return hipGetLastError();
 }
-
-}  // namespace
 
 hipError_t configure_lines() {
     for (const void* k : {reinterpret_cast<const void*>(dft_lines_kernel<true>),

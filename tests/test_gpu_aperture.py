@@ -1,0 +1,94 @@
+"""GPU: the finite-aperture Gram (edt_aperture_gram) and its damped solve
+against the oracle (oracle.aperture), pair by pair.
+
+* the windowed Gram Re(A^H S A) and its trace against the oracle's product
+  with the discrete-sinc matrix, to 1e-12 of the pair's largest entry, for
+  power-of-two and other line lengths (both transform paths), ragged depths,
+  two half-apertures and a window holding every offset (which must give
+  edt_assemble's FP64 Gram);
+* the FP64 damped solve (edt_solve without refinement) on that Gram against
+  the oracle's solve, to the FP64 bar 1e-10 (global and per pair);
+* 3D surveys are refused.
+"""
+import numpy as np
+import pytest
+
+from edt_inputs import make_config, make_custom
+from oracle.aperture import aperture_rows, aperture_solve, offset_window, window_kernel
+from oracle.rows import row_values
+from tests._cases import oracle_case, layered_small, rel_errors
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+E = pytest.importorskip("paper_0905_0238_amd")
+
+
+def _cases():
+    return {
+        "cfg1-N64": lambda: make_config(1),
+        "N48-layered": lambda: layered_small(),
+        "N32-nz200": lambda: layered_small(nz=200, N=32, nf=6, seed=3),
+        "N32-homogeneous": lambda: make_custom(N=32, nz=33, dx=12.5, dz=8.0, freqs=(6.0, 17.0, 29.0, 41.0),
+                                               vel=(2300.0,), zif=(), noise_rel=0.05, seed=11),
+    }
+
+
+def _gpu(s, r, b_max):
+    p = E.Plan(s)
+    vel = torch.tensor(np.asarray(s.vel, np.float64), device="cuda")
+    g64, _ = p.green(vel, want32=False)
+    d = torch.from_numpy(r["d_rows"]).cuda()
+    gram_full, rhs, trace_full = p.assemble(g64, None, d, "fp64")
+    gram, trace = p.aperture_gram(g64, b_max)
+    torch.cuda.synchronize()
+    return p, g64, d, gram, trace, gram_full, rhs, trace_full
+
+
+@pytest.mark.parametrize("frac", [0.15, 0.3])
+@pytest.mark.parametrize("name", list(_cases()))
+def test_aperture_gram_and_solve(name, frac):
+    s = _cases()[name]()
+    r = oracle_case(s)
+    b_max = frac * s.n_mid * s.d_mid / 2
+    w = offset_window(s, b_max)
+    assert 0 < w.sum() < s.n_mid
+    Sm = window_kernel(w)
+    p, g64, d, gram, trace, _, rhs, _ = _gpu(s, r, b_max)
+    G = gram.cpu().numpy()
+    t = trace.cpu().numpy()
+    low = np.tril(np.ones((s.nz, s.nz), bool))
+    for q, pr in enumerate(r["pl"].pairs):
+        if not pr.n_rows:
+            continue
+        A = row_values(s, pr, r["tabs"].lookup)
+        ref = (A.conj().T @ aperture_rows(s, pr, A, Sm)).real
+        scale = np.max(np.abs(ref))
+        assert np.max(np.abs(G[q][low] - ref[low])) <= 1e-12 * scale, (name, q)
+        assert abs(t[q] - np.trace(ref)) <= 1e-12 * abs(np.trace(ref)), (name, q)
+    x, v, info, _ = p.solve(g64, d, gram, rhs, trace, s.lambda_rel, refine=False)
+    torch.cuda.synchronize()
+    Vo, _ = aperture_solve(s, r["pl"], r["data"], r["tabs"], b_max)
+    g, per = rel_errors(v.cpu().numpy(), Vo, r["pl"])
+    print(f"{name} b = {b_max:.0f} m ({int(w.sum())} of {s.n_mid} offsets): solve error {g:.2e} global, {per:.2e} per pair")
+    assert g <= 1e-10 and per <= 1e-10, (g, per)
+
+
+def test_window_holding_every_offset_is_the_plain_gram():
+    s = layered_small()
+    r = oracle_case(s)
+    _, _, _, gram, trace, gram_full, _, trace_full = _gpu(s, r, 1e6)
+    low = np.tril(np.ones((s.nz, s.nz), bool))
+    G, Gf = gram.cpu().numpy(), gram_full.cpu().numpy()
+    for q in range(G.shape[0]):
+        scale = max(np.max(np.abs(Gf[q][low])), 1e-300)
+        assert np.max(np.abs(G[q][low] - Gf[q][low])) <= 1e-12 * scale
+    assert np.allclose(trace.cpu().numpy(), trace_full.cpu().numpy(), rtol=1e-12, atol=0)
+
+
+def test_3d_surveys_are_refused():
+    s = make_custom(dim=3, N=12, Nh=6, nz=5, dx=25.0, freqs=(5.0,), vel=(2000.0,))
+    p = E.Plan(s)
+    g64 = torch.zeros(1, 1, 5, dtype=torch.complex128, device="cuda")
+    with pytest.raises(RuntimeError, match="2D line survey"):
+        p.aperture_gram(g64, 100.0)
