@@ -275,15 +275,19 @@ class Plan:
         _lib.check(_lib.load().edt_model(self._h, _ptr(w), _ptr(m), _stream()), "edt_model")
         return m
 
+    def aperture_work(self):
+        """A device workspace for aperture_gram (the rows of one frequency)."""
+        nb = C.c_size_t(0)
+        _lib.check(_lib.load().edt_aperture_work_bytes(self._h, C.byref(nb)), "edt_aperture_work_bytes")
+        return torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=self.device)
+
     def aperture_gram(self, g64, b_max, out=None, work=None):
         """Finite-aperture Grams (lower triangles) and traces of every pair for
         records kept at |x_R - x_S| <= 2 b_max: (gram[P, nz, nz], trace[P])."""
         self.upload()
         L = _lib.load()
         if work is None:
-            nb = C.c_size_t(0)
-            _lib.check(L.edt_aperture_work_bytes(self._h, C.byref(nb)), "edt_aperture_work_bytes")
-            work = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=self.device)
+            work = self.aperture_work()
         if out is None:
             gram = torch.empty(self.n_pairs, self.nz, self.nz, dtype=torch.float64, device=self.device)
             trace = torch.empty(self.n_pairs, dtype=torch.float64, device=self.device)

@@ -86,6 +86,33 @@ def test_window_holding_every_offset_is_the_plain_gram():
     assert np.allclose(trace.cpu().numpy(), trace_full.cpu().numpy(), rtol=1e-12, atol=0)
 
 
+def test_sampled_pairs_at_full_size():
+    """2D N = 512, nz = 256, 128 frequencies, the paper's aperture-to-line
+    ratio (b = 0.075 N dx): the Gram of 4 seeded pairs against the oracle."""
+    from oracle.rows import plan as oracle_plan
+    from oracle.solve import gtables
+    s = make_config(2)
+    pl = oracle_plan(s)
+    rng = np.random.default_rng(9)
+    nonempty = [i for i, q in enumerate(pl.pairs) if q.n_rows > 0]
+    pick = sorted(rng.choice(nonempty, size=4, replace=False).tolist())
+    sub = [pl.pairs[i] for i in pick]
+    tabs = gtables(s, pl, pairs=sub)
+    b_max = 0.075 * s.n_mid * s.d_mid
+    Sm = window_kernel(offset_window(s, b_max))
+    p = E.Plan(s)
+    vel = torch.tensor(np.asarray(s.vel, np.float64), device="cuda")
+    g64, _ = p.green(vel, want32=False)
+    gram, trace = p.aperture_gram(g64, b_max)
+    torch.cuda.synchronize()
+    low = np.tril(np.ones((s.nz, s.nz), bool))
+    for i, pr in zip(pick, sub):
+        A = row_values(s, pr, tabs.lookup)
+        ref = (A.conj().T @ aperture_rows(s, pr, A, Sm)).real
+        G = gram[i].cpu().numpy()
+        assert np.max(np.abs(G[low] - ref[low])) <= 1e-12 * np.max(np.abs(ref)), i
+
+
 def test_3d_surveys_are_refused():
     s = make_custom(dim=3, N=12, Nh=6, nz=5, dx=25.0, freqs=(5.0,), vel=(2000.0,))
     p = E.Plan(s)
