@@ -9,60 +9,104 @@
 //     Re(A^H S A) = (1/N) sum_{o in window} Re(Ah(o)^H Ah(o)),
 //     Ah(o, z) = sum_a A(a, z) e^{2 pi i a o / N},
 // with the rows of one frequency transformed over a.  Per frequency: the rows
-// of every pair are laid out densely over a (zero where a row is cut),
-// transformed by the line-transform kernel, and the kept offsets enter a
-// lower-tile FP64 MFMA product that accumulates over the frequencies.  Rows
-// of one frequency mix, so unique rows do not merge here.
+// of every pair are built over a in LDS straight from the Green's tables (zero
+// where a row is cut) and transformed there, only the kept offsets go to HBM,
+// and they enter a lower-tile FP64 MFMA product that accumulates over the
+// frequencies.  Rows of one frequency mix, so unique rows do not merge here.
 
 #include <cmath>
 
 #include "dev_common.h"
+#include "lines.h"
 
 namespace edt {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// R[p][a][z] = w_f0^2 dz g(z; k_r) g(z; k_s) for the rows of pair p at
-// frequency f0 (receiver index a), zero elsewhere.  Rows of a pair are
-// ordered by frequency, so those of f0 are one range, found by bisection.
-__global__ __launch_bounds__(256) void ap_rows_kernel(const zd* __restrict__ g64, const uint32_t* __restrict__ rows,
-                                                      const int32_t* __restrict__ keys,
-                                                      const int64_t* __restrict__ row_off, int f0, int n_cls, int N,
-                                                      int nz, zd scale, zd* __restrict__ R) {
+// For the rows of pair p at frequency f0, lines z0 .. z0 + L - 1 of
+//     Ah(o, z) = sum_a A(a, z) e^{2 pi i a o / N},  A(a, z) = w^2 dz g(z; k_r) g(z; k_s)
+// (A = 0 where no row has receiver index a), built in LDS straight from the
+// Green's tables and transformed there; only the nW kept offsets
+// o = (lo + k) mod N are stored: Rh[p][k][z].  Rows of a pair are ordered by
+// frequency, so those of f0 are one range, found by bisection.  A power-of-two
+// N takes the radix-2 transform, any other N a direct sum for the kept
+// offsets only.
+template <bool POW2>
+__global__ __launch_bounds__(256) void ap_rows_fft_kernel(const zd* __restrict__ g64,
+                                                          const uint32_t* __restrict__ rows,
+                                                          const int32_t* __restrict__ keys,
+                                                          const int64_t* __restrict__ row_off, int f0, int n_cls,
+                                                          int N, int logn, int nz, int L, zd scale, int lo, int nW,
+                                                          zd* __restrict__ Rh) {
+    extern __shared__ zd s_mem[];
+    zd* s_x = s_mem;           // L lines of N values
+    zd* s_w = s_mem + L * N;   // twiddles e^{2 pi i k / N}: N / 2 (radix 2) or N (direct)
     __shared__ int64_t s_range[2];
-    const int p = blockIdx.x, tid = threadIdx.x;
-    zd* Rp = R + size_t(p) * N * nz;
-    for (int64_t e = tid; e < int64_t(N) * nz; e += 256) Rp[e] = zd{0.0, 0.0};
+    const int tid = threadIdx.x;
+    const int per_pair = nz / L;
+    const int p = int(blockIdx.x / unsigned(per_pair)), z0 = int(blockIdx.x % unsigned(per_pair)) * L;
+    const int nw = POW2 ? N / 2 : N;
+    for (int k = tid; k < nw; k += 256) {
+        double sv, cv;
+        sincospi(2.0 * double(k) / double(N), &sv, &cv);
+        s_w[k] = zd{cv, sv};
+    }
+    for (int e = tid; e < L * N; e += 256) s_x[e] = zd{0.0, 0.0};
     if (tid < 2) {
         // first row with frequency >= f0 + tid
-        int64_t lo = row_off[p], hi = row_off[p + 1];
+        int64_t a = row_off[p], b = row_off[p + 1];
         const uint32_t key = uint32_t(f0 + tid);
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) / 2;
-            if (rows[2 * mid] < key) lo = mid + 1;
-            else hi = mid;
+        while (a < b) {
+            const int64_t mid = (a + b) / 2;
+            if (rows[2 * mid] < key) a = mid + 1;
+            else b = mid;
         }
-        s_range[tid] = lo;
+        s_range[tid] = a;
     }
     __syncthreads();
     const int64_t r0 = s_range[0], n = s_range[1] - s_range[0];
     const zd* gf = g64 + size_t(f0) * n_cls * nz;
-    for (int64_t e = tid; e < n * nz; e += 256) {
-        const int64_t r = r0 + e / nz;
-        const int z = int(e % nz);
+    for (int64_t e = tid; e < n * L; e += 256) {
+        const int64_t r = r0 + e / L;
+        const int j = int(e % L), z = z0 + j;
         const uint32_t c = rows[2 * r + 1];
         const int a = keys[2 * r];
         const zd gr = gf[size_t(c & 0xFFFFu) * nz + z], gs = gf[size_t(c >> 16) * nz + z];
-        Rp[size_t(a) * nz + z] = scale * (gr * gs);
+        s_x[j * N + (POW2 ? bit_reverse(a, logn) : a)] = scale * (gr * gs);
+    }
+    __syncthreads();
+    zd* Rp = Rh + size_t(p) * nW * nz;
+    if constexpr (POW2) {
+        dit_lines(s_x, s_w, N, logn, L);
+        for (int e = tid; e < L * nW; e += 256) {
+            const int j = e % L, k = e / L;
+            int o = (lo + k) % N;
+            if (o < 0) o += N;
+            Rp[size_t(k) * nz + z0 + j] = s_x[j * N + o];
+        }
+    } else {
+        for (int e = tid; e < L * nW; e += 256) {
+            const int j = e % L, k = e / L;
+            int o = (lo + k) % N;
+            if (o < 0) o += N;
+            zd acc{0.0, 0.0};
+            int m = 0;   // (a o) mod N
+            for (int a = 0; a < N; ++a) {
+                acc = acc + s_w[m] * s_x[j * N + a];
+                m += o;
+                if (m >= N) m -= N;
+            }
+            Rp[size_t(k) * nz + z0 + j] = acc;
+        }
     }
 }
 
 // C (lower tiles, += or =) of (1/N) sum over kept offsets of Re(Ah^H Ah): a
 // real product over K = 2 nW (real and imaginary parts of the nW kept
-// offsets o = (lo + k) mod N).  Tiles dealt to the XCDs pair by pair; K in
+// offsets, stored compactly).  Tiles dealt to the XCDs pair by pair; K in
 // chunks of 32 staged in LDS, the next chunk's loads in flight.
-__global__ __launch_bounds__(256, 4) void ap_gram_kernel(const zd* __restrict__ Rh, int N, int nz, int nt, int lo,
-                                                         int nW, double invN, int first, double* __restrict__ gram,
+__global__ __launch_bounds__(256, 4) void ap_gram_kernel(const zd* __restrict__ Rh, int nz, int nt, int nW,
+                                                         double invN, int first, double* __restrict__ gram,
                                                          int n_pairs) {
     __shared__ double As[64][33];
     __shared__ double Bs[32][65];
@@ -75,7 +119,7 @@ __global__ __launch_bounds__(256, 4) void ap_gram_kernel(const zd* __restrict__ 
     const int tj = tile - ti * (ti + 1) / 2;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int r0 = 64 * ti, c0 = 64 * tj;
-    const zd* Rp = Rh + size_t(p) * N * nz;
+    const zd* Rp = Rh + size_t(p) * nW * nz;
     const int K = 2 * nW;
     const int li = lane & 15, lk = lane >> 4;
     const int wr = 32 * (wv >> 1), wc = 32 * (wv & 1);
@@ -87,14 +131,12 @@ __global__ __launch_bounds__(256, 4) void ap_gram_kernel(const zd* __restrict__ 
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[a][b][v] = 0.0;
     double ra[8], rb[8];
-    // element kk of K: offset (lo + kk / 2) mod N, real (kk even) or
-    // imaginary part; A(i, kk) = part of Ah[o][r0 + i], B(kk, j) = part of
-    // Ah[o][c0 + j]; threads run along z, so loads are contiguous
+    // element kk of K: kept offset kk / 2, real (kk even) or imaginary part;
+    // A(i, kk) = part of Ah[kk / 2][r0 + i], B(kk, j) = part of
+    // Ah[kk / 2][c0 + j]; threads run along z, so loads are contiguous
     auto value = [&](int kk, int z) {
         if (kk >= K || z >= nz) return 0.0;
-        int o = (lo + kk / 2) % N;
-        if (o < 0) o += N;
-        const zd v = Rp[size_t(o) * nz + z];
+        const zd v = Rp[size_t(kk / 2) * nz + z];
         return (kk & 1) ? v.y : v.x;
     };
     auto fetch = [&](int k0) {
@@ -174,6 +216,15 @@ void aperture_offsets(const edt_plan* p, double b_max, int* lo, int* nW) {
     *nW = count;
 }
 
+hipError_t configure_aperture() {
+    for (const void* k : {reinterpret_cast<const void*>(ap_rows_fft_kernel<true>),
+                          reinterpret_cast<const void*>(ap_rows_fft_kernel<false>)}) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_aperture_gram(const edt_plan* p, const zd* g64, double b_max, double* gram, double* trace,
                                 zd* R, hipStream_t st) {
     if (p->n_pairs == 0) return hipSuccess;
@@ -181,19 +232,36 @@ hipError_t launch_aperture_gram(const edt_plan* p, const zd* g64, double b_max, 
     const int P = int(p->n_pairs);
     int lo = 0, nW = 0;
     aperture_offsets(p, b_max, &lo, &nW);
+    const bool p2 = (N & (N - 1)) == 0;
+    const int nw = p2 ? N / 2 : N;
+    int logn = 0;
+    while ((1 << logn) < N) ++logn;
+    // lines per block: 4 adjacent depths when they fit (contiguous loads)
+    int L = 1;
+    for (int c : {4, 2})
+        if (nz % c == 0 && size_t(c * N + nw) * sizeof(zd) <= 64 * 1024) {
+            L = c;
+            break;
+        }
+    const size_t lds = size_t(L * N + nw) * sizeof(zd);
+    if (lds > 64 * 1024) return hipErrorInvalidValue;
+    const unsigned blocks = unsigned(P * (nz / L));
     for (int f = 0; f < p->n_freq; ++f) {
         // w^2 dz with w = 2 pi f + i eps
         const double wr = kTwoPiD * p->freq[size_t(f)], wi = p->eps;
         const zd scale{p->dz * (wr * wr - wi * wi), p->dz * (2.0 * wr * wi)};
-        hipLaunchKernelGGL(ap_rows_kernel, dim3(unsigned(P)), dim3(256), 0, st, g64,
-                           dptr<const uint32_t>(p, p->lay.rows), dptr<const int32_t>(p, p->lay.keys),
-                           dptr<const int64_t>(p, p->lay.row_off), f, p->n_cls, N, nz, scale, R);
+        if (p2)
+            hipLaunchKernelGGL(ap_rows_fft_kernel<true>, dim3(blocks), dim3(256), lds, st, g64,
+                               dptr<const uint32_t>(p, p->lay.rows), dptr<const int32_t>(p, p->lay.keys),
+                               dptr<const int64_t>(p, p->lay.row_off), f, p->n_cls, N, logn, nz, L, scale, lo, nW, R);
+        else
+            hipLaunchKernelGGL(ap_rows_fft_kernel<false>, dim3(blocks), dim3(256), lds, st, g64,
+                               dptr<const uint32_t>(p, p->lay.rows), dptr<const int32_t>(p, p->lay.keys),
+                               dptr<const int64_t>(p, p->lay.row_off), f, p->n_cls, N, logn, nz, L, scale, lo, nW, R);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        e = launch_lines(R, N, P, Lines{int64_t(N) * nz, 1, nz, nz}, 1.0, 1.0, st);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(ap_gram_kernel, dim3(xcd_pair_grid(P, nt * (nt + 1) / 2)), dim3(256), 0, st, R, N, nz,
-                           nt, lo, nW, 1.0 / double(N), f == 0 ? 1 : 0, gram, P);
+        hipLaunchKernelGGL(ap_gram_kernel, dim3(xcd_pair_grid(P, nt * (nt + 1) / 2)), dim3(256), 0, st, R, nz, nt, nW,
+                           1.0 / double(N), f == 0 ? 1 : 0, gram, P);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -423,6 +423,7 @@ size_t adjoint_lds_bytes(int nz) { return trisolve_lds_doubles(nz) * sizeof(doub
 hipError_t configure_adjoint_kernels(int bytes);
 hipError_t configure_gram_kernels();
 hipError_t configure_lines();
+hipError_t configure_aperture();
 // The largest dynamic LDS any supported depth count needs.
 static int max_dynamic_lds() {
     const size_t a = chol_lds_bytes(kMaxDepth), b = adjoint_lds_bytes(kMaxAdjointDepth);
@@ -441,6 +442,7 @@ hipError_t configure_kernels() {
     if (e == hipSuccess) e = configure_adjoint_kernels(bytes);
     if (e == hipSuccess) e = configure_gram_kernels();
     if (e == hipSuccess) e = configure_lines();
+    if (e == hipSuccess) e = configure_aperture();
     return e;
 }
 

@@ -13,41 +13,11 @@
 // loaded several at a time so that each load covers contiguous memory.
 
 #include "dev_common.h"
+#include "lines.h"
 
 namespace edt {
 
 constexpr size_t kLineLds = 64 * 1024;   // LDS of one block, values and twiddles
-
-// R consecutive radix-2 levels of decimation in time (spans h, 2h, ..., R h / 2)
-// in registers: a thread takes the R elements b0 + t h of one group, so a
-// length 2^m takes ceil(m / 3) passes over LDS instead of m.  At the level of
-// span H = lv h (blocks of M = 2H) element i pairs with i + H under the
-// twiddle W_M^(i mod H), and i mod H = pos + (t mod lv) h.
-template <int R>
-__device__ __forceinline__ void dit_levels(zd* s_x, const zd* s_w, int n, int h, int L) {
-    const int groups = n / R;
-    for (int g = threadIdx.x; g < L * groups; g += 256) {
-        const int j = g / groups, gg = g - j * groups;
-        const int pos = gg & (h - 1), blk = gg / h;
-        const int b0 = j * n + blk * R * h + pos;
-        zd x[R];
-#pragma unroll
-        for (int t = 0; t < R; ++t) x[t] = s_x[b0 + t * h];
-#pragma unroll
-        for (int lv = 1; lv < R; lv <<= 1) {
-            const int tstep = n / (2 * lv * h);
-#pragma unroll
-            for (int t = 0; t < R; ++t) {
-                if (t & lv) continue;
-                const zd u = s_w[(pos + (t & (lv - 1)) * h) * tstep] * x[t + lv];
-                x[t + lv] = x[t] - u;
-                x[t] = x[t] + u;
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < R; ++t) s_x[b0 + t * h] = x[t];
-    }
-}
 
 template <bool POW2>
 __global__ __launch_bounds__(256) void dft_lines_kernel(zd* __restrict__ data, int n, int logn, Lines g, int L,
@@ -71,28 +41,12 @@ __global__ __launch_bounds__(256) void dft_lines_kernel(zd* __restrict__ data, i
         const int j = line_of(e), i = elem_of(e);
         const zd v = data[base0 + int64_t(j) * g.step + int64_t(i) * g.stride];
         int at = i;
-        if constexpr (POW2) at = logn ? int(__brev(unsigned(i)) >> (32 - logn)) : 0;
+        if constexpr (POW2) at = bit_reverse(i, logn);
         s_x[j * n + at] = v;
     }
     __syncthreads();
     if constexpr (POW2) {
-        int h = 1;
-        for (int rem = logn; rem > 0;) {
-            if (rem >= 3) {
-                dit_levels<8>(s_x, s_w, n, h, L);
-                h *= 8;
-                rem -= 3;
-            } else if (rem == 2) {
-                dit_levels<4>(s_x, s_w, n, h, L);
-                h *= 4;
-                rem -= 2;
-            } else {
-                dit_levels<2>(s_x, s_w, n, h, L);
-                h *= 2;
-                rem -= 1;
-            }
-            __syncthreads();
-        }
+        dit_lines(s_x, s_w, n, logn, L);
         for (int e = tid; e < L * n; e += 256) {
             const int j = line_of(e), i = elem_of(e);
             data[base0 + int64_t(j) * g.step + int64_t(i) * g.stride] = scale * s_x[j * n + i];
