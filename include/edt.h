@@ -385,7 +385,8 @@ edt_status edt_shots_pack(const edt_plan* plan, const edt_c128* spectrum, edt_c1
  * gram: device [P][nz][nz], lower triangle written (FP64); trace: device [P],
  * its trace.  Solve with edt_solve without refinement (the refinement works
  * from the unwindowed rows) or edt_tsvd.  aperture_work: device, >=
- * edt_aperture_work_bytes (P n_mid nz complex128: the rows of one frequency).
+ * edt_aperture_work_bytes (about P n_mid nz complex128: the transformed rows
+ * of one frequency, plus per-pair frequency ranges and a twiddle table).
  * Errors: EDT_EINVAL for dim 3, n_mid > 2048, b_max negative or not finite,
  * or a null pointer (a plan with no pairs returns EDT_OK at once).
  */

@@ -35,36 +35,21 @@ template <bool POW2>
 __global__ __launch_bounds__(256) void ap_rows_fft_kernel(const zd* __restrict__ g64,
                                                           const uint32_t* __restrict__ rows,
                                                           const int32_t* __restrict__ keys,
-                                                          const int64_t* __restrict__ row_off, int f0, int n_cls,
-                                                          int N, int logn, int nz, int L, zd scale, int lo, int nW,
-                                                          zd* __restrict__ Rh) {
+                                                          const int64_t* __restrict__ franges, int f0, int n_freq,
+                                                          int n_cls, int N, int logn, int nz, int L, zd scale, int lo,
+                                                          int nW, const zd* __restrict__ tw, zd* __restrict__ Rh) {
     extern __shared__ zd s_mem[];
     zd* s_x = s_mem;           // L lines of N values
     zd* s_w = s_mem + L * N;   // twiddles e^{2 pi i k / N}: N / 2 (radix 2) or N (direct)
-    __shared__ int64_t s_range[2];
     const int tid = threadIdx.x;
     const int per_pair = nz / L;
     const int p = int(blockIdx.x / unsigned(per_pair)), z0 = int(blockIdx.x % unsigned(per_pair)) * L;
     const int nw = POW2 ? N / 2 : N;
-    for (int k = tid; k < nw; k += 256) {
-        double sv, cv;
-        sincospi(2.0 * double(k) / double(N), &sv, &cv);
-        s_w[k] = zd{cv, sv};
-    }
+    for (int k = tid; k < nw; k += 256) s_w[k] = tw[k];
     for (int e = tid; e < L * N; e += 256) s_x[e] = zd{0.0, 0.0};
-    if (tid < 2) {
-        // first row with frequency >= f0 + tid
-        int64_t a = row_off[p], b = row_off[p + 1];
-        const uint32_t key = uint32_t(f0 + tid);
-        while (a < b) {
-            const int64_t mid = (a + b) / 2;
-            if (rows[2 * mid] < key) a = mid + 1;
-            else b = mid;
-        }
-        s_range[tid] = a;
-    }
+    const int64_t r0 = franges[size_t(p) * (n_freq + 1) + f0];
+    const int64_t n = franges[size_t(p) * (n_freq + 1) + f0 + 1] - r0;
     __syncthreads();
-    const int64_t r0 = s_range[0], n = s_range[1] - s_range[0];
     const zd* gf = g64 + size_t(f0) * n_cls * nz;
     for (int64_t e = tid; e < n * L; e += 256) {
         const int64_t r = r0 + e / L;
@@ -185,6 +170,32 @@ __global__ __launch_bounds__(256, 4) void ap_gram_kernel(const zd* __restrict__ 
             }
 }
 
+// Per pair: the first row of each frequency (rows of a pair are ordered by
+// frequency), franges[p][f] for f = 0 .. n_freq, by bisection.
+__global__ __launch_bounds__(256) void ap_ranges_kernel(const uint32_t* __restrict__ rows,
+                                                        const int64_t* __restrict__ row_off, int n_freq,
+                                                        int64_t* __restrict__ franges) {
+    const int p = blockIdx.x;
+    for (int f = threadIdx.x; f <= n_freq; f += 256) {
+        int64_t a = row_off[p], b = row_off[p + 1];
+        while (a < b) {
+            const int64_t mid = (a + b) / 2;
+            if (rows[2 * mid] < uint32_t(f)) a = mid + 1;
+            else b = mid;
+        }
+        franges[size_t(p) * (n_freq + 1) + f] = a;
+    }
+}
+
+// tw[k] = e^{2 pi i k / N}, k < n.
+__global__ __launch_bounds__(256) void ap_twiddle_kernel(int N, int n, zd* __restrict__ tw) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    double sv, cv;
+    sincospi(2.0 * double(k) / double(N), &sv, &cv);
+    tw[k] = zd{cv, sv};
+}
+
 // trace[p] = sum of the diagonal (fixed order).
 __global__ __launch_bounds__(256) void ap_trace_kernel(const double* __restrict__ gram, int nz,
                                                        double* __restrict__ trace) {
@@ -199,7 +210,21 @@ __global__ __launch_bounds__(256) void ap_trace_kernel(const double* __restrict_
 }
 
 // ------------------------------------------------------------- launcher ---
-size_t aperture_work_bytes(const edt_plan* p) { return size_t(p->n_pairs) * p->n_mid * p->nz * sizeof(zd); }
+// Workspace: the kept offsets of one frequency (at most P N nz complex128),
+// the per-pair frequency ranges and the twiddle table.
+struct ApLayout {
+    size_t rh, ranges, tw, total;
+};
+ApLayout aperture_layout(const edt_plan* p) {
+    ApLayout l{};
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    l.rh = 0;
+    l.ranges = up(size_t(p->n_pairs) * p->n_mid * p->nz * sizeof(zd));
+    l.tw = l.ranges + up(size_t(p->n_pairs) * (p->n_freq + 1) * sizeof(int64_t));
+    l.total = l.tw + up(size_t(p->n_mid) * sizeof(zd));
+    return l;
+}
+size_t aperture_work_bytes(const edt_plan* p) { return aperture_layout(p).total; }
 
 // Kept signed offsets: |s| d_mid <= 2 b_max for s in [-N/2, (N - 1)/2]
 // (the same comparison as the oracle's); a contiguous range [lo, lo + nW).
@@ -226,8 +251,12 @@ hipError_t configure_aperture() {
 }
 
 hipError_t launch_aperture_gram(const edt_plan* p, const zd* g64, double b_max, double* gram, double* trace,
-                                zd* R, hipStream_t st) {
+                                unsigned char* work, hipStream_t st) {
     if (p->n_pairs == 0) return hipSuccess;
+    const ApLayout wl = aperture_layout(p);
+    zd* R = reinterpret_cast<zd*>(work + wl.rh);
+    int64_t* franges = reinterpret_cast<int64_t*>(work + wl.ranges);
+    zd* tw = reinterpret_cast<zd*>(work + wl.tw);
     const int N = p->n_mid, nz = p->nz, nt = (nz + 63) / 64;
     const int P = int(p->n_pairs);
     int lo = 0, nW = 0;
@@ -246,6 +275,9 @@ hipError_t launch_aperture_gram(const edt_plan* p, const zd* g64, double b_max, 
     const size_t lds = size_t(L * N + nw) * sizeof(zd);
     if (lds > 64 * 1024) return hipErrorInvalidValue;
     const unsigned blocks = unsigned(P * (nz / L));
+    hipLaunchKernelGGL(ap_ranges_kernel, dim3(unsigned(P)), dim3(256), 0, st, dptr<const uint32_t>(p, p->lay.rows),
+                       dptr<const int64_t>(p, p->lay.row_off), p->n_freq, franges);
+    hipLaunchKernelGGL(ap_twiddle_kernel, dim3(unsigned((nw + 255) / 256)), dim3(256), 0, st, N, nw, tw);
     for (int f = 0; f < p->n_freq; ++f) {
         // w^2 dz with w = 2 pi f + i eps
         const double wr = kTwoPiD * p->freq[size_t(f)], wi = p->eps;
@@ -253,11 +285,11 @@ hipError_t launch_aperture_gram(const edt_plan* p, const zd* g64, double b_max, 
         if (p2)
             hipLaunchKernelGGL(ap_rows_fft_kernel<true>, dim3(blocks), dim3(256), lds, st, g64,
                                dptr<const uint32_t>(p, p->lay.rows), dptr<const int32_t>(p, p->lay.keys),
-                               dptr<const int64_t>(p, p->lay.row_off), f, p->n_cls, N, logn, nz, L, scale, lo, nW, R);
+                               franges, f, p->n_freq, p->n_cls, N, logn, nz, L, scale, lo, nW, tw, R);
         else
             hipLaunchKernelGGL(ap_rows_fft_kernel<false>, dim3(blocks), dim3(256), lds, st, g64,
                                dptr<const uint32_t>(p, p->lay.rows), dptr<const int32_t>(p, p->lay.keys),
-                               dptr<const int64_t>(p, p->lay.row_off), f, p->n_cls, N, logn, nz, L, scale, lo, nW, R);
+                               franges, f, p->n_freq, p->n_cls, N, logn, nz, L, scale, lo, nW, tw, R);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(ap_gram_kernel, dim3(xcd_pair_grid(P, nt * (nt + 1) / 2)), dim3(256), 0, st, R, nz, nt, nW,

@@ -51,7 +51,7 @@ hipError_t launch_shots_pack(const edt_plan* p, const zd* F, zd* d_rows, hipStre
 hipError_t launch_model(const edt_plan* p, zd* v, double* model, hipStream_t st);
 size_t aperture_work_bytes(const edt_plan* p);
 hipError_t launch_aperture_gram(const edt_plan* p, const zd* g64, double b_max, double* gram, double* trace,
-                                zd* R, hipStream_t st);
+                                unsigned char* work, hipStream_t st);
 hipError_t launch_kz_restrict(const edt_plan* p, double K, double* gram, double* rhs, unsigned char* tw,
                               int32_t* n_keep, hipStream_t st);
 size_t chol_lds_bytes(int nz);
@@ -450,7 +450,7 @@ edt_status edt_aperture_gram(const edt_plan* p, const edt_c128* g64, double b_ma
         return EDT_EINVAL;
     }
     EDT_TRY(launch_aperture_gram(p, reinterpret_cast<const zd*>(g64), b_max, gram, trace,
-                                 static_cast<zd*>(aperture_work), stream),
+                                 static_cast<unsigned char*>(aperture_work), stream),
             "aperture gram");
     return EDT_OK;
 }
