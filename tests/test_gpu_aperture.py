@@ -119,3 +119,14 @@ def test_3d_surveys_are_refused():
     g64 = torch.zeros(1, 1, 5, dtype=torch.complex128, device="cuda")
     with pytest.raises(RuntimeError, match="2D line survey"):
         p.aperture_gram(g64, 100.0)
+
+
+def test_bad_half_aperture_is_refused():
+    s = layered_small()
+    p = E.Plan(s)
+    vel = torch.tensor(np.asarray(s.vel, np.float64), device="cuda")
+    g64, _ = p.green(vel, want32=False)
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(RuntimeError, match="b_max"):
+            p.aperture_gram(g64, bad)
+

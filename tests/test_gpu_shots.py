@@ -124,3 +124,15 @@ def test_shot_records_of_3d_surveys_are_refused():
     sh = torch.zeros(1, 12, 12, dtype=torch.complex128, device="cuda")
     with pytest.raises(RuntimeError, match="2D line survey"):
         p.shots_fft(sh)
+
+
+def test_transforms_longer_than_2048_are_refused():
+    s = make_custom(N=2050, nz=2, dx=5.0, freqs=(5.0,), vel=(2000.0,), model="zero")
+    p = E.Plan(s)
+    sh = torch.zeros(1, 1, 1, dtype=torch.complex128, device="cuda")
+    with pytest.raises(RuntimeError, match="n_mid > 2048"):
+        p.shots_fft(sh)
+    v = torch.zeros(p.n_km, s.nz, dtype=torch.complex128, device="cuda")
+    with pytest.raises(RuntimeError, match="n_mid > 2048"):
+        p.model(v)
+
