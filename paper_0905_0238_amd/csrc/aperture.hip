@@ -23,6 +23,8 @@ namespace edt {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+constexpr int kApLds = 80 * 1024;   // LDS of one row-transform block (gfx950: 160 KiB per CU)
+
 // For the rows of pair p at frequency f0, lines z0 .. z0 + L - 1 of
 //     Ah(o, z) = sum_a A(a, z) e^{2 pi i a o / N},  A(a, z) = w^2 dz g(z; k_r) g(z; k_s)
 // (A = 0 where no row has receiver index a), built in LDS straight from the
@@ -39,14 +41,15 @@ __global__ __launch_bounds__(256) void ap_rows_fft_kernel(const zd* __restrict__
                                                           int n_cls, int N, int logn, int nz, int L, zd scale, int lo,
                                                           int nW, const zd* __restrict__ tw, zd* __restrict__ Rh) {
     extern __shared__ zd s_mem[];
-    zd* s_x = s_mem;           // L lines of N values
-    zd* s_w = s_mem + L * N;   // twiddles e^{2 pi i k / N}: N / 2 (radix 2) or N (direct)
+    const int ns = lds_stride(N);
+    zd* s_x = s_mem;            // L lines of N values (padded layout)
+    zd* s_w = s_mem + L * ns;   // twiddles e^{2 pi i k / N}: N / 2 (radix 2) or N (direct)
     const int tid = threadIdx.x;
     const int per_pair = nz / L;
     const int p = int(blockIdx.x / unsigned(per_pair)), z0 = int(blockIdx.x % unsigned(per_pair)) * L;
     const int nw = POW2 ? N / 2 : N;
     for (int k = tid; k < nw; k += 256) s_w[k] = tw[k];
-    for (int e = tid; e < L * N; e += 256) s_x[e] = zd{0.0, 0.0};
+    for (int e = tid; e < L * ns; e += 256) s_x[e] = zd{0.0, 0.0};
     const int64_t r0 = franges[size_t(p) * (n_freq + 1) + f0];
     const int64_t n = franges[size_t(p) * (n_freq + 1) + f0 + 1] - r0;
     __syncthreads();
@@ -57,7 +60,7 @@ __global__ __launch_bounds__(256) void ap_rows_fft_kernel(const zd* __restrict__
         const uint32_t c = rows[2 * r + 1];
         const int a = keys[2 * r];
         const zd gr = gf[size_t(c & 0xFFFFu) * nz + z], gs = gf[size_t(c >> 16) * nz + z];
-        s_x[j * N + (POW2 ? bit_reverse(a, logn) : a)] = scale * (gr * gs);
+        s_x[j * ns + lds_pad(POW2 ? bit_reverse(a, logn) : a)] = scale * (gr * gs);
     }
     __syncthreads();
     zd* Rp = Rh + size_t(p) * nW * nz;
@@ -67,7 +70,7 @@ __global__ __launch_bounds__(256) void ap_rows_fft_kernel(const zd* __restrict__
             const int j = e % L, k = e / L;
             int o = (lo + k) % N;
             if (o < 0) o += N;
-            Rp[size_t(k) * nz + z0 + j] = s_x[j * N + o];
+            Rp[size_t(k) * nz + z0 + j] = s_x[j * ns + lds_pad(o)];
         }
     } else {
         for (int e = tid; e < L * nW; e += 256) {
@@ -77,7 +80,7 @@ __global__ __launch_bounds__(256) void ap_rows_fft_kernel(const zd* __restrict__
             zd acc{0.0, 0.0};
             int m = 0;   // (a o) mod N
             for (int a = 0; a < N; ++a) {
-                acc = acc + s_w[m] * s_x[j * N + a];
+                acc = acc + s_w[m] * s_x[j * ns + lds_pad(a)];
                 m += o;
                 if (m >= N) m -= N;
             }
@@ -244,7 +247,7 @@ void aperture_offsets(const edt_plan* p, double b_max, int* lo, int* nW) {
 hipError_t configure_aperture() {
     for (const void* k : {reinterpret_cast<const void*>(ap_rows_fft_kernel<true>),
                           reinterpret_cast<const void*>(ap_rows_fft_kernel<false>)}) {
-        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kApLds);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -268,12 +271,12 @@ hipError_t launch_aperture_gram(const edt_plan* p, const zd* g64, double b_max, 
     // lines per block: 4 adjacent depths when they fit (contiguous loads)
     int L = 1;
     for (int c : {4, 2})
-        if (nz % c == 0 && size_t(c * N + nw) * sizeof(zd) <= 64 * 1024) {
+        if (nz % c == 0 && size_t(c * lds_stride(N) + nw) * sizeof(zd) <= kApLds) {
             L = c;
             break;
         }
-    const size_t lds = size_t(L * N + nw) * sizeof(zd);
-    if (lds > 64 * 1024) return hipErrorInvalidValue;
+    const size_t lds = size_t(L * lds_stride(N) + nw) * sizeof(zd);
+    if (lds > kApLds) return hipErrorInvalidValue;
     const unsigned blocks = unsigned(P * (nz / L));
     hipLaunchKernelGGL(ap_ranges_kernel, dim3(unsigned(P)), dim3(256), 0, st, dptr<const uint32_t>(p, p->lay.rows),
                        dptr<const int64_t>(p, p->lay.row_off), p->n_freq, franges);

@@ -17,14 +17,15 @@
 
 namespace edt {
 
-constexpr size_t kLineLds = 64 * 1024;   // LDS of one block, values and twiddles
+constexpr size_t kLineLds = 80 * 1024;   // LDS of one block, values and twiddles (gfx950: 160 KiB per CU)
 
 template <bool POW2>
 __global__ __launch_bounds__(256) void dft_lines_kernel(zd* __restrict__ data, int n, int logn, Lines g, int L,
                                                         double sign, double scale) {
     extern __shared__ zd s_mem[];
-    zd* s_x = s_mem;           // L lines of n values
-    zd* s_w = s_mem + L * n;   // twiddles: n / 2 (radix 2) or n (direct)
+    const int ns = lds_stride(n);
+    zd* s_x = s_mem;            // L lines of n values (padded layout)
+    zd* s_w = s_mem + L * ns;   // twiddles: n / 2 (radix 2) or n (direct)
     const int tid = threadIdx.x;
     const int64_t l0 = int64_t(blockIdx.x) * L;
     const int64_t base0 = (l0 / g.per_slab) * g.slab + (l0 % g.per_slab) * g.step;
@@ -42,14 +43,14 @@ __global__ __launch_bounds__(256) void dft_lines_kernel(zd* __restrict__ data, i
         const zd v = data[base0 + int64_t(j) * g.step + int64_t(i) * g.stride];
         int at = i;
         if constexpr (POW2) at = bit_reverse(i, logn);
-        s_x[j * n + at] = v;
+        s_x[j * ns + lds_pad(at)] = v;
     }
     __syncthreads();
     if constexpr (POW2) {
         dit_lines(s_x, s_w, n, logn, L);
         for (int e = tid; e < L * n; e += 256) {
             const int j = line_of(e), i = elem_of(e);
-            data[base0 + int64_t(j) * g.step + int64_t(i) * g.stride] = scale * s_x[j * n + i];
+            data[base0 + int64_t(j) * g.step + int64_t(i) * g.stride] = scale * s_x[j * ns + lds_pad(i)];
         }
     } else {
         // every line is in LDS before the first store
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(256) void dft_lines_kernel(zd* __restrict__ data, i
             zd acc{0.0, 0.0};
             int m = 0;   // (k i) mod n
             for (int i = 0; i < n; ++i) {
-                acc = acc + s_w[m] * s_x[j * n + i];
+                acc = acc + s_w[m] * s_x[j * ns + lds_pad(i)];
                 m += k;
                 if (m >= n) m -= n;
             }
@@ -101,12 +102,12 @@ hipError_t launch_lines(zd* data, int n, int64_t n_slabs, Lines g, double sign, 
     // LDS footprint halves the blocks per CU)
     int L = 1;
     for (int c : {4, 2}) {
-        if (g.per_slab % c == 0 && size_t(c * n + nw) * sizeof(zd) <= kLineLds) {
+        if (g.per_slab % c == 0 && size_t(c * lds_stride(n) + nw) * sizeof(zd) <= kLineLds) {
             L = c;
             break;
         }
     }
-    const size_t lds = size_t(L * n + nw) * sizeof(zd);
+    const size_t lds = size_t(L * lds_stride(n) + nw) * sizeof(zd);
     if (lds > kLineLds) return hipErrorInvalidValue;
     int logn = 0;
     while ((1 << logn) < n) ++logn;
