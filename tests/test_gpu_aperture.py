@@ -74,6 +74,58 @@ def test_aperture_gram_and_solve(name, frac):
     assert g <= 1e-10 and per <= 1e-10, (g, per)
 
 
+@pytest.mark.parametrize("tol", [1e-2, 1e-3])
+def test_truncated_svd_on_the_aperture_gram(tol):
+    """The paper's own configuration: finite aperture and the truncated SVD
+    (edt_aperture_gram -> edt_tsvd) against the oracle's eigen-decomposition
+    of its windowed Gram, with the conditioning-derived bar of the plain
+    truncated-SVD test (pairs within a relative 1e-6 of the threshold left
+    out and counted)."""
+    from oracle.solve import normal_equations
+    from oracle.tsvd import tsvd_gram
+    s = layered_small()
+    r = oracle_case(s)
+    b_max = 0.3 * s.n_mid * s.d_mid / 2
+    Sm = window_kernel(offset_window(s, b_max))
+    p, g64, d, gram, trace, _, rhs, _ = _gpu(s, r, b_max)
+    _, v, info, _ = p.tsvd(gram, rhs, tol, max_iter=150)
+    torch.cuda.synchronize()
+    v = v.cpu().numpy()
+    u = np.finfo(np.float64).eps / 2
+    Vo = np.zeros_like(v)
+    checks = []
+    for pr, (d0, d1) in zip(r["pl"].pairs, r["data"]):
+        if not pr.n_rows:
+            continue
+        A = row_values(s, pr, r["tabs"].lookup)
+        Gw = (A.conj().T @ aperture_rows(s, pr, A, Sm)).real
+        _, c, _ = normal_equations(A, d0, d1)
+        x, w, t2 = tsvd_gram(Gw, c, tol)
+        if pr.self_conjugate:
+            x[1] = 0.0
+        Vo[pr.u] = x[0] + 1j * x[1]
+        if not pr.self_conjugate:
+            Vo[pr.u_neg] = x[0] - 1j * x[1]
+        checks.append((pr, w, t2))
+    nv = np.linalg.norm(Vo)
+    checked = ambiguous = 0
+    worst = 0.0
+    for pr, w, t2 in checks:
+        gap = np.min(np.abs(w - t2))
+        if gap <= 1e-6 * t2:
+            ambiguous += 1
+            continue
+        kept = w[w >= t2]
+        bar = max(1e-10, 100 * u * (w.max() / kept.min() + w.max() / gap))
+        idx = [pr.u] if pr.u == pr.u_neg else [pr.u, pr.u_neg]
+        err = np.linalg.norm(v[idx] - Vo[idx]) / max(np.linalg.norm(Vo[idx]), 1e-3 * nv)
+        assert err <= bar, (pr.u, err, bar)
+        checked += 1
+        worst = max(worst, err)
+    assert checked >= 0.9 * (checked + ambiguous) and checked > 0
+    print(f"aperture + truncated SVD tol {tol}: {checked} pairs, {ambiguous} ambiguous, worst {worst:.2e}")
+
+
 def test_window_holding_every_offset_is_the_plain_gram():
     s = layered_small()
     r = oracle_case(s)
