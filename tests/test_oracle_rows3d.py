@@ -2,11 +2,18 @@
 the paper calls ideal, with the midpoint-wavenumber decoupling of eq. DMV).
 
 In units of dk/2 a row of k_m index q_u and k_h index n has k_r = q_u + 2n
-and k_s = q_u - 2n.  For an even q_u these are whole-grid wavenumbers
-a = q_u/2 + n, b = q_u/2 - n, and the row must reproduce the datum (a, b) of a
-full-coverage periodic areal survey computed by brute force in space.  Odd
-q_u rows use the same formula; they are checked by the lattice symmetries.
+and k_s = q_u - 2n.  These half-grid wavenumbers are whole-grid wavenumbers
+of a survey with twice the period: the N-periodic model, repeated twice along
+each axis, sampled by a full-coverage periodic areal survey on the 2N x 2N
+grid.  Its data transform at receiver index a = q_u + 2n and source index
+b = q_u - 2n (mod 2N) is the datum of that row at +k_m, and at (-b, -a) the
+datum at -k_m, times 4 (the repeated model's spectrum at an even index 2q is
+four times the N-grid spectrum at q; at odd indices it vanishes).  Every row,
+odd q_u and the Nyquist k_m included, is compared with brute-force
+space-domain Born data.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -16,39 +23,85 @@ from oracle.rows import plan, kmax_of
 from oracle.solve import gtables, forward
 
 
-def test_even_km_rows_match_periodic_areal_born():
-    N = 8
+def _doubled_survey_spectrum(s, f_hz):
+    """d_mid^2 DFT over receivers and sources of the brute-force areal data of
+    the model repeated 2 x 2 times on the 2N x 2N periodic grid: [a, b] with
+    a, b in (2N)^2 flattened (x*2N + y)."""
+    N = s.n_mid
+    V2 = np.tile(s.v_true, (2, 2, 1))
+    D = born_3d(s.vel, s.zif, f_hz, s.eps, V2, s.d_mid, s.z, s.dz)
+    M = 2 * N
+    F = (s.d_mid ** 2) * np.fft.fft2(D.reshape(M, M, M, M), axes=(0, 1))
+    return np.fft.fft2(F, axes=(2, 3))
+
+
+@pytest.mark.parametrize("N,vel,zif", [(8, (1800.0, 2500.0), (40.0,)), (6, (2100.0, 1700.0, 2900.0), (30.0, 70.0))])
+def test_every_km_row_matches_doubled_periodic_areal_born(N, vel, zif):
     s = make_custom(dim=3, N=N, Nh=N // 2, nz=3, dx=30.0, dz=25.0, freqs=(6.0, 9.0),
-                    vel=(1800.0, 2500.0), zif=(40.0,), kappa=100.0, seed=7)
+                    vel=vel, zif=zif, kappa=100.0, seed=7)
     pl = plan(s)
     tabs = gtables(s, pl)
     clean = forward(s, pl, vhat(s), tabs)
-    checked = 0
+    M = 2 * N
+    checked = odd = 0
     for fi, f in enumerate(s.freqs):
-        D = born_3d(s.vel, s.zif, f, s.eps, s.v_true, s.d_mid, s.z, s.dz)
-        F = (s.d_mid ** 2) * np.fft.fft2(D.reshape(N, N, N, N), axes=(0, 1))
-        F = np.fft.fft2(F, axes=(2, 3))
+        F = _doubled_survey_spectrum(s, f)
         scale = np.max(np.abs(F))
+        # data coupling to an odd model index vanish (the repeated model has none)
+        ax, ay, bx, by = np.meshgrid(*(np.arange(M),) * 4, indexing="ij")
+        odd_sum = ((ax + bx) % 2 == 1) | ((ay + by) % 2 == 1)
+        assert np.max(np.abs(F[odd_sum])) <= 1e-12 * scale
         for p, (d0, d1) in zip(pl.pairs, clean):
             ux, uy = divmod(p.u, N)
             qx = ux if ux < (N + 1) // 2 else ux - N
             qy = uy if uy < (N + 1) // 2 else uy - N
-            if qx % 2 or qy % 2 or qx == -N // 2 or qy == -N // 2:
-                continue
             sel = np.nonzero(p.f == fi)[0]
             n = p.key0[sel, 1]
             nh = s.n_off
             nx = n // nh - nh // 2
             ny = n % nh - nh // 2
-            for sign, d in ((1, d0), (-1, d1)):
-                ax = (sign * qx // 2 + nx) % N
-                ay = (sign * qy // 2 + ny) % N
-                bx = (sign * qx // 2 - nx) % N
-                by = (sign * qy // 2 - ny) % N
-                ref = F[ax, ay, bx, by]
-                assert np.max(np.abs(ref - d[sel])) <= 1e-12 * scale
-                checked += sel.shape[0]
-    assert checked > 50
+            ax, ay = (qx + 2 * nx) % M, (qy + 2 * ny) % M
+            bx, by = (qx - 2 * nx) % M, (qy - 2 * ny) % M
+            ref0 = F[ax, ay, bx, by] / 4.0
+            ref1 = F[(-bx) % M, (-by) % M, (-ax) % M, (-ay) % M] / 4.0
+            assert np.max(np.abs(ref0 - d0[sel]), initial=0.0) <= 1e-12 * scale
+            assert np.max(np.abs(ref1 - d1[sel]), initial=0.0) <= 1e-12 * scale
+            checked += sel.shape[0]
+            if qx % 2 or qy % 2:
+                odd += sel.shape[0]
+    assert checked > 50 and odd > checked // 2
+
+
+def test_doubled_survey_pin_detects_a_wrong_half_grid_wavenumber():
+    """A half-grid |k_r| rounded to the whole grid (the mistake the doubled
+    survey is there to catch) changes the rows of odd k_m by far more than
+    the pin's tolerance."""
+    from oracle.rows import row_values
+    from oracle.green import green, omega
+    N = 8
+    s = make_custom(dim=3, N=N, Nh=N // 2, nz=3, dx=30.0, dz=25.0, freqs=(6.0,),
+                    vel=(1800.0, 2500.0), zif=(40.0,), kappa=100.0, seed=7)
+    pl = plan(s)
+    F = _doubled_survey_spectrum(s, s.freqs[0])
+    scale = np.max(np.abs(F))
+    vh = vhat(s)
+    dk = 2 * np.pi / (N * s.d_mid)
+    worst = 0.0
+    for p in pl.pairs:
+        ux, uy = divmod(p.u, N)
+        qx = ux if ux < (N + 1) // 2 else ux - N
+        qy = uy if uy < (N + 1) // 2 else uy - N
+        if not (qx % 2 or qy % 2):
+            continue
+        wrong = dataclasses.replace(p, kr=np.round(p.kr / dk) * dk)
+        A = row_values(s, wrong, lambda fi, k: green(s.vel, s.zif, omega(s.freqs[fi], s.eps), k, s.z))
+        d0 = A @ vh[p.u]
+        n = p.key0[:, 1]
+        nx, ny = n // s.n_off - s.n_off // 2, n % s.n_off - s.n_off // 2
+        ref = F[(qx + 2 * nx) % (2 * N), (qy + 2 * ny) % (2 * N), (qx - 2 * nx) % (2 * N),
+                (qy - 2 * ny) % (2 * N)] / 4.0
+        worst = max(worst, np.max(np.abs(ref - d0)))
+    assert worst > 1e-6 * scale
 
 
 def test_rows_invariant_under_lattice_rotation_and_cut():
