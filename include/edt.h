@@ -298,6 +298,36 @@ edt_status edt_solve(const edt_plan* plan, const edt_c128* g64, const edt_c128* 
                      int32_t* steps, void* work, hipStream_t stream);
 
 /*
+ * edt_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation, kernels and results as edt_solve, with its scratch in a
+ * library-owned static device array of EDT_STATIC_SCRATCH_BYTES instead of a
+ * caller workspace.  The caller still passes every input and output.
+ *   - Scratch needed (bytes, each part rounded up to 256): the damping, the
+ *     diagonal-block inverses (n_pairs * ceil(nz/32) * 8 KB), flags and
+ *     counters; with refinement also the summed data (n_urows * 64), the
+ *     residual partials (one 2 nz + 1 FP64 row per residual item) and three
+ *     per-pair refinement vectors; with escalation also the FP64 Gram
+ *     partials of every work item.  A plan needing more returns EDT_ENOMEM
+ *     (message with the size) and nothing is enqueued.
+ *   - opts->data_summed must be 0 (EDT_EINVAL): this call sums the data rows
+ *     itself, since the static array does not hold edt_assemble's sums.
+ *   - Each GPU holds one copy of the array until the process ends, shared by
+ *     every call on that GPU, and it keeps the last call's contents (what must
+ *     start at zero is cleared by kernels on the stream).  Calls on one stream
+ *     are ordered; calls that overlap on one GPU (other streams, threads, or
+ *     processes sharing a context) race on the array and must be serialised
+ *     by the caller.
+ *   - No hipMalloc, hipFree or allocating library routine is called; the
+ *     first call on a device looks up that device's address of the array.
+ */
+#define EDT_STATIC_SCRATCH_BYTES (256u * 1024u * 1024u)
+edt_status edt_solve_static(const edt_plan* plan, const edt_c128* g64, const edt_c128* d_rows, double* gram,
+                            const double* rhs, const double* trace, double lambda_rel,
+                            const edt_solve_opts* opts, double* x, edt_c128* v_out, int32_t* info,
+                            int32_t* steps, hipStream_t stream);
+
+/*
  * The paper's own solver (Section 3.1): per pair, the truncated-SVD solution
  * x+- = sum_{s_j^2 >= sigma^2} v_j (v_j . c+-) / s_j^2, where s_j^2 and v_j
  * are the eigenpairs of the pair's Gram (the squared singular values and the

@@ -9,6 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libedt.so")
 
 EDT_OK, EDT_EINVAL, EDT_ENOMEM, EDT_EHIP, EDT_ESTATE = 0, -1, -2, -3, -4
+STATIC_SCRATCH_BYTES = 256 * 1024 * 1024   # EDT_STATIC_SCRATCH_BYTES
 INFO_OK, INFO_EMPTY, INFO_NOCONV, INFO_NONFINITE = 0, -1, -2, -3
 FP64, FP32, BF16X3, FP16X3 = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3}
@@ -46,7 +47,7 @@ class SolveOpts(C.Structure):
 
 
 EXPORTS = ["edt_last_error", "edt_plan_create", "edt_survey_pair_rows", "edt_plan_destroy", "edt_plan_query",
-           "edt_plan_rowmap", "edt_plan_urows", "edt_plan_schedule", "edt_plan_upload", "edt_green", "edt_assemble", "edt_solve",
+           "edt_plan_rowmap", "edt_plan_urows", "edt_plan_schedule", "edt_plan_upload", "edt_green", "edt_assemble", "edt_solve", "edt_solve_static",
            "edt_forward", "edt_adjoint", "edt_tsvd_work_bytes", "edt_tsvd", "edt_kz_disk_radius", "edt_kz_restrict", "edt_shots_fft", "edt_shots_pack", "edt_model", "edt_aperture_work_bytes", "edt_aperture_gram", "edt_timing_enable",
            "edt_timing_read"]
 
@@ -76,6 +77,7 @@ def load(path: str = LIB_PATH):
         "edt_green": [vp, vp, vp, vp, vp],
         "edt_assemble": [vp, vp, vp, vp, C.c_int, vp, vp, vp, vp, vp],
         "edt_solve": [vp, vp, vp, vp, vp, vp, C.c_double, C.POINTER(SolveOpts), vp, vp, vp, vp, vp, vp],
+        "edt_solve_static": [vp, vp, vp, vp, vp, vp, C.c_double, C.POINTER(SolveOpts), vp, vp, vp, vp, vp],
         "edt_forward": [vp, vp, vp, vp, vp],
         "edt_adjoint": [vp, vp, vp, vp, vp, vp, vp, C.c_double, vp, vp, vp, vp, vp, vp],
         "edt_tsvd_work_bytes": [vp, C.POINTER(C.c_size_t)],

@@ -1,9 +1,11 @@
 // C-ABI entry points: argument checks and kernel orchestration on the
-// caller's stream.  No device memory is allocated here; all scratch lives in
-// the caller's workspace (layout from edt::work_layout).
+// caller's stream.  No device memory is allocated here: scratch lives in the
+// caller's workspace (layout from edt::work_layout), or, for the one
+// allocation-free entry point edt_solve_static, in a static device array.
 
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -228,14 +230,96 @@ edt_status edt_assemble(const edt_plan* p, const edt_c128* g64, const edt_c64* g
     return EDT_OK;
 }
 
-edt_status edt_solve(const edt_plan* p, const edt_c128* g64, const edt_c128* d_rows, double* gram,
-                     const double* rhs, const double* trace, double lambda_rel,
-                     const edt_solve_opts* opts, double* x, edt_c128* v_out, int32_t* info,
-                     int32_t* steps, void* work, hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+
+// Device scratch of one edt_solve call: every pointer the solve path hands
+// to its kernels.  Filled from the plan's workspace (edt_solve) or from the
+// library's static array (edt_solve_static); a section the call does not use
+// stays null.
+struct SolveScratch {
+    zd* ub = nullptr;             // [U][2] summed data (written by the data sum)
+    zd* ubw = nullptr;            // [U][2] conj(W) times the summed data
+    double* rpart = nullptr;      // residual partials per residual item
+    double* lam = nullptr;        // [P] damping
+    double* dinv = nullptr;       // [P][nblk][32][32] inverses of the diagonal blocks
+    int32_t* conv = nullptr;      // [P] converged flags
+    int32_t* aux = nullptr;       // [P] refinement steps when the caller passes none
+    int32_t* cnt = nullptr;       // [kMaxRefine + 2] sweep counters, failed factorisations
+    double* pcg_r = nullptr;      // [P][2][nz]
+    double* pcg_p = nullptr;      // [P][2][nz]
+    double* pcg_rho = nullptr;    // [P]
+    unsigned char* gram_part = nullptr;   // escalation: FP64 Gram partials per item
+    double* gram_rpart = nullptr;         // escalation: rhs and trace partials per item
+    double* esc_rhs = nullptr;            // escalation: [P][2][nz]
+    double* esc_trace = nullptr;          // escalation: [P]
+};
+
+SolveScratch scratch_from_work(const edt_plan* p, void* work) {
+    const WorkLayout wl = work_layout(p);
+    unsigned char* w = static_cast<unsigned char*>(work);
+    SolveScratch s;
+    s.ub = reinterpret_cast<zd*>(w + wl.ub);
+    s.ubw = reinterpret_cast<zd*>(w + wl.ubw);
+    s.rpart = reinterpret_cast<double*>(w + wl.rhs_part);
+    s.lam = reinterpret_cast<double*>(w + wl.lam);
+    s.dinv = reinterpret_cast<double*>(w + wl.dinv);
+    s.conv = reinterpret_cast<int32_t*>(w + wl.conv);
+    s.aux = reinterpret_cast<int32_t*>(w + wl.aux);
+    s.cnt = reinterpret_cast<int32_t*>(w + wl.counters);
+    s.pcg_r = reinterpret_cast<double*>(w + wl.pcg_r);
+    s.pcg_p = reinterpret_cast<double*>(w + wl.pcg_p);
+    s.pcg_rho = reinterpret_cast<double*>(w + wl.pcg_rho);
+    s.gram_part = w + wl.gram_part;
+    s.gram_rpart = reinterpret_cast<double*>(w + wl.gram_rpart);
+    s.esc_rhs = reinterpret_cast<double*>(w + wl.esc_rhs);
+    s.esc_trace = reinterpret_cast<double*>(w + wl.esc_trace);
+    return s;
+}
+
+// Compact scratch of a solve that uses only what its options need, packed
+// from `base` (null: sizes only).  Returns the bytes used.
+size_t compact_solve_scratch(const edt_plan* p, bool refine, bool escalate, unsigned char* base,
+                             SolveScratch* out) {
+    const size_t P = size_t(p->n_pairs), nz = size_t(p->nz), U = size_t(p->n_urows);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = (off + bytes + 255) / 256 * 256;
+        return base ? base + o : nullptr;
+    };
+    SolveScratch s;
+    s.lam = reinterpret_cast<double*>(take(P * sizeof(double)));
+    s.dinv = reinterpret_cast<double*>(take(P * size_t((p->nz + 31) / 32) * 32 * 32 * sizeof(double)));
+    s.conv = reinterpret_cast<int32_t*>(take(P * sizeof(int32_t)));
+    s.aux = reinterpret_cast<int32_t*>(take(P * sizeof(int32_t)));
+    s.cnt = reinterpret_cast<int32_t*>(take((kMaxRefine + 2) * sizeof(int32_t)));
+    if (refine) {
+        s.ub = reinterpret_cast<zd*>(take(U * 2 * sizeof(zd)));
+        s.ubw = reinterpret_cast<zd*>(take(U * 2 * sizeof(zd)));
+        s.rpart = reinterpret_cast<double*>(take(p->ritems.size() * (2 * nz + 1) * sizeof(double)));
+        s.pcg_r = reinterpret_cast<double*>(take(P * 2 * nz * sizeof(double)));
+        s.pcg_p = reinterpret_cast<double*>(take(P * 2 * nz * sizeof(double)));
+        s.pcg_rho = reinterpret_cast<double*>(take(P * sizeof(double)));
+        if (escalate) {
+            s.gram_part = take(p->items.size() * gram_part_bytes_per_item(p));
+            s.gram_rpart = reinterpret_cast<double*>(take(p->items.size() * size_t(rpart_width(p->nz)) * sizeof(double)));
+            s.esc_rhs = reinterpret_cast<double*>(take(P * 2 * nz * sizeof(double)));
+            s.esc_trace = reinterpret_cast<double*>(take(P * sizeof(double)));
+        }
+    }
+    if (out) *out = s;
+    return off;
+}
+
+edt_status check_solve_args(const edt_plan* p, const edt_c128* g64, const edt_c128* d_rows, double* gram,
+                            const double* rhs, const double* trace, double lambda_rel, const edt_solve_opts* opts,
+                            double* x, edt_c128* v_out, int32_t* info) {
     edt_status s = check_plan(p);
     if (s != EDT_OK) return s;
     const int refine = opts ? opts->refine : 0;
-    if (!gram || !rhs || !trace || !x || !v_out || !info || !work || (refine && (!g64 || !d_rows))) {
+    if (!gram || !rhs || !trace || !x || !v_out || !info || (refine && (!g64 || !d_rows))) {
         set_error("missing argument (g64 and d_rows are required with refinement)");
         return EDT_EINVAL;
     }
@@ -247,58 +331,132 @@ edt_status edt_solve(const edt_plan* p, const edt_c128* g64, const edt_c128* d_r
         set_error("refinement needs 0 <= max_refine <= " + std::to_string(kMaxRefine) + " and refine_tol > 0");
         return EDT_EINVAL;
     }
-    const WorkLayout wl = work_layout(p);
-    unsigned char* w = static_cast<unsigned char*>(work);
-    double* lam = reinterpret_cast<double*>(w + wl.lam);
-    int32_t* conv = reinterpret_cast<int32_t*>(w + wl.conv);
-    int32_t* stp = steps ? steps : reinterpret_cast<int32_t*>(w + wl.aux);
-    double* dinv = reinterpret_cast<double*>(w + wl.dinv);
+    return EDT_OK;
+}
+
+// The solve path shared by edt_solve and edt_solve_static (arguments checked).
+edt_status solve_impl(const edt_plan* p, const edt_c128* g64, const edt_c128* d_rows, double* gram,
+                      const double* rhs, const double* trace, double lambda_rel, const edt_solve_opts* opts,
+                      double* x, edt_c128* v_out, int32_t* info, int32_t* steps, const SolveScratch& ws,
+                      hipStream_t stream) {
+    const int refine = opts ? opts->refine : 0;
+    int32_t* stp = steps ? steps : ws.aux;
     // counters: pairs iterating before each sweep, then the failed factorisations
-    int32_t* cnt = reinterpret_cast<int32_t*>(w + wl.counters);
+    int32_t* cnt = ws.cnt;
     int32_t* n_failed = cnt + kMaxRefine + 1;
     if (refine) EDT_TRY(launch_reset_counters(cnt, kMaxRefine + 2, stream), "reset counters");
-    EDT_TRY(launch_chol(p, gram, trace, rhs, lambda_rel, lam, dinv, x, info, conv, stp, stream, 0, !refine,
+    EDT_TRY(launch_chol(p, gram, trace, rhs, lambda_rel, ws.lam, ws.dinv, x, info, ws.conv, stp, stream, 0, !refine,
                         refine ? n_failed : nullptr),
             "cholesky");
     if (refine) {
-        zd* ub = reinterpret_cast<zd*>(w + wl.ub);
-        zd* ubw = reinterpret_cast<zd*>(w + wl.ubw);
-        double* rpart = reinterpret_cast<double*>(w + wl.rhs_part);
         const zd* G64 = reinterpret_cast<const zd*>(g64);
         // the summed data, conj(W) B per unique row, unless the caller states
         // that edt_assemble left them in work
         if (!opts->data_summed)
-            EDT_TRY(launch_bsum(p, reinterpret_cast<const zd*>(d_rows), ub, stream, ubw), "bsum");
+            EDT_TRY(launch_bsum(p, reinterpret_cast<const zd*>(d_rows), ws.ub, stream, ws.ubw), "bsum");
         if (opts->escalate) {
             // pairs whose factorisation failed (info > 0): FP64 Gram, rhs and
             // trace from the rows, and a second factorisation; every launch
             // returns at once for the other pairs
-            double* erhs = reinterpret_cast<double*>(w + wl.esc_rhs);
-            double* etr = reinterpret_cast<double*>(w + wl.esc_trace);
-            double* gpart = reinterpret_cast<double*>(w + wl.gram_rpart);
-            EDT_TRY(launch_gram(p, EDT_FP64, G64, nullptr, ubw, nullptr, nullptr, w + wl.gram_part, gpart, stream,
-                                info, n_failed),
+            EDT_TRY(launch_gram(p, EDT_FP64, G64, nullptr, ws.ubw, nullptr, nullptr, ws.gram_part, ws.gram_rpart,
+                                stream, info, n_failed),
                     "escalate gram_fp64");
-            EDT_TRY(launch_gram_reduce(p, EDT_FP64, w + wl.gram_part, gram, stream, info), "escalate gram_reduce");
-            EDT_TRY(launch_rhs_reduce(p, gpart, erhs, etr, stream, info), "escalate rhs reduce");
-            EDT_TRY(launch_chol(p, gram, etr, erhs, lambda_rel, lam, dinv, x, info, conv, stp, stream, 1, 0, nullptr),
+            EDT_TRY(launch_gram_reduce(p, EDT_FP64, ws.gram_part, gram, stream, info), "escalate gram_reduce");
+            EDT_TRY(launch_rhs_reduce(p, ws.gram_rpart, ws.esc_rhs, ws.esc_trace, stream, info),
+                    "escalate rhs reduce");
+            EDT_TRY(launch_chol(p, gram, ws.esc_trace, ws.esc_rhs, lambda_rel, ws.lam, ws.dinv, x, info, ws.conv, stp,
+                                stream, 1, 0, nullptr),
                     "escalate cholesky");
         }
-        double* r = reinterpret_cast<double*>(w + wl.pcg_r);
-        double* pv = reinterpret_cast<double*>(w + wl.pcg_p);
-        double* rho = reinterpret_cast<double*>(w + wl.pcg_rho);
         // sweep 0: the data residual at x0; then one operator sweep per step
         for (int it = 0; it < opts->max_refine; ++it) {
-            EDT_TRY(launch_resid(p, G64, it == 0 ? ubw : nullptr, it == 0 ? x : pv,
-                                 conv, rpart, stream, cnt + it),
+            EDT_TRY(launch_resid(p, G64, it == 0 ? ws.ubw : nullptr, it == 0 ? x : ws.pcg_p, ws.conv, ws.rpart,
+                                 stream, cnt + it),
                     "refine residual");
-            EDT_TRY(launch_pcg_update(p, gram, dinv, rpart, lam, x, r, pv, rho, conv, stp, opts->refine_tol,
-                                      it == 0, cnt + it + 1, stream),
+            EDT_TRY(launch_pcg_update(p, gram, ws.dinv, ws.rpart, ws.lam, x, ws.pcg_r, ws.pcg_p, ws.pcg_rho, ws.conv,
+                                      stp, opts->refine_tol, it == 0, cnt + it + 1, stream),
                     "refine update");
         }
     }
-    EDT_TRY(launch_recombine(p, x, refine, conv, info, reinterpret_cast<zd*>(v_out), stream), "recombine");
+    EDT_TRY(launch_recombine(p, x, refine, ws.conv, info, reinterpret_cast<zd*>(v_out), stream), "recombine");
     return EDT_OK;
+}
+
+// The allocation-free solve's scratch: one array per GPU, for the life of
+// the process.  Host code never passes `scratch` itself to a kernel: it is a
+// host-side stand-in there; the device address of each GPU's copy comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[EDT_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+edt_status static_scratch(unsigned char** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "static scratch: hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("static scratch: device index out of range");
+        return EDT_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "static scratch: hipGetSymbolAddress");
+        if (!ptr) {
+            set_error("static scratch: no device address");
+            return EDT_EHIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+    return EDT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+edt_status edt_solve(const edt_plan* p, const edt_c128* g64, const edt_c128* d_rows, double* gram,
+                     const double* rhs, const double* trace, double lambda_rel,
+                     const edt_solve_opts* opts, double* x, edt_c128* v_out, int32_t* info,
+                     int32_t* steps, void* work, hipStream_t stream) {
+    edt_status s = check_solve_args(p, g64, d_rows, gram, rhs, trace, lambda_rel, opts, x, v_out, info);
+    if (s != EDT_OK) return s;
+    if (!work) {
+        set_error("missing argument: work");
+        return EDT_EINVAL;
+    }
+    return solve_impl(p, g64, d_rows, gram, rhs, trace, lambda_rel, opts, x, v_out, info, steps,
+                      scratch_from_work(p, work), stream);
+}
+
+edt_status edt_solve_static(const edt_plan* p, const edt_c128* g64, const edt_c128* d_rows, double* gram,
+                            const double* rhs, const double* trace, double lambda_rel,
+                            const edt_solve_opts* opts, double* x, edt_c128* v_out, int32_t* info,
+                            int32_t* steps, hipStream_t stream) {
+    edt_status s = check_solve_args(p, g64, d_rows, gram, rhs, trace, lambda_rel, opts, x, v_out, info);
+    if (s != EDT_OK) return s;
+    const bool refine = opts && opts->refine;
+    const bool escalate = refine && opts->escalate;
+    if (refine && opts->data_summed) {
+        set_error("edt_solve_static sums the data itself: data_summed must be 0");
+        return EDT_EINVAL;
+    }
+    const size_t need = compact_solve_scratch(p, refine, escalate, nullptr, nullptr);
+    if (need > size_t(EDT_STATIC_SCRATCH_BYTES)) {
+        set_error("edt_solve_static needs " + std::to_string(need) + " bytes of scratch, more than the " +
+                  std::to_string(size_t(EDT_STATIC_SCRATCH_BYTES)) + " it holds (use edt_solve with a workspace)");
+        return EDT_ENOMEM;
+    }
+    unsigned char* base = nullptr;
+    s = static_scratch(&base);
+    if (s != EDT_OK) return s;
+    SolveScratch ws;
+    compact_solve_scratch(p, refine, escalate, base, &ws);
+    return solve_impl(p, g64, d_rows, gram, rhs, trace, lambda_rel, opts, x, v_out, info, steps, ws, stream);
 }
 
 edt_status edt_tsvd_work_bytes(const edt_plan* p, size_t* bytes) {

@@ -208,6 +208,27 @@ class Plan:
                                          _ptr(steps), _ptr(self._work), _stream()), "edt_solve")
         return x, v, info, steps
 
+    def solve_static(self, g64, d_rows, gram, rhs, trace, lambda_rel, refine=False, refine_tol=1e-8,
+                     max_refine=8, escalate=True, out=None):
+        """solve() through edt_solve_static: the library's static device scratch
+        instead of the plan's workspace (no device allocation in the call; the
+        outputs are allocated here unless ``out`` gives them)."""
+        self.upload()
+        P, nz = self.n_pairs, self.nz
+        if out is None:
+            x = torch.empty(P, 2, nz, dtype=torch.float64, device=self.device)
+            v = self._c128(self.n_km, nz)
+            info = torch.empty(P, dtype=torch.int32, device=self.device)
+            steps = torch.zeros(P, dtype=torch.int32, device=self.device)
+        else:
+            x, v, info, steps = out
+        opts = _lib.SolveOpts(1 if refine else 0, float(refine_tol), int(max_refine),
+                              1 if (refine and escalate) else 0, 0)
+        _lib.check(_lib.load().edt_solve_static(self._h, _ptr(g64), _ptr(d_rows), _ptr(gram), _ptr(rhs),
+                                                _ptr(trace), float(lambda_rel), C.byref(opts), _ptr(x), _ptr(v),
+                                                _ptr(info), _ptr(steps), _stream()), "edt_solve_static")
+        return x, v, info, steps
+
     def tsvd(self, gram, rhs, tol_rel, max_iter=64, out=None, tsvd_work=None):
         """The paper's truncated-SVD solve from an assembled Gram (overwritten):
         (x[P, 2, nz], v[n_km, nz] complex128, info[P], iters[P]).  The default
