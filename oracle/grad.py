@@ -36,7 +36,11 @@ __all__ = ["grad"]
 
 
 def grad(s, pl, data, gV, lambda_rel=None, vel=None, pairs=None):
-    """Returns dict(d=[(gd0, gd1) per pair], lambda_rel=float, vel=array)."""
+    """Returns dict(d=[(gd0, gd1) per pair], lambda_rel=float, vel=array,
+    lambda_terms=array, lambda_abs=array): lambda_terms[p] = tr(G_p)/nz *
+    dL/dlambda_p, the per-pair terms whose sum is dL/dlambda_rel, and
+    lambda_abs[p] = tr(G_p)/nz * sum |y * x|, the magnitude a rounding error of
+    the dot product -y.x is relative to."""
     lam_rel = s.lambda_rel if lambda_rel is None else lambda_rel
     vel = s.vel if vel is None else np.asarray(vel, np.float64)
     pairs = pl.pairs if pairs is None else pairs
@@ -57,9 +61,13 @@ def grad(s, pl, data, gV, lambda_rel=None, vel=None, pairs=None):
 
     gd = []
     glam = 0.0
+    lterms = []
+    labs = []
     for p, (d0, d1) in zip(pairs, data):
         if p.n_rows == 0:
             gd.append((np.zeros(0, np.complex128), np.zeros(0, np.complex128)))
+            lterms.append(0.0)
+            labs.append(0.0)
             continue
         A = row_values(s, p, tabs.lookup)
         bp = 0.5 * (d0 + d1)
@@ -81,6 +89,8 @@ def grad(s, pl, data, gV, lambda_rel=None, vel=None, pairs=None):
             y[1] = 0.0
         dlam = -float(np.sum(y * x))
         glam += dlam * tr / nz
+        lterms.append(dlam * tr / nz)
+        labs.append(float(np.sum(np.abs(y * x))) * tr / nz)
         Ay = A @ y.T                      # (R, 2): dL/db+-, complex
         gbp, gbm = Ay[:, 0], Ay[:, 1]
         gd.append((0.5 * gbp + 0.5j * gbm, 0.5 * gbp - 0.5j * gbm))
@@ -101,4 +111,5 @@ def grad(s, pl, data, gV, lambda_rel=None, vel=None, pairs=None):
     gvel = np.zeros(vel.shape[0])
     for f in tk:
         gvel += np.einsum("kz,lkz->l", np.conj(tbar[f]), tdg[f]).real
-    return dict(d=gd, lambda_rel=glam, vel=gvel)
+    return dict(d=gd, lambda_rel=glam, vel=gvel, lambda_terms=np.array(lterms),
+                lambda_abs=np.array(labs))
