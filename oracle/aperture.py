@@ -24,7 +24,7 @@ import scipy.linalg
 from .rows import row_values
 from .solve import INFO_EMPTY, INFO_OK
 
-__all__ = ["offset_window", "window_kernel", "aperture_rows", "aperture_solve"]
+__all__ = ["offset_window", "window_kernel", "aperture_rows", "aperture_data", "aperture_solve"]
 
 
 def offset_window(s, b_max):
@@ -57,10 +57,28 @@ def aperture_rows(s, p, A, Sm):
     return B
 
 
+def aperture_data(s, pl, data, b_max, pairs=None):
+    """The windowed data d_W = S d of every pair: the data (d+, d-) of one
+    frequency are mixed by S(a - a') over their receiver indices a, as the
+    rows are (the records windowed in full offset, with the data outside the
+    kept rows taken as zero)."""
+    Sm = window_kernel(offset_window(s, b_max))
+    pairs = pl.pairs if pairs is None else pairs
+    out = []
+    for p, (d0, d1) in zip(pairs, data):
+        if not p.n_rows:
+            out.append((d0.copy(), d1.copy()))
+            continue
+        B = aperture_rows(s, p, np.stack([d0, d1], axis=1), Sm)
+        out.append((B[:, 0].copy(), B[:, 1].copy()))
+    return out
+
+
 def aperture_solve(s, pl, data, tabs, b_max, lambda_rel=None, pairs=None):
     """Damped solve of the windowed system: (Re(A^H S A) + lambda I) x =
-    Re(A^H b+-), lambda = lambda_rel tr / nz.  V~ (n_km, nz) and per-pair
-    details."""
+    Re(A^H b+-), lambda = lambda_rel tr / nz, with b+- formed from `data`,
+    which are the windowed data d_W (aperture_data) for the windowed system.
+    V~ (n_km, nz) and per-pair details."""
     if getattr(s, "dim", 2) != 2:
         raise ValueError("the 2D line survey only")
     lam_rel = s.lambda_rel if lambda_rel is None else lambda_rel

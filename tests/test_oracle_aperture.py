@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from edt_inputs import make_custom, vhat
-from oracle.aperture import aperture_rows, aperture_solve, offset_window, window_kernel
+from oracle.aperture import aperture_data, aperture_rows, aperture_solve, offset_window, window_kernel
 from oracle.born import born_2d
 from oracle.rows import plan, row_values
 from oracle.shots import shots_to_rows
@@ -38,6 +38,13 @@ def test_windowed_born_records_give_the_windowed_rows(N, b):
         B = aperture_rows(s, p, row_values(s, p, tabs.lookup), Sm)
         assert np.max(np.abs(B @ vh[p.u] - d0)) <= 1e-12 * scale
         assert np.max(np.abs(B @ vh[p.u_neg] - d1)) <= 1e-12 * scale
+    # the data form of the window: the unwindowed records' rows, windowed by
+    # aperture_data, are the windowed records' rows
+    D0 = np.stack([born_2d(s.vel, s.zif, f, s.eps, s.v_true, s.d_mid, s.z, s.dz) for f in s.freqs])
+    wd = aperture_data(s, pl, shots_to_rows(s, pl, D0), b)
+    for (a0, a1), (d0, d1) in zip(wd, rows):
+        assert np.max(np.abs(a0 - d0)) <= 1e-12 * scale
+        assert np.max(np.abs(a1 - d1)) <= 1e-12 * scale
 
 
 def test_discrete_sinc_is_a_real_projector():
