@@ -53,14 +53,24 @@ def parse():
     ap.add_argument("--max-refine", type=int, default=8)
     ap.add_argument("--chunk", type=int, default=0, help="rows per Gram item (0 = planner default)")
     ap.add_argument("--band", type=int, default=0, help="frequencies per Gram band (0 = planner default)")
-    ap.add_argument("--cpu-pairs", type=int, default=160, help="pairs in the oracle leg (about 10 s of host work)")
+    ap.add_argument("--cpu-pairs", type=int, default=0,
+                    help="pairs in the oracle leg (0: 160 for the 2D surveys, 512 for the 3D 128 x 128 one)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--only", choices=["both", "mixed", "fp64"], default="both")
-    ap.add_argument("--tune", action="store_true", help="autotune chunk_rows / gram_band per precision first")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the work-item shapes per precision first and store them in the tuned-shape "
+                         "table (EDT_TUNE_CACHE, else the package's table)")
+    ap.add_argument("--default-shapes", action="store_true",
+                    help="use the planner's default work-item shapes instead of the tuned-shape table")
     ap.add_argument("--stream", action="store_true",
                     help="solve in pair-range batches (always on for config 5, the 3D 256 x 256 survey)")
     ap.add_argument("--batch-rows", type=int, default=100_000_000, help="data rows per batch at most")
     ap.add_argument("--batch-pairs", type=int, default=4096, help="pairs per batch at most")
+    ap.add_argument("--data", choices=["c128", "c64"], default=None,
+                    help="storage of the data rows (default: complex64 for the 3D 256 x 256 survey, whose "
+                         "data are complex FP32, else complex128)")
+    ap.add_argument("--hbm-budget", type=float, default=None,
+                    help="device bytes the batch stream may hold (default: 200e9 for the 3D 256 x 256 survey)")
     ap.add_argument("--tsvd", type=float, default=1e-2,
                     help="relative tolerance of the truncated-SVD leg (the paper's own solver), "
                          "timed after the main passes; 0 skips it")
@@ -410,38 +420,74 @@ def aperture_leg(plan, vel, d_mid, reps, torch):
                                           f"all inside the timed call)"}}
 
 
+_CPU_JOB = None   # (survey, oracle plan, sampled pairs, their data): read by forked workers
+
+
+def _oracle_chunk(idx):
+    """One host process: the FP64 oracle solve of the sampled pairs idx
+    (their G0 tables, Born rows, normal equations, Cholesky) on one core."""
+    from threadpoolctl import threadpool_limits
+    from oracle.rows import row_values
+    from oracle.solve import gtables, solve_pair
+    s, pl, sub, data = _CPU_JOB
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        pairs = [sub[i] for i in idx]
+        tabs = gtables(s, pl, pairs=pairs)
+        xs = []
+        for i, q in zip(idx, pairs):
+            A = row_values(s, q, tabs.lookup)
+            xs.append(solve_pair(s, q, A, *data[i])[0])
+        return idx, xs, time.perf_counter() - t0
+
+
 def cpu_baseline_leg(s, plan, pipes, n_pairs_sample, torch):
-    """Time the FP64 oracle on a seeded sample of pairs (host cores), and state
-    the GPU error on the same oracle data for those pairs."""
+    """Time the FP64 oracle on a seeded sample of pairs on the host cores, one
+    single-threaded process per core (forked; each builds the tables its own
+    pairs need), and once more on one core alone; then state the GPU error on
+    the same oracle data for those pairs."""
+    global _CPU_JOB
+    import multiprocessing as mp
     from edt_inputs import vhat
-    from oracle.rows import plan as oplan, row_values
-    from oracle.solve import gtables, forward, noise_scale, add_noise, solve_pair
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
-    pl = oplan(s)
+    from oracle.rows import plan as oplan
+    from oracle.solve import gtables, forward, noise_scale, add_noise
+    cores = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()))
+    rows = E_pair_rows(s)
     rng = np.random.default_rng(1234)
-    nonempty = [i for i, q in enumerate(pl.pairs) if q.n_rows > 0]
-    pick = sorted(rng.choice(nonempty, size=min(n_pairs_sample, len(nonempty)), replace=False).tolist())
-    # noise scale needs the clean data of every row (max per frequency)
-    tabs_all = gtables(s, pl)
-    clean_all = forward(s, pl, vhat(s), tabs_all)
-    scale = noise_scale(s, pl, clean_all)
-    sub = [pl.pairs[i] for i in pick]
-    data = add_noise(s, pl, [clean_all[i] for i in pick], scale, pairs=sub)
-    del clean_all
-    # timed: the oracle solve of the sampled pairs (tables for their rows, rows,
-    # normal equations, Cholesky)
-    t0 = time.perf_counter()
-    tabs = gtables(s, pl, pairs=sub)
-    xs = []
-    for q, (d0, d1) in zip(sub, data):
-        A = row_values(s, q, tabs.lookup)
-        xs.append(solve_pair(s, q, A, d0, d1)[0])
-    dt = time.perf_counter() - t0
+    nonempty = np.nonzero(rows > 0)[0]
+    pick = sorted(rng.choice(nonempty, size=min(n_pairs_sample, nonempty.size), replace=False).tolist())
+    pl = oplan(s, only=pick)
+    sub = pl.pairs
+    # data of the sampled pairs: oracle forward map plus the counter-based
+    # noise, scaled by the sample's largest datum per frequency (an input)
+    tabs0 = gtables(s, pl)
+    clean = forward(s, pl, vhat(s), tabs0)
+    data = add_noise(s, pl, clean, noise_scale(s, pl, clean))
+    del tabs0, clean
+    # chunks of about equal Gram work per core (longest first)
+    cost = np.array([q.n_rows for q in sub], np.float64)
+    chunks = [[] for _ in range(cores)]
+    load = np.zeros(cores)
+    for i in np.argsort(-cost, kind="stable"):
+        c = int(np.argmin(load))
+        chunks[c].append(int(i))
+        load[c] += cost[i]
+    chunks = [c for c in chunks if c]
+    _CPU_JOB = (s, pl, sub, data)
+    xs = [None] * len(sub)
+    with mp.get_context("fork").Pool(len(chunks)) as pool:
+        pool.map(len, [[0]] * len(chunks))          # workers started before the clock
+        t0 = time.perf_counter()
+        for idx, xx, _ in pool.imap_unordered(_oracle_chunk, chunks):
+            for i, x in zip(idx, xx):
+                xs[i] = x
+        dt = time.perf_counter() - t0
     n_km = sum(1 if q.self_conjugate else 2 for q in sub)
+    # one core alone, on the heaviest chunk
+    one = chunks[0]
+    _, _, dt1 = _oracle_chunk(one)
+    n_km1 = sum(1 if sub[i].self_conjugate else 2 for i in one)
+    _CPU_JOB = None
     # GPU on identical inputs: the oracle's data overwrite the sampled pairs
     m = plan.rowmap()
     off = m["row_off"]
@@ -476,12 +522,20 @@ def cpu_baseline_leg(s, plan, pipes, n_pairs_sample, torch):
         fl = 1e-3 * norms.max()
         errs[r.prec] = {"global": float(np.sqrt(num / den)),
                         "per_pair_max": float(np.max(np.array(per) / np.maximum(norms, fl))),
-                        "pairs": len(sub)}
-    base = {"value": n_km / dt, "unit": "subproblems/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{len(sub)} of {plan.n_pairs} +-k_m pairs ({n_km} k_m, seeded), "
-                      f"FP64 NumPy/SciPy: G0 tables, Born rows, Re(A^H A), Cholesky; {dt:.1f} s",
+                        "pairs": len(sub), "largest_pair_rows": int(cost.max())}
+    base = {"value": n_km / dt, "unit": "subproblems/s", "cores": len(chunks), "kind": "oracle",
+            "sample": f"{len(sub)} of {plan.n_pairs} +-k_m pairs ({n_km} k_m, seeded), FP64 NumPy/SciPy "
+                      f"(G0 tables, Born rows, Re(A^H A), Cholesky), one single-threaded process per core over "
+                      f"pairs: {dt:.1f} s wall",
+            "single_core": {"value": n_km1 / dt1, "unit": "subproblems/s",
+                            "sample": f"{len(one)} pairs ({n_km1} k_m) on one core: {dt1:.1f} s"},
             "host_cpus": os.cpu_count()}
     return base, errs
+
+
+def E_pair_rows(s):
+    import paper_0905_0238_amd as E
+    return E.pair_rows(s)
 
 
 def stream_main(a, s, torch, E, CONFIG_NAMES):
@@ -493,9 +547,11 @@ def stream_main(a, s, torch, E, CONFIG_NAMES):
     precs = {"both": ["fp64"] + extra + [a.mixed], "mixed": [a.mixed], "fp64": ["fp64"]}[a.only]
     from edt_inputs import vhat
     t0 = time.perf_counter()
+    data = a.data or ("c64" if a.config == 5 else "c128")
+    budget = int(a.hbm_budget if a.hbm_budget is not None else (200e9 if a.config == 5 else 0))
     st = E.Stream(s, prec=precs[-1], also=precs[:-1], refine_tol=a.refine_tol, max_refine=a.max_refine,
                   batch_rows=a.batch_rows, batch_pairs=a.batch_pairs, chunk_rows=a.chunk, gram_band=a.band,
-                  threads=16)
+                  threads=16, data=data, hbm_budget=budget)
     plan_s = time.perf_counter() - t0
     print(f"# {len(st.batches)} batches planned in {plan_s:.1f} s", file=sys.stderr, flush=True)
     # synthetic data: Born forward map of the seeded model on the GPU plus
@@ -507,13 +563,14 @@ def stream_main(a, s, torch, E, CONFIG_NAMES):
     gen.manual_seed(int(s.seed))
     for b, p in enumerate(st.plans):
         if p.n_rows == 0:
-            st.set_data(b, torch.zeros(0, 2, dtype=torch.complex128))
+            st.set_data(b, torch.zeros(0, 2, dtype=p.data_dtype))
             continue
         d = p.forward(st.G64, vh)
         if s.noise_rel:
+            rdt = torch.float32 if d.dtype == torch.complex64 else torch.float64
             sc = s.noise_rel * float(d.abs().amax()) / np.sqrt(2.0)
-            re = torch.randn(d.shape, generator=gen, device="cuda", dtype=torch.float64)
-            im = torch.randn(d.shape, generator=gen, device="cuda", dtype=torch.float64)
+            re = torch.randn(d.shape, generator=gen, device="cuda", dtype=rdt)
+            im = torch.randn(d.shape, generator=gen, device="cuda", dtype=rdt)
             d += sc * torch.complex(re, im)
             del re, im
         st.set_data(b, d)
@@ -586,7 +643,8 @@ def stream_main(a, s, torch, E, CONFIG_NAMES):
         "config": {"workload": CONFIG_NAMES[a.config], "n_km": st.n_km, "n_pairs": st.n_pairs, "nz": s.nz,
                    "n_freq": s.n_freq, "rows": int(st.rows.sum()), "unique_rows": U, "precision": main_prec,
                    "refine_tol": a.refine_tol, "max_refine": a.max_refine, "batches": len(st.batches),
-                   "batch_rows": a.batch_rows, "batch_pairs": a.batch_pairs},
+                   "batch_rows": a.batch_rows, "batch_pairs": a.batch_pairs, "data_rows": data,
+                   "hbm_budget": budget},
         "roofline": roof,
     }
     if "fp64" in res and main_prec != "fp64":
@@ -623,17 +681,26 @@ def main():
     extra = [m for m in a.also.split(",") if m and m != a.mixed] if a.only == "both" else []
     precs = {"both": ["fp64"] + extra + [a.mixed], "mixed": [a.mixed], "fp64": ["fp64"]}[a.only]
     vel = torch.tensor(s.vel, dtype=torch.float64, device="cuda")
-    tuned = {}
-    if a.tune:
-        from paper_0905_0238_amd.tune import autotune
-        for pr in precs:
-            tuned[pr] = autotune(s, prec=pr)
+    from paper_0905_0238_amd.tune import autotune, shapes_for, DEFAULT_SHAPE
+    shapes, tuned, source = {}, {}, {}
+    for pr in precs:
+        if a.tune:
+            tuned[pr] = autotune(s, prec=pr, refine_tol=a.refine_tol, max_refine=a.max_refine,
+                                 log=lambda r: print("# tune", json.dumps(r), file=sys.stderr, flush=True))
+            shapes[pr] = {k: tuned[pr][k] for k in DEFAULT_SHAPE}
+            source[pr] = "tuned now"
+        elif a.chunk or a.band or a.default_shapes:
+            shapes[pr] = {"chunk_rows": a.chunk, "gram_band": a.band, "resid_group": 0}
+            source[pr] = "command line" if (a.chunk or a.band) else "planner default"
+        else:
+            shapes[pr] = shapes_for(s, pr)
+            source[pr] = "tuned-shape table" if shapes[pr] != DEFAULT_SHAPE else "planner default (not in table)"
     t0 = time.perf_counter()
     plans = {}
     for pr in precs:
-        opts = (tuned[pr]["chunk_rows"], tuned[pr]["gram_band"]) if pr in tuned else (a.chunk, a.band)
+        opts = tuple(shapes[pr][k] for k in ("chunk_rows", "gram_band", "resid_group"))
         if opts not in plans:
-            plans[opts] = E.Plan(s, chunk_rows=opts[0], gram_band=opts[1]).upload()
+            plans[opts] = E.Plan(s, chunk_rows=opts[0], gram_band=opts[1], resid_group=opts[2]).upload()
         plans[pr] = plans[opts]
     plan_s = time.perf_counter() - t0
     plan = plans[precs[-1]]
@@ -651,7 +718,8 @@ def main():
                           "refine_steps": {"max": int(st.max()), "mean": float(st.mean())},
                           "info_nonzero": int(np.sum((info != 0) & (info != -1))),
                           "items": {"chunk_rows": pipe.p.info["chunk_rows"], "gram_band": pipe.p.info["gram_band"],
-                                    "n_items": pipe.p.info["n_items"]}}
+                                    "resid_group": pipe.p.info["resid_group"], "n_items": pipe.p.info["n_items"],
+                                    "shape_source": source[pipe.prec]}}
         if pipe.prec in tuned:
             res[pipe.prec]["tuner"] = tuned[pipe.prec]["table"]
     main_prec = precs[-1]
@@ -674,7 +742,8 @@ def main():
         "config": {"workload": CONFIG_NAMES[a.config], "n_km": plan.n_km, "n_pairs": plan.n_pairs,
                    "nz": s.nz, "n_freq": s.n_freq, "rows": plan.n_rows, "unique_rows": plan.info["n_urows"],
                    "precision": main_prec, "refine_tol": a.refine_tol, "max_refine": a.max_refine,
-                   "chunk_rows": plan.info["chunk_rows"], "gram_band": plan.info["gram_band"]},
+                   "chunk_rows": plan.info["chunk_rows"], "gram_band": plan.info["gram_band"],
+                   "resid_group": plan.info["resid_group"], "shapes": source[main_prec]},
         "roofline": roof,
     }
     if "fp64" in res and main_prec != "fp64":
@@ -693,7 +762,8 @@ def main():
         if sl is not None:
             out["detail"]["shots"] = sl
     if not a.no_cpu:
-        base, errs = cpu_baseline_leg(s, plan, pipes, a.cpu_pairs, torch)
+        n_cpu = a.cpu_pairs or (512 if s.dim == 3 else 160)
+        base, errs = cpu_baseline_leg(s, plan, pipes, n_cpu, torch)
         out["cpu_baseline"] = base
         out["rel_err_vs_oracle"] = errs
     print(json.dumps(out), flush=True)

@@ -122,6 +122,15 @@ typedef struct {
 
 typedef struct edt_plan edt_plan;
 
+/* Storage type of the data rows d_rows (a plan option): complex128, or
+ * complex64 (half the bytes; read and widened to FP64 by the kernels, which
+ * compute in FP64 either way).  Every call that reads or writes data rows,
+ * and the data gradient of edt_adjoint, uses the plan's type. */
+typedef enum {
+    EDT_DATA_C128 = 0,
+    EDT_DATA_C64 = 1
+} edt_data_type;
+
 typedef struct {
     int64_t n_km;          /* number of k_m problems */
     int64_t n_pairs;       /* number of +-k_m pairs (factorisations) */
@@ -141,6 +150,11 @@ typedef struct {
     int64_t n_pairs_all;   /* pairs of the whole survey */
     int64_t pair_begin;    /* survey index of this plan's first pair */
     int resid_group;       /* frequencies per residual work item */
+    int data_type;         /* edt_data_type of d_rows */
+    size_t resident_bytes; /* device bytes of one pass of this plan: the device plan, the
+                              workspace, the data rows, the Gram, rhs, trace, x, info and steps
+                              of its pairs, v_out (n_km x nz) and the survey's Green's tables
+                              g64 and g32 */
 } edt_plan_info;
 
 typedef struct {
@@ -171,12 +185,22 @@ const char* edt_last_error(void);
  *               for one workspace.  The |k| classes, and so the Green's table,
  *               are those of the whole survey, so that every batch uses one
  *               table; v_out of a batch's solve receives only its pairs' k_m.
+ *   resid_group frequencies per residual work item (default: 2, widened
+ *               where rows are sparse until an average item holds 64 rows)
+ *   data_type   edt_data_type of the data rows (default complex128)
+ *   hbm_budget  device bytes one pass of the plan may hold (0 = no limit):
+ *               edt_plan_create returns EDT_ENOMEM, with the bytes needed in
+ *               the message, when resident_bytes (edt_plan_info) exceeds it,
+ *               e.g. when a pair range, down to a single pair, does not fit
  */
 typedef struct {
     int chunk_rows;
     int gram_band;
     int64_t pair_begin;
     int64_t pair_end;
+    int data_type;
+    size_t hbm_budget;
+    int resid_group;
 } edt_plan_opts;
 
 /*
@@ -187,8 +211,9 @@ typedef struct {
  * frequencies.  Both are laid out in an XCD-aware launch order.  opts is
  * nullable (= defaults).  Host only, no HIP calls.
  * Errors: EDT_EINVAL (dim, sizes, zif[0] <= 0, non-increasing zif, n_cls or
- * n_freq >= 65536, n_freq * n_cls * nz >= 2^32, chunk_rows or gram_band out of
- * range), EDT_ENOMEM.
+ * n_freq >= 65536, n_freq * n_cls * nz >= 2^32, chunk_rows, gram_band,
+ * resid_group or data_type out of range), EDT_ENOMEM (host memory, or the plan's device
+ * bytes above opts->hbm_budget).
  * *out is owned by the caller: edt_plan_destroy.
  */
 edt_status edt_plan_create(const edt_survey* survey, const edt_layers* layers,
@@ -260,7 +285,8 @@ edt_status edt_green(const edt_plan* plan, const double* vel_dev, edt_c128* g64,
  * i >= j is written) = Re(A_p^H A_p) in the given precision, and, from the
  * same pass over the rows, rhs[p][0|1][z] = Re(A_p^H b+-) and
  * trace[p] = tr Re(A_p^H A_p).  d_rows[r] = (datum at +k_m, datum at -k_m) of
- * row r, complex128, so b+ = (d0+d1)/2 and b- = (d0-d1)/(2i) (eq. Split).
+ * row r, in the plan's data type (complex128 or complex64), so
+ * b+ = (d0+d1)/2 and b- = (d0-d1)/(2i) (eq. Split), summed in FP64.
  * prec EDT_FP64 reads g64 and gives rhs and trace in FP64.  EDT_FP32,
  * EDT_BF16X3 and EDT_FP16X3 read g32 (from edt_green); their rhs and trace
  * come from FP32 rows summed per stage of 8 rows in FP32 and then in FP64
@@ -271,7 +297,7 @@ edt_status edt_green(const edt_plan* plan, const double* vel_dev, edt_c128* g64,
  * Gram, rhs and trace.
  */
 edt_status edt_assemble(const edt_plan* plan, const edt_c128* g64, const edt_c64* g32,
-                        const edt_c128* d_rows, edt_precision prec, double* gram, double* rhs,
+                        const void* d_rows, edt_precision prec, double* gram, double* rhs,
                         double* trace, void* work, hipStream_t stream);
 
 /*
@@ -290,9 +316,10 @@ edt_status edt_assemble(const edt_plan* plan, const edt_c128* g64, const edt_c64
  * factorisation.  A self-conjugate k_m keeps
  * x- = 0.  v_out[u] = x+ + i x-, v_out[-u] = x+ - i x- (eq. VSym), zero for
  * empty pairs.  x: [n_pairs][2][nz]; v_out: [n_km][nz]; info, steps: [n_pairs]
- * (steps nullable).  opts nullable (= no refinement).
+ * (steps nullable).  opts nullable (= no refinement).  d_rows: the plan's data
+ * type, as in edt_assemble.
  */
-edt_status edt_solve(const edt_plan* plan, const edt_c128* g64, const edt_c128* d_rows,
+edt_status edt_solve(const edt_plan* plan, const edt_c128* g64, const void* d_rows,
                      double* gram, const double* rhs, const double* trace, double lambda_rel,
                      const edt_solve_opts* opts, double* x, edt_c128* v_out, int32_t* info,
                      int32_t* steps, void* work, hipStream_t stream);
@@ -322,7 +349,7 @@ edt_status edt_solve(const edt_plan* plan, const edt_c128* g64, const edt_c128* 
  *     first call on a device looks up that device's address of the array.
  */
 #define EDT_STATIC_SCRATCH_BYTES (256u * 1024u * 1024u)
-edt_status edt_solve_static(const edt_plan* plan, const edt_c128* g64, const edt_c128* d_rows, double* gram,
+edt_status edt_solve_static(const edt_plan* plan, const edt_c128* g64, const void* d_rows, double* gram,
                             const double* rhs, const double* trace, double lambda_rel,
                             const edt_solve_opts* opts, double* x, edt_c128* v_out, int32_t* info,
                             int32_t* steps, hipStream_t stream);
@@ -394,14 +421,14 @@ edt_status edt_kz_restrict(const edt_plan* plan, double k_disk, double* gram, do
  * the data convention of every other call (a, b: receiver and source
  * wavenumber indices in fftfreq order).  One pass over the records per axis.
  *
- * edt_shots_pack: d_rows[n_rows][2] (device) from that spectrum: row r with
- * frequency f and key (a, b) (edt_plan_rowmap) gets (d~[f][a][b],
- * d~[f][-b][-a]), the datum at +k_m and its -k_m partner.  The spectrum is
+ * edt_shots_pack: d_rows[n_rows][2] (device, the plan's data type) from that
+ * spectrum: row r with frequency f and key (a, b) (edt_plan_rowmap) gets
+ * (d~[f][a][b], d~[f][-b][-a]), the datum at +k_m and its -k_m partner.  The spectrum is
  * only read, so the plans of several pair ranges (batches) of one survey can
  * each pack from one transform.
  */
 edt_status edt_shots_fft(const edt_plan* plan, edt_c128* shots, hipStream_t stream);
-edt_status edt_shots_pack(const edt_plan* plan, const edt_c128* spectrum, edt_c128* d_rows, hipStream_t stream);
+edt_status edt_shots_pack(const edt_plan* plan, const edt_c128* spectrum, void* d_rows, hipStream_t stream);
 
 /*
  * Finite aperture (eq. M) on the 2D line survey: the Gram of every pair when
@@ -437,10 +464,11 @@ edt_status edt_model(const edt_plan* plan, edt_c128* v_tilde, double* model, hip
 /*
  * Born forward map (eq. DMV): d_rows[r] = (A_r . v_in[u_p], A_r . v_in[-u_p]),
  * A_r = w_f^2 dz g(k_r) g(k_s), for every row r of pair p.
- * v_in: [n_km][nz] complex128; d_rows: [n_rows][2] complex128.
+ * v_in: [n_km][nz] complex128; d_rows: [n_rows][2] in the plan's data type
+ * (formed in FP64, rounded to complex64 for such a plan).
  */
 edt_status edt_forward(const edt_plan* plan, const edt_c128* g64, const edt_c128* v_in,
-                       edt_c128* d_rows, hipStream_t stream);
+                       void* d_rows, hipStream_t stream);
 
 /*
  * Kernel (d): reverse-mode gradient of a real loss L(V~) given
@@ -448,15 +476,16 @@ edt_status edt_forward(const edt_plan* plan, const edt_c128* g64, const edt_c128
  * solution `x` left by edt_solve, trace from edt_assemble, and recomputes the
  * Green's tables and their velocity sensitivities from vel_dev (g64 is the
  * table of the forward pass).  Outputs (each nullable):
- *   grad_d[r] = (dL/dd0, dL/dd1) in the same complex convention ([n_rows][2])
+ *   grad_d[r] = (dL/dd0, dL/dd1) in the same complex convention ([n_rows][2],
+ *               the plan's data type, like d_rows)
  *   grad_lambda[0] = dL/dlambda_rel
  *   grad_vel[l] = dL/dc_l, l < n_layers
  * The evanescent-cut mask is held fixed.
  */
 edt_status edt_adjoint(const edt_plan* plan, const double* vel_dev, const edt_c128* g64,
-                       const edt_c128* d_rows, const double* chol, const double* trace,
+                       const void* d_rows, const double* chol, const double* trace,
                        const double* x, double lambda_rel, const edt_c128* grad_v,
-                       edt_c128* grad_d, double* grad_lambda, double* grad_vel, void* work,
+                       void* grad_d, double* grad_lambda, double* grad_vel, void* work,
                        hipStream_t stream);
 
 /*

@@ -12,6 +12,8 @@ EDT_OK, EDT_EINVAL, EDT_ENOMEM, EDT_EHIP, EDT_ESTATE = 0, -1, -2, -3, -4
 STATIC_SCRATCH_BYTES = 256 * 1024 * 1024   # EDT_STATIC_SCRATCH_BYTES
 INFO_OK, INFO_EMPTY, INFO_NOCONV, INFO_NONFINITE = 0, -1, -2, -3
 FP64, FP32, BF16X3, FP16X3 = 0, 1, 2, 3
+DATA_C128, DATA_C64 = 0, 1
+DATA_TYPES = {"c128": DATA_C128, "c64": DATA_C64}
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3}
 
 
@@ -33,12 +35,14 @@ class PlanInfo(C.Structure):
                 ("n_layers", C.c_int), ("chunk_rows", C.c_int), ("gram_band", C.c_int),
                 ("table_elems", C.c_size_t),
                 ("dev_plan_bytes", C.c_size_t), ("work_bytes", C.c_size_t), ("gram_flops", C.c_double),
-                ("n_pairs_all", C.c_int64), ("pair_begin", C.c_int64), ("resid_group", C.c_int)]
+                ("n_pairs_all", C.c_int64), ("pair_begin", C.c_int64), ("resid_group", C.c_int),
+                ("data_type", C.c_int), ("resident_bytes", C.c_size_t)]
 
 
 class PlanOpts(C.Structure):
     _fields_ = [("chunk_rows", C.c_int), ("gram_band", C.c_int), ("pair_begin", C.c_int64),
-                ("pair_end", C.c_int64)]
+                ("pair_end", C.c_int64), ("data_type", C.c_int), ("hbm_budget", C.c_size_t),
+                ("resid_group", C.c_int)]
 
 
 class SolveOpts(C.Structure):

@@ -18,7 +18,7 @@ class EDTSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, d_rows, lambda_rel, vel, plan):
         lam = float(lambda_rel)
-        d = d_rows.detach().to(device=plan.device, dtype=torch.complex128).contiguous()
+        d = d_rows.detach().to(device=plan.device, dtype=plan.data_dtype).contiguous()
         vl = vel.detach().to(device=plan.device, dtype=torch.float64).contiguous()
         g64, _ = plan.green(vl, want32=False)
         gram, rhs, trace = plan.assemble(g64, None, d, "fp64")

@@ -27,7 +27,7 @@
 namespace edt {
 
 size_t adjoint_lds_bytes(int nz);
-hipError_t launch_bsum(const edt_plan* p, const zd* d_rows, zd* ub, hipStream_t st, zd* ubw = nullptr,
+hipError_t launch_bsum(const edt_plan* p, const void* d_rows, zd* ub, hipStream_t st, zd* ubw = nullptr,
                        float4* ub32 = nullptr);
 
 // ------------------------------------------------------------ 1. pairs ---
@@ -90,13 +90,15 @@ __global__ __launch_bounds__(256) void adj_pair_kernel(const double* __restrict_
 
 // ------------------------------------------------------------- 2. rows ---
 // One wave per unique row: A x+-, A y+- (sums over depth), e+- and the data
-// gradient of every data row the unique row stands for.
+// gradient of every data row the unique row stands for (in the plan's data
+// type).
+template <class D>
 __global__ __launch_bounds__(256) void adj_rows_kernel(
     const uint32_t* __restrict__ urows, const int32_t* __restrict__ urow_pair,
     const int32_t* __restrict__ umem_off, const int32_t* __restrict__ umem, const zd* __restrict__ g64,
     const double* __restrict__ freq, double eps, double dz, int ncls, int nz, int64_t U,
     const zd* __restrict__ ub, const double* __restrict__ x, const double* __restrict__ y,
-    zd* __restrict__ rowsc, zd* __restrict__ grad_d) {
+    zd* __restrict__ rowsc, D* __restrict__ grad_d) {
     const int lane = threadIdx.x & 63;
     const int64_t r = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (r >= U) return;
@@ -137,8 +139,8 @@ __global__ __launch_bounds__(256) void adj_rows_kernel(
         const zd gd0 = 0.5 * ayp + ih, gd1 = 0.5 * ayp - ih;
         for (int k = umem_off[r] + lane; k < umem_off[r + 1]; k += 64) {
             const int64_t dr = umem[k];
-            grad_d[2 * dr] = gd0;
-            grad_d[2 * dr + 1] = gd1;
+            store_datum(grad_d, 2 * dr, gd0);
+            store_datum(grad_d, 2 * dr + 1, gd1);
         }
     }
 }
@@ -426,9 +428,9 @@ static void launch_table(const edt_plan* p, const double* vel, const zd* g64, co
                        dptr<const int32_t>(p, p->lay.tab_ent), g64, x, y, dl, rowsc, gbar, vpart);
 }
 
-hipError_t launch_adjoint(const edt_plan* p, const double* vel, const zd* g64, const zd* d_rows,
+hipError_t launch_adjoint(const edt_plan* p, const double* vel, const zd* g64, const void* d_rows,
                           const double* chol, const double* trace, const double* x, double lambda_rel,
-                          const zd* grad_v, zd* grad_d, double* grad_lambda, double* grad_vel,
+                          const zd* grad_v, void* grad_d, double* grad_lambda, double* grad_vel,
                           unsigned char* work, hipStream_t st) {
     const WorkLayout wl = work_layout(p);
     zd* ub = reinterpret_cast<zd*>(work + wl.ub);
@@ -446,11 +448,19 @@ hipError_t launch_adjoint(const edt_plan* p, const double* vel, const zd* g64, c
                        dptr<const int32_t>(p, p->lay.pair_u), p->nz, grad_v, y, dl, glam_part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (p->n_urows) {
-        hipLaunchKernelGGL(adj_rows_kernel, dim3(unsigned((p->n_urows + 3) / 4)), dim3(256), 0, st,
-                           dptr<const uint32_t>(p, p->lay.urows), dptr<const int32_t>(p, p->lay.urow_pair),
-                           dptr<const int32_t>(p, p->lay.umem_off), dptr<const int32_t>(p, p->lay.umem), g64,
-                           dptr<const double>(p, p->lay.freq), p->eps, p->dz, p->n_cls, p->nz, p->n_urows,
-                           ub, x, y, rowsc, grad_d);
+        const dim3 grid(unsigned((p->n_urows + 3) / 4));
+        if (p->data_c64)
+            hipLaunchKernelGGL(adj_rows_kernel<float2>, grid, dim3(256), 0, st,
+                               dptr<const uint32_t>(p, p->lay.urows), dptr<const int32_t>(p, p->lay.urow_pair),
+                               dptr<const int32_t>(p, p->lay.umem_off), dptr<const int32_t>(p, p->lay.umem), g64,
+                               dptr<const double>(p, p->lay.freq), p->eps, p->dz, p->n_cls, p->nz, p->n_urows,
+                               ub, x, y, rowsc, static_cast<float2*>(grad_d));
+        else
+            hipLaunchKernelGGL(adj_rows_kernel<zd>, grid, dim3(256), 0, st,
+                               dptr<const uint32_t>(p, p->lay.urows), dptr<const int32_t>(p, p->lay.urow_pair),
+                               dptr<const int32_t>(p, p->lay.umem_off), dptr<const int32_t>(p, p->lay.umem), g64,
+                               dptr<const double>(p, p->lay.freq), p->eps, p->dz, p->n_cls, p->nz, p->n_urows,
+                               ub, x, y, rowsc, static_cast<zd*>(grad_d));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (grad_vel) {

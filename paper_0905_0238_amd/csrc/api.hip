@@ -22,11 +22,11 @@ hipError_t launch_gram_reduce(const edt_plan* p, edt_precision prec, const void*
                               hipStream_t st, const int32_t* only = nullptr);
 hipError_t launch_rhs_reduce(const edt_plan* p, const double* rpart, double* rhs, double* trace,
                              hipStream_t st, const int32_t* only = nullptr);
-hipError_t launch_bsum(const edt_plan* p, const zd* d_rows, zd* ub, hipStream_t st, zd* ubw = nullptr,
+hipError_t launch_bsum(const edt_plan* p, const void* d_rows, zd* ub, hipStream_t st, zd* ubw = nullptr,
                        float4* ub32 = nullptr);
 hipError_t launch_resid(const edt_plan* p, const zd* g64, const zd* ubw, const double* x,
                         const int32_t* conv, double* rpart, hipStream_t st, const int32_t* active);
-hipError_t launch_forward(const edt_plan* p, const zd* g64, const zd* v, zd* d_rows, hipStream_t st);
+hipError_t launch_forward(const edt_plan* p, const zd* g64, const zd* v, void* d_rows, hipStream_t st);
 hipError_t launch_chol(const edt_plan* p, double* gram, const double* trace, const double* rhs,
                        double lambda_rel, double* lam, double* dinv, double* x, int32_t* info,
                        int32_t* conv, int32_t* steps, hipStream_t st, int only_failed, int exact,
@@ -37,9 +37,9 @@ hipError_t launch_pcg_update(const edt_plan* p, const double* gram, const double
 hipError_t launch_reset_counters(int32_t* c, int n, hipStream_t st);
 hipError_t launch_recombine(const edt_plan* p, const double* x, int refine, const int32_t* conv,
                             int32_t* info, zd* v, hipStream_t st);
-hipError_t launch_adjoint(const edt_plan* p, const double* vel, const zd* g64, const zd* d_rows,
+hipError_t launch_adjoint(const edt_plan* p, const double* vel, const zd* g64, const void* d_rows,
                           const double* chol, const double* trace, const double* x, double lambda_rel,
-                          const zd* grad_v, zd* grad_d, double* grad_lambda, double* grad_vel,
+                          const zd* grad_v, void* grad_d, double* grad_lambda, double* grad_vel,
                           unsigned char* work, hipStream_t st);
 hipError_t launch_tsvd_init(const edt_plan* p, const double* gram, double tol_rel, unsigned char* tw,
                             int32_t* iters, hipStream_t st);
@@ -49,7 +49,7 @@ void tsvd_step_scales(double l0, int n, double* a);
 hipError_t launch_tsvd_final(const edt_plan* p, double* gram, const double* rhs, unsigned char* tw,
                              const int32_t* iters, hipStream_t st);
 hipError_t launch_shots_fft(const edt_plan* p, zd* shots, hipStream_t st);
-hipError_t launch_shots_pack(const edt_plan* p, const zd* F, zd* d_rows, hipStream_t st);
+hipError_t launch_shots_pack(const edt_plan* p, const zd* F, void* d_rows, hipStream_t st);
 hipError_t launch_model(const edt_plan* p, zd* v, double* model, hipStream_t st);
 size_t aperture_work_bytes(const edt_plan* p);
 hipError_t launch_aperture_gram(const edt_plan* p, const zd* g64, double b_max, double* gram, double* trace,
@@ -188,7 +188,7 @@ edt_status edt_green(const edt_plan* p, const double* vel_dev, edt_c128* g64, ed
 }
 
 edt_status edt_assemble(const edt_plan* p, const edt_c128* g64, const edt_c64* g32,
-                        const edt_c128* d_rows, edt_precision prec, double* gram, double* rhs,
+                        const void* d_rows, edt_precision prec, double* gram, double* rhs,
                         double* trace, void* work, hipStream_t stream) {
     edt_status s = check_plan(p);
     if (s != EDT_OK) return s;
@@ -213,7 +213,7 @@ edt_status edt_assemble(const edt_plan* p, const edt_c128* g64, const edt_c64* g
     const zd* G64 = reinterpret_cast<const zd*>(g64);
     // conj(W) B in FP64 for every precision: the FP64 Gram reads it, and the
     // data sweep of a refining edt_solve can reuse it
-    EDT_TRY(launch_bsum(p, reinterpret_cast<const zd*>(d_rows), ub, stream, ubw, f64 ? nullptr : ub32),
+    EDT_TRY(launch_bsum(p, d_rows, ub, stream, ubw, f64 ? nullptr : ub32),
             "bsum");
     // one pass over the rows gives the Gram partials and the right-hand side
     // and trace partials of every item
@@ -313,7 +313,7 @@ size_t compact_solve_scratch(const edt_plan* p, bool refine, bool escalate, unsi
     return off;
 }
 
-edt_status check_solve_args(const edt_plan* p, const edt_c128* g64, const edt_c128* d_rows, double* gram,
+edt_status check_solve_args(const edt_plan* p, const edt_c128* g64, const void* d_rows, double* gram,
                             const double* rhs, const double* trace, double lambda_rel, const edt_solve_opts* opts,
                             double* x, edt_c128* v_out, int32_t* info) {
     edt_status s = check_plan(p);
@@ -335,7 +335,7 @@ edt_status check_solve_args(const edt_plan* p, const edt_c128* g64, const edt_c1
 }
 
 // The solve path shared by edt_solve and edt_solve_static (arguments checked).
-edt_status solve_impl(const edt_plan* p, const edt_c128* g64, const edt_c128* d_rows, double* gram,
+edt_status solve_impl(const edt_plan* p, const edt_c128* g64, const void* d_rows, double* gram,
                       const double* rhs, const double* trace, double lambda_rel, const edt_solve_opts* opts,
                       double* x, edt_c128* v_out, int32_t* info, int32_t* steps, const SolveScratch& ws,
                       hipStream_t stream) {
@@ -353,7 +353,7 @@ edt_status solve_impl(const edt_plan* p, const edt_c128* g64, const edt_c128* d_
         // the summed data, conj(W) B per unique row, unless the caller states
         // that edt_assemble left them in work
         if (!opts->data_summed)
-            EDT_TRY(launch_bsum(p, reinterpret_cast<const zd*>(d_rows), ws.ub, stream, ws.ubw), "bsum");
+            EDT_TRY(launch_bsum(p, d_rows, ws.ub, stream, ws.ubw), "bsum");
         if (opts->escalate) {
             // pairs whose factorisation failed (info > 0): FP64 Gram, rhs and
             // trace from the rows, and a second factorisation; every launch
@@ -419,7 +419,7 @@ edt_status static_scratch(unsigned char** out) {
 
 extern "C" {
 
-edt_status edt_solve(const edt_plan* p, const edt_c128* g64, const edt_c128* d_rows, double* gram,
+edt_status edt_solve(const edt_plan* p, const edt_c128* g64, const void* d_rows, double* gram,
                      const double* rhs, const double* trace, double lambda_rel,
                      const edt_solve_opts* opts, double* x, edt_c128* v_out, int32_t* info,
                      int32_t* steps, void* work, hipStream_t stream) {
@@ -433,7 +433,7 @@ edt_status edt_solve(const edt_plan* p, const edt_c128* g64, const edt_c128* d_r
                       scratch_from_work(p, work), stream);
 }
 
-edt_status edt_solve_static(const edt_plan* p, const edt_c128* g64, const edt_c128* d_rows, double* gram,
+edt_status edt_solve_static(const edt_plan* p, const edt_c128* g64, const void* d_rows, double* gram,
                             const double* rhs, const double* trace, double lambda_rel,
                             const edt_solve_opts* opts, double* x, edt_c128* v_out, int32_t* info,
                             int32_t* steps, hipStream_t stream) {
@@ -561,7 +561,7 @@ edt_status edt_shots_fft(const edt_plan* p, edt_c128* shots, hipStream_t stream)
     return EDT_OK;
 }
 
-edt_status edt_shots_pack(const edt_plan* p, const edt_c128* spectrum, edt_c128* d_rows, hipStream_t stream) {
+edt_status edt_shots_pack(const edt_plan* p, const edt_c128* spectrum, void* d_rows, hipStream_t stream) {
     edt_status s = check_plan(p);
     if (s != EDT_OK) return s;
     if (!spectrum || !d_rows) {
@@ -572,7 +572,7 @@ edt_status edt_shots_pack(const edt_plan* p, const edt_c128* spectrum, edt_c128*
         set_error("shot records of the 2D line survey only");
         return EDT_EINVAL;
     }
-    EDT_TRY(launch_shots_pack(p, reinterpret_cast<const zd*>(spectrum), reinterpret_cast<zd*>(d_rows), stream),
+    EDT_TRY(launch_shots_pack(p, reinterpret_cast<const zd*>(spectrum), d_rows, stream),
             "shots pack");
     return EDT_OK;
 }
@@ -628,7 +628,7 @@ edt_status edt_model(const edt_plan* p, edt_c128* v_tilde, double* model, hipStr
     return EDT_OK;
 }
 
-edt_status edt_forward(const edt_plan* p, const edt_c128* g64, const edt_c128* v_in, edt_c128* d_rows,
+edt_status edt_forward(const edt_plan* p, const edt_c128* g64, const edt_c128* v_in, void* d_rows,
                        hipStream_t stream) {
     edt_status s = check_plan(p);
     if (s != EDT_OK) return s;
@@ -636,15 +636,14 @@ edt_status edt_forward(const edt_plan* p, const edt_c128* g64, const edt_c128* v
         set_error("missing argument");
         return EDT_EINVAL;
     }
-    EDT_TRY(launch_forward(p, reinterpret_cast<const zd*>(g64), reinterpret_cast<const zd*>(v_in),
-                           reinterpret_cast<zd*>(d_rows), stream),
+    EDT_TRY(launch_forward(p, reinterpret_cast<const zd*>(g64), reinterpret_cast<const zd*>(v_in), d_rows, stream),
             "forward");
     return EDT_OK;
 }
 
 edt_status edt_adjoint(const edt_plan* p, const double* vel_dev, const edt_c128* g64,
-                       const edt_c128* d_rows, const double* chol, const double* trace, const double* x,
-                       double lambda_rel, const edt_c128* grad_v, edt_c128* grad_d, double* grad_lambda,
+                       const void* d_rows, const double* chol, const double* trace, const double* x,
+                       double lambda_rel, const edt_c128* grad_v, void* grad_d, double* grad_lambda,
                        double* grad_vel, void* work, hipStream_t stream) {
     edt_status s = check_plan(p);
     if (s != EDT_OK) return s;
@@ -656,9 +655,9 @@ edt_status edt_adjoint(const edt_plan* p, const double* vel_dev, const edt_c128*
         set_error("the adjoint supports nz <= 256");
         return EDT_EINVAL;
     }
-    EDT_TRY(launch_adjoint(p, vel_dev, reinterpret_cast<const zd*>(g64), reinterpret_cast<const zd*>(d_rows),
+    EDT_TRY(launch_adjoint(p, vel_dev, reinterpret_cast<const zd*>(g64), d_rows,
                            chol, trace, x, lambda_rel, reinterpret_cast<const zd*>(grad_v),
-                           reinterpret_cast<zd*>(grad_d), grad_lambda, grad_vel,
+                           grad_d, grad_lambda, grad_vel,
                            static_cast<unsigned char*>(work), stream),
             "adjoint");
     return EDT_OK;

@@ -52,6 +52,18 @@ __device__ __forceinline__ zd zsqrt(zd a) {
 
 constexpr double kTwoPiD = 2.0 * 3.141592653589793;
 
+// Data rows are stored in complex128 or complex64 (the plan's data type);
+// every kernel reads and forms them in FP64.
+__device__ __forceinline__ zd load_datum(const zd* d, int64_t i) { return d[i]; }
+__device__ __forceinline__ zd load_datum(const float2* d, int64_t i) {
+    const float2 v = d[i];
+    return zd{double(v.x), double(v.y)};
+}
+__device__ __forceinline__ void store_datum(zd* d, int64_t i, zd v) { d[i] = v; }
+__device__ __forceinline__ void store_datum(float2* d, int64_t i, zd v) {
+    d[i] = make_float2(float(v.x), float(v.y));
+}
+
 // Complex angular frequency w = 2 pi f + i eps.
 __device__ __forceinline__ zd omega_of(double f, double eps) { return zd{kTwoPiD * f, eps}; }
 

@@ -82,6 +82,7 @@ struct edt_plan {
     std::vector<int32_t> tab_ent;        // [2 * 2U]
     // work items
     int chunk_rows;
+    int data_c64 = 0;                    // data rows in complex64 (else complex128)
     int gram_band;                       // frequencies per Gram band
     int resid_group = 2;                 // frequencies per residual work item
     std::vector<edt::Item> items;        // Gram items (pair, frequency band), pair-major
@@ -155,5 +156,7 @@ struct TsvdLayout {
 };
 TsvdLayout tsvd_layout(const edt_plan* p);
 size_t gram_part_bytes_per_item(const edt_plan* p);
+// Device bytes of one pass of the plan (edt_plan_info.resident_bytes).
+size_t resident_bytes(const edt_plan* p);
 
 }  // namespace edt

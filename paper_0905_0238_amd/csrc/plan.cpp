@@ -306,6 +306,18 @@ WorkLayout work_layout(const edt_plan* p) {
     return w;
 }
 
+size_t resident_bytes(const edt_plan* p) {
+    const size_t P = size_t(p->n_pairs), nz = size_t(p->nz);
+    const size_t datum = p->data_c64 ? 8 : 16;
+    size_t b = p->lay.total + work_layout(p).total;
+    b += size_t(p->n_rows) * 2 * datum;                  // d_rows
+    b += P * (nz * nz + 2 * nz + 1 + 2 * nz) * 8;        // gram, rhs, trace, x
+    b += P * 2 * 4;                                      // info, steps
+    b += size_t(p->n_km) * nz * 16;                      // v_out
+    b += size_t(p->n_freq) * size_t(p->n_cls) * nz * 24; // g64 and g32
+    return b;
+}
+
 }  // namespace edt
 
 namespace {
@@ -385,10 +397,16 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
     const int band_opt = opts ? opts->gram_band : 0;
     const int64_t pair_begin = opts ? opts->pair_begin : 0;
     const int64_t pair_end = opts && opts->pair_end > 0 ? opts->pair_end : INT64_MAX;
+    const int data_type = opts ? opts->data_type : EDT_DATA_C128;
+    const int rgroup_opt = opts ? opts->resid_group : 0;
+    const size_t hbm_budget = opts ? opts->hbm_budget : 0;
     if (!s || !l || !out) return fail(EDT_EINVAL, "null argument");
     *out = nullptr;
+    if (data_type != EDT_DATA_C128 && data_type != EDT_DATA_C64)
+        return fail(EDT_EINVAL, "data_type must be EDT_DATA_C128 or EDT_DATA_C64");
     if (chunk_rows < 0 || chunk_rows > kMaxChunk) return fail(EDT_EINVAL, "0 <= chunk_rows <= 2048");
     if (band_opt < 0) return fail(EDT_EINVAL, "gram_band >= 0");
+    if (rgroup_opt < 0) return fail(EDT_EINVAL, "resid_group >= 0");
     if (pair_begin < 0 || pair_begin > pair_end) return fail(EDT_EINVAL, "0 <= pair_begin <= pair_end");
     {
         const edt_status v = validate(s, l);
@@ -411,6 +429,7 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
         p->dz = s->dz;
         p->kappa = s->kappa;
         p->ctop = l->vel[0];
+        p->data_c64 = data_type == EDT_DATA_C64 ? 1 : 0;
         p->freq.assign(s->freq_hz, s->freq_hz + s->n_freq);
         if (l->n_layers > 1) p->zif.assign(l->zif, l->zif + l->n_layers - 1);
         const std::vector<double> kmax = kmax_of(s, p->ctop);
@@ -586,7 +605,8 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
         // from L2, and its partials are small (2 nz values), so its groups
         // stay narrow.
         const int64_t group_rows = int64_t(std::ceil(double(kMinResidRows) / std::max(per_pf, 1e-9)));
-        p->resid_group = int(std::max<int64_t>(kFreqGroup, std::min<int64_t>(p->n_freq, group_rows)));
+        p->resid_group = rgroup_opt > 0 ? std::min(rgroup_opt, p->n_freq)
+                                         : int(std::max<int64_t>(kFreqGroup, std::min<int64_t>(p->n_freq, group_rows)));
         std::vector<int32_t> rgroup;
         split_items(p, p->resid_group, kResidRows, p->ritems, p->pair_ritem, rgroup);
         p->rsched = xcd_schedule(p->ritems, rgroup);
@@ -643,6 +663,16 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
         put(L.pair_ritem, p->pair_ritem.data(), p->pair_ritem.size() * 4);
         put(L.grow, p->grow.data(), p->grow.size() * sizeof(edt::GRow));
         put(L.gsc, p->gsc.data(), p->gsc.size() * 8);
+        if (hbm_budget > 0) {
+            const size_t need = edt::resident_bytes(p);
+            if (need > hbm_budget) {
+                const int64_t pb = p->pair_begin, pe = p->pair_begin + p->n_pairs;
+                delete p;
+                return fail(EDT_ENOMEM, "pairs [" + std::to_string(pb) + ", " + std::to_string(pe) + ") need " +
+                                            std::to_string(need) + " device bytes, more than the budget of " +
+                                            std::to_string(hbm_budget));
+            }
+        }
     } catch (const std::bad_alloc&) {
         delete p;
         return fail(EDT_ENOMEM, "out of host memory while planning");
@@ -678,6 +708,8 @@ edt_status edt_plan_query(const edt_plan* p, edt_plan_info* o) {
     o->n_pairs_all = p->n_pairs_all;
     o->resid_group = p->resid_group;
     o->pair_begin = p->pair_begin;
+    o->data_type = p->data_c64 ? EDT_DATA_C64 : EDT_DATA_C128;
+    o->resident_bytes = edt::resident_bytes(p);
     return EDT_OK;
 }
 

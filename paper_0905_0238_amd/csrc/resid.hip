@@ -124,9 +124,10 @@ __device__ __forceinline__ void butterfly(double (&a)[NV], double (&out)[NV], in
 // side c = Re(A^H B) with A = W g g):
 //   ubw[u]  = conj(W) ub             (FP64 rows are built without W)
 //   ub32[u] = conj(W) / |W| ub, FP32 (FP32 rows already carry |W|)
+template <class D>
 __global__ __launch_bounds__(256) void bsum_kernel(const int32_t* __restrict__ umem_off,
                                                    const int32_t* __restrict__ umem,
-                                                   const zd* __restrict__ d_rows, int64_t U,
+                                                   const D* __restrict__ d_rows, int64_t U,
                                                    zd* __restrict__ ub, const uint32_t* __restrict__ urows,
                                                    const double* __restrict__ freq, double eps, double dz,
                                                    zd* __restrict__ ubw, float4* __restrict__ ub32) {
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(256) void bsum_kernel(const int32_t* __restrict__ u
     zd bp{0.0, 0.0}, bm{0.0, 0.0};
     for (int k = umem_off[u]; k < umem_off[u + 1]; ++k) {
         const int64_t r = umem[k];
-        const zd d0 = d_rows[2 * r], d1 = d_rows[2 * r + 1];
+        const zd d0 = load_datum(d_rows, 2 * r), d1 = load_datum(d_rows, 2 * r + 1);
         bp = bp + 0.5 * (d0 + d1);
         const zd df = d0 - d1;                    // (d0 - d1) / (2i) = -i (d0 - d1) / 2
         bm = bm + zd{0.5 * df.y, -0.5 * df.x};
@@ -278,7 +279,8 @@ __global__ __launch_bounds__(256, ZPL <= 4 ? 3 : 2) void resid_kernel(const Item
 }
 
 // Born forward map: for each unique row of an item, A.v[u] and A.v[-u],
-// scattered to every data row it stands for.
+// scattered to every data row it stands for (in the plan's data type).
+template <class D>
 __global__ __launch_bounds__(256) void forward_kernel(const uint32_t* __restrict__ urows,
                                                      const Item* __restrict__ items,
                                                      const int32_t* __restrict__ pair_u,
@@ -287,7 +289,7 @@ __global__ __launch_bounds__(256) void forward_kernel(const uint32_t* __restrict
                                                      const zd* __restrict__ g64,
                                                      const double* __restrict__ freq, double eps,
                                                      double dz, int ncls, int nz,
-                                                     const zd* __restrict__ v, zd* __restrict__ d_rows) {
+                                                     const zd* __restrict__ v, D* __restrict__ d_rows) {
     const Item it = items[blockIdx.x];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int u0 = pair_u[2 * it.pair], u1 = pair_u[2 * it.pair + 1];
@@ -313,21 +315,27 @@ __global__ __launch_bounds__(256) void forward_kernel(const uint32_t* __restrict
         const zd d0 = W * zd{a0, a1}, d1 = W * zd{a2, a3};
         for (int k = umem_off[r] + lane; k < umem_off[r + 1]; k += 64) {
             const int64_t dr = umem[k];
-            d_rows[2 * dr] = d0;
-            d_rows[2 * dr + 1] = d1;
+            store_datum(d_rows, 2 * dr, d0);
+            store_datum(d_rows, 2 * dr + 1, d1);
         }
     }
 }
 
 // ------------------------------------------------------------- launchers ---
-hipError_t launch_bsum(const edt_plan* p, const zd* d_rows, zd* ub, hipStream_t st, zd* ubw,
+hipError_t launch_bsum(const edt_plan* p, const void* d_rows, zd* ub, hipStream_t st, zd* ubw,
                        float4* ub32) {
     if (p->n_urows == 0) return hipSuccess;
     const unsigned blocks = unsigned((p->n_urows + 255) / 256);
-    hipLaunchKernelGGL(bsum_kernel, dim3(blocks), dim3(256), 0, st,
-                       dptr<const int32_t>(p, p->lay.umem_off), dptr<const int32_t>(p, p->lay.umem),
-                       d_rows, p->n_urows, ub, dptr<const uint32_t>(p, p->lay.urows),
-                       dptr<const double>(p, p->lay.freq), p->eps, p->dz, ubw, ub32);
+    if (p->data_c64)
+        hipLaunchKernelGGL(bsum_kernel<float2>, dim3(blocks), dim3(256), 0, st,
+                           dptr<const int32_t>(p, p->lay.umem_off), dptr<const int32_t>(p, p->lay.umem),
+                           static_cast<const float2*>(d_rows), p->n_urows, ub, dptr<const uint32_t>(p, p->lay.urows),
+                           dptr<const double>(p, p->lay.freq), p->eps, p->dz, ubw, ub32);
+    else
+        hipLaunchKernelGGL(bsum_kernel<zd>, dim3(blocks), dim3(256), 0, st,
+                           dptr<const int32_t>(p, p->lay.umem_off), dptr<const int32_t>(p, p->lay.umem),
+                           static_cast<const zd*>(d_rows), p->n_urows, ub, dptr<const uint32_t>(p, p->lay.urows),
+                           dptr<const double>(p, p->lay.freq), p->eps, p->dz, ubw, ub32);
     return hipGetLastError();
 }
 
@@ -372,13 +380,21 @@ hipError_t launch_resid(const edt_plan* p, const zd* g64, const zd* ubw, const d
     }
 }
 
-hipError_t launch_forward(const edt_plan* p, const zd* g64, const zd* v, zd* d_rows, hipStream_t st) {
+hipError_t launch_forward(const edt_plan* p, const zd* g64, const zd* v, void* d_rows, hipStream_t st) {
     const unsigned nit = unsigned(p->items.size());
     if (nit == 0) return hipSuccess;
-    hipLaunchKernelGGL(forward_kernel, dim3(nit), dim3(256), 0, st, dptr<const uint32_t>(p, p->lay.urows),
-                       dptr<const Item>(p, p->lay.items), dptr<const int32_t>(p, p->lay.pair_u),
-                       dptr<const int32_t>(p, p->lay.umem_off), dptr<const int32_t>(p, p->lay.umem), g64,
-                       dptr<const double>(p, p->lay.freq), p->eps, p->dz, p->n_cls, p->nz, v, d_rows);
+    if (p->data_c64)
+        hipLaunchKernelGGL(forward_kernel<float2>, dim3(nit), dim3(256), 0, st, dptr<const uint32_t>(p, p->lay.urows),
+                           dptr<const Item>(p, p->lay.items), dptr<const int32_t>(p, p->lay.pair_u),
+                           dptr<const int32_t>(p, p->lay.umem_off), dptr<const int32_t>(p, p->lay.umem), g64,
+                           dptr<const double>(p, p->lay.freq), p->eps, p->dz, p->n_cls, p->nz, v,
+                           static_cast<float2*>(d_rows));
+    else
+        hipLaunchKernelGGL(forward_kernel<zd>, dim3(nit), dim3(256), 0, st, dptr<const uint32_t>(p, p->lay.urows),
+                           dptr<const Item>(p, p->lay.items), dptr<const int32_t>(p, p->lay.pair_u),
+                           dptr<const int32_t>(p, p->lay.umem_off), dptr<const int32_t>(p, p->lay.umem), g64,
+                           dptr<const double>(p, p->lay.freq), p->eps, p->dz, p->n_cls, p->nz, v,
+                           static_cast<zd*>(d_rows));
     return hipGetLastError();
 }
 

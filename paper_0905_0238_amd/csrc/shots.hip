@@ -69,18 +69,19 @@ __global__ __launch_bounds__(256) void dft_lines_kernel(zd* __restrict__ data, i
 }
 
 // d_rows[r] = (F[f][a][b], F[f][-b][-a]) for the row's frequency f and key
-// (a, b): the datum at +k_m and its -k_m partner.
+// (a, b): the datum at +k_m and its -k_m partner (in the plan's data type).
+template <class D>
 __global__ __launch_bounds__(256) void rows_gather_kernel(const zd* __restrict__ F, const uint32_t* __restrict__ rows,
                                                           const int32_t* __restrict__ keys, int64_t n_rows, int N,
-                                                          zd* __restrict__ d_rows) {
+                                                          D* __restrict__ d_rows) {
     const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (r >= n_rows) return;
     const int64_t f = rows[2 * r];
     const int a = keys[2 * r], b = keys[2 * r + 1];
     const int a1 = b ? N - b : 0, b1 = a ? N - a : 0;
     const int64_t base = f * N * N;
-    d_rows[2 * r] = F[base + int64_t(a) * N + b];
-    d_rows[2 * r + 1] = F[base + int64_t(a1) * N + b1];
+    store_datum(d_rows, 2 * r, F[base + int64_t(a) * N + b]);
+    store_datum(d_rows, 2 * r + 1, F[base + int64_t(a1) * N + b1]);
 }
 
 __global__ __launch_bounds__(256) void real_part_kernel(const zd* __restrict__ v, int64_t n, double* __restrict__ out) {
@@ -140,11 +141,17 @@ hipError_t launch_shots_fft(const edt_plan* p, zd* shots, hipStream_t st) {
     return launch_lines(shots, N, p->n_freq, Lines{NN, 1, N, N}, -1.0, p->d_mid, st);        // along R
 }
 
-hipError_t launch_shots_pack(const edt_plan* p, const zd* F, zd* d_rows, hipStream_t st) {
+hipError_t launch_shots_pack(const edt_plan* p, const zd* F, void* d_rows, hipStream_t st) {
     if (p->n_rows == 0) return hipSuccess;
-    hipLaunchKernelGGL(rows_gather_kernel, dim3(unsigned((p->n_rows + 255) / 256)), dim3(256), 0, st, F,
-                       dptr<const uint32_t>(p, p->lay.rows), dptr<const int32_t>(p, p->lay.keys), p->n_rows,
-                       p->n_mid, d_rows);
+    const unsigned blocks = unsigned((p->n_rows + 255) / 256);
+    if (p->data_c64)
+        hipLaunchKernelGGL(rows_gather_kernel<float2>, dim3(blocks), dim3(256), 0, st, F,
+                           dptr<const uint32_t>(p, p->lay.rows), dptr<const int32_t>(p, p->lay.keys), p->n_rows,
+                           p->n_mid, static_cast<float2*>(d_rows));
+    else
+        hipLaunchKernelGGL(rows_gather_kernel<zd>, dim3(blocks), dim3(256), 0, st, F,
+                           dptr<const uint32_t>(p, p->lay.rows), dptr<const int32_t>(p, p->lay.keys), p->n_rows,
+                           p->n_mid, static_cast<zd*>(d_rows));
     return hipGetLastError();
 }
 

@@ -56,16 +56,24 @@ class Plan:
     kappa, vel (layer velocities; vel[0] fixes c_top for the evanescent cut)
     and zif (interface depths).  ``pairs = (begin, end)`` plans only that
     range of the survey's pairs (a batch); its Green's table is the survey's.
+    ``chunk_rows``, ``gram_band`` and ``resid_group`` shape the work items (0 =
+    the planner's default; see paper_0905_0238_amd.tune), ``data`` is the
+    storage of the data rows ("c128" or "c64") and ``hbm_budget`` (bytes, 0 =
+    none) makes the planner refuse a plan whose pass would not fit.
     """
 
     def __init__(self, survey, chunk_rows: int = 0, gram_band: int = 0, device: str = "cuda",
-                 pairs: tuple[int, int] | None = None):
+                 pairs: tuple[int, int] | None = None, data: str = "c128", hbm_budget: int = 0,
+                 resid_group: int = 0):
         L = _lib.load()
         self.device = torch.device(device)
         sv, ly, self._keep = _structs(survey)
         h = C.c_void_p()
         pb, pe = (0, 0) if pairs is None else (int(pairs[0]), int(pairs[1]))
-        opts = _lib.PlanOpts(int(chunk_rows), int(gram_band), pb, pe)
+        if data not in _lib.DATA_TYPES:
+            raise ValueError(f"data must be one of {sorted(_lib.DATA_TYPES)}")
+        opts = _lib.PlanOpts(int(chunk_rows), int(gram_band), pb, pe, _lib.DATA_TYPES[data], int(hbm_budget),
+                             int(resid_group))
         _lib.check(L.edt_plan_create(C.byref(sv), C.byref(ly), C.byref(opts), C.byref(h)),
                    "edt_plan_create")
         self._h = h
@@ -83,8 +91,19 @@ class Plan:
         self.n_rows = int(info.n_rows)
         self.n_layers = int(info.n_layers)
         self.table_shape = (int(info.n_freq), int(info.n_cls), int(info.nz))
+        self.data_dtype = torch.complex64 if data == "c64" else torch.complex128
         self._dev_plan = None
         self._work = None
+
+    def _rows(self, d, what="d_rows"):
+        """Check that d is a contiguous [n_rows, 2] tensor of the plan's data
+        type on its device (the kernels index it by the plan's rows)."""
+        shape_ok = tuple(d.shape) == (self.n_rows, 2) or (self.n_rows == 0 and d.numel() > 0)
+        if (d.dtype != self.data_dtype or not shape_ok or not d.is_contiguous()
+                or d.device.type != self.device.type):
+            raise ValueError(f"{what} must be a contiguous ({self.n_rows}, 2) {self.data_dtype} tensor on "
+                             f"{self.device}, got {tuple(d.shape)} {d.dtype} on {d.device}")
+        return d
 
     # ----------------------------------------------------------- host side --
     def rowmap(self):
@@ -161,6 +180,9 @@ class Plan:
     def _c128(self, *shape):
         return torch.empty(*shape, dtype=torch.complex128, device=self.device)
 
+    def _data_rows(self):
+        return torch.empty(self.n_rows, 2, dtype=self.data_dtype, device=self.device)
+
     def green(self, vel, want32: bool = True, out=None):
         """(g64, g32) tables of shape (n_freq, n_cls, nz)."""
         self.upload()
@@ -181,6 +203,7 @@ class Plan:
             trace = torch.empty(P, dtype=torch.float64, device=self.device)
         else:
             gram, rhs, trace = out
+        self._rows(d_rows)
         _lib.check(_lib.load().edt_assemble(self._h, _ptr(g64), _ptr(g32), _ptr(d_rows),
                                             _lib.PRECISIONS[prec], _ptr(gram), _ptr(rhs), _ptr(trace),
                                             _ptr(self._work), _stream()), "edt_assemble")
@@ -201,6 +224,8 @@ class Plan:
             steps = torch.zeros(P, dtype=torch.int32, device=self.device)
         else:
             x, v, info, steps = out
+        if refine:
+            self._rows(d_rows)
         opts = _lib.SolveOpts(1 if refine else 0, float(refine_tol), int(max_refine),
                               1 if (refine and escalate) else 0, 1 if data_summed else 0)
         _lib.check(_lib.load().edt_solve(self._h, _ptr(g64), _ptr(d_rows), _ptr(gram), _ptr(rhs), _ptr(trace),
@@ -222,6 +247,8 @@ class Plan:
             steps = torch.zeros(P, dtype=torch.int32, device=self.device)
         else:
             x, v, info, steps = out
+        if refine:
+            self._rows(d_rows)
         opts = _lib.SolveOpts(1 if refine else 0, float(refine_tol), int(max_refine),
                               1 if (refine and escalate) else 0, 0)
         _lib.check(_lib.load().edt_solve_static(self._h, _ptr(g64), _ptr(d_rows), _ptr(gram), _ptr(rhs),
@@ -285,9 +312,9 @@ class Plan:
         return shots
 
     def shots_pack(self, spectrum, out=None):
-        """d_rows[R, 2] (complex128) of this plan's rows from a shots_fft spectrum."""
+        """d_rows[R, 2] (the plan's data type) of this plan's rows from a shots_fft spectrum."""
         self.upload()
-        d = out if out is not None else self._c128(self.n_rows, 2)
+        d = self._rows(out) if out is not None else self._data_rows()
         _lib.check(_lib.load().edt_shots_pack(self._h, _ptr(spectrum), _ptr(d), _stream()), "edt_shots_pack")
         return d
 
@@ -324,9 +351,9 @@ class Plan:
         return gram, trace
 
     def forward(self, g64, v, out=None):
-        """Born data rows d_rows[R, 2] (complex128) of the model spectrum v[n_km, nz]."""
+        """Born data rows d_rows[R, 2] (the plan's data type) of the model spectrum v[n_km, nz]."""
         self.upload()
-        d = out if out is not None else self._c128(self.n_rows, 2)
+        d = self._rows(out) if out is not None else self._data_rows()
         v = v.to(device=self.device, dtype=torch.complex128).contiguous()
         _lib.check(_lib.load().edt_forward(self._h, _ptr(g64), _ptr(v), _ptr(d), _stream()), "edt_forward")
         return d
@@ -337,7 +364,8 @@ class Plan:
         self.upload()
         vel = vel.to(device=self.device, dtype=torch.float64).contiguous()
         grad_v = grad_v.to(device=self.device, dtype=torch.complex128).contiguous()
-        gd = self._c128(self.n_rows, 2) if want_d else None
+        self._rows(d_rows)
+        gd = self._data_rows() if want_d else None
         gl = torch.zeros(1, dtype=torch.float64, device=self.device) if want_lambda else None
         gvel = torch.zeros(self.n_layers, dtype=torch.float64, device=self.device) if want_vel else None
         _lib.check(_lib.load().edt_adjoint(self._h, _ptr(vel), _ptr(g64), _ptr(d_rows), _ptr(chol),

@@ -31,7 +31,7 @@ class Pipeline:
         P, nz = plan.n_pairs, plan.nz
         plan.upload()
         self.vel = vel.to(device=dev, dtype=torch.float64).contiguous().clone()
-        self.d = d_rows.to(device=dev, dtype=torch.complex128).contiguous().clone()
+        self.d = d_rows.to(device=dev, dtype=plan.data_dtype).contiguous().clone()
         self.G64 = torch.empty(*plan.table_shape, dtype=torch.complex128, device=dev)
         self.G32 = torch.empty(*plan.table_shape, dtype=torch.complex64, device=dev) if self.mixed else None
         self.gram = torch.zeros(P, nz, nz, dtype=torch.float64, device=dev)

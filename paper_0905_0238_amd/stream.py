@@ -10,7 +10,10 @@ sized for the largest batch.  The data rows of every batch stay resident.
 
 Batches are cut from the per-pair row counts (``pair_rows``) so that each
 holds at most ``batch_rows`` data rows and ``batch_pairs`` pairs; the plans of
-the batches are built on host threads (the planner releases the GIL).
+the batches are built on host threads (the planner releases the GIL).  With
+an HBM budget, the planner refuses a batch whose pass does not fit it, and the
+stream refuses a layout (all batches resident) that does not.  The data rows
+may be kept in complex64 (``data="c64"``), half the bytes of complex128.
 """
 from __future__ import annotations
 
@@ -50,7 +53,7 @@ class Stream:
 
     def __init__(self, survey, prec="fp16x3", lambda_rel=None, refine_tol=3e-6, max_refine=8,
                  batch_rows=100_000_000, batch_pairs=4096, chunk_rows=0, gram_band=0, device="cuda",
-                 threads=8, also=()):
+                 threads=8, also=(), data="c128", hbm_budget=0):
         self.s, self.prec = survey, prec
         self.lam = float(survey.lambda_rel if lambda_rel is None else lambda_rel)
         self.tol, self.maxr = float(refine_tol), int(max_refine)
@@ -59,11 +62,19 @@ class Stream:
         self.rows = pair_rows(survey)
         self.batches = cut_batches(self.rows, batch_rows, batch_pairs)
 
+        # every batch plan checks that one pass of it (its device plan,
+        # workspace, data and buffers, with the survey's tables and V~) fits
+        # the budget; the planner refuses one that does not (EDT_ENOMEM)
         def mk(r):
-            return Plan(survey, chunk_rows=chunk_rows, gram_band=gram_band, device=device, pairs=r)
+            return Plan(survey, chunk_rows=chunk_rows, gram_band=gram_band, device=device, pairs=r, data=data,
+                        hbm_budget=hbm_budget)
 
         with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
             self.plans = list(ex.map(mk, self.batches))
+        if hbm_budget:
+            need = self.planned_bytes()
+            if need > hbm_budget:
+                raise MemoryError(f"the stream needs {need} device bytes, more than the budget of {hbm_budget}")
         dev = torch.device(device)
         p0 = self.plans[0]
         nz = p0.nz
@@ -87,14 +98,31 @@ class Stream:
         self.d = [None] * len(self.plans)
         self.graphs = {}
 
+    def planned_bytes(self) -> int:
+        """Device bytes the stream will hold, from the plans alone: every
+        batch's device plan and data rows, one workspace and one Gram buffer
+        for the largest batch, the survey's tables, x, info, steps and V~."""
+        ps = self.plans
+        nz = ps[0].nz
+        datum = 8 if ps[0].data_dtype == torch.complex64 else 16
+        per_batch = sum(int(p.info["dev_plan_bytes"]) + p.n_rows * 2 * datum for p in ps)
+        work = max(int(p.info["work_bytes"]) for p in ps)
+        pmax = max(max(p.n_pairs for p in ps), 1)
+        gram = pmax * (nz * nz + 2 * nz + 1) * 8
+        n_pairs, n_km = int(ps[0].n_pairs_all), int(ps[0].n_km)
+        tables = int(ps[0].info["table_elems"]) * 24
+        outs = n_pairs * (2 * nz * 8 + 8) + n_km * nz * 16
+        return per_batch + work + gram + tables + outs
+
     def set_data(self, b: int, d_rows):
-        """Data rows of batch b ([rows of the batch, 2] complex128), kept resident."""
+        """Data rows of batch b ([rows of the batch, 2], converted to the plan's
+        data type), kept resident."""
         p = self.plans[b]
         if tuple(d_rows.shape) != (p.n_rows, 2):
             raise ValueError(f"batch {b} needs ({p.n_rows}, 2) data rows")
         if p.n_rows == 0:   # a batch of empty pairs still passes a valid pointer
-            d_rows = torch.zeros(1, 2, dtype=torch.complex128)
-        self.d[b] = d_rows.to(device=self.work.device, dtype=torch.complex128).contiguous()
+            d_rows = torch.zeros(1, 2, dtype=p.data_dtype)
+        self.d[b] = d_rows.to(device=self.work.device, dtype=p.data_dtype).contiguous()
 
     def step(self, prec=None):
         """One pass in precision ``prec`` (default: the stream's first)."""
