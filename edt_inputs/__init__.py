@@ -31,7 +31,7 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["Survey", "make_config", "make_custom", "staircase_layers",
+__all__ = ["Survey", "make_config", "make_custom", "make_lines", "staircase_layers",
            "vhat", "noise", "signed_index", "CONFIG_NAMES"]
 
 EPS_DEFAULT = 0.15  # imaginary part of the angular frequency, 1/s (Section 3.1)
@@ -65,8 +65,10 @@ class Survey:
     lambda_rel: float
     noise_rel: float             # noise modulus relative to max |d| per frequency
     seed: int
-    v_true: Optional[np.ndarray]  # 2D: (N, nz); 3D: (N, N, nz); real float64
+    v_true: Optional[np.ndarray]  # 2D: (N, nz); 3D: (N, N, nz); lines: (N, N_y, nz); real float64
     data_c64: bool = False       # data rows delivered as complex64
+    n_line: int = 0              # 3D line survey: number of parallel lines N_y (0: not a line survey)
+    d_line: float = 0.0          # 3D line survey: line spacing dy
 
     @property
     def n_layers(self) -> int:
@@ -78,6 +80,8 @@ class Survey:
 
     @property
     def n_km(self) -> int:
+        if self.n_line:
+            return self.n_mid * self.n_line
         return self.n_mid if self.dim == 2 else self.n_mid * self.n_mid
 
     @property
@@ -233,6 +237,25 @@ def make_square_experiment(*, depth=1500.0, two_layer=False, freqs=(1.0, 2.0, 3.
                   np.asarray(vel, np.float64), np.asarray(zif, np.float64), 0.0, 0.0, int(seed), v, False)
 
 
+def make_lines(*, Nx=16, dx=25.0, Ny=8, dy=50.0, nz=6, dz=20.0, freqs=(6.0, 11.0), vel=(1800.0, 2600.0),
+               zif=(45.0,), eps=EPS_DEFAULT, kappa=1.0, lambda_rel=1e-3, noise_rel=0.0, seed=0,
+               model="smooth", name="lines") -> Survey:
+    """A 3D survey of N_y parallel 2D lines (Section 2.2): along each line
+    N_x positions at dx, every source recorded by every receiver of its line;
+    lines dy apart, periodic in y.  Model V on the (N_x, N_y, nz) grid."""
+    rng = np.random.default_rng(seed)
+    shape = (Nx, Ny, nz)
+    if model == "smooth":
+        v = _smooth(rng, shape, (dx, dy, dz), ell=2.0 * max(dx, dz))
+    elif model == "zero":
+        v = np.zeros(shape)
+    else:
+        v = None
+    return Survey(name, 3, Nx, dx, 0, 0.0, np.asarray(freqs, dtype=np.float64), float(eps), nz, dz, dz / 2,
+                  float(kappa), np.asarray(vel, dtype=np.float64), np.asarray(zif, dtype=np.float64),
+                  float(lambda_rel), float(noise_rel), int(seed), v, False, int(Ny), float(dy))
+
+
 def vhat(s: Survey) -> np.ndarray:
     """Unnormalised horizontal DFT of the model, fftfreq order.
 
@@ -241,7 +264,7 @@ def vhat(s: Survey) -> np.ndarray:
     if s.dim == 2:
         return np.fft.fft(s.v_true, axis=0)
     vh = np.fft.fft2(s.v_true, axes=(0, 1))
-    return vh.reshape(s.n_mid * s.n_mid, s.nz)
+    return vh.reshape(s.n_km, s.nz)
 
 
 # ---------------------------------------------------------------- noise ----

@@ -28,6 +28,9 @@ aperture  finite aperture on the 2D line: the offset window as a discrete sinc
         over the receiver index, the windowed Gram Re(A^H S A) and its solve.
 shots   the transforms on either side: 2D shot records to the packed rows, and
         the solution spectrum V~ to the model V(x, z).
+lines3d the 3D survey of parallel 2D lines (Section 2.2): rows that sum, over
+        the line wavenumbers, products of Green's functions of 2D horizontal
+        wavevectors (the decoupled 3D equation's k_h'' integral), per (k_m, k_y).
 
 Every function is pinned by a test in ``tests/test_oracle_*.py`` against a
 closed form, an invariant, a library routine that solves the same problem a

@@ -19,7 +19,7 @@ import numpy as np
 
 from .green import green, omega
 
-__all__ = ["gper_2d", "born_2d"]
+__all__ = ["gper_2d", "born_2d", "gper_3d", "born_3d", "gper_rect", "born_lines"]
 
 
 def gper_2d(vel, zif, w, N, dx, z):
@@ -77,3 +77,35 @@ def born_3d(vel, zif, f_hz, eps, V, dx, z, dz):
         Gm = Gp[dxi[:, None, :, None], dxi[None, :, None, :], i].reshape(N * N, N * N)
         D += Gm @ (V[:, :, i].reshape(-1)[:, None] * Gm)
     return w * w * dx * dx * dz * D
+
+
+def gper_rect(vel, zif, w, Nx, dx, Ny, dy, z):
+    """G_per on an N_x x N_y periodic surface grid (spacings dx, dy): shape
+    (N_x, N_y, nz), index (x, y); G_per(x, y) = (1/(L_x L_y)) sum_q e^{i k.x} g(|k|)."""
+    Lx, Ly = Nx * dx, Ny * dy
+    kx = 2 * np.pi * np.fft.fftfreq(Nx, d=1.0 / Nx) / Lx
+    ky = 2 * np.pi * np.fft.fftfreq(Ny, d=1.0 / Ny) / Ly
+    KX, KY = np.meshgrid(kx, ky, indexing="ij")
+    kabs = np.hypot(KX, KY).ravel()
+    uk, inv = np.unique(kabs, return_inverse=True)
+    g = green(vel, zif, w, uk, z)[inv].reshape(Nx, Ny, -1)
+    return np.fft.ifft2(g, axes=(0, 1)) * (Nx * Ny) / (Lx * Ly)
+
+
+def born_lines(vel, zif, f_hz, eps, V, dx, dy, z, dz):
+    """3D survey of parallel lines (paper eq. Born3D): V on an (N_x, N_y, nz)
+    periodic grid, sources and receivers of line j at y_j, every source to
+    every receiver of its own line:
+        D[R, S, j] = w^2 dx dy dz sum_{n, m, i} G_per(x_R - x_n, y_j - y_m, z_i)
+                     V(x_n, y_m, z_i) G_per(x_n - x_S, y_m - y_j, z_i)."""
+    Nx, Ny, nz = V.shape
+    w = omega(f_hz, eps)
+    Gp = gper_rect(vel, zif, w, Nx, dx, Ny, dy, z)
+    ix, iy = np.arange(Nx), np.arange(Ny)
+    D = np.zeros((Nx, Nx, Ny), np.complex128)
+    for j in range(Ny):
+        for i in range(nz):
+            Gr = Gp[(ix[:, None, None] - ix[None, :, None]) % Nx, (j - iy[None, None, :]) % Ny, i]   # [R, n, m]
+            Gs = Gp[(ix[:, None, None] - ix[None, None, :]) % Nx, ((iy - j) % Ny)[None, :, None], i]  # [n, m, S]
+            D[:, :, j] += np.einsum("rnm,nm,nms->rs", Gr, V[:, :, i], Gs)
+    return w * w * dx * dy * dz * D

@@ -120,19 +120,21 @@ def normal_equations(A, d0, d1):
     return G, c, float(np.trace(G))
 
 
-def solve_pair(s, p, A, d0, d1, lambda_rel=None):
-    """x (2, nz), info, lambda, trace for one pair."""
+def solve_pair(s, p, A, d0, d1, lambda_rel=None, return_gram=False):
+    """x (2, nz), info, lambda, trace for one pair (and the Gram G if
+    return_gram)."""
     lam_rel = s.lambda_rel if lambda_rel is None else lambda_rel
     nz = s.nz
     if p.n_rows == 0:
-        return np.zeros((2, nz)), INFO_EMPTY, 0.0, 0.0
+        out = (np.zeros((2, nz)), INFO_EMPTY, 0.0, 0.0)
+        return out + (np.zeros((nz, nz)),) if return_gram else out
     G, c, tr = normal_equations(A, d0, d1)
     lam = lam_rel * tr / nz
     fac = scipy.linalg.cho_factor(G + lam * np.eye(nz), lower=True)
     x = scipy.linalg.cho_solve(fac, c.T).T
     if p.self_conjugate:
         x[1] = 0.0
-    return x, INFO_OK, lam, tr
+    return (x, INFO_OK, lam, tr, G) if return_gram else (x, INFO_OK, lam, tr)
 
 
 def solve(s, pl, data, tabs, lambda_rel=None, pairs=None):
