@@ -21,12 +21,17 @@ E = pytest.importorskip("paper_0905_0238_amd")
 
 
 def _sampled_case(cfg, n_sample, seed):
+    """A seeded sample of non-empty pairs, the largest pair always among them."""
     s = make_config(cfg)
-    pl = oracle_plan(s)
+    rows = E.pair_rows(s)
     rng = np.random.default_rng(seed)
-    nonempty = [i for i, q in enumerate(pl.pairs) if q.n_rows > 0]
-    pick = sorted(rng.choice(nonempty, size=n_sample, replace=False).tolist())
-    sub = [pl.pairs[i] for i in pick]
+    nonempty = np.flatnonzero(rows > 0)
+    pick = set(rng.choice(nonempty, size=n_sample - 1, replace=False).tolist())
+    pick.add(int(np.argmax(rows)))
+    pick = sorted(pick)
+    pl = oracle_plan(s, only=pick)
+    assert pl.index == pick
+    sub = pl.pairs
     tabs = gtables(s, pl, pairs=sub)
     clean = forward(s, pl, vhat(s), tabs, pairs=sub)
     data = add_noise(s, pl, clean, noise_scale(s, pl, clean, pairs=sub), pairs=sub)
@@ -53,14 +58,17 @@ def _errors(v, sub, xs):
     return np.sqrt(num / den), float(np.max(np.array(per) / np.maximum(norms, 1e-3 * norms.max())))
 
 
-@pytest.mark.parametrize("cfg,n_sample", [(2, 8), (4, 4)])
+@pytest.mark.parametrize("cfg,n_sample", [(2, 8), (4, 32)])
 def test_sampled_pairs_at_full_size(cfg, n_sample):
     s, pl, pick, sub, data, xs = _sampled_case(cfg, n_sample, seed=100 + cfg)
+    print(f"cfg{cfg}: {len(sub)} pairs, rows {min(q.n_rows for q in sub)}..{max(q.n_rows for q in sub)}", flush=True)
     p = E.Plan(s)
     m = p.rowmap()
     off = m["row_off"]
     # the library's pair order equals the oracle's (checked bit for bit on the CPU)
-    assert len(off) == len(pl.pairs) + 1
+    assert len(off) == len(E.pair_rows(s)) + 1
+    for i, q in zip(pick, sub):
+        assert off[i + 1] - off[i] == q.n_rows
     d = np.zeros((p.n_rows, 2), np.complex128)
     for i, (d0, d1) in zip(pick, data):
         d[off[i]:off[i + 1], 0] = d0
