@@ -432,40 +432,6 @@ struct UCfg {
     }
 };
 
-template <int NT, int W, bool F16>
-__device__ __forceinline__ void u_wave_mfma(f32x16 (&acc)[UCfg<NT>::TPW], const uint16_t* hi,
-                                            const uint16_t* lo, int lane) {
-    using C = UCfg<NT>;
-    typedef typename std::conditional<F16, f16x8, bf16x8>::type v8;
-    constexpr int t0 = C::t0(W), t1 = C::t1(W);
-    constexpr uint32_t need = t0 < t1 ? block_mask(t0, t1) : 0u;
-    v8 fh[NT], fl[NT];
-    const int roff = (lane & 31) * C::STR + (lane >> 5) * 8;
-#pragma unroll
-    for (int b = 0; b < NT; ++b) {
-        if (need & (1u << b)) {
-            fh[b] = *reinterpret_cast<const v8*>(hi + b * 32 * C::STR + roff);
-            fl[b] = *reinterpret_cast<const v8*>(lo + b * 32 * C::STR + roff);
-        }
-    }
-#pragma unroll
-    for (int m = 0; m < C::TPW; ++m) {
-        const int t = t0 + m;
-        if (t < t1) {
-            const int I = tri_I(t), J = tri_J(t);
-            if constexpr (F16) {
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fh[I], fh[J], acc[m], 0, 0, 0);
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fh[I], fl[J], acc[m], 0, 0, 0);
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fl[I], fh[J], acc[m], 0, 0, 0);
-            } else {
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh[I], fh[J], acc[m], 0, 0, 0);
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh[I], fl[J], acc[m], 0, 0, 0);
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fl[I], fh[J], acc[m], 0, 0, 0);
-            }
-        }
-    }
-}
-
 template <int NT, int W>
 __device__ __forceinline__ void u_store_tiles(const f32x16 (&acc)[UCfg<NT>::TPW], float* out, int lane,
                                               float scale, int bI0) {
@@ -491,30 +457,84 @@ struct RawHalf {
     float2 ga[4], gb[4];
 };
 
-// Diagonal split task (one super-block of NT <= 8 tiles from depth zI0):
-// thread t forms depth t % 256 of rows 4 (t / 256) .. +3 of every stage, so
-// a wave's row is uniform (its records are LDS broadcasts and its table base
-// a scalar); results as gram_split3_kernel<NT, 0, F16>.
-template <int NT, bool F16>
-__global__ __launch_bounds__(512, 1) void gram_split3u_kernel(const Item* __restrict__ items,
-                                                              const int32_t* __restrict__ sched,
-                                                              const GRow* __restrict__ grow,
-                                                              const float4* __restrict__ ub32,
-                                                              const float2* __restrict__ g32,
-                                                              const float* __restrict__ gmax, int nz, int zI0,
-                                                              int ntot, float* __restrict__ part,
-                                                              double* __restrict__ rpart, int max_rows) {
+// ------------------------------------ split, diagonal, per-wave schedule ---
+// The unified diagonal split task with each wave's code straight-line: the
+// kernel branches on the wave index once, outside the item loop, so that a
+// stage's MFMAs (from LDS), the table loads of a later stage and the VALU
+// forming the next stage sit in one basic block, and the scheduler is told to
+// interleave them (one MFMA, then a run of VALU, then a load), so the matrix
+// pipe and the VALU of a wave work at the same time instead of in turn.  The
+// products are issued product-major (every tile's hi.hi, then hi.lo, then
+// lo.hi), so consecutive MFMAs do not wait on one accumulator.  Results equal
+// the warp-specialised kernel's bit for bit (the same products accumulated
+// into each tile in the same order).
+template <int NT, int W, bool F16>
+__device__ __forceinline__ void w_wave_mfma(f32x16 (&acc)[UCfg<NT>::TPW], const uint16_t* hi, const uint16_t* lo,
+                                            int lane) {
+    using C = UCfg<NT>;
+    typedef typename std::conditional<F16, f16x8, bf16x8>::type v8;
+    constexpr int t0 = C::t0(W), t1 = C::t1(W);
+    constexpr uint32_t need = t0 < t1 ? block_mask(t0, t1) : 0u;
+    v8 fh[NT], fl[NT];
+    const int roff = (lane & 31) * C::STR + (lane >> 5) * 8;
+#pragma unroll
+    for (int b = 0; b < NT; ++b) {
+        if (need & (1u << b)) {
+            fh[b] = *reinterpret_cast<const v8*>(hi + b * 32 * C::STR + roff);
+            fl[b] = *reinterpret_cast<const v8*>(lo + b * 32 * C::STR + roff);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+#pragma unroll
+        for (int m = 0; m < C::TPW; ++m) {
+            const int t = t0 + m;
+            if (t < t1) {
+                const int I = tri_I(t), J = tri_J(t);
+                const v8 a = k == 2 ? fl[I] : fh[I];
+                const v8 b = k == 1 ? fl[J] : fh[J];
+                if constexpr (F16)
+                    acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc[m], 0, 0, 0);
+                else
+                    acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[m], 0, 0, 0);
+            }
+        }
+    }
+}
+
+// Blocks read by wave W's tiles (two 16-byte fragment reads each).
+template <int NT, int W>
+constexpr int w_frag_reads() {
+    constexpr int t0 = UCfg<NT>::t0(W), t1 = UCfg<NT>::t1(W);
+    constexpr uint32_t m = t0 < t1 ? block_mask(t0, t1) : 0u;
+    return 2 * __builtin_popcount(m);
+}
+
+// Scheduling of one stage of wave W: its fragment reads first, then each MFMA
+// followed by up to V VALU instructions and one vector-memory read.
+template <int NM, int NF, int V>
+__device__ __forceinline__ void w_interleave() {
+    __builtin_amdgcn_sched_group_barrier(0x100, NF, 0);
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, V, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+    }
+}
+
+template <int NT, int W, bool F16>
+__device__ __forceinline__ void split3w_wave(const Item& it, const GRow* __restrict__ grow,
+                                             const float4* __restrict__ ub32, const float2* __restrict__ g32,
+                                             const float* __restrict__ gmax, int nz, int zI0, int ntot,
+                                             float* __restrict__ part, double* __restrict__ rpart, int max_rows,
+                                             uint16_t (*sh)[2][UCfg<NT>::NZP * UCfg<NT>::STR], double* s_tr,
+                                             float* s_max, uint4* s_row) {
     using C = UCfg<NT>;
     constexpr int PF = 2;
     static_assert(PF + 1 <= kPadStages, "padding stages exceed the row LDS");
-    __shared__ __attribute__((aligned(16))) uint16_t sh[2][2][C::NZP * C::STR];
-    __shared__ double s_tr[8];
-    __shared__ float s_max[8];
-    extern __shared__ __attribute__((aligned(16))) uint4 s_row[];
-    const int32_t k = sched[blockIdx.x];
-    if (k < 0) return;   // hole in the XCD-aware schedule
-    const Item it = items[k];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    constexpr int NM = 3 * (C::t1(W) > C::t0(W) ? C::t1(W) - C::t0(W) : 0);
+    const int tid = threadIdx.x, lane = tid & 63;
     const int n = min(it.row_end - it.row_begin, max_rows);
     const int nst = (n + 7) >> 3;
     const int nsp = ((nst + 1 + PF - 1) / PF) * PF;   // + zero stages, a multiple of PF
@@ -529,7 +549,7 @@ __global__ __launch_bounds__(512, 1) void gram_split3u_kernel(const Item* __rest
         }
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-        if (lane == 0) s_max[wv] = mx;
+        if (lane == 0) s_max[W] = mx;
         __syncthreads();
         float m = s_max[0];
 #pragma unroll
@@ -537,9 +557,12 @@ __global__ __launch_bounds__(512, 1) void gram_split3u_kernel(const Item* __rest
         if (m > 0.0f && isfinite(m)) scale = ldexpf(1.0f, 14 - ilogbf(m) - 1);
     }
     const int z = tid & 255;
-    const int hf = __builtin_amdgcn_readfirstlane(tid >> 8);   // rows 4 hf .. 4 hf + 3 of a stage
+    constexpr int hf = W >> 2;   // rows 4 hf .. 4 hf + 3 of a stage
     const bool on = z < nzI;
     const uint32_t zc = uint32_t(zI0 + min(z, nzI - 1));   // clamped: loads are unconditional
+    // depths past nz form zeros through their scale (their LDS slots were
+    // zeroed above and must stay zero): no select or branch in the loop
+    const float lane_scale = on ? scale : 0.0f;
     if (z >= nzI && z < C::NZP) {   // depths past nz stay zero for the whole item
         const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
@@ -549,36 +572,50 @@ __global__ __launch_bounds__(512, 1) void gram_split3u_kernel(const Item* __rest
     }
     double cp = 0.0, cm = 0.0, tr = 0.0;   // per stage in FP32, then in FP64
     const uint32_t zoff = zc * uint32_t(sizeof(float2));   // byte offset of this lane's depth
-    auto load = [&](RawHalf& R, int s) {
+    // the row records of a stage (LDS broadcasts): the table offsets of the
+    // loads, and the scales and data of the row forming
+    auto read_off = [&](uint32_t (&o)[8], int s) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint4 a = s_row[2 * (8 * s + 4 * hf + j)];
-            const uint32_t o_r = __builtin_amdgcn_readfirstlane(a.x);
-            const uint32_t o_s = __builtin_amdgcn_readfirstlane(a.y);
-            R.ga[j] = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(g32 + o_r) + zoff);
-            R.gb[j] = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(g32 + o_s) + zoff);
+            o[2 * j] = __builtin_amdgcn_readfirstlane(a.x);
+            o[2 * j + 1] = __builtin_amdgcn_readfirstlane(a.y);
         }
     };
-    auto form = [&](const RawHalf& R, int buf, int s) {
+    auto read_rec = [&](uint4 (&ra)[4], uint4 (&rb)[4], int s) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            ra[j] = s_row[2 * (8 * s + 4 * hf + j)];
+            rb[j] = s_row[2 * (8 * s + 4 * hf + j) + 1];
+        }
+    };
+    auto load = [&](RawHalf& R, const uint32_t (&o)[8]) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            R.ga[j] = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(g32 + o[2 * j]) + zoff);
+            R.gb[j] = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(g32 + o[2 * j + 1]) + zoff);
+        }
+    };
+    auto form = [&](const RawHalf& R, const uint4 (&ra)[4], const uint4 (&rb)[4], int buf) {
         uint32_t h[4], l[4];
         float t = 0.0f, sp = 0.0f, sm = 0.0f;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const uint4 a = s_row[2 * (8 * s + 4 * hf + j)];
-            const uint4 b = s_row[2 * (8 * s + 4 * hf + j) + 1];
+            const uint4 a = ra[j];
+            const uint4 b = rb[j];
             const float sw = __uint_as_float(a.z), mt = __uint_as_float(a.w);
             const float px = R.ga[j].x * R.gb[j].x - R.ga[j].y * R.gb[j].y;
             const float py = R.ga[j].x * R.gb[j].y + R.ga[j].y * R.gb[j].x;
             sp += px * __uint_as_float(b.x) + py * __uint_as_float(b.y);
             sm += px * __uint_as_float(b.z) + py * __uint_as_float(b.w);
             t += mt * (px * px + py * py);
-            const float ss = F16 ? sw * scale : sw;
+            const float ss = sw * lane_scale;
             split_pack<F16>(ss * px, ss * py, h[j], l[j]);
         }
         tr += double(t);
         cp += double(sp);
         cm += double(sm);
-        if (on) {
+        if (z < C::NZP) {
             reinterpret_cast<uint4*>(sh[buf][0] + z * C::STR)[hf] = make_uint4(h[0], h[1], h[2], h[3]);
             reinterpret_cast<uint4*>(sh[buf][1] + z * C::STR)[hf] = make_uint4(l[0], l[1], l[2], l[3]);
         }
@@ -588,59 +625,51 @@ __global__ __launch_bounds__(512, 1) void gram_split3u_kernel(const Item* __rest
     for (int m = 0; m < C::TPW; ++m)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[m][v] = 0.0f;
-    auto compute = [&](int buf) {
-        const uint16_t* hi = sh[buf][0];
-        const uint16_t* lo = sh[buf][1];
-        switch (wv) {
-            case 0: u_wave_mfma<NT, 0, F16>(acc, hi, lo, lane); break;
-            case 1: u_wave_mfma<NT, 1, F16>(acc, hi, lo, lane); break;
-            case 2: u_wave_mfma<NT, 2, F16>(acc, hi, lo, lane); break;
-            case 3: u_wave_mfma<NT, 3, F16>(acc, hi, lo, lane); break;
-            case 4: u_wave_mfma<NT, 4, F16>(acc, hi, lo, lane); break;
-            case 5: u_wave_mfma<NT, 5, F16>(acc, hi, lo, lane); break;
-            case 6: u_wave_mfma<NT, 6, F16>(acc, hi, lo, lane); break;
-            default: u_wave_mfma<NT, 7, F16>(acc, hi, lo, lane); break;
-        }
-    };
     // stage k's raw values live in R[k % PF]; indices past the padded end are
     // clamped to its last (zero) stage
     RawHalf R[PF];
     __syncthreads();   // rows staged, padding depths zeroed
+    {
+        uint32_t o[8];
+        uint4 ra[4], rb[4];
 #pragma unroll
-    for (int q = 0; q < PF; ++q) load(R[q], q);
-    form(R[0], 0, 0);
+        for (int q = 0; q < PF; ++q) {
+            read_off(o, q);
+            load(R[q], o);
+        }
+        read_rec(ra, rb, 0);
+        form(R[0], ra, rb, 0);
+    }
     __syncthreads();
     for (int s = 0; s < nsp; s += PF) {
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
             const int t = s + q;
-            compute(t & 1);
-            load(R[q], min(t + PF, nsp - 1));
-            form(R[(q + 1) % PF], (t + 1) & 1, min(t + 1, nsp - 1));
+            // every LDS read of the stage first (records of the next rows,
+            // offsets of the loads two stages on, this stage's fragments),
+            // then the MFMAs interleaved with the loads and the row forming
+            uint4 ra[4], rb[4];
+            uint32_t o[8];
+            read_rec(ra, rb, min(t + 1, nsp - 1));
+            read_off(o, min(t + PF, nsp - 1));
+            w_wave_mfma<NT, W, F16>(acc, sh[t & 1][0], sh[t & 1][1], lane);
+            load(R[q], o);
+            form(R[(q + 1) % PF], ra, rb, (t + 1) & 1);
+            w_interleave<NM, w_frag_reads<NT, W>() + 12, 8>();
             __syncthreads();
         }
     }
     float* out = part + size_t(it.slot) * (ntot * (ntot + 1) / 2) * 1024;
     const float back = 1.0f / (scale * scale);
-    const int bI0 = zI0 / 32;
-    switch (wv) {
-        case 0: u_store_tiles<NT, 0>(acc, out, lane, back, bI0); break;
-        case 1: u_store_tiles<NT, 1>(acc, out, lane, back, bI0); break;
-        case 2: u_store_tiles<NT, 2>(acc, out, lane, back, bI0); break;
-        case 3: u_store_tiles<NT, 3>(acc, out, lane, back, bI0); break;
-        case 4: u_store_tiles<NT, 4>(acc, out, lane, back, bI0); break;
-        case 5: u_store_tiles<NT, 5>(acc, out, lane, back, bI0); break;
-        case 6: u_store_tiles<NT, 6>(acc, out, lane, back, bI0); break;
-        default: u_store_tiles<NT, 7>(acc, out, lane, back, bI0); break;
-    }
+    u_store_tiles<NT, W>(acc, out, lane, back, zI0 / 32);
     // the two row halves of depth z meet in LDS (the stage buffers are free)
     double* sc = reinterpret_cast<double*>(&sh[0][0][0]);
     if (hf == 1) {
         sc[z] = cp;
         sc[256 + z] = cm;
     }
-    const double t = wave_sum(on ? tr : 0.0);
-    if (lane == 0) s_tr[wv] = t;
+    const double tsum = wave_sum(on ? tr : 0.0);
+    if (lane == 0) s_tr[W] = tsum;
     __syncthreads();
     double* rp = rpart + size_t(it.slot) * rpart_width(nz);
     if (hf == 0 && on) {
@@ -650,6 +679,35 @@ __global__ __launch_bounds__(512, 1) void gram_split3u_kernel(const Item* __rest
     if (tid == 0)
         rp[2 * nz + zI0 / kSuperDepth] =
             ((s_tr[0] + s_tr[1]) + (s_tr[2] + s_tr[3])) + ((s_tr[4] + s_tr[5]) + (s_tr[6] + s_tr[7]));
+}
+
+template <int NT, bool F16>
+__global__ __launch_bounds__(512, 1) void gram_split3w_kernel(const Item* __restrict__ items,
+                                                              const int32_t* __restrict__ sched,
+                                                              const GRow* __restrict__ grow,
+                                                              const float4* __restrict__ ub32,
+                                                              const float2* __restrict__ g32,
+                                                              const float* __restrict__ gmax, int nz, int zI0,
+                                                              int ntot, float* __restrict__ part,
+                                                              double* __restrict__ rpart, int max_rows) {
+    using C = UCfg<NT>;
+    __shared__ __attribute__((aligned(16))) uint16_t sh[2][2][C::NZP * C::STR];
+    __shared__ double s_tr[8];
+    __shared__ float s_max[8];
+    extern __shared__ __attribute__((aligned(16))) uint4 s_row[];
+    const int32_t k = sched[blockIdx.x];
+    if (k < 0) return;   // hole in the XCD-aware schedule
+    const Item it = items[k];
+    switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+#define EDT_W(w)                                                                                              \
+    case w:                                                                                                   \
+        split3w_wave<NT, w, F16>(it, grow, ub32, g32, gmax, nz, zI0, ntot, part, rpart, max_rows, sh, s_tr, \
+                                 s_max, s_row);                                                               \
+        break;
+        EDT_W(0) EDT_W(1) EDT_W(2) EDT_W(3) EDT_W(4) EDT_W(5) EDT_W(6) EDT_W(7)
+#undef EDT_W
+        default: break;
+    }
 }
 
 // ------------------------------------------------------------------ FP32 ---
@@ -1140,6 +1198,7 @@ static bool split_unified() {
     return u;
 }
 
+
 // One Gram task kind (diagonal NTJ = 0 or rectangular) over every item.
 template <int NT, int NTJ>
 static hipError_t launch_gram_task(const edt_plan* p, edt_precision prec, const zd* g64,
@@ -1154,11 +1213,11 @@ static hipError_t launch_gram_task(const edt_plan* p, edt_precision prec, const 
     const unsigned grid = rd.gate ? std::min(nb, 512u) : nb;
     if ((prec == EDT_BF16X3 || prec == EDT_FP16X3) && NTJ == 0 && split_unified()) {
         if (prec == EDT_BF16X3)
-            hipLaunchKernelGGL((gram_split3u_kernel<NT, false>), dim3(nb), dim3(512), row_lds_bytes(p->chunk_rows),
+            hipLaunchKernelGGL((gram_split3w_kernel<NT, false>), dim3(nb), dim3(512), row_lds_bytes(p->chunk_rows),
                                st, items, sched, grow, rd.ub32, g32, rd.gmax, p->nz, zI0, ntot,
                                static_cast<float*>(part), rpart, p->chunk_rows);
         else
-            hipLaunchKernelGGL((gram_split3u_kernel<NT, true>), dim3(nb), dim3(512), row_lds_bytes(p->chunk_rows),
+            hipLaunchKernelGGL((gram_split3w_kernel<NT, true>), dim3(nb), dim3(512), row_lds_bytes(p->chunk_rows),
                                st, items, sched, grow, rd.ub32, g32, rd.gmax, p->nz, zI0, ntot,
                                static_cast<float*>(part), rpart, p->chunk_rows);
     } else if (prec == EDT_BF16X3)
@@ -1225,10 +1284,10 @@ static hipError_t configure_gram_task() {
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_split3_kernel<NT, NTJ, true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e == hipSuccess && NTJ == 0)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_split3u_kernel<NT, false>),
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_split3w_kernel<NT, false>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e == hipSuccess && NTJ == 0)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_split3u_kernel<NT, true>),
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_split3w_kernel<NT, true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e == hipSuccess && NTJ == 0)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_f32_kernel<NT>),
