@@ -90,6 +90,19 @@ typedef enum {
  * dim 3: areal survey, k_m on an n_mid x n_mid grid (spacing 2 pi/(n_mid d_mid)),
  *        k_h on an n_off x n_off grid with n_off*d_off == n_mid*d_mid/2, so
  *        k_r = (k_m + k_h)/2 and k_s = (k_m - k_h)/2 (eq. COV).
+ * dim 3 with n_line > 0: the survey of n_line parallel 2D lines of Section 2.2,
+ *        n_line <= 64 lines at spacing d_line (periodic in y), each with n_mid
+ *        positions at d_mid, every source recorded by every receiver of its
+ *        own line (n_off, d_off ignored).  A subproblem is a (k_m, k_y) pair,
+ *        flattened u = ux * n_line + c; its rows are (f, receiver index a),
+ *        source index b = ux - a, with value
+ *            (w^2 dz / L_y) sum_q g(|(k_a, k_q)|) g(|(k_b, k_{q-c})|),
+ *        the sum over the line wavenumbers q (the k_h'' integral of the
+ *        decoupled 3D equation, L_y = n_line d_line).  A term is kept iff both
+ *        |k| are within the cut below, a row iff a term is.  This survey is
+ *        assembled in FP64 and solved without refinement (edt_solve with
+ *        refine = 0, or edt_tsvd); edt_adjoint, edt_kz_restrict, edt_model and
+ *        the record calls refuse it.
  * Frequencies freq_hz[n_freq] are used simultaneously (Section 3.1); eps is the
  * imaginary part of w (Section 2.1; 0.15 1/s in Section 3.1).  Depths are
  * z_i = z0 + i*dz, i < nz.  A row is kept iff |k_r| and |k_s| are both
@@ -107,6 +120,8 @@ typedef struct {
     int nz;
     double z0, dz;
     double kappa;
+    int n_line;              /* dim 3: number of parallel lines (0: the areal survey) */
+    double d_line;           /* dim 3 with n_line > 0: line spacing, m */
 } edt_survey;
 
 /* Layered reference c0(z) (Section 2.1): layer 0 extends up to -infinity and
@@ -234,9 +249,11 @@ edt_status edt_plan_query(const edt_plan* plan, edt_plan_info* out);
 /*
  * Host copies of the plan (every pointer nullable; sizes from edt_plan_query):
  *   row_off[n_pairs+1]  first row of each pair
- *   rows[n_rows*3]      (f, class of |k_r|, class of |k_s|)
- *   keys[n_rows*2]      2D: fftfreq indices (a, b) of the +k_m datum, whose
- *                       -k_m partner is (-b, -a); 3D: (k_h index n, 0)
+ *   rows[n_rows*3]      (f, class of |k_r|, class of |k_s|); line survey:
+ *                       (f, class of (|a|, 0), class of (|b|, 0))
+ *   keys[n_rows*2]      2D and line survey: fftfreq indices (a, b) of the +k_m
+ *                       datum, whose -k_m partner is (-b, -a) (line survey: at
+ *                       -k_y); 3D areal: (k_h index n, 0)
  *   pair_km[n_pairs*2]  (u, index of -u); equal for a self-conjugate k_m
  *   cls_k[n_cls]        |k| of each class, rad/m
  */

@@ -21,7 +21,7 @@ class Survey(C.Structure):
     _fields_ = [("dim", C.c_int), ("n_mid", C.c_int), ("d_mid", C.c_double), ("n_off", C.c_int),
                 ("d_off", C.c_double), ("n_freq", C.c_int), ("freq_hz", C.POINTER(C.c_double)),
                 ("eps", C.c_double), ("nz", C.c_int), ("z0", C.c_double), ("dz", C.c_double),
-                ("kappa", C.c_double)]
+                ("kappa", C.c_double), ("n_line", C.c_int), ("d_line", C.c_double)]
 
 
 class Layers(C.Structure):

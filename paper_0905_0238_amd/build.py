@@ -19,7 +19,7 @@ OBJ_DIR = os.path.join(ROOT, "_build", "obj")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["plan.cpp", "green.hip", "gram.hip", "resid.hip", "chol.hip", "adjoint.hip", "tsvd.hip", "kz.hip", "shots.hip", "aperture.hip", "api.hip"]
+SOURCES = ["plan.cpp", "green.hip", "gram.hip", "resid.hip", "chol.hip", "adjoint.hip", "tsvd.hip", "kz.hip", "shots.hip", "aperture.hip", "lsurvey.hip", "api.hip"]
 
 COMMON = ["-std=c++17", "-O3", "-fPIC", "-I", os.path.join(ROOT, "include"), "-Wall",
           "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unknown-pragmas"]

@@ -212,6 +212,25 @@ __global__ __launch_bounds__(256) void ap_trace_kernel(const double* __restrict_
     if (tid == 0) trace[p] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
 }
 
+// The lower tiles of scale * Re(R_p^H R_p) for every pair's n_rows x nz complex
+// rows R_p (row-major, rows of pair p at R + p n_rows nz), written (first) or
+// added to gram[p]; the finite aperture's product, also used by the survey of
+// parallel lines on its materialised rows.
+hipError_t launch_rows_gram(const zd* R, int nz, int n_rows, double scale, int first, double* gram, int64_t P,
+                            hipStream_t st) {
+    if (P == 0) return hipSuccess;
+    const int nt = (nz + 63) / 64;
+    hipLaunchKernelGGL(ap_gram_kernel, dim3(xcd_pair_grid(P, nt * (nt + 1) / 2)), dim3(256), 0, st, R, nz, nt,
+                       n_rows, scale, first, gram, int(P));
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_trace(const double* gram, int nz, double* trace, int64_t P, hipStream_t st) {
+    if (P == 0) return hipSuccess;
+    hipLaunchKernelGGL(ap_trace_kernel, dim3(unsigned(P)), dim3(256), 0, st, gram, nz, trace);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------- launcher ---
 // Workspace: the kept offsets of one frequency (at most P N nz complex128),
 // the per-pair frequency ranges and the twiddle table.

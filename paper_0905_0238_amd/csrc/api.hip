@@ -58,6 +58,9 @@ hipError_t launch_kz_restrict(const edt_plan* p, double K, double* gram, double*
                               int32_t* n_keep, hipStream_t st);
 size_t chol_lds_bytes(int nz);
 hipError_t configure_kernels();
+hipError_t launch_line_assemble(const edt_plan* p, const zd* g64, const void* d_rows, double* gram, double* rhs,
+                                double* trace, unsigned char* work, hipStream_t st);
+hipError_t launch_line_forward(const edt_plan* p, const zd* g64, const zd* v, void* d_rows, hipStream_t st);
 
 Timer& timer_of(const edt_plan* p) {
     edt_plan* q = const_cast<edt_plan*>(p);
@@ -204,6 +207,18 @@ edt_status edt_assemble(const edt_plan* p, const edt_c128* g64, const edt_c64* g
         set_error("the FP32 Gram supports nz <= 256 (use FP64, BF16X3 or FP16X3)");
         return EDT_EINVAL;
     }
+    if (p->n_line) {
+        // the survey of parallel lines: rows are sums over the line
+        // wavenumbers, formed per frequency and multiplied in FP64
+        if (prec != EDT_FP64) {
+            set_error("the survey of parallel lines is assembled in FP64 only");
+            return EDT_EINVAL;
+        }
+        EDT_TRY(launch_line_assemble(p, reinterpret_cast<const zd*>(g64), d_rows, gram, rhs, trace,
+                                     static_cast<unsigned char*>(work), stream),
+                "line assemble");
+        return EDT_OK;
+    }
     const WorkLayout wl = work_layout(p);
     unsigned char* w = static_cast<unsigned char*>(work);
     zd* ub = reinterpret_cast<zd*>(w + wl.ub);
@@ -329,6 +344,10 @@ edt_status check_solve_args(const edt_plan* p, const edt_c128* g64, const void* 
     }
     if (refine && (opts->max_refine < 0 || opts->max_refine > kMaxRefine || !(opts->refine_tol > 0.0))) {
         set_error("refinement needs 0 <= max_refine <= " + std::to_string(kMaxRefine) + " and refine_tol > 0");
+        return EDT_EINVAL;
+    }
+    if (refine && p->n_line) {
+        set_error("the survey of parallel lines is solved without refinement (its Gram is FP64)");
         return EDT_EINVAL;
     }
     return EDT_OK;
@@ -532,6 +551,10 @@ edt_status edt_kz_restrict(const edt_plan* p, double k_disk, double* gram, doubl
         set_error("k_disk must be finite and >= 0");
         return EDT_EINVAL;
     }
+    if (p->n_line) {
+        set_error("the k_z restriction does not cover the survey of parallel lines");
+        return EDT_EINVAL;
+    }
     if (p->n_pairs == 0) return EDT_OK;   // an empty pair range
     if (!gram || !rhs || !tsvd_work) {
         set_error("missing argument");
@@ -620,6 +643,10 @@ edt_status edt_model(const edt_plan* p, edt_c128* v_tilde, double* model, hipStr
         set_error("missing argument");
         return EDT_EINVAL;
     }
+    if (p->n_line) {
+        set_error("the model transform does not cover the survey of parallel lines");
+        return EDT_EINVAL;
+    }
     if (p->n_mid > kMaxLine) {
         set_error("n_mid > " + std::to_string(kMaxLine) + " is not supported by the transform");
         return EDT_EINVAL;
@@ -635,6 +662,12 @@ edt_status edt_forward(const edt_plan* p, const edt_c128* g64, const edt_c128* v
     if (!g64 || !v_in || !d_rows) {
         set_error("missing argument");
         return EDT_EINVAL;
+    }
+    if (p->n_line) {
+        EDT_TRY(launch_line_forward(p, reinterpret_cast<const zd*>(g64), reinterpret_cast<const zd*>(v_in), d_rows,
+                                    stream),
+                "line forward");
+        return EDT_OK;
     }
     EDT_TRY(launch_forward(p, reinterpret_cast<const zd*>(g64), reinterpret_cast<const zd*>(v_in), d_rows, stream),
             "forward");
@@ -653,6 +686,10 @@ edt_status edt_adjoint(const edt_plan* p, const double* vel_dev, const edt_c128*
     }
     if (p->nz > kMaxAdjointDepth) {
         set_error("the adjoint supports nz <= 256");
+        return EDT_EINVAL;
+    }
+    if (p->n_line) {
+        set_error("the adjoint does not cover the survey of parallel lines");
         return EDT_EINVAL;
     }
     EDT_TRY(launch_adjoint(p, vel_dev, reinterpret_cast<const zd*>(g64), d_rows,

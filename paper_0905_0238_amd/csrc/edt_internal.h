@@ -28,7 +28,7 @@ struct GRow {
 struct DevLayout {
     size_t freq, zif, cls_k, row_off, pair_u, rows, keys, urow_off, urows, umem_off, umem,
         row_unique, urow_pair, tab_off, tab_ent, items, sched, pair_item, ritems, rsched, pair_ritem,
-        grow, gsc, total;
+        grow, gsc, lmask, lfr, lpair, total;
 };
 
 // Gram tasks split the depths into super-blocks of at most 256 (8 tiles of
@@ -54,6 +54,11 @@ struct edt_plan {
     // survey
     int dim, n_mid, n_off, n_freq, nz, n_layers;
     double d_mid, d_off, eps, z0, dz, kappa, ctop;
+    int n_line = 0;                      // 3D survey of parallel lines: number of lines (0: areal)
+    double d_line = 0.0;                 // line spacing
+    std::vector<uint64_t> lmask;         // line survey [R]: bit (q + n_line/2) set iff term q is kept
+    std::vector<int64_t> lfr;            // line survey [P][n_freq + 1]: first row of each frequency
+    std::vector<int32_t> lpair;          // line survey [R]: pair of each row
     std::vector<double> freq, zif;
     // |k| classes
     int n_cls;
@@ -140,6 +145,7 @@ struct WorkLayout {
     size_t adj_row;     // [U][4] complex128: e+, e-, A y+, A y-
     size_t adj_vel;     // [n_freq*n_cls][n_layers] per-entry velocity gradients
     size_t scal;        // [64] FP64 scalars
+    size_t lrows;       // line survey: [line_chunk][n_mid][nz] complex128 rows of one frequency
     size_t total;
 };
 WorkLayout work_layout(const edt_plan* p);
@@ -158,5 +164,7 @@ TsvdLayout tsvd_layout(const edt_plan* p);
 size_t gram_part_bytes_per_item(const edt_plan* p);
 // Device bytes of one pass of the plan (edt_plan_info.resident_bytes).
 size_t resident_bytes(const edt_plan* p);
+// Line survey: pairs whose rows of one frequency are formed at once.
+int64_t line_chunk(const edt_plan* p);
 
 }  // namespace edt

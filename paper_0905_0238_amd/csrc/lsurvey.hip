@@ -1,0 +1,202 @@
+// The 3D survey of parallel 2D lines (paper Section 2.2, eq. Born3D and the
+// decoupled 3D equation after it): per (k_m, k_y) pair, a row (f, receiver
+// index a) is the sum over the line wavenumbers q of products of Green's
+// functions of the 2D horizontal wavevectors (k_a, k_q) and (k_b, k_{q-c}),
+// weighted w^2 dz / L_y (the k_h'' integral on the periodic grid of lines).
+//
+// A row is a sum of up to n_line products, not one, so the rows of one
+// frequency are formed into HBM (a chunk of pairs at a time, every receiver
+// index a slot, zero where the row is cut) and the finite aperture's FP64
+// MFMA product accumulates Re(A^H A) over the frequencies; the right-hand
+// sides Re(A^H b+-) are accumulated from the same rows, and the trace is the
+// Gram's diagonal.  The rows' terms (which q are kept) come from the planner's
+// per-row masks, so no cut is decided here.
+
+#include "dev_common.h"
+
+namespace edt {
+
+__device__ __forceinline__ int signed_idx(int n, int N) { return n < (N + 1) / 2 ? n : n - N; }
+
+// Value of row r (receiver index a, source index b, term mask m) at depth z:
+// sum over the set bits of m, ascending q.
+__device__ __forceinline__ zd line_row_value(const zd* __restrict__ gf, int a, int b, uint64_t m, int qc, int Ny,
+                                             int nz, int z) {
+    const int ny2 = Ny / 2 + 1, ia = abs(a), ib = abs(b);
+    zd v{0.0, 0.0};
+    while (m) {
+        const int bit = __builtin_ctzll(m);
+        m &= m - 1;
+        const int q = bit - Ny / 2;
+        int pq = (q - qc) % Ny;
+        pq = signed_idx(pq < 0 ? pq + Ny : pq, Ny);
+        v = v + gf[size_t(ia * ny2 + abs(q)) * nz + z] * gf[size_t(ib * ny2 + abs(pq)) * nz + z];
+    }
+    return v;
+}
+
+// Rows of frequency f of the pairs p0 .. p0 + gridDim.x - 1: Rh[p - p0][slot][z]
+// with slot = a + Nx/2 the receiver index (zero where the pair has no row).
+// One block per pair; a slot map in LDS finds each slot's row.
+__global__ __launch_bounds__(256) void line_rows_kernel(const zd* __restrict__ g64, const int32_t* __restrict__ keys,
+                                                        const uint64_t* __restrict__ lmask,
+                                                        const int64_t* __restrict__ lfr,
+                                                        const int32_t* __restrict__ pair_u, int f, int n_freq,
+                                                        int n_cls, int Nx, int Ny, int nz, zd W, int64_t p0,
+                                                        zd* __restrict__ Rh) {
+    __shared__ int s_row[2048];
+    const int64_t p = p0 + blockIdx.x;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < Nx; i += 256) s_row[i] = -1;
+    __syncthreads();
+    const int64_t r0 = lfr[p * (n_freq + 1) + f], r1 = lfr[p * (n_freq + 1) + f + 1];
+    for (int64_t r = r0 + tid; r < r1; r += 256) s_row[signed_idx(keys[2 * r], Nx) + Nx / 2] = int(r - r0);
+    __syncthreads();
+    const int qc = signed_idx(pair_u[2 * p] % Ny, Ny);
+    const zd* gf = g64 + size_t(f) * n_cls * nz;
+    zd* out = Rh + size_t(blockIdx.x) * Nx * nz;
+    for (int e = tid; e < Nx * nz; e += 256) {
+        const int slot = e / nz, z = e % nz;
+        const int rr = s_row[slot];
+        zd v{0.0, 0.0};
+        if (rr >= 0) {
+            const int64_t r = r0 + rr;
+            v = W * line_row_value(gf, slot - Nx / 2, signed_idx(keys[2 * r + 1], Nx), lmask[r], qc, Ny, nz, z);
+        }
+        out[e] = v;
+    }
+}
+
+// rhs[p][0|1][z] (first: =, else +=) Re(sum over the rows of frequency f of
+// conj(A(z)) b+-), b+ = (d0 + d1)/2, b- = (d0 - d1)/(2i), from the formed rows.
+template <class D>
+__global__ __launch_bounds__(256) void line_rhs_kernel(const zd* __restrict__ Rh, const int32_t* __restrict__ keys,
+                                                       const int64_t* __restrict__ lfr, const D* __restrict__ d_rows,
+                                                       int f, int n_freq, int Nx, int nz, int64_t p0, int first,
+                                                       double* __restrict__ rhs) {
+    const int64_t p = p0 + blockIdx.x;
+    const int64_t r0 = lfr[p * (n_freq + 1) + f], r1 = lfr[p * (n_freq + 1) + f + 1];
+    const zd* R = Rh + size_t(blockIdx.x) * Nx * nz;
+    for (int z = threadIdx.x; z < nz; z += 256) {
+        double cp = 0.0, cm = 0.0;
+        for (int64_t r = r0; r < r1; ++r) {
+            const zd A = R[size_t(signed_idx(keys[2 * r], Nx) + Nx / 2) * nz + z];
+            const zd d0 = load_datum(d_rows, 2 * r), d1 = load_datum(d_rows, 2 * r + 1);
+            const zd bp = 0.5 * (d0 + d1);
+            const zd df = d0 - d1;
+            const zd bm{0.5 * df.y, -0.5 * df.x};
+            cp += A.x * bp.x + A.y * bp.y;
+            cm += A.x * bm.x + A.y * bm.y;
+        }
+        double* o = rhs + size_t(p) * 2 * nz;
+        o[z] = first ? cp : o[z] + cp;
+        o[nz + z] = first ? cm : o[nz + z] + cm;
+    }
+}
+
+// Born forward map of the line survey: d_rows[r] = (A_r . v[u], A_r . v[u_neg]);
+// one wave per row, lanes over depth.
+template <class D>
+__global__ __launch_bounds__(256) void line_forward_kernel(const zd* __restrict__ g64, const uint32_t* __restrict__ rows,
+                                                           const int32_t* __restrict__ keys,
+                                                           const uint64_t* __restrict__ lmask,
+                                                           const int32_t* __restrict__ lpair,
+                                                           const int32_t* __restrict__ pair_u,
+                                                           const double* __restrict__ freq, double eps, double scale,
+                                                           int n_cls, int Nx, int Ny, int nz, int64_t R,
+                                                           const zd* __restrict__ v, D* __restrict__ d_rows) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (r >= R) return;
+    const int f = int(rows[2 * r]);
+    const int p = lpair[r];
+    const int u0 = pair_u[2 * p], u1 = pair_u[2 * p + 1];
+    const int qc = signed_idx(u0 % Ny, Ny);
+    const zd* gf = g64 + size_t(f) * n_cls * nz;
+    const int a = signed_idx(keys[2 * r], Nx), b = signed_idx(keys[2 * r + 1], Nx);
+    const uint64_t m = lmask[r];
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    for (int z = lane; z < nz; z += 64) {
+        const zd A = line_row_value(gf, a, b, m, qc, Ny, nz, z);
+        const zd q0 = A * v[size_t(u0) * nz + z], q1 = A * v[size_t(u1) * nz + z];
+        s0 += q0.x;
+        s1 += q0.y;
+        s2 += q1.x;
+        s3 += q1.y;
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    s3 = wave_sum(s3);
+    if (lane == 0) {
+        const zd w = omega_of(freq[f], eps);
+        const zd W = scale * (w * w);
+        store_datum(d_rows, 2 * r, W * zd{s0, s1});
+        store_datum(d_rows, 2 * r + 1, W * zd{s2, s3});
+    }
+}
+
+hipError_t launch_rows_gram(const zd* R, int nz, int n_rows, double scale, int first, double* gram, int64_t P,
+                            hipStream_t st);
+hipError_t launch_gram_trace(const double* gram, int nz, double* trace, int64_t P, hipStream_t st);
+
+// FP64 Gram, right-hand sides and trace of a line survey, frequency by
+// frequency over chunks of pairs (the rows of one chunk and frequency live in
+// work at lrows).
+hipError_t launch_line_assemble(const edt_plan* p, const zd* g64, const void* d_rows, double* gram, double* rhs,
+                                double* trace, unsigned char* work, hipStream_t st) {
+    const int64_t P = p->n_pairs;
+    if (P == 0) return hipSuccess;
+    const WorkLayout wl = work_layout(p);
+    zd* Rh = reinterpret_cast<zd*>(work + wl.lrows);
+    const int64_t chunk = line_chunk(p);
+    const int Nx = p->n_mid, Ny = p->n_line, nz = p->nz;
+    const double Ly = double(Ny) * p->d_line;
+    for (int64_t p0 = 0; p0 < P; p0 += chunk) {
+        const int64_t np = std::min<int64_t>(chunk, P - p0);
+        for (int f = 0; f < p->n_freq; ++f) {
+            const double wr = kTwoPiD * p->freq[size_t(f)], wi = p->eps;
+            const zd W{p->dz * (wr * wr - wi * wi) / Ly, p->dz * (2.0 * wr * wi) / Ly};
+            hipLaunchKernelGGL(line_rows_kernel, dim3(unsigned(np)), dim3(256), 0, st, g64,
+                               dptr<const int32_t>(p, p->lay.keys), dptr<const uint64_t>(p, p->lay.lmask),
+                               dptr<const int64_t>(p, p->lay.lfr), dptr<const int32_t>(p, p->lay.pair_u), f,
+                               p->n_freq, p->n_cls, Nx, Ny, nz, W, p0, Rh);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            if ((e = launch_rows_gram(Rh, nz, Nx, 1.0, f == 0, gram + size_t(p0) * nz * nz, np, st)) != hipSuccess)
+                return e;
+            if (p->data_c64)
+                hipLaunchKernelGGL(line_rhs_kernel<float2>, dim3(unsigned(np)), dim3(256), 0, st, Rh,
+                                   dptr<const int32_t>(p, p->lay.keys), dptr<const int64_t>(p, p->lay.lfr),
+                                   static_cast<const float2*>(d_rows), f, p->n_freq, Nx, nz, p0, f == 0 ? 1 : 0, rhs);
+            else
+                hipLaunchKernelGGL(line_rhs_kernel<zd>, dim3(unsigned(np)), dim3(256), 0, st, Rh,
+                                   dptr<const int32_t>(p, p->lay.keys), dptr<const int64_t>(p, p->lay.lfr),
+                                   static_cast<const zd*>(d_rows), f, p->n_freq, Nx, nz, p0, f == 0 ? 1 : 0, rhs);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+    }
+    return launch_gram_trace(gram, nz, trace, P, st);
+}
+
+hipError_t launch_line_forward(const edt_plan* p, const zd* g64, const zd* v, void* d_rows, hipStream_t st) {
+    const int64_t R = p->n_rows;
+    if (R == 0) return hipSuccess;
+    const double scale = p->dz / (double(p->n_line) * p->d_line);
+    const dim3 grid(unsigned((R + 3) / 4));
+    if (p->data_c64)
+        hipLaunchKernelGGL(line_forward_kernel<float2>, grid, dim3(256), 0, st, g64, dptr<const uint32_t>(p, p->lay.rows),
+                           dptr<const int32_t>(p, p->lay.keys), dptr<const uint64_t>(p, p->lay.lmask),
+                           dptr<const int32_t>(p, p->lay.lpair), dptr<const int32_t>(p, p->lay.pair_u),
+                           dptr<const double>(p, p->lay.freq), p->eps, scale, p->n_cls, p->n_mid, p->n_line, p->nz,
+                           R, v, static_cast<float2*>(d_rows));
+    else
+        hipLaunchKernelGGL(line_forward_kernel<zd>, grid, dim3(256), 0, st, g64, dptr<const uint32_t>(p, p->lay.rows),
+                           dptr<const int32_t>(p, p->lay.keys), dptr<const uint64_t>(p, p->lay.lmask),
+                           dptr<const int32_t>(p, p->lay.lpair), dptr<const int32_t>(p, p->lay.pair_u),
+                           dptr<const double>(p, p->lay.freq), p->eps, scale, p->n_cls, p->n_mid, p->n_line, p->nz,
+                           R, v, static_cast<zd*>(d_rows));
+    return hipGetLastError();
+}
+
+}  // namespace edt

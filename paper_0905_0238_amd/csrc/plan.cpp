@@ -239,11 +239,74 @@ void rows_3d(edt_plan* p, const std::vector<double>& kmax, int64_t pb, int64_t p
     n_all = gp;
 }
 
+// 3D survey of parallel lines: pair (ux, c) with flattened k = ux N_y + c
+// (k <= its partner's); rows (f, a) with b = ux - a, kept iff a term q of the
+// line-wavenumber sum is: |(a dkx, q dky)| and |(b dkx, p dky)|, p = q - c
+// (signed, wrapped), both within the cut, compared as squared lengths written
+// (n dk)*(n dk) + (m dk')*(m dk').  Classes (|a|, |q|) -> |a| (N_y/2 + 1) + |q|.
+void rows_lines(edt_plan* p, const std::vector<double>& kmax, int64_t pb, int64_t pe,
+                std::vector<int64_t>& cls_r, std::vector<int64_t>& cls_s, int64_t& n_all,
+                std::vector<int64_t>* counts = nullptr) {
+    const int64_t Nx = p->n_mid, Ny = p->n_line, ny2 = Ny / 2 + 1;
+    const double dkx = kTwoPi / (double(Nx) * p->d_mid);
+    const double dky = kTwoPi / (double(Ny) * p->d_line);
+    p->n_km = Nx * Ny;
+    p->row_off.push_back(0);
+    int64_t gp = 0;
+    for (int64_t k = 0; k < Nx * Ny; ++k) {
+        const int64_t ux = k / Ny, c = k % Ny;
+        const int64_t kn = wrap(-ux, Nx) * Ny + wrap(-c, Ny);
+        if (kn < k) continue;
+        const bool mine = gp >= pb && gp < pe;
+        ++gp;
+        if (!mine && !counts) continue;
+        if (mine) {
+            p->pair_u.push_back(int32_t(k));
+            p->pair_u.push_back(int32_t(kn));
+        }
+        const int64_t qc = signed_of(c, Ny);
+        int64_t kept = 0;
+        for (int f = 0; f < p->n_freq; ++f) {
+            const double K2 = kmax[size_t(f)] * kmax[size_t(f)];
+            for (int64_t a = -(Nx / 2); a < Nx - Nx / 2; ++a) {
+                const int64_t b = signed_of(wrap(ux - a, Nx), Nx);
+                uint64_t m = 0;
+                for (int64_t q = -(Ny / 2); q < Ny - Ny / 2; ++q) {
+                    const int64_t pq = signed_of(wrap(q - qc, Ny), Ny);
+                    const double kr2 = (double(a) * dkx) * (double(a) * dkx) + (double(q) * dky) * (double(q) * dky);
+                    const double ks2 = (double(b) * dkx) * (double(b) * dkx) + (double(pq) * dky) * (double(pq) * dky);
+                    if (kr2 <= K2 && ks2 <= K2) m |= uint64_t(1) << uint64_t(q + Ny / 2);
+                }
+                if (!m) continue;
+                ++kept;
+                if (!mine) continue;
+                p->rows.push_back(uint32_t(f));
+                p->rows.push_back(0);
+                cls_r.push_back(std::llabs(a) * ny2);
+                cls_s.push_back(std::llabs(b) * ny2);
+                p->keys.push_back(int32_t(wrap(a, Nx)));
+                p->keys.push_back(int32_t(wrap(b, Nx)));
+                p->lmask.push_back(m);
+            }
+        }
+        if (mine) p->row_off.push_back(int64_t(cls_r.size()));
+        if (counts) counts->push_back(kept);
+    }
+    n_all = gp;
+}
+
 }  // namespace
 
 namespace edt {
 
 void set_error(const std::string& msg) { g_err = msg; }
+
+int64_t line_chunk(const edt_plan* p) {
+    if (!p->n_line || p->n_pairs == 0) return 0;
+    // rows of one frequency for at most 256 MiB of pairs at a time
+    const int64_t per = int64_t(p->n_mid) * p->nz * 16;
+    return std::max<int64_t>(1, std::min<int64_t>(p->n_pairs, (int64_t(256) << 20) / per));
+}
 
 size_t gram_part_bytes_per_item(const edt_plan* p) {
     const size_t nt = size_t((p->nz + 31) / 32);
@@ -302,6 +365,8 @@ WorkLayout work_layout(const edt_plan* p) {
     off = align256(off + size_t(p->n_freq) * size_t(p->n_cls) * size_t(p->n_layers) * sizeof(double));
     w.scal = off;
     off = align256(off + 64 * sizeof(double));
+    w.lrows = off;
+    off = align256(off + size_t(line_chunk(p)) * size_t(p->n_mid) * nz * 16);
     w.total = off;
     return w;
 }
@@ -329,7 +394,12 @@ edt_status validate(const edt_survey* s, const edt_layers* l) {
     if (s->n_freq < 1 || s->n_freq >= 65536 || !s->freq_hz) return fail(EDT_EINVAL, "1 <= n_freq < 65536");
     if (s->nz < 1 || s->nz > 1024) return fail(EDT_EINVAL, "1 <= nz <= 1024");
     if (!(s->dz > 0) || !(s->eps >= 0) || !(s->kappa > 0)) return fail(EDT_EINVAL, "dz > 0, eps >= 0, kappa > 0");
-    if (s->dim == 3) {
+    if (s->n_line != 0) {
+        if (s->dim != 3) return fail(EDT_EINVAL, "a survey of parallel lines has dim 3");
+        if (s->n_line < 1 || s->n_line > 64 || !(s->d_line > 0))
+            return fail(EDT_EINVAL, "line survey: 1 <= n_line <= 64 and d_line > 0");
+        if (s->n_mid > 2048) return fail(EDT_EINVAL, "line survey: n_mid <= 2048");
+    } else if (s->dim == 3) {
         if (s->n_off < 1 || !(s->d_off > 0)) return fail(EDT_EINVAL, "3D needs n_off >= 1, d_off > 0");
         const double a = double(s->n_off) * s->d_off, b = double(s->n_mid) * s->d_mid / 2.0;
         if (std::fabs(a - b) > 1e-9 * b) return fail(EDT_EINVAL, "3D areal survey needs n_off*d_off == n_mid*d_mid/2");
@@ -377,11 +447,14 @@ edt_status edt_survey_pair_rows(const edt_survey* s, const edt_layers* l, int64_
         q.n_off = s->dim == 3 ? s->n_off : 0;
         q.d_mid = s->d_mid;
         q.n_freq = s->n_freq;
+        q.n_line = s->n_line;
+        q.d_line = s->d_line;
         const std::vector<double> kmax = kmax_of(s, l->vel[0]);
         std::vector<int64_t> kr, ks, counts;
         std::vector<uint8_t> key_used;
         int64_t max_cls = -1, n_all = 0;
         if (s->dim == 2) rows_2d(&q, kmax, 0, 0, kr, ks, max_cls, n_all, &counts);
+        else if (s->n_line) rows_lines(&q, kmax, 0, 0, kr, ks, n_all, &counts);
         else rows_3d(&q, kmax, 0, 0, kr, ks, key_used, n_all, &counts);
         *n_pairs_all = n_all;
         if (rows_per_pair) std::memcpy(rows_per_pair, counts.data(), counts.size() * sizeof(int64_t));
@@ -418,7 +491,9 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
     try {
         p->dim = s->dim;
         p->n_mid = s->n_mid;
-        p->n_off = s->dim == 3 ? s->n_off : 0;
+        p->n_off = s->dim == 3 && !s->n_line ? s->n_off : 0;
+        p->n_line = s->n_line;
+        p->d_line = s->d_line;
         p->n_freq = s->n_freq;
         p->nz = s->nz;
         p->n_layers = l->n_layers;
@@ -438,6 +513,7 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
         std::vector<uint8_t> key_used;
         int64_t max_cls = -1, n_all = 0;
         if (p->dim == 2) rows_2d(p, kmax, pair_begin, pair_end, kr, ks, max_cls, n_all);
+        else if (p->n_line) rows_lines(p, kmax, pair_begin, pair_end, kr, ks, n_all);
         else rows_3d(p, kmax, pair_begin, pair_end, kr, ks, key_used, n_all);
         if (pair_end != INT64_MAX && pair_end > n_all) {
             delete p;
@@ -455,6 +531,15 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
         if (p->dim == 2) {
             p->n_cls = int(max_cls + 1);
             for (int c = 0; c < p->n_cls; ++c) p->cls_k.push_back(std::fabs(double(c)) * dk);
+        } else if (p->n_line) {
+            // every (|a|, |q|) of the line grid: |k| = |(a dkx, q dky)|
+            const double dky = kTwoPi / (double(p->n_line) * p->d_line);
+            const int nx2 = p->n_mid / 2 + 1, ny2 = p->n_line / 2 + 1;
+            p->n_cls = nx2 * ny2;
+            for (int ia = 0; ia < nx2; ++ia)
+                for (int iq = 0; iq < ny2; ++iq)
+                    p->cls_k.push_back(std::sqrt((double(ia) * dk) * (double(ia) * dk) +
+                                                 (double(iq) * dky) * (double(iq) * dky)));
         } else {
             // keys are small non-negative integers: rank them through a dense table
             cls_of_key.assign(key_used.size(), -1);
@@ -470,7 +555,7 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
         if (p->n_cls >= 65536) { delete p; return fail(EDT_EINVAL, "more than 65535 |k| classes"); }
         for (int64_t r = 0; r < p->n_rows; ++r) {
             uint32_t cr, cs;
-            if (p->dim == 2) { cr = uint32_t(kr[r]); cs = uint32_t(ks[r]); }
+            if (p->dim == 2 || p->n_line) { cr = uint32_t(kr[r]); cs = uint32_t(ks[r]); }
             else { cr = uint32_t(cls_of_key[size_t(kr[r])]); cs = uint32_t(cls_of_key[size_t(ks[r])]); }
             p->rows[2 * r + 1] = cr | (cs << 16);
         }
@@ -611,6 +696,21 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
         split_items(p, p->resid_group, kResidRows, p->ritems, p->pair_ritem, rgroup);
         p->rsched = xcd_schedule(p->ritems, rgroup);
 
+        // line survey: first row of each frequency of each pair
+        if (p->n_line) {
+            p->lpair.assign(size_t(p->n_rows), 0);
+            for (int64_t q = 0; q < p->n_pairs; ++q)
+                for (int64_t r = p->row_off[size_t(q)]; r < p->row_off[size_t(q) + 1]; ++r) p->lpair[size_t(r)] = int32_t(q);
+            p->lfr.assign(size_t(p->n_pairs) * size_t(p->n_freq + 1), 0);
+            for (int64_t q = 0; q < p->n_pairs; ++q) {
+                int64_t r = p->row_off[size_t(q)];
+                for (int f = 0; f <= p->n_freq; ++f) {
+                    while (r < p->row_off[size_t(q) + 1] && int(p->rows[2 * r]) < f) ++r;
+                    p->lfr[size_t(q) * size_t(p->n_freq + 1) + size_t(f)] = r;
+                }
+            }
+        }
+
         // device image
         edt::DevLayout& L = p->lay;
         size_t off = 0;
@@ -637,6 +737,9 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
         L.pair_ritem = off; off = align256(off + p->pair_ritem.size() * 4);
         L.grow = off;      off = align256(off + std::max<size_t>(1, p->grow.size()) * sizeof(edt::GRow));
         L.gsc = off;       off = align256(off + std::max<size_t>(1, p->gsc.size()) * 8);
+        L.lmask = off;     off = align256(off + std::max<size_t>(1, p->lmask.size()) * 8);
+        L.lfr = off;       off = align256(off + std::max<size_t>(1, p->lfr.size()) * 8);
+        L.lpair = off;     off = align256(off + std::max<size_t>(1, p->lpair.size()) * 4);
         L.total = off;
         p->host_image.assign(L.total, 0);
         auto put = [&](size_t o, const void* src, size_t n) { if (n) std::memcpy(p->host_image.data() + o, src, n); };
@@ -663,6 +766,9 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
         put(L.pair_ritem, p->pair_ritem.data(), p->pair_ritem.size() * 4);
         put(L.grow, p->grow.data(), p->grow.size() * sizeof(edt::GRow));
         put(L.gsc, p->gsc.data(), p->gsc.size() * 8);
+        put(L.lmask, p->lmask.data(), p->lmask.size() * 8);
+        put(L.lfr, p->lfr.data(), p->lfr.size() * 8);
+        put(L.lpair, p->lpair.data(), p->lpair.size() * 4);
         if (hbm_budget > 0) {
             const size_t need = edt::resident_bytes(p);
             if (need > hbm_budget) {

@@ -30,7 +30,8 @@ def _structs(survey):
     sv = _lib.Survey(int(survey.dim), int(survey.n_mid), float(survey.d_mid),
                      int(getattr(survey, "n_off", 0)), float(getattr(survey, "d_off", 0.0)),
                      int(freq.shape[0]), freq.ctypes.data_as(dp), float(survey.eps),
-                     int(survey.nz), float(survey.z0), float(survey.dz), float(survey.kappa))
+                     int(survey.nz), float(survey.z0), float(survey.dz), float(survey.kappa),
+                     int(getattr(survey, "n_line", 0)), float(getattr(survey, "d_line", 0.0)))
     ly = _lib.Layers(int(vel.shape[0]), vel.ctypes.data_as(dp), zif.ctypes.data_as(dp) if zif.size else None)
     return sv, ly, (freq, vel, zif)
 

@@ -1,0 +1,166 @@
+"""GPU: the 3D survey of parallel lines (paper Section 2.2) through the C-ABI,
+against the FP64 oracle (oracle.lines3d).
+
+* the rows' Gram Re(A^H A), right-hand sides and trace (edt_assemble, FP64)
+  against the oracle's rows, to 1e-12 of each pair's largest entry;
+* the damped solve (edt_solve without refinement) against the oracle's, to
+  1e-10 globally and per pair; complex64 data rows against the oracle fed
+  the same rounded data;
+* the Born forward map against the oracle's data, to 1e-12;
+* the truncated SVD runs on the line Gram;
+* what the line survey does not cover is refused.
+Surveys: odd and even grids, with and without the evanescent cut, depth
+counts that span several 64-tiles with a ragged tail, and a larger survey on
+sampled pairs.
+"""
+import numpy as np
+import pytest
+
+from edt_inputs import make_lines, vhat
+from oracle.lines3d import forward_lines, line_row_values, line_tables, plan_lines, solve_lines
+from oracle.solve import add_noise, noise_scale, normal_equations, pack
+from tests._cases import rel_errors
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+E = pytest.importorskip("paper_0905_0238_amd")
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+CASES = {
+    "even-nocut": lambda: make_lines(Nx=16, Ny=8, dx=25.0, dy=40.0, nz=24, dz=15.0, freqs=(6.0, 11.0, 17.0),
+                                     vel=(1800.0, 2600.0), zif=(45.0,), kappa=100.0, noise_rel=0.05, seed=1),
+    "odd-cut": lambda: make_lines(Nx=15, Ny=7, dx=20.0, dy=35.0, nz=33, dz=12.0, freqs=(9.0, 14.0, 22.0, 31.0),
+                                  vel=(2000.0, 2600.0, 1900.0), zif=(40.0, 140.0), kappa=1.0, noise_rel=0.05, seed=2),
+    "deep-cut": lambda: make_lines(Nx=24, Ny=12, dx=12.5, dy=25.0, nz=150, dz=8.0,
+                                   freqs=tuple(np.linspace(8.0, 40.0, 6)), vel=(1700.0, 2400.0, 3100.0),
+                                   zif=(120.0, 600.0), kappa=1.0, noise_rel=0.05, seed=3),
+}
+
+
+def _case(s):
+    pl = plan_lines(s)
+    tab = line_tables(s)
+    clean = forward_lines(s, pl, vhat(s), tab)
+    data = add_noise(s, pl, clean, noise_scale(s, pl, clean))
+    d_rows, off = pack(pl, data)
+    return pl, tab, clean, data, d_rows, off
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_line_gram_rhs_trace_and_solve(name):
+    s = CASES[name]()
+    pl, tab, clean, data, d_rows, off = _case(s)
+    p = E.Plan(s)
+    m = p.rowmap()
+    assert np.array_equal(m["row_off"], off)
+    assert p.n_km == s.n_mid * s.n_line
+    vel = _dev(np.asarray(s.vel, np.float64))
+    g64, _ = p.green(vel, want32=False)
+    d = _dev(d_rows)
+    gram, rhs, trace = p.assemble(g64, None, d, "fp64")
+    torch.cuda.synchronize()
+    G, Rc, T = gram.cpu().numpy(), rhs.cpu().numpy(), trace.cpu().numpy()
+    low = np.tril(np.ones((s.nz, s.nz), bool))
+    for i, (q, (d0, d1)) in enumerate(zip(pl.pairs, data)):
+        if not q.n_rows:
+            continue
+        A = line_row_values(s, q, tab)
+        Go, co, tro = normal_equations(A, d0, d1)
+        assert np.max(np.abs(G[i][low] - Go[low])) <= 1e-12 * np.max(np.abs(Go)), (name, i)
+        assert np.max(np.abs(Rc[i] - co)) <= 1e-12 * np.max(np.abs(co)), (name, i)
+        assert abs(T[i] - tro) <= 1e-12 * tro
+    x, v, info, _ = p.solve(g64, d, gram, rhs, trace, s.lambda_rel)
+    torch.cuda.synchronize()
+    Vo, _ = solve_lines(s, pl, data, tab)
+    g, per = rel_errors(v.cpu().numpy(), Vo, pl)
+    print(f"{name}: {len(pl.pairs)} pairs, {p.n_rows} rows; solve error {g:.2e} global, {per:.2e} per pair",
+          flush=True)
+    assert g <= 1e-10 and per <= 1e-10
+    info = info.cpu().numpy()
+    for q, inf in zip(pl.pairs, info):
+        assert inf == (-1 if q.n_rows == 0 else 0)
+
+
+@pytest.mark.parametrize("name", ["even-nocut", "odd-cut"])
+def test_line_forward_map(name):
+    s = CASES[name]()
+    pl, tab, clean, data, d_rows, off = _case(s)
+    ref, _ = pack(pl, clean)
+    for dt in ("c128", "c64"):
+        p = E.Plan(s, data=dt)
+        g64, _ = p.green(_dev(np.asarray(s.vel, np.float64)), want32=False)
+        d = p.forward(g64, _dev(vhat(s))).cpu().numpy().astype(np.complex128)
+        bar = 1e-12 if dt == "c128" else 2.0 ** -23
+        assert np.max(np.abs(d - ref)) <= bar * np.max(np.abs(ref)), (name, dt)
+
+
+def test_line_solve_on_complex64_rows():
+    from oracle.lines3d import solve_lines as sl
+    s = CASES["odd-cut"]()
+    pl, tab, clean, data, d_rows, off = _case(s)
+    d32 = d_rows.astype(np.complex64)
+    r64 = d32.astype(np.complex128)
+    data_r = [(r64[off[i]:off[i + 1], 0], r64[off[i]:off[i + 1], 1]) for i in range(len(pl.pairs))]
+    Vo, _ = sl(s, pl, data_r, tab)
+    p = E.Plan(s, data="c64")
+    out = p.run(_dev(np.asarray(s.vel, np.float64)), _dev(d32), s.lambda_rel, prec="fp64")
+    torch.cuda.synchronize()
+    g, per = rel_errors(out["v"].cpu().numpy(), Vo, pl)
+    assert g <= 1e-10 and per <= 1e-10
+
+
+def test_truncated_svd_on_the_line_gram():
+    from oracle.tsvd import tsvd_gram
+    s = CASES["odd-cut"]()
+    pl, tab, clean, data, d_rows, off = _case(s)
+    p = E.Plan(s)
+    g64, _ = p.green(_dev(np.asarray(s.vel, np.float64)), want32=False)
+    gram, rhs, _ = p.assemble(g64, None, _dev(d_rows), "fp64")
+    _, v, info, iters = p.tsvd(gram, rhs, 1e-2)
+    torch.cuda.synchronize()
+    v = v.cpu().numpy()
+    u = np.finfo(np.float64).eps / 2
+    nv = np.linalg.norm(v)
+    checked = 0
+    for q, (d0, d1) in zip(pl.pairs, data):
+        if not q.n_rows:
+            continue
+        Go, co, _ = normal_equations(line_row_values(s, q, tab), d0, d1)
+        x, w, t2 = tsvd_gram(Go, co, 1e-2)
+        if q.self_conjugate:
+            x[1] = 0.0
+        gap = np.min(np.abs(w - t2))
+        if gap <= 1e-6 * t2:
+            continue
+        kept = w[w >= t2]
+        bar = max(1e-10, 100 * u * (w.max() / kept.min() + w.max() / gap))
+        idx = [q.u] if q.self_conjugate else [q.u, q.u_neg]
+        ref = np.array([x[0] + 1j * x[1]] if q.self_conjugate else [x[0] + 1j * x[1], x[0] - 1j * x[1]])
+        err = np.linalg.norm(v[idx] - ref) / max(np.linalg.norm(ref), 1e-3 * nv)
+        assert err <= bar, (q.u, err, bar)
+        checked += 1
+    assert checked > 0
+
+
+def test_line_survey_refusals():
+    s = CASES["even-nocut"]()
+    pl, tab, clean, data, d_rows, off = _case(s)
+    p = E.Plan(s)
+    vel = _dev(np.asarray(s.vel, np.float64))
+    g64, g32 = p.green(vel)
+    d = _dev(d_rows)
+    with pytest.raises(RuntimeError, match="FP64 only"):
+        p.assemble(g64, g32, d, "fp16x3")
+    gram, rhs, trace = p.assemble(g64, None, d, "fp64")
+    with pytest.raises(RuntimeError, match="without refinement"):
+        p.solve(g64, d, gram, rhs, trace, s.lambda_rel, refine=True)
+    with pytest.raises(RuntimeError, match="parallel lines"):
+        p.kz_restrict(gram, rhs, 1.0, p.tsvd_work())
+    v = torch.zeros(p.n_km, s.nz, dtype=torch.complex128, device="cuda")
+    with pytest.raises(RuntimeError, match="parallel lines"):
+        p.model(v)

@@ -306,3 +306,42 @@ def test_invalid_pair_ranges_are_rejected(pairs):
     _lib_or_skip()
     with pytest.raises(RuntimeError):
         E.Plan(SURVEYS["cfg1"](), pairs=pairs)
+
+
+@pytest.mark.parametrize("kw", [dict(Nx=16, Ny=8, kappa=100.0), dict(Nx=15, Ny=7, kappa=1.0),
+                                dict(Nx=24, Ny=12, dx=12.5, dy=25.0, kappa=1.0, freqs=(8.0, 23.0, 40.0))])
+def test_line_survey_rows_equal_oracle(kw):
+    """The planner's rows of the 3D survey of parallel lines are the oracle's,
+    bit for bit: pairs, row order, frequencies and (a, b) keys."""
+    from edt_inputs import make_lines
+    from oracle.lines3d import plan_lines
+    _lib_or_skip()
+    s = make_lines(nz=5, model=None, **kw)
+    pl = plan_lines(s)
+    p = E.Plan(s)
+    m = p.rowmap()
+    assert p.n_pairs == len(pl.pairs) and p.n_km == s.n_mid * s.n_line
+    off = np.zeros(len(pl.pairs) + 1, np.int64)
+    off[1:] = np.cumsum([q.n_rows for q in pl.pairs])
+    assert np.array_equal(m["row_off"], off)
+    assert np.array_equal(m["pair_km"], np.array([[q.u, q.u_neg] for q in pl.pairs], np.int32))
+    f = np.concatenate([q.f for q in pl.pairs])
+    k = np.concatenate([q.key0[:, :2] for q in pl.pairs])
+    assert np.array_equal(m["rows"][:, 0], f) and np.array_equal(m["keys"], k)
+    assert np.array_equal(E.pair_rows(s), np.diff(off))
+    # classes: every (|a|, |q|) of the grid
+    Nx, Ny = s.n_mid, s.n_line
+    ia, iq = np.divmod(np.arange(m["cls_k"].size), Ny // 2 + 1)
+    ref = np.sqrt((ia * 2 * np.pi / (Nx * s.d_mid)) ** 2 + (iq * 2 * np.pi / (Ny * s.d_line)) ** 2)
+    assert np.allclose(m["cls_k"], ref, rtol=1e-15, atol=0)
+
+
+def test_line_survey_limits_are_refused():
+    from edt_inputs import make_lines
+    _lib_or_skip()
+    with pytest.raises(RuntimeError, match="n_line <= 64"):
+        E.Plan(make_lines(Nx=8, Ny=65, model=None))
+    s = make_lines(Nx=8, Ny=4, model=None)
+    s.dim = 2
+    with pytest.raises(RuntimeError, match="dim 3"):
+        E.Plan(s)
