@@ -9,7 +9,7 @@
 //
 // A work item is a chunk of one pair's rows.  A 256- (512-) thread workgroup
 // builds 8 complex rows (16 real rows of Ah) per stage straight from the
-// Green's tables into LDS (double-buffered), and its waves feed them to MFMA
+// Green's tables into LDS (a ring of stage buffers), and its waves feed them to MFMA
 // for the whole lower triangle of the nz x nz Gram, which stays in registers
 // across the chunk; A is never written to memory.  Each item stores its
 // partial Gram tile by tile; a second kernel sums the items of a pair in FP64
@@ -18,6 +18,8 @@
 // Precisions:
 //   BF16X3: v_mfma_f32_32x32x16_bf16, each value split x = hi + lo (bf16) and
 //           Ah^T Ah ~ hi^T hi + hi^T lo + lo^T hi with FP32 accumulation;
+//   FP16X3: the same with IEEE halves (v_mfma_f32_32x32x16_f16) on rows
+//           scaled by a power of two per item;
 //   FP32:   v_mfma_f32_32x32x2_f32;
 //   FP64:   v_mfma_f64_16x16x4_f64 on FP64 rows built from the FP64 table.
 
@@ -408,14 +410,12 @@ __global__ __launch_bounds__(512, 1) void gram_split3_kernel(const Item* __restr
     }
 }
 
-// ------------------------------------------- split, diagonal, unified ---
-// The diagonal split task again, with every wave both forming rows and
-// issuing MFMA: a wave's MFMAs on stage t (from LDS) are independent of its
-// VALU work forming stage t+1, so the two overlap inside the wave, and the
-// two waves of a SIMD cover each other's memory waits.
-// Tiles: the lower triangle in row-major order is cut into four SIMD groups
-// of G consecutive tiles; waves s and s+4 (one SIMD) take the first TA and
-// the remaining G-TA tiles of group s.
+// ------------------------------------------------- split, diagonal ---
+// Diagonal split tasks run with every wave both forming rows and issuing
+// MFMA.  Default tile deal (sizes without a compact one below): the lower
+// triangle in row-major order is cut into four SIMD groups of G consecutive
+// tiles; waves s and s+4 (one SIMD) take the first TA and the remaining G-TA
+// tiles of group s.
 template <int NT>
 struct UCfg {
     static constexpr int NTL = NT * (NT + 1) / 2;
@@ -432,83 +432,10 @@ struct UCfg {
     }
 };
 
-template <int NT, int W>
-__device__ __forceinline__ void u_store_tiles(const f32x16 (&acc)[UCfg<NT>::TPW], float* out, int lane,
-                                              float scale, int bI0) {
-    using C = UCfg<NT>;
-    constexpr int t0 = C::t0(W), t1 = C::t1(W);
-#pragma unroll
-    for (int m = 0; m < C::TPW; ++m) {
-        const int t = t0 + m;
-        if (t < t1) {
-            const int Ig = bI0 + tri_I(t), Jg = bI0 + tri_J(t);
-            float* o = out + size_t(Ig * (Ig + 1) / 2 + Jg) * 1024;
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                __builtin_nontemporal_store(acc[m][v] * scale, &o[i * 32 + (lane & 31)]);
-            }
-        }
-    }
-}
-
 // raw table values of half a stage (4 complex rows) at one depth
 struct RawHalf {
     float2 ga[4], gb[4];
 };
-
-// ------------------------------------ split, diagonal, per-wave schedule ---
-// The unified diagonal split task with each wave's code straight-line: the
-// kernel branches on the wave index once, outside the item loop, so that a
-// stage's MFMAs (from LDS), the table loads of a later stage and the VALU
-// forming the next stage sit in one basic block, and the scheduler is told to
-// interleave them (one MFMA, then a run of VALU, then a load), so the matrix
-// pipe and the VALU of a wave work at the same time instead of in turn.  The
-// products are issued product-major (every tile's hi.hi, then hi.lo, then
-// lo.hi), so consecutive MFMAs do not wait on one accumulator.  Results equal
-// the warp-specialised kernel's bit for bit (the same products accumulated
-// into each tile in the same order).
-template <int NT, int W, bool F16>
-__device__ __forceinline__ void w_wave_mfma(f32x16 (&acc)[UCfg<NT>::TPW], const uint16_t* hi, const uint16_t* lo,
-                                            int lane) {
-    using C = UCfg<NT>;
-    typedef typename std::conditional<F16, f16x8, bf16x8>::type v8;
-    constexpr int t0 = C::t0(W), t1 = C::t1(W);
-    constexpr uint32_t need = t0 < t1 ? block_mask(t0, t1) : 0u;
-    v8 fh[NT], fl[NT];
-    const int roff = (lane & 31) * C::STR + (lane >> 5) * 8;
-#pragma unroll
-    for (int b = 0; b < NT; ++b) {
-        if (need & (1u << b)) {
-            fh[b] = *reinterpret_cast<const v8*>(hi + b * 32 * C::STR + roff);
-            fl[b] = *reinterpret_cast<const v8*>(lo + b * 32 * C::STR + roff);
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-#pragma unroll
-        for (int m = 0; m < C::TPW; ++m) {
-            const int t = t0 + m;
-            if (t < t1) {
-                const int I = tri_I(t), J = tri_J(t);
-                const v8 a = k == 2 ? fl[I] : fh[I];
-                const v8 b = k == 1 ? fl[J] : fh[J];
-                if constexpr (F16)
-                    acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc[m], 0, 0, 0);
-                else
-                    acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[m], 0, 0, 0);
-            }
-        }
-    }
-}
-
-// Blocks read by wave W's tiles (two 16-byte fragment reads each).
-template <int NT, int W>
-constexpr int w_frag_reads() {
-    constexpr int t0 = UCfg<NT>::t0(W), t1 = UCfg<NT>::t1(W);
-    constexpr uint32_t m = t0 < t1 ? block_mask(t0, t1) : 0u;
-    return 2 * __builtin_popcount(m);
-}
 
 // Scheduling of one stage of wave W: its fragment reads first, then each MFMA
 // followed by up to V VALU instructions and one vector-memory read.
@@ -523,21 +450,71 @@ __device__ __forceinline__ void w_interleave() {
     }
 }
 
+
+// ------------------------- split, diagonal, fragments read a stage ahead ---
+// The diagonal split task with the LDS fragment reads taken off the critical
+// path: rows are formed two stages ahead into a ring of three LDS stage
+// buffers, and each wave reads the fragments of stage t + 1 into registers
+// while it issues the MFMAs of stage t, so per stage the LDS reads, the
+// matrix products and the row forming (VALU) of a wave overlap behind one
+// barrier.  The tiles of the 8- and 7-block tasks are dealt in compact groups
+// (2 x 2 squares of the rectangle below the half-way block, and runs of the
+// two triangles), so that a wave reads at most four blocks per stage.
+// Accumulation order per tile is that of the other split kernels (per stage:
+// hi.hi, hi.lo, lo.hi), so the Grams are the same bit for bit.
+template <int NT>
+struct PCfg {
+    // tile m of wave W as I * 8 + J (I >= J), or -1
+    __host__ __device__ static constexpr int tile(int W, int m) {
+        if constexpr (NT == 8) {
+            constexpr int T[8][5] = {{32, 33, 40, 41, -1}, {34, 35, 42, 43, -1}, {48, 49, 56, 57, -1},
+                                     {50, 51, 58, 59, -1}, {0, 8, 9, 16, 24},    {17, 18, 25, 26, 27},
+                                     {36, 44, 45, 52, 60}, {53, 54, 61, 62, 63}};
+            return m < 5 ? T[W][m] : -1;
+        } else if constexpr (NT == 7) {
+            constexpr int T[8][4] = {{24, 25, 26, -1}, {32, 33, 34, -1}, {40, 41, 42, -1}, {48, 49, 50, -1},
+                                     {0, 8, 9, 16},    {17, 18, 27, 35}, {36, 43, 44, 45}, {51, 52, 53, 54}};
+            return m < 4 ? T[W][m] : -1;
+        } else {
+            const int t = UCfg<NT>::t0(W) + m;
+            return (m < UCfg<NT>::TPW && t < UCfg<NT>::t1(W)) ? tri_I(t) * 8 + tri_J(t) : -1;
+        }
+    }
+    static constexpr int TPW = NT == 8 ? 5 : NT == 7 ? 4 : UCfg<NT>::TPW;
+    __host__ __device__ static constexpr uint32_t mask(int W) {
+        uint32_t b = 0;
+        for (int m = 0; m < TPW; ++m)
+            if (tile(W, m) >= 0) b |= (1u << (tile(W, m) >> 3)) | (1u << (tile(W, m) & 7));
+        return b;
+    }
+    // position of block b among the blocks of wave W
+    __host__ __device__ static constexpr int slot(int W, int b) {
+        return __builtin_popcount(mask(W) & ((1u << b) - 1u));
+    }
+};
+
 template <int NT, int W, bool F16>
-__device__ __forceinline__ void split3w_wave(const Item& it, const GRow* __restrict__ grow,
+__device__ __forceinline__ void split3p_wave(const Item& it, const GRow* __restrict__ grow,
                                              const float4* __restrict__ ub32, const float2* __restrict__ g32,
                                              const float* __restrict__ gmax, int nz, int zI0, int ntot,
                                              float* __restrict__ part, double* __restrict__ rpart, int max_rows,
                                              uint16_t (*sh)[2][UCfg<NT>::NZP * UCfg<NT>::STR], double* s_tr,
                                              float* s_max, uint4* s_row) {
     using C = UCfg<NT>;
-    constexpr int PF = 2;
-    static_assert(PF + 1 <= kPadStages, "padding stages exceed the row LDS");
-    constexpr int NM = 3 * (C::t1(W) > C::t0(W) ? C::t1(W) - C::t0(W) : 0);
+    using P = PCfg<NT>;
+    typedef typename std::conditional<F16, f16x8, bf16x8>::type v8;
+    constexpr uint32_t need = P::mask(W);
+    constexpr int NB = __builtin_popcount(need) > 0 ? __builtin_popcount(need) : 1;
+    constexpr int NM = [] {
+        int c = 0;
+        for (int m = 0; m < P::TPW; ++m) c += P::tile(W, m) >= 0 ? 3 : 0;
+        return c;
+    }();
+    static_assert(3 <= kPadStages, "padding stages exceed the row LDS");
     const int tid = threadIdx.x, lane = tid & 63;
     const int n = min(it.row_end - it.row_begin, max_rows);
     const int nst = (n + 7) >> 3;
-    const int nsp = ((nst + 1 + PF - 1) / PF) * PF;   // + zero stages, a multiple of PF
+    const int nsp = ((nst + 1 + 1) / 2) * 2;   // + zero stages, an even count
     const int nzI = min(C::NZP, nz - zI0);
     stage_rows(s_row, grow, ub32, it.row_begin, n, nsp, tid, 512);
     float scale = 1.0f;
@@ -560,18 +537,9 @@ __device__ __forceinline__ void split3w_wave(const Item& it, const GRow* __restr
     constexpr int hf = W >> 2;   // rows 4 hf .. 4 hf + 3 of a stage
     const bool on = z < nzI;
     const uint32_t zc = uint32_t(zI0 + min(z, nzI - 1));   // clamped: loads are unconditional
-    // depths past nz form zeros through their scale (their LDS slots were
-    // zeroed above and must stay zero): no select or branch in the loop
-    const float lane_scale = on ? scale : 0.0f;
-    if (z >= nzI && z < C::NZP) {   // depths past nz stay zero for the whole item
-        const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int h = 0; h < 2; ++h) reinterpret_cast<uint4*>(sh[b][h] + z * C::STR)[hf] = zero;
-    }
+    const float lane_scale = on ? scale : 0.0f;             // depths past nz form zeros
     double cp = 0.0, cm = 0.0, tr = 0.0;   // per stage in FP32, then in FP64
-    const uint32_t zoff = zc * uint32_t(sizeof(float2));   // byte offset of this lane's depth
+    const uint32_t zoff = zc * uint32_t(sizeof(float2));
     // the row records of a stage (LDS broadcasts): the table offsets of the
     // loads, and the scales and data of the row forming
     auto read_off = [&](uint32_t (&o)[8], int s) {
@@ -620,48 +588,100 @@ __device__ __forceinline__ void split3w_wave(const Item& it, const GRow* __restr
             reinterpret_cast<uint4*>(sh[buf][1] + z * C::STR)[hf] = make_uint4(l[0], l[1], l[2], l[3]);
         }
     };
-    f32x16 acc[C::TPW];
+    // fragments of the wave's blocks, two stages' worth
+    v8 fh[2][NB], fl[2][NB];
+    const int roff = (lane & 31) * C::STR + (lane >> 5) * 8;
+    auto frag = [&](v8 (&h)[NB], v8 (&l)[NB], int buf) {
 #pragma unroll
-    for (int m = 0; m < C::TPW; ++m)
+        for (int b = 0; b < NT; ++b) {
+            if (need & (1u << b)) {
+                h[P::slot(W, b)] = *reinterpret_cast<const v8*>(sh[buf][0] + b * 32 * C::STR + roff);
+                l[P::slot(W, b)] = *reinterpret_cast<const v8*>(sh[buf][1] + b * 32 * C::STR + roff);
+            }
+        }
+    };
+    f32x16 acc[P::TPW];
+#pragma unroll
+    for (int m = 0; m < P::TPW; ++m)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[m][v] = 0.0f;
-    // stage k's raw values live in R[k % PF]; indices past the padded end are
-    // clamped to its last (zero) stage
-    RawHalf R[PF];
-    __syncthreads();   // rows staged, padding depths zeroed
+    // products of one stage, product-major (every tile's hi.hi, then hi.lo,
+    // then lo.hi), so consecutive MFMAs do not wait on one accumulator
+    auto mfma = [&](const v8 (&h)[NB], const v8 (&l)[NB]) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+#pragma unroll
+            for (int m = 0; m < P::TPW; ++m) {
+                const int tl = P::tile(W, m);
+                if (tl >= 0) {
+                    const int I = P::slot(W, tl >> 3), J = P::slot(W, tl & 7);
+                    const v8 a = k == 2 ? l[I] : h[I];
+                    const v8 b = k == 1 ? l[J] : h[J];
+                    if constexpr (F16)
+                        acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc[m], 0, 0, 0);
+                    else
+                        acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[m], 0, 0, 0);
+                }
+            }
+        }
+    };
+    // stage k's raw table values live in R[k % 2]; stage indices past the
+    // padded end are clamped to its last (zero) stage
+    RawHalf R[2];
+    __syncthreads();   // rows staged
     {
         uint32_t o[8];
         uint4 ra[4], rb[4];
-#pragma unroll
-        for (int q = 0; q < PF; ++q) {
-            read_off(o, q);
-            load(R[q], o);
-        }
+        read_off(o, 0);
+        load(R[0], o);
+        read_off(o, 1);
+        load(R[1], o);
         read_rec(ra, rb, 0);
         form(R[0], ra, rb, 0);
+        read_off(o, min(2, nsp - 1));
+        load(R[0], o);
+        read_rec(ra, rb, 1);
+        form(R[1], ra, rb, 1);
+        read_off(o, min(3, nsp - 1));
+        load(R[1], o);
     }
     __syncthreads();
-    for (int s = 0; s < nsp; s += PF) {
+    frag(fh[0], fl[0], 0);
+    // iteration t: the products of stage t (fragments read in iteration t - 1),
+    // the fragments of stage t + 1, the rows of stage t + 2 (table values
+    // loaded in iteration t - 2) and the table loads of stage t + 4
+    for (int s = 0; s < nsp; s += 2) {
 #pragma unroll
-        for (int q = 0; q < PF; ++q) {
+        for (int q = 0; q < 2; ++q) {
             const int t = s + q;
-            // every LDS read of the stage first (records of the next rows,
-            // offsets of the loads two stages on, this stage's fragments),
-            // then the MFMAs interleaved with the loads and the row forming
             uint4 ra[4], rb[4];
             uint32_t o[8];
-            read_rec(ra, rb, min(t + 1, nsp - 1));
-            read_off(o, min(t + PF, nsp - 1));
-            w_wave_mfma<NT, W, F16>(acc, sh[t & 1][0], sh[t & 1][1], lane);
+            read_rec(ra, rb, min(t + 2, nsp - 1));
+            read_off(o, min(t + 4, nsp - 1));
+            frag(fh[q ^ 1], fl[q ^ 1], (t + 1) % 3);
+            mfma(fh[q], fl[q]);
+            form(R[q], ra, rb, (t + 2) % 3);
             load(R[q], o);
-            form(R[(q + 1) % PF], ra, rb, (t + 1) & 1);
-            w_interleave<NM, w_frag_reads<NT, W>() + 12, 8>();
+            w_interleave<NM, 2 * NB + 12, 8>();
             __syncthreads();
         }
     }
     float* out = part + size_t(it.slot) * (ntot * (ntot + 1) / 2) * 1024;
     const float back = 1.0f / (scale * scale);
-    u_store_tiles<NT, W>(acc, out, lane, back, zI0 / 32);
+    const int bI0 = zI0 / 32;
+#pragma unroll
+    for (int m = 0; m < P::TPW; ++m) {
+        const int tl = P::tile(W, m);
+        if (tl >= 0) {
+            const int Ig = bI0 + (tl >> 3), Jg = bI0 + (tl & 7);
+            float* o = out + size_t(Ig * (Ig + 1) / 2 + Jg) * 1024;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                __builtin_nontemporal_store(acc[m][v] * back, &o[i * 32 + (lane & 31)]);
+            }
+        }
+    }
     // the two row halves of depth z meet in LDS (the stage buffers are free)
     double* sc = reinterpret_cast<double*>(&sh[0][0][0]);
     if (hf == 1) {
@@ -682,7 +702,7 @@ __device__ __forceinline__ void split3w_wave(const Item& it, const GRow* __restr
 }
 
 template <int NT, bool F16>
-__global__ __launch_bounds__(512, 1) void gram_split3w_kernel(const Item* __restrict__ items,
+__global__ __launch_bounds__(512, 1) void gram_split3p_kernel(const Item* __restrict__ items,
                                                               const int32_t* __restrict__ sched,
                                                               const GRow* __restrict__ grow,
                                                               const float4* __restrict__ ub32,
@@ -691,7 +711,7 @@ __global__ __launch_bounds__(512, 1) void gram_split3w_kernel(const Item* __rest
                                                               int ntot, float* __restrict__ part,
                                                               double* __restrict__ rpart, int max_rows) {
     using C = UCfg<NT>;
-    __shared__ __attribute__((aligned(16))) uint16_t sh[2][2][C::NZP * C::STR];
+    __shared__ __attribute__((aligned(16))) uint16_t sh[3][2][C::NZP * C::STR];
     __shared__ double s_tr[8];
     __shared__ float s_max[8];
     extern __shared__ __attribute__((aligned(16))) uint4 s_row[];
@@ -701,7 +721,7 @@ __global__ __launch_bounds__(512, 1) void gram_split3w_kernel(const Item* __rest
     switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
 #define EDT_W(w)                                                                                              \
     case w:                                                                                                   \
-        split3w_wave<NT, w, F16>(it, grow, ub32, g32, gmax, nz, zI0, ntot, part, rpart, max_rows, sh, s_tr, \
+        split3p_wave<NT, w, F16>(it, grow, ub32, g32, gmax, nz, zI0, ntot, part, rpart, max_rows, sh, s_tr, \
                                  s_max, s_row);                                                               \
         break;
         EDT_W(0) EDT_W(1) EDT_W(2) EDT_W(3) EDT_W(4) EDT_W(5) EDT_W(6) EDT_W(7)
@@ -1198,7 +1218,6 @@ static bool split_unified() {
     return u;
 }
 
-
 // One Gram task kind (diagonal NTJ = 0 or rectangular) over every item.
 template <int NT, int NTJ>
 static hipError_t launch_gram_task(const edt_plan* p, edt_precision prec, const zd* g64,
@@ -1213,11 +1232,11 @@ static hipError_t launch_gram_task(const edt_plan* p, edt_precision prec, const 
     const unsigned grid = rd.gate ? std::min(nb, 512u) : nb;
     if ((prec == EDT_BF16X3 || prec == EDT_FP16X3) && NTJ == 0 && split_unified()) {
         if (prec == EDT_BF16X3)
-            hipLaunchKernelGGL((gram_split3w_kernel<NT, false>), dim3(nb), dim3(512), row_lds_bytes(p->chunk_rows),
+            hipLaunchKernelGGL((gram_split3p_kernel<NT, false>), dim3(nb), dim3(512), row_lds_bytes(p->chunk_rows),
                                st, items, sched, grow, rd.ub32, g32, rd.gmax, p->nz, zI0, ntot,
                                static_cast<float*>(part), rpart, p->chunk_rows);
         else
-            hipLaunchKernelGGL((gram_split3w_kernel<NT, true>), dim3(nb), dim3(512), row_lds_bytes(p->chunk_rows),
+            hipLaunchKernelGGL((gram_split3p_kernel<NT, true>), dim3(nb), dim3(512), row_lds_bytes(p->chunk_rows),
                                st, items, sched, grow, rd.ub32, g32, rd.gmax, p->nz, zI0, ntot,
                                static_cast<float*>(part), rpart, p->chunk_rows);
     } else if (prec == EDT_BF16X3)
@@ -1284,10 +1303,10 @@ static hipError_t configure_gram_task() {
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_split3_kernel<NT, NTJ, true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e == hipSuccess && NTJ == 0)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_split3w_kernel<NT, false>),
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_split3p_kernel<NT, false>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e == hipSuccess && NTJ == 0)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_split3w_kernel<NT, true>),
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_split3p_kernel<NT, true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e == hipSuccess && NTJ == 0)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_f32_kernel<NT>),
