@@ -164,3 +164,58 @@ def test_line_survey_refusals():
     v = torch.zeros(p.n_km, s.nz, dtype=torch.complex128, device="cuda")
     with pytest.raises(RuntimeError, match="parallel lines"):
         p.model(v)
+
+
+def test_sampled_pairs_of_a_larger_line_survey():
+    """128 lines' worth of positions (N_x = 128 at 12.5 m) on 32 lines 25 m
+    apart, nz = 128, 32 frequencies 4-40 Hz, four layers, with the cut: the
+    whole survey's Gram and solve on the GPU, 8 pairs (the largest by rows
+    among them) against the oracle, their data from the oracle.  FP64 bar
+    max(1e-10, 100 u kappa(H)) per pair (H = G + lambda I, kappa from the
+    oracle's eigenvalues)."""
+    s = make_lines(Nx=128, Ny=32, dx=12.5, dy=25.0, nz=128, dz=10.0, freqs=tuple(np.linspace(4.0, 40.0, 32)),
+                   vel=(1600.0, 2200.0, 2900.0, 3500.0), zif=(150.0, 450.0, 900.0), kappa=1.0,
+                   noise_rel=0.05, seed=7)
+    p = E.Plan(s)
+    off = p.rowmap()["row_off"]
+    rows = np.diff(off)
+    rng = np.random.default_rng(11)
+    nonempty = np.nonzero(rows)[0]
+    pick = sorted(set([int(np.argmax(rows))] + [int(i) for i in rng.choice(nonempty, 7, replace=False)]))
+    pl = plan_lines(s, only=pick)
+    assert pl.index == pick
+    for q, i in zip(pl.pairs, pick):
+        assert q.n_rows == rows[i]
+    tab = line_tables(s)
+    clean = forward_lines(s, pl, vhat(s), tab)
+    data = add_noise(s, pl, clean, noise_scale(s, pl, clean))
+    vel = _dev(np.asarray(s.vel, np.float64))
+    g64, _ = p.green(vel, want32=False)
+    d = p.forward(g64, _dev(vhat(s)))
+    for q, i, (d0, d1) in zip(pl.pairs, pick, data):
+        d[off[i]:off[i + 1], 0] = _dev(d0)
+        d[off[i]:off[i + 1], 1] = _dev(d1)
+    gram, rhs, trace = p.assemble(g64, None, d, "fp64")
+    G = gram[pick].cpu().numpy()
+    x, v, info, _ = p.solve(g64, d, gram, rhs, trace, s.lambda_rel)
+    torch.cuda.synchronize()
+    v, info = v.cpu().numpy(), info.cpu().numpy()
+    low = np.tril(np.ones((s.nz, s.nz), bool))
+    u = np.finfo(np.float64).eps / 2
+    worst = 0.0
+    for j, (q, i, (d0, d1)) in enumerate(zip(pl.pairs, pick, data)):
+        A = line_row_values(s, q, tab)
+        Go, _, tro = normal_equations(A, d0, d1)
+        assert np.max(np.abs(G[j][low] - Go[low])) <= 1e-12 * np.max(np.abs(Go)), i
+        from oracle.solve import solve_pair
+        xo, info_o, lam, _ = solve_pair(s, q, A, d0, d1)
+        assert info[i] == 0 and info_o == 0
+        w = np.linalg.eigvalsh(Go + lam * np.eye(s.nz))
+        idx = [q.u] if q.self_conjugate else [q.u, q.u_neg]
+        ref = np.array([xo[0] + 1j * xo[1], xo[0] - 1j * xo[1]])[:len(idx)]
+        err = np.linalg.norm(v[idx] - ref) / np.linalg.norm(ref)
+        bar = max(1e-10, 100 * u * w.max() / w.min())
+        assert err <= bar, (i, q.n_rows, err, bar)
+        worst = max(worst, err)
+    print(f"line survey 128x32, nz 128: {len(rows)} pairs, {int(rows.sum())} rows, largest {int(rows.max())}; "
+          f"8 sampled pairs worst {worst:.2e}", flush=True)
