@@ -179,16 +179,20 @@ def _f64_mfma_flops(plan, nz):
     return stages * (nb * (nb + 1) // 2) * 4 * 16 * 16 * 4 * 2.0
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, prec, shape):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE passes scaled by a plain-copy calibration), or
-    None if there is none or the kernel's source changed since it was taken."""
+    None if there is none for this workload, precision and work-item shape
+    (chunk_rows, gram_band, resid_group as the plan uses them), or if the
+    kernel's source changed since it was taken."""
     import glob
     import hashlib
     for fn in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")):
         with open(fn) as fh:
             t = json.load(fh)
-        if t.get("kernel") != kernel or t.get("workload") != workload:
+        if t.get("kernel") != kernel or t.get("workload") != workload or t.get("precision") != prec:
+            continue
+        if t.get("shape") != shape:
             continue
         with open(os.path.join(ROOT, t["source"]), "rb") as fh:
             if hashlib.sha1(fh.read()).hexdigest() != t["source_sha1"]:
@@ -730,7 +734,9 @@ def main():
         v.pop("_steps")
         v["gram_mfma"] = gram_mfma(plans[pr], s, v["kernels"])
     roof["kernel"] = dom
-    roof["traffic"] = measured_traffic(dom, CONFIG_NAMES[a.config])
+    mp = plans[main_prec]
+    roof["traffic"] = measured_traffic(dom, CONFIG_NAMES[a.config], main_prec,
+                                       {k: int(mp.info[k]) for k in ("chunk_rows", "gram_band", "resid_group")})
     if roof["traffic"] is not None:
         roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)"
     out = {
