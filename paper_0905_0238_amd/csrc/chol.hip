@@ -25,13 +25,34 @@ namespace edt {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// Factor gram[p] + lambda_p I in place, store the diagonal-block inverses in
-// dinv[p][nblk][32][32] and solve for x from rhs (exact: with the corrected
-// block solves, for a result that no refinement follows).
-// Dynamic LDS: the panel (nz x CBP doubles) and D (32 x CBP doubles), reused
-// by the solve afterwards.
-// Q: row-block groups of the panel accumulators (wave w holds the 16-row
-// blocks w + 4 q, q < Q): 4 for nz <= 256, 7 for nz <= 448.
+// Staging of finished columns for the panel update (even depth counts).  A
+// 16-column block of the rows k0 .. k0 + m - 1 (padded to rows64, a multiple
+// of 64) takes rows64 x 128 bytes, piece-major: the 16-byte piece p (columns
+// 2p, 2p + 1) of row r sits at slot p * rows64 + r, so the 16 rows an MFMA
+// operand reads at one column are 256 contiguous bytes (no bank conflict) and
+// a lane's address is a fixed offset plus a wave-uniform one.  Loads go
+// straight to LDS (global_load_lds_dwordx4: lane l of a wave writes the 16
+// bytes at the wave's base + 16 l): one wave instruction moves one piece of
+// 64 consecutive rows.
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) const void glb_void_t;
+
+// Pieces of 16 bytes the panel region holds (the dynamic LDS before D).
+__device__ __forceinline__ int stage_pieces(int nz) { return (nz * CBP * 8) / 16; }
+
+__device__ __forceinline__ void stage_columns(const double* __restrict__ A, int nz, int k0, int m, int c0, int nb,
+                                              int rows64, double* smem, int wvu, int lane) {
+    const int per_piece = rows64 >> 6;         // wave instructions per piece
+    const int total = nb * 8 * per_piece;      // wave instructions of the trip
+    for (int j = wvu; j < total; j += 4) {     // wave-uniform
+        const int bp = j / per_piece;          // block * 8 + piece
+        const int r = (j - bp * per_piece) * 64 + lane;
+        const int row = min(r, m - 1);         // padding rows read a valid row
+        const double* src = A + size_t(k0 + row) * nz + c0 + 16 * (bp >> 3) + 2 * (bp & 7);
+        __builtin_amdgcn_global_load_lds((glb_void_t*)(src), (lds_void_t*)(smem + 128 * size_t(j)), 16, 0, 0);
+    }
+}
+
 template <int Q>
 __global__ __launch_bounds__(256, Q > 4 ? 1 : 2) void chol_solve_kernel(
     double* __restrict__ gram, const double* __restrict__ trace, const double* __restrict__ rhs,
@@ -86,8 +107,53 @@ __global__ __launch_bounds__(256, Q > 4 ? 1 : 2) void chol_solve_kernel(
                     }
                     acc[q][cb][v] = a;
                 }
-        // P -= L[k0+i][t] L[k0+j][t], t < k0: 32 finished columns at a time
-        for (int t0 = 0; t0 < k0; t0 += CB) {
+        // P -= L[k0+i][t] L[k0+j][t], t < k0.  Even depth counts: the finished
+        // columns are staged in LDS by direct (register-free) loads, as many
+        // 16-column blocks per memory round trip as the panel region holds;
+        // odd depth counts (rows not 16-byte aligned): 32 columns at a time
+        // through registers.
+        if ((nz & 1) == 0 && k0 > 0) {
+            const int rows64 = (m + 63) & ~63;
+            const int blk = rows64 * 8;   // 16-byte pieces of one 16-column block
+            const int nbt = max(1, min(stage_pieces(nz) / blk, k0 / 16));
+            const int wvu = __builtin_amdgcn_readfirstlane(wv);
+            // lane part of the operand indices: column kk + lk of staged row i
+            // is at the uniform column part of kk + lo + 2 i
+            const int lo = (lk >> 1) * rows64 * 2 + (lk & 1);
+            for (int c0 = 0; c0 < k0; c0 += 16 * nbt) {
+                const int nb = min(nbt, (k0 - c0) / 16);
+                stage_columns(A, nz, k0, m, c0, nb, rows64, smem, wvu, lane);
+                __builtin_amdgcn_s_waitcnt(0);   // this wave's direct loads are in LDS
+                __syncthreads();
+                for (int kb0 = 0; kb0 < 16 * nb; kb0 += 8) {
+                    // the operands of two K steps are read before their MFMAs
+                    double bv[2][2], av[2][Q];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int kk = kb0 + 4 * h;
+                        const int u = (kk >> 4) * rows64 * 16 + ((kk & 15) >> 1) * rows64 * 2 + lo;
+                        bv[h][0] = (li < kb) ? smem[u + 2 * li] : 0.0;
+                        bv[h][1] = (16 + li < kb) ? smem[u + 2 * (16 + li)] : 0.0;
+#pragma unroll
+                        for (int q = 0; q < Q; ++q) {
+                            const int i = 16 * (wv + 4 * q) + li;
+                            av[h][q] = (wv + 4 * q < nrb && i < m) ? -smem[u + 2 * i] : 0.0;
+                        }
+                    }
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int q = 0; q < Q; ++q) {
+                            if (wv + 4 * q < nrb) {
+                                acc[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h][q], bv[h][0], acc[q][0], 0, 0, 0);
+                                acc[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h][q], bv[h][1], acc[q][1], 0, 0, 0);
+                            }
+                        }
+                }
+                __syncthreads();
+            }
+        }
+        for (int t0 = 0; (nz & 1) && t0 < k0; t0 += CB) {
             // the loads of a half chunk go out together (clamped rows), then
             // the stores: two memory round trips per chunk
             for (int h = 0; 128 * h < m; ++h) {
@@ -130,19 +196,30 @@ __global__ __launch_bounds__(256, Q > 4 ? 1 : 2) void chol_solve_kernel(
                     if (rb < nrb && i < m) sP[i * CBP + j] = acc[q][cb][v];
                 }
         __syncthreads();
-        // Factor the kb x kb diagonal block in one wave and invert it.  Lane
-        // (bi, bj) = (lane / 8, lane % 8) holds the 4 x 4 blocks of rows
-        // 4 bi.., columns 4 bj.. of L (a) and of D = L^{-1} (dv).  Right-
-        // looking, the pivot steps unrolled by four so that register indices
-        // are static, with no branches (a partial block is padded with the
-        // identity): at pivot k,
-        // column k of L and row k of D are scaled by their owners and passed
-        // to every lane by cross-lane permutes, then rows > k of both are
-        // updated.
+        // Factor the kb x kb diagonal block in one wave and invert it, by
+        // 4 x 4 blocks.  Lane (bi, bj) = (lane / 8, lane % 8) holds block
+        // (bi, bj) of the panel's diagonal block (a, becoming L) and of the
+        // identity (x, becoming D = L^{-1}); a partial block is padded with
+        // the identity.  Right-looking over the diagonal blocks g:
+        //  * every lane factors its own 4 x 4 block in registers (only lane
+        //    (g, g)'s result is used): L_gg and D_gg = L_gg^{-1};
+        //  * the column below: L_ig = A_ig D_gg^T; block row g of D:
+        //    X_g = D_gg X_g;
+        //  * the trailing blocks: A_ij -= L_ig L_jg^T, X_ij -= L_ig X_gj.
+        // The blocks a lane needs from another pass through LDS (the panel's
+        // D buffer, written with its final value afterwards); a wave-scope
+        // fence pair orders each exchange (without it the compiler may run the
+        // readers' branch before the writers', the branches being exclusive
+        // within one lane).
         if (tid < 64) {
+            auto wave_sync = [] {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            };
             const int bi = tid >> 3, bj = tid & 7;
             const bool act = bi >= bj;
-            double a[4][4], dv[4][4];
+            double a[4][4], x[4][4];
             int bad = 0;   // first failing column of this block (wave-uniform)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
@@ -150,53 +227,141 @@ __global__ __launch_bounds__(256, Q > 4 ? 1 : 2) void chol_solve_kernel(
                 for (int c = 0; c < 4; ++c) {
                     const int i = 4 * bi + r, jj = 4 * bj + c;
                     a[r][c] = (act && i < kb && jj < kb && jj <= i) ? sP[i * CBP + jj] : (i == jj ? 1.0 : 0.0);
-                    dv[r][c] = (i == jj) ? 1.0 : 0.0;
+                    x[r][c] = (i == jj) ? 1.0 : 0.0;
                 }
-            for (int kb4 = 0; kb4 < CB / 4; ++kb4)
-#pragma unroll
-            for (int kr = 0; kr < 4; ++kr) {
-                const int k = 4 * kb4 + kr;
-                double d = readlane_d(a[kr][kr], kb4 * 9);   // lane of diagonal block (kb4, kb4)
-                const bool ok = d > 0.0 && isfinite(d);
-                bad = (!ok && bad == 0 && k < kb) ? k0 + k + 1 : bad;
-                d = ok ? d : 1.0;
-                // 1/sqrt(d) from the hardware estimate and two Newton steps
-                double inv = __builtin_amdgcn_rsq(d);
-                const double hd = 0.5 * d;
-                inv = inv * fma(-hd * inv, inv, 1.5);
-                inv = inv * fma(-hd * inv, inv, 1.5);
-                const double lkk = d * inv;
-                // colz: L[i][k] below the pivot, zero at and above it, so the
-                // rank-1 updates below need no masks (a zero factor leaves the
-                // finished rows and columns unchanged)
-                double colz[4], drow[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = 4 * bi + r;
-                    const double v = a[r][kr] * inv;
-                    colz[r] = (i > k) ? v : 0.0;
-                    if (bj == kb4) a[r][kr] = (i > k) ? v : ((i == k) ? lkk : a[r][kr]);
-                }
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const double v = dv[kr][c] * inv;   // D[k][4 bj + c], final
-                    drow[c] = v;
-                    if (bi == kb4) dv[kr][c] = v;
-                }
-                double ci[4], cj[4], dr[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    ci[q] = __shfl(colz[q], 8 * bi + kb4, 64);   // L[4 bi + q][k]
-                    cj[q] = __shfl(colz[q], 8 * bj + kb4, 64);   // L[4 bj + q][k]
-                    dr[q] = __shfl(drow[q], 8 * kb4 + bj, 64);  // D[k][4 bj + q]
-                }
+            double* sDg = sD;             // D_gg
+            double* sCol = sD + 16;       // [bi][16]: L_ig
+            double* sRow = sD + 16 * 9;   // [bj][16]: X_gj
+            for (int g = 0; g < 8; ++g) {
+                // 4 x 4 Cholesky of the lane's own block, and its inverse
+                double l[4][4], d[4][4];
+                int fail = 0;   // 1 + first failing pivot of the block, or 0
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        a[r][c] -= ci[r] * cj[c];
-                        dv[r][c] -= ci[r] * dr[c];
+                    for (int c = 0; c < 4; ++c) l[r][c] = a[r][c];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    double dk = l[k][k];
+                    const bool ok = dk > 0.0 && isfinite(dk);
+                    fail = (!ok && fail == 0) ? k + 1 : fail;
+                    dk = ok ? dk : 1.0;
+                    // 1/sqrt(dk) from the hardware estimate and two Newton steps
+                    double inv = __builtin_amdgcn_rsq(dk);
+                    const double hd = 0.5 * dk;
+                    inv = inv * fma(-hd * inv, inv, 1.5);
+                    inv = inv * fma(-hd * inv, inv, 1.5);
+                    l[k][k] = dk * inv;
+                    d[k][k] = inv;
+#pragma unroll
+                    for (int i = k + 1; i < 4; ++i) l[i][k] *= inv;
+#pragma unroll
+                    for (int i = k + 1; i < 4; ++i)
+#pragma unroll
+                        for (int j = k + 1; j <= i; ++j) l[i][j] -= l[i][k] * l[j][k];
+                }
+#pragma unroll
+                for (int i = 1; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < i; ++j) {
+                        double t = 0.0;
+#pragma unroll
+                        for (int k = j; k < i; ++k) t += l[i][k] * d[k][j];
+                        d[i][j] = -d[i][i] * t;
                     }
+                const int fg = __builtin_amdgcn_readlane(fail, 9 * g);
+                bad = (bad == 0 && fg != 0 && 4 * g + fg - 1 < kb) ? k0 + 4 * g + fg : bad;
+                if (bi == g && bj == g) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            a[r][c] = c <= r ? l[r][c] : 0.0;
+                            sDg[4 * r + c] = c <= r ? d[r][c] : 0.0;
+                        }
+                }
+                wave_sync();
+                double dg[4][4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) dg[r][c] = sDg[4 * r + c];
+                if (bi > g && bj == g) {   // L_ig = A_ig D_gg^T
+                    double t[4][4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            double v = 0.0;
+#pragma unroll
+                            for (int k = 0; k <= c; ++k) v += a[r][k] * dg[c][k];
+                            t[r][c] = v;
+                        }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            a[r][c] = t[r][c];
+                            sCol[16 * bi + 4 * r + c] = t[r][c];
+                        }
+                }
+                if (bi == g && bj <= g) {   // X_gj = D_gg X_gj
+                    double t[4][4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            double v = 0.0;
+#pragma unroll
+                            for (int k = 0; k <= r; ++k) v += dg[r][k] * x[k][c];
+                            t[r][c] = v;
+                        }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            x[r][c] = t[r][c];
+                            sRow[16 * bj + 4 * r + c] = t[r][c];
+                        }
+                }
+                wave_sync();
+                if (bi > g) {
+                    double li[4][4], lj[4][4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) li[r][c] = sCol[16 * bi + 4 * r + c];
+                    if (bj > g && act) {   // A_ij -= L_ig L_jg^T
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) lj[r][c] = sCol[16 * bj + 4 * r + c];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) {
+                                double v = a[r][c];
+#pragma unroll
+                                for (int k = 0; k < 4; ++k) v -= li[r][k] * lj[c][k];
+                                a[r][c] = v;
+                            }
+                    } else if (bj <= g) {   // X_ij -= L_ig X_gj
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) lj[r][c] = sRow[16 * bj + 4 * r + c];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) {
+                                double v = x[r][c];
+#pragma unroll
+                                for (int k = 0; k < 4; ++k) v -= li[r][k] * lj[k][c];
+                                x[r][c] = v;
+                            }
+                    }
+                }
+                wave_sync();   // every read of this step before the next step's writes
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r)
@@ -204,7 +369,7 @@ __global__ __launch_bounds__(256, Q > 4 ? 1 : 2) void chol_solve_kernel(
                 for (int c = 0; c < 4; ++c) {
                     const int i = 4 * bi + r, jj = 4 * bj + c;
                     if (act && i < kb && jj <= i) sP[i * CBP + jj] = a[r][c];
-                    sD[i * CBP + jj] = act ? dv[r][c] : 0.0;
+                    sD[i * CBP + jj] = act ? x[r][c] : 0.0;
                 }
             if (tid == 0 && bad != 0 && s_bad == 0) s_bad = bad;
         }
