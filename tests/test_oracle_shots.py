@@ -5,6 +5,11 @@
   seeded model (odd and even N, with and without the evanescent cut);
 * a single plane-wave shot record lands on exactly the row of its (a, b) key,
   with value dx N^2;
+* 3D areal (Section 2.2): brute-force Born records of the doubled periodic
+  survey (the N-periodic model repeated 2 x 2 times on the 2N x 2N grid) go
+  to the rows of every k_m, odd components included; a plane-wave record of
+  the doubled survey lands on the rows whose half-grid wavenumbers are its
+  own, with value d_mid^2 (2N)^4 / 4;
 * model_from_spectrum inverts the spectrum that defines the seeded model, in
   2D and 3D.
 """
@@ -12,7 +17,7 @@ import numpy as np
 import pytest
 
 from edt_inputs import make_custom, vhat
-from oracle.born import born_2d
+from oracle.born import born_2d, born_3d
 from oracle.rows import plan
 from oracle.shots import model_from_spectrum, shots_to_rows
 from oracle.solve import gtables, forward
@@ -56,3 +61,56 @@ def test_model_from_its_spectrum():
     assert np.allclose(model_from_spectrum(s2, vhat(s2)), s2.v_true, rtol=0, atol=1e-13)
     s3 = make_custom(dim=3, N=8, Nh=4, nz=5, dx=25.0, freqs=(3.0,), vel=(2000.0,), seed=4)
     assert np.allclose(model_from_spectrum(s3, vhat(s3)), s3.v_true, rtol=0, atol=1e-13)
+
+
+def _signed(u, N):
+    return u if u < (N + 1) // 2 else u - N
+
+
+@pytest.mark.parametrize("N,vel,zif", [(8, (1800.0, 2500.0), (40.0,)), (5, (2100.0, 1700.0, 2900.0), (30.0, 70.0))])
+def test_areal_born_records_give_the_rows(N, vel, zif):
+    s = make_custom(dim=3, N=N, Nh=N // 2 + 1, nz=3, dx=30.0, dz=25.0, freqs=(6.0, 9.0), vel=vel, zif=zif,
+                    kappa=100.0, seed=11)
+    pl = plan(s)
+    clean = forward(s, pl, vhat(s), gtables(s, pl))
+    M = 2 * N
+    V2 = np.tile(s.v_true, (2, 2, 1))
+    D = np.stack([born_3d(s.vel, s.zif, f, s.eps, V2, s.d_mid, s.z, s.dz).reshape(M, M, M, M)
+                  for f in s.freqs])
+    rows = shots_to_rows(s, pl, D)
+    scale = max(np.max(np.abs(d0)) for d0, _ in clean if d0.size)
+    odd = 0
+    for p, (d0, d1), (e0, e1) in zip(pl.pairs, clean, rows):
+        assert np.max(np.abs(e0 - d0), initial=0) <= 1e-12 * scale
+        assert np.max(np.abs(e1 - d1), initial=0) <= 1e-12 * scale
+        ux, uy = divmod(p.u, N)
+        odd += (ux % 2 or uy % 2) * d0.size
+    assert odd > 0
+
+
+def test_areal_plane_wave_lands_on_its_rows():
+    N = 6
+    M = 2 * N
+    s = make_custom(dim=3, N=N, Nh=N, nz=2, dx=20.0, freqs=(7.0,), vel=(2000.0,), kappa=100.0)
+    pl = plan(s)
+    a0, b0 = (3, 1), (7, 5)      # receiver and source wavenumber indices on the 2N grid (a - b = 4n)
+    g = np.arange(M)
+    ph = (a0[0] * g[:, None, None, None] + a0[1] * g[None, :, None, None]
+          + b0[0] * g[None, None, :, None] + b0[1] * g[None, None, None, :])
+    D = np.exp(2j * np.pi * ph / M)[None]
+    rows = shots_to_rows(s, pl, D)
+    peak = s.d_mid ** 2 * M ** 4 / 4.0
+    hits = 0
+    for p, (d0, d1) in zip(pl.pairs, rows):
+        ux, uy = divmod(p.u, N)
+        q = np.array([_signed(ux, N), _signed(uy, N)])
+        n = p.key0[:, 1]
+        nv = np.stack([n // s.n_off - s.n_off // 2, n % s.n_off - s.n_off // 2], axis=1)
+        r0, s0 = (q + 2 * nv) % M, (q - 2 * nv) % M           # +k_m datum
+        r1, s1 = (-s0) % M, (-r0) % M                         # -k_m datum
+        for r, sv, d in ((r0, s0, d0), (r1, s1, d1)):
+            at = np.all(r == a0, axis=1) & np.all(sv == b0, axis=1)
+            want = np.where(at, peak, 0.0)
+            assert np.max(np.abs(d - want), initial=0) <= 1e-10 * peak
+            hits += int(at.sum())
+    assert hits >= 1
