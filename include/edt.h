@@ -429,20 +429,35 @@ edt_status edt_kz_restrict(const edt_plan* plan, double k_disk, double* gram, do
 
 /*
  * The transforms on either side of the decoupled problems (Section 2.1), for
- * the 2D line survey (EDT_EINVAL for dim 3 and for n_mid > 2048).
+ * the 2D line survey and the 3D areal survey (Section 2.2); EDT_EINVAL for the
+ * survey of parallel lines, for n_mid > 2048 (2D) and for n_mid > 128 (3D).
  *
- * edt_shots_fft: shots[n_freq][n_mid][n_mid] (complex128, device; [f][R][S],
+ * edt_shots_fft, 2D: shots[n_freq][n_mid][n_mid] (complex128, device; [f][R][S],
  * the record of the source at x_S = S d_mid by the receiver at x_R, at the
  * plan's frequency f) is overwritten by its transform
  *     d~[f][a][b] = d_mid sum_{R,S} D[f][R][S] exp(-2 pi i (a R + b S) / n_mid),
  * the data convention of every other call (a, b: receiver and source
  * wavenumber indices in fftfreq order).  One pass over the records per axis.
  *
+ * edt_shots_fft, 3D areal: a row of k_m index q and k_h index n has receiver
+ * and source wavenumbers q + 2n and q - 2n per axis in units of dk/2
+ * (dk = 2 pi / (n_mid d_mid)): half-grid wavenumbers, which are whole-grid
+ * ones of a survey of twice the period.  The records are therefore those of
+ * the full-coverage periodic areal survey on the 2 n_mid x 2 n_mid grid of
+ * spacing d_mid: shots[n_freq][M][M][M][M], M = 2 n_mid, [f][Rx][Ry][Sx][Sy]
+ * (16 M^4 bytes per frequency: 69 GB at n_mid = 128), overwritten by
+ *     F[f][a][b] = d_mid^2 sum_{R,S} D[f][R][S] exp(-2 pi i (a.R + b.S) / M)
+ * (a, b: 2-vectors).  One pass over the records per axis.
+ *
  * edt_shots_pack: d_rows[n_rows][2] (device, the plan's data type) from that
- * spectrum: row r with frequency f and key (a, b) (edt_plan_rowmap) gets
- * (d~[f][a][b], d~[f][-b][-a]), the datum at +k_m and its -k_m partner.  The spectrum is
- * only read, so the plans of several pair ranges (batches) of one survey can
- * each pack from one transform.
+ * spectrum.  2D: row r with frequency f and key (a, b) (edt_plan_rowmap) gets
+ * (d~[f][a][b], d~[f][-b][-a]), the datum at +k_m and its -k_m partner.  3D
+ * areal: row r of the pair with k_m index q and of k_h index n gets
+ * (F[f][a][b], F[f][-b][-a]) / 4 with a = q + 2n, b = q - 2n (mod M per
+ * axis): the N-periodic model has on the doubled grid a spectrum at even
+ * indices only, 4 times its own.  The spectrum is only read, so the plans of
+ * several pair ranges (batches) of one survey can each pack from one
+ * transform.
  */
 edt_status edt_shots_fft(const edt_plan* plan, edt_c128* shots, hipStream_t stream);
 edt_status edt_shots_pack(const edt_plan* plan, const edt_c128* spectrum, void* d_rows, hipStream_t stream);

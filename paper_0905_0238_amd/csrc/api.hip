@@ -565,6 +565,26 @@ edt_status edt_kz_restrict(const edt_plan* p, double k_disk, double* gram, doubl
     return EDT_OK;
 }
 
+namespace {
+// Surveys whose shot records the transform takes: the 2D line, and the 3D
+// areal survey up to n_mid = kMaxAreal (its doubled records).
+edt_status check_records(const edt_plan* p, bool transform) {
+    if (p->dim == 3 && p->n_line > 0) {
+        set_error("shot records of the 2D line and the 3D areal survey only");
+        return EDT_EINVAL;
+    }
+    if (p->dim == 3 && p->n_mid > kMaxAreal) {
+        set_error("3D areal records: n_mid > " + std::to_string(kMaxAreal) + " is not supported");
+        return EDT_EINVAL;
+    }
+    if (transform && p->n_mid > kMaxLine) {
+        set_error("n_mid > " + std::to_string(kMaxLine) + " is not supported by the transform");
+        return EDT_EINVAL;
+    }
+    return EDT_OK;
+}
+}  // namespace
+
 edt_status edt_shots_fft(const edt_plan* p, edt_c128* shots, hipStream_t stream) {
     edt_status s = check_plan(p);
     if (s != EDT_OK) return s;
@@ -572,14 +592,8 @@ edt_status edt_shots_fft(const edt_plan* p, edt_c128* shots, hipStream_t stream)
         set_error("missing argument");
         return EDT_EINVAL;
     }
-    if (p->dim != 2) {
-        set_error("shot records of the 2D line survey only");
-        return EDT_EINVAL;
-    }
-    if (p->n_mid > kMaxLine) {
-        set_error("n_mid > " + std::to_string(kMaxLine) + " is not supported by the transform");
-        return EDT_EINVAL;
-    }
+    s = check_records(p, true);
+    if (s != EDT_OK) return s;
     EDT_TRY(launch_shots_fft(p, reinterpret_cast<zd*>(shots), stream), "shots fft");
     return EDT_OK;
 }
@@ -591,10 +605,8 @@ edt_status edt_shots_pack(const edt_plan* p, const edt_c128* spectrum, void* d_r
         set_error("missing argument");
         return EDT_EINVAL;
     }
-    if (p->dim != 2) {
-        set_error("shot records of the 2D line survey only");
-        return EDT_EINVAL;
-    }
+    s = check_records(p, false);
+    if (s != EDT_OK) return s;
     EDT_TRY(launch_shots_pack(p, reinterpret_cast<const zd*>(spectrum), d_rows, stream),
             "shots pack");
     return EDT_OK;

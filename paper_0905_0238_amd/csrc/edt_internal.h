@@ -42,6 +42,8 @@ constexpr int kMaxAdjointDepth = 256;
 // Refinement sweeps of one solve at most (device counters per sweep).
 constexpr int kMaxRefine = 62;
 constexpr int kMaxLine = 2048;   // longest 1D transform of the shot-record and model transforms
+constexpr int kMaxAreal = 128;   // largest n_mid of the 3D areal records (16 (2 n_mid)^4 bytes per frequency)
+constexpr int64_t kMaxLineBlocks = int64_t(1) << 16;   // workgroups of one transform launch
 constexpr int kMaxSignIter = 200;   // sign-iteration steps of the truncated-SVD solve at most
 constexpr int n_super(int nz) { return (nz + kSuperDepth - 1) / kSuperDepth; }
 constexpr int rpart_width(int nz) { return 2 * nz + n_super(nz); }

@@ -1,6 +1,10 @@
 // The transforms on either side of the decoupled problems (paper Section
-// 2.1): shot records of the 2D line survey to the packed wavenumber-domain
-// rows, and the solution spectrum V~ to the model V(x, z).
+// 2.1): shot records to the packed wavenumber-domain rows, and the solution
+// spectrum V~ to the model V(x, z).  The records are those of the 2D line
+// survey, [f][R][S], or of the 3D areal survey (Section 2.2) on the doubled
+// periodic 2N x 2N grid, [f][Rx][Ry][Sx][Sy]: a row's receiver and source
+// wavenumbers q +- 2n (units of dk/2) are half-grid wavenumbers of the N
+// grid and whole-grid ones of a survey of twice the period.
 //
 // Both are batches of 1D discrete Fourier transforms along one axis of a
 // dense array, done one line (or a few adjacent lines) per block in LDS:
@@ -21,13 +25,13 @@ constexpr size_t kLineLds = 80 * 1024;   // LDS of one block, values and twiddle
 
 template <bool POW2>
 __global__ __launch_bounds__(256) void dft_lines_kernel(zd* __restrict__ data, int n, int logn, Lines g, int L,
-                                                        double sign, double scale) {
+                                                        int64_t line0, double sign, double scale) {
     extern __shared__ zd s_mem[];
     const int ns = lds_stride(n);
     zd* s_x = s_mem;            // L lines of n values (padded layout)
     zd* s_w = s_mem + L * ns;   // twiddles: n / 2 (radix 2) or n (direct)
     const int tid = threadIdx.x;
-    const int64_t l0 = int64_t(blockIdx.x) * L;
+    const int64_t l0 = line0 + int64_t(blockIdx.x) * L;
     const int64_t base0 = (l0 / g.per_slab) * g.slab + (l0 % g.per_slab) * g.step;
     const bool adjacent = g.step == 1;
     const int nw = POW2 ? n / 2 : n;
@@ -84,6 +88,40 @@ __global__ __launch_bounds__(256) void rows_gather_kernel(const zd* __restrict__
     store_datum(d_rows, 2 * r + 1, F[base + int64_t(a1) * N + b1]);
 }
 
+// 3D areal: one block per pair, k_m index q = (qx, qy) (signed); row r with
+// frequency f and k_h index n = (nx, ny) reads the doubled survey's spectrum
+// F[f][a][b] at a = q + 2n, b = q - 2n (mod M = 2N per axis), and the -k_m
+// partner at (-b, -a); both are 4 times the row's data (the N-periodic model
+// has on the 2N grid a spectrum at even indices only, 4 times its own).
+template <class D>
+__global__ __launch_bounds__(256) void rows_gather_areal_kernel(const zd* __restrict__ F,
+                                                                const uint32_t* __restrict__ rows,
+                                                                const int32_t* __restrict__ keys,
+                                                                const int64_t* __restrict__ row_off,
+                                                                const int32_t* __restrict__ pair_u, int N, int Nh,
+                                                                D* __restrict__ d_rows) {
+    const int64_t pq = blockIdx.x;
+    const int u = pair_u[2 * pq];
+    const int ux = u / N, uy = u % N;
+    const int qx = ux < (N + 1) / 2 ? ux : ux - N, qy = uy < (N + 1) / 2 ? uy : uy - N;
+    const int M = 2 * N;
+    const int64_t M2 = int64_t(M) * M;
+    auto wrap = [M](int v) { return ((v % M) + M) % M; };
+    auto at = [&](int64_t f, int ax, int ay, int bx, int by) {
+        return f * M2 * M2 + (int64_t(ax) * M + ay) * M2 + int64_t(bx) * M + by;
+    };
+    const int nlo = Nh / 2;
+    for (int64_t r = row_off[pq] + threadIdx.x; r < row_off[pq + 1]; r += 256) {
+        const int64_t f = rows[2 * r];
+        const int n = keys[2 * r];
+        const int nx = n / Nh - nlo, ny = n % Nh - nlo;
+        const int ax = wrap(qx + 2 * nx), ay = wrap(qy + 2 * ny);
+        const int bx = wrap(qx - 2 * nx), by = wrap(qy - 2 * ny);
+        store_datum(d_rows, 2 * r, 0.25 * F[at(f, ax, ay, bx, by)]);
+        store_datum(d_rows, 2 * r + 1, 0.25 * F[at(f, wrap(-bx), wrap(-by), wrap(-ax), wrap(-ay))]);
+    }
+}
+
 __global__ __launch_bounds__(256) void real_part_kernel(const zd* __restrict__ v, int64_t n, double* __restrict__ out) {
     const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (i < n) out[i] = v[i].x;
@@ -112,15 +150,21 @@ hipError_t launch_lines(zd* data, int n, int64_t n_slabs, Lines g, double sign, 
     if (lds > kLineLds) return hipErrorInvalidValue;
     int logn = 0;
     while ((1 << logn) < n) ++logn;
+    // A grid holds fewer than 2^32 work-items: a large batch is launched in
+    // runs of blocks (each block's L lines lie in one slab).
     const int64_t blocks = n_slabs * (g.per_slab / L);
-    if (blocks <= 0) return hipSuccess;
-    if (p2)
-        hipLaunchKernelGGL(dft_lines_kernel<true>, dim3(unsigned(blocks)), dim3(256), lds, st, data, n, logn, g, L,
-                           sign, scale);
-    else
-        hipLaunchKernelGGL(dft_lines_kernel<false>, dim3(unsigned(blocks)), dim3(256), lds, st, data, n, logn, g,
-                           L, sign, scale);
-    return hipGetLastError();
+    for (int64_t b0 = 0; b0 < blocks; b0 += kMaxLineBlocks) {
+        const unsigned nb = unsigned(std::min(kMaxLineBlocks, blocks - b0));
+        if (p2)
+            hipLaunchKernelGGL(dft_lines_kernel<true>, dim3(nb), dim3(256), lds, st, data, n, logn, g, L, b0 * L,
+                               sign, scale);
+        else
+            hipLaunchKernelGGL(dft_lines_kernel<false>, dim3(nb), dim3(256), lds, st, data, n, logn, g, L, b0 * L,
+                               sign, scale);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t configure_lines() {
@@ -132,9 +176,20 @@ hipError_t configure_lines() {
     return hipSuccess;
 }
 
-// shots[f][R][S] <- dx * DFT over R and S (forward sign).
+// shots[f][R][S] <- dx * DFT over R and S (forward sign); 3D areal:
+// shots[f][Rx][Ry][Sx][Sy] (M = 2N per axis) <- dx^2 * DFT over all four.
 hipError_t launch_shots_fft(const edt_plan* p, zd* shots, hipStream_t st) {
     const int N = p->n_mid;
+    if (p->dim == 3) {
+        const int M = 2 * N;
+        const int64_t M2 = int64_t(M) * M, M3 = M2 * M, nf = p->n_freq;
+        hipError_t e = launch_lines(shots, M, nf * M2, Lines{M2, M, 1, M}, -1.0, 1.0, st);   // along Sy
+        if (e == hipSuccess) e = launch_lines(shots, M, nf * M2, Lines{M2, 1, M, M}, -1.0, 1.0, st);   // Sx
+        if (e == hipSuccess) e = launch_lines(shots, M, nf * M, Lines{M3, 1, M2, int(M2)}, -1.0, 1.0, st);   // Ry
+        if (e == hipSuccess)
+            e = launch_lines(shots, M, nf, Lines{M3 * M, 1, M3, int(M3)}, -1.0, p->d_mid * p->d_mid, st);   // Rx
+        return e;
+    }
     const int64_t NN = int64_t(N) * N;
     hipError_t e = launch_lines(shots, N, p->n_freq, Lines{NN, N, 1, N}, -1.0, 1.0, st);   // along S
     if (e != hipSuccess) return e;
@@ -143,6 +198,20 @@ hipError_t launch_shots_fft(const edt_plan* p, zd* shots, hipStream_t st) {
 
 hipError_t launch_shots_pack(const edt_plan* p, const zd* F, void* d_rows, hipStream_t st) {
     if (p->n_rows == 0) return hipSuccess;
+    if (p->dim == 3) {
+        const unsigned np = unsigned(p->n_pairs);
+        if (p->data_c64)
+            hipLaunchKernelGGL(rows_gather_areal_kernel<float2>, dim3(np), dim3(256), 0, st, F,
+                               dptr<const uint32_t>(p, p->lay.rows), dptr<const int32_t>(p, p->lay.keys),
+                               dptr<const int64_t>(p, p->lay.row_off), dptr<const int32_t>(p, p->lay.pair_u),
+                               p->n_mid, p->n_off, static_cast<float2*>(d_rows));
+        else
+            hipLaunchKernelGGL(rows_gather_areal_kernel<zd>, dim3(np), dim3(256), 0, st, F,
+                               dptr<const uint32_t>(p, p->lay.rows), dptr<const int32_t>(p, p->lay.keys),
+                               dptr<const int64_t>(p, p->lay.row_off), dptr<const int32_t>(p, p->lay.pair_u),
+                               p->n_mid, p->n_off, static_cast<zd*>(d_rows));
+        return hipGetLastError();
+    }
     const unsigned blocks = unsigned((p->n_rows + 255) / 256);
     if (p->data_c64)
         hipLaunchKernelGGL(rows_gather_kernel<float2>, dim3(blocks), dim3(256), 0, st, F,

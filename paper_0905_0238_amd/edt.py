@@ -84,6 +84,7 @@ class Plan:
         self.nz = int(survey.nz)
         self.dim = int(getattr(survey, "dim", 2))
         self.n_mid = int(survey.n_mid)
+        self.n_line = int(getattr(survey, "n_line", 0))
         self.n_freq = int(info.n_freq)
         self.n_km = int(info.n_km)
         self.n_pairs = int(info.n_pairs)
@@ -305,15 +306,33 @@ class Plan:
                                                _stream()), "edt_kz_restrict")
         return n_keep
 
+    def records_shape(self):
+        """Shape of the shot records: (n_freq, N, N) [f, receiver, source] on the
+        2D line; (n_freq, 2N, 2N, 2N, 2N) [f, Rx, Ry, Sx, Sy] for the 3D areal
+        survey (the doubled periodic survey, whose whole-grid wavenumbers are
+        the rows' half-grid ones)."""
+        if self.n_line:
+            raise ValueError("shot records of the 2D line and the 3D areal survey only")
+        if self.dim == 3:
+            return (self.n_freq,) + (2 * self.n_mid,) * 4
+        return (self.n_freq, self.n_mid, self.n_mid)
+
+    def _check_records(self, t, what):
+        want = int(np.prod(self.records_shape()))
+        if t.dtype != torch.complex128 or not t.is_cuda or not t.is_contiguous() or t.numel() != want:
+            raise ValueError(f"{what}: a contiguous complex128 device tensor of shape {self.records_shape()}")
+
     def shots_fft(self, shots):
-        """In place: shots[n_freq, N, N] (complex128, [f, receiver, source]) becomes
-        d_mid times its DFT over receivers and sources."""
+        """In place: the shot records (records_shape(), complex128) become their
+        DFT over receivers and sources, times d_mid per axis."""
+        self._check_records(shots, "shots_fft")
         self.upload()
         _lib.check(_lib.load().edt_shots_fft(self._h, _ptr(shots), _stream()), "edt_shots_fft")
         return shots
 
     def shots_pack(self, spectrum, out=None):
         """d_rows[R, 2] (the plan's data type) of this plan's rows from a shots_fft spectrum."""
+        self._check_records(spectrum, "shots_pack")
         self.upload()
         d = self._rows(out) if out is not None else self._data_rows()
         _lib.check(_lib.load().edt_shots_pack(self._h, _ptr(spectrum), _ptr(d), _stream()), "edt_shots_pack")

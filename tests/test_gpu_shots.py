@@ -10,15 +10,24 @@
   nz = 200 grid; bar 1e-12 of the largest model value;
 * end to end on a small survey: shot records -> rows -> FP64 solve -> model,
   against the oracle's solve and model, to the FP64 bar 1e-10;
-* 3D shot records are refused.
+* 3D areal survey: seeded random records of the doubled periodic survey
+  [f, Rx, Ry, Sx, Sy] (2N per axis) -> packed rows, for 2N a power of two,
+  even and odd, with the evanescent cut, in complex64 rows, and at 2N = 64
+  (whose first pass takes two launches); brute-force Born records of the
+  repeated model -> the oracle's clean rows; records -> rows -> FP64 solve ->
+  model end to end (bar 1e-10); the survey of parallel lines and n_mid above
+  128 are refused.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
-from edt_inputs import make_config, make_custom
+from edt_inputs import make_config, make_custom, make_lines, vhat
+from oracle.born import born_3d
 from oracle.rows import plan as oracle_plan
 from oracle.shots import model_from_spectrum, shots_to_rows
-from oracle.solve import pack
+from oracle.solve import forward, gtables, pack
 from tests._cases import oracle_case, layered_small
 
 torch = pytest.importorskip("torch")
@@ -118,18 +127,115 @@ def test_end_to_end_from_shot_records():
     assert err <= 1e-10
 
 
-def test_shot_records_of_3d_surveys_are_refused():
-    s = make_custom(dim=3, N=12, Nh=6, nz=5, dx=25.0, freqs=(5.0,), vel=(2000.0,))
+def _areal_cases():
+    kw = dict(dim=3, nz=3, dx=30.0, dz=25.0, vel=(1800.0, 2500.0), zif=(40.0,), seed=5)
+    return {
+        "N8-radix2": lambda: make_custom(N=8, Nh=4, freqs=(6.0, 9.0), kappa=100.0, **kw),
+        "N6-direct": lambda: make_custom(N=6, Nh=6, freqs=(6.0, 9.0, 12.0), kappa=100.0, **kw),
+        "N5-odd": lambda: make_custom(N=5, Nh=3, freqs=(7.0,), kappa=100.0, **kw),
+        "N16-cut": lambda: make_custom(N=16, Nh=8, freqs=(6.0, 11.0), kappa=1.0, **kw),
+        "N32-two-launches": lambda: make_custom(N=32, Nh=16, freqs=(5.0, 8.0), kappa=1.0, **kw),
+    }
+
+
+def _areal_records(s, seed):
+    rng = np.random.default_rng(seed)
+    shape = (len(s.freqs),) + (2 * s.n_mid,) * 4
+    return rng.normal(size=shape) + 1j * rng.normal(size=shape)
+
+
+@pytest.mark.parametrize("name", list(_areal_cases()))
+def test_areal_shot_records_to_rows(name):
+    s = _areal_cases()[name]()
+    pl = oracle_plan(s)
+    D = _areal_records(s, 29)
     p = E.Plan(s)
-    sh = torch.zeros(1, 12, 12, dtype=torch.complex128, device="cuda")
-    with pytest.raises(RuntimeError, match="2D line survey"):
-        p.shots_fft(sh)
+    assert p.records_shape() == D.shape
+    _check_rows(name, pl, _gpu_rows(p, D), shots_to_rows(s, pl, D))
+
+
+def test_areal_shot_records_to_complex64_rows():
+    s = _areal_cases()["N8-radix2"]()
+    pl = oracle_plan(s)
+    D = _areal_records(s, 31)
+    p = E.Plan(s, data="c64")
+    d = _gpu_rows(p, D)
+    assert d.dtype == np.complex64
+    ref, _ = pack(pl, shots_to_rows(s, pl, D))
+    scale = np.max(np.abs(ref))
+    # the library rounds its FP64 datum once
+    err = np.max(np.abs(d.astype(np.complex128) - ref))
+    assert err <= 1.2e-7 * scale, err / scale
+
+
+def test_areal_born_records_give_the_oracle_rows():
+    """Brute-force Born records of the N-periodic model repeated 2 x 2 times
+    on the doubled grid: the GPU rows equal the oracle's clean rows."""
+    s = make_custom(dim=3, N=8, Nh=4, nz=3, dx=30.0, dz=25.0, freqs=(6.0, 9.0), vel=(1800.0, 2500.0),
+                    zif=(40.0,), kappa=100.0, seed=7)
+    pl = oracle_plan(s)
+    clean = forward(s, pl, vhat(s), gtables(s, pl))
+    M = 2 * s.n_mid
+    V2 = np.tile(s.v_true, (2, 2, 1))
+    D = np.stack([born_3d(s.vel, s.zif, f, s.eps, V2, s.d_mid, s.z, s.dz).reshape(M, M, M, M)
+                  for f in s.freqs])
+    _check_rows("3D Born records", pl, _gpu_rows(E.Plan(s), D), clean)
+
+
+def test_areal_end_to_end_from_shot_records():
+    """Doubled-survey records whose transform holds 4 times the oracle's noisy
+    data at the rows' keys (zero elsewhere) -> GPU transform, pack, FP64
+    solve and model, against the oracle's solve and model."""
+    s = make_custom(dim=3, N=8, Nh=4, nz=12, dx=30.0, dz=15.0, freqs=(5.0, 8.0, 11.0, 14.0),
+                    vel=(1800.0, 2500.0), zif=(60.0,), kappa=1.0, noise_rel=0.05, seed=13)
+    r = oracle_case(s)
+    N, M, nh = s.n_mid, 2 * s.n_mid, s.n_off
+    F = np.zeros((len(s.freqs),) + (M,) * 4, np.complex128)
+    for p_, (d0, d1) in zip(r["pl"].pairs, r["data"]):
+        ux, uy = divmod(p_.u, N)
+        qx, qy = (ux if ux < (N + 1) // 2 else ux - N), (uy if uy < (N + 1) // 2 else uy - N)
+        n = p_.key0[:, 1]
+        nx, ny = n // nh - nh // 2, n % nh - nh // 2
+        ax, ay, bx, by = (qx + 2 * nx) % M, (qy + 2 * ny) % M, (qx - 2 * nx) % M, (qy - 2 * ny) % M
+        F[p_.f, ax, ay, bx, by] = 4.0 * d0
+        F[p_.f, (-bx) % M, (-by) % M, (-ax) % M, (-ay) % M] = 4.0 * d1
+    D = np.fft.ifftn(F, axes=(1, 2, 3, 4)) / s.d_mid ** 2
+    p = E.Plan(s)
+    vel = torch.tensor(np.asarray(s.vel, np.float64), device="cuda")
+    sh = torch.from_numpy(D).cuda()
+    p.shots_fft(sh)
+    d = p.shots_pack(sh)
+    out = p.run(vel, d, s.lambda_rel, prec="fp64")
+    m = p.model(out["v"])
+    torch.cuda.synchronize()
+    ref = model_from_spectrum(s, r["V"])
+    err = np.max(np.abs(m.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    print(f"3D end to end: model error {err:.2e}")
+    assert err <= 1e-10
+
+
+def test_records_of_line_surveys_and_large_areal_grids_are_refused():
+    from paper_0905_0238_amd import _lib
+    sl = make_lines(Nx=16, Ny=4, nz=4, freqs=(6.0,))
+    pl_ = E.Plan(sl)
+    pl_.upload()
+    with pytest.raises(ValueError, match="3D areal survey only"):
+        pl_.records_shape()
+    buf = torch.zeros(16, dtype=torch.complex128, device="cuda")
+    st = _lib.load().edt_shots_fft(pl_._h, ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(0))
+    assert st == _lib.EDT_EINVAL
+    sa = make_custom(dim=3, N=130, Nh=2, nz=2, dx=25.0, freqs=(5.0,), vel=(2000.0,), kappa=1.0, model="zero")
+    pa = E.Plan(sa)
+    pa.upload()
+    st = _lib.load().edt_shots_fft(pa._h, ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(0))
+    assert st == _lib.EDT_EINVAL
+    torch.cuda.synchronize()
 
 
 def test_transforms_longer_than_2048_are_refused():
     s = make_custom(N=2050, nz=2, dx=5.0, freqs=(5.0,), vel=(2000.0,), model="zero")
     p = E.Plan(s)
-    sh = torch.zeros(1, 1, 1, dtype=torch.complex128, device="cuda")
+    sh = torch.zeros(1, 2050, 2050, dtype=torch.complex128, device="cuda")
     with pytest.raises(RuntimeError, match="n_mid > 2048"):
         p.shots_fft(sh)
     v = torch.zeros(p.n_km, s.nz, dtype=torch.complex128, device="cuda")
