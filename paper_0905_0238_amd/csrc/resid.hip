@@ -13,9 +13,10 @@
 //
 // Layout: a 256-thread block per work item; each wave takes its own rows,
 // lanes span depth (ZPL depths per lane).  A x needs a sum over depth per
-// row: four rows at a time (two beyond 256 depths) are reduced with a
-// transposing butterfly of lane swaps and DPP moves, so a row costs about one
-// cross-lane exchange per lane instead of six.
+// row: two rows at a time are reduced with a transposing butterfly of lane
+// swaps and DPP moves, so a row costs about one cross-lane exchange per lane
+// instead of six.  Up to 256 depths the table columns of a wave's next two
+// rows are loaded while the current two compute.
 
 #include "dev_common.h"
 
@@ -47,47 +48,13 @@ constexpr int kDppRowHalfMirror = 0x141;   // lane i <- lane 7 - i of its half r
 constexpr int kDppQuadXor2 = 0x4E;         // quad_perm [2, 3, 0, 1]
 constexpr int kDppQuadXor1 = 0xB1;         // quad_perm [1, 0, 3, 2]
 
-// Sum each of 16 per-lane values over the 64 lanes; every lane receives all
-// 16 totals.  Four halving steps leave lane l with the partial total of
-// index 8*b5 + 4*b4 + 2*b3 + b2 (b = bits of l): the lane swaps pair l with
-// l ^ 32 and l ^ 16, the row mirrors pair l with a lane of the other bit-3
-// (bit-2) half of its row (half row); two quad exchanges finish the sum.
-// No step goes through LDS.  The input array is overwritten.
-__device__ __forceinline__ void butterfly16(double (&a)[16], double (&out)[16], int lane) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {   // bit 5: lanes 0..31 keep index i, lanes 32..63 index i + 8
-        double x = a[i], y = a[i + 8];
-        swap32_d(x, y);
-        a[i] = x + y;
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {   // bit 4
-        double x = a[i], y = a[i + 4];
-        swap16_d(x, y);
-        a[i] = x + y;
-    }
-    const bool b3 = lane & 8, b2 = lane & 4;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {   // bit 3
-        const double lo = a[i] + dpp_d<kDppRowMirror>(a[i]);
-        const double hi = a[i + 2] + dpp_d<kDppRowMirror>(a[i + 2]);
-        a[i] = b3 ? hi : lo;
-    }
-    {   // bit 2
-        const double lo = a[0] + dpp_d<kDppRowHalfMirror>(a[0]);
-        const double hi = a[1] + dpp_d<kDppRowHalfMirror>(a[1]);
-        a[0] = b2 ? hi : lo;
-    }
-    double s = a[0];
-    s += dpp_d<kDppQuadXor2>(s);
-    s += dpp_d<kDppQuadXor1>(s);
-#pragma unroll
-    for (int k = 0; k < 16; ++k) out[k] = readlane_d(s, k << 2);
-}
-
-// The same for 8 values (two rows): three halving steps leave lane l with
-// index 4*b5 + 2*b4 + b3; the half-row mirror (which flips bits 0-2) and two
-// quad exchanges sum the 8 lanes of each group.
+// Sum each of 8 per-lane values (two rows' four partial dot products) over
+// the 64 lanes; every lane receives all 8 totals.  Three halving steps leave
+// lane l with the partial total of index 4*b5 + 2*b4 + b3 (b = bits of l):
+// the lane swaps pair l with l ^ 32 and l ^ 16, the row mirror pairs l with a
+// lane of the other bit-3 half of its row; the half-row mirror (which flips
+// bits 0-2) and two quad exchanges sum the 8 lanes of each group.  No step
+// goes through LDS.  The input array is overwritten.
 __device__ __forceinline__ void butterfly8(double (&a)[8], double (&out)[8], int lane) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {   // bit 5
@@ -112,12 +79,6 @@ __device__ __forceinline__ void butterfly8(double (&a)[8], double (&out)[8], int
     for (int k = 0; k < 8; ++k) out[k] = readlane_d(s, k << 3);
 }
 
-template <int NV>
-__device__ __forceinline__ void butterfly(double (&a)[NV], double (&out)[NV], int lane) {
-    static_assert(NV == 8 || NV == 16, "two or four rows");
-    if constexpr (NV == 16) butterfly16(a, out, lane);
-    else butterfly8(a, out, lane);
-}
 
 // ub[u] = (sum of b+ over the data rows of unique row u, sum of b-).
 // Optionally also the data as the Gram kernels consume them (the right-hand
@@ -159,8 +120,8 @@ __global__ __launch_bounds__(256) void bsum_kernel(const int32_t* __restrict__ u
     }
 }
 
-// Refinement residual, partial over one work item (a pair's rows within two
-// frequencies):  r+-(z) = Re(A^H (B+- - mult A x+-)), written to
+// Refinement residual, partial over one work item (a pair's rows within a
+// group of frequencies):  r+-(z) = Re(A^H (B+- - mult A x+-)), written to
 // rpart[slot][h*nz + z].  With A = W p, p = g(k_r) g(k_s) and the row data
 // ubw = conj(W) B from bsum_kernel, a row contributes
 //   Re(conj(p) (ubw - |W|^2 mult (p . x))),   |W|^2 mult = gsc^2.
@@ -168,9 +129,10 @@ __global__ __launch_bounds__(256) void bsum_kernel(const int32_t* __restrict__ u
 // partial of -Re(A^H A) x (the operator applied to a search direction).
 // Rows past the item (padding of the last batch) get zero data and weight and
 // depths past nz get x = 0, so no per-element masking is needed; the depths
-// past nz are never stored.
-template <int ZPL, int RB, bool DATA>
-__global__ __launch_bounds__(256, ZPL <= 4 ? 3 : 2) void resid_kernel(const Item* __restrict__ items,
+// past nz are never stored.  PIPE: two column buffers in turn (two waves per
+// SIMD); without, one buffer (three waves per SIMD up to 384 depths).
+template <int ZPL, int RB, bool DATA, bool PIPE = (ZPL <= 4)>
+__global__ __launch_bounds__(256, PIPE || ZPL > 4 ? 2 : 3) void resid_kernel(const Item* __restrict__ items,
                                                     const int32_t* __restrict__ sched,
                                                     const GRow* __restrict__ grow,
                                                     const double* __restrict__ gsc,
@@ -180,6 +142,7 @@ __global__ __launch_bounds__(256, ZPL <= 4 ? 3 : 2) void resid_kernel(const Item
                                                     const int32_t* __restrict__ conv,
                                                     double* __restrict__ rpart, int nsched,
                                                     const int32_t* __restrict__ active) {
+    static_assert(RB == 2, "two rows per wave per batch (one 8-value reduction)");
     __shared__ double s_acc[4][2][ZPL * 64];
     // no pair left iterating: the whole sweep is skipped with one load
     if (active && *active == 0) return;
@@ -204,32 +167,33 @@ __global__ __launch_bounds__(256, ZPL <= 4 ? 3 : 2) void resid_kernel(const Item
 #pragma unroll
     for (int q = 0; q < ZPL; ++q) acc[0][q] = acc[1][q] = 0.0;
 
-    for (int b0 = 0; b0 < n; b0 += 4 * RB) {
-        // the RB rows of this wave in the batch
-        zd gr[RB][ZPL], gs[RB][ZPL], bp[RB], bm[RB];
-        double w2[RB];
+    // Software pipeline: the table columns of a batch are loaded while the
+    // previous batch computes, and the column offsets of the batch after
+    // that are fetched at the same time (one memory latency per batch,
+    // overlapped with arithmetic).
+    auto row_of = [&](int b, int j) { return int64_t(it.row_begin) + min(b + 4 * j + wv, n - 1); };
+    // depths lane + 64 q with q < ZPL - 1 are below nz; the last one is clamped
+    const int zl = min(lane + 64 * (ZPL - 1), nz - 1) - lane;
+    // two column buffers in turn: batch b computes from one while batch b + 1
+    // is loaded into the other
+    zd ar[RB][ZPL], as[RB][ZPL], br[RB][ZPL], bs[RB][ZPL];
+    (void)br;
+    (void)bs;
+    GRow gn[RB];
+    auto load_columns = [&](zd (&gr)[RB][ZPL], zd (&gs)[RB][ZPL], const GRow (&g)[RB]) {
 #pragma unroll
         for (int j = 0; j < RB; ++j) {
-            const int r = b0 + 4 * j + wv;
-            const bool on = r < n;
-            const int64_t row = int64_t(it.row_begin) + min(r, n - 1);
-            const GRow g = grow[row];
-            const double sc = gsc[row];
-            if constexpr (DATA) {
-                const zd b0v = ubw[2 * row], b1v = ubw[2 * row + 1];
-                bp[j] = on ? b0v : zd{0.0, 0.0};
-                bm[j] = on ? b1v : zd{0.0, 0.0};
-            } else {
-                bp[j] = bm[j] = zd{0.0, 0.0};
-            }
-            w2[j] = on ? sc * sc : 0.0;
+            const zd* cr = g64 + g[j].off_r + lane;
+            const zd* cs = g64 + g[j].off_s + lane;
 #pragma unroll
             for (int q = 0; q < ZPL; ++q) {
-                const int zc = min(lane + 64 * q, nz - 1);
-                gr[j][q] = g64[size_t(g.off_r) + zc];
-                gs[j][q] = g64[size_t(g.off_s) + zc];
+                const int dz = q < ZPL - 1 ? 64 * q : zl;
+                gr[j][q] = cr[dz];
+                gs[j][q] = cs[dz];
             }
         }
+    };
+    auto compute = [&](const zd (&gr)[RB][ZPL], const zd (&gs)[RB][ZPL], int b0) {
         zd P[RB][ZPL];
 #pragma unroll
         for (int j = 0; j < RB; ++j)
@@ -251,17 +215,70 @@ __global__ __launch_bounds__(256, ZPL <= 4 ? 3 : 2) void resid_kernel(const Item
             v[4 * j + 2] = a2;
             v[4 * j + 3] = a3;
         }
-        butterfly<4 * RB>(v, y, lane);
+        // the rows' data and weights (scalar loads, used after the reduction)
+        zd bp[RB], bm[RB];
+        double w2[RB];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            const bool on = b0 + 4 * j + wv < n;
+            const int64_t row = row_of(b0, j);
+            const double sc = gsc[row];
+            if constexpr (DATA) {
+                const zd b0v = ubw[2 * row], b1v = ubw[2 * row + 1];
+                bp[j] = on ? b0v : zd{0.0, 0.0};
+                bm[j] = on ? b1v : zd{0.0, 0.0};
+            } else {
+                bp[j] = bm[j] = zd{0.0, 0.0};
+            }
+            w2[j] = on ? sc * sc : 0.0;
+        }
+        butterfly8(v, y, lane);
 #pragma unroll
         for (int j = 0; j < RB; ++j) {
             const zd cp{bp[j].x - w2[j] * y[4 * j], bp[j].y - w2[j] * y[4 * j + 1]};
             const zd cm{bm[j].x - w2[j] * y[4 * j + 2], bm[j].y - w2[j] * y[4 * j + 3]};
 #pragma unroll
             for (int q = 0; q < ZPL; ++q) {
-                acc[0][q] += P[j][q].x * cp.x + P[j][q].y * cp.y;
-                acc[1][q] += P[j][q].x * cm.x + P[j][q].y * cm.y;
+                acc[0][q] = fma(P[j][q].x, cp.x, acc[0][q]);
+                acc[0][q] = fma(P[j][q].y, cp.y, acc[0][q]);
+                acc[1][q] = fma(P[j][q].x, cm.x, acc[1][q]);
+                acc[1][q] = fma(P[j][q].y, cm.y, acc[1][q]);
             }
         }
+    };
+    constexpr int B = 4 * RB;   // rows of a batch (all waves)
+    if constexpr (!PIPE) {
+        // one buffer: each batch waits for its own columns (beyond 256
+        // depths two buffers would not leave registers for two waves)
+        for (int b0 = 0; b0 < n; b0 += B) {
+            GRow g[RB];
+#pragma unroll
+            for (int j = 0; j < RB; ++j) g[j] = grow[row_of(b0, j)];
+            load_columns(ar, as, g);
+            compute(ar, as, b0);
+        }
+    } else {
+    {
+        GRow g0[RB];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) g0[j] = grow[row_of(0, j)];
+        load_columns(ar, as, g0);
+#pragma unroll
+        for (int j = 0; j < RB; ++j) gn[j] = grow[row_of(B, j)];
+    }
+    // (the loads are unconditional, so that the waits stay exact: past the
+    // item's end they read its last row again, and those values are unused)
+    for (int b0 = 0; b0 < n; b0 += 2 * B) {
+        load_columns(br, bs, gn);
+#pragma unroll
+        for (int j = 0; j < RB; ++j) gn[j] = grow[row_of(b0 + 2 * B, j)];
+        compute(ar, as, b0);
+        if (b0 + B >= n) break;
+        load_columns(ar, as, gn);
+#pragma unroll
+        for (int j = 0; j < RB; ++j) gn[j] = grow[row_of(b0 + 3 * B, j)];
+        compute(br, bs, b0 + B);
+    }
     }
 #pragma unroll
     for (int q = 0; q < ZPL; ++q) {
@@ -346,10 +363,8 @@ constexpr int kResidGrid = 4096;
 template <int ZPL>
 static hipError_t launch_resid_z(const edt_plan* p, const zd* g64, const zd* ubw, const double* x,
                                  const int32_t* conv, double* rpart, const int32_t* active, hipStream_t st) {
-    // rows per wave per batch: four (one 16-value reduction) up to 256
-    // depths; two beyond, where four rows' table values would not leave
-    // registers for a second wave per SIMD
-    constexpr int kRB = ZPL <= 4 ? 4 : 2;
+    // rows per wave per batch: two (one 8-value reduction)
+    constexpr int kRB = 2;
     const int nit = int(p->rsched.size());
     if (nit == 0) return hipSuccess;
     const unsigned grid = unsigned(std::min(nit, kResidGrid));
