@@ -41,6 +41,71 @@ inline int64_t wrap(int64_t n, int64_t N) { return ((n % N) + N) % N; }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Order the unique rows of one pair and frequency along chains of shared
+// table columns: a unique row joins its two |k| classes, and consecutive rows
+// of a chain share one class (the 2D rows (a, u - a) form paths
+// ... -|u - a|-|a|-|u + a|- ...).  Each row is oriented so that its first
+// class is the one it shares with the row before it.  grp[g] = [i, j) of seg
+// (sorted by the unordered class pair); walk receives (g, first | second << 16)
+// in chain order.  Deterministic: classes are taken in the order the sorted
+// rows first name them; paths start at odd-degree classes (path ends), then at
+// any class with an unused row.  Linear in the number of rows (an adjacency
+// list by counting, no sort).
+void chain_order(const std::vector<std::pair<uint32_t, int32_t>>& seg,
+                 const std::vector<std::pair<uint32_t, uint32_t>>& grp,
+                 std::vector<std::pair<uint32_t, uint32_t>>& walk) {
+    const size_t G = grp.size();
+    walk.clear();
+    static thread_local std::vector<int32_t> deg(65536, 0), start(65536, 0), cursor(65536, 0);
+    static thread_local std::vector<uint32_t> touched, adj;
+    static thread_local std::vector<char> used;
+    touched.clear();
+    auto ends = [&](size_t g, uint32_t& a, uint32_t& b) {
+        const uint32_t key = seg[grp[g].first].first;
+        a = key & 0xFFFFu;
+        b = key >> 16;
+    };
+    for (size_t g = 0; g < G; ++g) {
+        uint32_t a, b;
+        ends(g, a, b);
+        if (deg[a]++ == 0) touched.push_back(a);
+        if (b != a && deg[b]++ == 0) touched.push_back(b);
+    }
+    int32_t off = 0;
+    for (const uint32_t c : touched) {
+        start[c] = cursor[c] = off;
+        off += deg[c];
+    }
+    adj.resize(size_t(off));
+    for (size_t g = 0; g < G; ++g) {
+        uint32_t a, b;
+        ends(g, a, b);
+        adj[size_t(cursor[a]++)] = uint32_t(g);
+        if (b != a) adj[size_t(cursor[b]++)] = uint32_t(g);
+    }
+    for (const uint32_t c : touched) cursor[c] = start[c];
+    used.assign(G, 0);
+    auto walk_from = [&](uint32_t c) {
+        for (;;) {
+            int32_t& cur = cursor[c];
+            const int32_t end = start[c] + deg[c];
+            while (cur < end && used[adj[size_t(cur)]]) ++cur;
+            if (cur >= end) return;
+            const uint32_t g = adj[size_t(cur)];
+            used[g] = 1;
+            uint32_t a, b;
+            ends(g, a, b);
+            const uint32_t o = a == c ? b : a;
+            walk.push_back({g, c | (o << 16)});
+            c = o;
+        }
+    };
+    for (const uint32_t c : touched)
+        if (deg[c] % 2 == 1) walk_from(c);
+    for (const uint32_t c : touched) walk_from(c);
+    for (const uint32_t c : touched) deg[c] = 0;
+}
+
 // Split every pair's unique rows (sorted by frequency) into work items that
 // stay inside one band of `band` frequencies and hold at most `max_rows`
 // rows.  Items are pair-major; pair_first[q] is the first item of pair q and
@@ -570,6 +635,7 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
         p->row_unique.assign(size_t(p->n_rows), -1);
         p->umem.reserve(size_t(p->n_rows));
         std::vector<std::pair<uint32_t, int32_t>> seg;
+        std::vector<std::pair<uint32_t, uint32_t>> grp, walk;
         int64_t n_u = 0;
         for (int64_t q = 0; q < p->n_pairs; ++q) {
             int64_t r = p->row_off[q];
@@ -583,20 +649,25 @@ edt_status edt_plan_create(const edt_survey* s, const edt_layers* l, const edt_p
                     ++e;
                 }
                 std::sort(seg.begin(), seg.end());
+                grp.clear();
                 for (size_t i = 0; i < seg.size();) {
                     size_t j = i;
                     while (j < seg.size() && seg[j].first == seg[i].first) ++j;
-                    const size_t m = j - i;
-                    if (m >= 65536) { delete p; return fail(EDT_EINVAL, "row multiplicity >= 65536"); }
-                    p->urows.push_back(f | (uint32_t(m) << 16));
-                    p->urows.push_back(seg[i].first);
+                    if (j - i >= 65536) { delete p; return fail(EDT_EINVAL, "row multiplicity >= 65536"); }
+                    grp.push_back({uint32_t(i), uint32_t(j)});
+                    i = j;
+                }
+                chain_order(seg, grp, walk);
+                for (const auto& w : walk) {
+                    const auto [i, j] = grp[w.first];
+                    p->urows.push_back(f | (uint32_t(j - i) << 16));
+                    p->urows.push_back(w.second);
                     for (size_t k = i; k < j; ++k) {
                         p->umem.push_back(seg[k].second);
                         p->row_unique[size_t(seg[k].second)] = int32_t(n_u);
                     }
                     p->umem_off.push_back(int32_t(p->umem.size()));
                     ++n_u;
-                    i = j;
                 }
                 r = e;
             }

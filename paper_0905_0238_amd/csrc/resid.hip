@@ -171,7 +171,7 @@ __global__ __launch_bounds__(256, PIPE || ZPL > 4 ? 2 : 3) void resid_kernel(con
     // previous batch computes, and the column offsets of the batch after
     // that are fetched at the same time (one memory latency per batch,
     // overlapped with arithmetic).
-    auto row_of = [&](int b, int j) { return int64_t(it.row_begin) + min(b + 4 * j + wv, n - 1); };
+    auto row_of = [&](int b, int j) { return int64_t(it.row_begin) + min(b + RB * wv + j, n - 1); };
     // depths lane + 64 q with q < ZPL - 1 are below nz; the last one is clamped
     const int zl = min(lane + 64 * (ZPL - 1), nz - 1) - lane;
     // two column buffers in turn: batch b computes from one while batch b + 1
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(256, PIPE || ZPL > 4 ? 2 : 3) void resid_kernel(con
         double w2[RB];
 #pragma unroll
         for (int j = 0; j < RB; ++j) {
-            const bool on = b0 + 4 * j + wv < n;
+            const bool on = b0 + RB * wv + j < n;
             const int64_t row = row_of(b0, j);
             const double sc = gsc[row];
             if constexpr (DATA) {
