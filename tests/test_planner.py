@@ -146,6 +146,46 @@ def test_unique_rows_merge_equal_born_rows(name):
         assert len(keys) == len(seg)
 
 
+@pytest.mark.parametrize("name", ["cfg1", "2d-even-cut", "2d-odd-nocut", "3d-small", "3d-nocut"])
+def test_unique_rows_follow_chains_of_shared_columns(name):
+    """Within a pair and frequency the unique rows are ordered along chains of
+    shared |k| classes, each row oriented (first class, second class) so that
+    a chained row's first class is the row before's second.  In 2D a class
+    joins at most two unique rows, so the class graph is paths (a class with a
+    row to itself ends one) and cycles, and every component is one chain:
+    the chain links number the rows less the components."""
+    _lib_or_skip()
+    s = SURVEYS[name]()
+    p = E.Plan(s)
+    u = p.urows()
+    uo, ur = u["urow_off"], u["urows"]
+    links = rows = comps = 0
+    for q in range(p.n_pairs):
+        seg = ur[uo[q]:uo[q + 1]]
+        for f in np.unique(seg[:, 0]):
+            g = seg[seg[:, 0] == f]
+            k = int(np.sum(g[:-1, 3] == g[1:, 2]))
+            parent = {}
+
+            def root(c):
+                while parent.setdefault(c, c) != c:
+                    c = parent[c]
+                return c
+            for a, b in g[:, 2:]:
+                parent[root(int(a))] = root(int(b))
+            nc = len({root(c) for c in list(parent)})
+            if s.dim == 2:
+                deg = {}
+                for a, b in g[:, 2:]:
+                    deg[int(a)] = deg.get(int(a), 0) + 1
+                    if b != a:
+                        deg[int(b)] = deg.get(int(b), 0) + 1
+                assert max(deg.values()) <= 2
+                assert k == len(g) - nc, (q, f)
+            links, rows, comps = links + k, rows + len(g), comps + nc
+    assert rows == len(ur) and links >= rows - 2 * comps
+
+
 def _check_items(p, which, band, max_rows):
     items, sched = p.schedule(which)
     u = p.urows()
