@@ -349,7 +349,7 @@ edt_status edt_solve(const edt_plan* plan, const edt_c128* g64, const void* d_ro
  * caller workspace.  The caller still passes every input and output.
  *   - Scratch needed (bytes, each part rounded up to 256): the damping, the
  *     diagonal-block inverses (n_pairs * ceil(nz/32) * 8 KB), flags and
- *     counters; with refinement also the summed data (n_urows * 64), the
+ *     counters; with refinement also the summed data (n_urows * 32), the
  *     residual partials (one 2 nz + 1 FP64 row per residual item) and three
  *     per-pair refinement vectors; with escalation also the FP64 Gram
  *     partials of every work item.  A plan needing more returns EDT_ENOMEM

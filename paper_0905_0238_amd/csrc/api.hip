@@ -221,14 +221,13 @@ edt_status edt_assemble(const edt_plan* p, const edt_c128* g64, const edt_c64* g
     }
     const WorkLayout wl = work_layout(p);
     unsigned char* w = static_cast<unsigned char*>(work);
-    zd* ub = reinterpret_cast<zd*>(w + wl.ub);
     zd* ubw = reinterpret_cast<zd*>(w + wl.ubw);
     float4* ub32 = reinterpret_cast<float4*>(w + wl.ub32);
     const bool f64 = prec == EDT_FP64;
     const zd* G64 = reinterpret_cast<const zd*>(g64);
     // conj(W) B in FP64 for every precision: the FP64 Gram reads it, and the
     // data sweep of a refining edt_solve can reuse it
-    EDT_TRY(launch_bsum(p, d_rows, ub, stream, ubw, f64 ? nullptr : ub32),
+    EDT_TRY(launch_bsum(p, d_rows, nullptr, stream, ubw, f64 ? nullptr : ub32),
             "bsum");
     // one pass over the rows gives the Gram partials and the right-hand side
     // and trace partials of every item
@@ -254,7 +253,6 @@ namespace {
 // library's static array (edt_solve_static); a section the call does not use
 // stays null.
 struct SolveScratch {
-    zd* ub = nullptr;             // [U][2] summed data (written by the data sum)
     zd* ubw = nullptr;            // [U][2] conj(W) times the summed data
     double* rpart = nullptr;      // residual partials per residual item
     double* lam = nullptr;        // [P] damping
@@ -275,7 +273,6 @@ SolveScratch scratch_from_work(const edt_plan* p, void* work) {
     const WorkLayout wl = work_layout(p);
     unsigned char* w = static_cast<unsigned char*>(work);
     SolveScratch s;
-    s.ub = reinterpret_cast<zd*>(w + wl.ub);
     s.ubw = reinterpret_cast<zd*>(w + wl.ubw);
     s.rpart = reinterpret_cast<double*>(w + wl.rhs_part);
     s.lam = reinterpret_cast<double*>(w + wl.lam);
@@ -311,7 +308,6 @@ size_t compact_solve_scratch(const edt_plan* p, bool refine, bool escalate, unsi
     s.aux = reinterpret_cast<int32_t*>(take(P * sizeof(int32_t)));
     s.cnt = reinterpret_cast<int32_t*>(take((kMaxRefine + 2) * sizeof(int32_t)));
     if (refine) {
-        s.ub = reinterpret_cast<zd*>(take(U * 2 * sizeof(zd)));
         s.ubw = reinterpret_cast<zd*>(take(U * 2 * sizeof(zd)));
         s.rpart = reinterpret_cast<double*>(take(p->ritems.size() * (2 * nz + 1) * sizeof(double)));
         s.pcg_r = reinterpret_cast<double*>(take(P * 2 * nz * sizeof(double)));
@@ -372,7 +368,7 @@ edt_status solve_impl(const edt_plan* p, const edt_c128* g64, const void* d_rows
         // the summed data, conj(W) B per unique row, unless the caller states
         // that edt_assemble left them in work
         if (!opts->data_summed)
-            EDT_TRY(launch_bsum(p, d_rows, ws.ub, stream, ws.ubw), "bsum");
+            EDT_TRY(launch_bsum(p, d_rows, nullptr, stream, ws.ubw), "bsum");
         if (opts->escalate) {
             // pairs whose factorisation failed (info > 0): FP64 Gram, rhs and
             // trace from the rows, and a second factorisation; every launch

@@ -80,7 +80,8 @@ __device__ __forceinline__ void butterfly8(double (&a)[8], double (&out)[8], int
 }
 
 
-// ub[u] = (sum of b+ over the data rows of unique row u, sum of b-).
+// ub[u] = (sum of b+ over the data rows of unique row u, sum of b-) (ub
+// nullable: the Gram and refinement read only the weighted forms below).
 // Optionally also the data as the Gram kernels consume them (the right-hand
 // side c = Re(A^H B) with A = W g g):
 //   ubw[u]  = conj(W) ub             (FP64 rows are built without W)
@@ -102,8 +103,10 @@ __global__ __launch_bounds__(256) void bsum_kernel(const int32_t* __restrict__ u
         const zd df = d0 - d1;                    // (d0 - d1) / (2i) = -i (d0 - d1) / 2
         bm = bm + zd{0.5 * df.y, -0.5 * df.x};
     }
-    ub[2 * u] = bp;
-    ub[2 * u + 1] = bm;
+    if (ub) {
+        ub[2 * u] = bp;
+        ub[2 * u + 1] = bm;
+    }
     if (ubw || ub32) {
         const uint32_t a = urows[2 * u];
         const zd w = omega_of(freq[a & 0xFFFFu], eps);

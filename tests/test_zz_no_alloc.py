@@ -108,7 +108,7 @@ def test_static_solve_refuses_oversized_plans_and_summed_data():
         return L.edt_solve_static(p._h, ptr, ptr, ptr, ptr, ptr, 1e-3, C.byref(opts), ptr, ptr, iptr, iptr,
                                   stream)
 
-    # the 2D 512-trace survey: refinement fits (about 157 MB), escalation's
+    # the 2D 512-trace survey: refinement fits (about 111 MB), escalation's
     # FP64 Gram partials (1.2 GB) do not
     assert call(1, 1, 0) == _lib.EDT_ENOMEM
     msg = L.edt_last_error().decode()
