@@ -93,33 +93,57 @@ __global__ __launch_bounds__(256) void green_kernel(const double* __restrict__ f
         }
     }
     __syncthreads();
-    for (int t = tid; t < ne * nz; t += 256) {
-        const int e = t / nz, i = t - e * nz;
-        const double z = z0 + double(i) * dz;
-        // layer index = number of interfaces at or above z
-        int lo = 0, hi = L - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (s_zif[mid] <= z) lo = mid + 1;
-            else hi = mid;
+    // Outputs: within layer j the function is u1 + u2 with u1 ~ exp(i k_j z)
+    // and u2 ~ exp(-i k_j z) (u2 = 0 in the bottom half space).  Thread (e, c)
+    // takes depths c, c + 16, ... of entry e: each term is evaluated directly
+    // where a layer is entered and carried down by its factor exp(+-i k_j 16 dz)
+    // otherwise (at most nz / 16 products, a relative error of a few units of
+    // rounding), so consecutive threads still store consecutive depths.
+    static_assert(kGreenEntries * 16 == 256, "16 threads per entry");
+    const int e = tid >> 4, c = tid & 15;
+    if (e < ne) {
+        int lay = -1;
+        bool have_f = false;
+        zd u1{0.0, 0.0}, u2{0.0, 0.0}, f1{1.0, 0.0}, f2{1.0, 0.0};
+        for (int i = c; i < nz; i += 16) {
+            const double z = z0 + double(i) * dz;
+            // layer index = number of interfaces at or above z
+            int lo = 0, hi = L - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s_zif[mid] <= z) lo = mid + 1;
+                else hi = mid;
+            }
+            const int j = lo;
+            if (j != lay || z < 0.0) {
+                const zd kj = s_k[e * L + j];
+                if (j == 0) {
+                    u1 = s_half[e] * zexpi(kj, fabs(z));
+                    u2 = L > 1 ? s_half[e] * (s_R[e * L] * zexpi(kj, 2.0 * s_zif[0] - z)) : zd{0.0, 0.0};
+                } else if (j == L - 1) {
+                    u1 = s_b[e * L + j] * zexpi(kj, z - s_zif[j - 1]);
+                    u2 = zd{0.0, 0.0};
+                } else {
+                    u1 = s_b[e * L + j] * zexpi(kj, z - s_zif[j - 1]);
+                    u2 = s_b[e * L + j] * (s_R[e * L + j] * zexpi(kj, 2.0 * s_zif[j] - s_zif[j - 1] - z));
+                }
+                lay = z < 0.0 ? -1 : j;   // above the source depth: evaluated directly
+                have_f = false;
+            } else {
+                if (!have_f) {   // the layer's step factors, once it holds a second depth
+                    const zd kj = s_k[e * L + j];
+                    f1 = zexpi(kj, 16.0 * dz);
+                    f2 = zexpi(kj, -16.0 * dz);
+                    have_f = true;
+                }
+                u1 = u1 * f1;
+                u2 = u2 * f2;
+            }
+            const zd g = u1 + u2;
+            const size_t at = size_t(e0 + e) * nz + i;
+            g64[at] = g;
+            if (WRITE32) g32[at] = make_float2(float(s_sc[e] * g.x), float(s_sc[e] * g.y));
         }
-        const int j = lo;
-        const zd kj = s_k[e * L + j];
-        zd g;
-        if (j == 0) {
-            zd t0 = zexpi(kj, fabs(z));
-            if (L > 1) t0 = t0 + s_R[e * L] * zexpi(kj, 2.0 * s_zif[0] - z);
-            g = s_half[e] * t0;
-        } else if (j == L - 1) {
-            g = s_b[e * L + j] * zexpi(kj, z - s_zif[j - 1]);
-        } else {
-            const zd t0 = zexpi(kj, z - s_zif[j - 1]) +
-                          s_R[e * L + j] * zexpi(kj, 2.0 * s_zif[j] - s_zif[j - 1] - z);
-            g = s_b[e * L + j] * t0;
-        }
-        const size_t at = size_t(e0 + e) * nz + i;
-        g64[at] = g;
-        if (WRITE32) g32[at] = make_float2(float(s_sc[e] * g.x), float(s_sc[e] * g.y));
     }
 }
 
