@@ -15,8 +15,9 @@
   even and odd, with the evanescent cut, in complex64 rows, and at 2N = 64
   (whose first pass takes two launches); brute-force Born records of the
   repeated model -> the oracle's clean rows; records -> rows -> FP64 solve ->
-  model end to end (bar 1e-10); the survey of parallel lines and n_mid above
-  128 are refused.
+  model end to end (bar 1e-10); at the largest grid (n_mid = 128, 69 GB of
+  records) a plane wave made on the device lands on exactly its rows; the
+  survey of parallel lines and n_mid above 128 are refused.
 """
 import ctypes
 
@@ -212,6 +213,54 @@ def test_areal_end_to_end_from_shot_records():
     err = np.max(np.abs(m.cpu().numpy() - ref)) / np.max(np.abs(ref))
     print(f"3D end to end: model error {err:.2e}")
     assert err <= 1e-10
+
+
+def test_areal_records_at_the_largest_grid():
+    """n_mid = 128, the largest grid the transform takes: one frequency of
+    records on 256 positions per axis (69 GB), a plane wave made on the device
+    (the oracle's transform would not fit the host).  Every row must be zero
+    except those whose half-grid wavenumbers are the wave's, which get
+    d_mid^2 (2N)^4 / 4; each pass runs as several launches of at most 65,536
+    workgroups."""
+    N, M = 128, 256
+    free, _ = torch.cuda.mem_get_info()
+    if free < 80e9:
+        pytest.skip("needs about 70 GB of free device memory")
+    s = make_custom(dim=3, N=N, Nh=4, nz=2, dx=25.0, freqs=(5.0,), vel=(2000.0,), kappa=100.0, model=None)
+    p = E.Plan(s)
+    a0, b0 = (3, 1), (7, 5)   # a - b = 4 n with n = (-1, -1), q = (5, 3)
+    g = torch.arange(M, device="cuda", dtype=torch.float64)
+
+    def wave(k):
+        return torch.polar(torch.ones_like(g), 2.0 * np.pi * k * g / M)
+    rec = torch.empty((1, M, M, M, M), dtype=torch.complex128, device="cuda")
+    inner = wave(a0[1])[:, None, None] * wave(b0[0])[None, :, None] * wave(b0[1])[None, None, :]
+    ex = wave(a0[0])
+    for x in range(M):
+        rec[0, x] = ex[x] * inner
+    del inner
+    p.shots_fft(rec)
+    d = p.shots_pack(rec)
+    torch.cuda.synchronize()
+    del rec
+    d = d.cpu().numpy()
+    m = p.rowmap()
+    nh = s.n_off
+    u = np.repeat(m["pair_km"][:, 0], np.diff(m["row_off"]))
+    ux, uy = u // N, u % N
+    qx, qy = np.where(ux < (N + 1) // 2, ux, ux - N), np.where(uy < (N + 1) // 2, uy, uy - N)
+    n = m["keys"][:, 0]
+    nx, ny = n // nh - nh // 2, n % nh - nh // 2
+    ax, ay, bx, by = (qx + 2 * nx) % M, (qy + 2 * ny) % M, (qx - 2 * nx) % M, (qy - 2 * ny) % M
+    peak = s.d_mid ** 2 * float(M) ** 4 / 4.0
+    hit0 = (ax == a0[0]) & (ay == a0[1]) & (bx == b0[0]) & (by == b0[1])
+    hit1 = ((-bx) % M == a0[0]) & ((-by) % M == a0[1]) & ((-ax) % M == b0[0]) & ((-ay) % M == b0[1])
+    err0 = np.max(np.abs(d[:, 0] - np.where(hit0, peak, 0.0)))
+    err1 = np.max(np.abs(d[:, 1] - np.where(hit1, peak, 0.0)))
+    print(f"2N = {M}: {len(d)} rows, {int(hit0.sum())} + {int(hit1.sum())} hits, "
+          f"max error {max(err0, err1) / peak:.2e} of the peak")
+    assert hit0.sum() + hit1.sum() >= 1
+    assert max(err0, err1) <= 1e-10 * peak
 
 
 def test_records_of_line_surveys_and_large_areal_grids_are_refused():
