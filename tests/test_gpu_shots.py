@@ -16,7 +16,8 @@
   (whose first pass takes two launches); brute-force Born records of the
   repeated model -> the oracle's clean rows; records -> rows -> FP64 solve ->
   model end to end (bar 1e-10); at the largest grid (n_mid = 128, 69 GB of
-  records) a plane wave made on the device lands on exactly its rows; the
+  records) a plane wave made on the device lands on exactly its rows, and so
+  at the longest 2D transform (n_mid = 2048); the
   survey of parallel lines and n_mid above 128 are refused.
 """
 import ctypes
@@ -279,6 +280,32 @@ def test_records_of_line_surveys_and_large_areal_grids_are_refused():
     st = _lib.load().edt_shots_fft(pa._h, ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(0))
     assert st == _lib.EDT_EINVAL
     torch.cuda.synchronize()
+
+
+def test_line_records_at_the_longest_transform():
+    """n_mid = 2048, the longest transform: a plane wave of receiver index a0
+    and source index b0 lands on exactly the rows keyed (a0, b0) (at +k_m)
+    and (-b0, -a0) (at -k_m), with value d_mid N^2; every other datum is zero."""
+    N = 2048
+    s = make_custom(N=N, nz=2, dx=5.0, freqs=(6.0, 11.0), vel=(2000.0,), kappa=1.0, model=None)
+    p = E.Plan(s)
+    a0, b0 = 37, 2048 - 45
+    g = torch.arange(N, device="cuda", dtype=torch.float64)
+    wa = torch.polar(torch.ones_like(g), 2.0 * np.pi * a0 * g / N)
+    wb = torch.polar(torch.ones_like(g), 2.0 * np.pi * b0 * g / N)
+    rec = (wa[:, None] * wb[None, :]).expand(len(s.freqs), N, N).contiguous()
+    p.shots_fft(rec)
+    d = p.shots_pack(rec)
+    torch.cuda.synchronize()
+    d = d.cpu().numpy()
+    keys = p.rowmap()["keys"]
+    peak = s.d_mid * float(N) ** 2
+    hit0 = (keys[:, 0] == a0) & (keys[:, 1] == b0)
+    hit1 = (((-keys[:, 1]) % N) == a0) & (((-keys[:, 0]) % N) == b0)
+    err = max(np.max(np.abs(d[:, 0] - np.where(hit0, peak, 0.0))),
+              np.max(np.abs(d[:, 1] - np.where(hit1, peak, 0.0))))
+    assert hit0.sum() + hit1.sum() >= 1
+    assert err <= 1e-10 * peak, err / peak
 
 
 def test_transforms_longer_than_2048_are_refused():
