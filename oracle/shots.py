@@ -31,6 +31,12 @@ at a = q + 2n, b = q - 2n (mod 2N per axis) is 4 times the row's datum at
 on the 2N grid has its spectrum at the even indices 2q only, 4 times the
 N-grid spectrum there.  (The pin compares these rows with brute-force
 space-domain Born data of the model repeated 2 x 2 times.)
+
+3D survey of parallel lines (Section 2.2; oracle.lines3d): records
+D[f, j, R, S] of line j, receiver R and source S; the datum of key
+(a, b, c) is d_mid sum_{j, R, S} D e^{-2 pi i (a R + b S) / N_x}
+e^{-2 pi i c j / N_y}, and a row of pair (u, c) keyed (a, b, c) has its
+-k partner at (-b, -a, -c).
 """
 from __future__ import annotations
 
@@ -43,8 +49,11 @@ def shots_to_rows(s, pl, D, pairs=None):
     """Shot records -> list of (d+, d-) per pair, in the oracle's row order.
 
     2D line: D (n_freq, N, N) [f, receiver, source].  3D areal: D (n_freq,
-    2N, 2N, 2N, 2N) [f, Rx, Ry, Sx, Sy], the doubled periodic survey."""
+    2N, 2N, 2N, 2N) [f, Rx, Ry, Sx, Sy], the doubled periodic survey.  3D
+    parallel lines: D (n_freq, N_y, N_x, N_x) [f, line, receiver, source]."""
     pairs = pl.pairs if pairs is None else pairs
+    if getattr(s, "n_line", 0):
+        return _line_rows(s, D, pairs)
     if getattr(s, "dim", 2) == 3:
         return _areal_rows(s, D, pairs)
     F = s.d_mid * np.fft.fft2(np.asarray(D, np.complex128), axes=(1, 2))
@@ -87,3 +96,15 @@ def model_from_spectrum(s, V):
         N = s.n_mid
         return np.real(np.fft.ifft2(V.reshape(N, N, -1), axes=(0, 1)))
     return np.real(np.fft.ifft(V, axis=0))
+
+
+def _line_rows(s, D, pairs):
+    Ny, N = s.n_line, s.n_mid
+    D = np.asarray(D, np.complex128).reshape(len(s.freqs), Ny, N, N)
+    F = s.d_mid * np.fft.fftn(D, axes=(1, 2, 3))
+    out = []
+    for p in pairs:
+        d0 = F[p.f, p.key0[:, 2], p.key0[:, 0], p.key0[:, 1]]
+        d1 = F[p.f, p.key1[:, 2], p.key1[:, 0], p.key1[:, 1]]
+        out.append((d0, d1))
+    return out

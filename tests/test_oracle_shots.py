@@ -10,14 +10,19 @@
   to the rows of every k_m, odd components included; a plane-wave record of
   the doubled survey lands on the rows whose half-grid wavenumbers are its
   own, with value d_mid^2 (2N)^4 / 4;
+* 3D parallel lines (Section 2.2): brute-force Born records of the line
+  survey [f, line, receiver, source] go to the rows (no evanescent cut: the
+  cut drops terms of the rows' quadrature that full Born data keep); a
+  plane-wave record lands on the rows keyed by its (a, b, c), at +k and at
+  the -k partner, with value d_mid N_y N_x^2;
 * model_from_spectrum inverts the spectrum that defines the seeded model, in
   2D and 3D.
 """
 import numpy as np
 import pytest
 
-from edt_inputs import make_custom, vhat
-from oracle.born import born_2d, born_3d
+from edt_inputs import make_custom, make_lines, vhat
+from oracle.born import born_2d, born_3d, born_lines
 from oracle.rows import plan
 from oracle.shots import model_from_spectrum, shots_to_rows
 from oracle.solve import gtables, forward
@@ -112,5 +117,44 @@ def test_areal_plane_wave_lands_on_its_rows():
             at = np.all(r == a0, axis=1) & np.all(sv == b0, axis=1)
             want = np.where(at, peak, 0.0)
             assert np.max(np.abs(d - want), initial=0) <= 1e-10 * peak
+            hits += int(at.sum())
+    assert hits >= 1
+
+
+@pytest.mark.parametrize("Nx,Ny,kappa", [(8, 6, 100.0), (7, 5, 100.0)])
+def test_line_survey_born_records_give_the_rows(Nx, Ny, kappa):
+    from oracle.lines3d import forward_lines, line_tables, plan_lines
+    s = make_lines(Nx=Nx, Ny=Ny, dx=30.0, dy=45.0, nz=3, dz=25.0, freqs=(6.0, 9.0), vel=(1800.0, 2500.0),
+                   zif=(40.0,), kappa=kappa, seed=5)
+    pl = plan_lines(s)
+    clean = forward_lines(s, pl, vhat(s), line_tables(s))
+    D = np.stack([np.transpose(born_lines(s.vel, s.zif, f, s.eps, s.v_true, s.d_mid, s.d_line, s.z, s.dz),
+                               (2, 0, 1)) for f in s.freqs])
+    rows = shots_to_rows(s, pl, D)
+    scale = max(np.max(np.abs(d0)) for d0, _ in clean if d0.size)
+    n = 0
+    for (d0, d1), (e0, e1) in zip(clean, rows):
+        assert np.max(np.abs(e0 - d0), initial=0) <= 1e-12 * scale
+        assert np.max(np.abs(e1 - d1), initial=0) <= 1e-12 * scale
+        n += d0.size
+    assert n > 0
+
+
+def test_line_survey_plane_wave_lands_on_its_rows():
+    from oracle.lines3d import plan_lines
+    Nx, Ny = 10, 6
+    s = make_lines(Nx=Nx, Ny=Ny, dx=20.0, dy=30.0, nz=2, freqs=(7.0,), vel=(2000.0,), zif=(), kappa=100.0)
+    pl = plan_lines(s)
+    a0, b0, c0 = 3, 8, 2
+    j, n = np.arange(Ny), np.arange(Nx)
+    D = np.exp(2j * np.pi * (c0 * j[:, None, None] / Ny + a0 * n[None, :, None] / Nx
+                             + b0 * n[None, None, :] / Nx))[None]
+    rows = shots_to_rows(s, pl, D)
+    peak = s.d_mid * Ny * Nx * Nx
+    hits = 0
+    for p, (d0, d1) in zip(pl.pairs, rows):
+        for keys, d in ((p.key0, d0), (p.key1, d1)):
+            at = (keys[:, 0] == a0) & (keys[:, 1] == b0) & (keys[:, 2] == c0)
+            assert np.max(np.abs(d - np.where(at, peak, 0.0)), initial=0) <= 1e-10 * peak
             hits += int(at.sum())
     assert hits >= 1
