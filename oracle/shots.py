@@ -90,8 +90,11 @@ def _areal_rows(s, D, pairs):
 
 def model_from_spectrum(s, V):
     """V~ (n_km, nz) in fftfreq order -> the real model: (N, nz) in 2D,
-    (N, N, nz) in 3D."""
+    (N, N, nz) in 3D, (N_x, N_y, nz) on the survey of parallel lines (k_m
+    index ux N_y + c, the inverse DFT over x and over the line index)."""
     V = np.asarray(V, np.complex128)
+    if getattr(s, "n_line", 0):
+        return np.real(np.fft.ifft2(V.reshape(s.n_mid, s.n_line, -1), axes=(0, 1)))
     if getattr(s, "dim", 2) == 3:
         N = s.n_mid
         return np.real(np.fft.ifft2(V.reshape(N, N, -1), axes=(0, 1)))

@@ -16,7 +16,8 @@
   plane-wave record lands on the rows keyed by its (a, b, c), at +k and at
   the -k partner, with value d_mid N_y N_x^2;
 * model_from_spectrum inverts the spectrum that defines the seeded model, in
-  2D and 3D.
+  2D, 3D and on the survey of parallel lines; one spectral line of the line
+  survey gives its closed-form cosine.
 """
 import numpy as np
 import pytest
@@ -66,6 +67,26 @@ def test_model_from_its_spectrum():
     assert np.allclose(model_from_spectrum(s2, vhat(s2)), s2.v_true, rtol=0, atol=1e-13)
     s3 = make_custom(dim=3, N=8, Nh=4, nz=5, dx=25.0, freqs=(3.0,), vel=(2000.0,), seed=4)
     assert np.allclose(model_from_spectrum(s3, vhat(s3)), s3.v_true, rtol=0, atol=1e-13)
+    sl = make_lines(Nx=9, Ny=6, nz=4, freqs=(3.0,), vel=(2000.0,), seed=6)
+    assert np.allclose(model_from_spectrum(sl, vhat(sl)), sl.v_true, rtol=0, atol=1e-13)
+
+
+def test_line_model_of_one_spectral_line():
+    """One k_m entry (ux, c) = (2, 5) with value w at depth 1, its partner
+    (-2, -5) with conj(w): the model is 2 Re(w e^{2 pi i (2 x / N_x + 5 y / N_y)})
+    / (N_x N_y) at depth 1 and zero elsewhere."""
+    Nx, Ny, nz = 9, 7, 3
+    sl = make_lines(Nx=Nx, Ny=Ny, nz=nz, freqs=(3.0,), vel=(2000.0,), model="zero")
+    w = 0.7 - 1.3j
+    V = np.zeros((Nx * Ny, nz), np.complex128)
+    V[2 * Ny + 5, 1] = w
+    V[(Nx - 2) * Ny + (Ny - 5), 1] = np.conj(w)
+    m = model_from_spectrum(sl, V)
+    x, y = np.arange(Nx)[:, None], np.arange(Ny)[None, :]
+    want = 2.0 * np.real(w * np.exp(2j * np.pi * (2 * x / Nx + 5 * y / Ny))) / (Nx * Ny)
+    assert m.shape == (Nx, Ny, nz)
+    assert np.max(np.abs(m[:, :, 1] - want)) <= 1e-15
+    assert not m[:, :, 0].any() and not m[:, :, 2].any()
 
 
 def _signed(u, N):
