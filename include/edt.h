@@ -101,8 +101,7 @@ typedef enum {
  *        decoupled 3D equation, L_y = n_line d_line).  A term is kept iff both
  *        |k| are within the cut below, a row iff a term is.  This survey is
  *        assembled in FP64 and solved without refinement (edt_solve with
- *        refine = 0, or edt_tsvd); edt_adjoint, edt_kz_restrict, edt_model and
- *        the record calls refuse it.
+ *        refine = 0, or edt_tsvd); edt_adjoint and edt_kz_restrict refuse it.
  * Frequencies freq_hz[n_freq] are used simultaneously (Section 3.1); eps is the
  * imaginary part of w (Section 2.1; 0.15 1/s in Section 3.1).  Depths are
  * z_i = z0 + i*dz, i < nz.  A row is kept iff |k_r| and |k_s| are both
@@ -429,8 +428,9 @@ edt_status edt_kz_restrict(const edt_plan* plan, double k_disk, double* gram, do
 
 /*
  * The transforms on either side of the decoupled problems (Section 2.1), for
- * the 2D line survey and the 3D areal survey (Section 2.2); EDT_EINVAL for the
- * survey of parallel lines, for n_mid > 2048 (2D) and for n_mid > 128 (3D).
+ * the 2D line survey, the 3D areal survey and the 3D survey of parallel lines
+ * (Section 2.2); EDT_EINVAL for n_mid > 2048 and, on the areal survey, for
+ * n_mid > 128.
  *
  * edt_shots_fft, 2D: shots[n_freq][n_mid][n_mid] (complex128, device; [f][R][S],
  * the record of the source at x_S = S d_mid by the receiver at x_R, at the
@@ -449,13 +449,20 @@ edt_status edt_kz_restrict(const edt_plan* plan, double k_disk, double* gram, do
  *     F[f][a][b] = d_mid^2 sum_{R,S} D[f][R][S] exp(-2 pi i (a.R + b.S) / M)
  * (a, b: 2-vectors).  One pass over the records per axis.
  *
+ * edt_shots_fft, 3D parallel lines: shots[n_freq][n_line][n_mid][n_mid]
+ * ([f][j][R][S], the records of line j at y_j = j d_line) becomes
+ *     d~[f][c][a][b] = d_mid sum_{j,R,S} D[f][j][R][S]
+ *                      exp(-2 pi i (a R + b S) / n_mid) exp(-2 pi i c j / n_line).
+ *
  * edt_shots_pack: d_rows[n_rows][2] (device, the plan's data type) from that
  * spectrum.  2D: row r with frequency f and key (a, b) (edt_plan_rowmap) gets
  * (d~[f][a][b], d~[f][-b][-a]), the datum at +k_m and its -k_m partner.  3D
  * areal: row r of the pair with k_m index q and of k_h index n gets
  * (F[f][a][b], F[f][-b][-a]) / 4 with a = q + 2n, b = q - 2n (mod M per
  * axis): the N-periodic model has on the doubled grid a spectrum at even
- * indices only, 4 times its own.  The spectrum is only read, so the plans of
+ * indices only, 4 times its own.  Parallel lines: row r of the pair with k_y
+ * index c and key (a, b) gets (d~[f][c][a][b], d~[f][-c][-b][-a]).  The
+ * spectrum is only read, so the plans of
  * several pair ranges (batches) of one survey can each pack from one
  * transform.
  */
@@ -485,11 +492,13 @@ edt_status edt_aperture_gram(const edt_plan* plan, const edt_c128* g64, double b
 
 /*
  * The model from its spectrum (Section 2.1): v_tilde[n_km][nz] (complex128,
- * device, fftfreq order; 3D u = ux n_mid + uy) is overwritten by its inverse
- * transform over u (over ux and uy in 3D),
- *     V(x_n, z) = (1/n_mid) sum_u V~(u, z) exp(2 pi i u n / n_mid)   (per axis),
- * and model (double, device: [n_mid][nz], or [n_mid][n_mid][nz] in 3D) gets
- * its real part.  EDT_EINVAL for n_mid > 2048.
+ * device, fftfreq order; 3D areal u = ux n_mid + uy, parallel lines
+ * u = ux n_line + c) is overwritten by its inverse transform over u (over ux
+ * and uy, or ux and the line wavenumber c, in 3D),
+ *     V(x_n, z) = (1/n) sum_u V~(u, z) exp(2 pi i u n / n)   (per axis of length n),
+ * and model (double, device: [n_mid][nz], [n_mid][n_mid][nz] in 3D areal,
+ * [n_mid][n_line][nz] on parallel lines) gets its real part.  EDT_EINVAL for
+ * n_mid > 2048.
  */
 edt_status edt_model(const edt_plan* plan, edt_c128* v_tilde, double* model, hipStream_t stream);
 

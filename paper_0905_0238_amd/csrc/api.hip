@@ -562,14 +562,11 @@ edt_status edt_kz_restrict(const edt_plan* p, double k_disk, double* gram, doubl
 }
 
 namespace {
-// Surveys whose shot records the transform takes: the 2D line, and the 3D
-// areal survey up to n_mid = kMaxAreal (its doubled records).
+// Surveys whose shot records the transform takes: the 2D line, the 3D
+// survey of parallel lines, and the 3D areal survey up to n_mid = kMaxAreal
+// (its doubled records).
 edt_status check_records(const edt_plan* p, bool transform) {
-    if (p->dim == 3 && p->n_line > 0) {
-        set_error("shot records of the 2D line and the 3D areal survey only");
-        return EDT_EINVAL;
-    }
-    if (p->dim == 3 && p->n_mid > kMaxAreal) {
+    if (p->dim == 3 && p->n_line == 0 && p->n_mid > kMaxAreal) {
         set_error("3D areal records: n_mid > " + std::to_string(kMaxAreal) + " is not supported");
         return EDT_EINVAL;
     }
@@ -649,10 +646,6 @@ edt_status edt_model(const edt_plan* p, edt_c128* v_tilde, double* model, hipStr
     if (s != EDT_OK) return s;
     if (!v_tilde || !model) {
         set_error("missing argument");
-        return EDT_EINVAL;
-    }
-    if (p->n_line) {
-        set_error("the model transform does not cover the survey of parallel lines");
         return EDT_EINVAL;
     }
     if (p->n_mid > kMaxLine) {

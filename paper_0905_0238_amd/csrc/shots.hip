@@ -1,10 +1,11 @@
 // The transforms on either side of the decoupled problems (paper Section
 // 2.1): shot records to the packed wavenumber-domain rows, and the solution
 // spectrum V~ to the model V(x, z).  The records are those of the 2D line
-// survey, [f][R][S], or of the 3D areal survey (Section 2.2) on the doubled
-// periodic 2N x 2N grid, [f][Rx][Ry][Sx][Sy]: a row's receiver and source
-// wavenumbers q +- 2n (units of dk/2) are half-grid wavenumbers of the N
-// grid and whole-grid ones of a survey of twice the period.
+// survey, [f][R][S], of the 3D areal survey (Section 2.2) on the doubled
+// periodic 2N x 2N grid, [f][Rx][Ry][Sx][Sy] (a row's receiver and source
+// wavenumbers q +- 2n, in units of dk/2, are half-grid wavenumbers of the N
+// grid and whole-grid ones of a survey of twice the period), or of the 3D
+// survey of parallel lines, [f][line][R][S].
 //
 // Both are batches of 1D discrete Fourier transforms along one axis of a
 // dense array, done one line (or a few adjacent lines) per block in LDS:
@@ -122,6 +123,28 @@ __global__ __launch_bounds__(256) void rows_gather_areal_kernel(const zd* __rest
     }
 }
 
+// 3D survey of parallel lines: one block per pair (flattened k = ux N_y + c);
+// row r with frequency f and key (a, b) reads F[f][c][a][b] and its -k
+// partner F[f][-c][-b][-a].
+template <class D>
+__global__ __launch_bounds__(256) void rows_gather_lines_kernel(const zd* __restrict__ F,
+                                                                const uint32_t* __restrict__ rows,
+                                                                const int32_t* __restrict__ keys,
+                                                                const int64_t* __restrict__ row_off,
+                                                                const int32_t* __restrict__ pair_u, int N, int Ny,
+                                                                D* __restrict__ d_rows) {
+    const int64_t pq = blockIdx.x;
+    const int c = pair_u[2 * pq] % Ny, c1 = c ? Ny - c : 0;
+    const int64_t NN = int64_t(N) * N;
+    for (int64_t r = row_off[pq] + threadIdx.x; r < row_off[pq + 1]; r += 256) {
+        const int64_t f = rows[2 * r];
+        const int a = keys[2 * r], b = keys[2 * r + 1];
+        const int a1 = b ? N - b : 0, b1 = a ? N - a : 0;
+        store_datum(d_rows, 2 * r, F[(f * Ny + c) * NN + int64_t(a) * N + b]);
+        store_datum(d_rows, 2 * r + 1, F[(f * Ny + c1) * NN + int64_t(a1) * N + b1]);
+    }
+}
+
 __global__ __launch_bounds__(256) void real_part_kernel(const zd* __restrict__ v, int64_t n, double* __restrict__ out) {
     const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (i < n) out[i] = v[i].x;
@@ -177,9 +200,20 @@ hipError_t configure_lines() {
 }
 
 // shots[f][R][S] <- dx * DFT over R and S (forward sign); 3D areal:
-// shots[f][Rx][Ry][Sx][Sy] (M = 2N per axis) <- dx^2 * DFT over all four.
+// shots[f][Rx][Ry][Sx][Sy] (M = 2N per axis) <- dx^2 * DFT over all four;
+// parallel lines: shots[f][line][R][S] <- dx * DFT over R, S and the line.
 hipError_t launch_shots_fft(const edt_plan* p, zd* shots, hipStream_t st) {
     const int N = p->n_mid;
+    if (p->n_line > 0) {
+        const int Ny = p->n_line;
+        const int64_t NN = int64_t(N) * N, nl = int64_t(p->n_freq) * Ny;
+        hipError_t e = launch_lines(shots, N, nl, Lines{NN, N, 1, N}, -1.0, 1.0, st);   // along S
+        if (e == hipSuccess)   // along R (a single line takes the scale here)
+            e = launch_lines(shots, N, nl, Lines{NN, 1, N, N}, -1.0, Ny == 1 ? p->d_mid : 1.0, st);
+        if (e == hipSuccess && Ny > 1)   // along the line index
+            e = launch_lines(shots, Ny, p->n_freq, Lines{NN * Ny, 1, NN, int(NN)}, -1.0, p->d_mid, st);
+        return e;
+    }
     if (p->dim == 3) {
         const int M = 2 * N;
         const int64_t M2 = int64_t(M) * M, M3 = M2 * M, nf = p->n_freq;
@@ -198,6 +232,20 @@ hipError_t launch_shots_fft(const edt_plan* p, zd* shots, hipStream_t st) {
 
 hipError_t launch_shots_pack(const edt_plan* p, const zd* F, void* d_rows, hipStream_t st) {
     if (p->n_rows == 0) return hipSuccess;
+    if (p->n_line > 0) {
+        const unsigned np = unsigned(p->n_pairs);
+        if (p->data_c64)
+            hipLaunchKernelGGL(rows_gather_lines_kernel<float2>, dim3(np), dim3(256), 0, st, F,
+                               dptr<const uint32_t>(p, p->lay.rows), dptr<const int32_t>(p, p->lay.keys),
+                               dptr<const int64_t>(p, p->lay.row_off), dptr<const int32_t>(p, p->lay.pair_u),
+                               p->n_mid, p->n_line, static_cast<float2*>(d_rows));
+        else
+            hipLaunchKernelGGL(rows_gather_lines_kernel<zd>, dim3(np), dim3(256), 0, st, F,
+                               dptr<const uint32_t>(p, p->lay.rows), dptr<const int32_t>(p, p->lay.keys),
+                               dptr<const int64_t>(p, p->lay.row_off), dptr<const int32_t>(p, p->lay.pair_u),
+                               p->n_mid, p->n_line, static_cast<zd*>(d_rows));
+        return hipGetLastError();
+    }
     if (p->dim == 3) {
         const unsigned np = unsigned(p->n_pairs);
         if (p->data_c64)
@@ -224,13 +272,20 @@ hipError_t launch_shots_pack(const edt_plan* p, const zd* F, void* d_rows, hipSt
     return hipGetLastError();
 }
 
-// v[u][z] <- inverse DFT over u (2D) or (ux, uy) (3D), scaled by 1/N per
-// axis; model = its real part.
+// v[u][z] <- inverse DFT over u (2D), (ux, uy) (3D areal) or (ux, c)
+// (parallel lines, u = ux N_y + c), scaled by 1/length per axis; model = its
+// real part.
 hipError_t launch_model(const edt_plan* p, zd* v, double* model, hipStream_t st) {
     const int N = p->n_mid, nz = p->nz;
     const double inv = 1.0 / double(N);
-    hipError_t e;
-    if (p->dim == 3) {
+    hipError_t e = hipSuccess;
+    if (p->n_line > 0) {
+        const int Ny = p->n_line;
+        const int64_t row = int64_t(Ny) * nz;
+        if (Ny > 1) e = launch_lines(v, Ny, N, Lines{row, 1, nz, nz}, 1.0, 1.0 / double(Ny), st);   // along c
+        if (e != hipSuccess) return e;
+        e = launch_lines(v, N, 1, Lines{row * N, 1, row, int(row)}, 1.0, inv, st);                // along ux
+    } else if (p->dim == 3) {
         const int64_t row = int64_t(N) * nz;
         e = launch_lines(v, N, N, Lines{row, 1, nz, nz}, 1.0, inv, st);                 // along uy
         if (e != hipSuccess) return e;

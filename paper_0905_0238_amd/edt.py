@@ -308,11 +308,12 @@ class Plan:
 
     def records_shape(self):
         """Shape of the shot records: (n_freq, N, N) [f, receiver, source] on the
-        2D line; (n_freq, 2N, 2N, 2N, 2N) [f, Rx, Ry, Sx, Sy] for the 3D areal
-        survey (the doubled periodic survey, whose whole-grid wavenumbers are
-        the rows' half-grid ones)."""
+        2D line; (n_freq, N_y, N, N) [f, line, receiver, source] for the 3D
+        survey of parallel lines; (n_freq, 2N, 2N, 2N, 2N) [f, Rx, Ry, Sx, Sy]
+        for the 3D areal survey (the doubled periodic survey, whose whole-grid
+        wavenumbers are the rows' half-grid ones)."""
         if self.n_line:
-            raise ValueError("shot records of the 2D line and the 3D areal survey only")
+            return (self.n_freq, self.n_line, self.n_mid, self.n_mid)
         if self.dim == 3:
             return (self.n_freq,) + (2 * self.n_mid,) * 4
         return (self.n_freq, self.n_mid, self.n_mid)
@@ -339,11 +340,17 @@ class Plan:
         return d
 
     def model(self, v, out=None, overwrite=False):
-        """The real model V(x, z) ([N, nz], or [N, N, nz] in 3D) from the spectrum
-        v[n_km, nz]; v is used as scratch when overwrite is set, else copied."""
+        """The real model V(x, z) ([N, nz], [N, N, nz] in 3D, [N, N_y, nz] on
+        parallel lines) from the spectrum v[n_km, nz]; v is used as scratch
+        when overwrite is set, else copied."""
         self.upload()
         w = v if overwrite else v.clone()
-        shape = (self.n_mid, self.n_mid, self.nz) if self.dim == 3 else (self.n_mid, self.nz)
+        if self.n_line:
+            shape = (self.n_mid, self.n_line, self.nz)
+        elif self.dim == 3:
+            shape = (self.n_mid, self.n_mid, self.nz)
+        else:
+            shape = (self.n_mid, self.nz)
         m = out if out is not None else torch.empty(shape, dtype=torch.float64, device=self.device)
         _lib.check(_lib.load().edt_model(self._h, _ptr(w), _ptr(m), _stream()), "edt_model")
         return m

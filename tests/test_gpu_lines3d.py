@@ -161,9 +161,6 @@ def test_line_survey_refusals():
         p.solve(g64, d, gram, rhs, trace, s.lambda_rel, refine=True)
     with pytest.raises(RuntimeError, match="parallel lines"):
         p.kz_restrict(gram, rhs, 1.0, p.tsvd_work())
-    v = torch.zeros(p.n_km, s.nz, dtype=torch.complex128, device="cuda")
-    with pytest.raises(RuntimeError, match="parallel lines"):
-        p.model(v)
 
 
 def test_sampled_pairs_of_a_larger_line_survey():

@@ -17,8 +17,14 @@
   repeated model -> the oracle's clean rows; records -> rows -> FP64 solve ->
   model end to end (bar 1e-10); at the largest grid (n_mid = 128, 69 GB of
   records) a plane wave made on the device lands on exactly its rows, and so
-  at the longest 2D transform (n_mid = 2048); the
-  survey of parallel lines and n_mid above 128 are refused.
+  at the longest 2D transform (n_mid = 2048); n_mid above 128 is refused;
+* 3D survey of parallel lines: seeded random records [f, line, R, S] ->
+  packed rows, for power-of-two, odd and even lengths, with and without the
+  evanescent cut, a single line, and complex64 rows; brute-force Born records
+  -> the oracle's clean rows; records -> rows -> FP64 solve against the
+  oracle's, and the model from the solution (bar 1e-10); at n_mid = 2048 a
+  plane wave made on the device lands on exactly its rows; random spectra ->
+  the model [N_x, N_y, nz] (bar 1e-12).
 """
 import ctypes
 
@@ -26,11 +32,12 @@ import numpy as np
 import pytest
 
 from edt_inputs import make_config, make_custom, make_lines, vhat
-from oracle.born import born_3d
+from oracle.born import born_3d, born_lines
+from oracle.lines3d import forward_lines, line_tables, plan_lines, solve_lines
 from oracle.rows import plan as oracle_plan
 from oracle.shots import model_from_spectrum, shots_to_rows
-from oracle.solve import forward, gtables, pack
-from tests._cases import oracle_case, layered_small
+from oracle.solve import add_noise, forward, gtables, noise_scale, pack
+from tests._cases import layered_small, oracle_case, rel_errors
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -57,7 +64,7 @@ def _records(s, seed):
 
 
 def _gpu_rows(p, D):
-    sh = torch.from_numpy(D).cuda()
+    sh = torch.from_numpy(np.ascontiguousarray(D)).cuda()
     p.shots_fft(sh)
     d = p.shots_pack(sh)
     torch.cuda.synchronize()
@@ -264,22 +271,150 @@ def test_areal_records_at_the_largest_grid():
     assert max(err0, err1) <= 1e-10 * peak
 
 
-def test_records_of_line_surveys_and_large_areal_grids_are_refused():
+def test_areal_records_beyond_n_mid_128_are_refused():
     from paper_0905_0238_amd import _lib
-    sl = make_lines(Nx=16, Ny=4, nz=4, freqs=(6.0,))
-    pl_ = E.Plan(sl)
-    pl_.upload()
-    with pytest.raises(ValueError, match="3D areal survey only"):
-        pl_.records_shape()
     buf = torch.zeros(16, dtype=torch.complex128, device="cuda")
-    st = _lib.load().edt_shots_fft(pl_._h, ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(0))
-    assert st == _lib.EDT_EINVAL
     sa = make_custom(dim=3, N=130, Nh=2, nz=2, dx=25.0, freqs=(5.0,), vel=(2000.0,), kappa=1.0, model="zero")
     pa = E.Plan(sa)
     pa.upload()
     st = _lib.load().edt_shots_fft(pa._h, ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(0))
     assert st == _lib.EDT_EINVAL
     torch.cuda.synchronize()
+
+
+def _line_cases():
+    kw = dict(nz=4, dz=20.0, vel=(1800.0, 2500.0), zif=(40.0,), seed=9)
+    return {
+        "Nx16-Ny8-radix2": lambda: make_lines(Nx=16, Ny=8, dx=25.0, dy=40.0, freqs=(6.0, 11.0, 17.0),
+                                              kappa=100.0, **kw),
+        "Nx15-Ny7-odd-cut": lambda: make_lines(Nx=15, Ny=7, dx=20.0, dy=35.0, freqs=(9.0, 14.0, 22.0),
+                                               kappa=1.0, **kw),
+        "Nx24-Ny12-direct-cut": lambda: make_lines(Nx=24, Ny=12, dx=12.5, dy=25.0, freqs=(8.0, 20.0, 40.0),
+                                                   kappa=1.0, **kw),
+        "Nx12-Ny1": lambda: make_lines(Nx=12, Ny=1, dx=25.0, dy=40.0, freqs=(6.0, 11.0), kappa=100.0, **kw),
+    }
+
+
+def _line_records(s, seed):
+    rng = np.random.default_rng(seed)
+    shape = (len(s.freqs), s.n_line, s.n_mid, s.n_mid)
+    return rng.normal(size=shape) + 1j * rng.normal(size=shape)
+
+
+@pytest.mark.parametrize("name", list(_line_cases()))
+def test_line_survey_shot_records_to_rows(name):
+    s = _line_cases()[name]()
+    pl = plan_lines(s)
+    D = _line_records(s, 37)
+    p = E.Plan(s)
+    assert p.records_shape() == D.shape
+    _check_rows(name, pl, _gpu_rows(p, D), shots_to_rows(s, pl, D))
+
+
+def test_line_survey_shot_records_to_complex64_rows():
+    s = _line_cases()["Nx15-Ny7-odd-cut"]()
+    pl = plan_lines(s)
+    D = _line_records(s, 41)
+    d = _gpu_rows(E.Plan(s, data="c64"), D)
+    assert d.dtype == np.complex64
+    ref, _ = pack(pl, shots_to_rows(s, pl, D))
+    # the library rounds its FP64 datum once
+    err = np.max(np.abs(d.astype(np.complex128) - ref))
+    assert err <= 1.2e-7 * np.max(np.abs(ref)), err / np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("Nx,Ny", [(8, 6), (7, 5)])
+def test_line_survey_born_records_give_the_oracle_rows(Nx, Ny):
+    """Brute-force Born records of the line survey [f, line, R, S]: the GPU
+    rows equal the oracle's clean rows (no evanescent cut, which would drop
+    quadrature terms the brute-force records keep)."""
+    s = make_lines(Nx=Nx, Ny=Ny, dx=30.0, dy=45.0, nz=3, dz=25.0, freqs=(6.0, 9.0), vel=(1800.0, 2500.0),
+                   zif=(40.0,), kappa=100.0, seed=5)
+    pl = plan_lines(s)
+    clean = forward_lines(s, pl, vhat(s), line_tables(s))
+    D = np.stack([np.transpose(born_lines(s.vel, s.zif, f, s.eps, s.v_true, s.d_mid, s.d_line, s.z, s.dz),
+                               (2, 0, 1)) for f in s.freqs])
+    _check_rows(f"line Born records {Nx} x {Ny}", pl, _gpu_rows(E.Plan(s), D), clean)
+
+
+def test_line_survey_end_to_end_from_shot_records():
+    """Records whose transform holds the oracle's noisy data at the rows'
+    keys -> GPU transform, pack and FP64 solve, against the oracle's solve of
+    the oracle's rows of the same records."""
+    s = make_lines(Nx=12, Ny=6, dx=25.0, dy=40.0, nz=16, dz=15.0, freqs=(5.0, 8.0, 11.0, 14.0),
+                   vel=(1800.0, 2500.0), zif=(60.0,), kappa=1.0, noise_rel=0.05, seed=17)
+    pl = plan_lines(s)
+    tab = line_tables(s)
+    clean = forward_lines(s, pl, vhat(s), tab)
+    data = add_noise(s, pl, clean, noise_scale(s, pl, clean))
+    F = np.zeros((len(s.freqs), s.n_line, s.n_mid, s.n_mid), np.complex128)
+    for q, (d0, d1) in zip(pl.pairs, data):
+        F[q.f, q.key0[:, 2], q.key0[:, 0], q.key0[:, 1]] = d0
+        F[q.f, q.key1[:, 2], q.key1[:, 0], q.key1[:, 1]] = d1
+    D = np.fft.ifftn(F, axes=(1, 2, 3)) / s.d_mid
+    Vo, _ = solve_lines(s, pl, shots_to_rows(s, pl, D), tab)
+    p = E.Plan(s)
+    vel = torch.tensor(np.asarray(s.vel, np.float64), device="cuda")
+    sh = torch.from_numpy(D).cuda()
+    p.shots_fft(sh)
+    d = p.shots_pack(sh)
+    out = p.run(vel, d, s.lambda_rel, prec="fp64")
+    m = p.model(out["v"])
+    torch.cuda.synchronize()
+    g, per = rel_errors(out["v"].cpu().numpy(), Vo, pl)
+    ref = model_from_spectrum(s, Vo)
+    err = np.max(np.abs(m.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    print(f"line survey end to end: solve error {g:.2e} global, {per:.2e} per pair; model error {err:.2e}")
+    assert g <= 1e-10 and per <= 1e-10 and err <= 1e-10
+
+
+@pytest.mark.parametrize("Nx,Ny,nz", [(16, 8, 5), (15, 7, 33), (24, 1, 4), (128, 32, 70), (2048, 3, 2)])
+def test_line_survey_model_from_spectrum(Nx, Ny, nz):
+    """Seeded random spectra [N_x N_y, nz] -> the model [N_x, N_y, nz]:
+    radix-2 and direct lengths on both axes, a single line, the transform's
+    longest x axis; bar 1e-12 of the largest model value."""
+    s = make_lines(Nx=Nx, Ny=Ny, nz=nz, freqs=(3.0,), vel=(2000.0,), model="zero")
+    rng = np.random.default_rng(Nx * 100 + Ny)
+    V = rng.normal(size=(Nx * Ny, nz)) + 1j * rng.normal(size=(Nx * Ny, nz))
+    m = E.Plan(s).model(torch.from_numpy(V).cuda())
+    torch.cuda.synchronize()
+    ref = model_from_spectrum(s, V)
+    assert m.shape == ref.shape
+    err = np.max(np.abs(m.cpu().numpy() - ref))
+    assert err <= 1e-12 * np.max(np.abs(ref)), err / np.max(np.abs(ref))
+
+
+def test_line_survey_records_at_the_longest_transform():
+    """n_mid = 2048 on 4 lines: a plane wave of line index c0, receiver index
+    a0 and source index b0 lands on exactly the rows keyed (a0, b0, c0) (at
+    +k) and (-b0, -a0, -c0) (at -k), with value d_mid N_y N^2."""
+    N, Ny = 2048, 4
+    s = make_lines(Nx=N, Ny=Ny, dx=5.0, dy=100.0, nz=2, freqs=(11.0,), vel=(2000.0,), zif=(), kappa=1.0,
+                   model="zero")
+    p = E.Plan(s)
+    a0, b0, c0 = 37, 2048 - 45, 3
+    g = torch.arange(N, device="cuda", dtype=torch.float64)
+    gy = torch.arange(Ny, device="cuda", dtype=torch.float64)
+    wa = torch.polar(torch.ones_like(g), 2.0 * np.pi * a0 * g / N)
+    wb = torch.polar(torch.ones_like(g), 2.0 * np.pi * b0 * g / N)
+    wc = torch.polar(torch.ones_like(gy), 2.0 * np.pi * c0 * gy / Ny)
+    rec = (wc[:, None, None] * wa[None, :, None] * wb[None, None, :])[None].contiguous()
+    p.shots_fft(rec)
+    d = p.shots_pack(rec)
+    torch.cuda.synchronize()
+    d = d.cpu().numpy()
+    m = p.rowmap()
+    keys = m["keys"]
+    c = np.repeat(m["pair_km"][:, 0] % Ny, np.diff(m["row_off"]))
+    peak = s.d_mid * Ny * float(N) ** 2
+    hit0 = (keys[:, 0] == a0) & (keys[:, 1] == b0) & (c == c0)
+    hit1 = (((-keys[:, 1]) % N) == a0) & (((-keys[:, 0]) % N) == b0) & (((-c) % Ny) == c0)
+    err = max(np.max(np.abs(d[:, 0] - np.where(hit0, peak, 0.0))),
+              np.max(np.abs(d[:, 1] - np.where(hit1, peak, 0.0))))
+    print(f"N = {N}, N_y = {Ny}: {len(d)} rows, {int(hit0.sum())} + {int(hit1.sum())} hits, "
+          f"max error {err / peak:.2e} of the peak")
+    assert hit0.sum() + hit1.sum() >= 1
+    assert err <= 1e-10 * peak, err / peak
 
 
 def test_line_records_at_the_longest_transform():
