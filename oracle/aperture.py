@@ -15,6 +15,12 @@ datum at -u is convolved over the same receiver index.  The windowed system
 is (S A) x = d_W, and since the circulant S is an orthogonal projector its
 normal equations have the Gram Re(A^H S A) and the right-hand sides
 Re(A^H d_W).  Rows cut as evanescent are zero in A.
+
+Survey of parallel lines (Section 2.2): the decoupled 3D equation carries
+the same sinc over the offset wavenumber.  Each line is a 2D line of N_x
+positions whose records are kept where |x_R - x_S| <= 2 b; the window does
+not depend on the line, so at the pair (k_m, k_y) it is the same circulant
+S over the receiver index, applied to the line rows (oracle.lines3d).
 """
 from __future__ import annotations
 
@@ -78,9 +84,19 @@ def aperture_solve(s, pl, data, tabs, b_max, lambda_rel=None, pairs=None):
     """Damped solve of the windowed system: (Re(A^H S A) + lambda I) x =
     Re(A^H b+-), lambda = lambda_rel tr / nz, with b+- formed from `data`,
     which are the windowed data d_W (aperture_data) for the windowed system.
-    V~ (n_km, nz) and per-pair details."""
-    if getattr(s, "dim", 2) != 2:
-        raise ValueError("the 2D line survey only")
+    V~ (n_km, nz) and per-pair details.  2D line: `tabs` from
+    oracle.solve.gtables; survey of parallel lines: the table of
+    oracle.lines3d.line_tables and its plan."""
+    if getattr(s, "n_line", 0):
+        from .lines3d import line_row_values
+
+        def rows_of(p):
+            return line_row_values(s, p, tabs)
+    elif getattr(s, "dim", 2) == 2:
+        def rows_of(p):
+            return row_values(s, p, tabs.lookup)
+    else:
+        raise ValueError("the 2D line survey and the survey of parallel lines only")
     lam_rel = s.lambda_rel if lambda_rel is None else lambda_rel
     Sm = window_kernel(offset_window(s, b_max))
     pairs = pl.pairs if pairs is None else pairs
@@ -90,7 +106,7 @@ def aperture_solve(s, pl, data, tabs, b_max, lambda_rel=None, pairs=None):
         x = np.zeros((2, s.nz))
         inf, G = INFO_EMPTY, None
         if p.n_rows:
-            A = row_values(s, p, tabs.lookup)
+            A = rows_of(p)
             B = aperture_rows(s, p, A, Sm)
             G = (A.conj().T @ B).real
             bp, bm = 0.5 * (d0 + d1), (d0 - d1) / 2j
