@@ -101,7 +101,8 @@ typedef enum {
  *        decoupled 3D equation, L_y = n_line d_line).  A term is kept iff both
  *        |k| are within the cut below, a row iff a term is.  This survey is
  *        assembled in FP64 and solved without refinement (edt_solve with
- *        refine = 0, or edt_tsvd); edt_adjoint and edt_kz_restrict refuse it.
+ *        refine = 0, or edt_tsvd), and edt_aperture_gram gives its finite-aperture
+ *        Gram; edt_adjoint and edt_kz_restrict refuse it.
  * Frequencies freq_hz[n_freq] are used simultaneously (Section 3.1); eps is the
  * imaginary part of w (Section 2.1; 0.15 1/s in Section 3.1).  Depths are
  * z_i = z0 + i*dz, i < nz.  A row is kept iff |k_r| and |k_s| are both
@@ -470,7 +471,8 @@ edt_status edt_shots_fft(const edt_plan* plan, edt_c128* shots, hipStream_t stre
 edt_status edt_shots_pack(const edt_plan* plan, const edt_c128* spectrum, void* d_rows, hipStream_t stream);
 
 /*
- * Finite aperture (eq. M) on the 2D line survey: the Gram of every pair when
+ * Finite aperture (eq. M) on the 2D line survey and the survey of parallel
+ * lines: the Gram of every pair when
  * the records are kept only for full offsets |x_R - x_S| <= 2 b_max (b_max:
  * the largest half-offset, m).  On the periodic line the offset window acts
  * at each k_m as a circular convolution S of the rows over the receiver
@@ -483,8 +485,14 @@ edt_status edt_shots_pack(const edt_plan* plan, const edt_c128* spectrum, void* 
  * from the unwindowed rows) or edt_tsvd.  aperture_work: device, >=
  * edt_aperture_work_bytes (about P n_mid nz complex128: the transformed rows
  * of one frequency, plus per-pair frequency ranges and a twiddle table).
- * Errors: EDT_EINVAL for dim 3, n_mid > 2048, b_max negative or not finite,
- * or a null pointer (a plan with no pairs returns EDT_OK at once).
+ * Survey of parallel lines (Section 2.2, whose decoupled equation carries the
+ * same sinc over the offset wavenumber): the window acts on every line's
+ * offsets alike, so each (k_m, k_y) pair takes the same circulant S over its
+ * receiver index, applied to the line rows (formed per chunk of pairs and
+ * frequency as in edt_assemble); aperture_work then holds a chunk's rows and
+ * their kept offsets (at most 512 MiB).
+ * Errors: EDT_EINVAL for the 3D areal survey, n_mid > 2048, b_max negative or
+ * not finite, or a null pointer (a plan with no pairs returns EDT_OK at once).
  */
 edt_status edt_aperture_work_bytes(const edt_plan* plan, size_t* bytes);
 edt_status edt_aperture_gram(const edt_plan* plan, const edt_c128* g64, double b_max, double* gram, double* trace,

@@ -246,7 +246,10 @@ ApLayout aperture_layout(const edt_plan* p) {
     l.total = l.tw + up(size_t(p->n_mid) * sizeof(zd));
     return l;
 }
-size_t aperture_work_bytes(const edt_plan* p) { return aperture_layout(p).total; }
+size_t line_aperture_work_bytes(const edt_plan* p);
+size_t aperture_work_bytes(const edt_plan* p) {
+    return p->n_line ? line_aperture_work_bytes(p) : aperture_layout(p).total;
+}
 
 // Kept signed offsets: |s| d_mid <= 2 b_max for s in [-N/2, (N - 1)/2]
 // (the same comparison as the oracle's); a contiguous range [lo, lo + nW).

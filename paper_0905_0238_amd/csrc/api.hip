@@ -58,6 +58,8 @@ hipError_t launch_kz_restrict(const edt_plan* p, double K, double* gram, double*
                               int32_t* n_keep, hipStream_t st);
 size_t chol_lds_bytes(int nz);
 hipError_t configure_kernels();
+hipError_t launch_line_aperture_gram(const edt_plan* p, const zd* g64, double b_max, double* gram, double* trace,
+                                     unsigned char* work, hipStream_t st);
 hipError_t launch_line_assemble(const edt_plan* p, const zd* g64, const void* d_rows, double* gram, double* rhs,
                                 double* trace, unsigned char* work, hipStream_t st);
 hipError_t launch_line_forward(const edt_plan* p, const zd* g64, const zd* v, void* d_rows, hipStream_t st);
@@ -618,8 +620,8 @@ edt_status edt_aperture_gram(const edt_plan* p, const edt_c128* g64, double b_ma
                              void* aperture_work, hipStream_t stream) {
     edt_status s = check_plan(p);
     if (s != EDT_OK) return s;
-    if (p->dim != 2) {
-        set_error("finite aperture of the 2D line survey only");
+    if (p->dim != 2 && !p->n_line) {
+        set_error("finite aperture of the 2D line survey and the survey of parallel lines only");
         return EDT_EINVAL;
     }
     if (p->n_mid > kMaxLine) {
@@ -635,9 +637,14 @@ edt_status edt_aperture_gram(const edt_plan* p, const edt_c128* g64, double b_ma
         set_error("missing argument");
         return EDT_EINVAL;
     }
-    EDT_TRY(launch_aperture_gram(p, reinterpret_cast<const zd*>(g64), b_max, gram, trace,
-                                 static_cast<unsigned char*>(aperture_work), stream),
-            "aperture gram");
+    if (p->n_line)
+        EDT_TRY(launch_line_aperture_gram(p, reinterpret_cast<const zd*>(g64), b_max, gram, trace,
+                                          static_cast<unsigned char*>(aperture_work), stream),
+                "aperture gram");
+    else
+        EDT_TRY(launch_aperture_gram(p, reinterpret_cast<const zd*>(g64), b_max, gram, trace,
+                                     static_cast<unsigned char*>(aperture_work), stream),
+                "aperture gram");
     return EDT_OK;
 }
 

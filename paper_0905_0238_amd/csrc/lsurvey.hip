@@ -179,6 +179,71 @@ hipError_t launch_line_assemble(const edt_plan* p, const zd* g64, const void* d_
     return launch_gram_trace(gram, nz, trace, P, st);
 }
 
+// Finite aperture on the survey of parallel lines (the sinc over the offset
+// wavenumber in the decoupled 3D equation).  The window |x_R - x_S| <= 2 b
+// is the same on every line, so at each pair it is the circulant of the 2D
+// line over the receiver index: per chunk and frequency the formed rows are
+// transformed over their receiver slot (Ah(o) = sum_a A(a) e^{2 pi i a o / N_x};
+// the slot's shift by N_x / 2 is a phase per offset, which Re(Ah^H Ah)
+// cancels), the kept offsets are copied together, and the FP64 product adds
+// (1 / N_x) Re(Ah^H Ah) over them.
+
+void aperture_offsets(const edt_plan* p, double b_max, int* lo, int* nW);
+
+// K[p][i][z] = Rh[p][(lo + i) mod N_x][z] for the nW kept offsets.
+__global__ __launch_bounds__(256) void line_kept_kernel(const zd* __restrict__ Rh, int Nx, int nz, int lo, int nW,
+                                                        int bpp, zd* __restrict__ K) {
+    const int64_t p = blockIdx.x / bpp;
+    const int e = int(blockIdx.x % bpp) * 256 + int(threadIdx.x);
+    if (e >= nW * nz) return;
+    const int i = e / nz, z = e - i * nz;
+    int o = (lo + i) % Nx;
+    if (o < 0) o += Nx;
+    K[(p * nW + i) * nz + z] = Rh[(p * Nx + o) * nz + z];
+}
+
+// Work: the rows of one chunk and frequency, then their kept offsets.
+size_t line_aperture_work_bytes(const edt_plan* p) {
+    const size_t rows = (size_t(line_chunk(p)) * p->n_mid * p->nz * sizeof(zd) + 255) & ~size_t(255);
+    return std::max<size_t>(256, 2 * rows);
+}
+
+hipError_t launch_line_aperture_gram(const edt_plan* p, const zd* g64, double b_max, double* gram, double* trace,
+                                     unsigned char* work, hipStream_t st) {
+    const int64_t P = p->n_pairs;
+    if (P == 0) return hipSuccess;
+    const int64_t chunk = line_chunk(p);
+    const int Nx = p->n_mid, Ny = p->n_line, nz = p->nz;
+    zd* Rh = reinterpret_cast<zd*>(work);
+    zd* K = reinterpret_cast<zd*>(work + line_aperture_work_bytes(p) / 2);
+    int lo = 0, nW = 0;
+    aperture_offsets(p, b_max, &lo, &nW);
+    const int bpp = (nW * nz + 255) / 256;
+    const double Ly = double(Ny) * p->d_line;
+    for (int64_t p0 = 0; p0 < P; p0 += chunk) {
+        const int64_t np = std::min<int64_t>(chunk, P - p0);
+        for (int f = 0; f < p->n_freq; ++f) {
+            const double wr = kTwoPiD * p->freq[size_t(f)], wi = p->eps;
+            const zd W{p->dz * (wr * wr - wi * wi) / Ly, p->dz * (2.0 * wr * wi) / Ly};
+            hipLaunchKernelGGL(line_rows_kernel, dim3(unsigned(np)), dim3(256), 0, st, g64,
+                               dptr<const int32_t>(p, p->lay.keys), dptr<const uint64_t>(p, p->lay.lmask),
+                               dptr<const int64_t>(p, p->lay.lfr), dptr<const int32_t>(p, p->lay.pair_u), f,
+                               p->n_freq, p->n_cls, Nx, Ny, nz, W, p0, Rh);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            if ((e = launch_lines(Rh, Nx, np, Lines{int64_t(Nx) * nz, 1, nz, nz}, 1.0, 1.0, st)) != hipSuccess)
+                return e;
+            hipLaunchKernelGGL(line_kept_kernel, dim3(unsigned(np * bpp)), dim3(256), 0, st, Rh, Nx, nz, lo, nW, bpp,
+                               K);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((e = launch_rows_gram(K, nz, nW, 1.0 / double(Nx), f == 0, gram + size_t(p0) * nz * nz, np, st)) !=
+                hipSuccess)
+                return e;
+        }
+    }
+    return launch_gram_trace(gram, nz, trace, P, st);
+}
+
 hipError_t launch_line_forward(const edt_plan* p, const zd* g64, const zd* v, void* d_rows, hipStream_t st) {
     const int64_t R = p->n_rows;
     if (R == 0) return hipSuccess;

@@ -14,7 +14,8 @@ against the oracle (oracle.aperture), pair by pair.
   binding's default step limit, from windowed data and end to end from
   records windowed in full offset (transform, gather, windowed Gram,
   truncated SVD, model);
-* 3D surveys are refused.
+* 3D areal surveys are refused (the survey of parallel lines is covered in
+  tests/test_gpu_lines3d.py).
 """
 import numpy as np
 import pytest
@@ -236,7 +237,7 @@ def test_sampled_pairs_at_full_size():
         assert np.max(np.abs(G[low] - ref[low])) <= 1e-12 * np.max(np.abs(ref)), i
 
 
-def test_3d_surveys_are_refused():
+def test_3d_areal_surveys_are_refused():
     s = make_custom(dim=3, N=12, Nh=6, nz=5, dx=25.0, freqs=(5.0,), vel=(2000.0,))
     p = E.Plan(s)
     g64 = torch.zeros(1, 1, 5, dtype=torch.complex128, device="cuda")

@@ -8,6 +8,11 @@ against the FP64 oracle (oracle.lines3d).
   the same rounded data;
 * the Born forward map against the oracle's data, to 1e-12;
 * the truncated SVD runs on the line Gram;
+* the finite aperture (edt_aperture_gram, the offset window on every line):
+  the windowed Gram and trace against the oracle's Re(A^H S A) to 1e-12, the
+  damped solve of windowed data against the oracle's to 1e-10, a window
+  holding every offset gives edt_assemble's Gram, and sampled pairs of the
+  larger survey (three chunks of pairs) against the oracle;
 * what the line survey does not cover is refused.
 Surveys: odd and even grids, with and without the evanescent cut, depth
 counts that span several 64-tiles with a ragged tail, and a larger survey on
@@ -18,6 +23,7 @@ import pytest
 
 from edt_inputs import make_lines, vhat
 from oracle.lines3d import forward_lines, line_row_values, line_tables, plan_lines, solve_lines
+from oracle.aperture import aperture_data, aperture_rows, aperture_solve, offset_window, window_kernel
 from oracle.solve import add_noise, noise_scale, normal_equations, pack
 from tests._cases import rel_errors
 
@@ -147,6 +153,43 @@ def test_truncated_svd_on_the_line_gram():
     assert checked > 0
 
 
+@pytest.mark.parametrize("name,b", [("even-nocut", 60.0), ("odd-cut", 45.0), ("deep-cut", 40.0)])
+def test_line_aperture_gram_and_solve(name, b):
+    s = CASES[name]()
+    pl, tab, clean, data, d_rows, off = _case(s)
+    w = offset_window(s, b)
+    assert 0 < w.sum() < s.n_mid
+    Sm = window_kernel(w)
+    dW = aperture_data(s, pl, data, b)
+    p = E.Plan(s)
+    g64, _ = p.green(_dev(np.asarray(s.vel, np.float64)), want32=False)
+    d = _dev(pack(pl, dW)[0])
+    gram_full, rhs, trace_full = p.assemble(g64, None, d, "fp64")
+    gram, trace = p.aperture_gram(g64, b)
+    x, v, info, _ = p.solve(g64, d, gram.clone(), rhs, trace, s.lambda_rel)   # the solve factors in place
+    gram_all, trace_all = p.aperture_gram(g64, 1e6)
+    torch.cuda.synchronize()
+    G, T = gram.cpu().numpy(), trace.cpu().numpy()
+    low = np.tril(np.ones((s.nz, s.nz), bool))
+    for i, q in enumerate(pl.pairs):
+        if not q.n_rows:
+            continue
+        A = line_row_values(s, q, tab)
+        ref = (A.conj().T @ aperture_rows(s, q, A, Sm)).real
+        assert np.max(np.abs(G[i][low] - ref[low])) <= 1e-12 * np.max(np.abs(ref)), (name, i)
+        assert abs(T[i] - np.trace(ref)) <= 1e-12 * abs(np.trace(ref)), (name, i)
+    Vo, _ = aperture_solve(s, pl, dW, tab, b)
+    g, per = rel_errors(v.cpu().numpy(), Vo, pl)
+    print(f"{name}: aperture b = {b} m ({int(w.sum())} of {s.n_mid} offsets); solve error {g:.2e} global, "
+          f"{per:.2e} per pair", flush=True)
+    assert g <= 1e-10 and per <= 1e-10
+    Ga, Gf = gram_all.cpu().numpy(), gram_full.cpu().numpy()
+    for i in range(len(pl.pairs)):
+        scale = max(np.max(np.abs(Gf[i][low])), 1e-300)
+        assert np.max(np.abs(Ga[i][low] - Gf[i][low])) <= 1e-12 * scale
+    assert np.allclose(trace_all.cpu().numpy(), trace_full.cpu().numpy(), rtol=1e-12, atol=0)
+
+
 def test_line_survey_refusals():
     s = CASES["even-nocut"]()
     pl, tab, clean, data, d_rows, off = _case(s)
@@ -216,3 +259,14 @@ def test_sampled_pairs_of_a_larger_line_survey():
         worst = max(worst, err)
     print(f"line survey 128x32, nz 128: {len(rows)} pairs, {int(rows.sum())} rows, largest {int(rows.max())}; "
           f"8 sampled pairs worst {worst:.2e}", flush=True)
+    # the finite aperture over the whole survey (three chunks of pairs), the
+    # sampled pairs against the oracle
+    b = 0.15 * s.n_mid * s.d_mid
+    Sm = window_kernel(offset_window(s, b))
+    gram_w, trace_w = p.aperture_gram(g64, b)
+    Gw, Tw = gram_w[pick].cpu().numpy(), trace_w[pick].cpu().numpy()
+    for j, (q, i) in enumerate(zip(pl.pairs, pick)):
+        A = line_row_values(s, q, tab)
+        ref = (A.conj().T @ aperture_rows(s, q, A, Sm)).real
+        assert np.max(np.abs(Gw[j][low] - ref[low])) <= 1e-12 * np.max(np.abs(ref)), i
+        assert abs(Tw[j] - np.trace(ref)) <= 1e-12 * abs(np.trace(ref)), i
