@@ -390,6 +390,52 @@ def shots_leg(plan, reps, torch):
                         "per_call": f"2 passes x (read + write) x 16 B x n_freq N^2 = {nb:.4g} B"}}
 
 
+def lines_leg(reps, torch):
+    """3D survey of parallel lines (FP64): 128 positions at 12.5 m on 32
+    lines 25 m apart, nz = 128, 32 frequencies 4-40 Hz, four layers, with the
+    evanescent cut; data from the device Born map of the seeded model.  Times
+    per call of green + assemble + damped solve, and of the finite-aperture
+    Gram (b = 0.15 N_x dx).  The Gram's algorithmic work is 2 nz (nz + 1)
+    flop per row; its rate over the whole pass (the rows' forming, a sum of
+    up to N_y products per value, is inside the time) against the FP64 MFMA
+    peak."""
+    import paper_0905_0238_amd as E
+    from edt_inputs import make_lines, vhat
+    s = make_lines(Nx=128, Ny=32, dx=12.5, dy=25.0, nz=128, dz=10.0, freqs=tuple(np.linspace(4.0, 40.0, 32)),
+                   vel=(1600.0, 2200.0, 2900.0, 3500.0), zif=(150.0, 450.0, 900.0), kappa=1.0, seed=7)
+    p = E.Plan(s)
+    vel = torch.tensor(np.asarray(s.vel, np.float64), device="cuda")
+    g64, _ = p.green(vel, want32=False)
+    d = p.forward(g64, torch.from_numpy(np.ascontiguousarray(vhat(s))).cuda())
+    b = 0.15 * s.n_mid * s.d_mid
+    work = p.aperture_work()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_solve = t_ap = 0.0
+    for r in range(reps + 1):
+        ev[0].record()
+        g64, _ = p.green(vel, want32=False)
+        gram, rhs, trace = p.assemble(g64, None, d, "fp64")
+        x, v, info, _ = p.solve(g64, d, gram, rhs, trace, s.lambda_rel)
+        ev[1].record()
+        p.aperture_gram(g64, b, work=work)
+        ev[2].record()
+        torch.cuda.synchronize()
+        if r > 0:
+            t_solve += ev[0].elapsed_time(ev[1])
+            t_ap += ev[1].elapsed_time(ev[2])
+    t_solve /= reps
+    t_ap /= reps
+    fl = float(p.n_rows) * 2 * s.nz * (s.nz + 1)
+    ach = fl / (t_solve * 1e-3) / 1e12
+    return {"survey": "128 positions x 32 lines, nz 128, 32 frequencies", "pairs": int(p.n_pairs),
+            "rows": int(p.n_rows), "ms_per_pass": t_solve, "subproblems_per_s": p.n_km / (t_solve * 1e-3),
+            "aperture_ms_per_call": t_ap, "aperture_b_m": b,
+            "assembly_products": {"bound": "mfma", "achieved": ach, "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                                  "frac": ach / PEAK["fp64"],
+                                  "per_pass": f"rows x 2 nz (nz+1) = {fl:.4g} flop over the whole pass "
+                                              f"(rows, products, right-hand sides and solve inside the time)"}}
+
+
 def aperture_leg(plan, vel, d_mid, reps, torch):
     """Finite aperture (2D): the windowed Gram of every pair with the paper's
     aperture-to-line ratio (a 6 km full-offset window on its 40 km line, so
@@ -767,6 +813,7 @@ def main():
         sl = shots_leg(plans["fp64"], 3, torch)
         if sl is not None:
             out["detail"]["shots"] = sl
+        out["detail"]["lines"] = lines_leg(2, torch)
     if not a.no_cpu:
         n_cpu = a.cpu_pairs or (512 if s.dim == 3 else 160)
         base, errs = cpu_baseline_leg(s, plan, pipes, n_cpu, torch)

@@ -5,9 +5,10 @@
 // weighted w^2 dz / L_y (the k_h'' integral on the periodic grid of lines).
 //
 // A row is a sum of up to n_line products, not one, so the rows of one
-// frequency are formed into HBM (a chunk of pairs at a time, every receiver
-// index a slot, zero where the row is cut) and the finite aperture's FP64
-// MFMA product accumulates Re(A^H A) over the frequencies; the right-hand
+// frequency are formed into HBM (a chunk of pairs at a time, as many slots per
+// pair as the chunk's largest row count, zero past a pair's rows) and the
+// finite aperture's FP64 MFMA product accumulates Re(A^H A) over the
+// frequencies; the right-hand
 // sides Re(A^H b+-) are accumulated from the same rows, and the trace is the
 // Gram's diagonal.  The rows' terms (which q are kept) come from the planner's
 // per-row masks, so no cut is decided here.
@@ -35,52 +36,59 @@ __device__ __forceinline__ zd line_row_value(const zd* __restrict__ gf, int a, i
     return v;
 }
 
-// Rows of frequency f of the pairs p0 .. p0 + gridDim.x - 1: Rh[p - p0][slot][z]
-// with slot = a + Nx/2 the receiver index (zero where the pair has no row).
-// One block per pair; a slot map in LDS finds each slot's row.
+// Rows of frequency f of the pairs p0 .. p0 + gridDim.x - 1, one block per
+// pair.  SLOTS: Rh[p - p0][slot][z] with slot = a + Nx/2 the receiver index
+// (zero where the pair has no row; a slot map in LDS finds each slot's row),
+// the layout the transform over the receiver index needs.  Otherwise
+// compact: Rh[p - p0][i][z] holds the pair's i-th row of the frequency, zero
+// for i past its rows (nr slots per pair, the chunk's largest row count).
+template <bool SLOTS>
 __global__ __launch_bounds__(256) void line_rows_kernel(const zd* __restrict__ g64, const int32_t* __restrict__ keys,
                                                         const uint64_t* __restrict__ lmask,
                                                         const int64_t* __restrict__ lfr,
                                                         const int32_t* __restrict__ pair_u, int f, int n_freq,
-                                                        int n_cls, int Nx, int Ny, int nz, zd W, int64_t p0,
+                                                        int n_cls, int Nx, int Ny, int nz, int nr, zd W, int64_t p0,
                                                         zd* __restrict__ Rh) {
-    __shared__ int s_row[2048];
+    __shared__ int s_row[SLOTS ? 2048 : 1];
     const int64_t p = p0 + blockIdx.x;
     const int tid = threadIdx.x;
-    for (int i = tid; i < Nx; i += 256) s_row[i] = -1;
-    __syncthreads();
     const int64_t r0 = lfr[p * (n_freq + 1) + f], r1 = lfr[p * (n_freq + 1) + f + 1];
-    for (int64_t r = r0 + tid; r < r1; r += 256) s_row[signed_idx(keys[2 * r], Nx) + Nx / 2] = int(r - r0);
-    __syncthreads();
+    if constexpr (SLOTS) {
+        for (int i = tid; i < Nx; i += 256) s_row[i] = -1;
+        __syncthreads();
+        for (int64_t r = r0 + tid; r < r1; r += 256) s_row[signed_idx(keys[2 * r], Nx) + Nx / 2] = int(r - r0);
+        __syncthreads();
+    }
     const int qc = signed_idx(pair_u[2 * p] % Ny, Ny);
     const zd* gf = g64 + size_t(f) * n_cls * nz;
-    zd* out = Rh + size_t(blockIdx.x) * Nx * nz;
-    for (int e = tid; e < Nx * nz; e += 256) {
-        const int slot = e / nz, z = e % nz;
-        const int rr = s_row[slot];
+    zd* out = Rh + size_t(blockIdx.x) * nr * nz;
+    for (int e = tid; e < nr * nz; e += 256) {
+        const int i = e / nz, z = e % nz;
+        const int rr = SLOTS ? s_row[i] : (i < r1 - r0 ? i : -1);
         zd v{0.0, 0.0};
         if (rr >= 0) {
             const int64_t r = r0 + rr;
-            v = W * line_row_value(gf, slot - Nx / 2, signed_idx(keys[2 * r + 1], Nx), lmask[r], qc, Ny, nz, z);
+            v = W * line_row_value(gf, signed_idx(keys[2 * r], Nx), signed_idx(keys[2 * r + 1], Nx), lmask[r], qc,
+                                   Ny, nz, z);
         }
         out[e] = v;
     }
 }
 
 // rhs[p][0|1][z] (first: =, else +=) Re(sum over the rows of frequency f of
-// conj(A(z)) b+-), b+ = (d0 + d1)/2, b- = (d0 - d1)/(2i), from the formed rows.
+// conj(A(z)) b+-), b+ = (d0 + d1)/2, b- = (d0 - d1)/(2i), from the rows
+// formed compactly (nr per pair).
 template <class D>
-__global__ __launch_bounds__(256) void line_rhs_kernel(const zd* __restrict__ Rh, const int32_t* __restrict__ keys,
-                                                       const int64_t* __restrict__ lfr, const D* __restrict__ d_rows,
-                                                       int f, int n_freq, int Nx, int nz, int64_t p0, int first,
-                                                       double* __restrict__ rhs) {
+__global__ __launch_bounds__(256) void line_rhs_kernel(const zd* __restrict__ Rh, const int64_t* __restrict__ lfr,
+                                                       const D* __restrict__ d_rows, int f, int n_freq, int nr, int nz,
+                                                       int64_t p0, int first, double* __restrict__ rhs) {
     const int64_t p = p0 + blockIdx.x;
     const int64_t r0 = lfr[p * (n_freq + 1) + f], r1 = lfr[p * (n_freq + 1) + f + 1];
-    const zd* R = Rh + size_t(blockIdx.x) * Nx * nz;
+    const zd* R = Rh + size_t(blockIdx.x) * nr * nz;
     for (int z = threadIdx.x; z < nz; z += 256) {
         double cp = 0.0, cm = 0.0;
         for (int64_t r = r0; r < r1; ++r) {
-            const zd A = R[size_t(signed_idx(keys[2 * r], Nx) + Nx / 2) * nz + z];
+            const zd A = R[size_t(r - r0) * nz + z];
             const zd d0 = load_datum(d_rows, 2 * r), d1 = load_datum(d_rows, 2 * r + 1);
             const zd bp = 0.5 * (d0 + d1);
             const zd df = d0 - d1;
@@ -157,22 +165,30 @@ hipError_t launch_line_assemble(const edt_plan* p, const zd* g64, const void* d_
         for (int f = 0; f < p->n_freq; ++f) {
             const double wr = kTwoPiD * p->freq[size_t(f)], wi = p->eps;
             const zd W{p->dz * (wr * wr - wi * wi) / Ly, p->dz * (2.0 * wr * wi) / Ly};
-            hipLaunchKernelGGL(line_rows_kernel, dim3(unsigned(np)), dim3(256), 0, st, g64,
+            // rows formed compactly: as many slots per pair as the chunk's
+            // largest row count at this frequency (at least one, of zeros)
+            int64_t nr = 1;
+            for (int64_t q = p0; q < p0 + np; ++q) {
+                const int64_t* fr = p->lfr.data() + size_t(q) * size_t(p->n_freq + 1);
+                nr = std::max<int64_t>(nr, fr[f + 1] - fr[f]);
+            }
+            hipLaunchKernelGGL(line_rows_kernel<false>, dim3(unsigned(np)), dim3(256), 0, st, g64,
                                dptr<const int32_t>(p, p->lay.keys), dptr<const uint64_t>(p, p->lay.lmask),
                                dptr<const int64_t>(p, p->lay.lfr), dptr<const int32_t>(p, p->lay.pair_u), f,
-                               p->n_freq, p->n_cls, Nx, Ny, nz, W, p0, Rh);
+                               p->n_freq, p->n_cls, Nx, Ny, nz, int(nr), W, p0, Rh);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
-            if ((e = launch_rows_gram(Rh, nz, Nx, 1.0, f == 0, gram + size_t(p0) * nz * nz, np, st)) != hipSuccess)
+            if ((e = launch_rows_gram(Rh, nz, int(nr), 1.0, f == 0, gram + size_t(p0) * nz * nz, np, st)) !=
+                hipSuccess)
                 return e;
             if (p->data_c64)
                 hipLaunchKernelGGL(line_rhs_kernel<float2>, dim3(unsigned(np)), dim3(256), 0, st, Rh,
-                                   dptr<const int32_t>(p, p->lay.keys), dptr<const int64_t>(p, p->lay.lfr),
-                                   static_cast<const float2*>(d_rows), f, p->n_freq, Nx, nz, p0, f == 0 ? 1 : 0, rhs);
+                                   dptr<const int64_t>(p, p->lay.lfr), static_cast<const float2*>(d_rows), f,
+                                   p->n_freq, int(nr), nz, p0, f == 0 ? 1 : 0, rhs);
             else
                 hipLaunchKernelGGL(line_rhs_kernel<zd>, dim3(unsigned(np)), dim3(256), 0, st, Rh,
-                                   dptr<const int32_t>(p, p->lay.keys), dptr<const int64_t>(p, p->lay.lfr),
-                                   static_cast<const zd*>(d_rows), f, p->n_freq, Nx, nz, p0, f == 0 ? 1 : 0, rhs);
+                                   dptr<const int64_t>(p, p->lay.lfr), static_cast<const zd*>(d_rows), f, p->n_freq,
+                                   int(nr), nz, p0, f == 0 ? 1 : 0, rhs);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     }
@@ -225,10 +241,10 @@ hipError_t launch_line_aperture_gram(const edt_plan* p, const zd* g64, double b_
         for (int f = 0; f < p->n_freq; ++f) {
             const double wr = kTwoPiD * p->freq[size_t(f)], wi = p->eps;
             const zd W{p->dz * (wr * wr - wi * wi) / Ly, p->dz * (2.0 * wr * wi) / Ly};
-            hipLaunchKernelGGL(line_rows_kernel, dim3(unsigned(np)), dim3(256), 0, st, g64,
+            hipLaunchKernelGGL(line_rows_kernel<true>, dim3(unsigned(np)), dim3(256), 0, st, g64,
                                dptr<const int32_t>(p, p->lay.keys), dptr<const uint64_t>(p, p->lay.lmask),
                                dptr<const int64_t>(p, p->lay.lfr), dptr<const int32_t>(p, p->lay.pair_u), f,
-                               p->n_freq, p->n_cls, Nx, Ny, nz, W, p0, Rh);
+                               p->n_freq, p->n_cls, Nx, Ny, nz, Nx, W, p0, Rh);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
             if ((e = launch_lines(Rh, Nx, np, Lines{int64_t(Nx) * nz, 1, nz, nz}, 1.0, 1.0, st)) != hipSuccess)
