@@ -19,19 +19,26 @@ namespace edt {
 
 __device__ __forceinline__ int signed_idx(int n, int N) { return n < (N + 1) / 2 ? n : n - N; }
 
-// Value of row r (receiver index a, source index b, term mask m) at depth z:
-// sum over the set bits of m, ascending q.
+// Value of row r (receiver index a, source index b, term mask m) at depth z.
+// The terms q and -q share the receiver factor g(|(k_a, k_q)|), so the sum
+// runs over |q|: one receiver load and up to two source loads per |q|.
 __device__ __forceinline__ zd line_row_value(const zd* __restrict__ gf, int a, int b, uint64_t m, int qc, int Ny,
                                              int nz, int z) {
-    const int ny2 = Ny / 2 + 1, ia = abs(a), ib = abs(b);
-    zd v{0.0, 0.0};
-    while (m) {
-        const int bit = __builtin_ctzll(m);
-        m &= m - 1;
-        const int q = bit - Ny / 2;
+    const int ny2 = Ny / 2 + 1, ia = abs(a), ib = abs(b), h = Ny / 2;
+    auto src = [&](int q) {   // g(|(k_b, k_{q-c})|)
         int pq = (q - qc) % Ny;
         pq = signed_idx(pq < 0 ? pq + Ny : pq, Ny);
-        v = v + gf[size_t(ia * ny2 + abs(q)) * nz + z] * gf[size_t(ib * ny2 + abs(pq)) * nz + z];
+        return gf[size_t(ib * ny2 + abs(pq)) * nz + z];
+    };
+    zd v{0.0, 0.0};
+    for (int k = 0; k <= h; ++k) {
+        const bool kp = k + h < Ny && ((m >> (k + h)) & 1u);   // q = +k
+        const bool kn = k > 0 && ((m >> (h - k)) & 1u);        // q = -k
+        if (!kp && !kn) continue;
+        zd s{0.0, 0.0};
+        if (kp) s = src(k);
+        if (kn) s = s + src(-k);
+        v = v + gf[size_t(ia * ny2 + k) * nz + z] * s;
     }
     return v;
 }
