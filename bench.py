@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--tsvd", type=float, default=1e-2,
                     help="relative tolerance of the truncated-SVD leg (the paper's own solver), "
                          "timed after the main passes; 0 skips it")
+    ap.add_argument("--lines-only", action="store_true",
+                    help="time only the 3D survey of parallel lines (profiling runs of its kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three plain 1 GiB device copies (the reference for the HBM byte "
                          "counters FETCH_SIZE / WRITE_SIZE) and exit")
@@ -723,6 +725,9 @@ def main():
         sys.exit(2)
     if a.copy_calibration:
         return copy_calibration(torch)
+    if a.lines_only:
+        print(json.dumps({"lines": lines_leg(max(1, a.steps), torch)}), flush=True)
+        return None
     import paper_0905_0238_amd as E
     from edt_inputs import make_config, CONFIG_NAMES
     s = make_config(a.config)
