@@ -488,9 +488,9 @@ edt_status edt_shots_pack(const edt_plan* plan, const edt_c128* spectrum, void* 
  * Survey of parallel lines (Section 2.2, whose decoupled equation carries the
  * same sinc over the offset wavenumber): the window acts on every line's
  * offsets alike, so each (k_m, k_y) pair takes the same circulant S over its
- * receiver index, applied to the line rows (formed per chunk of pairs and
- * frequency as in edt_assemble); aperture_work then holds a chunk's rows and
- * their kept offsets (at most 512 MiB).
+ * receiver index, applied to the line rows (built per chunk of pairs and
+ * frequency); aperture_work then holds a chunk's kept offsets (at most
+ * 256 MiB).
  * Errors: EDT_EINVAL for the 3D areal survey, n_mid > 2048, b_max negative or
  * not finite, or a null pointer (a plan with no pairs returns EDT_OK at once).
  */

@@ -266,13 +266,14 @@ void aperture_offsets(const edt_plan* p, double b_max, int* lo, int* nW) {
     *nW = count;
 }
 
+hipError_t configure_line_aperture();
 hipError_t configure_aperture() {
     for (const void* k : {reinterpret_cast<const void*>(ap_rows_fft_kernel<true>),
                           reinterpret_cast<const void*>(ap_rows_fft_kernel<false>)}) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kApLds);
         if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    return configure_line_aperture();
 }
 
 hipError_t launch_aperture_gram(const edt_plan* p, const zd* g64, double b_max, double* gram, double* trace,

@@ -14,6 +14,7 @@
 // per-row masks, so no cut is decided here.
 
 #include "dev_common.h"
+#include "lines.h"
 
 namespace edt {
 
@@ -44,37 +45,25 @@ __device__ __forceinline__ zd line_row_value(const zd* __restrict__ gf, int a, i
 }
 
 // Rows of frequency f of the pairs p0 .. p0 + gridDim.x - 1, one block per
-// pair.  SLOTS: Rh[p - p0][slot][z] with slot = a + Nx/2 the receiver index
-// (zero where the pair has no row; a slot map in LDS finds each slot's row),
-// the layout the transform over the receiver index needs.  Otherwise
-// compact: Rh[p - p0][i][z] holds the pair's i-th row of the frequency, zero
-// for i past its rows (nr slots per pair, the chunk's largest row count).
-template <bool SLOTS>
+// pair, formed compactly: Rh[p - p0][i][z] holds the pair's i-th row of the
+// frequency, zero for i past its rows (nr slots per pair, the chunk's largest
+// row count).
 __global__ __launch_bounds__(256) void line_rows_kernel(const zd* __restrict__ g64, const int32_t* __restrict__ keys,
                                                         const uint64_t* __restrict__ lmask,
                                                         const int64_t* __restrict__ lfr,
                                                         const int32_t* __restrict__ pair_u, int f, int n_freq,
                                                         int n_cls, int Nx, int Ny, int nz, int nr, zd W, int64_t p0,
                                                         zd* __restrict__ Rh) {
-    __shared__ int s_row[SLOTS ? 2048 : 1];
     const int64_t p = p0 + blockIdx.x;
-    const int tid = threadIdx.x;
-    const int64_t r0 = lfr[p * (n_freq + 1) + f], r1 = lfr[p * (n_freq + 1) + f + 1];
-    if constexpr (SLOTS) {
-        for (int i = tid; i < Nx; i += 256) s_row[i] = -1;
-        __syncthreads();
-        for (int64_t r = r0 + tid; r < r1; r += 256) s_row[signed_idx(keys[2 * r], Nx) + Nx / 2] = int(r - r0);
-        __syncthreads();
-    }
+    const int64_t r0 = lfr[p * (n_freq + 1) + f], n = lfr[p * (n_freq + 1) + f + 1] - r0;
     const int qc = signed_idx(pair_u[2 * p] % Ny, Ny);
     const zd* gf = g64 + size_t(f) * n_cls * nz;
     zd* out = Rh + size_t(blockIdx.x) * nr * nz;
-    for (int e = tid; e < nr * nz; e += 256) {
+    for (int e = threadIdx.x; e < nr * nz; e += 256) {
         const int i = e / nz, z = e % nz;
-        const int rr = SLOTS ? s_row[i] : (i < r1 - r0 ? i : -1);
         zd v{0.0, 0.0};
-        if (rr >= 0) {
-            const int64_t r = r0 + rr;
+        if (i < n) {
+            const int64_t r = r0 + i;
             v = W * line_row_value(gf, signed_idx(keys[2 * r], Nx), signed_idx(keys[2 * r + 1], Nx), lmask[r], qc,
                                    Ny, nz, z);
         }
@@ -179,7 +168,7 @@ hipError_t launch_line_assemble(const edt_plan* p, const zd* g64, const void* d_
                 const int64_t* fr = p->lfr.data() + size_t(q) * size_t(p->n_freq + 1);
                 nr = std::max<int64_t>(nr, fr[f + 1] - fr[f]);
             }
-            hipLaunchKernelGGL(line_rows_kernel<false>, dim3(unsigned(np)), dim3(256), 0, st, g64,
+            hipLaunchKernelGGL(line_rows_kernel, dim3(unsigned(np)), dim3(256), 0, st, g64,
                                dptr<const int32_t>(p, p->lay.keys), dptr<const uint64_t>(p, p->lay.lmask),
                                dptr<const int64_t>(p, p->lay.lfr), dptr<const int32_t>(p, p->lay.pair_u), f,
                                p->n_freq, p->n_cls, Nx, Ny, nz, int(nr), W, p0, Rh);
@@ -205,30 +194,95 @@ hipError_t launch_line_assemble(const edt_plan* p, const zd* g64, const void* d_
 // Finite aperture on the survey of parallel lines (the sinc over the offset
 // wavenumber in the decoupled 3D equation).  The window |x_R - x_S| <= 2 b
 // is the same on every line, so at each pair it is the circulant of the 2D
-// line over the receiver index: per chunk and frequency the formed rows are
-// transformed over their receiver slot (Ah(o) = sum_a A(a) e^{2 pi i a o / N_x};
-// the slot's shift by N_x / 2 is a phase per offset, which Re(Ah^H Ah)
-// cancels), the kept offsets are copied together, and the FP64 product adds
-// (1 / N_x) Re(Ah^H Ah) over them.
+// line over the receiver index: per chunk and frequency the rows are built
+// over their receiver index in LDS, transformed there
+// (Ah(o) = sum_a A(a) e^{2 pi i a o / N_x}), and only the kept offsets go to
+// HBM, where the FP64 product adds (1 / N_x) Re(Ah^H Ah) over them.
 
 void aperture_offsets(const edt_plan* p, double b_max, int* lo, int* nW);
 
-// K[p][i][z] = Rh[p][(lo + i) mod N_x][z] for the nW kept offsets.
-__global__ __launch_bounds__(256) void line_kept_kernel(const zd* __restrict__ Rh, int Nx, int nz, int lo, int nW,
-                                                        int bpp, zd* __restrict__ K) {
-    const int64_t p = blockIdx.x / bpp;
-    const int e = int(blockIdx.x % bpp) * 256 + int(threadIdx.x);
-    if (e >= nW * nz) return;
-    const int i = e / nz, z = e - i * nz;
-    int o = (lo + i) % Nx;
-    if (o < 0) o += Nx;
-    K[(p * nW + i) * nz + z] = Rh[(p * Nx + o) * nz + z];
+constexpr int kLineApLds = 80 * 1024;   // LDS of one build block
+
+// Pair p0 + blockIdx.x / (nz / L), depths z0 .. z0 + L - 1: the rows of
+// frequency f placed at their receiver index (fftfreq order; zero where the
+// pair has no row), transformed over it, and the kept offsets
+// o = (lo + k) mod N_x stored as K[p - p0][k][z].  A power-of-two N_x takes
+// the radix-2 transform, any other a direct sum for the kept offsets only.
+template <bool POW2>
+__global__ __launch_bounds__(256) void line_ap_rows_kernel(const zd* __restrict__ g64,
+                                                           const int32_t* __restrict__ keys,
+                                                           const uint64_t* __restrict__ lmask,
+                                                           const int64_t* __restrict__ lfr,
+                                                           const int32_t* __restrict__ pair_u, int f, int n_freq,
+                                                           int n_cls, int Nx, int logn, int Ny, int nz, int L, zd W,
+                                                           int64_t p0, int lo, int nW, zd* __restrict__ K) {
+    extern __shared__ zd s_mem[];
+    const int ns = lds_stride(Nx);
+    zd* s_x = s_mem;            // L lines of Nx values (padded layout)
+    zd* s_w = s_mem + L * ns;   // twiddles e^{2 pi i k / Nx}: Nx / 2 (radix 2) or Nx (direct)
+    const int tid = threadIdx.x;
+    const int per_pair = nz / L;
+    const int64_t pl = blockIdx.x / unsigned(per_pair), p = p0 + pl;
+    const int z0 = int(blockIdx.x % unsigned(per_pair)) * L;
+    const int nw = POW2 ? Nx / 2 : Nx;
+    for (int k = tid; k < nw; k += 256) {
+        double sv, cv;
+        sincospi(2.0 * double(k) / double(Nx), &sv, &cv);
+        s_w[k] = zd{cv, sv};
+    }
+    for (int e = tid; e < L * ns; e += 256) s_x[e] = zd{0.0, 0.0};
+    const int64_t r0 = lfr[p * (n_freq + 1) + f], n = lfr[p * (n_freq + 1) + f + 1] - r0;
+    const int qc = signed_idx(pair_u[2 * p] % Ny, Ny);
+    const zd* gf = g64 + size_t(f) * n_cls * nz;
+    __syncthreads();
+    for (int64_t e = tid; e < n * L; e += 256) {
+        const int64_t r = r0 + e / L;
+        const int j = int(e % L), z = z0 + j;
+        const int a = keys[2 * r];
+        const zd v = W * line_row_value(gf, signed_idx(a, Nx), signed_idx(keys[2 * r + 1], Nx), lmask[r], qc, Ny,
+                                        nz, z);
+        s_x[j * ns + lds_pad(POW2 ? bit_reverse(a, logn) : a)] = v;
+    }
+    __syncthreads();
+    zd* Kp = K + size_t(pl) * nW * nz;
+    if constexpr (POW2) {
+        dit_lines(s_x, s_w, Nx, logn, L);
+        for (int e = tid; e < L * nW; e += 256) {
+            const int j = e % L, k = e / L;
+            int o = (lo + k) % Nx;
+            if (o < 0) o += Nx;
+            Kp[size_t(k) * nz + z0 + j] = s_x[j * ns + lds_pad(o)];
+        }
+    } else {
+        for (int e = tid; e < L * nW; e += 256) {
+            const int j = e % L, k = e / L;
+            int o = (lo + k) % Nx;
+            if (o < 0) o += Nx;
+            zd acc{0.0, 0.0};
+            int m = 0;   // (a o) mod Nx
+            for (int a = 0; a < Nx; ++a) {
+                acc = acc + s_w[m] * s_x[j * ns + lds_pad(a)];
+                m += o;
+                if (m >= Nx) m -= Nx;
+            }
+            Kp[size_t(k) * nz + z0 + j] = acc;
+        }
+    }
 }
 
-// Work: the rows of one chunk and frequency, then their kept offsets.
+hipError_t configure_line_aperture() {
+    for (const void* k : {reinterpret_cast<const void*>(line_ap_rows_kernel<true>),
+                          reinterpret_cast<const void*>(line_ap_rows_kernel<false>)}) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kLineApLds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Work: the kept offsets of one chunk and frequency.
 size_t line_aperture_work_bytes(const edt_plan* p) {
-    const size_t rows = (size_t(line_chunk(p)) * p->n_mid * p->nz * sizeof(zd) + 255) & ~size_t(255);
-    return std::max<size_t>(256, 2 * rows);
+    const size_t kept = (size_t(line_chunk(p)) * p->n_mid * p->nz * sizeof(zd) + 255) & ~size_t(255);
+    return std::max<size_t>(256, kept);
 }
 
 hipError_t launch_line_aperture_gram(const edt_plan* p, const zd* g64, double b_max, double* gram, double* trace,
@@ -237,28 +291,41 @@ hipError_t launch_line_aperture_gram(const edt_plan* p, const zd* g64, double b_
     if (P == 0) return hipSuccess;
     const int64_t chunk = line_chunk(p);
     const int Nx = p->n_mid, Ny = p->n_line, nz = p->nz;
-    zd* Rh = reinterpret_cast<zd*>(work);
-    zd* K = reinterpret_cast<zd*>(work + line_aperture_work_bytes(p) / 2);
+    zd* K = reinterpret_cast<zd*>(work);
     int lo = 0, nW = 0;
     aperture_offsets(p, b_max, &lo, &nW);
-    const int bpp = (nW * nz + 255) / 256;
+    const bool p2 = (Nx & (Nx - 1)) == 0;
+    const int nw = p2 ? Nx / 2 : Nx;
+    int logn = 0;
+    while ((1 << logn) < Nx) ++logn;
+    // depths per block: 4 adjacent ones when they fit (contiguous stores)
+    int L = 1;
+    for (int c : {4, 2})
+        if (nz % c == 0 && size_t(c * lds_stride(Nx) + nw) * sizeof(zd) <= kLineApLds) {
+            L = c;
+            break;
+        }
+    const size_t lds = size_t(L * lds_stride(Nx) + nw) * sizeof(zd);
+    if (lds > kLineApLds) return hipErrorInvalidValue;
     const double Ly = double(Ny) * p->d_line;
     for (int64_t p0 = 0; p0 < P; p0 += chunk) {
         const int64_t np = std::min<int64_t>(chunk, P - p0);
+        const unsigned blocks = unsigned(np * (nz / L));
         for (int f = 0; f < p->n_freq; ++f) {
             const double wr = kTwoPiD * p->freq[size_t(f)], wi = p->eps;
             const zd W{p->dz * (wr * wr - wi * wi) / Ly, p->dz * (2.0 * wr * wi) / Ly};
-            hipLaunchKernelGGL(line_rows_kernel<true>, dim3(unsigned(np)), dim3(256), 0, st, g64,
-                               dptr<const int32_t>(p, p->lay.keys), dptr<const uint64_t>(p, p->lay.lmask),
-                               dptr<const int64_t>(p, p->lay.lfr), dptr<const int32_t>(p, p->lay.pair_u), f,
-                               p->n_freq, p->n_cls, Nx, Ny, nz, Nx, W, p0, Rh);
+            if (p2)
+                hipLaunchKernelGGL(line_ap_rows_kernel<true>, dim3(blocks), dim3(256), lds, st, g64,
+                                   dptr<const int32_t>(p, p->lay.keys), dptr<const uint64_t>(p, p->lay.lmask),
+                                   dptr<const int64_t>(p, p->lay.lfr), dptr<const int32_t>(p, p->lay.pair_u), f,
+                                   p->n_freq, p->n_cls, Nx, logn, Ny, nz, L, W, p0, lo, nW, K);
+            else
+                hipLaunchKernelGGL(line_ap_rows_kernel<false>, dim3(blocks), dim3(256), lds, st, g64,
+                                   dptr<const int32_t>(p, p->lay.keys), dptr<const uint64_t>(p, p->lay.lmask),
+                                   dptr<const int64_t>(p, p->lay.lfr), dptr<const int32_t>(p, p->lay.pair_u), f,
+                                   p->n_freq, p->n_cls, Nx, logn, Ny, nz, L, W, p0, lo, nW, K);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
-            if ((e = launch_lines(Rh, Nx, np, Lines{int64_t(Nx) * nz, 1, nz, nz}, 1.0, 1.0, st)) != hipSuccess)
-                return e;
-            hipLaunchKernelGGL(line_kept_kernel, dim3(unsigned(np * bpp)), dim3(256), 0, st, Rh, Nx, nz, lo, nW, bpp,
-                               K);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
             if ((e = launch_rows_gram(K, nz, nW, 1.0 / double(Nx), f == 0, gram + size_t(p0) * nz * nz, np, st)) !=
                 hipSuccess)
                 return e;
