@@ -8,6 +8,10 @@ over z, and V~(k_x, k_z) is kept only inside the disk |k| <= 2.2 w_max / c0
 model is the pair's k_m, so at one pair the kept vertical wavenumbers are
 those with k_z^2 + |k_m|^2 <= K^2.
 
+On the survey of parallel lines (Section 2.2) the subproblem is a pair
+(k_m, k_y), the model's horizontal wavenumber is (k_m, k_y), and the disk is
+taken in (|(k_m, k_y)|, k_z).
+
 Readings: the transform over z is the discrete one on the inversion's depth
 grid (nz depths at spacing dz, k_z,j = 2 pi j / (nz dz) for the fftfreq
 indices j), and c0, undefined for a layered reference, is the velocity of the
@@ -40,9 +44,16 @@ def _signed(u, N):
 
 
 def pair_km2(s, u):
-    """|k_m|^2 of the k_m index u (fftfreq order; 3D: u = ux N + uy)."""
+    """|k_m|^2 of the k_m index u (fftfreq order; 3D: u = ux N + uy; parallel
+    lines: u = ux N_y + c, |(k_m, k_y)|^2)."""
     N = s.n_mid
     dk = TWO_PI / (N * s.d_mid)
+    if getattr(s, "n_line", 0):
+        Ny = s.n_line
+        ux, c = divmod(u, Ny)
+        kx = _signed(ux, N) * dk
+        ky = _signed(c, Ny) * (TWO_PI / (Ny * s.d_line))
+        return kx * kx + ky * ky
     if getattr(s, "dim", 2) == 3:
         ux, uy = divmod(u, N)
         kx = _signed(ux, N) * dk
@@ -83,7 +94,17 @@ def kz_basis(nz, dz, km2, K):
 def kz_tsvd_solve(s, pl, data, tabs, tol_rel, K, pairs=None):
     """Truncated-SVD solution restricted to the disk of radius K:
     V~ (n_km, nz) complex128 in fftfreq order and per-pair details (x, info,
-    the eigenvalues of F^T G F, sigma^2 and the number of kept columns)."""
+    the eigenvalues of F^T G F, sigma^2 and the number of kept columns).
+    Survey of parallel lines: `tabs` is the table of
+    oracle.lines3d.line_tables and `pl` its plan."""
+    if getattr(s, "n_line", 0):
+        from .lines3d import line_row_values
+
+        def rows_of(p):
+            return line_row_values(s, p, tabs)
+    else:
+        def rows_of(p):
+            return row_values(s, p, tabs.lookup)
     pairs = pl.pairs if pairs is None else pairs
     nz = s.nz
     V = np.zeros((pl.n_km, nz), np.complex128)
@@ -95,7 +116,7 @@ def kz_tsvd_solve(s, pl, data, tabs, tol_rel, K, pairs=None):
         if p.n_rows:
             inf = INFO_OK
             if F.shape[1]:
-                A = row_values(s, p, tabs.lookup)
+                A = rows_of(p)
                 G, c, _ = normal_equations(A, d0, d1)
                 y, w, tau2 = tsvd_gram(F.T @ G @ F, c @ F, tol_rel)
                 x = y @ F.T

@@ -13,11 +13,13 @@
 import numpy as np
 import pytest
 
-from edt_inputs import make_custom, vhat
+from edt_inputs import make_custom, make_lines, vhat
 from oracle.kz import kz_basis, kz_disk_radius, kz_kept, kz_tsvd_solve, pair_km2
 from oracle.rows import plan, row_values
 from oracle.solve import gtables, forward, synth_data, normal_equations, INFO_EMPTY
-from oracle.tsvd import tsvd_solve
+from oracle.tsvd import tsvd_gram, tsvd_solve
+from oracle.lines3d import forward_lines, line_row_values, line_tables, plan_lines
+from oracle.solve import add_noise, noise_scale
 
 
 def _mask(nz, kept):
@@ -131,3 +133,65 @@ def test_band_limited_model_is_recovered():
     V, info = kz_tsvd_solve(s, pl, clean, tabs, 0.0, K)
     assert np.max(np.abs(V - vb)) <= 1e-7 * np.max(np.abs(vb))
     assert all(i["info"] != INFO_EMPTY for i in info)
+
+
+def test_km2_of_the_line_survey_follows_both_fftfreq_orders():
+    """u = ux N_y + c: |(k_m, k_y)|^2 with its own spacing on each axis
+    (N_x != N_y, so a transposed index fails)."""
+    Nx, Ny, dx, dy = 10, 6, 25.0, 40.0
+    s = make_lines(Nx=Nx, Ny=Ny, dx=dx, dy=dy, nz=5, freqs=(3.0,), vel=(2000.0,), model="zero")
+    fx, fy = np.fft.fftfreq(Nx) * Nx, np.fft.fftfreq(Ny) * Ny
+    for u in range(Nx * Ny):
+        ux, c = divmod(u, Ny)
+        want = (fx[ux] * 2 * np.pi / (Nx * dx)) ** 2 + (fy[c] * 2 * np.pi / (Ny * dy)) ** 2
+        assert np.isclose(pair_km2(s, u), want, rtol=1e-14)
+
+
+def _line_case():
+    s = make_lines(Nx=12, Ny=5, dx=25.0, dy=40.0, nz=16, dz=10.0, freqs=(6.0, 14.0, 23.0), vel=(1900.0, 2700.0),
+                   zif=(40.0,), kappa=1.0, noise_rel=0.05, seed=8)
+    pl = plan_lines(s)
+    tab = line_tables(s)
+    clean = forward_lines(s, pl, vhat(s), tab)
+    return s, pl, tab, add_noise(s, pl, clean, noise_scale(s, pl, clean))
+
+
+def test_line_disk_holding_every_kz_is_the_plain_tsvd():
+    s, pl, tab, data = _line_case()
+    Vr, _ = kz_tsvd_solve(s, pl, data, tab, 1e-2, K=1e3)
+    V = np.zeros_like(Vr)
+    for p, (d0, d1) in zip(pl.pairs, data):
+        if not p.n_rows:
+            continue
+        G, c, _ = normal_equations(line_row_values(s, p, tab), d0, d1)
+        x, _, _ = tsvd_gram(G, c, 1e-2)
+        if p.self_conjugate:
+            x[1] = 0.0
+        V[p.u] = x[0] + 1j * x[1]
+        if not p.self_conjugate:
+            V[p.u_neg] = x[0] - 1j * x[1]
+    assert np.max(np.abs(Vr - V)) <= 1e-9 * np.max(np.abs(V))
+
+
+def test_line_restricted_solution_lives_in_the_disk():
+    s, pl, tab, data = _line_case()
+    K = 0.6 * kz_disk_radius(s)
+    V, info = kz_tsvd_solve(s, pl, data, tab, 0.0, K)
+    nz = s.nz
+    n_out = n_part = 0
+    for p, (d0, d1), inf in zip(pl.pairs, data, info):
+        kept = kz_kept(nz, s.dz, pair_km2(s, p.u), K)
+        m = _mask(nz, kept)
+        x = inf["x"]
+        if not kept:
+            n_out += 1
+            assert not np.any(x)
+            continue
+        n_part += 0 < len(kept) < nz // 2 + 1
+        assert np.max(np.abs(np.fft.fft(x, axis=1)[:, ~m]), initial=0.0) <= 1e-10 * max(np.max(np.abs(x)), 1e-300)
+        if p.n_rows == 0:
+            continue
+        G, c, _ = normal_equations(line_row_values(s, p, tab), d0, d1)
+        r = np.fft.fft(x @ G - c, axis=1)[:, m]
+        assert np.max(np.abs(r)) <= 1e-8 * np.max(np.abs(np.fft.fft(c, axis=1)[:, m]))
+    assert n_out > 0 and n_part > 0
