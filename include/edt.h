@@ -102,7 +102,7 @@ typedef enum {
  *        |k| are within the cut below, a row iff a term is.  This survey is
  *        assembled in FP64 and solved without refinement (edt_solve with
  *        refine = 0, or edt_tsvd), and edt_aperture_gram gives its finite-aperture
- *        Gram; edt_adjoint and edt_kz_restrict refuse it.
+ *        Gram, and edt_kz_restrict its k_z restriction; edt_adjoint refuses it.
  * Frequencies freq_hz[n_freq] are used simultaneously (Section 3.1); eps is the
  * imaginary part of w (Section 2.1; 0.15 1/s in Section 3.1).  Depths are
  * z_i = z0 + i*dz, i < nz.  A row is kept iff |k_r| and |k_s| are both
@@ -414,7 +414,9 @@ edt_status edt_kz_disk_radius(const edt_plan* plan, double factor, double* k_dis
  * Q G Q and Q c, in place; edt_tsvd on the result gives the truncated-SVD
  * solution restricted to the disk (Q G Q vanishes off the kept modes, whose
  * singular values are then zero and dropped; use tol_rel > 0).  Apply it
- * before edt_tsvd only: edt_solve's refinement works from the rows.
+ * before edt_tsvd only: edt_solve's refinement works from the rows.  On the
+ * survey of parallel lines the model's horizontal wavenumber is (k_m, k_y),
+ * and |k_m|^2 above reads |k_m|^2 + |k_y|^2.
  * gram: [P][nz][nz] lower triangles from edt_assemble (EDT_FP64); rhs:
  * [P][2][nz]; both device, overwritten.  n_keep: device int32 [P] or NULL,
  * the number of kept real modes per pair (0 for a pair with |k_m| > k_disk,

@@ -549,10 +549,6 @@ edt_status edt_kz_restrict(const edt_plan* p, double k_disk, double* gram, doubl
         set_error("k_disk must be finite and >= 0");
         return EDT_EINVAL;
     }
-    if (p->n_line) {
-        set_error("the k_z restriction does not cover the survey of parallel lines");
-        return EDT_EINVAL;
-    }
     if (p->n_pairs == 0) return EDT_OK;   // an empty pair range
     if (!gram || !rhs || !tsvd_work) {
         set_error("missing argument");

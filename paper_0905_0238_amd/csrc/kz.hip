@@ -25,13 +25,21 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // Largest kept index j in [0, nz/2] of the pair of k_m index u, or -1.  The
 // comparison is evaluated exactly as written (no fused multiply-adds), so the
-// kept set is a plain function of the IEEE products and sums.
-__device__ int kz_jmax(int u, int dim, int n_mid, double d_mid, int nz, double dz, double K) {
+// kept set is a plain function of the IEEE products and sums.  On the survey
+// of parallel lines u = ux n_line + c and the horizontal wavenumber is
+// (k_m, k_y).
+__device__ int kz_jmax(int u, int dim, int n_mid, double d_mid, int n_line, double d_line, int nz, double dz,
+                       double K) {
 #pragma clang fp contract(off)
     const double dk = kTwoPiD / (double(n_mid) * d_mid);
     auto sgn = [&](int v) { return v < (n_mid + 1) / 2 ? v : v - n_mid; };
     double km2;
-    if (dim == 3) {
+    if (n_line > 0) {
+        const int c = u % n_line;
+        const double kx = double(sgn(u / n_line)) * dk;
+        const double ky = double(c < (n_line + 1) / 2 ? c : c - n_line) * (kTwoPiD / (double(n_line) * d_line));
+        km2 = kx * kx + ky * ky;
+    } else if (dim == 3) {
         const double kx = double(sgn(u / n_mid)) * dk, ky = double(sgn(u % n_mid)) * dk;
         km2 = kx * kx + ky * ky;
     } else {
@@ -50,10 +58,10 @@ __device__ int kz_jmax(int u, int dim, int n_mid, double d_mid, int nz, double d
 
 // Per pair: the circulant row q (nz values) and the number of kept modes.
 __global__ __launch_bounds__(256) void kz_q_kernel(const int32_t* __restrict__ pair_u, int dim, int n_mid,
-                                                   double d_mid, int nz, double dz, double K,
-                                                   double* __restrict__ q, int32_t* __restrict__ n_keep) {
+                                                   double d_mid, int n_line, double d_line, int nz, double dz,
+                                                   double K, double* __restrict__ q, int32_t* __restrict__ n_keep) {
     const int p = blockIdx.x, tid = threadIdx.x;
-    const int jmax = kz_jmax(pair_u[2 * p], dim, n_mid, d_mid, nz, dz, K);
+    const int jmax = kz_jmax(pair_u[2 * p], dim, n_mid, d_mid, n_line, d_line, nz, dz, K);
     const int jc = jmax < (nz - 1) / 2 ? jmax : (nz - 1) / 2;   // cos/sin pairs j = 1..jc
     const bool nyq = (nz % 2 == 0) && jmax == nz / 2;
     for (int d = tid; d < nz; d += 256) {
@@ -213,7 +221,7 @@ hipError_t launch_kz_restrict(const edt_plan* p, double K, double* gram, double*
     double* q = reinterpret_cast<double*>(tw + l.x0);
     double* T = reinterpret_cast<double*>(tw + l.y);
     hipLaunchKernelGGL(kz_q_kernel, dim3(P), dim3(256), 0, st, dptr<const int32_t>(p, p->lay.pair_u), p->dim,
-                       p->n_mid, p->d_mid, nz, p->dz, K, q, n_keep);
+                       p->n_mid, p->d_mid, p->n_line, p->d_line, nz, p->dz, K, q, n_keep);
     hipLaunchKernelGGL(kz_gemm_kernel<0>, dim3(xcd_pair_grid(P, nt * nt)), dim3(256), 0, st, gram, q, T, nz, nt,
                        int(P));
     hipLaunchKernelGGL(kz_gemm_kernel<1>, dim3(xcd_pair_grid(P, nt * (nt + 1) / 2)), dim3(256), 0, st, T, q, gram,

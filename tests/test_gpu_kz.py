@@ -18,16 +18,21 @@ on the restricted system, against the oracle (oracle.kz), pair by pair.
   are left out and counted;
 * a disk that holds every k_z leaves the system unchanged, a disk of radius 0
   keeps only the constant mode of k_m = 0, and at the full size of the 2D
-  N = 512 survey a seeded sample of pairs matches the oracle.
+  N = 512 survey a seeded sample of pairs matches the oracle;
+* the survey of parallel lines, whose disk is in (|(k_m, k_y)|, k_z): the kept
+  counts and the restricted truncated-SVD solution against the oracle, on an
+  odd and an even grid.
 """
 import numpy as np
 import pytest
 
-from edt_inputs import make_config, make_custom, vhat
+from edt_inputs import make_config, make_custom, make_lines, vhat
 from oracle.kz import kz_basis, kz_disk_radius, kz_tsvd_solve, pair_km2
 from oracle.rows import plan as oracle_plan, row_values
 from oracle.solve import gtables, forward, noise_scale, add_noise, normal_equations
 from oracle.tsvd import tsvd_solve
+from oracle.lines3d import forward_lines, line_tables, plan_lines
+from oracle.solve import pack
 from tests._cases import oracle_case, layered_small
 
 torch = pytest.importorskip("torch")
@@ -247,3 +252,39 @@ def test_sampled_pairs_at_full_size():
 
     _check_solution("cfg2-sample", s, _Sub, v.cpu().numpy(), info.cpu().numpy()[pick], Vo, info_o,
                     n_keep[pick], tol)
+
+
+_LINE_CASES = {
+    "lines-odd": lambda: make_lines(Nx=15, Ny=7, dx=20.0, dy=35.0, nz=33, dz=12.0, freqs=(9.0, 14.0, 22.0, 31.0),
+                                    vel=(2000.0, 2600.0, 1900.0), zif=(40.0, 140.0), kappa=1.0, noise_rel=0.05,
+                                    seed=2),
+    "lines-even": lambda: make_lines(Nx=16, Ny=8, dx=25.0, dy=40.0, nz=40, dz=10.0, freqs=(6.0, 11.0, 17.0),
+                                     vel=(1800.0, 2600.0), zif=(45.0,), kappa=1.0, noise_rel=0.05, seed=1),
+}
+
+
+@pytest.mark.parametrize("scale", [1.0, 0.5])
+@pytest.mark.parametrize("name", list(_LINE_CASES))
+def test_restricted_tsvd_on_the_line_survey(name, scale):
+    s = _LINE_CASES[name]()
+    pl = plan_lines(s)
+    tab = line_tables(s)
+    clean = forward_lines(s, pl, vhat(s), tab)
+    data = add_noise(s, pl, clean, noise_scale(s, pl, clean))
+    K = _radius(s, scale)
+    tol = 1e-2
+    Vo, info_o = kz_tsvd_solve(s, pl, data, tab, tol, K)
+    p = E.Plan(s)
+    vel = torch.tensor(np.asarray(s.vel, np.float64), device="cuda")
+    g64, _ = p.green(vel, want32=False)
+    d = torch.from_numpy(pack(pl, data)[0]).cuda()
+    gram, rhs, _ = p.assemble(g64, None, d, "fp64")
+    work = p.tsvd_work()
+    n_keep = p.kz_restrict(gram, rhs, K, work, n_keep=True)
+    x, v, info, iters = p.tsvd(gram, rhs, tol, max_iter=150, tsvd_work=work)
+    torch.cuda.synchronize()
+    nk = n_keep.cpu().numpy()
+    assert [int(k) for k in nk] == [io["n_keep"] for io in info_o]
+    if scale < 1.0:
+        assert any(0 < k < s.nz for k in nk) and any(k == 0 for k in nk)
+    _check_solution(name, s, pl, v.cpu().numpy(), info.cpu().numpy(), Vo, info_o, nk, tol)

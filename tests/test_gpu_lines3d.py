@@ -202,8 +202,6 @@ def test_line_survey_refusals():
     gram, rhs, trace = p.assemble(g64, None, d, "fp64")
     with pytest.raises(RuntimeError, match="without refinement"):
         p.solve(g64, d, gram, rhs, trace, s.lambda_rel, refine=True)
-    with pytest.raises(RuntimeError, match="parallel lines"):
-        p.kz_restrict(gram, rhs, 1.0, p.tsvd_work())
 
 
 def test_sampled_pairs_of_a_larger_line_survey():
