@@ -8,10 +8,9 @@
 // frequency are formed into HBM (a chunk of pairs at a time, as many slots per
 // pair as the chunk's largest row count, zero past a pair's rows) and the
 // finite aperture's FP64 MFMA product accumulates Re(A^H A) over the
-// frequencies; the right-hand
-// sides Re(A^H b+-) are accumulated from the same rows, and the trace is the
-// Gram's diagonal.  The rows' terms (which q are kept) come from the planner's
-// per-row masks, so no cut is decided here.
+// frequencies; the right-hand sides Re(A^H b+-) are accumulated from the same
+// rows, and the trace is the Gram's diagonal.  The rows' terms (which q are
+// kept) come from the planner's per-row masks, so no cut is decided here.
 
 #include "dev_common.h"
 #include "lines.h"
