@@ -102,7 +102,7 @@ typedef enum {
  *        |k| are within the cut below, a row iff a term is.  This survey is
  *        assembled in FP64 and solved without refinement (edt_solve with
  *        refine = 0, or edt_tsvd), and edt_aperture_gram gives its finite-aperture
- *        Gram, and edt_kz_restrict its k_z restriction; edt_adjoint refuses it.
+ *        Gram, edt_kz_restrict its k_z restriction and edt_adjoint its gradient.
  * Frequencies freq_hz[n_freq] are used simultaneously (Section 3.1); eps is the
  * imaginary part of w (Section 2.1; 0.15 1/s in Section 3.1).  Depths are
  * z_i = z0 + i*dz, i < nz.  A row is kept iff |k_r| and |k_s| are both
@@ -531,7 +531,10 @@ edt_status edt_forward(const edt_plan* plan, const edt_c128* g64, const edt_c128
  *               the plan's data type, like d_rows)
  *   grad_lambda[0] = dL/dlambda_rel
  *   grad_vel[l] = dL/dc_l, l < n_layers
- * The evanescent-cut mask is held fixed.
+ * The evanescent-cut mask is held fixed.  On the survey of parallel lines a
+ * row's gradient flows to both factors of every kept term of the row; those
+ * table gradients are added atomically (their summation order varies from
+ * call to call, at the rounding level), the other surveys' in a fixed order.
  */
 edt_status edt_adjoint(const edt_plan* plan, const double* vel_dev, const edt_c128* g64,
                        const void* d_rows, const double* chol, const double* trace,

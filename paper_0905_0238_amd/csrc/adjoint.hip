@@ -154,7 +154,7 @@ __global__ __launch_bounds__(256) void adj_table_kernel(
     const int32_t* __restrict__ tab_off, const int32_t* __restrict__ tab_ent,
     const zd* __restrict__ g64, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ dl, const zd* __restrict__ rowsc, zd* __restrict__ gbar,
-    double* __restrict__ vel_part) {
+    const zd* __restrict__ gbar_in, double* __restrict__ vel_part) {
     __shared__ zd s_k[4][kMaxLayers], s_R[4][kMaxLayers], s_rho[4][kMaxLayers], s_b[4][kMaxLayers];
     __shared__ zd s_c[4][4][ZPL * 64];   // per-depth adjoint contributions: k, R, b, H
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -171,7 +171,15 @@ __global__ __launch_bounds__(256) void adj_table_kernel(
     zd gb[ZPL];
 #pragma unroll
     for (int q = 0; q < ZPL; ++q) gb[q] = zd{0.0, 0.0};
-    if (active) {
+    if (active && gbar_in) {
+        // gathered beforehand (the survey of parallel lines)
+        const int64_t e = int64_t(f) * ncls + c;
+#pragma unroll
+        for (int q = 0; q < ZPL; ++q) {
+            const int z = lane + 64 * q;
+            if (z < nz) gb[q] = gbar_in[e * nz + z];
+        }
+    } else if (active) {
         const int64_t e = int64_t(f) * ncls + c;
         const zd* gself = g64 + e * nz;
         zd gs[ZPL];
@@ -417,15 +425,34 @@ __global__ __launch_bounds__(256) void ordered_sum_kernel(const double* __restri
 // ------------------------------------------------------------- launcher ---
 template <int ZPL>
 static void launch_table(const edt_plan* p, const double* vel, const zd* g64, const double* x,
-                         const double* y, const double* dl, const zd* rowsc, zd* gbar, double* vpart,
-                         double lambda_rel, hipStream_t st) {
+                         const double* y, const double* dl, const zd* rowsc, zd* gbar, const zd* gbar_in,
+                         double* vpart, double lambda_rel, hipStream_t st) {
     const int64_t waves = int64_t(p->n_freq) * p->n_cls;
     hipLaunchKernelGGL(adj_table_kernel<ZPL>, dim3(unsigned((waves + 3) / 4)), dim3(256), 0, st,
                        dptr<const double>(p, p->lay.freq), dptr<const double>(p, p->lay.zif),
                        dptr<const double>(p, p->lay.cls_k), vel, p->n_freq, p->n_cls, p->nz, p->n_layers,
                        p->eps, p->z0, p->dz, lambda_rel, dptr<const uint32_t>(p, p->lay.urows),
                        dptr<const int32_t>(p, p->lay.urow_pair), dptr<const int32_t>(p, p->lay.tab_off),
-                       dptr<const int32_t>(p, p->lay.tab_ent), g64, x, y, dl, rowsc, gbar, vpart);
+                       dptr<const int32_t>(p, p->lay.tab_ent), g64, x, y, dl, rowsc, gbar, gbar_in, vpart);
+}
+
+// Table adjoint and the layer sums: grad_vel from the table gradient (gbar_in
+// given) or from the rows' scalars (gathered per entry, gbar written).
+static hipError_t launch_vel(const edt_plan* p, const double* vel, const zd* g64, const double* x,
+                             const double* y, const double* dl, const zd* rowsc, zd* gbar, const zd* gbar_in,
+                             double* vpart, double lambda_rel, double* grad_vel, hipStream_t st) {
+    switch ((p->nz + 63) / 64) {
+        case 1: launch_table<1>(p, vel, g64, x, y, dl, rowsc, gbar, gbar_in, vpart, lambda_rel, st); break;
+        case 2: launch_table<2>(p, vel, g64, x, y, dl, rowsc, gbar, gbar_in, vpart, lambda_rel, st); break;
+        case 3: launch_table<3>(p, vel, g64, x, y, dl, rowsc, gbar, gbar_in, vpart, lambda_rel, st); break;
+        case 4: launch_table<4>(p, vel, g64, x, y, dl, rowsc, gbar, gbar_in, vpart, lambda_rel, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(ordered_sum_kernel, dim3(unsigned(p->n_layers)), dim3(256), 0, st, vpart,
+                       int64_t(p->n_freq) * p->n_cls, p->n_layers, grad_vel);
+    return hipGetLastError();
 }
 
 hipError_t launch_adjoint(const edt_plan* p, const double* vel, const zd* g64, const void* d_rows,
@@ -463,22 +490,161 @@ hipError_t launch_adjoint(const edt_plan* p, const double* vel, const zd* g64, c
                                ub, x, y, rowsc, static_cast<zd*>(grad_d));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (grad_vel) {
-        switch ((p->nz + 63) / 64) {
-            case 1: launch_table<1>(p, vel, g64, x, y, dl, rowsc, gbar, vpart, lambda_rel, st); break;
-            case 2: launch_table<2>(p, vel, g64, x, y, dl, rowsc, gbar, vpart, lambda_rel, st); break;
-            case 3: launch_table<3>(p, vel, g64, x, y, dl, rowsc, gbar, vpart, lambda_rel, st); break;
-            case 4: launch_table<4>(p, vel, g64, x, y, dl, rowsc, gbar, vpart, lambda_rel, st); break;
-            default: return hipErrorInvalidValue;
-        }
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(ordered_sum_kernel, dim3(unsigned(p->n_layers)), dim3(256), 0, st, vpart,
-                           int64_t(p->n_freq) * p->n_cls, p->n_layers, grad_vel);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
+    if (grad_vel &&
+        (e = launch_vel(p, vel, g64, x, y, dl, rowsc, gbar, nullptr, vpart, lambda_rel, grad_vel, st)) !=
+            hipSuccess)
+        return e;
     if (grad_lambda) {
         hipLaunchKernelGGL(ordered_sum_kernel, dim3(1), dim3(256), 0, st, glam_part, p->n_pairs, 1,
                            grad_lambda);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// ------------------------------------------- survey of parallel lines ---
+// A line row is A = (w^2 dz / L_y) sum_q g(k_a, k_q) g(k_b, k_{q-c}) over its
+// kept terms, formed per run of pairs and frequency into Rh (nr slots per
+// pair).  One block per pair of the run, a wave per row: A x+-, A y+-, e+- =
+// b+- - A x+-, the data gradient, and Abar = y+ e+ + y- e- - x+ A y+ - x- A y-
+// + kappa A, which flows to both factors of every term of the row:
+// gbar(k_a, k_q) += conj(W g(k_b, k_{q-c})) Abar and symmetrically (atomic
+// adds: a table entry takes terms from rows of many pairs).
+__device__ __forceinline__ int sidx(int n, int N) { return n < (N + 1) / 2 ? n : n - N; }
+
+template <class D>
+__global__ __launch_bounds__(256) void line_adj_kernel(
+    const zd* __restrict__ Rh, const zd* __restrict__ g64, const int32_t* __restrict__ keys,
+    const uint64_t* __restrict__ lmask, const int64_t* __restrict__ lfr, const int32_t* __restrict__ pair_u,
+    const D* __restrict__ d_rows, const double* __restrict__ x, const double* __restrict__ y,
+    const double* __restrict__ dl, int f, int n_freq, int n_cls, int Nx, int Ny, int nz, int nr, zd W,
+    double lambda_rel, int64_t p0, D* __restrict__ grad_d, zd* __restrict__ gbar) {
+    const int64_t p = p0 + blockIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t r0 = lfr[p * (n_freq + 1) + f], n = lfr[p * (n_freq + 1) + f + 1] - r0;
+    const zd* R = Rh + size_t(blockIdx.x) * nr * nz;
+    const double* xp = x + size_t(p) * 2 * nz;
+    const double* yp = y + size_t(p) * 2 * nz;
+    const double kap = dl[p] * 2.0 * lambda_rel / double(nz);
+    const int ny2 = Ny / 2 + 1, qc = sidx(pair_u[2 * p] % Ny, Ny);
+    const zd* gf = g64 + size_t(f) * n_cls * nz;
+    zd* gb = gbar ? gbar + size_t(f) * n_cls * nz : nullptr;
+    for (int64_t i = wv; i < n; i += 4) {
+        const int64_t r = r0 + i;
+        const zd* A = R + size_t(i) * nz;
+        double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int z = lane; z < nz; z += 64) {
+            const zd a = A[z];
+            v[0] += a.x * xp[z];
+            v[1] += a.y * xp[z];
+            v[2] += a.x * xp[nz + z];
+            v[3] += a.y * xp[nz + z];
+            v[4] += a.x * yp[z];
+            v[5] += a.y * yp[z];
+            v[6] += a.x * yp[nz + z];
+            v[7] += a.y * yp[nz + z];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = wave_sum(v[k]);
+        const zd axp{v[0], v[1]}, axm{v[2], v[3]}, ayp{v[4], v[5]}, aym{v[6], v[7]};
+        const zd d0 = load_datum(d_rows, 2 * r), d1 = load_datum(d_rows, 2 * r + 1);
+        const zd df = d0 - d1;
+        const zd ep = 0.5 * (d0 + d1) - axp, em = zd{0.5 * df.y, -0.5 * df.x} - axm;
+        if (grad_d && lane == 0) {
+            const zd ih = zd{-0.5 * aym.y, 0.5 * aym.x};   // (i/2) A y-
+            store_datum(grad_d, 2 * r, 0.5 * ayp + ih);
+            store_datum(grad_d, 2 * r + 1, 0.5 * ayp - ih);
+        }
+        if (!gb) continue;
+        const int ia = abs(sidx(keys[2 * r], Nx)), ib = abs(sidx(keys[2 * r + 1], Nx));
+        const uint64_t mask = lmask[r];
+        for (int z = lane; z < nz; z += 64) {
+            zd Ab = yp[z] * ep + yp[nz + z] * em;
+            Ab = Ab - xp[z] * ayp - xp[nz + z] * aym;
+            Ab = Ab + kap * A[z];
+            uint64_t m = mask;
+            while (m) {
+                const int bit = __builtin_ctzll(m);
+                m &= m - 1;
+                const int q = bit - Ny / 2;
+                int pq = (q - qc) % Ny;
+                pq = sidx(pq < 0 ? pq + Ny : pq, Ny);
+                const size_t ca = size_t(ia * ny2 + abs(q)) * nz + z, cb = size_t(ib * ny2 + abs(pq)) * nz + z;
+                const zd ta = zconj(W * gf[cb]) * Ab, tb = zconj(W * gf[ca]) * Ab;
+                atomicAdd(&gb[ca].x, ta.x);
+                atomicAdd(&gb[ca].y, ta.y);
+                atomicAdd(&gb[cb].x, tb.x);
+                atomicAdd(&gb[cb].y, tb.y);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void zero_kernel(double* __restrict__ a, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) a[i] = 0.0;
+}
+
+int line_row_slots(const edt_plan* p, int f, int64_t p0, int64_t np);
+zd line_row_weight(const edt_plan* p, int f);
+hipError_t launch_line_rows(const edt_plan* p, const zd* g64, int f, int64_t p0, int64_t np, int nr, zd* Rh,
+                            hipStream_t st);
+
+hipError_t launch_line_adjoint(const edt_plan* p, const double* vel, const zd* g64, const void* d_rows,
+                               const double* chol, const double* trace, const double* x, double lambda_rel,
+                               const zd* grad_v, void* grad_d, double* grad_lambda, double* grad_vel,
+                               unsigned char* work, hipStream_t st) {
+    const WorkLayout wl = work_layout(p);
+    double* y = reinterpret_cast<double*>(work + wl.adj_y);
+    double* dl = reinterpret_cast<double*>(work + wl.adj_dl);
+    double* vpart = reinterpret_cast<double*>(work + wl.adj_vel);
+    double* glam_part = reinterpret_cast<double*>(work + wl.aux);
+    zd* gbar = reinterpret_cast<zd*>(work + wl.gbar);
+    zd* Rh = reinterpret_cast<zd*>(work + wl.lrows);
+    const int64_t P = p->n_pairs;
+    if (P == 0) return hipSuccess;
+    hipError_t e;
+    hipLaunchKernelGGL(adj_pair_kernel, dim3(unsigned(P)), dim3(256), adjoint_lds_bytes(p->nz), st, chol, x, trace,
+                       dptr<const int64_t>(p, p->lay.row_off), dptr<const int32_t>(p, p->lay.pair_u), p->nz, grad_v,
+                       y, dl, glam_part);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (grad_vel) {
+        const int64_t nd = int64_t(p->n_freq) * p->n_cls * p->nz * 2;
+        hipLaunchKernelGGL(zero_kernel, dim3(unsigned(std::min<int64_t>((nd + 255) / 256, 65536))), dim3(256), 0,
+                           st, reinterpret_cast<double*>(gbar), nd);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (grad_d || grad_vel) {
+        const int64_t chunk = line_chunk(p);
+        for (int64_t p0 = 0; p0 < P; p0 += chunk) {
+            const int64_t np = std::min<int64_t>(chunk, P - p0);
+            for (int f = 0; f < p->n_freq; ++f) {
+                const int nr = line_row_slots(p, f, p0, np);
+                if ((e = launch_line_rows(p, g64, f, p0, np, nr, Rh, st)) != hipSuccess) return e;
+                const zd W = line_row_weight(p, f);
+                if (p->data_c64)
+                    hipLaunchKernelGGL(line_adj_kernel<float2>, dim3(unsigned(np)), dim3(256), 0, st, Rh, g64,
+                                       dptr<const int32_t>(p, p->lay.keys), dptr<const uint64_t>(p, p->lay.lmask),
+                                       dptr<const int64_t>(p, p->lay.lfr), dptr<const int32_t>(p, p->lay.pair_u),
+                                       static_cast<const float2*>(d_rows), x, y, dl, f, p->n_freq, p->n_cls,
+                                       p->n_mid, p->n_line, p->nz, nr, W, lambda_rel, p0,
+                                       static_cast<float2*>(grad_d), grad_vel ? gbar : nullptr);
+                else
+                    hipLaunchKernelGGL(line_adj_kernel<zd>, dim3(unsigned(np)), dim3(256), 0, st, Rh, g64,
+                                       dptr<const int32_t>(p, p->lay.keys), dptr<const uint64_t>(p, p->lay.lmask),
+                                       dptr<const int64_t>(p, p->lay.lfr), dptr<const int32_t>(p, p->lay.pair_u),
+                                       static_cast<const zd*>(d_rows), x, y, dl, f, p->n_freq, p->n_cls,
+                                       p->n_mid, p->n_line, p->nz, nr, W, lambda_rel, p0, static_cast<zd*>(grad_d),
+                                       grad_vel ? gbar : nullptr);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+            }
+        }
+    }
+    if (grad_vel &&
+        (e = launch_vel(p, vel, g64, x, y, dl, nullptr, nullptr, gbar, vpart, lambda_rel, grad_vel, st)) !=
+            hipSuccess)
+        return e;
+    if (grad_lambda) {
+        hipLaunchKernelGGL(ordered_sum_kernel, dim3(1), dim3(256), 0, st, glam_part, P, 1, grad_lambda);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

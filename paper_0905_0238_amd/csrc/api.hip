@@ -37,6 +37,10 @@ hipError_t launch_pcg_update(const edt_plan* p, const double* gram, const double
 hipError_t launch_reset_counters(int32_t* c, int n, hipStream_t st);
 hipError_t launch_recombine(const edt_plan* p, const double* x, int refine, const int32_t* conv,
                             int32_t* info, zd* v, hipStream_t st);
+hipError_t launch_line_adjoint(const edt_plan* p, const double* vel, const zd* g64, const void* d_rows,
+                               const double* chol, const double* trace, const double* x, double lambda_rel,
+                               const zd* grad_v, void* grad_d, double* grad_lambda, double* grad_vel,
+                               unsigned char* work, hipStream_t st);
 hipError_t launch_adjoint(const edt_plan* p, const double* vel, const zd* g64, const void* d_rows,
                           const double* chol, const double* trace, const double* x, double lambda_rel,
                           const zd* grad_v, void* grad_d, double* grad_lambda, double* grad_vel,
@@ -692,15 +696,17 @@ edt_status edt_adjoint(const edt_plan* p, const double* vel_dev, const edt_c128*
         set_error("the adjoint supports nz <= 256");
         return EDT_EINVAL;
     }
-    if (p->n_line) {
-        set_error("the adjoint does not cover the survey of parallel lines");
-        return EDT_EINVAL;
-    }
-    EDT_TRY(launch_adjoint(p, vel_dev, reinterpret_cast<const zd*>(g64), d_rows,
-                           chol, trace, x, lambda_rel, reinterpret_cast<const zd*>(grad_v),
-                           grad_d, grad_lambda, grad_vel,
-                           static_cast<unsigned char*>(work), stream),
-            "adjoint");
+    if (p->n_line)
+        EDT_TRY(launch_line_adjoint(p, vel_dev, reinterpret_cast<const zd*>(g64), d_rows, chol, trace, x,
+                                    lambda_rel, reinterpret_cast<const zd*>(grad_v), grad_d, grad_lambda, grad_vel,
+                                    static_cast<unsigned char*>(work), stream),
+                "adjoint");
+    else
+        EDT_TRY(launch_adjoint(p, vel_dev, reinterpret_cast<const zd*>(g64), d_rows,
+                               chol, trace, x, lambda_rel, reinterpret_cast<const zd*>(grad_v),
+                               grad_d, grad_lambda, grad_vel,
+                               static_cast<unsigned char*>(work), stream),
+                "adjoint");
     return EDT_OK;
 }
 

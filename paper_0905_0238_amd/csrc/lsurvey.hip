@@ -143,6 +143,35 @@ hipError_t launch_rows_gram(const zd* R, int nz, int n_rows, double scale, int f
                             hipStream_t st);
 hipError_t launch_gram_trace(const double* gram, int nz, double* trace, int64_t P, hipStream_t st);
 
+// Row slots per pair for the run of pairs p0 .. p0 + np - 1 at frequency f:
+// the largest row count among them (at least one).
+int line_row_slots(const edt_plan* p, int f, int64_t p0, int64_t np) {
+    int64_t nr = 1;
+    for (int64_t q = p0; q < p0 + np; ++q) {
+        const int64_t* fr = p->lfr.data() + size_t(q) * size_t(p->n_freq + 1);
+        nr = std::max<int64_t>(nr, fr[f + 1] - fr[f]);
+    }
+    return int(nr);
+}
+
+// The row weight w^2 dz / L_y of frequency f.
+zd line_row_weight(const edt_plan* p, int f) {
+    const double Ly = double(p->n_line) * p->d_line;
+    const double wr = kTwoPiD * p->freq[size_t(f)], wi = p->eps;
+    return zd{p->dz * (wr * wr - wi * wi) / Ly, p->dz * (2.0 * wr * wi) / Ly};
+}
+
+// The rows of frequency f of the run of pairs p0 .. p0 + np - 1, compactly
+// (nr slots per pair), into Rh.
+hipError_t launch_line_rows(const edt_plan* p, const zd* g64, int f, int64_t p0, int64_t np, int nr, zd* Rh,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(line_rows_kernel, dim3(unsigned(np)), dim3(256), 0, st, g64,
+                       dptr<const int32_t>(p, p->lay.keys), dptr<const uint64_t>(p, p->lay.lmask),
+                       dptr<const int64_t>(p, p->lay.lfr), dptr<const int32_t>(p, p->lay.pair_u), f, p->n_freq,
+                       p->n_cls, p->n_mid, p->n_line, p->nz, nr, line_row_weight(p, f), p0, Rh);
+    return hipGetLastError();
+}
+
 // FP64 Gram, right-hand sides and trace of a line survey, frequency by
 // frequency over chunks of pairs (the rows of one chunk and frequency live in
 // work at lrows).
@@ -153,37 +182,23 @@ hipError_t launch_line_assemble(const edt_plan* p, const zd* g64, const void* d_
     const WorkLayout wl = work_layout(p);
     zd* Rh = reinterpret_cast<zd*>(work + wl.lrows);
     const int64_t chunk = line_chunk(p);
-    const int Nx = p->n_mid, Ny = p->n_line, nz = p->nz;
-    const double Ly = double(Ny) * p->d_line;
+    const int nz = p->nz;
     for (int64_t p0 = 0; p0 < P; p0 += chunk) {
         const int64_t np = std::min<int64_t>(chunk, P - p0);
         for (int f = 0; f < p->n_freq; ++f) {
-            const double wr = kTwoPiD * p->freq[size_t(f)], wi = p->eps;
-            const zd W{p->dz * (wr * wr - wi * wi) / Ly, p->dz * (2.0 * wr * wi) / Ly};
-            // rows formed compactly: as many slots per pair as the chunk's
-            // largest row count at this frequency (at least one, of zeros)
-            int64_t nr = 1;
-            for (int64_t q = p0; q < p0 + np; ++q) {
-                const int64_t* fr = p->lfr.data() + size_t(q) * size_t(p->n_freq + 1);
-                nr = std::max<int64_t>(nr, fr[f + 1] - fr[f]);
-            }
-            hipLaunchKernelGGL(line_rows_kernel, dim3(unsigned(np)), dim3(256), 0, st, g64,
-                               dptr<const int32_t>(p, p->lay.keys), dptr<const uint64_t>(p, p->lay.lmask),
-                               dptr<const int64_t>(p, p->lay.lfr), dptr<const int32_t>(p, p->lay.pair_u), f,
-                               p->n_freq, p->n_cls, Nx, Ny, nz, int(nr), W, p0, Rh);
-            hipError_t e = hipGetLastError();
+            const int nr = line_row_slots(p, f, p0, np);
+            hipError_t e = launch_line_rows(p, g64, f, p0, np, nr, Rh, st);
             if (e != hipSuccess) return e;
-            if ((e = launch_rows_gram(Rh, nz, int(nr), 1.0, f == 0, gram + size_t(p0) * nz * nz, np, st)) !=
-                hipSuccess)
+            if ((e = launch_rows_gram(Rh, nz, nr, 1.0, f == 0, gram + size_t(p0) * nz * nz, np, st)) != hipSuccess)
                 return e;
             if (p->data_c64)
                 hipLaunchKernelGGL(line_rhs_kernel<float2>, dim3(unsigned(np)), dim3(256), 0, st, Rh,
                                    dptr<const int64_t>(p, p->lay.lfr), static_cast<const float2*>(d_rows), f,
-                                   p->n_freq, int(nr), nz, p0, f == 0 ? 1 : 0, rhs);
+                                   p->n_freq, nr, nz, p0, f == 0 ? 1 : 0, rhs);
             else
                 hipLaunchKernelGGL(line_rhs_kernel<zd>, dim3(unsigned(np)), dim3(256), 0, st, Rh,
                                    dptr<const int64_t>(p, p->lay.lfr), static_cast<const zd*>(d_rows), f, p->n_freq,
-                                   int(nr), nz, p0, f == 0 ? 1 : 0, rhs);
+                                   nr, nz, p0, f == 0 ? 1 : 0, rhs);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     }

@@ -13,6 +13,8 @@ against the FP64 oracle (oracle.lines3d).
   damped solve of windowed data against the oracle's to 1e-10, a window
   holding every offset gives edt_assemble's Gram, and sampled pairs of the
   larger survey (three chunks of pairs) against the oracle;
+* the adjoint (edt_adjoint) against the oracle's gradient: data to 1e-9,
+  damping and layer velocities to 1e-8, on the three surveys;
 * what the line survey does not cover is refused.
 Surveys: odd and even grids, with and without the evanescent cut, depth
 counts that span several 64-tiles with a ragged tail, and a larger survey on
@@ -188,6 +190,34 @@ def test_line_aperture_gram_and_solve(name, b):
         scale = max(np.max(np.abs(Gf[i][low])), 1e-300)
         assert np.max(np.abs(Ga[i][low] - Gf[i][low])) <= 1e-12 * scale
     assert np.allclose(trace_all.cpu().numpy(), trace_full.cpu().numpy(), rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_line_adjoint_matches_the_oracle_gradient(name):
+    from oracle.grad import grad_lines
+    s = CASES[name]()
+    pl, tab, clean, data, d_rows, off = _case(s)
+    rng = np.random.default_rng(3)
+    T = rng.normal(size=(pl.n_km, s.nz)) + 1j * rng.normal(size=(pl.n_km, s.nz))
+    Vo, _ = solve_lines(s, pl, data, tab)
+    gV = 2.0 * (Vo - T)
+    go = grad_lines(s, pl, data, gV)
+    p = E.Plan(s)
+    vel = _dev(np.asarray(s.vel, np.float64))
+    d = _dev(d_rows)
+    out = p.run(vel, d, s.lambda_rel, prec="fp64")
+    gd, gl, gvel = p.adjoint(vel, out["g64"], d, out["gram"], out["trace"], out["x"], s.lambda_rel, _dev(gV))
+    torch.cuda.synchronize()
+    gd = gd.cpu().numpy()
+    ref_d = np.zeros_like(gd)
+    for i, (a0, a1) in enumerate(go["d"]):
+        ref_d[off[i]:off[i + 1], 0] = a0
+        ref_d[off[i]:off[i + 1], 1] = a1
+    ed = np.max(np.abs(gd - ref_d)) / np.max(np.abs(ref_d))
+    el = abs(gl.item() - go["lambda_rel"]) / abs(go["lambda_rel"])
+    ev = np.max(np.abs(gvel.cpu().numpy() - go["vel"])) / np.max(np.abs(go["vel"]))
+    print(f"{name}: adjoint errors data {ed:.2e}, damping {el:.2e}, velocities {ev:.2e}", flush=True)
+    assert ed <= 1e-9 and el <= 1e-8 and ev <= 1e-8
 
 
 def test_line_survey_refusals():
