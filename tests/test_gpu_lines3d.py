@@ -220,6 +220,35 @@ def test_line_adjoint_matches_the_oracle_gradient(name):
     assert ed <= 1e-9 and el <= 1e-8 and ev <= 1e-8
 
 
+def test_line_autograd_through_the_solve():
+    """torch.autograd through edt_solve on a line survey: the velocity,
+    damping and data gradients of |V~ - T|^2 against the oracle's."""
+    from oracle.grad import grad_lines
+    from paper_0905_0238_amd.autograd import edt_solve
+    s = CASES["odd-cut"]()
+    pl, tab, clean, data, d_rows, off = _case(s)
+    rng = np.random.default_rng(5)
+    T = rng.normal(size=(pl.n_km, s.nz)) + 1j * rng.normal(size=(pl.n_km, s.nz))
+    Vo, _ = solve_lines(s, pl, data, tab)
+    go = grad_lines(s, pl, data, 2.0 * (Vo - T))
+    p = E.Plan(s)
+    vel = _dev(np.asarray(s.vel, np.float64)).requires_grad_(True)
+    lam = torch.tensor(s.lambda_rel, dtype=torch.float64, device="cuda", requires_grad=True)
+    d = _dev(d_rows).requires_grad_(True)
+    V = edt_solve(d, lam, vel, p)
+    loss = torch.sum(torch.abs(V - _dev(T)) ** 2)
+    loss.backward()
+    torch.cuda.synchronize()
+    gv = vel.grad.cpu().numpy()
+    assert np.max(np.abs(gv - go["vel"])) <= 1e-8 * np.max(np.abs(go["vel"]))
+    assert abs(lam.grad.item() - go["lambda_rel"]) <= 1e-8 * abs(go["lambda_rel"])
+    ref_d = np.zeros_like(d_rows)
+    for i, (a0, a1) in enumerate(go["d"]):
+        ref_d[off[i]:off[i + 1], 0] = a0
+        ref_d[off[i]:off[i + 1], 1] = a1
+    assert np.max(np.abs(d.grad.cpu().numpy() - ref_d)) <= 1e-9 * np.max(np.abs(ref_d))
+
+
 def test_line_survey_refusals():
     s = CASES["even-nocut"]()
     pl, tab, clean, data, d_rows, off = _case(s)
