@@ -220,6 +220,39 @@ def test_line_adjoint_matches_the_oracle_gradient(name):
     assert ed <= 1e-9 and el <= 1e-8 and ev <= 1e-8
 
 
+def test_line_adjoint_on_complex64_rows():
+    """A complex64 plan reads its data rows widened to FP64 and writes the data
+    gradient rounded once to complex64: against the oracle fed the same
+    rounded data, 1.2e-7 of the largest data gradient (the rounding), 1e-8 for
+    the damping and the velocities."""
+    from oracle.grad import grad_lines
+    s = CASES["even-nocut"]()
+    pl, tab, clean, data, d_rows, off = _case(s)
+    d32 = d_rows.astype(np.complex64)
+    r64 = d32.astype(np.complex128)
+    data_r = [(r64[off[i]:off[i + 1], 0], r64[off[i]:off[i + 1], 1]) for i in range(len(pl.pairs))]
+    rng = np.random.default_rng(7)
+    T = rng.normal(size=(pl.n_km, s.nz)) + 1j * rng.normal(size=(pl.n_km, s.nz))
+    Vo, _ = solve_lines(s, pl, data_r, tab)
+    go = grad_lines(s, pl, data_r, 2.0 * (Vo - T))
+    p = E.Plan(s, data="c64")
+    vel = _dev(np.asarray(s.vel, np.float64))
+    d = _dev(d32)
+    out = p.run(vel, d, s.lambda_rel, prec="fp64")
+    gd, gl, gvel = p.adjoint(vel, out["g64"], d, out["gram"], out["trace"], out["x"], s.lambda_rel,
+                             _dev(2.0 * (Vo - T)))
+    torch.cuda.synchronize()
+    gd = gd.cpu().numpy()
+    assert gd.dtype == np.complex64
+    ref_d = np.zeros(gd.shape, np.complex128)
+    for i, (a0, a1) in enumerate(go["d"]):
+        ref_d[off[i]:off[i + 1], 0] = a0
+        ref_d[off[i]:off[i + 1], 1] = a1
+    assert np.max(np.abs(gd.astype(np.complex128) - ref_d)) <= 1.2e-7 * np.max(np.abs(ref_d))
+    assert abs(gl.item() - go["lambda_rel"]) <= 1e-8 * abs(go["lambda_rel"])
+    assert np.max(np.abs(gvel.cpu().numpy() - go["vel"])) <= 1e-8 * np.max(np.abs(go["vel"]))
+
+
 def test_line_autograd_through_the_solve():
     """torch.autograd through edt_solve on a line survey: the velocity,
     damping and data gradients of |V~ - T|^2 against the oracle's."""
