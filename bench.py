@@ -396,8 +396,8 @@ def lines_leg(reps, torch):
     """3D survey of parallel lines (FP64): 128 positions at 12.5 m on 32
     lines 25 m apart, nz = 128, 32 frequencies 4-40 Hz, four layers, with the
     evanescent cut; data from the device Born map of the seeded model.  Times
-    per call of green + assemble + damped solve, and of the finite-aperture
-    Gram (b = 0.15 N_x dx).  The Gram's algorithmic work is 2 nz (nz + 1)
+    per call of green + assemble + damped solve, of the finite-aperture Gram
+    (b = 0.15 N_x dx) and of the adjoint.  The Gram's algorithmic work is 2 nz (nz + 1)
     flop per row; its rate over the whole pass (the rows' forming, a sum of
     up to N_y products per value, is inside the time) against the FP64 MFMA
     peak."""
@@ -427,11 +427,24 @@ def lines_leg(reps, torch):
             t_ap += ev[1].elapsed_time(ev[2])
     t_solve /= reps
     t_ap /= reps
+    # the adjoint of the last pass (data, damping and velocity gradients)
+    g = torch.Generator(device="cuda").manual_seed(3)
+    gv = torch.complex(torch.randn(p.n_km, s.nz, generator=g, device="cuda", dtype=torch.float64),
+                       torch.randn(p.n_km, s.nz, generator=g, device="cuda", dtype=torch.float64))
+    t_adj = 0.0
+    for r in range(reps + 1):
+        ev[0].record()
+        p.adjoint(vel, g64, d, gram, trace, x, s.lambda_rel, gv)
+        ev[1].record()
+        torch.cuda.synchronize()
+        if r > 0:
+            t_adj += ev[0].elapsed_time(ev[1])
+    t_adj /= reps
     fl = float(p.n_rows) * 2 * s.nz * (s.nz + 1)
     ach = fl / (t_solve * 1e-3) / 1e12
     return {"survey": "128 positions x 32 lines, nz 128, 32 frequencies", "pairs": int(p.n_pairs),
             "rows": int(p.n_rows), "ms_per_pass": t_solve, "subproblems_per_s": p.n_km / (t_solve * 1e-3),
-            "aperture_ms_per_call": t_ap, "aperture_b_m": b,
+            "aperture_ms_per_call": t_ap, "aperture_b_m": b, "adjoint_ms_per_call": t_adj,
             "assembly_products": {"bound": "mfma", "achieved": ach, "peak": PEAK["fp64"], "unit": "TFLOP/s",
                                   "frac": ach / PEAK["fp64"],
                                   "per_pass": f"rows x 2 nz (nz+1) = {fl:.4g} flop over the whole pass "
