@@ -562,19 +562,28 @@ __global__ __launch_bounds__(256) void line_adj_kernel(
             zd Ab = yp[z] * ep + yp[nz + z] * em;
             Ab = Ab - xp[z] * ayp - xp[nz + z] * aym;
             Ab = Ab + kap * A[z];
-            uint64_t m = mask;
-            while (m) {
-                const int bit = __builtin_ctzll(m);
-                m &= m - 1;
-                const int q = bit - Ny / 2;
-                int pq = (q - qc) % Ny;
-                pq = sidx(pq < 0 ? pq + Ny : pq, Ny);
-                const size_t ca = size_t(ia * ny2 + abs(q)) * nz + z, cb = size_t(ib * ny2 + abs(pq)) * nz + z;
-                const zd ta = zconj(W * gf[cb]) * Ab, tb = zconj(W * gf[ca]) * Ab;
+            // the terms q and -q share the receiver-side entry (ia, |q|): their
+            // contributions to it are summed before its atomic add
+            const int h = Ny / 2;
+            for (int k = 0; k <= h; ++k) {
+                const bool kp = k + h < Ny && ((mask >> (k + h)) & 1u);   // q = +k
+                const bool kn = k > 0 && ((mask >> (h - k)) & 1u);        // q = -k
+                if (!kp && !kn) continue;
+                const size_t ca = size_t(ia * ny2 + k) * nz + z;
+                const zd tb = zconj(W * gf[ca]) * Ab;
+                zd ta{0.0, 0.0};
+                for (int sgn = 0; sgn < 2; ++sgn) {
+                    if (!(sgn == 0 ? kp : kn)) continue;
+                    const int q = sgn == 0 ? k : -k;
+                    int pq = (q - qc) % Ny;
+                    pq = sidx(pq < 0 ? pq + Ny : pq, Ny);
+                    const size_t cb = size_t(ib * ny2 + abs(pq)) * nz + z;
+                    ta = ta + zconj(W * gf[cb]) * Ab;
+                    atomicAdd(&gb[cb].x, tb.x);
+                    atomicAdd(&gb[cb].y, tb.y);
+                }
                 atomicAdd(&gb[ca].x, ta.x);
                 atomicAdd(&gb[ca].y, ta.y);
-                atomicAdd(&gb[cb].x, tb.x);
-                atomicAdd(&gb[cb].y, tb.y);
             }
         }
     }
